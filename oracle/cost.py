@@ -1,0 +1,255 @@
+"""Trajectory-optimisation costs and their joint-space gradient in FP64.  TEST INFRASTRUCTURE.
+
+One optimisation iteration (Sec. III-B) computes kinematics (2), the collision, self-collision and
+bound costs (3), aggregates them (4) and back-propagates through those steps (5).  The paper names
+the costs without formulas; the readings used here:
+
+  activation depth of sphere s:  d_s = max(0, eta - min_k (sd_k(p_s) - r_s)),  k* = first arg-min
+  world cost                      w_c * d_s^2
+  self pair (a, b):               e = |p_a - p_b| - r_a - r_b,   w_s * max(0, eta - e)^2
+  bound cost:                     w_b * sum_j max(0, q_j - hi_j)^2 + max(0, lo_j - q_j)^2
+  configuration cost              c = w_c sum_s d_s^2 + w_s sum_pairs max(0, eta - e)^2 + w_b bound
+  trajectory cost                 sum_t c_t + w_v sum_t |q_{t+1} - q_t|^2
+
+The stored per-sphere distance tensor holds d_s (zero for spheres farther than eta from every
+cuboid, which is what makes it mostly zeros, Sec. III-C).  Its gradient w.r.t. the sphere centre is
+-2 w_c d_s grad sd_{k*} plus the self-pair terms -2 w_s max(0, eta - e) (p_a - p_b)/|p_a - p_b| (zero
+for coincident centres).  Joint-space gradient, by reverse accumulation down the chain:
+
+  J_j = z_j . sum_{s: l(s) >= j} (p_s - o_j) x G_s
+
+and, independently, through the explicit geometric Jacobian dp_s/dq_j = z_j x (p_s - o_j).
+
+Quantisation emulation (Sec. IV-B: quantise-then-dequantise at every kernel invocation): with a
+precision assignment the five stored tensors -- link poses L, sphere positions S, distances D,
+sphere gradients G, joint gradients J -- are each replaced by dec(enc(.)) of their FP32 rounding at
+the point where the GPU path writes them; all other arithmetic stays FP64.  S is computed from the
+unquantised poses; the backward pass uses the quantised poses in stored mode and recomputes them
+from q in recompute mode.
+
+Parity pins (tests/test_oracle_cost.py): adjoint == explicit Jacobian to 1e-12; joint gradient ==
+central differences of the trajectory cost; sphere gradient == central differences of the
+configuration cost; self pair closed form; hand-computed single-sphere cases; at f32 with emulation
+the costs differ from the unquantised ones by FP32 rounding only.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import Dict, Optional, Tuple
+
+import numpy as np
+
+from . import formats as fmts
+from .geometry import obb_signed_distance
+from .kinematics import (N_JOINTS, forward_kinematics, joint_axes, link_pose_values, poses_from_values,
+                         sphere_positions)
+
+TENSORS = ("link_poses", "sphere_pos", "sphere_dist", "sphere_grad", "joint_grad")
+
+
+@dataclass
+class CostParams:
+    eta: float = 0.02
+    w_coll: float = 100.0
+    w_self: float = 100.0
+    w_bound: float = 10.0
+    w_smooth: float = 1.0
+
+
+@dataclass
+class Precision:
+    """Format name and power-of-two scale exponent per stored tensor, plus the pose mode."""
+
+    link_poses: Tuple[str, int] = ("f32", 0)
+    sphere_pos: Tuple[str, int] = ("f32", 0)
+    sphere_dist: Tuple[str, int] = ("f32", 0)
+    sphere_grad: Tuple[str, int] = ("f32", 0)
+    joint_grad: Tuple[str, int] = ("f32", 0)
+    recompute_poses: bool = False
+
+    def get(self, tensor: str) -> Tuple[str, int]:
+        return getattr(self, tensor)
+
+
+def world_term(S: np.ndarray, radius: np.ndarray, pose: np.ndarray, half_ext: np.ndarray,
+               world_of_cfg: np.ndarray, eta: float):
+    """Per sphere: activation depth d [B, n_s], unit gradient of sd at k* [B, n_s, 3], k* [B, n_s]
+    and the kink margin [B, n_s] (gap to the runner-up cuboid, inside-axis gap)."""
+    B, n_s, _ = S.shape
+    d = np.zeros((B, n_s))
+    grad = np.zeros((B, n_s, 3))
+    kstar = np.zeros((B, n_s), dtype=np.int64)
+    margin = np.full((B, n_s), np.inf)
+    for w in np.unique(world_of_cfg):
+        idx = np.nonzero(world_of_cfg == w)[0]
+        P = S[idx]                                    # [b, n_s, 3]
+        best = np.full(P.shape[:2], np.inf)
+        second = np.full(P.shape[:2], np.inf)
+        bgrad = np.zeros(P.shape)
+        bgap = np.full(P.shape[:2], np.inf)
+        bk = np.zeros(P.shape[:2], dtype=np.int64)
+        for k in range(pose.shape[1]):
+            R, c, h = pose[w, k, :, :3], pose[w, k, :, 3], half_ext[w, k]
+            sd, g, gap = obb_signed_distance(P, R, c, h)
+            e = sd - radius[None, :]
+            better = e < best                          # strict: ties keep the lower index
+            second = np.where(better, best, np.minimum(second, e))
+            best = np.where(better, e, best)
+            bk = np.where(better, k, bk)
+            bgrad = np.where(better[..., None], g, bgrad)
+            bgap = np.where(better, gap, bgap)
+        d[idx] = np.maximum(0.0, eta - best)
+        grad[idx] = bgrad
+        kstar[idx] = bk
+        margin[idx] = np.minimum(second - best, bgap)
+    return d, grad, kstar, margin
+
+
+def self_term(S: np.ndarray, radius: np.ndarray, pairs: np.ndarray, eta: float):
+    """Per configuration: sum of max(0, eta - e)^2 over pairs [B], the gradient of that sum w.r.t.
+    every sphere centre [B, n_s, 3] and the smallest centre distance [B]."""
+    B, n_s, _ = S.shape
+    a, b = pairs[:, 0], pairs[:, 1]
+    diff = S[:, a] - S[:, b]                           # [B, P, 3]
+    dist = np.sqrt(np.sum(diff * diff, axis=-1))
+    e = dist - radius[a] - radius[b]
+    act = np.maximum(0.0, eta - e)
+    cost = np.sum(act * act, axis=1)
+    unit = np.where(dist[..., None] > 0, diff / np.where(dist > 0, dist, 1.0)[..., None], 0.0)
+    ga = -2.0 * act[..., None] * unit                  # d/dp_a; d/dp_b is the negative
+    grad = np.zeros((B, n_s, 3))
+    for p in range(pairs.shape[0]):
+        grad[:, a[p]] += ga[:, p]
+        grad[:, b[p]] -= ga[:, p]
+    return cost, grad, np.min(dist, axis=1) if pairs.shape[0] else np.full(B, np.inf)
+
+
+def bound_term(q: np.ndarray, q_lo: np.ndarray, q_hi: np.ndarray):
+    over = np.maximum(0.0, q - q_hi)
+    under = np.maximum(0.0, q_lo - q)
+    return np.sum(over * over + under * under, axis=1), 2.0 * over - 2.0 * under
+
+
+def joint_grad_adjoint(T: np.ndarray, P: np.ndarray, G: np.ndarray, sphere_link: np.ndarray) -> np.ndarray:
+    """J[b, j-1] = z_j . sum_{s: l(s) >= j} (p_s - o_j) x G_s  (reverse accumulation)."""
+    z, o = joint_axes(T)
+    B = P.shape[0]
+    J = np.zeros((B, N_JOINTS))
+    link = np.asarray(sphere_link)
+    for j in range(1, N_JOINTS + 1):
+        sel = link >= j
+        r = P[:, sel] - o[:, j - 1][:, None, :]
+        torque = np.sum(np.cross(r, G[:, sel]), axis=1)
+        J[:, j - 1] = np.sum(z[:, j - 1] * torque, axis=1)
+    return J
+
+
+def joint_grad_jacobian(T: np.ndarray, P: np.ndarray, G: np.ndarray, sphere_link: np.ndarray) -> np.ndarray:
+    """J = Jac^T G with the explicit geometric Jacobian dp_s/dq_j = z_j x (p_s - o_j) (l(s) >= j)."""
+    z, o = joint_axes(T)
+    B, n_s, _ = P.shape
+    jac = np.zeros((B, n_s, 3, N_JOINTS))
+    for s in range(n_s):
+        for j in range(1, int(sphere_link[s]) + 1 if sphere_link[s] <= N_JOINTS else N_JOINTS + 1):
+            jac[:, s, :, j - 1] = np.cross(z[:, j - 1], P[:, s] - o[:, j - 1])
+    return np.einsum("bsij,bsi->bj", jac, G)
+
+
+def smoothness_grad(q: np.ndarray, T: int, n_ls: int) -> Tuple[np.ndarray, np.ndarray]:
+    """Per trajectory-candidate smoothness sum |q_{t+1} - q_t|^2 [n_tc] and its gradient [B, 7]."""
+    B = q.shape[0]
+    qt = q.reshape(B // T, T, N_JOINTS)
+    dq = qt[:, 1:] - qt[:, :-1]
+    val = np.sum(dq * dq, axis=(1, 2))
+    g = np.zeros_like(qt)
+    g[:, 1:] += 2.0 * dq
+    g[:, :-1] -= 2.0 * dq
+    return val, g.reshape(B, N_JOINTS)
+
+
+def world_index(B: int, traj_per_world: int, T: int, n_ls: int) -> np.ndarray:
+    b = np.arange(B)
+    return (b // (T * n_ls)) // traj_per_world
+
+
+def _store(x: np.ndarray, prec: Optional[Precision], tensor: str):
+    """(codes, stored float64 values) at a storage point; unquantised pass-through when prec is None."""
+    if prec is None:
+        return None, np.asarray(x, dtype=np.float64)
+    fmt, k = prec.get(tensor)
+    return fmts.roundtrip(x, fmt, k)
+
+
+def fwd_bwd(robot, worlds, q: np.ndarray, traj_per_world: int, T: int, n_ls: int,
+            prec: Optional[Precision] = None, params: CostParams = CostParams(),
+            upstream: Optional[np.ndarray] = None, emulate_scalars: bool = True) -> Dict[str, np.ndarray]:
+    """Whole forward + backward pass for configurations q [B, 7] laid out as
+    b = ((traj * n_ls + candidate) * T + t).  With `prec` None this is the unquantised FP64 truth;
+    otherwise each stored tensor goes through the reference codec (f32 = FP32 rounding) where the
+    GPU path writes it.  `upstream` is d(loss)/d(cost_traj) per trajectory-candidate (default 1)."""
+    q = np.asarray(q, dtype=np.float64)
+    B = q.shape[0]
+    n_tc = B // T
+    assert n_tc * T == B and (n_tc // n_ls) * n_ls == n_tc
+    wid = world_index(B, traj_per_world, T, n_ls)
+    eta = params.eta
+    out: Dict[str, np.ndarray] = {}
+
+    # (2) kinematics: link poses and sphere centres
+    Tk = forward_kinematics(robot.fixed_tf, q)
+    Lval = link_pose_values(Tk)
+    out["L_codes"], L_hat = _store(Lval, None if (prec is not None and prec.recompute_poses) else prec,
+                                   "link_poses")
+    S = sphere_positions(Tk, robot.sphere_center, robot.sphere_link)
+    out["S_codes"], S_hat = _store(S, prec, "sphere_pos")
+    bcost, bgrad = bound_term(q, robot.q_lo, robot.q_hi)
+
+    # (3) costs from the stored sphere positions
+    d, gdir, kstar, margin = world_term(S_hat, robot.sphere_radius, worlds.pose, worlds.half_ext, wid, eta)
+    scost, sgrad, min_pair = self_term(S_hat, robot.sphere_radius, robot.pairs, eta)
+    G = -2.0 * params.w_coll * d[..., None] * gdir + params.w_self * sgrad
+    out["D_codes"], D_hat = _store(d, prec, "sphere_dist")
+    out["G_codes"], G_hat = _store(G, prec, "sphere_grad")
+    if prec is not None and emulate_scalars:
+        scost_st = fmts.fp32(params.w_self * scost).astype(np.float64)
+        bcost_st = fmts.fp32(bcost).astype(np.float64)
+    else:
+        scost_st, bcost_st = params.w_self * scost, bcost
+
+    # (4) aggregation
+    cfg = params.w_coll * np.sum(D_hat * D_hat, axis=1) + scost_st + params.w_bound * bcost_st
+    smooth, sgr = smoothness_grad(q, T, n_ls)
+    cost_traj = cfg.reshape(n_tc, T).sum(axis=1) + params.w_smooth * smooth
+
+    # (5) backward to joint space
+    if prec is not None and not prec.recompute_poses:
+        Tb = poses_from_values(L_hat)
+        Pb = sphere_positions(Tb, robot.sphere_center, robot.sphere_link)
+    else:
+        Tb, Pb = Tk, S
+    Jsph = joint_grad_adjoint(Tb, Pb, G_hat, robot.sphere_link)
+    up = np.ones(n_tc) if upstream is None else np.asarray(upstream, dtype=np.float64)
+    J = up.repeat(T)[:, None] * (Jsph + params.w_bound * bgrad + params.w_smooth * sgr)
+    out["J_codes"], J_hat = _store(J, prec, "joint_grad")
+
+    out.update(L=Lval, L_hat=L_hat, S=S, S_hat=S_hat, D=d, D_hat=D_hat, G=G, G_hat=G_hat, J=J, J_hat=J_hat,
+               self_cost=scost_st, bound_cost=bcost_st, cfg_cost=cfg, cost_traj=cost_traj, grad_q=J_hat,
+               kstar=kstar, margin=margin, min_pair_dist=min_pair, world=wid, poses=Tk)
+    return out
+
+
+def config_cost(robot, worlds, q: np.ndarray, world_of_cfg: np.ndarray, params: CostParams = CostParams()):
+    """Unquantised configuration cost c(q) [B] (for finite-difference checks)."""
+    Tk = forward_kinematics(robot.fixed_tf, q)
+    S = sphere_positions(Tk, robot.sphere_center, robot.sphere_link)
+    d, _, _, _ = world_term(S, robot.sphere_radius, worlds.pose, worlds.half_ext, world_of_cfg, params.eta)
+    sc, _, _ = self_term(S, robot.sphere_radius, robot.pairs, params.eta)
+    bc, _ = bound_term(q, robot.q_lo, robot.q_hi)
+    return params.w_coll * np.sum(d * d, axis=1) + params.w_self * sc + params.w_bound * bc
+
+
+def sphere_cost(robot, worlds, S: np.ndarray, world_of_cfg: np.ndarray, params: CostParams = CostParams()):
+    """Collision part of the configuration cost as a function of the sphere centres [B, n_s, 3]."""
+    d, _, _, _ = world_term(S, robot.sphere_radius, worlds.pose, worlds.half_ext, world_of_cfg, params.eta)
+    sc, _, _ = self_term(S, robot.sphere_radius, robot.pairs, params.eta)
+    return params.w_coll * np.sum(d * d, axis=1) + params.w_self * sc
