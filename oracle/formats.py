@@ -20,7 +20,7 @@ NaN inputs give a NaN code where the format has one (which NaN code is not part 
 and are outside the contract for e3m2/e2m1.
 
 Per-tensor scale (not in the paper; restricted to powers of two so that scaling is exact):
-  write  code = enc(fp32(fp32(x) * 2^-k))     read  x_hat = dec(code) * 2^k
+  write  code = enc(fp32(fp32(x) * 2^-k))     read  x_hat = fp32(dec(code) * 2^k)
 with -16 <= k <= 16 and k = 0 for f32.
 
 Packed layout: element i occupies bits [b*i, b*i + b) of a little-endian bit stream (bit j of the
@@ -219,9 +219,12 @@ def quantize(x, fmt, k: int = 0) -> np.ndarray:
 
 
 def dequantize(codes, fmt, k: int = 0) -> np.ndarray:
-    """Values of the read path: dec(code) * 2^k (exact in float64)."""
+    """Values of the read path: the float32 value dec(code) * 2^k, returned as float64.  The product
+    is exact whenever it lies in float32 range (k >= -16 keeps every subnormal code representable);
+    scaled-up BF16 codes beyond float32 range read back as +-Inf."""
     check_scale(fmt, k)
-    return decode(codes, fmt) * (2.0 ** k)
+    with np.errstate(over="ignore"):
+        return fp32(decode(codes, fmt) * (2.0 ** k)).astype(np.float64)
 
 
 def roundtrip(x, fmt, k: int = 0) -> Tuple[np.ndarray, np.ndarray]:

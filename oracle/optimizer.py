@@ -8,12 +8,14 @@ rule below is a reading (per trajectory, n = T * 7 variables, the start and goal
   candidates  x_i = fp32(x + alpha_i d),  alpha = (1, 1/2, 1/4, 1/8)[:N]
   accept      the first i with c_i <= c + 1e-4 alpha_i g.d  (Armijo, FP64); otherwise the
               lowest-cost candidate if it is below c (first index on ties); otherwise none:
-              stay at x, clear the history and restart from d = -g
+              stay at x, clear the history and keep backtracking along the same direction,
+              d = fp32(d * alpha_min / 2)
   update      s = fp32(x_i - x), y = fp32(g_i - g); keep (s, y, rho = 1/(s.y)) in a ring of m pairs
               when s.y > 1e-10 |s| |y|
   direction   two-loop recursion over the history, initial scaling gamma = s.y / y.y of the newest
-              pair (1 with no history), vectors and dots in FP64, d = fp32(-r); if g.d >= 0 the
-              history is cleared and d = -g
+              pair, vectors and dots in FP64, d = fp32(-r); with no history, or if g.d >= 0 (the
+              history is then cleared), the steepest-descent direction capped so that no joint
+              moves more than max_step at alpha = 1: d = fp32(-g * min(1, max_step / |g|_inf))
 Gradients are zero on the pinned rows t = 0 and t = T - 1.
 
 Parity pins (tests/test_oracle_optimizer.py): the two-loop direction equals the dense inverse-Hessian
@@ -30,6 +32,7 @@ import numpy as np
 ALPHAS = (1.0, 0.5, 0.25, 0.125)
 ARMIJO_C1 = 1e-4
 CURVATURE_EPS = 1e-10
+MAX_STEP = float(np.float32(0.2))  # radians per joint at alpha = 1 (a float32 value, as the GPU holds it)
 N_JOINTS = 7
 
 
@@ -90,13 +93,22 @@ def dense_inverse_hessian(hist, n: int) -> np.ndarray:
     return H
 
 
-def direction(st: TrajState, m: int) -> Tuple[np.ndarray, bool]:
+def steepest(g: np.ndarray, max_step: float = MAX_STEP) -> np.ndarray:
+    """-g capped so that its largest component is at most max_step."""
+    gmax = float(np.max(np.abs(g))) if g.size else 0.0
+    scale = min(1.0, max_step / gmax) if gmax > 0.0 else 1.0
+    return fp32(-g * scale)
+
+
+def direction(st: TrajState, m: int, max_step: float = MAX_STEP) -> Tuple[np.ndarray, bool]:
     """(d, reset): the next search direction from the state's gradient and history."""
+    if not st.hist:
+        return steepest(st.g, max_step), False
     r = two_loop(st.g, st.hist)
     d = fp32(-r)
     if float(st.g @ d) >= 0.0:
         st.hist.clear()
-        return fp32(-st.g), True
+        return steepest(st.g, max_step), True
     return d, False
 
 
@@ -106,10 +118,9 @@ def candidates(x: np.ndarray, d: np.ndarray, n_ls: int) -> np.ndarray:
     return fp32(x[None] + a * d[None]).swapaxes(0, -2) if x.ndim > 1 else fp32(x[None] + a * d[None])
 
 
-def init_state(x0: np.ndarray, cost0: float, g0: np.ndarray, T: int) -> TrajState:
+def init_state(x0: np.ndarray, cost0: float, g0: np.ndarray, T: int, max_step: float = MAX_STEP) -> TrajState:
     g = pin_rows(fp32(g0), T)
-    st = TrajState(x=fp32(x0), g=g, d=fp32(-g), cost=float(cost0))
-    return st
+    return TrajState(x=fp32(x0), g=g, d=steepest(g, max_step), cost=float(cost0))
 
 
 def select(cost: float, gd: float, cand_cost: np.ndarray) -> int:
@@ -121,7 +132,8 @@ def select(cost: float, gd: float, cand_cost: np.ndarray) -> int:
     return i if cand_cost[i] < cost else -1
 
 
-def step(st: TrajState, cand_cost: np.ndarray, cand_grad: np.ndarray, T: int, m: int = 8) -> dict:
+def step(st: TrajState, cand_cost: np.ndarray, cand_grad: np.ndarray, T: int, m: int = 8,
+         max_step: float = MAX_STEP) -> dict:
     """One iteration for one trajectory.  cand_grad [n_ls, n] are the joint gradients of the
     candidates (pinned rows are zeroed here).  Mutates st; returns what was decided."""
     n_ls = cand_cost.shape[0]
@@ -130,7 +142,7 @@ def step(st: TrajState, cand_cost: np.ndarray, cand_grad: np.ndarray, T: int, m:
     info = {"accepted": i, "gd": gd, "curvature_ok": False, "reset": False}
     if i < 0:
         st.hist.clear()
-        st.d = fp32(-st.g)
+        st.d = fp32(st.d * (ALPHAS[n_ls - 1] * 0.5))
         info["reset"] = True
         return info
     x_new = fp32(st.x + ALPHAS[i] * st.d)
@@ -144,5 +156,5 @@ def step(st: TrajState, cand_cost: np.ndarray, cand_grad: np.ndarray, T: int, m:
             st.hist.pop(0)
         info["curvature_ok"] = True
     st.x, st.g, st.cost = x_new, g_new, float(cand_cost[i])
-    st.d, info["reset"] = direction(st, m)
+    st.d, info["reset"] = direction(st, m, max_step)
     return info

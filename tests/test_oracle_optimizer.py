@@ -62,15 +62,32 @@ def test_converges_on_convex_quadratic():
     def grad(x):
         return A @ x - b
 
-    st = O.init_state(x0, f(x0), grad(x0), T)
+    st = O.init_state(x0, f(x0), grad(x0), T, max_step=np.inf)
     for _ in range(60):
         cand = O.candidates(st.x, st.d, n_ls)
         costs = np.array([f(c) for c in cand])
         grads = np.array([grad(c) for c in cand])
-        O.step(st, costs, grads, T)
+        O.step(st, costs, grads, T, max_step=np.inf)
     # optimum over the free variables with the pinned rows held at x0
     x_opt = x0.copy()
     Aff = A[np.ix_(free, free)]
     x_opt[free] = np.linalg.solve(Aff, b[free] - A[np.ix_(free, ~free)] @ x0[~free])
     assert f(st.x) - f(x_opt) < 1e-6 * abs(f(x0) - f(x_opt))
     np.testing.assert_array_equal(st.x[~free], x0[~free])
+
+
+def test_capped_steepest_direction_and_backtracking():
+    g = np.array([0.0, 4.0, -1.0, 0.5])
+    np.testing.assert_array_equal(O.steepest(g, 0.2), O.fp32([0.0, -0.2, 0.05, -0.025]))
+    np.testing.assert_array_equal(O.steepest(g * 0.01, 0.2), O.fp32(-g * 0.01))  # small gradients untouched
+    # a rejected line search keeps x and scales the direction by alpha_min / 2 = 1/16
+    T = 3
+    x = np.zeros(21)
+    gg = O.pin_rows(np.arange(21, dtype=float), T)
+    st = O.init_state(x, 1.0, gg, T)
+    d0 = st.d.copy()
+    info = O.step(st, np.array([2.0, 2.0, 2.0, 2.0]), np.zeros((4, 21)), T)
+    assert info["accepted"] == -1 and info["reset"]
+    np.testing.assert_array_equal(st.x, x)
+    np.testing.assert_array_equal(st.d, O.fp32(d0 / 16.0))
+    assert np.max(np.abs(d0)) == np.float32(0.2)
