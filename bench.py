@@ -1,0 +1,266 @@
+"""Benchmark: one trajectory-optimisation iteration per step (candidate generation, kinematics,
+sphere costs, aggregation, adjoint, line-search selection and L-BFGS update) over a batch of
+64 worlds x 64 seeds x 48 timesteps = 196,608 configurations of a synthetic 7-joint arm with 60
+spheres and 300 self pairs among 64 random cuboids per world.  Reports configuration evaluations
+(cost + joint gradient) per second for a variable-precision assignment of the five stored tensors
+and for FP32 on the same GPU, with per-kernel times from HIP events recorded around each launch on
+the stream the kernels run on, the dominant kernel's roofline, and the FP64 oracle's rate on the
+host cores for a bounded sample.
+
+  python bench.py [--steps K] [--warmup W] [--precision NAME] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X published peaks
+HBM_PEAK_GBS = 8000.0
+# FP32 vector peak without packed-FP32 instructions: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz x 2
+# (an FMA is two flops).  The 157.3 TFLOP/s figure needs packed FP32, which this build does not emit.
+VALU_PEAK_TFLOPS = 78.6
+
+PRECISIONS = {
+    "f32": {},
+    # the paper's per-tensor findings: sphere positions need FP16, the gradient / distance tensors
+    # tolerate FP4-FP8
+    "paper_like": {"link_poses": "f16", "sphere_pos": "f16", "sphere_dist": ("e2m1", -3),
+                   "sphere_grad": ("e2m1", 5), "joint_grad": ("e4m3", 2)},
+    "all_fp8": {"link_poses": ("e4m3", -7), "sphere_pos": ("e4m3", -7), "sphere_dist": ("e4m3", -10),
+                "sphere_grad": ("e5m2", -9), "joint_grad": ("e5m2", -5)},
+    "mixed_fp4": {"link_poses": ("e4m3", -7), "sphere_pos": ("e4m3", -7), "sphere_dist": ("e2m1", -3),
+                  "sphere_grad": ("e2m1", 5), "joint_grad": ("e4m3", 2)},
+}
+BITS = {"f32": 32, "f16": 16, "bf16": 16, "e4m3": 8, "e5m2": 8, "e3m2": 6, "e2m1": 4}
+N_WORLDS, TPW, T, N_LS, N_SPHERES, N_CUBOIDS, N_PAIRS = 64, 64, 48, 1, 60, 64, 300
+HIST_M = 8
+# algorithmic FP32 operations of one sphere-cuboid test (FMA = 2): R^T p - R^T c (18),
+# |u| - h (3), max(a, 0) (3), |max(a,0)|^2 (5), min(max_i a_i, 0) (3), key (1), running arg-min (2)
+FLOPS_PER_SPHERE_CUBOID = 35
+# one self-pair visit: difference (3), squared norm (5), sqrt (1), clearance (2), activation (2)
+FLOPS_PER_PAIR_VISIT = 13
+
+
+def fmt_of(prec, name):
+    v = prec.get(name, "f32")
+    return v if isinstance(v, str) else v[0]
+
+
+def tensor_bytes(prec):
+    """Algorithmic bytes per configuration of each stored tensor (no padding)."""
+    vals = {"link_poses": 96, "sphere_pos": 3 * N_SPHERES, "sphere_dist": N_SPHERES,
+            "sphere_grad": 3 * N_SPHERES, "joint_grad": 7}
+    return {k: v * BITS[fmt_of(prec, k)] / 8.0 for k, v in vals.items()}
+
+
+def kernel_bytes(prec, recompute=False):
+    """Algorithmic HBM bytes per configuration of each kernel (stored tensors, q, FP32 scalars)."""
+    b = tensor_bytes(prec)
+    L = 0.0 if recompute else b["link_poses"]
+    n = T * 7
+    k5_per_traj = (3 * n * 4) * 2 + 2 * HIST_M * n * 4 + 2 * n * 4 + N_LS * n * 4 + n * b["joint_grad"] / 7 * 1 + 64
+    return {
+        "fk": 28 + L + b["sphere_pos"] + 4,
+        "sphere_cost": b["sphere_pos"] + b["sphere_dist"] + b["sphere_grad"] + 4,
+        "reduce": b["sphere_dist"] + 8 + 28,
+        "adjoint": b["sphere_grad"] + L + 28 + b["joint_grad"],
+        "optimizer": k5_per_traj / (T * N_LS),
+    }
+
+
+def kernel_flops_per_cfg():
+    return N_SPHERES * N_CUBOIDS * FLOPS_PER_SPHERE_CUBOID + 2 * N_PAIRS * FLOPS_PER_PAIR_VISIT
+
+
+def traffic_from_profile(kernel_src_hash):
+    """HBM bytes per launch measured with rocprofv3 counters, if taken on the current kernels."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path))
+    except Exception:
+        return None
+    return rec if rec.get("kernels_sha256") == kernel_src_hash else None
+
+
+def kernels_hash():
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "codec.hpp", "layout.hpp"):
+        h.update(open(os.path.join(ROOT, "paper_2310_07854_amd", "csrc", f), "rb").read())
+    return h.hexdigest()
+
+
+def run_variant(torch, ctx, opt_cls, x0, prec, steps, warmup):
+    ctx.set_precision(prec)
+    opt = opt_cls(ctx, N_WORLDS, TPW, T, n_ls=N_LS, m=HIST_M)
+    opt.init(x0)
+    for _ in range(warmup):
+        opt.step()
+    torch.cuda.synchronize()
+    ctx.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        opt.step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = ctx.profile_read()
+    ctx.profile_enable(False)
+    cost = float(opt.cost.sum())
+    return (t1 - t0), prof, cost
+
+
+def cpu_baseline(prec, budget_s=15.0):
+    """The FP64 oracle (quantisation emulated at the same five tensors) timed on the host for one
+    optimisation iteration of a sample of whole trajectories, single-threaded."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import cost as OC
+    from oracle import optimizer as OO
+    from synthetic import make_robot, make_trajectories, make_worlds
+
+    robot = make_robot(N_SPHERES, N_PAIRS)
+    worlds = make_worlds(N_WORLDS, N_CUBOIDS)
+    traj = make_trajectories(N_WORLDS, TPW, T)  # [W, S, T, 7]
+    kw = {t: ((v, 0) if isinstance(v, str) else tuple(v)) for t, v in prec.items()}
+    oprec = OC.Precision(**kw)
+
+    def one(n_traj):
+        # trajectories 0..n_traj-1 of world 0.. in order; candidates = current points (N_LS = 1)
+        x = traj.reshape(-1, T, 7)[:n_traj]
+        wl_pose = worlds.pose[np.arange(n_traj) // TPW]
+        wl_half = worlds.half_ext[np.arange(n_traj) // TPW]
+        from synthetic import Worlds
+        sub = Worlds(pose=wl_pose, half_ext=wl_half)
+        t0 = time.perf_counter()
+        out = OC.fwd_bwd(robot, sub, x.reshape(-1, 7), 1, T, N_LS, prec=oprec)
+        for i in range(n_traj):
+            st = OO.TrajState(x=x[i].reshape(-1), g=np.zeros(T * 7), d=-np.ones(T * 7) * 1e-3,
+                              cost=float(out["cost_traj"][i]) + 1.0)
+            OO.step(st, out["cost_traj"][i:i + 1], out["grad_q"].reshape(n_traj, 1, -1)[i], T, HIST_M)
+        return time.perf_counter() - t0
+
+    with threadpool_limits(limits=1):
+        t_small = one(2)
+        n = int(max(2, min(N_WORLDS * TPW, 2 * budget_s / max(t_small, 1e-6))))
+        dt = one(n)
+    return {"value": n * T * N_LS / dt, "unit": "evals/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n} trajectories x {T} timesteps = {n * T} configurations, one iteration, "
+                      f"{dt:.1f} s single-threaded"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--precision", default="paper_like", choices=[k for k in PRECISIONS if k != "f32"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--variants", action="store_true", help="also time every other assignment")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (--gpus {args.gpus} requested): the cost path shards by world "
+              "with no communication, so more GPUs are not exercised here.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2310_07854_amd import Context, TrajectoryOptimizer
+    from synthetic import make_robot, make_trajectories, make_worlds
+
+    B = N_WORLDS * TPW * T * N_LS
+    robot = make_robot(N_SPHERES, N_PAIRS)
+    worlds = make_worlds(N_WORLDS, N_CUBOIDS)
+    x0 = torch.tensor(make_trajectories(N_WORLDS, TPW, T).reshape(N_WORLDS * TPW, T, 7), dtype=torch.float32,
+                      device="cuda:0")
+    ctx = Context(0)
+    ctx.set_robot(robot)
+    ctx.set_worlds(worlds.pose, worlds.half_ext)
+
+    results = {}
+    names = ["f32", args.precision] + ([k for k in PRECISIONS if k not in ("f32", args.precision)]
+                                       if args.variants else [])
+    for name in names:
+        dt, prof, cost = run_variant(torch, ctx, TrajectoryOptimizer, x0, PRECISIONS[name], args.steps, args.warmup)
+        results[name] = {"seconds": dt, "prof": prof, "cost": cost}
+        print(f"# {name}: {dt / args.steps * 1e3:.3f} ms/step, {B * args.steps / dt / 1e6:.1f} M evals/s, "
+              f"kernels " + ", ".join(f"{k} {v[0] / max(v[1], 1) * 1e3:.1f}us" for k, v in prof.items() if v[1]),
+              file=sys.stderr, flush=True)
+
+    main_r = results[args.precision]
+    f32_r = results["f32"]
+    dt = main_r["seconds"]
+    value = B * args.steps / dt
+    value_f32 = B * args.steps / f32_r["seconds"]
+    prec = PRECISIONS[args.precision]
+    kb = kernel_bytes(prec)
+    per_kernel = {}
+    for k, (ms, n) in main_r["prof"].items():
+        if n == 0:
+            continue
+        avg_s = ms / n / 1e3
+        entry = {"avg_us": avg_s * 1e6, "launches": n}
+        if k in kb:
+            entry["algorithmic_GBs"] = kb[k] * B / avg_s / 1e9
+        per_kernel[k] = entry
+    dom = max(per_kernel, key=lambda k: per_kernel[k]["avg_us"] * per_kernel[k]["launches"])
+    dom_s = per_kernel[dom]["avg_us"] * 1e-6
+    traffic = traffic_from_profile(kernels_hash())
+    if dom == "sphere_cost":
+        achieved = kernel_flops_per_cfg() * B / dom_s / 1e12
+        roofline = {"kernel": "k_sphere_cost", "bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TFLOPS,
+                    "unit": "TFLOP/s", "frac": achieved / VALU_PEAK_TFLOPS}
+    else:
+        achieved = kb[dom] * B / dom_s / 1e9
+        roofline = {"kernel": "k_" + dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS}
+    roofline["traffic"] = (traffic or {}).get("bytes_per_launch", {}).get(roofline["kernel"]) if traffic else None
+
+    step_bytes = sum(kb[k] for k in kb) * B
+    line = {
+        "metric": "cost fwd+bwd evals/s (one optimiser iteration per step), variable precision vs FP32",
+        "value": value,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "64 worlds x 64 seeds x 48 timesteps = 196,608 configurations per step; 7-joint "
+                               "arm, 60 spheres, 300 self pairs, 64 oriented cuboids per world; 1 step scale",
+                   "precision": args.precision, "formats": {k: v for k, v in prec.items()},
+                   "recompute_poses": False},
+        "fp32_value": value_f32,
+        "speedup_vs_fp32_pct": (value / value_f32 - 1.0) * 100.0,
+        "hbm_algorithmic_GBs": step_bytes / (dt / args.steps) / 1e9,
+        "kernels": per_kernel,
+        "fp32_kernels": {k: v[0] / max(v[1], 1) * 1e3 for k, v in f32_r["prof"].items() if v[1]},
+        "roofline": roofline,
+    }
+    for name in results:
+        if name not in ("f32", args.precision):
+            line.setdefault("variants", {})[name] = B * args.steps / results[name]["seconds"]
+    ctx.close()
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(prec)
+    else:
+        line["cpu_baseline"] = None
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

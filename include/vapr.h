@@ -1,0 +1,252 @@
+/*
+ * vapr.h -- C ABI of the variable-precision trajectory-optimisation cost library for MI355X.
+ *
+ * The library evaluates, for a batch of joint configurations of a 7-joint serial arm in worlds of
+ * oriented cuboids, the trajectory-optimisation cost and its joint-space gradient, and runs the
+ * line-search + L-BFGS step that consumes them (the optimisation iteration of Sec. III-B of
+ * "VaPr: Variable-Precision Tensors to Accelerate Robot Motion Planning").  The five large
+ * intermediate tensors of that iteration -- link poses L, sphere positions S, per-sphere distances
+ * D, sphere-position gradients G and joint gradients J (Sec. III-C) -- are stored in per-tensor
+ * formats chosen from FP32, FP16, BF16, FP8 E4M3/E5M2, FP6 E3M2 and FP4 E2M1 (Sec. IV-A, IV-C);
+ * all arithmetic is FP32, reductions feeding the line search are FP64.
+ *
+ * Conventions shared by every call
+ *  - Every function returns a vapr_status.  Argument errors are detected on the host before any
+ *    work is queued and leave all state unchanged.  VAPR_E_HIP reports a failed HIP call or kernel
+ *    launch; faults inside kernels surface at the caller's next synchronisation.
+ *  - "dev" pointers are device memory on the context's device, "host" pointers host memory.
+ *    Device buffers must be 4-byte aligned (torch allocations are).  The caller owns every buffer it
+ *    passes; the library owns only its copies of the robot and world tables.
+ *  - All device work is queued on the context's HIP stream, asynchronously; host pointers are
+ *    consumed before the call returns.
+ *  - A context is used by one host thread at a time.
+ *  - Configuration layout: a batch of B = n_worlds * traj_per_world * n_ls * T configurations is
+ *    ordered b = ((traj * n_ls + cand) * T + t) with traj = world * traj_per_world + seed, so the
+ *    T timesteps of one trajectory candidate are contiguous and all candidates of a world are
+ *    contiguous.  q is row-major [B][7] FP32.
+ */
+#ifndef VAPR_H
+#define VAPR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define VAPR_ABI_VERSION 1
+
+typedef enum {
+  VAPR_OK = 0,
+  VAPR_E_INVALID = 1,      /* bad argument: null pointer, size out of range, unknown enum, ...   */
+  VAPR_E_OOM = 2,          /* the library could not allocate its robot/world tables             */
+  VAPR_E_HIP = 3,          /* a HIP runtime call or kernel launch failed                        */
+  VAPR_E_UNSUPPORTED = 4,  /* valid request this build does not implement (e.g. n_joints != 7)  */
+  VAPR_E_STATE = 5         /* call order violated: no robot/world, workspace not from a forward
+                              pass of this shape and precision, optimiser shape mismatch        */
+} vapr_status;
+
+/* Storage formats (Sec. IV-A).  Encoding rounds to nearest, ties to even; subnormals are kept.
+ * FP16/BF16 overflow to Inf (IEEE); E4M3/E5M2/E3M2/E2M1 saturate to their largest finite value,
+ * Inf inputs included.  NaN gives a NaN code where the format has one and is outside the contract
+ * for E3M2/E2M1.  Packed layout: element i occupies bits [b*i, b*i+b) of a little-endian bit
+ * stream (b = 32, 16, 16, 8, 8, 6, 4). */
+typedef enum {
+  VAPR_F32 = 0,
+  VAPR_F16 = 1,   /* E5M10, bias 15, max 65504            */
+  VAPR_BF16 = 2,  /* E8M7,  bias 127                      */
+  VAPR_E4M3 = 3,  /* bias 7, max 448, NaN = S.1111.111    */
+  VAPR_E5M2 = 4,  /* bias 15, max 57344                   */
+  VAPR_E3M2 = 5,  /* FP6, bias 3, max 28, no Inf/NaN      */
+  VAPR_E2M1 = 6   /* FP4, bias 1, max 6, no Inf/NaN       */
+} vapr_format;
+
+/* One stored tensor's format with a power-of-two scale: a value x is stored as
+ * enc(fp32(x) * 2^-scale_exp) and read back as the FP32 value dec(code) * 2^scale_exp (exact; only
+ * scaled-up BF16 codes can leave FP32 range and read back as Inf).  -16 <= scale_exp <= 16, and
+ * scale_exp must be 0 for VAPR_F32. */
+typedef struct {
+  int32_t fmt;
+  int32_t scale_exp;
+} vapr_tensor_format;
+
+/* Precision assignment, one format per large tensor (Sec. IV-B).  recompute_poses != 0 drops the
+ * link-pose tensor: the backward pass recomputes the poses from q instead of reading L. */
+typedef struct {
+  vapr_tensor_format link_poses;   /* L: links 1..8 as row-major 3x4 [R | t], 96 values/config  */
+  vapr_tensor_format sphere_pos;   /* S: sphere centres in the world frame, n_s x 3 per config  */
+  vapr_tensor_format sphere_dist;  /* D: activation depth max(0, eta - clearance), n_s          */
+  vapr_tensor_format sphere_grad;  /* G: d(config cost)/d(sphere centre), n_s x 3               */
+  vapr_tensor_format joint_grad;   /* J: d(loss)/dq, 7 per config                               */
+  int32_t recompute_poses;
+} vapr_precision;
+
+/* Cost weights (Sec. III-B step (3); the paper gives no values).
+ * configuration cost c = w_coll * sum_s d_s^2 + w_self * sum_pairs max(0, eta - e)^2
+ *                        + w_bound * sum_j (max(0, q_j - hi_j)^2 + max(0, lo_j - q_j)^2)
+ * trajectory cost      = sum_t c_t + w_smooth * sum_t |q_{t+1} - q_t|^2
+ * with d_s = max(0, eta - min_k(sd_k(p_s) - r_s)) and e = |p_a - p_b| - r_a - r_b.
+ * Defaults: eta 0.02 m, w_coll 100, w_self 100, w_bound 10, w_smooth 1. */
+typedef struct {
+  float eta;
+  float w_coll;
+  float w_self;
+  float w_bound;
+  float w_smooth;
+} vapr_cost_params;
+
+typedef struct vapr_ctx vapr_ctx;
+
+/* Library ABI version (VAPR_ABI_VERSION). */
+int vapr_abi_version(void);
+
+/* Create a context on HIP device `device` queuing work on `hip_stream` (a hipStream_t; NULL is the
+ * null stream).  Defaults: all tensors FP32 stored mode, default cost weights.  *out is set on
+ * success only. */
+int vapr_create(vapr_ctx** out, int device, void* hip_stream);
+/* Free the context and the library-owned tables.  NULL is accepted. */
+int vapr_destroy(vapr_ctx* ctx);
+/* Replace the stream used by later calls. */
+int vapr_set_stream(vapr_ctx* ctx, void* hip_stream);
+
+/* Upload the arm and its sphere model (Sec. II-B: kinematics and self-distance queries).  Host
+ * arrays, copied:
+ *   fixed_tf      [n_joints+1][3][4]  F_1..F_8; T_j = T_{j-1} F_j Rz(q_j) (j <= 7), T_8 = T_7 F_8,
+ *                                      T_0 = I.  Each rotation block must satisfy |R^T R - I| < 1e-5.
+ *   sphere_center [n_spheres][3]       in the frame of the sphere's link
+ *   sphere_radius [n_spheres]          > 0
+ *   sphere_link   [n_spheres]          link index 0..8 (0 = fixed base)
+ *   pairs         [n_pairs][2]         self-collision sphere pairs, a != b
+ *   q_lo, q_hi    [n_joints]           joint limits, q_lo <= q_hi
+ * Limits: n_joints == 7 (else VAPR_E_UNSUPPORTED), 1 <= n_spheres <= 256, 0 <= n_pairs <= 4096.
+ * Replaces a previous robot; workspaces sized for another sphere count become invalid. */
+int vapr_set_robot(vapr_ctx* ctx, int n_joints, const float* fixed_tf, int n_spheres,
+                   const float* sphere_center, const float* sphere_radius, const int32_t* sphere_link,
+                   int n_pairs, const int32_t* pairs, const float* q_lo, const float* q_hi);
+
+/* Upload the worlds (Sec. II-B: robot-environment distance queries).  Host arrays, copied:
+ *   pose     [n_worlds][n_cuboids][3][4]  world <- box transform [R | c]; |R^T R - I| < 1e-5
+ *   half_ext [n_worlds][n_cuboids][3]     > 0
+ * Limits: 1 <= n_worlds <= 65536, 0 <= n_cuboids <= 256. */
+int vapr_set_worlds(vapr_ctx* ctx, int n_worlds, int n_cuboids, const float* pose, const float* half_ext);
+
+/* Select the storage format of each large tensor (Sec. IV-B, IV-C).  Unknown format or scale out
+ * of range -> VAPR_E_INVALID.  Workspaces filled under another precision become invalid. */
+int vapr_set_precision(vapr_ctx* ctx, const vapr_precision* p);
+int vapr_get_precision(const vapr_ctx* ctx, vapr_precision* p);
+
+/* Set the cost weights (all finite, eta > 0, weights >= 0). */
+int vapr_set_cost_params(vapr_ctx* ctx, const vapr_cost_params* p);
+
+/* Bytes of device workspace a forward/backward pass of this batch shape needs at the current
+ * precision (holds L, S, D, G, J and two FP32 scalars per configuration).  Requires a robot. */
+int vapr_workspace_size(const vapr_ctx* ctx, int n_worlds, int traj_per_world, int T, int n_ls,
+                        size_t* bytes);
+
+/* Forward pass: kinematics -> sphere costs -> aggregation (Sec. III-B steps (2)-(4)).
+ *   q         dev [B][7]               configurations in the layout above
+ *   ws        dev, ws_bytes >= vapr_workspace_size(...)
+ *   cost_traj dev [n_worlds*traj_per_world*n_ls] FP64, trajectory-candidate costs
+ *   cost_cfg  dev [B] FP32 per-configuration cost, or NULL
+ * 1 <= T <= 4096, 1 <= n_ls <= 4, n_worlds <= the uploaded world count.  Requires robot and
+ * worlds (VAPR_E_STATE otherwise).  Records ws as holding a forward pass of this shape. */
+int vapr_cost_fwd(vapr_ctx* ctx, int n_worlds, int traj_per_world, int T, int n_ls, const float* q,
+                  void* ws, size_t ws_bytes, double* cost_traj, float* cost_cfg);
+
+/* Backward pass (Sec. III-B step (5)): joint gradient of sum_tc grad_cost_traj[tc] * cost_traj[tc].
+ *   q              dev [B][7], the same configurations as the forward pass
+ *   ws             a workspace filled by vapr_cost_fwd (or vapr_ws_import) of the same shape under
+ *                  the current precision, else VAPR_E_STATE
+ *   grad_cost_traj dev [n_traj*n_ls] FP64 upstream gradient, or NULL for all ones
+ *   grad_q         dev [B][7] FP32 receives dec(enc(J)), the stored joint gradient, or NULL
+ * J is always written to ws in its storage format (what vapr_optimizer_step reads). */
+int vapr_cost_bwd(vapr_ctx* ctx, const float* q, void* ws, size_t ws_bytes, const double* grad_cost_traj,
+                  float* grad_q);
+
+/* Optimiser state for n_traj trajectories of T timesteps (n = T*7 variables each), all dev,
+ * caller-owned (checkpointing is a copy of these buffers).  Rows t = 0 and t = T-1 are pinned. */
+typedef struct {
+  int32_t n_traj, T, n_ls, m;  /* 1 <= T <= 64, 1 <= n_ls <= 4, 1 <= m <= 8                      */
+  float max_step;              /* > 0: cap on a joint's move at alpha = 1 along steepest descent  */
+  float* x;                    /* [n_traj][n] current point                                       */
+  float* g;                    /* [n_traj][n] gradient at x (pinned rows zero)                    */
+  float* d;                    /* [n_traj][n] search direction                                    */
+  double* cost;                /* [n_traj]    cost at x                                           */
+  float* s_hist;               /* [n_traj][m][n] ring of position differences                     */
+  float* y_hist;               /* [n_traj][m][n] ring of gradient differences                     */
+  double* rho;                 /* [n_traj][m] 1 / (s.y)                                           */
+  int32_t* hist_len;           /* [n_traj]    pairs held (0..m)                                   */
+  int32_t* hist_head;          /* [n_traj]    ring slot the next pair goes to                     */
+  int32_t* accepted;           /* [n_traj]    last accepted candidate index, -1 = none            */
+  int32_t* flags;              /* [n_traj]    bit 0 pair stored, bit 1 direction reset            */
+} vapr_lbfgs_state;
+
+/* Start the optimiser (Sec. III-B step (1)).  x must hold the start point; ws holds a forward +
+ * backward pass at x with n_ls = 1 and upstream all ones (its J is the gradient) and cost0 dev
+ * [n_traj] FP64 its costs.  Sets g (pinned rows zeroed), cost, the capped steepest-descent direction
+ * d = -g * min(1, max_step / |g|_inf), empty history, and writes the first candidates q_cand dev
+ * [n_traj][st.n_ls][T][7]: q = fp32(x + alpha_i d), alpha = 1, 1/2, 1/4, 1/8. */
+int vapr_optimizer_init(vapr_ctx* ctx, const vapr_lbfgs_state* st, const void* ws, size_t ws_bytes,
+                        const double* cost0, float* q_cand);
+
+/* One iteration's line-search selection and L-BFGS update (Sec. III-B steps (6), (7)) followed by
+ * the next candidates (step (1)).  ws holds the forward + backward pass of the current candidates
+ * (n_ls = st.n_ls, upstream all ones) and cost_cand dev [n_traj*n_ls] FP64 their costs.  Accepts the
+ * first candidate meeting Armijo (c1 = 1e-4), else the cheapest if below the current cost, else
+ * none (x kept, history cleared, d scaled by alpha_min / 2 to keep backtracking); stores (s, y) when
+ * s.y > 1e-10|s||y|; two-loop direction with FP64 dots, or the capped steepest-descent direction
+ * when the history is empty or the two-loop result is not a descent direction (history cleared).
+ * Writes the next candidates to q_cand, which may alias the buffer the current candidates were
+ * read from. */
+int vapr_optimizer_step(vapr_ctx* ctx, const vapr_lbfgs_state* st, const void* ws, size_t ws_bytes,
+                        const double* cost_cand, float* q_cand);
+
+/* Element-wise codec on the context-free current device (Sec. IV-C's conversion of a tensor on
+ * write and read).  in/out dev; out holds vapr_packed_bytes(fmt, n) bytes in the packed layout.
+ * stream: hipStream_t or NULL.  0 <= n <= 2^32. */
+int vapr_quantize(int fmt, int scale_exp, const float* in, void* out, int64_t n, void* hip_stream);
+int vapr_dequantize(int fmt, int scale_exp, const void* in, float* out, int64_t n, void* hip_stream);
+size_t vapr_packed_bytes(int fmt, int64_t n);
+
+/* Tensor identifiers for workspace export/import. */
+typedef enum {
+  VAPR_T_LINK_POSES = 0,   /* codes, canonical order [B][8][12]  (stored mode only)          */
+  VAPR_T_SPHERE_POS = 1,   /* codes, [B][n_s][3]                                           */
+  VAPR_T_SPHERE_DIST = 2,  /* codes, [B][n_s]                                              */
+  VAPR_T_SPHERE_GRAD = 3,  /* codes, [B][n_s][3]                                           */
+  VAPR_T_JOINT_GRAD = 4,   /* codes, [B][7]                                                */
+  VAPR_T_SELF_COST = 5,    /* FP32 [B]: w_self * sum over pairs of max(0, eta - e)^2       */
+  VAPR_T_BOUND_COST = 6    /* FP32 [B]: unweighted joint-limit cost                        */
+} vapr_tensor;
+
+/* Copy one stored tensor between a workspace and a dense buffer in canonical element order, in the
+ * packed layout of the tensor's current format (vapr_packed_bytes(fmt, count) bytes).  Used to
+ * inspect and to seed individual stages.  Import records ws as holding a forward pass of this shape
+ * (so a backward pass may follow).  out/in dev; sizes checked against the shape. */
+int vapr_ws_export(vapr_ctx* ctx, int n_worlds, int traj_per_world, int T, int n_ls, const void* ws,
+                   size_t ws_bytes, int tensor, void* out, size_t out_bytes);
+int vapr_ws_import(vapr_ctx* ctx, int n_worlds, int traj_per_world, int T, int n_ls, void* ws,
+                   size_t ws_bytes, int tensor, const void* in, size_t in_bytes);
+
+/* Run the forward pass from stage `first` on: 1 = kinematics (same as vapr_cost_fwd), 2 = sphere
+ * costs then aggregation (reads S from ws), 3 = aggregation only (reads D and the two scalars). */
+int vapr_cost_fwd_from(vapr_ctx* ctx, int first, int n_worlds, int traj_per_world, int T, int n_ls,
+                       const float* q, void* ws, size_t ws_bytes, double* cost_traj, float* cost_cfg);
+
+/* Per-kernel timing with HIP events recorded around each launch on the context's stream.
+ * enable != 0 starts recording (and clears totals); vapr_profile_read synchronises the stream and
+ * returns, per kernel id (0 fk, 1 sphere_cost, 2 reduce, 3 adjoint, 4 optimizer, 5 codec, 6 repack),
+ * the summed milliseconds and launch counts for up to n_ids ids. */
+int vapr_profile_enable(vapr_ctx* ctx, int enable);
+int vapr_profile_read(vapr_ctx* ctx, double* total_ms, int64_t* launches, int n_ids);
+
+/* Static description of a status code; the last error message of a context (or of the calling
+ * thread when ctx is NULL).  Never NULL. */
+const char* vapr_status_string(int status);
+const char* vapr_last_error(const vapr_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* VAPR_H */

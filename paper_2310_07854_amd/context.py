@@ -1,0 +1,239 @@
+"""Python face of the library: a context owning the robot/world tables, plus thin wrappers of every
+C entry point.  torch supplies device memory and the current stream; every step of the cost path
+runs in the HIP kernels behind the C ABI.
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+from typing import Dict, Mapping, Optional, Sequence, Tuple, Union
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+TENSORS = ("link_poses", "sphere_pos", "sphere_dist", "sphere_grad", "joint_grad")
+FormatSpec = Union[str, Tuple[str, int]]
+
+
+def _stream_handle() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _dev(t: torch.Tensor, dtype: torch.dtype, what: str) -> int:
+    if not t.is_cuda:
+        raise ValueError(f"{what} must be a device tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{what} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{what} must be contiguous")
+    return t.data_ptr()
+
+
+def _host(a, dtype) -> np.ndarray:
+    if isinstance(a, torch.Tensor):
+        a = a.detach().cpu().numpy()
+    return np.ascontiguousarray(np.asarray(a), dtype=dtype)
+
+
+def _ptr(a: np.ndarray) -> int:
+    return a.ctypes.data
+
+
+@dataclass(frozen=True)
+class Shape:
+    """Batch shape of a cost evaluation: B = n_worlds * traj_per_world * n_ls * T."""
+
+    n_worlds: int
+    traj_per_world: int
+    T: int
+    n_ls: int = 1
+
+    @property
+    def n_traj(self) -> int:
+        return self.n_worlds * self.traj_per_world
+
+    @property
+    def n_tc(self) -> int:
+        return self.n_traj * self.n_ls
+
+    @property
+    def B(self) -> int:
+        return self.n_tc * self.T
+
+    def args(self):
+        return (self.n_worlds, self.traj_per_world, self.T, self.n_ls)
+
+
+def precision_struct(spec: Mapping[str, FormatSpec], recompute_poses: bool = False) -> L.PrecisionC:
+    p = L.PrecisionC()
+    for name in TENSORS:
+        v = spec.get(name, "f32")
+        fmt, k = (v, 0) if isinstance(v, str) else v
+        setattr(p, name, L.TensorFormat(L.FORMAT_IDS[fmt], int(k)))
+    p.recompute_poses = 1 if recompute_poses else 0
+    return p
+
+
+class Context:
+    """One library context on a device.  Work is queued on torch's current stream at call time."""
+
+    def __init__(self, device: int = 0):
+        self._lib = L.load()
+        self.device = device
+        h = ctypes.c_void_p()
+        with torch.cuda.device(device):
+            L.check(self._lib.vapr_create(ctypes.byref(h), device, _stream_handle()))
+        self._h = h
+        self.n_spheres = 0
+        self.precision: Dict[str, Tuple[str, int]] = {t: ("f32", 0) for t in TENSORS}
+        self.recompute_poses = False
+
+    # -- lifetime ----------------------------------------------------------------------------
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.vapr_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _call(self, name: str, *args) -> None:
+        fn = getattr(self._lib, name)
+        self._lib.vapr_set_stream(self._h, _stream_handle())
+        L.check(fn(self._h, *args), self._h)
+
+    # -- setup ---------------------------------------------------------------------------------
+    def set_robot(self, robot) -> None:
+        """robot: object with fixed_tf [8,3,4], sphere_center [n_s,3], sphere_radius [n_s],
+        sphere_link [n_s], pairs [P,2], q_lo [7], q_hi [7] (numpy or CPU tensors)."""
+        fixed = _host(robot.fixed_tf, np.float32)
+        centers = _host(robot.sphere_center, np.float32)
+        radius = _host(robot.sphere_radius, np.float32)
+        link = _host(robot.sphere_link, np.int32)
+        pairs = _host(robot.pairs, np.int32).reshape(-1, 2)
+        lo, hi = _host(robot.q_lo, np.float32), _host(robot.q_hi, np.float32)
+        self._call("vapr_set_robot", 7, _ptr(fixed), int(radius.shape[0]), _ptr(centers), _ptr(radius), _ptr(link),
+                   int(pairs.shape[0]), _ptr(pairs) if pairs.size else None, _ptr(lo), _ptr(hi))
+        self.n_spheres = int(radius.shape[0])
+
+    def set_worlds(self, pose, half_ext) -> None:
+        pose = _host(pose, np.float32)
+        half = _host(half_ext, np.float32)
+        W, K = pose.shape[0], pose.shape[1]
+        self._call("vapr_set_worlds", W, K, _ptr(pose) if pose.size else None, _ptr(half) if half.size else None)
+
+    def set_precision(self, spec: Optional[Mapping[str, FormatSpec]] = None, recompute_poses: bool = False) -> None:
+        spec = spec or {}
+        p = precision_struct(spec, recompute_poses)
+        self._call("vapr_set_precision", ctypes.byref(p))
+        self.precision = {t: ((spec.get(t, "f32"), 0) if isinstance(spec.get(t, "f32"), str) else tuple(spec[t]))
+                          for t in TENSORS}
+        self.recompute_poses = recompute_poses
+
+    def set_cost_params(self, eta=0.02, w_coll=100.0, w_self=100.0, w_bound=10.0, w_smooth=1.0) -> None:
+        p = L.CostParamsC(eta, w_coll, w_self, w_bound, w_smooth)
+        self._call("vapr_set_cost_params", ctypes.byref(p))
+
+    # -- cost path -----------------------------------------------------------------------------
+    def workspace_size(self, shape: Shape) -> int:
+        n = ctypes.c_size_t()
+        L.check(self._lib.vapr_workspace_size(self._h, *shape.args(), ctypes.byref(n)), self._h)
+        return int(n.value)
+
+    def new_workspace(self, shape: Shape) -> torch.Tensor:
+        return torch.empty(self.workspace_size(shape), dtype=torch.uint8, device=f"cuda:{self.device}")
+
+    def cost_fwd(self, q: torch.Tensor, shape: Shape, ws: Optional[torch.Tensor] = None,
+                 cost_traj: Optional[torch.Tensor] = None, cost_cfg: Optional[torch.Tensor] = None,
+                 first: int = 1):
+        """Trajectory-candidate costs [n_tc] float64 (and the workspace that holds the stored
+        tensors).  first > 1 resumes from a stored stage (2: sphere costs, 3: aggregation)."""
+        if ws is None:
+            ws = self.new_workspace(shape)
+        if cost_traj is None:
+            cost_traj = torch.empty(shape.n_tc, dtype=torch.float64, device=q.device)
+        if q.shape != (shape.B, 7):
+            raise ValueError(f"q must be [{shape.B}, 7]")
+        cfg_ptr = _dev(cost_cfg, torch.float32, "cost_cfg") if cost_cfg is not None else None
+        self._call("vapr_cost_fwd_from", first, *shape.args(), _dev(q, torch.float32, "q"),
+                   _dev(ws, torch.uint8, "ws"), ws.numel(), _dev(cost_traj, torch.float64, "cost_traj"), cfg_ptr)
+        return cost_traj, ws
+
+    def cost_bwd(self, q: torch.Tensor, ws: torch.Tensor, grad_cost_traj: Optional[torch.Tensor] = None,
+                 grad_q: Optional[torch.Tensor] = None, want_grad: bool = True) -> Optional[torch.Tensor]:
+        if want_grad and grad_q is None:
+            grad_q = torch.empty_like(q)
+        up = _dev(grad_cost_traj, torch.float64, "grad_cost_traj") if grad_cost_traj is not None else None
+        gp = _dev(grad_q, torch.float32, "grad_q") if grad_q is not None else None
+        self._call("vapr_cost_bwd", _dev(q, torch.float32, "q"), _dev(ws, torch.uint8, "ws"), ws.numel(), up, gp)
+        return grad_q
+
+    # -- stored tensors --------------------------------------------------------------------------
+    def tensor_count(self, name: str) -> int:
+        return {"link_poses": 96, "sphere_pos": 3 * self.n_spheres, "sphere_dist": self.n_spheres,
+                "sphere_grad": 3 * self.n_spheres, "joint_grad": 7, "self_cost": 1, "bound_cost": 1}[name]
+
+    def tensor_nbytes(self, name: str, shape: Shape) -> int:
+        n = shape.B * self.tensor_count(name)
+        if name in ("self_cost", "bound_cost"):
+            return 4 * n
+        fmt = L.FORMAT_IDS[self.precision[name][0]]
+        return int(self._lib.vapr_packed_bytes(fmt, n))
+
+    def ws_export(self, name: str, ws: torch.Tensor, shape: Shape) -> torch.Tensor:
+        """Packed codes (uint8) of a stored tensor in canonical order, or float32 for the scalars."""
+        nb = self.tensor_nbytes(name, shape)
+        out = torch.empty((nb + 3) // 4 * 4, dtype=torch.uint8, device=ws.device)
+        self._call("vapr_ws_export", *shape.args(), _dev(ws, torch.uint8, "ws"), ws.numel(), L.TENSOR_IDS[name],
+                   out.data_ptr(), out.numel())
+        out = out[:nb]
+        return out.view(torch.float32) if name in ("self_cost", "bound_cost") else out
+
+    def ws_import(self, name: str, ws: torch.Tensor, shape: Shape, data: torch.Tensor) -> None:
+        data = data.contiguous()
+        nb = data.numel() * data.element_size()
+        buf = torch.zeros((nb + 3) // 4 * 4, dtype=torch.uint8, device=ws.device)
+        buf[:nb] = data.view(torch.uint8).reshape(-1)
+        self._call("vapr_ws_import", *shape.args(), _dev(ws, torch.uint8, "ws"), ws.numel(), L.TENSOR_IDS[name],
+                   buf.data_ptr(), buf.numel())
+
+    # -- per-kernel timing -----------------------------------------------------------------------
+    def profile_enable(self, on: bool = True) -> None:
+        self._call("vapr_profile_enable", 1 if on else 0)
+
+    def profile_read(self) -> Dict[str, Tuple[float, int]]:
+        n = len(L.KERNEL_NAMES)
+        ms = (ctypes.c_double * n)()
+        cnt = (ctypes.c_int64 * n)()
+        self._call("vapr_profile_read", ms, cnt, n)
+        return {name: (ms[i], cnt[i]) for i, name in enumerate(L.KERNEL_NAMES)}
+
+
+def quantize(x: torch.Tensor, fmt: str, scale_exp: int = 0) -> torch.Tensor:
+    """Packed codes (uint8 tensor) of float32 device tensor x."""
+    lib = L.load()
+    f = L.FORMAT_IDS[fmt]
+    n = x.numel()
+    nb = int(lib.vapr_packed_bytes(f, n))
+    out = torch.empty((nb + 3) // 4 * 4, dtype=torch.uint8, device=x.device)
+    L.check(lib.vapr_quantize(f, scale_exp, _dev(x, torch.float32, "x"), out.data_ptr(), n, _stream_handle()))
+    return out[:nb]
+
+
+def dequantize(codes: torch.Tensor, fmt: str, n: int, scale_exp: int = 0) -> torch.Tensor:
+    """float32 values of n packed codes (uint8 device tensor)."""
+    lib = L.load()
+    f = L.FORMAT_IDS[fmt]
+    nb = int(lib.vapr_packed_bytes(f, n))
+    buf = codes
+    if codes.numel() % 4 or codes.data_ptr() % 4:
+        buf = torch.zeros((nb + 3) // 4 * 4, dtype=torch.uint8, device=codes.device)
+        buf[:nb] = codes[:nb]
+    out = torch.empty(n, dtype=torch.float32, device=codes.device)
+    L.check(lib.vapr_dequantize(f, scale_exp, _dev(buf, torch.uint8, "codes"), out.data_ptr(), n, _stream_handle()))
+    return out

@@ -1,0 +1,1028 @@
+// HIP kernels for gfx950 of one trajectory-optimisation iteration (Sec. III-B):
+//   k_fk          step (2) forward kinematics -> link poses L, sphere centres S, bound cost
+//   k_sphere_cost step (3) world (oriented cuboids) and self-pair costs -> distances D, gradients G
+//   k_reduce      step (4) aggregation into FP64 trajectory-candidate costs
+//   k_adjoint     step (5) reverse accumulation down the chain -> joint gradients J
+//   k_optimizer   steps (6), (7), (1): line-search selection, L-BFGS update, next candidates
+// plus the element-wise codec and the workspace repacking used for inspection.
+//
+// Mapping: one configuration per lane, 64 configurations per wavefront; the stored tensors are
+// tiled per wavefront (layout.hpp) so every tensor access of a wavefront is 256 contiguous bytes.
+// Robot tables and cuboids are read with wave-uniform addresses, which the compiler turns into
+// scalar loads: the inner cuboid loop runs on SGPR operands with no LDS traffic.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "codec.hpp"
+#include "kernels.hpp"
+#include "layout.hpp"
+
+namespace vapr {
+
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// Read-only tables (robot, cuboids) are read through the constant address space: they are never
+// written while a kernel runs, so wave-uniform reads become scalar (SMEM) loads into SGPRs.
+template <typename T>
+using cptr = const __attribute__((address_space(4))) T*;
+template <typename T>
+__device__ __forceinline__ cptr<T> as_const(const T* p) {
+  return (cptr<T>)p;
+}
+// sphere s of the robot table: (cx, cy, cz, r)
+__device__ __forceinline__ float4 sphere_of(const float4* sph, int s) {
+  const cptr<float> p = as_const(reinterpret_cast<const float*>(sph)) + 4 * s;
+  return make_float4(p[0], p[1], p[2], p[3]);
+}
+
+// ---- stored-tensor group access (format dispatched once per group, wave-uniform) -------------
+
+template <int F, int N>
+__device__ __forceinline__ void store_group_t(const TV& t, int64_t b, int slot, const float (&v)[N]) {
+  constexpr int DW = group_dwords(F, N);
+  uint32_t w[DW];
+  encode_group<F, N>(v, t.inv, w);
+#pragma unroll
+  for (int k = 0; k < DW; ++k) t.p[plane_index(b, t.P, slot * DW + k)] = w[k];
+}
+
+template <int N>
+__device__ __forceinline__ void store_group(const TV& t, int64_t b, int slot, const float (&v)[N]) {
+  switch (t.fmt) {
+    case F32: store_group_t<F32, N>(t, b, slot, v); break;
+    case F16: store_group_t<F16, N>(t, b, slot, v); break;
+    case BF16: store_group_t<BF16, N>(t, b, slot, v); break;
+    case E4M3: store_group_t<E4M3, N>(t, b, slot, v); break;
+    case E5M2: store_group_t<E5M2, N>(t, b, slot, v); break;
+    case E3M2: store_group_t<E3M2, N>(t, b, slot, v); break;
+    default: store_group_t<E2M1, N>(t, b, slot, v); break;
+  }
+}
+
+template <int F, int N>
+__device__ __forceinline__ void load_group_t(const TV& t, int64_t b, int slot, float (&v)[N]) {
+  constexpr int DW = group_dwords(F, N);
+  uint32_t w[DW];
+#pragma unroll
+  for (int k = 0; k < DW; ++k) w[k] = t.p[plane_index(b, t.P, slot * DW + k)];
+  decode_group<F, N>(w, t.scale, v);
+}
+
+template <int N>
+__device__ __forceinline__ void load_group(const TV& t, int64_t b, int slot, float (&v)[N]) {
+  switch (t.fmt) {
+    case F32: load_group_t<F32, N>(t, b, slot, v); break;
+    case F16: load_group_t<F16, N>(t, b, slot, v); break;
+    case BF16: load_group_t<BF16, N>(t, b, slot, v); break;
+    case E4M3: load_group_t<E4M3, N>(t, b, slot, v); break;
+    case E5M2: load_group_t<E5M2, N>(t, b, slot, v); break;
+    case E3M2: load_group_t<E3M2, N>(t, b, slot, v); break;
+    default: load_group_t<E2M1, N>(t, b, slot, v); break;
+  }
+}
+
+// stored value of element `pos` of the group in slot `slot` (group of N values)
+template <int F, int N>
+__device__ __forceinline__ float load_elem_t(const TV& t, int64_t b, int slot, int pos) {
+  constexpr int DW = group_dwords(F, N);
+  constexpr int BITS = Fmt<F>::BITS;
+  const int bit = pos * BITS, wi = bit >> 5, sh = bit & 31;
+  uint64_t v = t.p[plane_index(b, t.P, slot * DW + wi)];
+  if (sh + BITS > 32) v |= (uint64_t)t.p[plane_index(b, t.P, slot * DW + wi + 1)] << 32;
+  const uint32_t code = (uint32_t)(v >> sh) & (BITS == 32 ? 0xffffffffu : ((1u << BITS) - 1u));
+  return decode_one<F>(code, t.scale);
+}
+
+template <int N>
+__device__ __forceinline__ float load_elem(const TV& t, int64_t b, int slot, int pos) {
+  switch (t.fmt) {
+    case F32: return load_elem_t<F32, N>(t, b, slot, pos);
+    case F16: return load_elem_t<F16, N>(t, b, slot, pos);
+    case BF16: return load_elem_t<BF16, N>(t, b, slot, pos);
+    case E4M3: return load_elem_t<E4M3, N>(t, b, slot, pos);
+    case E5M2: return load_elem_t<E5M2, N>(t, b, slot, pos);
+    case E3M2: return load_elem_t<E3M2, N>(t, b, slot, pos);
+    default: return load_elem_t<E2M1, N>(t, b, slot, pos);
+  }
+}
+
+// stored values of a group after a round trip through the format (what a reader will see)
+template <int F, int N>
+__device__ __forceinline__ void roundtrip_t(const TV& t, float (&v)[N]) {
+  constexpr int DW = group_dwords(F, N);
+  uint32_t w[DW];
+  encode_group<F, N>(v, t.inv, w);
+  decode_group<F, N>(w, t.scale, v);
+}
+
+template <int N>
+__device__ __forceinline__ void roundtrip(const TV& t, float (&v)[N]) {
+  switch (t.fmt) {
+    case F32: roundtrip_t<F32, N>(t, v); break;
+    case F16: roundtrip_t<F16, N>(t, v); break;
+    case BF16: roundtrip_t<BF16, N>(t, v); break;
+    case E4M3: roundtrip_t<E4M3, N>(t, v); break;
+    case E5M2: roundtrip_t<E5M2, N>(t, v); break;
+    case E3M2: roundtrip_t<E3M2, N>(t, v); break;
+    default: roundtrip_t<E2M1, N>(t, v); break;
+  }
+}
+
+// ---- serial chain ------------------------------------------------------------------------------
+
+// T_j = T_{j-1} F_j Rz(q_j) (j = 1..7), T_8 = T_7 F_8; Tl[l-1] holds link l as row-major [R | t].
+__device__ __forceinline__ void chain(const float* __restrict__ fixed, const float (&qv)[N_JOINTS],
+                                      float (&Tl)[N_FIXED][LINK_VALUES]) {
+  float R[9] = {1.f, 0.f, 0.f, 0.f, 1.f, 0.f, 0.f, 0.f, 1.f};
+  float t[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+  for (int l = 0; l < N_FIXED; ++l) {
+    const cptr<float> F = as_const(fixed) + l * LINK_VALUES;
+    float nR[9], nt[3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+        nR[i * 3 + j] = fmaf(R[i * 3 + 0], F[0 * 4 + j], fmaf(R[i * 3 + 1], F[1 * 4 + j], R[i * 3 + 2] * F[2 * 4 + j]));
+      nt[i] = fmaf(R[i * 3 + 0], F[3], fmaf(R[i * 3 + 1], F[7], fmaf(R[i * 3 + 2], F[11], t[i])));
+    }
+    if (l < N_JOINTS) {
+      float s, c;
+      sincosf(qv[l], &s, &c);
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        const float c0 = nR[i * 3 + 0], c1 = nR[i * 3 + 1];
+        nR[i * 3 + 0] = fmaf(c, c0, s * c1);
+        nR[i * 3 + 1] = fmaf(c, c1, -s * c0);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < 9; ++i) R[i] = nR[i];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) t[i] = nt[i];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      Tl[l][i * 4 + 0] = R[i * 3 + 0];
+      Tl[l][i * 4 + 1] = R[i * 3 + 1];
+      Tl[l][i * 4 + 2] = R[i * 3 + 2];
+      Tl[l][i * 4 + 3] = t[i];
+    }
+  }
+}
+
+__device__ __forceinline__ void xform(const float (&T)[LINK_VALUES], float cx, float cy, float cz, float& x,
+                                      float& y, float& z) {
+  x = fmaf(T[0], cx, fmaf(T[1], cy, fmaf(T[2], cz, T[3])));
+  y = fmaf(T[4], cx, fmaf(T[5], cy, fmaf(T[6], cz, T[7])));
+  z = fmaf(T[8], cx, fmaf(T[9], cy, fmaf(T[10], cz, T[11])));
+}
+
+// world position of a sphere on link l (wave-uniform l selects a statically indexed pose)
+__device__ __forceinline__ void sphere_world(int l, const float (&Tl)[N_FIXED][LINK_VALUES], float cx, float cy,
+                                             float cz, float& x, float& y, float& z) {
+  switch (l) {
+#define VAPR_LINK_CASE(k) \
+  case k: xform(Tl[k - 1], cx, cy, cz, x, y, z); break;
+    VAPR_LINK_CASE(1) VAPR_LINK_CASE(2) VAPR_LINK_CASE(3) VAPR_LINK_CASE(4)
+    VAPR_LINK_CASE(5) VAPR_LINK_CASE(6) VAPR_LINK_CASE(7) VAPR_LINK_CASE(8)
+#undef VAPR_LINK_CASE
+    default: x = cx; y = cy; z = cz; break;
+  }
+}
+
+__device__ __forceinline__ float bound_cost(const RobotArgs& R, const float (&qv)[N_JOINTS]) {
+  float bc = 0.f;
+#pragma unroll
+  for (int j = 0; j < N_JOINTS; ++j) {
+    const float over = fmaxf(qv[j] - R.q_hi[j], 0.f), under = fmaxf(R.q_lo[j] - qv[j], 0.f);
+    bc = fmaf(over, over, fmaf(under, under, bc));
+  }
+  return bc;
+}
+
+// ---- K1: forward kinematics ---------------------------------------------------------------------
+
+// links 4*GR+1 .. 4*GR+4 as one packed group (static group index keeps Tl in registers)
+template <int GR>
+__device__ __forceinline__ void store_link_group(const TV& L, int64_t b, const float (&Tl)[N_FIXED][LINK_VALUES]) {
+  float v[L_GROUP];
+#pragma unroll
+  for (int i = 0; i < L_GROUP; ++i) v[i] = Tl[GR * 4 + i / LINK_VALUES][i % LINK_VALUES];
+  store_group<L_GROUP>(L, b, GR, v);
+}
+
+template <int GR>
+__device__ __forceinline__ void load_link_group(const TV& L, int64_t b, float (&Tl)[N_FIXED][LINK_VALUES]) {
+  float v[L_GROUP];
+  load_group<L_GROUP>(L, b, GR, v);
+#pragma unroll
+  for (int i = 0; i < L_GROUP; ++i) Tl[GR * 4 + i / LINK_VALUES][i % LINK_VALUES] = v[i];
+}
+
+__global__ __launch_bounds__(256) void k_fk(const float* __restrict__ q, RobotArgs R, TV L, TV S,
+                                            float* __restrict__ bound, int64_t B, int store_L) {
+  const int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (b >= B) return;
+  float qv[N_JOINTS];
+#pragma unroll
+  for (int j = 0; j < N_JOINTS; ++j) qv[j] = q[b * N_JOINTS + j];
+  bound[b] = bound_cost(R, qv);
+
+  float Tl[N_FIXED][LINK_VALUES];
+  chain(R.fixed, qv, Tl);
+  if (store_L) {
+    store_link_group<0>(L, b, Tl);
+    store_link_group<1>(L, b, Tl);
+  }
+  const int ng = uniform(R.n_groups);
+  for (int g = 0; g < ng; ++g) {
+    float px[SPH_GROUP], py[SPH_GROUP], pz[SPH_GROUP];
+#pragma unroll
+    for (int i = 0; i < SPH_GROUP; ++i) {
+      const int s = g * SPH_GROUP + i;
+      const float4 c = sphere_of(R.sph, s);
+      sphere_world(as_const(R.link)[s], Tl, c.x, c.y, c.z, px[i], py[i], pz[i]);
+    }
+    store_group<SPH_GROUP>(S, b, g * 3 + 0, px);
+    store_group<SPH_GROUP>(S, b, g * 3 + 1, py);
+    store_group<SPH_GROUP>(S, b, g * 3 + 2, pz);
+  }
+}
+
+// ---- K2: sphere costs ---------------------------------------------------------------------------
+
+// Signed distance to one cuboid and its gradient (per-lane cuboid).
+__device__ __forceinline__ void cuboid_sd_grad(const float* __restrict__ bx, float px, float py, float pz, float& sd,
+                                               float& gx, float& gy, float& gz) {
+  const float4 b0 = *reinterpret_cast<const float4*>(bx);
+  const float4 b1 = *reinterpret_cast<const float4*>(bx + 4);
+  const float4 b2 = *reinterpret_cast<const float4*>(bx + 8);
+  const float4 b3 = *reinterpret_cast<const float4*>(bx + 12);
+  const float A[9] = {b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, b1.z, b1.w, b2.x};
+  const float o[3] = {b2.y, b2.z, b2.w};
+  const float h[3] = {b3.x, b3.y, b3.z};
+  float u[3], a[3], m[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    u[i] = fmaf(A[i * 3 + 0], px, fmaf(A[i * 3 + 1], py, A[i * 3 + 2] * pz)) - o[i];
+    a[i] = fabsf(u[i]) - h[i];
+    m[i] = fmaxf(a[i], 0.f);
+  }
+  const float n2 = fmaf(m[0], m[0], fmaf(m[1], m[1], m[2] * m[2]));
+  float n[3];
+  if (n2 > 0.f) {
+    sd = sqrtf(n2);
+    const float inv = 1.0f / sd;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) n[i] = (u[i] >= 0.f ? m[i] : -m[i]) * inv;
+  } else {
+    const int ax = (a[0] >= a[1] && a[0] >= a[2]) ? 0 : (a[1] >= a[2] ? 1 : 2);
+    sd = ax == 0 ? a[0] : (ax == 1 ? a[1] : a[2]);
+    const float uu = ax == 0 ? u[0] : (ax == 1 ? u[1] : u[2]);
+    const float sg = uu >= 0.f ? 1.f : -1.f;
+    n[0] = ax == 0 ? sg : 0.f;
+    n[1] = ax == 1 ? sg : 0.f;
+    n[2] = ax == 2 ? sg : 0.f;
+  }
+  // gradient R n = A^T n
+  gx = fmaf(A[0], n[0], fmaf(A[3], n[1], A[6] * n[2]));
+  gy = fmaf(A[1], n[0], fmaf(A[4], n[1], A[7] * n[2]));
+  gz = fmaf(A[2], n[0], fmaf(A[5], n[1], A[8] * n[2]));
+}
+
+// Closest cuboid of NA spheres against the K cuboids of one world.  The comparison key is
+// |max(a,0)|^2 outside (> 0) and max_i a_i inside (<= 0), a monotone function of the signed
+// distance, so no square root is taken per pair; the first index wins ties.
+template <int NA>
+__device__ __forceinline__ void closest_cuboids(cptr<float> wbox, int K, const float (&px)[SPH_GROUP],
+                                                const float (&py)[SPH_GROUP], const float (&pz)[SPH_GROUP],
+                                                float (&best)[SPH_GROUP], int (&bk)[SPH_GROUP]) {
+  for (int k = 0; k < K; ++k) {
+    const cptr<float> bx = wbox + k * 16;
+    const float A0 = bx[0], A1 = bx[1], A2 = bx[2], A3 = bx[3], A4 = bx[4], A5 = bx[5], A6 = bx[6], A7 = bx[7],
+                A8 = bx[8];
+    const float o0 = bx[9], o1 = bx[10], o2 = bx[11], h0 = bx[12], h1 = bx[13], h2 = bx[14];
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+      const float u0 = fmaf(A0, px[i], fmaf(A1, py[i], A2 * pz[i])) - o0;
+      const float u1 = fmaf(A3, px[i], fmaf(A4, py[i], A5 * pz[i])) - o1;
+      const float u2 = fmaf(A6, px[i], fmaf(A7, py[i], A8 * pz[i])) - o2;
+      const float a0 = fabsf(u0) - h0, a1 = fabsf(u1) - h1, a2 = fabsf(u2) - h2;
+      const float m0 = fmaxf(a0, 0.f), m1 = fmaxf(a1, 0.f), m2 = fmaxf(a2, 0.f);
+      const float key = fmaf(m0, m0, fmaf(m1, m1, m2 * m2)) + fminf(fmaxf(fmaxf(a0, a1), a2), 0.f);
+      if (key < best[i]) {
+        best[i] = key;
+        bk[i] = k;
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_sphere_cost(RobotArgs R, WorldArgs W, TV S, TV D, TV G,
+                                                     float* __restrict__ selfc, ShapeArgs sh, CostArgs cp) {
+  const int64_t wave_first = (int64_t)blockIdx.x * 256 + uniform(threadIdx.x & ~63);
+  if (wave_first >= sh.B) return;
+  const int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (b >= sh.B) return;
+  const int64_t wave_last = (wave_first + 63 < sh.B ? wave_first + 63 : sh.B - 1);
+  const int w_lo = uniform((int)(wave_first / sh.cfg_per_world));
+  const int w_hi = uniform((int)(wave_last / sh.cfg_per_world));
+  const int my_w = (int)(b / sh.cfg_per_world);
+  const int K = uniform(W.K);
+  const int ng = uniform(R.n_groups);
+  const int n_s = uniform(R.n_s);
+  float self_acc = 0.f;
+
+  for (int g = 0; g < ng; ++g) {
+    float px[SPH_GROUP], py[SPH_GROUP], pz[SPH_GROUP];
+    load_group<SPH_GROUP>(S, b, g * 3 + 0, px);
+    load_group<SPH_GROUP>(S, b, g * 3 + 1, py);
+    load_group<SPH_GROUP>(S, b, g * 3 + 2, pz);
+    float best[SPH_GROUP];
+    int bk[SPH_GROUP];
+#pragma unroll
+    for (int i = 0; i < SPH_GROUP; ++i) {
+      best[i] = INFINITY;
+      bk[i] = 0;
+    }
+    const int active = uniform(min(SPH_GROUP, n_s - g * SPH_GROUP));
+    for (int w = w_lo; w <= w_hi; ++w) {
+      if (my_w != w) continue;
+      // readfirstlane keeps the address uniform (inside this branch w equals the per-lane my_w)
+      const cptr<float> wbox = as_const(W.box) + (int64_t)uniform(w) * K * 16;
+      if (active > 12) closest_cuboids<16>(wbox, K, px, py, pz, best, bk);
+      else if (active > 8) closest_cuboids<12>(wbox, K, px, py, pz, best, bk);
+      else if (active > 4) closest_cuboids<8>(wbox, K, px, py, pz, best, bk);
+      else closest_cuboids<4>(wbox, K, px, py, pz, best, bk);
+    }
+
+    float dv[SPH_GROUP], gx[SPH_GROUP], gy[SPH_GROUP], gz[SPH_GROUP];
+    const float* mybox = W.box + (int64_t)my_w * K * 16;
+#pragma unroll
+    for (int i = 0; i < SPH_GROUP; ++i) {
+      dv[i] = 0.f;
+      gx[i] = gy[i] = gz[i] = 0.f;
+      if (i < active && K > 0) {
+        float sd, nx, ny, nz;
+        cuboid_sd_grad(mybox + bk[i] * 16, px[i], py[i], pz[i], sd, nx, ny, nz);
+        const float r = sphere_of(R.sph, g * SPH_GROUP + i).w;
+        const float d = fmaxf(cp.eta - (sd - r), 0.f);
+        dv[i] = d;
+        const float coef = -2.f * cp.w_c * d;
+        gx[i] = coef * nx;
+        gy[i] = coef * ny;
+        gz[i] = coef * nz;
+      }
+    }
+    // self pairs: every pair is visited from both spheres; each visit adds its own sphere's
+    // gradient and the lower index adds the cost, so no cross-lane or atomic accumulation is needed
+#pragma unroll
+    for (int i = 0; i < SPH_GROUP; ++i) {
+      if (i >= active) continue;
+      const int s = g * SPH_GROUP + i;
+      const float rs = sphere_of(R.sph, s).w;
+      const int j0 = as_const(R.csr_off)[s], j1 = as_const(R.csr_off)[s + 1];
+      for (int j = j0; j < j1; ++j) {
+        const int t = as_const(R.csr_nbr)[j];
+        const int tg = t / SPH_GROUP, tp = t % SPH_GROUP;
+        const float tx = load_elem<SPH_GROUP>(S, b, tg * 3 + 0, tp);
+        const float ty = load_elem<SPH_GROUP>(S, b, tg * 3 + 1, tp);
+        const float tz = load_elem<SPH_GROUP>(S, b, tg * 3 + 2, tp);
+        const float dx = px[i] - tx, dy = py[i] - ty, dz = pz[i] - tz;
+        const float dist = sqrtf(fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
+        const float e = dist - rs - sphere_of(R.sph, t).w;
+        const float act = fmaxf(cp.eta - e, 0.f);
+        if (act > 0.f) {
+          if (dist > 0.f) {
+            const float coef = -2.f * cp.w_s * act / dist;
+            gx[i] = fmaf(coef, dx, gx[i]);
+            gy[i] = fmaf(coef, dy, gy[i]);
+            gz[i] = fmaf(coef, dz, gz[i]);
+          }
+          if (s < t) self_acc = fmaf(act, act, self_acc);
+        }
+      }
+    }
+    store_group<SPH_GROUP>(D, b, g, dv);
+    store_group<SPH_GROUP>(G, b, g * 3 + 0, gx);
+    store_group<SPH_GROUP>(G, b, g * 3 + 1, gy);
+    store_group<SPH_GROUP>(G, b, g * 3 + 2, gz);
+  }
+  selfc[b] = cp.w_s * self_acc;
+}
+
+// ---- K3: aggregation -----------------------------------------------------------------------------
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+__global__ __launch_bounds__(256) void k_reduce(TV D, const float* __restrict__ selfc,
+                                                const float* __restrict__ boundc, const float* __restrict__ q,
+                                                double* __restrict__ cost_traj, float* __restrict__ cost_cfg,
+                                                ShapeArgs sh, CostArgs cp, int n_s) {
+  const int64_t tc = (int64_t)blockIdx.x * 4 + uniform(threadIdx.x >> 6);
+  if (tc >= sh.n_tc) return;
+  const int lane = threadIdx.x & 63;
+  const int T = sh.T;
+  const int ng = (n_s + SPH_GROUP - 1) / SPH_GROUP;
+  double acc = 0.0;
+  for (int t0 = 0; t0 < T; t0 += 64) {
+    const int t = t0 + lane;
+    if (t < T) {
+      const int64_t b = tc * T + t;
+      double sq = 0.0;
+      for (int g = 0; g < ng; ++g) {
+        float dv[SPH_GROUP];
+        load_group<SPH_GROUP>(D, b, g, dv);
+        const int active = min(SPH_GROUP, n_s - g * SPH_GROUP);
+#pragma unroll
+        for (int i = 0; i < SPH_GROUP; ++i)
+          if (i < active) sq = fma((double)dv[i], (double)dv[i], sq);
+      }
+      const double c = (double)cp.w_c * sq + (double)selfc[b] + (double)cp.w_b * (double)boundc[b];
+      if (cost_cfg) cost_cfg[b] = (float)c;
+      double sm = 0.0;
+      if (t + 1 < T) {
+#pragma unroll
+        for (int j = 0; j < N_JOINTS; ++j) {
+          const double dq = (double)q[(b + 1) * N_JOINTS + j] - (double)q[b * N_JOINTS + j];
+          sm = fma(dq, dq, sm);
+        }
+      }
+      acc += c + (double)cp.w_v * sm;
+    }
+  }
+  acc = wave_sum(acc);
+  if (lane == 0) cost_traj[tc] = acc;
+}
+
+// ---- K4: reverse accumulation -------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_adjoint(const float* __restrict__ q, RobotArgs R, TV L, TV G, TV J,
+                                                 const double* __restrict__ up, float* __restrict__ grad_q,
+                                                 ShapeArgs sh, CostArgs cp, int recompute) {
+  const int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (b >= sh.B) return;
+  float qv[N_JOINTS];
+#pragma unroll
+  for (int j = 0; j < N_JOINTS; ++j) qv[j] = q[b * N_JOINTS + j];
+
+  float Tl[N_FIXED][LINK_VALUES];
+  if (recompute) {
+    chain(R.fixed, qv, Tl);
+  } else {
+    load_link_group<0>(L, b, Tl);
+    load_link_group<1>(L, b, Tl);
+  }
+  // per-link force and moment (about the world origin) of the sphere gradients
+  float fa[N_FIXED][3], ma[N_FIXED][3];
+#pragma unroll
+  for (int l = 0; l < N_FIXED; ++l)
+#pragma unroll
+    for (int i = 0; i < 3; ++i) fa[l][i] = ma[l][i] = 0.f;
+
+  const int ng = uniform(R.n_groups);
+  const int n_s = uniform(R.n_s);
+  for (int g = 0; g < ng; ++g) {
+    float gx[SPH_GROUP], gy[SPH_GROUP], gz[SPH_GROUP];
+    load_group<SPH_GROUP>(G, b, g * 3 + 0, gx);
+    load_group<SPH_GROUP>(G, b, g * 3 + 1, gy);
+    load_group<SPH_GROUP>(G, b, g * 3 + 2, gz);
+#pragma unroll
+    for (int i = 0; i < SPH_GROUP; ++i) {
+      const int s = g * SPH_GROUP + i;
+      if (s >= n_s) break;
+      const float4 c = sphere_of(R.sph, s);
+      switch (as_const(R.link)[s]) {
+#define VAPR_ACC_CASE(k)                                                            \
+  case k: {                                                                         \
+    float x, y, z;                                                                  \
+    xform(Tl[k - 1], c.x, c.y, c.z, x, y, z);                                       \
+    fa[k - 1][0] += gx[i];                                                          \
+    fa[k - 1][1] += gy[i];                                                          \
+    fa[k - 1][2] += gz[i];                                                          \
+    ma[k - 1][0] = fmaf(y, gz[i], fmaf(-z, gy[i], ma[k - 1][0]));                   \
+    ma[k - 1][1] = fmaf(z, gx[i], fmaf(-x, gz[i], ma[k - 1][1]));                   \
+    ma[k - 1][2] = fmaf(x, gy[i], fmaf(-y, gx[i], ma[k - 1][2]));                   \
+  } break;
+        VAPR_ACC_CASE(1) VAPR_ACC_CASE(2) VAPR_ACC_CASE(3) VAPR_ACC_CASE(4)
+        VAPR_ACC_CASE(5) VAPR_ACC_CASE(6) VAPR_ACC_CASE(7) VAPR_ACC_CASE(8)
+#undef VAPR_ACC_CASE
+        default: break;  // base link: no joint moves it
+      }
+    }
+  }
+  // tip to base: F_j, M_j over links >= j; J_j = z_j . (M_j - o_j x F_j)
+  float Jv[J_GROUP];
+  float F[3] = {0.f, 0.f, 0.f}, M[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+  for (int l = N_FIXED; l >= 1; --l) {
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      F[i] += fa[l - 1][i];
+      M[i] += ma[l - 1][i];
+    }
+    if (l <= N_JOINTS) {
+      const float* T = Tl[l - 1];
+      const float zx = T[2], zy = T[6], zz = T[10], ox = T[3], oy = T[7], oz = T[11];
+      const float tx = M[0] - (oy * F[2] - oz * F[1]);
+      const float ty = M[1] - (oz * F[0] - ox * F[2]);
+      const float tz = M[2] - (ox * F[1] - oy * F[0]);
+      Jv[l - 1] = fmaf(zx, tx, fmaf(zy, ty, zz * tz));
+    }
+  }
+  const int T = sh.T;
+  const int64_t tc = b / T;
+  const int t = (int)(b - tc * T);
+  const float scale = up ? (float)up[tc] : 1.f;
+#pragma unroll
+  for (int j = 0; j < N_JOINTS; ++j) {
+    const float over = fmaxf(qv[j] - R.q_hi[j], 0.f), under = fmaxf(R.q_lo[j] - qv[j], 0.f);
+    float gj = fmaf(cp.w_b, 2.f * over - 2.f * under, Jv[j]);
+    float sm = 0.f;
+    if (t >= 1) sm += 2.f * (qv[j] - q[(b - 1) * N_JOINTS + j]);
+    if (t + 1 < T) sm -= 2.f * (q[(b + 1) * N_JOINTS + j] - qv[j]);
+    gj = fmaf(cp.w_v, sm, gj);
+    Jv[j] = gj * scale;
+  }
+  Jv[N_JOINTS] = 0.f;
+  store_group<J_GROUP>(J, b, 0, Jv);
+  if (grad_q) {
+    roundtrip<J_GROUP>(J, Jv);
+#pragma unroll
+    for (int j = 0; j < N_JOINTS; ++j) grad_q[b * N_JOINTS + j] = Jv[j];
+  }
+}
+
+// ---- K5: line search + L-BFGS ----------------------------------------------------------------
+
+constexpr int OPT_NE = (MAX_OPT_T * N_JOINTS + 63) / 64;  // variables per lane
+
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+// -g capped so that its largest component is at most max_step (scale computed in FP64)
+__device__ __forceinline__ void steepest(const float (&g)[OPT_NE], float max_step, float (&d)[OPT_NE]) {
+  float gm = 0.f;
+#pragma unroll
+  for (int k = 0; k < OPT_NE; ++k) gm = fmaxf(gm, fabsf(g[k]));
+  gm = wave_max(gm);
+  double scale = 1.0;
+  if (gm > 0.f) scale = fmin(1.0, (double)max_step / (double)gm);
+#pragma unroll
+  for (int k = 0; k < OPT_NE; ++k) d[k] = (float)(-(double)g[k] * scale);
+}
+__constant__ float c_alpha[MAX_LS] = {1.0f, 0.5f, 0.25f, 0.125f};
+
+__global__ __launch_bounds__(256) void k_optimizer(OptArgs o, TV J, const double* __restrict__ cost_in,
+                                                   float* __restrict__ q_cand, int mode) {
+  const int tr = blockIdx.x * 4 + uniform(threadIdx.x >> 6);
+  if (tr >= o.n_traj) return;
+  const int lane = threadIdx.x & 63;
+  const int T = o.T, n = T * N_JOINTS, m = o.m, n_ls = o.n_ls;
+  const int64_t vb = (int64_t)tr * n;
+  float x[OPT_NE], g[OPT_NE], d[OPT_NE];
+#pragma unroll
+  for (int k = 0; k < OPT_NE; ++k) {
+    const int e = lane + 64 * k;
+    x[k] = e < n ? o.x[vb + e] : 0.f;
+    g[k] = e < n ? o.g[vb + e] : 0.f;
+    d[k] = e < n ? o.d[vb + e] : 0.f;
+  }
+  auto cand_grad = [&](int cand, int e) -> float {
+    const int t = e / N_JOINTS, j = e - t * N_JOINTS;
+    if (t == 0 || t == T - 1) return 0.f;  // start and goal are pinned
+    const int64_t b = ((int64_t)tr * (mode == 0 ? 1 : n_ls) + cand) * T + t;
+    return load_elem<J_GROUP>(J, b, 0, j);
+  };
+  int len = o.hist_len[tr], head = o.hist_head[tr], flags = 0, acc = 0;
+
+  if (mode == 0) {
+#pragma unroll
+    for (int k = 0; k < OPT_NE; ++k) {
+      const int e = lane + 64 * k;
+      g[k] = e < n ? cand_grad(0, e) : 0.f;
+    }
+    steepest(g, o.max_step, d);
+    len = 0;
+    head = 0;
+    if (lane == 0) o.cost[tr] = cost_in[tr];
+  } else {
+    double gd = 0.0;
+#pragma unroll
+    for (int k = 0; k < OPT_NE; ++k) gd = fma((double)g[k], (double)d[k], gd);
+    gd = wave_sum(gd);
+    const double c0 = o.cost[tr];
+    int sel = -1;
+    for (int i = 0; i < n_ls; ++i) {
+      if (cost_in[(int64_t)tr * n_ls + i] <= c0 + 1e-4 * (double)c_alpha[i] * gd) {
+        sel = i;
+        break;
+      }
+    }
+    if (sel < 0) {
+      int bi = 0;
+      for (int i = 1; i < n_ls; ++i)
+        if (cost_in[(int64_t)tr * n_ls + i] < cost_in[(int64_t)tr * n_ls + bi]) bi = i;
+      if (cost_in[(int64_t)tr * n_ls + bi] < c0) sel = bi;
+    }
+    acc = sel;
+    if (sel < 0) {
+      // keep x, drop the history, keep backtracking along the same direction
+      len = 0;
+      head = 0;
+      flags = 2;
+      const float shrink = 0.5f * c_alpha[n_ls - 1];
+#pragma unroll
+      for (int k = 0; k < OPT_NE; ++k) d[k] *= shrink;
+    } else {
+      const float alpha = c_alpha[sel];
+      float s[OPT_NE], y[OPT_NE];
+      double sy = 0.0, ss = 0.0, yy = 0.0;
+#pragma unroll
+      for (int k = 0; k < OPT_NE; ++k) {
+        const int e = lane + 64 * k;
+        const float xn = fmaf(alpha, d[k], x[k]);
+        const float gn = e < n ? cand_grad(sel, e) : 0.f;
+        s[k] = e < n ? xn - x[k] : 0.f;
+        y[k] = gn - g[k];
+        x[k] = e < n ? xn : 0.f;
+        g[k] = gn;
+        sy = fma((double)s[k], (double)y[k], sy);
+        ss = fma((double)s[k], (double)s[k], ss);
+        yy = fma((double)y[k], (double)y[k], yy);
+      }
+      sy = wave_sum(sy);
+      ss = wave_sum(ss);
+      yy = wave_sum(yy);
+      if (lane == 0) o.cost[tr] = cost_in[(int64_t)tr * n_ls + sel];
+      if (sy > 1e-10 * sqrt(ss) * sqrt(yy)) {
+        const int64_t hb = ((int64_t)tr * m + head) * n;
+#pragma unroll
+        for (int k = 0; k < OPT_NE; ++k) {
+          const int e = lane + 64 * k;
+          if (e < n) {
+            o.s_hist[hb + e] = s[k];
+            o.y_hist[hb + e] = y[k];
+          }
+        }
+        if (lane == 0) o.rho[(int64_t)tr * m + head] = 1.0 / sy;
+        head = (head + 1) % m;
+        len = min(len + 1, m);
+        flags |= 1;
+      }
+      // two-loop recursion, newest pair first; history kept in registers (age order)
+      double qv[OPT_NE], a_it[MAX_HIST];
+      float hs[MAX_HIST][OPT_NE], hy[MAX_HIST][OPT_NE];
+      double rho_it[MAX_HIST];
+#pragma unroll
+      for (int k = 0; k < OPT_NE; ++k) qv[k] = (double)g[k];
+#pragma unroll
+      for (int it = 0; it < MAX_HIST; ++it) {
+        a_it[it] = 0.0;
+        rho_it[it] = 0.0;
+        if (it < len) {
+          const int slot = (head - 1 - it + 2 * m) % m;
+          const int64_t hb = ((int64_t)tr * m + slot) * n;
+          rho_it[it] = o.rho[(int64_t)tr * m + slot];
+#pragma unroll
+          for (int k = 0; k < OPT_NE; ++k) {
+            const int e = lane + 64 * k;
+            hs[it][k] = e < n ? o.s_hist[hb + e] : 0.f;
+            hy[it][k] = e < n ? o.y_hist[hb + e] : 0.f;
+          }
+          double sq = 0.0;
+#pragma unroll
+          for (int k = 0; k < OPT_NE; ++k) sq = fma((double)hs[it][k], qv[k], sq);
+          a_it[it] = rho_it[it] * wave_sum(sq);
+#pragma unroll
+          for (int k = 0; k < OPT_NE; ++k) qv[k] = fma(-a_it[it], (double)hy[it][k], qv[k]);
+        }
+      }
+      double gamma = 1.0;
+      if (len > 0) {
+        double a = 0.0, c = 0.0;
+#pragma unroll
+        for (int k = 0; k < OPT_NE; ++k) {
+          a = fma((double)hs[0][k], (double)hy[0][k], a);
+          c = fma((double)hy[0][k], (double)hy[0][k], c);
+        }
+        gamma = wave_sum(a) / wave_sum(c);
+      }
+#pragma unroll
+      for (int k = 0; k < OPT_NE; ++k) qv[k] *= gamma;
+#pragma unroll
+      for (int it = MAX_HIST - 1; it >= 0; --it) {
+        if (it < len) {
+          double yr = 0.0;
+#pragma unroll
+          for (int k = 0; k < OPT_NE; ++k) yr = fma((double)hy[it][k], qv[k], yr);
+          const double beta = rho_it[it] * wave_sum(yr);
+#pragma unroll
+          for (int k = 0; k < OPT_NE; ++k) qv[k] = fma(a_it[it] - beta, (double)hs[it][k], qv[k]);
+        }
+      }
+      double gdn = 0.0;
+#pragma unroll
+      for (int k = 0; k < OPT_NE; ++k) {
+        d[k] = (float)(-qv[k]);
+        gdn = fma((double)g[k], (double)d[k], gdn);
+      }
+      gdn = wave_sum(gdn);
+      if (len == 0) {
+        steepest(g, o.max_step, d);
+      } else if (gdn >= 0.0) {
+        len = 0;
+        head = 0;
+        flags |= 2;
+        steepest(g, o.max_step, d);
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < OPT_NE; ++k) {
+    const int e = lane + 64 * k;
+    if (e < n) {
+      o.x[vb + e] = x[k];
+      o.g[vb + e] = g[k];
+      o.d[vb + e] = d[k];
+      for (int i = 0; i < n_ls; ++i) q_cand[((int64_t)tr * n_ls + i) * n + e] = fmaf(c_alpha[i], d[k], x[k]);
+    }
+  }
+  if (lane == 0) {
+    o.hist_len[tr] = len;
+    o.hist_head[tr] = head;
+    o.accepted[tr] = acc;
+    o.flags[tr] = flags;
+  }
+}
+
+// ---- element-wise codec -------------------------------------------------------------------------
+
+template <int F>
+__global__ __launch_bounds__(256) void k_quantize(float inv, const float* __restrict__ in, uint8_t* __restrict__ out,
+                                                  int64_t n) {
+  constexpr int DW = group_dwords(F, 16);
+  const int64_t gi = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t i0 = gi * 16;
+  if (i0 >= n) return;
+  float v[16];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) v[i] = (i0 + i < n) ? in[i0 + i] : 0.f;
+  uint32_t w[DW];
+  encode_group<F, 16>(v, inv, w);
+  if (i0 + 16 <= n) {
+    uint32_t* o32 = reinterpret_cast<uint32_t*>(out) + gi * DW;
+#pragma unroll
+    for (int k = 0; k < DW; ++k) o32[k] = w[k];
+  } else {
+    const int64_t total = (n * Fmt<F>::BITS + 7) / 8;
+    const int64_t start = gi * DW * 4;
+    for (int64_t by = start; by < total; ++by) {
+      const int k = (int)(by - start);
+      out[by] = (uint8_t)(w[k >> 2] >> ((k & 3) * 8));
+    }
+  }
+}
+
+template <int F>
+__global__ __launch_bounds__(256) void k_dequantize(float scale, const uint8_t* __restrict__ in,
+                                                    float* __restrict__ out, int64_t n) {
+  constexpr int DW = group_dwords(F, 16);
+  const int64_t gi = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t i0 = gi * 16;
+  if (i0 >= n) return;
+  uint32_t w[DW];
+  if (i0 + 16 <= n) {
+    const uint32_t* i32 = reinterpret_cast<const uint32_t*>(in) + gi * DW;
+#pragma unroll
+    for (int k = 0; k < DW; ++k) w[k] = i32[k];
+  } else {
+#pragma unroll
+    for (int k = 0; k < DW; ++k) w[k] = 0;
+    const int64_t total = (n * Fmt<F>::BITS + 7) / 8;
+    const int64_t start = gi * DW * 4;
+    for (int64_t by = start; by < total; ++by) {
+      const int k = (int)(by - start);
+      w[k >> 2] |= (uint32_t)in[by] << ((k & 3) * 8);
+    }
+  }
+  float v[16];
+  decode_group<F, 16>(w, scale, v);
+#pragma unroll
+  for (int i = 0; i < 16; ++i)
+    if (i0 + i < n) out[i0 + i] = v[i];
+}
+
+// ---- workspace <-> canonical order repacking (no arithmetic on values) --------------------------
+
+// slot and position inside the slot's group of element `loc` of one configuration
+__device__ __forceinline__ void elem_slot(int tensor, int loc, int& slot, int& pos) {
+  switch (tensor) {
+    case T_L: {
+      const int l = loc / LINK_VALUES, k = loc % LINK_VALUES;
+      slot = l / 4;
+      pos = (l % 4) * LINK_VALUES + k;
+    } break;
+    case T_S:
+    case T_G: {
+      const int s = loc / 3, c = loc % 3;
+      slot = (s / SPH_GROUP) * 3 + c;
+      pos = s % SPH_GROUP;
+    } break;
+    case T_D:
+      slot = loc / SPH_GROUP;
+      pos = loc % SPH_GROUP;
+      break;
+    default:
+      slot = 0;
+      pos = loc;
+      break;
+  }
+}
+
+__device__ __forceinline__ int group_size(int tensor) {
+  return tensor == T_L ? L_GROUP : (tensor == T_J ? J_GROUP : SPH_GROUP);
+}
+
+__device__ __forceinline__ uint32_t get_code(const TV& t, int tensor, int64_t b, int slot, int pos) {
+  const int bits = format_bits(t.fmt);
+  const int DW = group_dwords(t.fmt, group_size(tensor));
+  const int bit = pos * bits, wi = bit >> 5, sh = bit & 31;
+  uint64_t v = t.p[plane_index(b, t.P, slot * DW + wi)];
+  if (sh + bits > 32) v |= (uint64_t)t.p[plane_index(b, t.P, slot * DW + wi + 1)] << 32;
+  return (uint32_t)(v >> sh) & (bits == 32 ? 0xffffffffu : ((1u << bits) - 1u));
+}
+
+__device__ __forceinline__ uint32_t read_flat(const uint8_t* flat, int64_t e, int bits) {
+  const int64_t bit = e * bits;
+  const int64_t by = bit >> 3;
+  const int sh = (int)(bit & 7);
+  uint64_t v = 0;
+  const int nbytes = (sh + bits + 7) / 8;
+  for (int k = 0; k < nbytes; ++k) v |= (uint64_t)flat[by + k] << (8 * k);
+  return (uint32_t)(v >> sh) & (bits == 32 ? 0xffffffffu : ((1u << bits) - 1u));
+}
+
+// export: one thread per 16 consecutive canonical elements
+__global__ __launch_bounds__(256) void k_export(TV t, int tensor, int64_t B, int ecfg, uint8_t* __restrict__ flat) {
+  const int64_t gi = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t total_e = B * ecfg;
+  const int64_t e0 = gi * 16;
+  if (e0 >= total_e) return;
+  const int bits = format_bits(t.fmt);
+  uint64_t acc = 0;
+  int nb = 0;
+  int64_t byte_out = e0 * bits / 8;  // 16 * bits is a whole number of bytes
+  const int64_t total_bytes = (total_e * bits + 7) / 8;
+  for (int i = 0; i < 16; ++i) {
+    const int64_t e = e0 + i;
+    uint32_t c = 0;
+    if (e < total_e) {
+      const int64_t b = e / ecfg;
+      int slot, pos;
+      elem_slot(tensor, (int)(e - b * ecfg), slot, pos);
+      c = get_code(t, tensor, b, slot, pos);
+    }
+    acc |= (uint64_t)c << nb;
+    nb += bits;
+    while (nb >= 8) {
+      if (byte_out < total_bytes) flat[byte_out] = (uint8_t)acc;
+      ++byte_out;
+      acc >>= 8;
+      nb -= 8;
+    }
+  }
+}
+
+// import: one thread per (configuration, slot) group
+__global__ __launch_bounds__(256) void k_import(TV t, int tensor, int64_t B, int ecfg, int n_slots, int n_s,
+                                                const uint8_t* __restrict__ flat) {
+  const int64_t gi = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (gi >= B * n_slots) return;
+  const int64_t b = gi / n_slots;
+  const int slot = (int)(gi - b * n_slots);
+  const int gs = group_size(tensor);
+  const int bits = format_bits(t.fmt);
+  const int DW = group_dwords(t.fmt, gs);
+  uint32_t w[L_GROUP];  // largest group: 48 FP32 values
+  for (int k = 0; k < DW; ++k) w[k] = 0;
+  for (int pos = 0; pos < gs; ++pos) {
+    // canonical element of (slot, pos), if any
+    int loc = -1;
+    switch (tensor) {
+      case T_L: loc = (slot * 4 + pos / LINK_VALUES) * LINK_VALUES + pos % LINK_VALUES; break;
+      case T_S:
+      case T_G: {
+        const int s = (slot / 3) * SPH_GROUP + pos;
+        loc = s < n_s ? s * 3 + slot % 3 : -1;
+      } break;
+      case T_D: {
+        const int s = slot * SPH_GROUP + pos;
+        loc = s < n_s ? s : -1;
+      } break;
+      default: loc = pos < N_JOINTS ? pos : -1; break;
+    }
+    if (loc < 0 || loc >= ecfg) continue;
+    const uint32_t c = read_flat(flat, b * ecfg + loc, bits);
+    const int bit = pos * bits, wi = bit >> 5, sh = bit & 31;
+    const uint64_t v = (uint64_t)c << sh;
+    w[wi] |= (uint32_t)v;
+    if (sh + bits > 32) w[wi + 1] |= (uint32_t)(v >> 32);
+  }
+  for (int k = 0; k < DW; ++k) t.p[plane_index(b, t.P, slot * DW + k)] = w[k];
+}
+
+// ---- launch wrappers ----------------------------------------------------------------------------
+
+static inline unsigned blocks_for(int64_t n, int per_block) { return (unsigned)((n + per_block - 1) / per_block); }
+
+hipError_t launch_fk(hipStream_t s, const float* q, const RobotArgs& R, const TV& L, const TV& S, float* bound,
+                     int64_t B, int store_L) {
+  hipLaunchKernelGGL(k_fk, dim3(blocks_for(B, 256)), dim3(256), 0, s, q, R, L, S, bound, B, store_L);
+  return hipGetLastError();
+}
+
+hipError_t launch_sphere_cost(hipStream_t s, const RobotArgs& R, const WorldArgs& W, const TV& S, const TV& D,
+                              const TV& G, float* selfc, const ShapeArgs& sh, const CostArgs& cp) {
+  hipLaunchKernelGGL(k_sphere_cost, dim3(blocks_for(sh.B, 256)), dim3(256), 0, s, R, W, S, D, G, selfc, sh, cp);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce(hipStream_t s, const TV& D, const float* selfc, const float* boundc, const float* q,
+                         double* cost_traj, float* cost_cfg, const ShapeArgs& sh, const CostArgs& cp, int n_s) {
+  hipLaunchKernelGGL(k_reduce, dim3(blocks_for(sh.n_tc, 4)), dim3(256), 0, s, D, selfc, boundc, q, cost_traj,
+                     cost_cfg, sh, cp, n_s);
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint(hipStream_t s, const float* q, const RobotArgs& R, const TV& L, const TV& G, const TV& J,
+                          const double* up, float* grad_q, const ShapeArgs& sh, const CostArgs& cp, int recompute) {
+  hipLaunchKernelGGL(k_adjoint, dim3(blocks_for(sh.B, 256)), dim3(256), 0, s, q, R, L, G, J, up, grad_q, sh, cp,
+                     recompute);
+  return hipGetLastError();
+}
+
+hipError_t launch_optimizer(hipStream_t s, const OptArgs& o, const TV& J, const double* cost_in, float* q_cand,
+                            int mode) {
+  hipLaunchKernelGGL(k_optimizer, dim3(blocks_for(o.n_traj, 4)), dim3(256), 0, s, o, J, cost_in, q_cand, mode);
+  return hipGetLastError();
+}
+
+hipError_t launch_quantize(hipStream_t s, int fmt, float inv, const float* in, uint8_t* out, int64_t n) {
+  const dim3 grid(blocks_for((n + 15) / 16, 256)), block(256);
+  switch (fmt) {
+    case F32: hipLaunchKernelGGL(k_quantize<F32>, grid, block, 0, s, inv, in, out, n); break;
+    case F16: hipLaunchKernelGGL(k_quantize<F16>, grid, block, 0, s, inv, in, out, n); break;
+    case BF16: hipLaunchKernelGGL(k_quantize<BF16>, grid, block, 0, s, inv, in, out, n); break;
+    case E4M3: hipLaunchKernelGGL(k_quantize<E4M3>, grid, block, 0, s, inv, in, out, n); break;
+    case E5M2: hipLaunchKernelGGL(k_quantize<E5M2>, grid, block, 0, s, inv, in, out, n); break;
+    case E3M2: hipLaunchKernelGGL(k_quantize<E3M2>, grid, block, 0, s, inv, in, out, n); break;
+    default: hipLaunchKernelGGL(k_quantize<E2M1>, grid, block, 0, s, inv, in, out, n); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_dequantize(hipStream_t s, int fmt, float scale, const uint8_t* in, float* out, int64_t n) {
+  const dim3 grid(blocks_for((n + 15) / 16, 256)), block(256);
+  switch (fmt) {
+    case F32: hipLaunchKernelGGL(k_dequantize<F32>, grid, block, 0, s, scale, in, out, n); break;
+    case F16: hipLaunchKernelGGL(k_dequantize<F16>, grid, block, 0, s, scale, in, out, n); break;
+    case BF16: hipLaunchKernelGGL(k_dequantize<BF16>, grid, block, 0, s, scale, in, out, n); break;
+    case E4M3: hipLaunchKernelGGL(k_dequantize<E4M3>, grid, block, 0, s, scale, in, out, n); break;
+    case E5M2: hipLaunchKernelGGL(k_dequantize<E5M2>, grid, block, 0, s, scale, in, out, n); break;
+    case E3M2: hipLaunchKernelGGL(k_dequantize<E3M2>, grid, block, 0, s, scale, in, out, n); break;
+    default: hipLaunchKernelGGL(k_dequantize<E2M1>, grid, block, 0, s, scale, in, out, n); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_repack(hipStream_t s, int tensor, const TV& t, int64_t B, int ecfg, int n_s, uint8_t* flat,
+                         int direction) {
+  if (direction == 0) {
+    hipLaunchKernelGGL(k_export, dim3(blocks_for((B * ecfg + 15) / 16, 256)), dim3(256), 0, s, t, tensor, B, ecfg,
+                       flat);
+  } else {
+    int n_slots;
+    const int ng = (n_s + SPH_GROUP - 1) / SPH_GROUP;
+    switch (tensor) {
+      case T_L: n_slots = L_GROUPS; break;
+      case T_S:
+      case T_G: n_slots = ng * 3; break;
+      case T_D: n_slots = ng; break;
+      default: n_slots = 1; break;
+    }
+    hipLaunchKernelGGL(k_import, dim3(blocks_for(B * n_slots, 256)), dim3(256), 0, s, t, tensor, B, ecfg, n_slots,
+                       n_s, (const uint8_t*)flat);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace vapr

@@ -1,0 +1,79 @@
+// Kernel argument structs and launch wrappers shared by kernels.hip and the C ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "layout.hpp"
+
+namespace vapr {
+
+struct RobotArgs {
+  const float* fixed;    // [8][12] F_1..F_8, row-major [R | t]
+  const float4* sph;     // [n_groups*16] (cx, cy, cz, r); padding spheres are zero
+  const int* link;       // [n_groups*16] link of each sphere; padding -> 0
+  const int* csr_off;    // [n_s + 1] self-pair partners of each sphere
+  const int* csr_nbr;    // [2 * n_pairs]
+  int n_s, n_groups;
+  float q_lo[N_JOINTS], q_hi[N_JOINTS];
+};
+
+struct WorldArgs {
+  const float* box;  // [W][K][16]: A = R^T row-major (9), o = A c (3), h (3), pad
+  int K;
+};
+
+struct TV {  // one stored tensor inside a workspace
+  uint32_t* p;
+  int fmt;
+  int P;
+  float scale;  // 2^k
+  float inv;    // 2^-k
+};
+
+struct ShapeArgs {
+  int64_t B;
+  int T, n_ls, tpw;
+  int64_t cfg_per_world;
+  int64_t n_tc;
+};
+
+struct CostArgs {
+  float eta, w_c, w_s, w_b, w_v;
+};
+
+struct OptArgs {
+  int n_traj, T, n_ls, m;
+  float max_step;
+  float* x;
+  float* g;
+  float* d;
+  double* cost;
+  float* s_hist;
+  float* y_hist;
+  double* rho;
+  int* hist_len;
+  int* hist_head;
+  int* accepted;
+  int* flags;
+};
+
+enum KernelId { K_FK = 0, K_SPHERE = 1, K_REDUCE = 2, K_ADJOINT = 3, K_OPT = 4, K_CODEC = 5, K_REPACK = 6, N_KERNEL_IDS = 7 };
+
+// launch wrappers (return hipError_t of the launch)
+hipError_t launch_fk(hipStream_t s, const float* q, const RobotArgs& R, const TV& L, const TV& S, float* bound,
+                     int64_t B, int store_L);
+hipError_t launch_sphere_cost(hipStream_t s, const RobotArgs& R, const WorldArgs& W, const TV& S, const TV& D,
+                              const TV& G, float* selfc, const ShapeArgs& sh, const CostArgs& cp);
+hipError_t launch_reduce(hipStream_t s, const TV& D, const float* selfc, const float* boundc, const float* q,
+                         double* cost_traj, float* cost_cfg, const ShapeArgs& sh, const CostArgs& cp, int n_s);
+hipError_t launch_adjoint(hipStream_t s, const float* q, const RobotArgs& R, const TV& L, const TV& G, const TV& J,
+                          const double* up, float* grad_q, const ShapeArgs& sh, const CostArgs& cp, int recompute);
+hipError_t launch_optimizer(hipStream_t s, const OptArgs& o, const TV& J, const double* cost_in, float* q_cand,
+                            int mode);
+hipError_t launch_quantize(hipStream_t s, int fmt, float inv, const float* in, uint8_t* out, int64_t n);
+hipError_t launch_dequantize(hipStream_t s, int fmt, float scale, const uint8_t* in, float* out, int64_t n);
+// tensor: T_L .. T_J; per-configuration element count ecfg; direction 0 export (ws -> flat), 1 import
+hipError_t launch_repack(hipStream_t s, int tensor, const TV& t, int64_t B, int ecfg, int n_s, uint8_t* flat,
+                         int direction);
+
+}  // namespace vapr

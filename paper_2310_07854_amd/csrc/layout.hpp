@@ -1,0 +1,91 @@
+// Workspace layout of the five stored tensors (Sec. III-C) in HBM.
+//
+// Every tensor is a set of dword "planes" per configuration, tiled by blocks of 64 configurations
+// (one wavefront, one configuration per lane): dword (b, p) of a tensor with P planes lives at
+//     base + ((b >> 6) * P + p) * 64 + (b & 63).
+// A wavefront therefore reads or writes 256 contiguous bytes per instruction and a block's whole
+// tensor is one contiguous run of P * 256 bytes.
+//
+// Plane contents (values packed as in codec.hpp, dw(n) = dwords of a packed group of n values):
+//   L  links 1..8, [R | t] row-major: 2 groups of 48 values (links 1-4, 5-8)   2 * dw(48) planes
+//   S  ceil(n_s/16) groups of 16 spheres x 3 components, plane = (g*3 + c)*dw(16) + w
+//   D  ceil(n_s/16) groups of 16 spheres,                plane = g*dw(16) + w
+//   G  like S
+//   J  one group of 8 values (7 joints + a zero)          dw(8) planes
+// followed by two FP32 arrays [Bp] (self cost, bound cost).  Regions are 256-byte aligned.
+#pragma once
+#include <stddef.h>
+#include <stdint.h>
+
+#include "codec.hpp"
+
+namespace vapr {
+
+constexpr int N_JOINTS = 7;
+constexpr int N_FIXED = 8;          // F_1..F_8
+constexpr int N_LINKS = 9;          // link 0 (base) .. link 8
+constexpr int LINK_VALUES = 12;
+constexpr int L_GROUP = 48;         // 4 links per packed group
+constexpr int L_GROUPS = 2;
+constexpr int SPH_GROUP = 16;
+constexpr int J_GROUP = 8;
+constexpr int MAX_SPHERES = 256;
+constexpr int MAX_PAIRS = 4096;
+constexpr int MAX_CUBOIDS = 256;
+constexpr int MAX_T = 4096;
+constexpr int MAX_LS = 4;
+constexpr int MAX_OPT_T = 64;
+constexpr int MAX_HIST = 8;
+
+struct TensorFormat {
+  int fmt;
+  int scale_exp;
+};
+
+struct PrecisionCfg {
+  TensorFormat t[5];  // L, S, D, G, J
+  int recompute;
+};
+
+enum { T_L = 0, T_S = 1, T_D = 2, T_G = 3, T_J = 4 };
+
+struct Layout {
+  int64_t B, Bp, nblk;
+  int n_s, n_groups;
+  int P[5];             // planes per tensor
+  size_t off[7];        // byte offsets: L S D G J self bound
+  size_t bytes;
+};
+
+__host__ __device__ inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+inline Layout make_layout(int64_t B, int n_s, const PrecisionCfg& pc) {
+  Layout L{};
+  L.B = B;
+  L.Bp = (B + 63) / 64 * 64;
+  L.nblk = L.Bp / 64;
+  L.n_s = n_s;
+  L.n_groups = (n_s + SPH_GROUP - 1) / SPH_GROUP;
+  L.P[T_L] = pc.recompute ? 0 : L_GROUPS * group_dwords(pc.t[T_L].fmt, L_GROUP);
+  L.P[T_S] = L.n_groups * 3 * group_dwords(pc.t[T_S].fmt, SPH_GROUP);
+  L.P[T_D] = L.n_groups * group_dwords(pc.t[T_D].fmt, SPH_GROUP);
+  L.P[T_G] = L.n_groups * 3 * group_dwords(pc.t[T_G].fmt, SPH_GROUP);
+  L.P[T_J] = group_dwords(pc.t[T_J].fmt, J_GROUP);
+  size_t o = 0;
+  for (int i = 0; i < 5; ++i) {
+    L.off[i] = o;
+    o += align256((size_t)L.P[i] * (size_t)L.Bp * 4);
+  }
+  L.off[5] = o;
+  o += align256((size_t)L.Bp * 4);
+  L.off[6] = o;
+  o += align256((size_t)L.Bp * 4);
+  L.bytes = o;
+  return L;
+}
+
+__host__ __device__ inline int64_t plane_index(int64_t b, int P, int p) {
+  return ((b >> 6) * P + p) * 64 + (b & 63);
+}
+
+}  // namespace vapr

@@ -1,0 +1,700 @@
+// Host side of the C ABI declared in include/vapr.h: argument validation, robot/world tables,
+// workspace layout and bookkeeping, kernel launches on the caller's stream, per-kernel event timing.
+#include "../../include/vapr.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "kernels.hpp"
+#include "layout.hpp"
+
+using namespace vapr;
+
+namespace {
+
+thread_local std::string g_thread_err;
+
+struct WsRecord {
+  int n_worlds, tpw, T, n_ls;
+  int64_t B;
+  PrecisionCfg prec;
+  uint64_t robot_gen;
+};
+
+struct ProfEvent {
+  int id;
+  hipEvent_t start, stop;
+};
+
+}  // namespace
+
+struct vapr_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  // robot
+  bool has_robot = false;
+  uint64_t robot_gen = 0;
+  int n_s = 0, n_groups = 0, n_pairs = 0;
+  float* d_fixed = nullptr;
+  float4* d_sph = nullptr;
+  int* d_link = nullptr;
+  int* d_csr_off = nullptr;
+  int* d_csr_nbr = nullptr;
+  float q_lo[N_JOINTS], q_hi[N_JOINTS];
+  // worlds
+  bool has_worlds = false;
+  int n_worlds = 0, n_cuboids = 0;
+  float* d_box = nullptr;
+  // settings
+  PrecisionCfg prec{};
+  CostArgs params{0.02f, 100.f, 100.f, 10.f, 1.f};
+  std::unordered_map<const void*, WsRecord> ws;
+  std::string err;
+  // profiling
+  bool prof = false;
+  std::vector<ProfEvent> prof_live;
+  std::vector<hipEvent_t> prof_pool;
+  double prof_ms[N_KERNEL_IDS] = {};
+  int64_t prof_n[N_KERNEL_IDS] = {};
+};
+
+namespace {
+
+int fail(vapr_ctx* ctx, int status, const std::string& msg) {
+  g_thread_err = msg;
+  if (ctx) ctx->err = msg;
+  return status;
+}
+
+int hip_fail(vapr_ctx* ctx, hipError_t e, const char* what) {
+  return fail(ctx, VAPR_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define VAPR_HIP(ctx, call)                                 \
+  do {                                                      \
+    hipError_t e_ = (call);                                 \
+    if (e_ != hipSuccess) return hip_fail(ctx, e_, #call);  \
+  } while (0)
+
+bool valid_format(const vapr_tensor_format& f) {
+  if (f.fmt < VAPR_F32 || f.fmt > VAPR_E2M1) return false;
+  if (f.scale_exp < -16 || f.scale_exp > 16) return false;
+  if (f.fmt == VAPR_F32 && f.scale_exp != 0) return false;
+  return true;
+}
+
+bool finite_all(const float* p, size_t n) {
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(p[i])) return false;
+  return true;
+}
+
+bool rotation_ok(const float* tf34) {
+  // rows of R are tf34[0..2], tf34[4..6], tf34[8..10]
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      double s = 0;
+      for (int k = 0; k < 3; ++k) s += (double)tf34[k * 4 + i] * (double)tf34[k * 4 + j];
+      if (std::fabs(s - (i == j ? 1.0 : 0.0)) >= 1e-5) return false;
+    }
+  return true;
+}
+
+template <typename T>
+int upload(vapr_ctx* ctx, T** dst, const T* src, size_t n) {
+  T* p = nullptr;
+  if (n == 0) n = 1;
+  hipError_t e = hipMalloc((void**)&p, n * sizeof(T));
+  if (e != hipSuccess) return fail(ctx, VAPR_E_OOM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  if (src) {
+    e = hipMemcpy(p, src, n * sizeof(T), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+      (void)hipFree(p);
+      return hip_fail(ctx, e, "hipMemcpy");
+    }
+  }
+  *dst = p;
+  return VAPR_OK;
+}
+
+void free_robot(vapr_ctx* ctx) {
+  (void)hipFree(ctx->d_fixed);
+  (void)hipFree(ctx->d_sph);
+  (void)hipFree(ctx->d_link);
+  (void)hipFree(ctx->d_csr_off);
+  (void)hipFree(ctx->d_csr_nbr);
+  ctx->d_fixed = nullptr;
+  ctx->d_sph = nullptr;
+  ctx->d_link = nullptr;
+  ctx->d_csr_off = ctx->d_csr_nbr = nullptr;
+  ctx->has_robot = false;
+}
+
+PrecisionCfg to_cfg(const vapr_precision& p) {
+  PrecisionCfg c{};
+  c.t[T_L] = {p.link_poses.fmt, p.link_poses.scale_exp};
+  c.t[T_S] = {p.sphere_pos.fmt, p.sphere_pos.scale_exp};
+  c.t[T_D] = {p.sphere_dist.fmt, p.sphere_dist.scale_exp};
+  c.t[T_G] = {p.sphere_grad.fmt, p.sphere_grad.scale_exp};
+  c.t[T_J] = {p.joint_grad.fmt, p.joint_grad.scale_exp};
+  c.recompute = p.recompute_poses ? 1 : 0;
+  return c;
+}
+
+bool same_prec(const PrecisionCfg& a, const PrecisionCfg& b) {
+  for (int i = 0; i < 5; ++i)
+    if (a.t[i].fmt != b.t[i].fmt || a.t[i].scale_exp != b.t[i].scale_exp) return false;
+  return a.recompute == b.recompute;
+}
+
+TV tensor_view(void* ws, const Layout& L, const PrecisionCfg& pc, int t) {
+  TV v;
+  v.p = reinterpret_cast<uint32_t*>(static_cast<char*>(ws) + L.off[t]);
+  v.fmt = pc.t[t].fmt;
+  v.P = L.P[t];
+  v.scale = std::ldexp(1.0f, pc.t[t].scale_exp);
+  v.inv = std::ldexp(1.0f, -pc.t[t].scale_exp);
+  return v;
+}
+
+RobotArgs robot_args(const vapr_ctx* ctx) {
+  RobotArgs R{};
+  R.fixed = ctx->d_fixed;
+  R.sph = ctx->d_sph;
+  R.link = ctx->d_link;
+  R.csr_off = ctx->d_csr_off;
+  R.csr_nbr = ctx->d_csr_nbr;
+  R.n_s = ctx->n_s;
+  R.n_groups = ctx->n_groups;
+  for (int j = 0; j < N_JOINTS; ++j) {
+    R.q_lo[j] = ctx->q_lo[j];
+    R.q_hi[j] = ctx->q_hi[j];
+  }
+  return R;
+}
+
+int check_shape(vapr_ctx* ctx, int n_worlds, int tpw, int T, int n_ls, int64_t* B) {
+  if (!ctx) return fail(nullptr, VAPR_E_INVALID, "null context");
+  if (!ctx->has_robot) return fail(ctx, VAPR_E_STATE, "no robot uploaded");
+  if (n_worlds < 1 || tpw < 1 || T < 1 || T > MAX_T || n_ls < 1 || n_ls > MAX_LS)
+    return fail(ctx, VAPR_E_INVALID, "batch shape out of range");
+  const int64_t b = (int64_t)n_worlds * tpw * n_ls * T;
+  if (b > ((int64_t)1 << 31)) return fail(ctx, VAPR_E_INVALID, "batch too large");
+  *B = b;
+  return VAPR_OK;
+}
+
+ShapeArgs shape_args(int n_worlds, int tpw, int T, int n_ls) {
+  ShapeArgs sh;
+  sh.T = T;
+  sh.n_ls = n_ls;
+  sh.tpw = tpw;
+  sh.cfg_per_world = (int64_t)tpw * n_ls * T;
+  sh.n_tc = (int64_t)n_worlds * tpw * n_ls;
+  sh.B = sh.n_tc * T;
+  return sh;
+}
+
+// timed launch helper
+template <typename F>
+int timed(vapr_ctx* ctx, int id, F&& launch, const char* what) {
+  hipEvent_t a = nullptr, b = nullptr;
+  if (ctx && ctx->prof) {
+    for (hipEvent_t* ev : {&a, &b}) {
+      if (!ctx->prof_pool.empty()) {
+        *ev = ctx->prof_pool.back();
+        ctx->prof_pool.pop_back();
+      } else {
+        VAPR_HIP(ctx, hipEventCreate(ev));
+      }
+    }
+    VAPR_HIP(ctx, hipEventRecord(a, ctx->stream));
+  }
+  hipError_t e = launch();
+  if (e != hipSuccess) return hip_fail(ctx, e, what);
+  if (ctx && ctx->prof) {
+    VAPR_HIP(ctx, hipEventRecord(b, ctx->stream));
+    ctx->prof_live.push_back({id, a, b});
+  }
+  return VAPR_OK;
+}
+
+int run_fwd(vapr_ctx* ctx, int first, int n_worlds, int tpw, int T, int n_ls, const float* q, void* ws,
+            size_t ws_bytes, double* cost_traj, float* cost_cfg) {
+  int64_t B;
+  int st = check_shape(ctx, n_worlds, tpw, T, n_ls, &B);
+  if (st) return st;
+  if (first < 1 || first > 3) return fail(ctx, VAPR_E_INVALID, "first stage must be 1, 2 or 3");
+  if (!ctx->has_worlds) return fail(ctx, VAPR_E_STATE, "no worlds uploaded");
+  if (n_worlds > ctx->n_worlds) return fail(ctx, VAPR_E_INVALID, "n_worlds exceeds the uploaded worlds");
+  if (!q || !ws || !cost_traj) return fail(ctx, VAPR_E_INVALID, "null pointer");
+  const Layout L = make_layout(B, ctx->n_s, ctx->prec);
+  if (ws_bytes < L.bytes) return fail(ctx, VAPR_E_INVALID, "workspace too small");
+  if (first >= 2) {
+    auto it = ctx->ws.find(ws);
+    if (it == ctx->ws.end() || it->second.B != B || !same_prec(it->second.prec, ctx->prec) ||
+        it->second.robot_gen != ctx->robot_gen)
+      return fail(ctx, VAPR_E_STATE, "workspace does not hold this shape at the current precision");
+  }
+  const ShapeArgs sh = shape_args(n_worlds, tpw, T, n_ls);
+  const RobotArgs R = robot_args(ctx);
+  const TV tL = tensor_view(ws, L, ctx->prec, T_L), tS = tensor_view(ws, L, ctx->prec, T_S),
+           tD = tensor_view(ws, L, ctx->prec, T_D), tG = tensor_view(ws, L, ctx->prec, T_G);
+  float* selfc = reinterpret_cast<float*>(static_cast<char*>(ws) + L.off[5]);
+  float* boundc = reinterpret_cast<float*>(static_cast<char*>(ws) + L.off[6]);
+  hipStream_t s = ctx->stream;
+  if (first <= 1) {
+    st = timed(ctx, K_FK, [&] { return launch_fk(s, q, R, tL, tS, boundc, B, ctx->prec.recompute ? 0 : 1); },
+               "k_fk launch");
+    if (st) return st;
+  }
+  if (first <= 2) {
+    WorldArgs W{ctx->d_box, ctx->n_cuboids};
+    const CostArgs cp = ctx->params;
+    st = timed(ctx, K_SPHERE, [&] { return launch_sphere_cost(s, R, W, tS, tD, tG, selfc, sh, cp); },
+               "k_sphere_cost launch");
+    if (st) return st;
+  }
+  const CostArgs cp = ctx->params;
+  const int n_s = ctx->n_s;
+  st = timed(ctx, K_REDUCE, [&] { return launch_reduce(s, tD, selfc, boundc, q, cost_traj, cost_cfg, sh, cp, n_s); },
+             "k_reduce launch");
+  if (st) return st;
+  ctx->ws[ws] = WsRecord{n_worlds, tpw, T, n_ls, B, ctx->prec, ctx->robot_gen};
+  return VAPR_OK;
+}
+
+int tensor_count(const vapr_ctx* ctx, int tensor) {
+  switch (tensor) {
+    case VAPR_T_LINK_POSES: return N_FIXED * LINK_VALUES;
+    case VAPR_T_SPHERE_POS:
+    case VAPR_T_SPHERE_GRAD: return ctx->n_s * 3;
+    case VAPR_T_SPHERE_DIST: return ctx->n_s;
+    case VAPR_T_JOINT_GRAD: return N_JOINTS;
+    default: return 1;
+  }
+}
+
+int check_opt(vapr_ctx* ctx, const vapr_lbfgs_state* st, const void* ws, int init, WsRecord* rec) {
+  if (!ctx) return fail(nullptr, VAPR_E_INVALID, "null context");
+  if (!st || !ws) return fail(ctx, VAPR_E_INVALID, "null pointer");
+  if (!st->x || !st->g || !st->d || !st->cost || !st->s_hist || !st->y_hist || !st->rho || !st->hist_len ||
+      !st->hist_head || !st->accepted || !st->flags)
+    return fail(ctx, VAPR_E_INVALID, "null optimiser buffer");
+  if (st->T < 1 || st->T > MAX_OPT_T || st->n_ls < 1 || st->n_ls > MAX_LS || st->m < 1 || st->m > MAX_HIST ||
+      st->n_traj < 1 || !(st->max_step > 0.f) || !std::isfinite(st->max_step))
+    return fail(ctx, VAPR_E_INVALID, "optimiser shape out of range");
+  auto it = ctx->ws.find(ws);
+  if (it == ctx->ws.end()) return fail(ctx, VAPR_E_STATE, "workspace holds no forward pass");
+  const WsRecord& r = it->second;
+  if (!same_prec(r.prec, ctx->prec) || r.robot_gen != ctx->robot_gen)
+    return fail(ctx, VAPR_E_STATE, "workspace was filled under another precision or robot");
+  if ((int64_t)r.n_worlds * r.tpw != st->n_traj || r.T != st->T || r.n_ls != (init ? 1 : st->n_ls))
+    return fail(ctx, VAPR_E_STATE, "workspace shape does not match the optimiser state");
+  *rec = r;
+  return VAPR_OK;
+}
+
+OptArgs opt_args(const vapr_lbfgs_state* st) {
+  OptArgs o;
+  o.n_traj = st->n_traj;
+  o.T = st->T;
+  o.n_ls = st->n_ls;
+  o.m = st->m;
+  o.max_step = st->max_step;
+  o.x = st->x;
+  o.g = st->g;
+  o.d = st->d;
+  o.cost = st->cost;
+  o.s_hist = st->s_hist;
+  o.y_hist = st->y_hist;
+  o.rho = st->rho;
+  o.hist_len = st->hist_len;
+  o.hist_head = st->hist_head;
+  o.accepted = st->accepted;
+  o.flags = st->flags;
+  return o;
+}
+
+int run_opt(vapr_ctx* ctx, const vapr_lbfgs_state* st, const void* ws, size_t ws_bytes, const double* cost,
+            float* q_cand, int mode) {
+  WsRecord rec;
+  int s = check_opt(ctx, st, ws, mode == 0, &rec);
+  if (s) return s;
+  if (!cost || !q_cand) return fail(ctx, VAPR_E_INVALID, "null pointer");
+  const Layout L = make_layout(rec.B, ctx->n_s, ctx->prec);
+  if (ws_bytes < L.bytes) return fail(ctx, VAPR_E_INVALID, "workspace too small");
+  const TV tJ = tensor_view(const_cast<void*>(ws), L, ctx->prec, T_J);
+  const OptArgs o = opt_args(st);
+  return timed(ctx, K_OPT, [&] { return launch_optimizer(ctx->stream, o, tJ, cost, q_cand, mode); },
+               "k_optimizer launch");
+}
+
+}  // namespace
+
+extern "C" {
+
+int vapr_abi_version(void) { return VAPR_ABI_VERSION; }
+
+const char* vapr_status_string(int status) {
+  switch (status) {
+    case VAPR_OK: return "ok";
+    case VAPR_E_INVALID: return "invalid argument";
+    case VAPR_E_OOM: return "out of device memory";
+    case VAPR_E_HIP: return "HIP error";
+    case VAPR_E_UNSUPPORTED: return "unsupported";
+    case VAPR_E_STATE: return "invalid state";
+    default: return "unknown status";
+  }
+}
+
+const char* vapr_last_error(const vapr_ctx* ctx) { return ctx ? ctx->err.c_str() : g_thread_err.c_str(); }
+
+int vapr_create(vapr_ctx** out, int device, void* hip_stream) {
+  if (!out) return fail(nullptr, VAPR_E_INVALID, "null output pointer");
+  int n = 0;
+  hipError_t e = hipGetDeviceCount(&n);
+  if (e != hipSuccess) return hip_fail(nullptr, e, "hipGetDeviceCount");
+  if (device < 0 || device >= n) return fail(nullptr, VAPR_E_INVALID, "device index out of range");
+  e = hipSetDevice(device);
+  if (e != hipSuccess) return hip_fail(nullptr, e, "hipSetDevice");
+  vapr_ctx* c = new vapr_ctx();
+  c->device = device;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  vapr_precision p{};
+  p.link_poses = p.sphere_pos = p.sphere_dist = p.sphere_grad = p.joint_grad = {VAPR_F32, 0};
+  c->prec = to_cfg(p);
+  *out = c;
+  return VAPR_OK;
+}
+
+int vapr_destroy(vapr_ctx* ctx) {
+  if (!ctx) return VAPR_OK;
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  free_robot(ctx);
+  (void)hipFree(ctx->d_box);
+  for (auto& pe : ctx->prof_live) {
+    (void)hipEventDestroy(pe.start);
+    (void)hipEventDestroy(pe.stop);
+  }
+  for (auto ev : ctx->prof_pool) (void)hipEventDestroy(ev);
+  delete ctx;
+  return VAPR_OK;
+}
+
+int vapr_set_stream(vapr_ctx* ctx, void* hip_stream) {
+  if (!ctx) return fail(nullptr, VAPR_E_INVALID, "null context");
+  ctx->stream = static_cast<hipStream_t>(hip_stream);
+  return VAPR_OK;
+}
+
+int vapr_set_robot(vapr_ctx* ctx, int n_joints, const float* fixed_tf, int n_spheres, const float* sphere_center,
+                   const float* sphere_radius, const int32_t* sphere_link, int n_pairs, const int32_t* pairs,
+                   const float* q_lo, const float* q_hi) {
+  if (!ctx) return fail(nullptr, VAPR_E_INVALID, "null context");
+  if (n_joints != N_JOINTS) return fail(ctx, VAPR_E_UNSUPPORTED, "only 7-joint arms are supported");
+  if (!fixed_tf || !sphere_center || !sphere_radius || !sphere_link || !q_lo || !q_hi || (n_pairs > 0 && !pairs))
+    return fail(ctx, VAPR_E_INVALID, "null pointer");
+  if (n_spheres < 1 || n_spheres > MAX_SPHERES) return fail(ctx, VAPR_E_INVALID, "n_spheres out of range");
+  if (n_pairs < 0 || n_pairs > MAX_PAIRS) return fail(ctx, VAPR_E_INVALID, "n_pairs out of range");
+  if (!finite_all(fixed_tf, N_FIXED * 12) || !finite_all(sphere_center, (size_t)n_spheres * 3) ||
+      !finite_all(sphere_radius, n_spheres) || !finite_all(q_lo, N_JOINTS) || !finite_all(q_hi, N_JOINTS))
+    return fail(ctx, VAPR_E_INVALID, "non-finite robot data");
+  for (int j = 0; j < N_FIXED; ++j)
+    if (!rotation_ok(fixed_tf + j * 12)) return fail(ctx, VAPR_E_INVALID, "fixed transform is not a rotation");
+  for (int s = 0; s < n_spheres; ++s) {
+    if (!(sphere_radius[s] > 0.f)) return fail(ctx, VAPR_E_INVALID, "sphere radius must be > 0");
+    if (sphere_link[s] < 0 || sphere_link[s] >= N_LINKS) return fail(ctx, VAPR_E_INVALID, "sphere link out of range");
+  }
+  for (int j = 0; j < N_JOINTS; ++j)
+    if (q_lo[j] > q_hi[j]) return fail(ctx, VAPR_E_INVALID, "q_lo > q_hi");
+  std::vector<std::vector<int>> nbr(n_spheres);
+  for (int p = 0; p < n_pairs; ++p) {
+    const int a = pairs[2 * p], b = pairs[2 * p + 1];
+    if (a < 0 || b < 0 || a >= n_spheres || b >= n_spheres || a == b)
+      return fail(ctx, VAPR_E_INVALID, "self-collision pair out of range");
+    nbr[a].push_back(b);
+    nbr[b].push_back(a);
+  }
+  const int ng = (n_spheres + SPH_GROUP - 1) / SPH_GROUP;
+  std::vector<float4> sph((size_t)ng * SPH_GROUP, make_float4(0.f, 0.f, 0.f, 0.f));
+  std::vector<int> link((size_t)ng * SPH_GROUP, 0);
+  for (int s = 0; s < n_spheres; ++s) {
+    sph[s] = make_float4(sphere_center[3 * s], sphere_center[3 * s + 1], sphere_center[3 * s + 2], sphere_radius[s]);
+    link[s] = sphere_link[s];
+  }
+  std::vector<int> off(n_spheres + 1, 0), flat;
+  for (int s = 0; s < n_spheres; ++s) {
+    off[s + 1] = off[s] + (int)nbr[s].size();
+    for (int t : nbr[s]) flat.push_back(t);
+  }
+  if (ctx->has_robot || ctx->d_fixed) {
+    VAPR_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    free_robot(ctx);
+  }
+  int st;
+  if ((st = upload(ctx, &ctx->d_fixed, fixed_tf, N_FIXED * 12)) ||
+      (st = upload(ctx, &ctx->d_sph, sph.data(), sph.size())) ||
+      (st = upload(ctx, &ctx->d_link, link.data(), link.size())) ||
+      (st = upload(ctx, &ctx->d_csr_off, off.data(), off.size())) ||
+      (st = upload(ctx, &ctx->d_csr_nbr, flat.empty() ? nullptr : flat.data(), flat.size()))) {
+    free_robot(ctx);
+    return st;
+  }
+  ctx->n_s = n_spheres;
+  ctx->n_groups = ng;
+  ctx->n_pairs = n_pairs;
+  for (int j = 0; j < N_JOINTS; ++j) {
+    ctx->q_lo[j] = q_lo[j];
+    ctx->q_hi[j] = q_hi[j];
+  }
+  ctx->has_robot = true;
+  ctx->robot_gen++;
+  return VAPR_OK;
+}
+
+int vapr_set_worlds(vapr_ctx* ctx, int n_worlds, int n_cuboids, const float* pose, const float* half_ext) {
+  if (!ctx) return fail(nullptr, VAPR_E_INVALID, "null context");
+  if (n_worlds < 1 || n_worlds > 65536 || n_cuboids < 0 || n_cuboids > MAX_CUBOIDS)
+    return fail(ctx, VAPR_E_INVALID, "world shape out of range");
+  const size_t nb = (size_t)n_worlds * n_cuboids;
+  if (nb > 0 && (!pose || !half_ext)) return fail(ctx, VAPR_E_INVALID, "null pointer");
+  if (nb > 0 && (!finite_all(pose, nb * 12) || !finite_all(half_ext, nb * 3)))
+    return fail(ctx, VAPR_E_INVALID, "non-finite world data");
+  // per cuboid: A = R^T row-major, o = A c, h, pad
+  std::vector<float> box(nb * 16 + 16, 0.f);
+  for (size_t i = 0; i < nb; ++i) {
+    const float* P = pose + i * 12;
+    if (!rotation_ok(P)) return fail(ctx, VAPR_E_INVALID, "cuboid pose is not a rotation");
+    float* B = box.data() + i * 16;
+    for (int r = 0; r < 3; ++r) {
+      double o = 0;
+      for (int c = 0; c < 3; ++c) {
+        B[r * 3 + c] = P[c * 4 + r];
+        o += (double)P[c * 4 + r] * (double)P[c * 4 + 3];
+      }
+      B[9 + r] = (float)o;
+      const float h = half_ext[i * 3 + r];
+      if (!(h > 0.f)) return fail(ctx, VAPR_E_INVALID, "half extents must be > 0");
+      B[12 + r] = h;
+    }
+  }
+  if (ctx->d_box) {
+    VAPR_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    (void)hipFree(ctx->d_box);
+    ctx->d_box = nullptr;
+    ctx->has_worlds = false;
+  }
+  int st = upload(ctx, &ctx->d_box, box.data(), box.size());
+  if (st) return st;
+  ctx->n_worlds = n_worlds;
+  ctx->n_cuboids = n_cuboids;
+  ctx->has_worlds = true;
+  return VAPR_OK;
+}
+
+int vapr_set_precision(vapr_ctx* ctx, const vapr_precision* p) {
+  if (!ctx) return fail(nullptr, VAPR_E_INVALID, "null context");
+  if (!p) return fail(ctx, VAPR_E_INVALID, "null precision");
+  const vapr_tensor_format* f[5] = {&p->link_poses, &p->sphere_pos, &p->sphere_dist, &p->sphere_grad, &p->joint_grad};
+  for (int i = 0; i < 5; ++i)
+    if (!valid_format(*f[i])) return fail(ctx, VAPR_E_INVALID, "unknown format or scale out of range");
+  ctx->prec = to_cfg(*p);
+  return VAPR_OK;
+}
+
+int vapr_get_precision(const vapr_ctx* ctx, vapr_precision* p) {
+  if (!ctx || !p) return fail(nullptr, VAPR_E_INVALID, "null pointer");
+  vapr_tensor_format* f[5] = {&p->link_poses, &p->sphere_pos, &p->sphere_dist, &p->sphere_grad, &p->joint_grad};
+  for (int i = 0; i < 5; ++i) *f[i] = {ctx->prec.t[i].fmt, ctx->prec.t[i].scale_exp};
+  p->recompute_poses = ctx->prec.recompute;
+  return VAPR_OK;
+}
+
+int vapr_set_cost_params(vapr_ctx* ctx, const vapr_cost_params* p) {
+  if (!ctx) return fail(nullptr, VAPR_E_INVALID, "null context");
+  if (!p) return fail(ctx, VAPR_E_INVALID, "null params");
+  const float v[5] = {p->eta, p->w_coll, p->w_self, p->w_bound, p->w_smooth};
+  if (!finite_all(v, 5) || !(p->eta > 0.f) || p->w_coll < 0.f || p->w_self < 0.f || p->w_bound < 0.f ||
+      p->w_smooth < 0.f)
+    return fail(ctx, VAPR_E_INVALID, "cost parameters out of range");
+  ctx->params = CostArgs{p->eta, p->w_coll, p->w_self, p->w_bound, p->w_smooth};
+  return VAPR_OK;
+}
+
+int vapr_workspace_size(const vapr_ctx* cctx, int n_worlds, int tpw, int T, int n_ls, size_t* bytes) {
+  vapr_ctx* ctx = const_cast<vapr_ctx*>(cctx);
+  if (!bytes) return fail(ctx, VAPR_E_INVALID, "null output pointer");
+  int64_t B;
+  int st = check_shape(ctx, n_worlds, tpw, T, n_ls, &B);
+  if (st) return st;
+  *bytes = make_layout(B, ctx->n_s, ctx->prec).bytes;
+  return VAPR_OK;
+}
+
+int vapr_cost_fwd(vapr_ctx* ctx, int n_worlds, int tpw, int T, int n_ls, const float* q, void* ws, size_t ws_bytes,
+                  double* cost_traj, float* cost_cfg) {
+  return run_fwd(ctx, 1, n_worlds, tpw, T, n_ls, q, ws, ws_bytes, cost_traj, cost_cfg);
+}
+
+int vapr_cost_fwd_from(vapr_ctx* ctx, int first, int n_worlds, int tpw, int T, int n_ls, const float* q, void* ws,
+                       size_t ws_bytes, double* cost_traj, float* cost_cfg) {
+  return run_fwd(ctx, first, n_worlds, tpw, T, n_ls, q, ws, ws_bytes, cost_traj, cost_cfg);
+}
+
+int vapr_cost_bwd(vapr_ctx* ctx, const float* q, void* ws, size_t ws_bytes, const double* grad_cost_traj,
+                  float* grad_q) {
+  if (!ctx) return fail(nullptr, VAPR_E_INVALID, "null context");
+  if (!q || !ws) return fail(ctx, VAPR_E_INVALID, "null pointer");
+  auto it = ctx->ws.find(ws);
+  if (it == ctx->ws.end()) return fail(ctx, VAPR_E_STATE, "workspace holds no forward pass");
+  const WsRecord r = it->second;
+  if (!same_prec(r.prec, ctx->prec)) return fail(ctx, VAPR_E_STATE, "precision changed since the forward pass");
+  if (r.robot_gen != ctx->robot_gen) return fail(ctx, VAPR_E_STATE, "robot changed since the forward pass");
+  const Layout L = make_layout(r.B, ctx->n_s, ctx->prec);
+  if (ws_bytes < L.bytes) return fail(ctx, VAPR_E_INVALID, "workspace too small");
+  const ShapeArgs sh = shape_args(r.n_worlds, r.tpw, r.T, r.n_ls);
+  const RobotArgs R = robot_args(ctx);
+  const TV tL = tensor_view(ws, L, ctx->prec, T_L), tG = tensor_view(ws, L, ctx->prec, T_G),
+           tJ = tensor_view(ws, L, ctx->prec, T_J);
+  const CostArgs cp = ctx->params;
+  const int rec = ctx->prec.recompute;
+  return timed(ctx, K_ADJOINT,
+               [&] { return launch_adjoint(ctx->stream, q, R, tL, tG, tJ, grad_cost_traj, grad_q, sh, cp, rec); },
+               "k_adjoint launch");
+}
+
+int vapr_optimizer_init(vapr_ctx* ctx, const vapr_lbfgs_state* st, const void* ws, size_t ws_bytes,
+                        const double* cost0, float* q_cand) {
+  return run_opt(ctx, st, ws, ws_bytes, cost0, q_cand, 0);
+}
+
+int vapr_optimizer_step(vapr_ctx* ctx, const vapr_lbfgs_state* st, const void* ws, size_t ws_bytes,
+                        const double* cost_cand, float* q_cand) {
+  return run_opt(ctx, st, ws, ws_bytes, cost_cand, q_cand, 1);
+}
+
+size_t vapr_packed_bytes(int fmt, int64_t n) {
+  if (fmt < VAPR_F32 || fmt > VAPR_E2M1 || n < 0) return 0;
+  return (size_t)((n * format_bits(fmt) + 7) / 8);
+}
+
+static int codec_check(int fmt, int scale_exp, const void* in, const void* out, int64_t n) {
+  vapr_tensor_format f{fmt, scale_exp};
+  if (!valid_format(f)) return fail(nullptr, VAPR_E_INVALID, "unknown format or scale out of range");
+  if (n < 0 || n > ((int64_t)1 << 32)) return fail(nullptr, VAPR_E_INVALID, "element count out of range");
+  if (n > 0 && (!in || !out)) return fail(nullptr, VAPR_E_INVALID, "null pointer");
+  if ((reinterpret_cast<uintptr_t>(in) | reinterpret_cast<uintptr_t>(out)) & 3)
+    return fail(nullptr, VAPR_E_INVALID, "buffers must be 4-byte aligned");
+  return VAPR_OK;
+}
+
+int vapr_quantize(int fmt, int scale_exp, const float* in, void* out, int64_t n, void* hip_stream) {
+  int st = codec_check(fmt, scale_exp, in, out, n);
+  if (st || n == 0) return st;
+  hipError_t e = launch_quantize(static_cast<hipStream_t>(hip_stream), fmt, std::ldexp(1.0f, -scale_exp), in,
+                                 static_cast<uint8_t*>(out), n);
+  return e == hipSuccess ? VAPR_OK : hip_fail(nullptr, e, "k_quantize launch");
+}
+
+int vapr_dequantize(int fmt, int scale_exp, const void* in, float* out, int64_t n, void* hip_stream) {
+  int st = codec_check(fmt, scale_exp, in, out, n);
+  if (st || n == 0) return st;
+  hipError_t e = launch_dequantize(static_cast<hipStream_t>(hip_stream), fmt, std::ldexp(1.0f, scale_exp),
+                                   static_cast<const uint8_t*>(in), out, n);
+  return e == hipSuccess ? VAPR_OK : hip_fail(nullptr, e, "k_dequantize launch");
+}
+
+static int ws_io(vapr_ctx* ctx, int n_worlds, int tpw, int T, int n_ls, void* ws, size_t ws_bytes, int tensor,
+                 void* buf, size_t buf_bytes, int direction) {
+  int64_t B;
+  int st = check_shape(ctx, n_worlds, tpw, T, n_ls, &B);
+  if (st) return st;
+  if (!ws || !buf) return fail(ctx, VAPR_E_INVALID, "null pointer");
+  if (tensor < VAPR_T_LINK_POSES || tensor > VAPR_T_BOUND_COST) return fail(ctx, VAPR_E_INVALID, "unknown tensor");
+  const Layout L = make_layout(B, ctx->n_s, ctx->prec);
+  if (ws_bytes < L.bytes) return fail(ctx, VAPR_E_INVALID, "workspace too small");
+  if (direction == 0) {
+    auto it = ctx->ws.find(ws);
+    if (it == ctx->ws.end() || it->second.B != B || !same_prec(it->second.prec, ctx->prec))
+      return fail(ctx, VAPR_E_STATE, "workspace does not hold this shape at the current precision");
+  }
+  if (tensor >= VAPR_T_SELF_COST) {
+    if (buf_bytes < (size_t)B * 4) return fail(ctx, VAPR_E_INVALID, "buffer too small");
+    char* arr = static_cast<char*>(ws) + L.off[tensor == VAPR_T_SELF_COST ? 5 : 6];
+    st = timed(ctx, K_REPACK,
+               [&] {
+                 return direction == 0 ? hipMemcpyAsync(buf, arr, (size_t)B * 4, hipMemcpyDeviceToDevice, ctx->stream)
+                                       : hipMemcpyAsync(arr, buf, (size_t)B * 4, hipMemcpyDeviceToDevice, ctx->stream);
+               },
+               "scalar copy");
+  } else {
+    if (tensor == VAPR_T_LINK_POSES && ctx->prec.recompute)
+      return fail(ctx, VAPR_E_INVALID, "no link-pose tensor in recompute mode");
+    const int ecfg = tensor_count(ctx, tensor);
+    const int fmt = ctx->prec.t[tensor].fmt;
+    if (buf_bytes < vapr_packed_bytes(fmt, B * ecfg)) return fail(ctx, VAPR_E_INVALID, "buffer too small");
+    const TV tv = tensor_view(ws, L, ctx->prec, tensor);
+    const int n_s = ctx->n_s;
+    st = timed(ctx, K_REPACK,
+               [&] { return launch_repack(ctx->stream, tensor, tv, B, ecfg, n_s, static_cast<uint8_t*>(buf), direction); },
+               "repack launch");
+  }
+  if (st) return st;
+  if (direction == 1) ctx->ws[ws] = WsRecord{n_worlds, tpw, T, n_ls, B, ctx->prec, ctx->robot_gen};
+  return VAPR_OK;
+}
+
+int vapr_ws_export(vapr_ctx* ctx, int n_worlds, int tpw, int T, int n_ls, const void* ws, size_t ws_bytes, int tensor,
+                   void* out, size_t out_bytes) {
+  return ws_io(ctx, n_worlds, tpw, T, n_ls, const_cast<void*>(ws), ws_bytes, tensor, out, out_bytes, 0);
+}
+
+int vapr_ws_import(vapr_ctx* ctx, int n_worlds, int tpw, int T, int n_ls, void* ws, size_t ws_bytes, int tensor,
+                   const void* in, size_t in_bytes) {
+  return ws_io(ctx, n_worlds, tpw, T, n_ls, ws, ws_bytes, tensor, const_cast<void*>(in), in_bytes, 1);
+}
+
+int vapr_profile_enable(vapr_ctx* ctx, int enable) {
+  if (!ctx) return fail(nullptr, VAPR_E_INVALID, "null context");
+  for (auto& pe : ctx->prof_live) {
+    ctx->prof_pool.push_back(pe.start);
+    ctx->prof_pool.push_back(pe.stop);
+  }
+  ctx->prof_live.clear();
+  for (int i = 0; i < N_KERNEL_IDS; ++i) {
+    ctx->prof_ms[i] = 0;
+    ctx->prof_n[i] = 0;
+  }
+  ctx->prof = enable != 0;
+  return VAPR_OK;
+}
+
+int vapr_profile_read(vapr_ctx* ctx, double* total_ms, int64_t* launches, int n_ids) {
+  if (!ctx) return fail(nullptr, VAPR_E_INVALID, "null context");
+  if (n_ids < 0 || (n_ids > 0 && (!total_ms || !launches))) return fail(ctx, VAPR_E_INVALID, "bad output arrays");
+  VAPR_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  for (auto& pe : ctx->prof_live) {
+    float ms = 0.f;
+    VAPR_HIP(ctx, hipEventElapsedTime(&ms, pe.start, pe.stop));
+    ctx->prof_ms[pe.id] += ms;
+    ctx->prof_n[pe.id] += 1;
+    ctx->prof_pool.push_back(pe.start);
+    ctx->prof_pool.push_back(pe.stop);
+  }
+  ctx->prof_live.clear();
+  for (int i = 0; i < n_ids; ++i) {
+    total_ms[i] = i < N_KERNEL_IDS ? ctx->prof_ms[i] : 0.0;
+    launches[i] = i < N_KERNEL_IDS ? ctx->prof_n[i] : 0;
+  }
+  return VAPR_OK;
+}
+
+}  // extern "C"

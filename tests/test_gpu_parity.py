@@ -1,0 +1,302 @@
+"""GPU cost path against the FP64 oracle.
+
+* FP32 end to end (tiny and batched workloads): trajectory costs within the derived cost tolerance,
+  joint gradients within the gradient tolerance on kink-free configurations.
+* Every stage under reduced formats, each fed the oracle's own stored inputs through workspace
+  import: stored codes equal the oracle's except, by at most one step, where the oracle value lies
+  within float32 computation error of a rounding boundary.
+* Ragged and degenerate shapes, the full 196,608-configuration batch on sampled trajectories,
+  determinism, the autograd Function, and error paths.
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+
+from oracle import cost as OC
+from oracle import formats as F
+from synthetic import Worlds, make_configs, make_robot, make_workload, make_worlds
+from synthetic.generators import Workload
+from tests.gpu_helpers import (ORACLE_KEY, TENSORS, compare_codes, cost_tolerance, dev, export_codes, grad_tolerance,
+                               import_codes, kink_free, make_context, need_gpu, oracle_precision, shape_of, torch)
+
+pytestmark = pytest.mark.gpu
+
+PRECISIONS = {
+    "f16": {t: "f16" for t in TENSORS},
+    "bf16": {t: "bf16" for t in TENSORS},
+    "fp8": {"link_poses": ("e4m3", -7), "sphere_pos": ("e4m3", -7), "sphere_dist": ("e4m3", -10),
+            "sphere_grad": ("e5m2", -9), "joint_grad": ("e5m2", -5)},
+    "fp6": {"link_poses": ("e3m2", -3), "sphere_pos": ("e3m2", -3), "sphere_dist": ("e3m2", -6),
+            "sphere_grad": ("e3m2", 2), "joint_grad": ("e3m2", 6)},
+    "mixed_fp4": {"link_poses": ("e4m3", -7), "sphere_pos": ("e4m3", -7), "sphere_dist": ("e2m1", -3),
+                  "sphere_grad": ("e2m1", 5), "joint_grad": ("e4m3", 2)},
+    "paper_like": {"link_poses": "f16", "sphere_pos": "f16", "sphere_dist": ("e2m1", -3),
+                   "sphere_grad": ("e2m1", 5), "joint_grad": ("e4m3", 2)},
+}
+
+
+def dense_workload(seed=11, n_worlds=2, tpw=8, T=8, n_ls=4, n_spheres=60, n_cuboids=40, n_pairs=300):
+    """Collision-rich variant: cuboids twice the standard size and joint angles reaching past the
+    limits, so that many spheres, pairs and limits are active."""
+    robot = make_robot(n_spheres, n_pairs, seed=seed)
+    w = make_worlds(n_worlds, n_cuboids, seed=seed)
+    w = Worlds(pose=w.pose, half_ext=(w.half_ext * 2.0).astype(np.float32).astype(np.float64))
+    B = n_worlds * tpw * n_ls * T
+    q = make_configs(B, seed=seed, lo=-3.2, hi=3.2)
+    return Workload("dense", robot, w, tpw, T, n_ls, q)
+
+
+def run_gpu(ctx, wl, upstream=None):
+    shape = shape_of(wl)
+    q = dev(wl.q, torch.float32)
+    cost, ws = ctx.cost_fwd(q, shape)
+    up = dev(upstream, torch.float64) if upstream is not None else None
+    grad = ctx.cost_bwd(q, ws, up)
+    torch.cuda.synchronize()
+    return cost.cpu().numpy(), grad.cpu().numpy(), ws, shape, q
+
+
+def run_oracle(wl, prec=None, recompute=False, upstream=None):
+    return OC.fwd_bwd(wl.robot, wl.worlds, wl.q, wl.traj_per_world, wl.T, wl.n_ls,
+                      prec=oracle_precision(prec, recompute), upstream=upstream)
+
+
+def check_fp32(wl, ref, cost, grad):
+    tol = cost_tolerance(ref, wl.robot.n_pairs, wl.T)
+    err = np.abs(cost - ref["cost_traj"])
+    assert np.all(err <= tol), f"cost: max err {err.max():.3e}, worst ratio {(err / tol).max():.3f}"
+    ok = kink_free(ref)
+    gerr = np.abs(grad - ref["grad_q"])
+    gtol = grad_tolerance(ref)
+    bad = (gerr > gtol).any(axis=1) & ok
+    assert not bad.any(), f"grad: {int(bad.sum())} configs out of tolerance, max err {gerr[ok].max():.3e}"
+    assert ok.mean() > 0.5
+
+
+@pytest.mark.parametrize("name", ["tiny", "batched"])
+def test_fp32_end_to_end(name):
+    need_gpu()
+    wl = make_workload(name)
+    ctx = make_context(wl)
+    cost, grad, ws, shape, _ = run_gpu(ctx, wl)
+    ref = run_oracle(wl, {})
+    check_fp32(wl, ref, cost, grad)
+    # stored FP32 tensors: positions and poses to float32 computation accuracy
+    S = export_codes(ctx, "sphere_pos", ws, shape).view(np.float32).reshape(ref["S"].shape)
+    assert np.abs(S - ref["S"]).max() < 4e-6
+    Lv = export_codes(ctx, "link_poses", ws, shape).view(np.float32).reshape(ref["L"].shape)
+    assert np.abs(Lv - ref["L"]).max() < 4e-6
+    D = export_codes(ctx, "sphere_dist", ws, shape).view(np.float32).reshape(ref["D"].shape)
+    assert np.abs(D - ref["D"]).max() < 8e-6
+
+
+def test_fp32_dense_with_upstream_and_recompute():
+    need_gpu()
+    wl = dense_workload()
+    up = np.random.default_rng(3).uniform(-2, 2, size=wl.B // wl.T)
+    for recompute in (False, True):
+        ctx = make_context(wl, {}, recompute)
+        cost, grad, _, _, _ = run_gpu(ctx, wl, up)
+        ref = run_oracle(wl, {}, recompute, up)
+        assert (ref["D"] > 0).mean() > 0.05
+        check_fp32(wl, ref, cost, grad)
+
+
+@pytest.mark.parametrize("pname", list(PRECISIONS))
+def test_stage_fk_codes(pname):
+    need_gpu()
+    prec = PRECISIONS[pname]
+    wl = dense_workload()
+    ctx = make_context(wl, prec)
+    _, _, ws, shape, _ = run_gpu(ctx, wl)
+    ref = run_oracle(wl, prec)
+    for name in ("link_poses", "sphere_pos"):
+        fmt, k = ctx.precision[name]
+        got = export_codes(ctx, name, ws, shape)
+        compare_codes(name, fmt, k, got, ref[ORACLE_KEY[name] + "_codes"], ref[ORACLE_KEY[name]])
+
+
+@pytest.mark.parametrize("pname", list(PRECISIONS))
+def test_stage_sphere_cost_codes(pname):
+    need_gpu()
+    prec = PRECISIONS[pname]
+    wl = dense_workload()
+    ctx = make_context(wl, prec)
+    ref = run_oracle(wl, prec)
+    shape = shape_of(wl)
+    q = dev(wl.q, torch.float32)
+    ws = ctx.new_workspace(shape)
+    import_codes(ctx, "sphere_pos", ws, shape, ref["S_codes"])
+    ctx.ws_import("bound_cost", ws, shape, dev(ref["bound_cost"], torch.float32))
+    cost, _ = ctx.cost_fwd(q, shape, ws=ws, first=2)
+    torch.cuda.synchronize()
+    # spheres whose closest cuboid or inside axis is within 1e-4 of switching have a set-valued
+    # gradient; their G is not compared
+    kink = (ref["D"] > 0) & (ref["margin"] < 1e-4)
+    for name in ("sphere_dist", "sphere_grad"):
+        fmt, k = ctx.precision[name]
+        got = export_codes(ctx, name, ws, shape)
+        ex = np.repeat(kink[..., None], 3, axis=2) if name == "sphere_grad" else None
+        compare_codes(name, fmt, k, got, ref[ORACLE_KEY[name] + "_codes"], ref[ORACLE_KEY[name]], ex)
+    sc = ctx.ws_export("self_cost", ws, shape).cpu().numpy()
+    np.testing.assert_allclose(sc, ref["self_cost"], rtol=2e-5, atol=2e-4)
+
+
+@pytest.mark.parametrize("pname", ["f16", "fp8", "mixed_fp4"])
+def test_stage_reduce(pname):
+    need_gpu()
+    prec = PRECISIONS[pname]
+    wl = dense_workload()
+    ctx = make_context(wl, prec)
+    ref = run_oracle(wl, prec)
+    shape = shape_of(wl)
+    q = dev(wl.q, torch.float32)
+    ws = ctx.new_workspace(shape)
+    import_codes(ctx, "sphere_dist", ws, shape, ref["D_codes"])
+    ctx.ws_import("self_cost", ws, shape, dev(ref["self_cost"], torch.float32))
+    ctx.ws_import("bound_cost", ws, shape, dev(ref["bound_cost"], torch.float32))
+    cfg = torch.empty(shape.B, dtype=torch.float32, device="cuda:0")
+    cost, _ = ctx.cost_fwd(q, shape, ws=ws, first=3, cost_cfg=cfg)
+    # identical stored inputs: only FP64 summation order and the FP32 q differences remain
+    np.testing.assert_allclose(cost.cpu().numpy(), ref["cost_traj"], rtol=1e-9, atol=1e-9)
+    np.testing.assert_allclose(cfg.cpu().numpy(), ref["cfg_cost"], rtol=1e-6, atol=1e-6)
+
+
+@pytest.mark.parametrize("pname", list(PRECISIONS))
+@pytest.mark.parametrize("recompute", [False, True])
+def test_stage_adjoint_codes(pname, recompute):
+    need_gpu()
+    prec = PRECISIONS[pname]
+    wl = dense_workload()
+    up = np.random.default_rng(5).uniform(0.5, 2.0, size=wl.B // wl.T)
+    ctx = make_context(wl, prec, recompute)
+    ref = run_oracle(wl, prec, recompute, up)
+    shape = shape_of(wl)
+    q = dev(wl.q, torch.float32)
+    ws = ctx.new_workspace(shape)
+    if not recompute:
+        import_codes(ctx, "link_poses", ws, shape, ref["L_codes"])
+    import_codes(ctx, "sphere_grad", ws, shape, ref["G_codes"])
+    grad = ctx.cost_bwd(q, ws, dev(up, torch.float64))
+    torch.cuda.synchronize()
+    fmt, k = ctx.precision["joint_grad"]
+    got = export_codes(ctx, "joint_grad", ws, shape)
+    compare_codes("joint_grad", fmt, k, got, ref["J_codes"], ref["J"])
+    # grad_q is the dequantised stored gradient
+    np.testing.assert_array_equal(grad.cpu().numpy().astype(np.float64).reshape(-1),
+                                  F.dequantize(got, fmt, k))
+
+
+@pytest.mark.parametrize("case", ["ragged", "no_cuboids", "no_pairs", "one_sphere", "worlds_in_wave"])
+def test_edge_shapes(case):
+    need_gpu()
+    kw = dict(seed=21, n_worlds=3, tpw=3, T=5, n_ls=2, n_spheres=37, n_cuboids=7, n_pairs=40)
+    if case == "no_cuboids":
+        kw["n_cuboids"] = 0
+    if case == "no_pairs":
+        kw["n_pairs"] = 0
+    if case == "one_sphere":
+        kw.update(n_spheres=1, n_pairs=0)
+    if case == "worlds_in_wave":
+        kw.update(n_worlds=9, tpw=1, T=4, n_ls=1)
+    wl = dense_workload(**kw)
+    ctx = make_context(wl, {})
+    cost, grad, _, _, _ = run_gpu(ctx, wl)
+    ref = run_oracle(wl, {})
+    check_fp32(wl, ref, cost, grad)
+
+
+def _sampled_oracle(wl, tcs, prec):
+    """Oracle on whole trajectory candidates `tcs` of a workload, each in its own world."""
+    T = wl.T
+    rows = np.concatenate([np.arange(tc * T, (tc + 1) * T) for tc in tcs])
+    worlds = [(tc // wl.n_ls) // wl.traj_per_world for tc in tcs]
+    sub = Worlds(pose=wl.worlds.pose[worlds], half_ext=wl.worlds.half_ext[worlds])
+    ref = OC.fwd_bwd(wl.robot, sub, wl.q[rows], 1, T, 1, prec=oracle_precision(prec))
+    return ref, rows
+
+
+@pytest.mark.parametrize("pname", ["f32", "fp8"])
+def test_large_batch_sampled(pname):
+    need_gpu()
+    prec = {} if pname == "f32" else PRECISIONS[pname]
+    wl = make_workload("large")
+    ctx = make_context(wl, prec)
+    cost, grad, ws, shape, _ = run_gpu(ctx, wl)
+    rng = np.random.default_rng(7)
+    tcs = np.sort(rng.choice(shape.n_tc, size=12, replace=False))
+    tcs[-1] = shape.n_tc - 1
+    ref, rows = _sampled_oracle(wl, tcs, prec)
+    if pname == "f32":
+        sub = dataclasses.replace(wl, q=wl.q[rows])
+        check_fp32(sub, ref, cost[tcs], grad[rows])
+    else:
+        S = export_codes(ctx, "sphere_pos", ws, shape).reshape(shape.B, -1)[rows]
+        fmt, k = ctx.precision["sphere_pos"]
+        compare_codes("sphere_pos", fmt, k, S, ref["S_codes"], ref["S"])
+        assert np.all(np.isfinite(cost)) and np.all(np.isfinite(grad))
+
+
+def test_deterministic():
+    need_gpu()
+    wl = dense_workload()
+    ctx = make_context(wl, PRECISIONS["mixed_fp4"])
+    c1, g1, ws1, shape, _ = run_gpu(ctx, wl)
+    c2, g2, ws2, _, _ = run_gpu(ctx, wl)
+    assert np.array_equal(c1, c2) and np.array_equal(g1, g2)
+    for name in TENSORS:
+        assert np.array_equal(export_codes(ctx, name, ws1, shape), export_codes(ctx, name, ws2, shape))
+
+
+def test_autograd_function():
+    need_gpu()
+    from paper_2310_07854_amd import trajectory_cost
+
+    wl = dense_workload()
+    ctx = make_context(wl, {})
+    shape = shape_of(wl)
+    w = np.random.default_rng(9).uniform(0.5, 1.5, size=shape.n_tc)
+    q = dev(wl.q, torch.float32).requires_grad_(True)
+    loss = (trajectory_cost(q, ctx, shape) * dev(w)).sum()
+    loss.backward()
+    ref = run_oracle(wl, {}, False, w)
+    ok = kink_free(ref)
+    g = q.grad.cpu().numpy()
+    assert np.all(np.abs(g - ref["grad_q"])[ok] <= grad_tolerance(ref)[ok])
+    # central differences of the GPU cost itself on a few coordinates
+    rng = np.random.default_rng(10)
+    for b in rng.choice(np.nonzero(ok)[0], size=6, replace=False):
+        j = int(rng.integers(0, 7))
+        h = 1e-3
+        qp, qm = q.detach().clone(), q.detach().clone()
+        qp[b, j] += h
+        qm[b, j] -= h
+        fd = ((trajectory_cost(qp, ctx, shape) - trajectory_cost(qm, ctx, shape)) * dev(w)).sum().item() / (2 * h)
+        assert fd == pytest.approx(g[b, j], rel=2e-2, abs=0.5)
+
+
+def test_error_paths():
+    need_gpu()
+    from paper_2310_07854_amd import VaprError, _lib as L
+
+    wl = make_workload("tiny")
+    ctx = make_context(wl, {})
+    shape = shape_of(wl)
+    q = dev(wl.q, torch.float32)
+    cost, ws = ctx.cost_fwd(q, shape)
+    ctx.set_precision({"sphere_pos": "f16"})
+    with pytest.raises(VaprError) as e:
+        ctx.cost_bwd(q, ws)
+    assert e.value.status == L.E_STATE
+    with pytest.raises(VaprError) as e:
+        ctx.cost_fwd(q, shape, ws=ws[:16])
+    assert e.value.status == L.E_INVALID
+    bad = dataclasses.replace(wl.robot, fixed_tf=wl.robot.fixed_tf * 2.0)
+    with pytest.raises(VaprError) as e:
+        ctx.set_robot(bad)
+    assert e.value.status == L.E_INVALID
+    fresh = ctx.new_workspace(shape)
+    with pytest.raises(VaprError) as e:
+        ctx.cost_bwd(q, fresh)
+    assert e.value.status == L.E_STATE
