@@ -207,7 +207,8 @@ def fwd_bwd(robot, worlds, q: np.ndarray, traj_per_world: int, T: int, n_ls: int
     # (3) costs from the stored sphere positions
     d, gdir, kstar, margin = world_term(S_hat, robot.sphere_radius, worlds.pose, worlds.half_ext, wid, eta)
     scost, sgrad, min_pair = self_term(S_hat, robot.sphere_radius, robot.pairs, eta)
-    G = -2.0 * params.w_coll * d[..., None] * gdir + params.w_self * sgrad
+    # an inactive sphere (d = 0) contributes an exact zero (+0), not -0 from the product
+    G = np.where(d[..., None] > 0, -2.0 * params.w_coll * d[..., None] * gdir, 0.0) + params.w_self * sgrad
     out["D_codes"], D_hat = _store(d, prec, "sphere_dist")
     out["G_codes"], G_hat = _store(G, prec, "sphere_grad")
     if prec is not None and emulate_scalars:

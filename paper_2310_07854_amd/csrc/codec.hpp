@@ -177,6 +177,21 @@ __device__ __forceinline__ void fp4_unpack2(uint32_t w, float& a, float& b) {
   b = p[1];
 }
 
+// The FP6 converts read their multi-register sources over several cycles while writing the
+// result: the result registers must not overlap the sources (the early-clobber "=&v" below), which
+// the compiler does not otherwise guarantee for these instructions.
+__device__ __forceinline__ u32x6 fp6_pack32(f32x16 a, f32x16 b) {
+  u32x6 o;
+  asm volatile("v_cvt_scalef32_2xpk16_bf6_f32 %0, %1, %2, 1.0" : "=&v"(o) : "v"(a), "v"(b));
+  return o;
+}
+
+__device__ __forceinline__ f32x32 fp6_unpack32(u32x6 w) {
+  f32x32 o;
+  asm volatile("v_cvt_scalef32_pk32_f32_bf6 %0, %1, 1.0" : "=&v"(o) : "v"(w));
+  return o;
+}
+
 // encode N values (scaled by inv = 2^-k first) and pack them
 template <int F, int N>
 __device__ __forceinline__ void encode_group(const float (&v)[N], float inv, uint32_t (&w)[group_dwords(F, N)]) {
@@ -186,7 +201,11 @@ __device__ __forceinline__ void encode_group(const float (&v)[N], float inv, uin
   } else if constexpr (F == F16) {
 #pragma unroll
     for (int i = 0; i < N / 2; ++i) {
-      const _Float16 a = (_Float16)(v[2 * i] * inv), b = (_Float16)(v[2 * i + 1] * inv);
+      // The empty asm keeps the scaled value an FP32 register: fused into v_fma_mixlo_f16 (which
+      // adds +0) a product of -0 would come out as +0.
+      float ya = v[2 * i] * inv, yb = v[2 * i + 1] * inv;
+      asm volatile("" : "+v"(ya), "+v"(yb));
+      const _Float16 a = (_Float16)ya, b = (_Float16)yb;
       w[i] = (uint32_t)__builtin_bit_cast(uint16_t, a) | ((uint32_t)__builtin_bit_cast(uint16_t, b) << 16);
     }
   } else if constexpr (F == BF16) {
@@ -219,7 +238,7 @@ __device__ __forceinline__ void encode_group(const float (&v)[N], float inv, uin
 #pragma unroll
       for (int i = 0; i < 16; ++i) a[i] = (g * 16 + i < N) ? v[g * 16 + i] * inv : 0.f;
       const f32x16 z = {};
-      const u32x6 o = __builtin_amdgcn_cvt_scalef32_2xpk16_bf6_f32(a, z, 1.0f);
+      const u32x6 o = fp6_pack32(a, z);
       if constexpr (N == 8) {
         w[0] = o[0];
         w[1] = o[1];
@@ -278,7 +297,7 @@ __device__ __forceinline__ void decode_group(const uint32_t (&w)[group_dwords(F,
         in[1] = w[3 * g + 1];
         in[2] = w[3 * g + 2];
       }
-      const f32x32 o = __builtin_amdgcn_cvt_scalef32_pk32_f32_bf6(in, 1.0f);
+      const f32x32 o = fp6_unpack32(in);
 #pragma unroll
       for (int i = 0; i < 16; ++i)
         if (g * 16 + i < N) v[g * 16 + i] = o[i];
