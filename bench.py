@@ -151,8 +151,8 @@ def cpu_baseline(prec, budget_s=15.0):
         return time.perf_counter() - t0
 
     with threadpool_limits(limits=1):
-        t_small = one(2)
-        n = int(max(2, min(N_WORLDS * TPW, 2 * budget_s / max(t_small, 1e-6))))
+        t_small = one(8)
+        n = int(max(8, min(N_WORLDS * TPW, 8 * budget_s / max(t_small, 1e-6))))
         dt = one(n)
     return {"value": n * T * N_LS / dt, "unit": "evals/s", "cores": 1, "kind": "oracle",
             "sample": f"{n} trajectories x {T} timesteps = {n * T} configurations, one iteration, "
@@ -167,7 +167,20 @@ def main():
     ap.add_argument("--precision", default="paper_like", choices=[k for k in PRECISIONS if k != "f32"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--variants", action="store_true", help="also time every other assignment")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB MiB, 5 times (profiler calibration)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+
+        n = args.copy_calibration * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_MiB": args.copy_calibration, "launches": 5}))
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (--gpus {args.gpus} requested): the cost path shards by world "
               "with no communication, so more GPUs are not exercised here.", file=sys.stderr)
