@@ -139,6 +139,13 @@ int vapr_get_precision(const vapr_ctx* ctx, vapr_precision* p);
 /* Set the cost weights (all finite, eta > 0, weights >= 0). */
 int vapr_set_cost_params(vapr_ctx* ctx, const vapr_cost_params* p);
 
+/* Exact cuboid culling in the sphere-cost stage (default on).  A voxel grid records, per world,
+ * which cuboids can come within eta + max sphere radius of each voxel; cuboids out of reach of
+ * every sphere of a wavefront are not tested.  Results are identical with and without culling (it
+ * skips only cuboids whose clearance is >= eta); enable = 0 tests every cuboid.  The grid is
+ * rebuilt on the next forward pass after the robot, the worlds or eta change. */
+int vapr_set_culling(vapr_ctx* ctx, int enable);
+
 /* Bytes of device workspace a forward/backward pass of this batch shape needs at the current
  * precision (holds L, S, D, G, J and two FP32 scalars per configuration).  Requires a robot. */
 int vapr_workspace_size(const vapr_ctx* ctx, int n_worlds, int traj_per_world, int T, int n_ls,

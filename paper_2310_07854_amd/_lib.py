@@ -64,6 +64,7 @@ SIGNATURES = {
     "vapr_set_precision": (_I, [_P, ctypes.POINTER(PrecisionC)]),
     "vapr_get_precision": (_I, [_P, ctypes.POINTER(PrecisionC)]),
     "vapr_set_cost_params": (_I, [_P, ctypes.POINTER(CostParamsC)]),
+    "vapr_set_culling": (_I, [_P, _I]),
     "vapr_workspace_size": (_I, [_P, _I, _I, _I, _I, ctypes.POINTER(_SZ)]),
     "vapr_cost_fwd": (_I, [_P, _I, _I, _I, _I, _P, _P, _SZ, _P, _P]),
     "vapr_cost_fwd_from": (_I, [_P, _I, _I, _I, _I, _I, _P, _P, _SZ, _P, _P]),

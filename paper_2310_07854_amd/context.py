@@ -139,6 +139,10 @@ class Context:
         p = L.CostParamsC(eta, w_coll, w_self, w_bound, w_smooth)
         self._call("vapr_set_cost_params", ctypes.byref(p))
 
+    def set_culling(self, enable: bool) -> None:
+        """Exact cuboid culling in the sphere-cost stage (on by default; results are identical)."""
+        self._call("vapr_set_culling", 1 if enable else 0)
+
     # -- cost path -----------------------------------------------------------------------------
     def workspace_size(self, shape: Shape) -> int:
         n = ctypes.c_size_t()

@@ -179,7 +179,8 @@ __device__ __forceinline__ void fp4_unpack2(uint32_t w, float& a, float& b) {
 
 // The FP6 converts read their multi-register sources over several cycles while writing the
 // result: the result registers must not overlap the sources (the early-clobber "=&v" below), which
-// the compiler does not otherwise guarantee for these instructions.
+// the compiler does not otherwise guarantee for these instructions.  The 2x16 packer interleaves
+// its two sources; the 32-wide unpacker returns the codes in stream order.
 __device__ __forceinline__ u32x6 fp6_pack32(f32x16 a, f32x16 b) {
   u32x6 o;
   asm volatile("v_cvt_scalef32_2xpk16_bf6_f32 %0, %1, %2, 1.0" : "=&v"(o) : "v"(a), "v"(b));
@@ -229,16 +230,20 @@ __device__ __forceinline__ void encode_group(const float (&v)[N], float inv, uin
       t = __builtin_amdgcn_cvt_scalef32_pk_fp4_f32(t, v[8 * i + 4] * inv, v[8 * i + 5] * inv, 1.0f, 2);
       w[i] = __builtin_amdgcn_cvt_scalef32_pk_fp4_f32(t, v[8 * i + 6] * inv, v[8 * i + 7] * inv, 1.0f, 3);
     }
-  } else {  // E3M2: 16 values -> 3 dwords per half of the 2x16 packer
+  } else {  // E3M2: 16 values -> 3 dwords
     static_assert(N % 16 == 0 || N == 8, "FP6 groups are 8 or a multiple of 16 values");
     constexpr int NB = (N + 15) / 16;
 #pragma unroll
     for (int g = 0; g < NB; ++g) {
-      f32x16 a;
+      // the packer interleaves its sources (output slot 2i <- a[i], 2i+1 <- b[i]): even values go
+      // to a, odd values to b, and the upper 16 slots stay zero
+      f32x16 a = {}, b = {};
 #pragma unroll
-      for (int i = 0; i < 16; ++i) a[i] = (g * 16 + i < N) ? v[g * 16 + i] * inv : 0.f;
-      const f32x16 z = {};
-      const u32x6 o = fp6_pack32(a, z);
+      for (int i = 0; i < 8; ++i) {
+        a[i] = (g * 16 + 2 * i < N) ? v[g * 16 + 2 * i] * inv : 0.f;
+        b[i] = (g * 16 + 2 * i + 1 < N) ? v[g * 16 + 2 * i + 1] * inv : 0.f;
+      }
+      const u32x6 o = fp6_pack32(a, b);
       if constexpr (N == 8) {
         w[0] = o[0];
         w[1] = o[1];

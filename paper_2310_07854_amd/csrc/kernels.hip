@@ -60,51 +60,67 @@ __device__ __forceinline__ void store_group(const TV& t, int64_t b, int slot, co
   }
 }
 
+// A lane's view of a stored tensor: plane p of the lane's configuration is base[p * 64].  The same
+// formula serves the tensor in HBM (base = block start + lane) and a block staged in LDS.
+__device__ __forceinline__ const uint32_t* lane_base(const TV& t, int64_t b) {
+  return t.p + ((b >> 6) * t.P) * 64 + (b & 63);
+}
+
 template <int F, int N>
-__device__ __forceinline__ void load_group_t(const TV& t, int64_t b, int slot, float (&v)[N]) {
+__device__ __forceinline__ void load_group_at(const uint32_t* base, int slot, float scale, float (&v)[N]) {
   constexpr int DW = group_dwords(F, N);
   uint32_t w[DW];
 #pragma unroll
-  for (int k = 0; k < DW; ++k) w[k] = t.p[plane_index(b, t.P, slot * DW + k)];
-  decode_group<F, N>(w, t.scale, v);
+  for (int k = 0; k < DW; ++k) w[k] = base[(slot * DW + k) * 64];
+  decode_group<F, N>(w, scale, v);
+}
+
+template <int N>
+__device__ __forceinline__ void load_group_fmt(int fmt, const uint32_t* base, int slot, float scale, float (&v)[N]) {
+  switch (fmt) {
+    case F32: load_group_at<F32, N>(base, slot, scale, v); break;
+    case F16: load_group_at<F16, N>(base, slot, scale, v); break;
+    case BF16: load_group_at<BF16, N>(base, slot, scale, v); break;
+    case E4M3: load_group_at<E4M3, N>(base, slot, scale, v); break;
+    case E5M2: load_group_at<E5M2, N>(base, slot, scale, v); break;
+    case E3M2: load_group_at<E3M2, N>(base, slot, scale, v); break;
+    default: load_group_at<E2M1, N>(base, slot, scale, v); break;
+  }
 }
 
 template <int N>
 __device__ __forceinline__ void load_group(const TV& t, int64_t b, int slot, float (&v)[N]) {
-  switch (t.fmt) {
-    case F32: load_group_t<F32, N>(t, b, slot, v); break;
-    case F16: load_group_t<F16, N>(t, b, slot, v); break;
-    case BF16: load_group_t<BF16, N>(t, b, slot, v); break;
-    case E4M3: load_group_t<E4M3, N>(t, b, slot, v); break;
-    case E5M2: load_group_t<E5M2, N>(t, b, slot, v); break;
-    case E3M2: load_group_t<E3M2, N>(t, b, slot, v); break;
-    default: load_group_t<E2M1, N>(t, b, slot, v); break;
-  }
+  load_group_fmt<N>(t.fmt, lane_base(t, b), slot, t.scale, v);
 }
 
-// stored value of element `pos` of the group in slot `slot` (group of N values)
+// stored value of element `pos` of the group of N values in slot `slot`
 template <int F, int N>
-__device__ __forceinline__ float load_elem_t(const TV& t, int64_t b, int slot, int pos) {
+__device__ __forceinline__ float load_elem_at(const uint32_t* base, int slot, int pos, float scale) {
   constexpr int DW = group_dwords(F, N);
   constexpr int BITS = Fmt<F>::BITS;
   const int bit = pos * BITS, wi = bit >> 5, sh = bit & 31;
-  uint64_t v = t.p[plane_index(b, t.P, slot * DW + wi)];
-  if (sh + BITS > 32) v |= (uint64_t)t.p[plane_index(b, t.P, slot * DW + wi + 1)] << 32;
+  uint64_t v = base[(slot * DW + wi) * 64];
+  if (sh + BITS > 32) v |= (uint64_t)base[(slot * DW + wi + 1) * 64] << 32;
   const uint32_t code = (uint32_t)(v >> sh) & (BITS == 32 ? 0xffffffffu : ((1u << BITS) - 1u));
-  return decode_one<F>(code, t.scale);
+  return decode_one<F>(code, scale);
+}
+
+template <int N>
+__device__ __forceinline__ float load_elem_fmt(int fmt, const uint32_t* base, int slot, int pos, float scale) {
+  switch (fmt) {
+    case F32: return load_elem_at<F32, N>(base, slot, pos, scale);
+    case F16: return load_elem_at<F16, N>(base, slot, pos, scale);
+    case BF16: return load_elem_at<BF16, N>(base, slot, pos, scale);
+    case E4M3: return load_elem_at<E4M3, N>(base, slot, pos, scale);
+    case E5M2: return load_elem_at<E5M2, N>(base, slot, pos, scale);
+    case E3M2: return load_elem_at<E3M2, N>(base, slot, pos, scale);
+    default: return load_elem_at<E2M1, N>(base, slot, pos, scale);
+  }
 }
 
 template <int N>
 __device__ __forceinline__ float load_elem(const TV& t, int64_t b, int slot, int pos) {
-  switch (t.fmt) {
-    case F32: return load_elem_t<F32, N>(t, b, slot, pos);
-    case F16: return load_elem_t<F16, N>(t, b, slot, pos);
-    case BF16: return load_elem_t<BF16, N>(t, b, slot, pos);
-    case E4M3: return load_elem_t<E4M3, N>(t, b, slot, pos);
-    case E5M2: return load_elem_t<E5M2, N>(t, b, slot, pos);
-    case E3M2: return load_elem_t<E3M2, N>(t, b, slot, pos);
-    default: return load_elem_t<E2M1, N>(t, b, slot, pos);
-  }
+  return load_elem_fmt<N>(t.fmt, lane_base(t, b), slot, pos, t.scale);
 }
 
 // stored values of a group after a round trip through the format (what a reader will see)
@@ -369,10 +385,12 @@ __global__ __launch_bounds__(256) void k_sphere_cost(RobotArgs R, WorldArgs W, T
         const float r = sphere_of(R.sph, g * SPH_GROUP + i).w;
         const float d = fmaxf(cp.eta - (sd - r), 0.f);
         dv[i] = d;
-        const float coef = -2.f * cp.w_c * d;
-        gx[i] = coef * nx;
-        gy[i] = coef * ny;
-        gz[i] = coef * nz;
+        if (d > 0.f) {
+          const float coef = -2.f * cp.w_c * d;
+          gx[i] = coef * nx;
+          gy[i] = coef * ny;
+          gz[i] = coef * nz;
+        }
       }
     }
     // self pairs: every pair is visited from both spheres; each visit adds its own sphere's
@@ -410,6 +428,189 @@ __global__ __launch_bounds__(256) void k_sphere_cost(RobotArgs R, WorldArgs W, T
     store_group<SPH_GROUP>(G, b, g * 3 + 2, gz);
   }
   selfc[b] = cp.w_s * self_acc;
+}
+
+// ---- K2 on a block staged in LDS, with exact cuboid culling -------------------------------------
+//
+// One workgroup per block of 64 configurations and one wavefront per group of 16 spheres.  The
+// block's stored sphere positions (all groups) are copied once into LDS; each wavefront decodes its
+// own group for the world term and reads self-pair partners of any group from LDS.
+//
+// Culling: a voxel grid over the region where any cuboid can be within reach holds, per world and
+// voxel, a bit per cuboid that may lie within eta + r_max (+ margin) of some point of the voxel.  A
+// cuboid without the bit has clearance >= eta for every sphere in the voxel, so it can change
+// neither the activation depth (clamped at zero) nor the closest cuboid of an active sphere: the
+// result is identical to testing every cuboid.  The wavefront tests, per sphere, the union of its
+// lanes' candidate sets, keeping the cuboid on scalar operands.
+
+__device__ __forceinline__ uint32_t wave_or(uint32_t v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v |= (uint32_t)__shfl_xor((int)v, off, 64);
+  return v;
+}
+
+__device__ __forceinline__ int voxel_of(const GridArgs& g, float x, float y, float z) {
+  const float fx = (x - g.ox) * g.inv_cell, fy = (y - g.oy) * g.inv_cell, fz = (z - g.oz) * g.inv_cell;
+  const float n = (float)g.n;
+  // also false for NaN coordinates
+  if (!(fx >= 0.f && fx < n && fy >= 0.f && fy < n && fz >= 0.f && fz < n)) return -1;
+  return ((int)fz * g.n + (int)fy) * g.n + (int)fx;
+}
+
+// one sphere against one cuboid (scalar operands), running closest-cuboid key
+__device__ __forceinline__ void cuboid_key(cptr<float> bx, float px, float py, float pz, int k, float& best,
+                                           int& bk) {
+  const float u0 = fmaf(bx[0], px, fmaf(bx[1], py, bx[2] * pz)) - bx[9];
+  const float u1 = fmaf(bx[3], px, fmaf(bx[4], py, bx[5] * pz)) - bx[10];
+  const float u2 = fmaf(bx[6], px, fmaf(bx[7], py, bx[8] * pz)) - bx[11];
+  const float a0 = fabsf(u0) - bx[12], a1 = fabsf(u1) - bx[13], a2 = fabsf(u2) - bx[14];
+  const float m0 = fmaxf(a0, 0.f), m1 = fmaxf(a1, 0.f), m2 = fmaxf(a2, 0.f);
+  const float key = fmaf(m0, m0, fmaf(m1, m1, m2 * m2)) + fminf(fmaxf(fmaxf(a0, a1), a2), 0.f);
+  if (key < best) {
+    best = key;
+    bk = k;
+  }
+}
+
+__global__ __launch_bounds__(512) void k_sphere_cost_blk(RobotArgs R, WorldArgs W, GridArgs Gd, TV S, TV D, TV G,
+                                                          float* __restrict__ selfc, ShapeArgs sh, CostArgs cp) {
+  extern __shared__ uint32_t lds[];
+  const int lane = threadIdx.x & 63;
+  const int g = uniform(threadIdx.x >> 6);
+  const int ng = uniform(R.n_groups);
+  const int n_s = uniform(R.n_s);
+  const int K = uniform(W.K);
+  const int64_t blk = blockIdx.x;
+  const int64_t b = blk * 64 + lane;
+  const bool valid = b < sh.B;
+  const int P = S.P;
+
+  // stage the block's stored positions: P planes x 64 dwords, contiguous in HBM
+  {
+    const uint4* src = reinterpret_cast<const uint4*>(S.p + blk * (int64_t)P * 64);
+    uint4* dst = reinterpret_cast<uint4*>(lds);
+    for (int i = threadIdx.x; i < P * 16; i += blockDim.x) dst[i] = src[i];
+  }
+  float* part = reinterpret_cast<float*>(lds + P * 64);  // [ng][64] self-cost partials
+  __syncthreads();
+  const uint32_t* sb = lds + lane;
+
+  const int64_t first = blk * 64;
+  const int64_t last = (first + 63 < sh.B ? first + 63 : sh.B - 1);
+  const int w_lo = uniform((int)(first / sh.cfg_per_world));
+  const int w_hi = uniform((int)(last / sh.cfg_per_world));
+  const int my_w = valid ? (int)(b / sh.cfg_per_world) : -1;
+  const int active = uniform(min(SPH_GROUP, n_s - g * SPH_GROUP));
+
+  float px[SPH_GROUP], py[SPH_GROUP], pz[SPH_GROUP];
+  load_group_fmt<SPH_GROUP>(S.fmt, sb, g * 3 + 0, S.scale, px);
+  load_group_fmt<SPH_GROUP>(S.fmt, sb, g * 3 + 1, S.scale, py);
+  load_group_fmt<SPH_GROUP>(S.fmt, sb, g * 3 + 2, S.scale, pz);
+  float best[SPH_GROUP];
+  int bk[SPH_GROUP];
+#pragma unroll
+  for (int i = 0; i < SPH_GROUP; ++i) {
+    best[i] = INFINITY;
+    bk[i] = 0;
+  }
+
+  if (Gd.MW > 0) {
+    int vox[SPH_GROUP];
+#pragma unroll
+    for (int i = 0; i < SPH_GROUP; ++i) vox[i] = voxel_of(Gd, px[i], py[i], pz[i]);
+    const int64_t n3 = (int64_t)Gd.n * Gd.n * Gd.n;
+    for (int w = w_lo; w <= w_hi; ++w) {
+      const int wu = uniform(w);
+      const cptr<float> wbox = as_const(W.box) + (int64_t)wu * K * 16;
+#pragma unroll
+      for (int i = 0; i < SPH_GROUP; ++i) {
+        if (i >= active) continue;
+        for (int mw = 0; mw < Gd.MW; ++mw) {
+          uint32_t m = 0;
+          if (my_w == wu && vox[i] >= 0) m = Gd.mask[((int64_t)wu * n3 + vox[i]) * Gd.MW + mw];
+          m = (uint32_t)uniform((int)wave_or(m));
+          if (my_w == wu) {
+            while (m) {
+              const int k = mw * 32 + __builtin_ctz(m);
+              m &= m - 1;
+              cuboid_key(wbox + k * 16, px[i], py[i], pz[i], k, best[i], bk[i]);
+            }
+          }
+        }
+      }
+    }
+  } else {
+    for (int w = w_lo; w <= w_hi; ++w) {
+      if (my_w != w) continue;
+      const cptr<float> wbox = as_const(W.box) + (int64_t)uniform(w) * K * 16;
+      if (active > 12) closest_cuboids<16>(wbox, K, px, py, pz, best, bk);
+      else if (active > 8) closest_cuboids<12>(wbox, K, px, py, pz, best, bk);
+      else if (active > 4) closest_cuboids<8>(wbox, K, px, py, pz, best, bk);
+      else closest_cuboids<4>(wbox, K, px, py, pz, best, bk);
+    }
+  }
+
+  float dv[SPH_GROUP], gx[SPH_GROUP], gy[SPH_GROUP], gz[SPH_GROUP];
+  const float* mybox = W.box + (int64_t)(valid ? my_w : 0) * K * 16;
+#pragma unroll
+  for (int i = 0; i < SPH_GROUP; ++i) {
+    dv[i] = 0.f;
+    gx[i] = gy[i] = gz[i] = 0.f;
+    if (i < active && K > 0 && valid) {
+      float sd, nx, ny, nz;
+      cuboid_sd_grad(mybox + bk[i] * 16, px[i], py[i], pz[i], sd, nx, ny, nz);
+      const float r = sphere_of(R.sph, g * SPH_GROUP + i).w;
+      const float d = fmaxf(cp.eta - (sd - r), 0.f);
+      dv[i] = d;
+      if (d > 0.f) {
+        const float coef = -2.f * cp.w_c * d;
+        gx[i] = coef * nx;
+        gy[i] = coef * ny;
+        gz[i] = coef * nz;
+      }
+    }
+  }
+  float self_acc = 0.f;
+#pragma unroll
+  for (int i = 0; i < SPH_GROUP; ++i) {
+    if (i >= active) continue;
+    const int s = g * SPH_GROUP + i;
+    const float rs = sphere_of(R.sph, s).w;
+    const int j0 = as_const(R.csr_off)[s], j1 = as_const(R.csr_off)[s + 1];
+    for (int j = j0; j < j1; ++j) {
+      const int t = as_const(R.csr_nbr)[j];
+      const int tg = t / SPH_GROUP, tp = t % SPH_GROUP;
+      const float tx = load_elem_fmt<SPH_GROUP>(S.fmt, sb, tg * 3 + 0, tp, S.scale);
+      const float ty = load_elem_fmt<SPH_GROUP>(S.fmt, sb, tg * 3 + 1, tp, S.scale);
+      const float tz = load_elem_fmt<SPH_GROUP>(S.fmt, sb, tg * 3 + 2, tp, S.scale);
+      const float dx = px[i] - tx, dy = py[i] - ty, dz = pz[i] - tz;
+      const float dist = sqrtf(fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
+      const float e = dist - rs - sphere_of(R.sph, t).w;
+      const float act = fmaxf(cp.eta - e, 0.f);
+      if (act > 0.f) {
+        if (dist > 0.f) {
+          const float coef = -2.f * cp.w_s * act / dist;
+          gx[i] = fmaf(coef, dx, gx[i]);
+          gy[i] = fmaf(coef, dy, gy[i]);
+          gz[i] = fmaf(coef, dz, gz[i]);
+        }
+        if (s < t) self_acc = fmaf(act, act, self_acc);
+      }
+    }
+  }
+  if (valid) {
+    store_group<SPH_GROUP>(D, b, g, dv);
+    store_group<SPH_GROUP>(G, b, g * 3 + 0, gx);
+    store_group<SPH_GROUP>(G, b, g * 3 + 1, gy);
+    store_group<SPH_GROUP>(G, b, g * 3 + 2, gz);
+  }
+  part[g * 64 + lane] = self_acc;
+  __syncthreads();
+  if (g == 0 && valid) {
+    float sum = 0.f;
+    for (int gg = 0; gg < ng; ++gg) sum += part[gg * 64 + lane];
+    selfc[b] = cp.w_s * sum;
+  }
 }
 
 // ---- K3: aggregation -----------------------------------------------------------------------------
@@ -678,55 +879,62 @@ __global__ __launch_bounds__(256) void k_optimizer(OptArgs o, TV J, const double
         len = min(len + 1, m);
         flags |= 1;
       }
-      // two-loop recursion, newest pair first; history kept in registers (age order)
+      // two-loop recursion, newest pair first; the second pass re-reads the pairs (L2-resident)
+      // rather than holding them in registers, which keeps many wavefronts resident
       double qv[OPT_NE], a_it[MAX_HIST];
-      float hs[MAX_HIST][OPT_NE], hy[MAX_HIST][OPT_NE];
-      double rho_it[MAX_HIST];
 #pragma unroll
       for (int k = 0; k < OPT_NE; ++k) qv[k] = (double)g[k];
+      double gamma = 1.0;
 #pragma unroll
       for (int it = 0; it < MAX_HIST; ++it) {
         a_it[it] = 0.0;
-        rho_it[it] = 0.0;
         if (it < len) {
           const int slot = (head - 1 - it + 2 * m) % m;
           const int64_t hb = ((int64_t)tr * m + slot) * n;
-          rho_it[it] = o.rho[(int64_t)tr * m + slot];
+          const double rho = o.rho[(int64_t)tr * m + slot];
+          float hs[OPT_NE], hy[OPT_NE];
 #pragma unroll
           for (int k = 0; k < OPT_NE; ++k) {
             const int e = lane + 64 * k;
-            hs[it][k] = e < n ? o.s_hist[hb + e] : 0.f;
-            hy[it][k] = e < n ? o.y_hist[hb + e] : 0.f;
+            hs[k] = e < n ? o.s_hist[hb + e] : 0.f;
+            hy[k] = e < n ? o.y_hist[hb + e] : 0.f;
           }
-          double sq = 0.0;
+          double sq = 0.0, sy0 = 0.0, yy0 = 0.0;
 #pragma unroll
-          for (int k = 0; k < OPT_NE; ++k) sq = fma((double)hs[it][k], qv[k], sq);
-          a_it[it] = rho_it[it] * wave_sum(sq);
+          for (int k = 0; k < OPT_NE; ++k) {
+            sq = fma((double)hs[k], qv[k], sq);
+            if (it == 0) {
+              sy0 = fma((double)hs[k], (double)hy[k], sy0);
+              yy0 = fma((double)hy[k], (double)hy[k], yy0);
+            }
+          }
+          a_it[it] = rho * wave_sum(sq);
+          if (it == 0) gamma = wave_sum(sy0) / wave_sum(yy0);
 #pragma unroll
-          for (int k = 0; k < OPT_NE; ++k) qv[k] = fma(-a_it[it], (double)hy[it][k], qv[k]);
+          for (int k = 0; k < OPT_NE; ++k) qv[k] = fma(-a_it[it], (double)hy[k], qv[k]);
         }
-      }
-      double gamma = 1.0;
-      if (len > 0) {
-        double a = 0.0, c = 0.0;
-#pragma unroll
-        for (int k = 0; k < OPT_NE; ++k) {
-          a = fma((double)hs[0][k], (double)hy[0][k], a);
-          c = fma((double)hy[0][k], (double)hy[0][k], c);
-        }
-        gamma = wave_sum(a) / wave_sum(c);
       }
 #pragma unroll
       for (int k = 0; k < OPT_NE; ++k) qv[k] *= gamma;
 #pragma unroll
       for (int it = MAX_HIST - 1; it >= 0; --it) {
         if (it < len) {
+          const int slot = (head - 1 - it + 2 * m) % m;
+          const int64_t hb = ((int64_t)tr * m + slot) * n;
+          const double rho = o.rho[(int64_t)tr * m + slot];
+          float hs[OPT_NE], hy[OPT_NE];
+#pragma unroll
+          for (int k = 0; k < OPT_NE; ++k) {
+            const int e = lane + 64 * k;
+            hs[k] = e < n ? o.s_hist[hb + e] : 0.f;
+            hy[k] = e < n ? o.y_hist[hb + e] : 0.f;
+          }
           double yr = 0.0;
 #pragma unroll
-          for (int k = 0; k < OPT_NE; ++k) yr = fma((double)hy[it][k], qv[k], yr);
-          const double beta = rho_it[it] * wave_sum(yr);
+          for (int k = 0; k < OPT_NE; ++k) yr = fma((double)hy[k], qv[k], yr);
+          const double beta = rho * wave_sum(yr);
 #pragma unroll
-          for (int k = 0; k < OPT_NE; ++k) qv[k] = fma(a_it[it] - beta, (double)hs[it][k], qv[k]);
+          for (int k = 0; k < OPT_NE; ++k) qv[k] = fma(a_it[it] - beta, (double)hs[k], qv[k]);
         }
       }
       double gdn = 0.0;
@@ -953,6 +1161,17 @@ hipError_t launch_fk(hipStream_t s, const float* q, const RobotArgs& R, const TV
 hipError_t launch_sphere_cost(hipStream_t s, const RobotArgs& R, const WorldArgs& W, const TV& S, const TV& D,
                               const TV& G, float* selfc, const ShapeArgs& sh, const CostArgs& cp) {
   hipLaunchKernelGGL(k_sphere_cost, dim3(blocks_for(sh.B, 256)), dim3(256), 0, s, R, W, S, D, G, selfc, sh, cp);
+  return hipGetLastError();
+}
+
+size_t sphere_cost_lds_bytes(int P_S, int n_groups) { return (size_t)P_S * 256 + (size_t)n_groups * 256; }
+
+hipError_t launch_sphere_cost_blk(hipStream_t s, const RobotArgs& R, const WorldArgs& W, const GridArgs& Gd,
+                                  const TV& S, const TV& D, const TV& G, float* selfc, const ShapeArgs& sh,
+                                  const CostArgs& cp) {
+  const size_t lds = sphere_cost_lds_bytes(S.P, R.n_groups);
+  hipLaunchKernelGGL(k_sphere_cost_blk, dim3(blocks_for(sh.B, 64)), dim3(64 * R.n_groups), lds, s, R, W, Gd, S, D,
+                     G, selfc, sh, cp);
   return hipGetLastError();
 }
 

@@ -22,6 +22,12 @@ struct WorldArgs {
   int K;
 };
 
+struct GridArgs {  // cuboid candidate masks per world and voxel (MW == 0: test every cuboid)
+  const uint32_t* mask;  // [W][n^3][MW]
+  float ox, oy, oz, inv_cell;
+  int n, MW;
+};
+
 struct TV {  // one stored tensor inside a workspace
   uint32_t* p;
   int fmt;
@@ -64,6 +70,11 @@ hipError_t launch_fk(hipStream_t s, const float* q, const RobotArgs& R, const TV
                      int64_t B, int store_L);
 hipError_t launch_sphere_cost(hipStream_t s, const RobotArgs& R, const WorldArgs& W, const TV& S, const TV& D,
                               const TV& G, float* selfc, const ShapeArgs& sh, const CostArgs& cp);
+// LDS bytes of the block-staged sphere-cost kernel (used for <= 8 sphere groups and <= 64 KiB)
+size_t sphere_cost_lds_bytes(int P_S, int n_groups);
+hipError_t launch_sphere_cost_blk(hipStream_t s, const RobotArgs& R, const WorldArgs& W, const GridArgs& Gd,
+                                  const TV& S, const TV& D, const TV& G, float* selfc, const ShapeArgs& sh,
+                                  const CostArgs& cp);
 hipError_t launch_reduce(hipStream_t s, const TV& D, const float* selfc, const float* boundc, const float* q,
                          double* cost_traj, float* cost_cfg, const ShapeArgs& sh, const CostArgs& cp, int n_s);
 hipError_t launch_adjoint(hipStream_t s, const float* q, const RobotArgs& R, const TV& L, const TV& G, const TV& J,

@@ -4,6 +4,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -51,6 +52,13 @@ struct vapr_ctx {
   bool has_worlds = false;
   int n_worlds = 0, n_cuboids = 0;
   float* d_box = nullptr;
+  std::vector<float> h_pose, h_half;  // host copies for the culling grid
+  // culling grid (built lazily when robot, worlds or eta change)
+  bool cull = true;
+  bool grid_valid = false;
+  uint32_t* d_grid = nullptr;
+  GridArgs grid{};
+  float r_max = 0.f;
   // settings
   PrecisionCfg prec{};
   CostArgs params{0.02f, 100.f, 100.f, 10.f, 1.f};
@@ -225,6 +233,86 @@ int timed(vapr_ctx* ctx, int id, F&& launch, const char* what) {
   return VAPR_OK;
 }
 
+// Candidate masks for exact cuboid culling.  The signed distance to a box is 1-Lipschitz, so for
+// any point x of a voxel with centre c and half-diagonal hv, sd(x) >= sd(c) - hv.  A cuboid whose
+// sd at the centre is >= hv + eta + r_max + margin is at clearance >= eta from every sphere in the
+// voxel; its bit stays clear.  The margin (1 mm) covers float32 rounding of the voxel assignment
+// and of the clearance on the GPU.  Points outside the grid are out of reach of every cuboid.
+int build_grid(vapr_ctx* ctx) {
+  ctx->grid = GridArgs{};
+  if (ctx->d_grid) {
+    VAPR_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    (void)hipFree(ctx->d_grid);
+    ctx->d_grid = nullptr;
+  }
+  const int W = ctx->n_worlds, K = ctx->n_cuboids;
+  ctx->grid_valid = true;
+  if (!ctx->cull || K == 0) return VAPR_OK;
+  const double margin = 1e-3;
+  const double reach = (double)ctx->params.eta + (double)ctx->r_max + margin;
+  double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+  std::vector<double> ext((size_t)W * K * 3);
+  for (size_t i = 0; i < (size_t)W * K; ++i) {
+    const float* P = ctx->h_pose.data() + i * 12;
+    const float* h = ctx->h_half.data() + i * 3;
+    for (int r = 0; r < 3; ++r) {
+      double e = 0;
+      for (int c = 0; c < 3; ++c) e += std::fabs((double)P[r * 4 + c]) * h[c];
+      ext[i * 3 + r] = e;
+      lo[r] = std::min(lo[r], (double)P[r * 4 + 3] - e - reach);
+      hi[r] = std::max(hi[r], (double)P[r * 4 + 3] + e + reach);
+    }
+  }
+  const double span = std::max(hi[0] - lo[0], std::max(hi[1] - lo[1], hi[2] - lo[2]));
+  const int n = std::max(1, std::min(48, (int)std::ceil(span / 0.08)));
+  const double cell = span / n;
+  const double hv = cell * std::sqrt(3.0) * 0.5;
+  const int MW = (K + 31) / 32;
+  const size_t n3 = (size_t)n * n * n;
+  std::vector<uint32_t> mask((size_t)W * n3 * MW, 0u);
+  for (int w = 0; w < W; ++w)
+    for (int k = 0; k < K; ++k) {
+      const size_t i = (size_t)w * K + k;
+      const float* P = ctx->h_pose.data() + i * 12;
+      const float* h = ctx->h_half.data() + i * 3;
+      int i0[3], i1[3];
+      for (int r = 0; r < 3; ++r) {
+        const double c = P[r * 4 + 3], e = ext[i * 3 + r] + reach + hv;
+        i0[r] = std::max(0, (int)std::floor((c - e - lo[r]) / cell));
+        i1[r] = std::min(n - 1, (int)std::floor((c + e - lo[r]) / cell));
+      }
+      for (int z = i0[2]; z <= i1[2]; ++z)
+        for (int y = i0[1]; y <= i1[1]; ++y)
+          for (int x = i0[0]; x <= i1[0]; ++x) {
+            const double pc[3] = {lo[0] + (x + 0.5) * cell, lo[1] + (y + 0.5) * cell, lo[2] + (z + 0.5) * cell};
+            double d[3], a[3], o2 = 0, amax = -1e300;
+            for (int r = 0; r < 3; ++r) d[r] = pc[r] - P[r * 4 + 3];
+            for (int c = 0; c < 3; ++c) {
+              const double u = P[0 * 4 + c] * d[0] + P[1 * 4 + c] * d[1] + P[2 * 4 + c] * d[2];
+              a[c] = std::fabs(u) - h[c];
+              const double m = std::max(a[c], 0.0);
+              o2 += m * m;
+              amax = std::max(amax, a[c]);
+            }
+            const double sd = std::sqrt(o2) + std::min(amax, 0.0);
+            if (sd < hv + reach) {
+              const size_t v = ((size_t)z * n + y) * n + x;
+              mask[((size_t)w * n3 + v) * MW + k / 32] |= 1u << (k % 32);
+            }
+          }
+    }
+  int st = upload(ctx, &ctx->d_grid, mask.data(), mask.size());
+  if (st) return st;
+  ctx->grid.mask = ctx->d_grid;
+  ctx->grid.ox = (float)lo[0];
+  ctx->grid.oy = (float)lo[1];
+  ctx->grid.oz = (float)lo[2];
+  ctx->grid.inv_cell = (float)(1.0 / cell);
+  ctx->grid.n = n;
+  ctx->grid.MW = MW;
+  return VAPR_OK;
+}
+
 int run_fwd(vapr_ctx* ctx, int first, int n_worlds, int tpw, int T, int n_ls, const float* q, void* ws,
             size_t ws_bytes, double* cost_traj, float* cost_cfg) {
   int64_t B;
@@ -257,8 +345,15 @@ int run_fwd(vapr_ctx* ctx, int first, int n_worlds, int tpw, int T, int n_ls, co
   if (first <= 2) {
     WorldArgs W{ctx->d_box, ctx->n_cuboids};
     const CostArgs cp = ctx->params;
-    st = timed(ctx, K_SPHERE, [&] { return launch_sphere_cost(s, R, W, tS, tD, tG, selfc, sh, cp); },
-               "k_sphere_cost launch");
+    if (!ctx->grid_valid && (st = build_grid(ctx))) return st;
+    const GridArgs Gd = ctx->grid;
+    if (ctx->n_groups <= 8 && sphere_cost_lds_bytes(L.P[T_S], ctx->n_groups) <= 65536) {
+      st = timed(ctx, K_SPHERE, [&] { return launch_sphere_cost_blk(s, R, W, Gd, tS, tD, tG, selfc, sh, cp); },
+                 "k_sphere_cost_blk launch");
+    } else {
+      st = timed(ctx, K_SPHERE, [&] { return launch_sphere_cost(s, R, W, tS, tD, tG, selfc, sh, cp); },
+                 "k_sphere_cost launch");
+    }
     if (st) return st;
   }
   const CostArgs cp = ctx->params;
@@ -380,6 +475,7 @@ int vapr_destroy(vapr_ctx* ctx) {
   (void)hipStreamSynchronize(ctx->stream);
   free_robot(ctx);
   (void)hipFree(ctx->d_box);
+  (void)hipFree(ctx->d_grid);
   for (auto& pe : ctx->prof_live) {
     (void)hipEventDestroy(pe.start);
     (void)hipEventDestroy(pe.stop);
@@ -457,6 +553,9 @@ int vapr_set_robot(vapr_ctx* ctx, int n_joints, const float* fixed_tf, int n_sph
   }
   ctx->has_robot = true;
   ctx->robot_gen++;
+  ctx->r_max = 0.f;
+  for (int i = 0; i < n_spheres; ++i) ctx->r_max = std::max(ctx->r_max, sphere_radius[i]);
+  ctx->grid_valid = false;
   return VAPR_OK;
 }
 
@@ -497,6 +596,9 @@ int vapr_set_worlds(vapr_ctx* ctx, int n_worlds, int n_cuboids, const float* pos
   ctx->n_worlds = n_worlds;
   ctx->n_cuboids = n_cuboids;
   ctx->has_worlds = true;
+  ctx->h_pose.assign(pose, pose + nb * 12);
+  ctx->h_half.assign(half_ext, half_ext + nb * 3);
+  ctx->grid_valid = false;
   return VAPR_OK;
 }
 
@@ -526,6 +628,14 @@ int vapr_set_cost_params(vapr_ctx* ctx, const vapr_cost_params* p) {
       p->w_smooth < 0.f)
     return fail(ctx, VAPR_E_INVALID, "cost parameters out of range");
   ctx->params = CostArgs{p->eta, p->w_coll, p->w_self, p->w_bound, p->w_smooth};
+  ctx->grid_valid = false;
+  return VAPR_OK;
+}
+
+int vapr_set_culling(vapr_ctx* ctx, int enable) {
+  if (!ctx) return fail(nullptr, VAPR_E_INVALID, "null context");
+  ctx->cull = enable != 0;
+  ctx->grid_valid = false;
   return VAPR_OK;
 }
 

@@ -188,10 +188,13 @@ def test_stage_adjoint_codes(pname, recompute):
                                   F.dequantize(got, fmt, k))
 
 
-@pytest.mark.parametrize("case", ["ragged", "no_cuboids", "no_pairs", "one_sphere", "worlds_in_wave"])
+@pytest.mark.parametrize("case", ["ragged", "no_cuboids", "no_pairs", "one_sphere", "worlds_in_wave",
+                                  "many_spheres"])
 def test_edge_shapes(case):
     need_gpu()
     kw = dict(seed=21, n_worlds=3, tpw=3, T=5, n_ls=2, n_spheres=37, n_cuboids=7, n_pairs=40)
+    if case == "many_spheres":  # more than 8 sphere groups: the kernel that reads positions from HBM
+        kw.update(n_spheres=150, n_pairs=400)
     if case == "no_cuboids":
         kw["n_cuboids"] = 0
     if case == "no_pairs":
@@ -300,3 +303,33 @@ def test_error_paths():
     with pytest.raises(VaprError) as e:
         ctx.cost_bwd(q, fresh)
     assert e.value.status == L.E_STATE
+
+
+@pytest.mark.parametrize("wname,pname", [("dense", "f32"), ("dense", "mixed_fp4"), ("batched", "f32"),
+                                         ("large", "paper_like"), ("edge", "f32")])
+def test_culling_is_exact(wname, pname):
+    """Skipping cuboids that are out of reach changes nothing: stored codes, self costs and
+    trajectory costs are bit-identical with and without culling."""
+    need_gpu()
+    prec = {} if pname == "f32" else PRECISIONS[pname]
+    if wname == "dense":
+        wl = dense_workload()
+    elif wname == "edge":
+        wl = dense_workload(seed=21, n_worlds=9, tpw=1, T=4, n_ls=1, n_spheres=37, n_cuboids=7, n_pairs=40)
+    else:
+        wl = make_workload(wname)
+    ctx = make_context(wl, prec)
+    shape = shape_of(wl)
+    q = dev(wl.q, torch.float32)
+    out = []
+    for cull in (True, False):
+        ctx.set_culling(cull)
+        cost, ws = ctx.cost_fwd(q, shape)
+        torch.cuda.synchronize()
+        out.append((cost.cpu().numpy(), {n: export_codes(ctx, n, ws, shape) for n in ("sphere_dist", "sphere_grad")},
+                    ctx.ws_export("self_cost", ws, shape).cpu().numpy()))
+    (c1, t1, s1), (c2, t2, s2) = out
+    assert np.array_equal(c1, c2)
+    assert np.array_equal(s1, s2)
+    for n in t1:
+        assert np.array_equal(t1[n], t2[n]), n
