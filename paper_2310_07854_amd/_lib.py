@@ -90,6 +90,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     global _lib
     if _lib is not None:
         return _lib
+    # torch brings its own HIP runtime; loading it first makes this library bind to the same one
+    # (two runtimes in one process do not share devices or streams)
+    import torch  # noqa: F401
     if not os.path.exists(path):
         raise ImportError(f"{path} is not built; run `python -m paper_2310_07854_amd.build` "
                           "(there is no fallback implementation)")

@@ -443,6 +443,11 @@ __global__ __launch_bounds__(256) void k_sphere_cost(RobotArgs R, WorldArgs W, T
 // result is identical to testing every cuboid.  The wavefront tests, per sphere, the union of its
 // lanes' candidate sets, keeping the cuboid on scalar operands.
 
+#ifndef VAPR_CULL_SPHERES
+#define VAPR_CULL_SPHERES 4
+#endif
+constexpr int CQ = VAPR_CULL_SPHERES;  // spheres sharing one candidate list (divides 16)
+
 __device__ __forceinline__ uint32_t wave_or(uint32_t v) {
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) v |= (uint32_t)__shfl_xor((int)v, off, 64);
@@ -472,6 +477,7 @@ __device__ __forceinline__ void cuboid_key(cptr<float> bx, float px, float py, f
   }
 }
 
+template <int FS>
 __global__ __launch_bounds__(512) void k_sphere_cost_blk(RobotArgs R, WorldArgs W, GridArgs Gd, TV S, TV D, TV G,
                                                           float* __restrict__ selfc, ShapeArgs sh, CostArgs cp) {
   extern __shared__ uint32_t lds[];
@@ -503,9 +509,9 @@ __global__ __launch_bounds__(512) void k_sphere_cost_blk(RobotArgs R, WorldArgs 
   const int active = uniform(min(SPH_GROUP, n_s - g * SPH_GROUP));
 
   float px[SPH_GROUP], py[SPH_GROUP], pz[SPH_GROUP];
-  load_group_fmt<SPH_GROUP>(S.fmt, sb, g * 3 + 0, S.scale, px);
-  load_group_fmt<SPH_GROUP>(S.fmt, sb, g * 3 + 1, S.scale, py);
-  load_group_fmt<SPH_GROUP>(S.fmt, sb, g * 3 + 2, S.scale, pz);
+  load_group_at<FS, SPH_GROUP>(sb, g * 3 + 0, S.scale, px);
+  load_group_at<FS, SPH_GROUP>(sb, g * 3 + 1, S.scale, py);
+  load_group_at<FS, SPH_GROUP>(sb, g * 3 + 2, S.scale, pz);
   float best[SPH_GROUP];
   int bk[SPH_GROUP];
 #pragma unroll
@@ -522,19 +528,26 @@ __global__ __launch_bounds__(512) void k_sphere_cost_blk(RobotArgs R, WorldArgs 
     for (int w = w_lo; w <= w_hi; ++w) {
       const int wu = uniform(w);
       const cptr<float> wbox = as_const(W.box) + (int64_t)wu * K * 16;
+      const uint32_t* wmask = Gd.mask + (int64_t)wu * n3 * Gd.MW;
+      for (int mw = 0; mw < Gd.MW; ++mw) {
+        uint32_t mk[SPH_GROUP];
 #pragma unroll
-      for (int i = 0; i < SPH_GROUP; ++i) {
-        if (i >= active) continue;
-        for (int mw = 0; mw < Gd.MW; ++mw) {
-          uint32_t m = 0;
-          if (my_w == wu && vox[i] >= 0) m = Gd.mask[((int64_t)wu * n3 + vox[i]) * Gd.MW + mw];
-          m = (uint32_t)uniform((int)wave_or(m));
-          if (my_w == wu) {
-            while (m) {
-              const int k = mw * 32 + __builtin_ctz(m);
-              m &= m - 1;
-              cuboid_key(wbox + k * 16, px[i], py[i], pz[i], k, best[i], bk[i]);
-            }
+        for (int i = 0; i < SPH_GROUP; ++i)
+          mk[i] = (i < active && my_w == wu && vox[i] >= 0) ? wmask[(int64_t)vox[i] * Gd.MW + mw] : 0u;
+        // candidates are shared by CQ consecutive spheres: one scalar load of a cuboid serves them all
+#pragma unroll
+        for (int i0 = 0; i0 < SPH_GROUP; i0 += CQ) {
+          if (i0 >= active) continue;
+          uint32_t mq = 0;
+#pragma unroll
+          for (int i = i0; i < i0 + CQ; ++i) mq |= mk[i];
+          uint32_t m = (uint32_t)uniform((int)wave_or(mq));
+          if (my_w != wu) continue;
+          while (m) {
+            const int k = mw * 32 + __builtin_ctz(m);
+            m &= m - 1;
+#pragma unroll
+            for (int i = i0; i < i0 + CQ; ++i) cuboid_key(wbox + k * 16, px[i], py[i], pz[i], k, best[i], bk[i]);
           }
         }
       }
@@ -570,31 +583,48 @@ __global__ __launch_bounds__(512) void k_sphere_cost_blk(RobotArgs R, WorldArgs 
       }
     }
   }
+  // Self pairs: partners of any group are read from the staged block in batches of PB so that
+  // their reads are in flight together.  Each pair is visited from both of its spheres: each visit
+  // adds its own sphere's gradient and the lower index adds the cost, so no cross-lane or atomic
+  // accumulation is needed.
   float self_acc = 0.f;
+  constexpr int PB = 4;
 #pragma unroll
   for (int i = 0; i < SPH_GROUP; ++i) {
     if (i >= active) continue;
     const int s = g * SPH_GROUP + i;
     const float rs = sphere_of(R.sph, s).w;
     const int j0 = as_const(R.csr_off)[s], j1 = as_const(R.csr_off)[s + 1];
-    for (int j = j0; j < j1; ++j) {
-      const int t = as_const(R.csr_nbr)[j];
-      const int tg = t / SPH_GROUP, tp = t % SPH_GROUP;
-      const float tx = load_elem_fmt<SPH_GROUP>(S.fmt, sb, tg * 3 + 0, tp, S.scale);
-      const float ty = load_elem_fmt<SPH_GROUP>(S.fmt, sb, tg * 3 + 1, tp, S.scale);
-      const float tz = load_elem_fmt<SPH_GROUP>(S.fmt, sb, tg * 3 + 2, tp, S.scale);
-      const float dx = px[i] - tx, dy = py[i] - ty, dz = pz[i] - tz;
-      const float dist = sqrtf(fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
-      const float e = dist - rs - sphere_of(R.sph, t).w;
-      const float act = fmaxf(cp.eta - e, 0.f);
-      if (act > 0.f) {
-        if (dist > 0.f) {
-          const float coef = -2.f * cp.w_s * act / dist;
-          gx[i] = fmaf(coef, dx, gx[i]);
-          gy[i] = fmaf(coef, dy, gy[i]);
-          gz[i] = fmaf(coef, dz, gz[i]);
+    for (int j = j0; j < j1; j += PB) {
+      float tx[PB], ty[PB], tz[PB], rt[PB];
+      int tt[PB];
+#pragma unroll
+      for (int u = 0; u < PB; ++u) {
+        const int jj = j + u < j1 ? j + u : j;  // a repeated partner is read but not used
+        const int t = as_const(R.csr_nbr)[jj];
+        tt[u] = t;
+        const int tg = t / SPH_GROUP, tp = t % SPH_GROUP;
+        tx[u] = load_elem_at<FS, SPH_GROUP>(sb, tg * 3 + 0, tp, S.scale);
+        ty[u] = load_elem_at<FS, SPH_GROUP>(sb, tg * 3 + 1, tp, S.scale);
+        tz[u] = load_elem_at<FS, SPH_GROUP>(sb, tg * 3 + 2, tp, S.scale);
+        rt[u] = sphere_of(R.sph, t).w;
+      }
+#pragma unroll
+      for (int u = 0; u < PB; ++u) {
+        if (j + u >= j1) continue;
+        const float dx = px[i] - tx[u], dy = py[i] - ty[u], dz = pz[i] - tz[u];
+        const float dist = sqrtf(fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
+        const float e = dist - rs - rt[u];
+        const float act = fmaxf(cp.eta - e, 0.f);
+        if (act > 0.f) {
+          if (dist > 0.f) {
+            const float coef = -2.f * cp.w_s * act / dist;
+            gx[i] = fmaf(coef, dx, gx[i]);
+            gy[i] = fmaf(coef, dy, gy[i]);
+            gz[i] = fmaf(coef, dz, gz[i]);
+          }
+          if (s < tt[u]) self_acc = fmaf(act, act, self_acc);
         }
-        if (s < t) self_acc = fmaf(act, act, self_acc);
       }
     }
   }
@@ -1170,8 +1200,14 @@ hipError_t launch_sphere_cost_blk(hipStream_t s, const RobotArgs& R, const World
                                   const TV& S, const TV& D, const TV& G, float* selfc, const ShapeArgs& sh,
                                   const CostArgs& cp) {
   const size_t lds = sphere_cost_lds_bytes(S.P, R.n_groups);
-  hipLaunchKernelGGL(k_sphere_cost_blk, dim3(blocks_for(sh.B, 64)), dim3(64 * R.n_groups), lds, s, R, W, Gd, S, D,
-                     G, selfc, sh, cp);
+  const dim3 grid(blocks_for(sh.B, 64)), block(64 * R.n_groups);
+  switch (S.fmt) {
+#define VAPR_K2(F) \
+  case F: hipLaunchKernelGGL(k_sphere_cost_blk<F>, grid, block, lds, s, R, W, Gd, S, D, G, selfc, sh, cp); break;
+    VAPR_K2(F32) VAPR_K2(F16) VAPR_K2(BF16) VAPR_K2(E4M3) VAPR_K2(E5M2) VAPR_K2(E3M2) VAPR_K2(E2M1)
+#undef VAPR_K2
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
