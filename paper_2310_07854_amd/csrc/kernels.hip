@@ -38,13 +38,20 @@ __device__ __forceinline__ float4 sphere_of(const float4* sph, int s) {
 
 // ---- stored-tensor group access (format dispatched once per group, wave-uniform) -------------
 
+// A lane's view of a stored tensor: plane p of the lane's configuration is base[p * 64].  The same
+// formula serves the tensor in HBM (base = block start + lane) and a block staged in LDS.
+__device__ __forceinline__ uint32_t* lane_base(const TV& t, int64_t b) {
+  return t.p + ((b >> 6) * t.P) * 64 + (b & 63);
+}
+
 template <int F, int N>
 __device__ __forceinline__ void store_group_t(const TV& t, int64_t b, int slot, const float (&v)[N]) {
   constexpr int DW = group_dwords(F, N);
   uint32_t w[DW];
   encode_group<F, N>(v, t.inv, w);
+  uint32_t* base = lane_base(t, b) + slot * DW * 64;
 #pragma unroll
-  for (int k = 0; k < DW; ++k) t.p[plane_index(b, t.P, slot * DW + k)] = w[k];
+  for (int k = 0; k < DW; ++k) base[k * 64] = w[k];
 }
 
 template <int N>
@@ -58,12 +65,6 @@ __device__ __forceinline__ void store_group(const TV& t, int64_t b, int slot, co
     case E3M2: store_group_t<E3M2, N>(t, b, slot, v); break;
     default: store_group_t<E2M1, N>(t, b, slot, v); break;
   }
-}
-
-// A lane's view of a stored tensor: plane p of the lane's configuration is base[p * 64].  The same
-// formula serves the tensor in HBM (base = block start + lane) and a block staged in LDS.
-__device__ __forceinline__ const uint32_t* lane_base(const TV& t, int64_t b) {
-  return t.p + ((b >> 6) * t.P) * 64 + (b & 63);
 }
 
 template <int F, int N>
@@ -145,13 +146,21 @@ __device__ __forceinline__ void roundtrip(const TV& t, float (&v)[N]) {
   }
 }
 
-// ---- serial chain ------------------------------------------------------------------------------
+// ---- serial chain, link poses of a tile in LDS ---------------------------------------------------
 
-// T_j = T_{j-1} F_j Rz(q_j) (j = 1..7), T_8 = T_7 F_8; Tl[l-1] holds link l as row-major [R | t].
-__device__ __forceinline__ void chain(const float* __restrict__ fixed, const float (&qv)[N_JOINTS],
-                                      float (&Tl)[N_FIXED][LINK_VALUES]) {
+// LDS image of the nine link poses of a 64-configuration tile: value k of link l (0..8, [R | t]
+// row-major; link 0 is the identity) for lane j is word (l * 12 + k) * 64 + j, so a wavefront-wide
+// access touches 64 consecutive words, one per bank.
+constexpr int TILE_POSE_WORDS = N_LINKS * LINK_VALUES * 64;
+
+// T_0 = I, T_j = T_{j-1} F_j Rz(q_j) (j = 1..7), T_8 = T_7 F_8, each link written to the tile as
+// it is formed
+__device__ __forceinline__ void chain_to_tile(const float* __restrict__ fixed, const float (&qv)[N_JOINTS],
+                                              float* tile, int lane) {
   float R[9] = {1.f, 0.f, 0.f, 0.f, 1.f, 0.f, 0.f, 0.f, 1.f};
   float t[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+  for (int k = 0; k < LINK_VALUES; ++k) tile[k * 64 + lane] = (k == 0 || k == 5 || k == 10) ? 1.f : 0.f;
 #pragma unroll
   for (int l = 0; l < N_FIXED; ++l) {
     const cptr<float> F = as_const(fixed) + l * LINK_VALUES;
@@ -177,14 +186,45 @@ __device__ __forceinline__ void chain(const float* __restrict__ fixed, const flo
     for (int i = 0; i < 9; ++i) R[i] = nR[i];
 #pragma unroll
     for (int i = 0; i < 3; ++i) t[i] = nt[i];
+    float* out = tile + (l + 1) * LINK_VALUES * 64 + lane;
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-      Tl[l][i * 4 + 0] = R[i * 3 + 0];
-      Tl[l][i * 4 + 1] = R[i * 3 + 1];
-      Tl[l][i * 4 + 2] = R[i * 3 + 2];
-      Tl[l][i * 4 + 3] = t[i];
+      out[(i * 4 + 0) * 64] = R[i * 3 + 0];
+      out[(i * 4 + 1) * 64] = R[i * 3 + 1];
+      out[(i * 4 + 2) * 64] = R[i * 3 + 2];
+      out[(i * 4 + 3) * 64] = t[i];
     }
   }
+}
+
+// pose of link l (0..8) of this lane
+__device__ __forceinline__ void pose_from_tile(const float* tile, int l, int lane, float (&T)[LINK_VALUES]) {
+  const float* p = tile + l * LINK_VALUES * 64 + lane;
+#pragma unroll
+  for (int k = 0; k < LINK_VALUES; ++k) T[k] = p[k * 64];
+}
+
+// The same read issued as explicit LDS instructions, so that it stays inside its wave-uniform
+// branch (the compiler would otherwise hoist the guarded reads of every sphere out of their branches
+// and keep all of them live).  Six ds_read2st64_b32 (two words 64 words apart each), then a wait.
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void pose_from_tile_guarded(const float* tile, int l, int lane, float (&T)[LINK_VALUES]) {
+  const uint32_t addr =
+      (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) float*)(tile + l * LINK_VALUES * 64 + lane);
+  f32x2 a, b, c, d, e, f;
+  asm volatile(
+      "ds_read2st64_b32 %0, %6 offset0:0 offset1:1\n"
+      "ds_read2st64_b32 %1, %6 offset0:2 offset1:3\n"
+      "ds_read2st64_b32 %2, %6 offset0:4 offset1:5\n"
+      "ds_read2st64_b32 %3, %6 offset0:6 offset1:7\n"
+      "ds_read2st64_b32 %4, %6 offset0:8 offset1:9\n"
+      "ds_read2st64_b32 %5, %6 offset0:10 offset1:11\n"
+      "s_waitcnt lgkmcnt(0)"
+      : "=&v"(a), "=&v"(b), "=&v"(c), "=&v"(d), "=&v"(e), "=&v"(f)
+      : "v"(addr)
+      : "memory");
+  T[0] = a.x; T[1] = a.y; T[2] = b.x; T[3] = b.y; T[4] = c.x; T[5] = c.y;
+  T[6] = d.x; T[7] = d.y; T[8] = e.x; T[9] = e.y; T[10] = f.x; T[11] = f.y;
 }
 
 __device__ __forceinline__ void xform(const float (&T)[LINK_VALUES], float cx, float cy, float cz, float& x,
@@ -192,19 +232,6 @@ __device__ __forceinline__ void xform(const float (&T)[LINK_VALUES], float cx, f
   x = fmaf(T[0], cx, fmaf(T[1], cy, fmaf(T[2], cz, T[3])));
   y = fmaf(T[4], cx, fmaf(T[5], cy, fmaf(T[6], cz, T[7])));
   z = fmaf(T[8], cx, fmaf(T[9], cy, fmaf(T[10], cz, T[11])));
-}
-
-// world position of a sphere on link l (wave-uniform l selects a statically indexed pose)
-__device__ __forceinline__ void sphere_world(int l, const float (&Tl)[N_FIXED][LINK_VALUES], float cx, float cy,
-                                             float cz, float& x, float& y, float& z) {
-  switch (l) {
-#define VAPR_LINK_CASE(k) \
-  case k: xform(Tl[k - 1], cx, cy, cz, x, y, z); break;
-    VAPR_LINK_CASE(1) VAPR_LINK_CASE(2) VAPR_LINK_CASE(3) VAPR_LINK_CASE(4)
-    VAPR_LINK_CASE(5) VAPR_LINK_CASE(6) VAPR_LINK_CASE(7) VAPR_LINK_CASE(8)
-#undef VAPR_LINK_CASE
-    default: x = cx; y = cy; z = cz; break;
-  }
 }
 
 __device__ __forceinline__ float bound_cost(const RobotArgs& R, const float (&qv)[N_JOINTS]) {
@@ -219,50 +246,65 @@ __device__ __forceinline__ float bound_cost(const RobotArgs& R, const float (&qv
 
 // ---- K1: forward kinematics ---------------------------------------------------------------------
 
-// links 4*GR+1 .. 4*GR+4 as one packed group (static group index keeps Tl in registers)
-template <int GR>
-__device__ __forceinline__ void store_link_group(const TV& L, int64_t b, const float (&Tl)[N_FIXED][LINK_VALUES]) {
-  float v[L_GROUP];
+// World centres of sphere group g (p_s = R_l c_s + t_l).  The pose is re-read from the tile only
+// when the link changes from one sphere to the next; robots list their spheres link by link, so a
+// group reads two or three poses.  The zero padding sits on link 0.
+template <int FS>
+__device__ __forceinline__ void place_group(const RobotArgs& R, const TV& S, int64_t b, int g, const float* tile,
+                                            int lane) {
+  float px[SPH_GROUP], py[SPH_GROUP], pz[SPH_GROUP];
+  float T[LINK_VALUES];
+  int cur = as_const(R.link)[g * SPH_GROUP];
+  pose_from_tile(tile, cur, lane, T);
 #pragma unroll
-  for (int i = 0; i < L_GROUP; ++i) v[i] = Tl[GR * 4 + i / LINK_VALUES][i % LINK_VALUES];
-  store_group<L_GROUP>(L, b, GR, v);
+  for (int i = 0; i < SPH_GROUP; ++i) {
+    const int s = g * SPH_GROUP + i;
+    const float4 c = sphere_of(R.sph, s);
+    const int l = as_const(R.link)[s];
+    if (l != cur) {
+      cur = l;
+      pose_from_tile_guarded(tile, l, lane, T);
+    }
+    xform(T, c.x, c.y, c.z, px[i], py[i], pz[i]);
+    // computed here, not sunk past the next pose change (which would keep every pose version live)
+    asm volatile("" : "+v"(px[i]), "+v"(py[i]), "+v"(pz[i]));
+  }
+  store_group_t<FS, SPH_GROUP>(S, b, g * 3 + 0, px);
+  store_group_t<FS, SPH_GROUP>(S, b, g * 3 + 1, py);
+  store_group_t<FS, SPH_GROUP>(S, b, g * 3 + 2, pz);
 }
 
-template <int GR>
-__device__ __forceinline__ void load_link_group(const TV& L, int64_t b, float (&Tl)[N_FIXED][LINK_VALUES]) {
-  float v[L_GROUP];
-  load_group<L_GROUP>(L, b, GR, v);
-#pragma unroll
-  for (int i = 0; i < L_GROUP; ++i) Tl[GR * 4 + i / LINK_VALUES][i % LINK_VALUES] = v[i];
-}
-
+// One block of four wavefronts per 64-configuration tile: wavefront 0 runs the chain into LDS, then
+// the sphere groups and the two link-pose groups are shared out over the wavefronts.
+template <int FS>
 __global__ __launch_bounds__(256) void k_fk(const float* __restrict__ q, RobotArgs R, TV L, TV S,
                                             float* __restrict__ bound, int64_t B, int store_L) {
-  const int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (b >= B) return;
-  float qv[N_JOINTS];
+  __shared__ float tile[TILE_POSE_WORDS];
+  const int wave = uniform(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int64_t b = (int64_t)blockIdx.x * 64 + lane;
+  const bool live = b < B;
+  if (wave == 0) {
+    float qv[N_JOINTS];
 #pragma unroll
-  for (int j = 0; j < N_JOINTS; ++j) qv[j] = q[b * N_JOINTS + j];
-  bound[b] = bound_cost(R, qv);
-
-  float Tl[N_FIXED][LINK_VALUES];
-  chain(R.fixed, qv, Tl);
-  if (store_L) {
-    store_link_group<0>(L, b, Tl);
-    store_link_group<1>(L, b, Tl);
+    for (int j = 0; j < N_JOINTS; ++j) qv[j] = live ? q[b * N_JOINTS + j] : 0.f;
+    if (live) bound[b] = bound_cost(R, qv);
+    chain_to_tile(R.fixed, qv, tile, lane);
   }
+  __syncthreads();
+  if (!live) return;
   const int ng = uniform(R.n_groups);
-  for (int g = 0; g < ng; ++g) {
-    float px[SPH_GROUP], py[SPH_GROUP], pz[SPH_GROUP];
+  const int n_items = ng + (store_L ? L_GROUPS : 0);
+  // items: sphere groups, then link-pose groups; wavefront 0 (which ran the chain) starts at item 3
+  for (int it = (wave + 3) & 3; it < n_items; it += 4) {
+    if (it < ng) {
+      place_group<FS>(R, S, b, it, tile, lane);
+    } else {
+      const int gr = it - ng;
+      float v[L_GROUP];
 #pragma unroll
-    for (int i = 0; i < SPH_GROUP; ++i) {
-      const int s = g * SPH_GROUP + i;
-      const float4 c = sphere_of(R.sph, s);
-      sphere_world(as_const(R.link)[s], Tl, c.x, c.y, c.z, px[i], py[i], pz[i]);
+      for (int i = 0; i < L_GROUP; ++i) v[i] = tile[(LINK_VALUES + gr * L_GROUP + i) * 64 + lane];
+      store_group<L_GROUP>(L, b, gr, v);
     }
-    store_group<SPH_GROUP>(S, b, g * 3 + 0, px);
-    store_group<SPH_GROUP>(S, b, g * 3 + 1, py);
-    store_group<SPH_GROUP>(S, b, g * 3 + 2, pz);
   }
 }
 
@@ -693,79 +735,108 @@ __global__ __launch_bounds__(256) void k_reduce(TV D, const float* __restrict__ 
 
 // ---- K4: reverse accumulation -------------------------------------------------------------------
 
-__global__ __launch_bounds__(256) void k_adjoint(const float* __restrict__ q, RobotArgs R, TV L, TV G, TV J,
-                                                 const double* __restrict__ up, float* __restrict__ grad_q,
-                                                 ShapeArgs sh, CostArgs cp, int recompute) {
-  const int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (b >= sh.B) return;
-  float qv[N_JOINTS];
-#pragma unroll
-  for (int j = 0; j < N_JOINTS; ++j) qv[j] = q[b * N_JOINTS + j];
-
-  float Tl[N_FIXED][LINK_VALUES];
-  if (recompute) {
-    chain(R.fixed, qv, Tl);
-  } else {
-    load_link_group<0>(L, b, Tl);
-    load_link_group<1>(L, b, Tl);
-  }
-  // per-link force and moment (about the world origin) of the sphere gradients
-  float fa[N_FIXED][3], ma[N_FIXED][3];
-#pragma unroll
-  for (int l = 0; l < N_FIXED; ++l)
-#pragma unroll
-    for (int i = 0; i < 3; ++i) fa[l][i] = ma[l][i] = 0.f;
-
-  const int ng = uniform(R.n_groups);
-  const int n_s = uniform(R.n_s);
-  for (int g = 0; g < ng; ++g) {
+// Force and moment (about the world origin) of the sphere gradients on link l: spheres of the link
+// are visited in increasing index over the groups that hold them, with G decoded a group at a time.
+template <int FG>
+__device__ __forceinline__ void link_wrench(const RobotArgs& R, const uint32_t* gbase, float gscale, int l,
+                                            const float (&T)[LINK_VALUES], float (&f)[3], float (&m)[3]) {
+  const cptr<int> lg = as_const(R.link_groups) + 2 * l;
+  const int g_lo = lg[0], g_hi = lg[1];
+  for (int g = g_lo; g < g_hi; ++g) {
     float gx[SPH_GROUP], gy[SPH_GROUP], gz[SPH_GROUP];
-    load_group<SPH_GROUP>(G, b, g * 3 + 0, gx);
-    load_group<SPH_GROUP>(G, b, g * 3 + 1, gy);
-    load_group<SPH_GROUP>(G, b, g * 3 + 2, gz);
+    load_group_at<FG, SPH_GROUP>(gbase, g * 3 + 0, gscale, gx);
+    load_group_at<FG, SPH_GROUP>(gbase, g * 3 + 1, gscale, gy);
+    load_group_at<FG, SPH_GROUP>(gbase, g * 3 + 2, gscale, gz);
 #pragma unroll
     for (int i = 0; i < SPH_GROUP; ++i) {
       const int s = g * SPH_GROUP + i;
-      if (s >= n_s) break;
+      if (as_const(R.link)[s] != l) continue;
       const float4 c = sphere_of(R.sph, s);
-      switch (as_const(R.link)[s]) {
-#define VAPR_ACC_CASE(k)                                                            \
-  case k: {                                                                         \
-    float x, y, z;                                                                  \
-    xform(Tl[k - 1], c.x, c.y, c.z, x, y, z);                                       \
-    fa[k - 1][0] += gx[i];                                                          \
-    fa[k - 1][1] += gy[i];                                                          \
-    fa[k - 1][2] += gz[i];                                                          \
-    ma[k - 1][0] = fmaf(y, gz[i], fmaf(-z, gy[i], ma[k - 1][0]));                   \
-    ma[k - 1][1] = fmaf(z, gx[i], fmaf(-x, gz[i], ma[k - 1][1]));                   \
-    ma[k - 1][2] = fmaf(x, gy[i], fmaf(-y, gx[i], ma[k - 1][2]));                   \
-  } break;
-        VAPR_ACC_CASE(1) VAPR_ACC_CASE(2) VAPR_ACC_CASE(3) VAPR_ACC_CASE(4)
-        VAPR_ACC_CASE(5) VAPR_ACC_CASE(6) VAPR_ACC_CASE(7) VAPR_ACC_CASE(8)
-#undef VAPR_ACC_CASE
-        default: break;  // base link: no joint moves it
-      }
+      float x, y, z;
+      xform(T, c.x, c.y, c.z, x, y, z);
+      f[0] += gx[i];
+      f[1] += gy[i];
+      f[2] += gz[i];
+      m[0] = fmaf(y, gz[i], fmaf(-z, gy[i], m[0]));
+      m[1] = fmaf(z, gx[i], fmaf(-x, gz[i], m[1]));
+      m[2] = fmaf(x, gy[i], fmaf(-y, gx[i], m[2]));
     }
   }
+}
+
+// One block of four wavefronts per 64-configuration tile.  Phase 1 puts the link poses in LDS
+// (decoded from L by wavefronts 0-1, or recomputed by wavefront 0); phase 2 gives each wavefront
+// links w+1 and w+5 and leaves their force and moment in LDS; phase 3 (wavefront 0) sums them from
+// the tip to the base into the joint gradients.
+template <int FG>
+__global__ __launch_bounds__(256) void k_adjoint(const float* __restrict__ q, RobotArgs R, TV L, TV G, TV J,
+                                                 const double* __restrict__ up, float* __restrict__ grad_q,
+                                                 ShapeArgs sh, CostArgs cp, int recompute) {
+  __shared__ float tile[TILE_POSE_WORDS];
+  __shared__ float wrench[N_FIXED * 6 * 64];  // link l: force (3), moment (3) at ((l-1)*6 + k)*64 + lane
+  const int wave = uniform(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int64_t b = (int64_t)blockIdx.x * 64 + lane;
+  const bool live = b < sh.B;
+  if (recompute) {
+    if (wave == 0) {
+      float qv[N_JOINTS];
+#pragma unroll
+      for (int j = 0; j < N_JOINTS; ++j) qv[j] = live ? q[b * N_JOINTS + j] : 0.f;
+      chain_to_tile(R.fixed, qv, tile, lane);
+    }
+  } else if (wave < L_GROUPS) {
+    float v[L_GROUP];
+    if (live) {
+      load_group<L_GROUP>(L, b, wave, v);
+    } else {
+#pragma unroll
+      for (int i = 0; i < L_GROUP; ++i) v[i] = 0.f;
+    }
+#pragma unroll
+    for (int i = 0; i < L_GROUP; ++i) tile[(LINK_VALUES + wave * L_GROUP + i) * 64 + lane] = v[i];
+  }
+  __syncthreads();
+
+  const uint32_t* gbase = lane_base(G, b);
+  for (int l = wave + 1; l <= N_FIXED; l += 4) {
+    float T[LINK_VALUES];
+    pose_from_tile(tile, l, lane, T);
+    float f[3] = {0.f, 0.f, 0.f}, m[3] = {0.f, 0.f, 0.f};
+    if (live) link_wrench<FG>(R, gbase, G.scale, l, T, f, m);
+    float* w = wrench + (l - 1) * 6 * 64 + lane;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      w[k * 64] = f[k];
+      w[(3 + k) * 64] = m[k];
+    }
+  }
+  __syncthreads();
+  if (wave != 0 || !live) return;
+
   // tip to base: F_j, M_j over links >= j; J_j = z_j . (M_j - o_j x F_j)
   float Jv[J_GROUP];
   float F[3] = {0.f, 0.f, 0.f}, M[3] = {0.f, 0.f, 0.f};
 #pragma unroll
   for (int l = N_FIXED; l >= 1; --l) {
+    const float* w = wrench + (l - 1) * 6 * 64 + lane;
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-      F[i] += fa[l - 1][i];
-      M[i] += ma[l - 1][i];
+      F[i] += w[i * 64];
+      M[i] += w[(3 + i) * 64];
     }
     if (l <= N_JOINTS) {
-      const float* T = Tl[l - 1];
-      const float zx = T[2], zy = T[6], zz = T[10], ox = T[3], oy = T[7], oz = T[11];
+      const float* T = tile + l * LINK_VALUES * 64 + lane;
+      const float zx = T[2 * 64], zy = T[6 * 64], zz = T[10 * 64];
+      const float ox = T[3 * 64], oy = T[7 * 64], oz = T[11 * 64];
       const float tx = M[0] - (oy * F[2] - oz * F[1]);
       const float ty = M[1] - (oz * F[0] - ox * F[2]);
       const float tz = M[2] - (ox * F[1] - oy * F[0]);
       Jv[l - 1] = fmaf(zx, tx, fmaf(zy, ty, zz * tz));
     }
   }
+  float qv[N_JOINTS];
+#pragma unroll
+  for (int j = 0; j < N_JOINTS; ++j) qv[j] = q[b * N_JOINTS + j];
   const int T = sh.T;
   const int64_t tc = b / T;
   const int t = (int)(b - tc * T);
@@ -1184,7 +1255,15 @@ static inline unsigned blocks_for(int64_t n, int per_block) { return (unsigned)(
 
 hipError_t launch_fk(hipStream_t s, const float* q, const RobotArgs& R, const TV& L, const TV& S, float* bound,
                      int64_t B, int store_L) {
-  hipLaunchKernelGGL(k_fk, dim3(blocks_for(B, 256)), dim3(256), 0, s, q, R, L, S, bound, B, store_L);
+  const dim3 grid(blocks_for(B, 64)), block(256);
+  switch (S.fmt) {
+#define VAPR_FK_CASE(F) \
+  case F: hipLaunchKernelGGL(k_fk<F>, grid, block, 0, s, q, R, L, S, bound, B, store_L); break;
+    VAPR_FK_CASE(F32) VAPR_FK_CASE(F16) VAPR_FK_CASE(BF16) VAPR_FK_CASE(E4M3) VAPR_FK_CASE(E5M2)
+    VAPR_FK_CASE(E3M2) VAPR_FK_CASE(E2M1)
+#undef VAPR_FK_CASE
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
@@ -1220,8 +1299,15 @@ hipError_t launch_reduce(hipStream_t s, const TV& D, const float* selfc, const f
 
 hipError_t launch_adjoint(hipStream_t s, const float* q, const RobotArgs& R, const TV& L, const TV& G, const TV& J,
                           const double* up, float* grad_q, const ShapeArgs& sh, const CostArgs& cp, int recompute) {
-  hipLaunchKernelGGL(k_adjoint, dim3(blocks_for(sh.B, 256)), dim3(256), 0, s, q, R, L, G, J, up, grad_q, sh, cp,
-                     recompute);
+  const dim3 grid(blocks_for(sh.B, 64)), block(256);
+  switch (G.fmt) {
+#define VAPR_ADJ_CASE(F) \
+  case F: hipLaunchKernelGGL(k_adjoint<F>, grid, block, 0, s, q, R, L, G, J, up, grad_q, sh, cp, recompute); break;
+    VAPR_ADJ_CASE(F32) VAPR_ADJ_CASE(F16) VAPR_ADJ_CASE(BF16) VAPR_ADJ_CASE(E4M3) VAPR_ADJ_CASE(E5M2)
+    VAPR_ADJ_CASE(E3M2) VAPR_ADJ_CASE(E2M1)
+#undef VAPR_ADJ_CASE
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

@@ -13,6 +13,7 @@ struct RobotArgs {
   const int* link;       // [n_groups*16] link of each sphere; padding -> 0
   const int* csr_off;    // [n_s + 1] self-pair partners of each sphere
   const int* csr_nbr;    // [2 * n_pairs]
+  const int* link_groups;  // [N_LINKS][2]: first and one-past-last sphere group holding a sphere of the link
   int n_s, n_groups;
   float q_lo[N_JOINTS], q_hi[N_JOINTS];
 };

@@ -47,6 +47,7 @@ struct vapr_ctx {
   int* d_link = nullptr;
   int* d_csr_off = nullptr;
   int* d_csr_nbr = nullptr;
+  int* d_link_groups = nullptr;
   float q_lo[N_JOINTS], q_hi[N_JOINTS];
   // worlds
   bool has_worlds = false;
@@ -137,10 +138,12 @@ void free_robot(vapr_ctx* ctx) {
   (void)hipFree(ctx->d_link);
   (void)hipFree(ctx->d_csr_off);
   (void)hipFree(ctx->d_csr_nbr);
+  (void)hipFree(ctx->d_link_groups);
   ctx->d_fixed = nullptr;
   ctx->d_sph = nullptr;
   ctx->d_link = nullptr;
   ctx->d_csr_off = ctx->d_csr_nbr = nullptr;
+  ctx->d_link_groups = nullptr;
   ctx->has_robot = false;
 }
 
@@ -178,6 +181,7 @@ RobotArgs robot_args(const vapr_ctx* ctx) {
   R.link = ctx->d_link;
   R.csr_off = ctx->d_csr_off;
   R.csr_nbr = ctx->d_csr_nbr;
+  R.link_groups = ctx->d_link_groups;
   R.n_s = ctx->n_s;
   R.n_groups = ctx->n_groups;
   for (int j = 0; j < N_JOINTS; ++j) {
@@ -526,6 +530,20 @@ int vapr_set_robot(vapr_ctx* ctx, int n_joints, const float* fixed_tf, int n_sph
     sph[s] = make_float4(sphere_center[3 * s], sphere_center[3 * s + 1], sphere_center[3 * s + 2], sphere_radius[s]);
     link[s] = sphere_link[s];
   }
+  // per link: the range of sphere groups that hold its spheres (empty range: none)
+  std::vector<int> lgr(2 * N_LINKS, 0);
+  for (int l = 0; l < N_LINKS; ++l) {
+    int lo = -1, hi = -1;
+    for (int s = 0; s < n_spheres; ++s)
+      if (sphere_link[s] == l) {
+        if (lo < 0) lo = s / SPH_GROUP;
+        hi = s / SPH_GROUP + 1;
+      }
+    if (lo >= 0) {
+      lgr[2 * l] = lo;
+      lgr[2 * l + 1] = hi;
+    }
+  }
   std::vector<int> off(n_spheres + 1, 0), flat;
   for (int s = 0; s < n_spheres; ++s) {
     off[s + 1] = off[s] + (int)nbr[s].size();
@@ -540,7 +558,8 @@ int vapr_set_robot(vapr_ctx* ctx, int n_joints, const float* fixed_tf, int n_sph
       (st = upload(ctx, &ctx->d_sph, sph.data(), sph.size())) ||
       (st = upload(ctx, &ctx->d_link, link.data(), link.size())) ||
       (st = upload(ctx, &ctx->d_csr_off, off.data(), off.size())) ||
-      (st = upload(ctx, &ctx->d_csr_nbr, flat.empty() ? nullptr : flat.data(), flat.size()))) {
+      (st = upload(ctx, &ctx->d_csr_nbr, flat.empty() ? nullptr : flat.data(), flat.size())) ||
+      (st = upload(ctx, &ctx->d_link_groups, lgr.data(), lgr.size()))) {
     free_robot(ctx);
     return st;
   }

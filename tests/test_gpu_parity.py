@@ -188,12 +188,26 @@ def test_stage_adjoint_codes(pname, recompute):
                                   F.dequantize(got, fmt, k))
 
 
+def shuffled_robot(robot, seed):
+    """The same robot with its spheres listed in a seeded random order (links interleaved), so
+    consecutive spheres change link often and every link's spheres span several groups."""
+    perm = np.random.default_rng(seed).permutation(robot.n_spheres)  # new sphere i is old perm[i]
+    inv = np.empty_like(perm)
+    inv[perm] = np.arange(perm.size)
+    pairs = np.sort(inv[robot.pairs], axis=1)
+    pairs = pairs[np.lexsort((pairs[:, 1], pairs[:, 0]))].astype(np.int32)
+    return dataclasses.replace(robot, sphere_center=robot.sphere_center[perm],
+                               sphere_radius=robot.sphere_radius[perm],
+                               sphere_link=robot.sphere_link[perm].astype(np.int32), pairs=pairs)
+
+
 @pytest.mark.parametrize("case", ["ragged", "no_cuboids", "no_pairs", "one_sphere", "worlds_in_wave",
-                                  "many_spheres"])
+                                  "many_spheres", "shuffled_links", "shuffled_many_spheres"])
 def test_edge_shapes(case):
     need_gpu()
     kw = dict(seed=21, n_worlds=3, tpw=3, T=5, n_ls=2, n_spheres=37, n_cuboids=7, n_pairs=40)
-    if case == "many_spheres":  # more than 8 sphere groups: the kernel that reads positions from HBM
+    if case in ("many_spheres", "shuffled_many_spheres"):
+        # more than 8 sphere groups: the kernel that reads positions from HBM
         kw.update(n_spheres=150, n_pairs=400)
     if case == "no_cuboids":
         kw["n_cuboids"] = 0
@@ -204,6 +218,9 @@ def test_edge_shapes(case):
     if case == "worlds_in_wave":
         kw.update(n_worlds=9, tpw=1, T=4, n_ls=1)
     wl = dense_workload(**kw)
+    if case.startswith("shuffled"):
+        wl = dataclasses.replace(wl, robot=shuffled_robot(wl.robot, seed=5))
+        assert np.any(np.diff(wl.robot.sphere_link) < 0)
     ctx = make_context(wl, {})
     cost, grad, _, _, _ = run_gpu(ctx, wl)
     ref = run_oracle(wl, {})
