@@ -474,9 +474,9 @@ __global__ __launch_bounds__(256) void k_sphere_cost(RobotArgs R, WorldArgs W, T
 
 // ---- K2 on a block staged in LDS, with exact cuboid culling -------------------------------------
 //
-// One workgroup per block of 64 configurations and one wavefront per group of 16 spheres.  The
-// block's stored sphere positions (all groups) are copied once into LDS; each wavefront decodes its
-// own group for the world term and reads self-pair partners of any group from LDS.
+// One workgroup per block of 64 configurations and one wavefront per group of 16 spheres.  Each
+// wavefront decodes its own group's stored positions once and leaves them, as FP32, in the block's
+// LDS image, where the self-pair partners of any group are read.
 //
 // Culling: a voxel grid over the region where any cuboid can be within reach holds, per world and
 // voxel, a bit per cuboid that may lie within eta + r_max (+ margin) of some point of the voxel.  A
@@ -520,9 +520,9 @@ __device__ __forceinline__ void cuboid_key(cptr<float> bx, float px, float py, f
 }
 
 template <int FS>
-__global__ __launch_bounds__(512) void k_sphere_cost_blk(RobotArgs R, WorldArgs W, GridArgs Gd, TV S, TV D, TV G,
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3))) void k_sphere_cost_blk(RobotArgs R, WorldArgs W, GridArgs Gd, TV S, TV D, TV G,
                                                           float* __restrict__ selfc, ShapeArgs sh, CostArgs cp) {
-  extern __shared__ uint32_t lds[];
+  extern __shared__ float lds_f[];
   const int lane = threadIdx.x & 63;
   const int g = uniform(threadIdx.x >> 6);
   const int ng = uniform(R.n_groups);
@@ -531,17 +531,29 @@ __global__ __launch_bounds__(512) void k_sphere_cost_blk(RobotArgs R, WorldArgs 
   const int64_t blk = blockIdx.x;
   const int64_t b = blk * 64 + lane;
   const bool valid = b < sh.B;
-  const int P = S.P;
+  float* pos = lds_f;                                // sphere s, component c: pos[(s * 3 + c) * 64 + lane]
+  float* part = lds_f + ng * SPH_GROUP * 3 * 64;     // [ng][64] self-cost partials
 
-  // stage the block's stored positions: P planes x 64 dwords, contiguous in HBM
-  {
-    const uint4* src = reinterpret_cast<const uint4*>(S.p + blk * (int64_t)P * 64);
-    uint4* dst = reinterpret_cast<uint4*>(lds);
-    for (int i = threadIdx.x; i < P * 16; i += blockDim.x) dst[i] = src[i];
+  float px[SPH_GROUP], py[SPH_GROUP], pz[SPH_GROUP];
+  if (valid) {
+    const uint32_t* sb = lane_base(S, b);
+    load_group_at<FS, SPH_GROUP>(sb, g * 3 + 0, S.scale, px);
+    load_group_at<FS, SPH_GROUP>(sb, g * 3 + 1, S.scale, py);
+    load_group_at<FS, SPH_GROUP>(sb, g * 3 + 2, S.scale, pz);
+  } else {
+#pragma unroll
+    for (int i = 0; i < SPH_GROUP; ++i) px[i] = py[i] = pz[i] = 0.f;
   }
-  float* part = reinterpret_cast<float*>(lds + P * 64);  // [ng][64] self-cost partials
+  {
+    float* mine = pos + g * SPH_GROUP * 3 * 64 + lane;
+#pragma unroll
+    for (int i = 0; i < SPH_GROUP; ++i) {
+      mine[(i * 3 + 0) * 64] = px[i];
+      mine[(i * 3 + 1) * 64] = py[i];
+      mine[(i * 3 + 2) * 64] = pz[i];
+    }
+  }
   __syncthreads();
-  const uint32_t* sb = lds + lane;
 
   const int64_t first = blk * 64;
   const int64_t last = (first + 63 < sh.B ? first + 63 : sh.B - 1);
@@ -550,10 +562,6 @@ __global__ __launch_bounds__(512) void k_sphere_cost_blk(RobotArgs R, WorldArgs 
   const int my_w = valid ? (int)(b / sh.cfg_per_world) : -1;
   const int active = uniform(min(SPH_GROUP, n_s - g * SPH_GROUP));
 
-  float px[SPH_GROUP], py[SPH_GROUP], pz[SPH_GROUP];
-  load_group_at<FS, SPH_GROUP>(sb, g * 3 + 0, S.scale, px);
-  load_group_at<FS, SPH_GROUP>(sb, g * 3 + 1, S.scale, py);
-  load_group_at<FS, SPH_GROUP>(sb, g * 3 + 2, S.scale, pz);
   float best[SPH_GROUP];
   int bk[SPH_GROUP];
 #pragma unroll
@@ -625,10 +633,11 @@ __global__ __launch_bounds__(512) void k_sphere_cost_blk(RobotArgs R, WorldArgs 
       }
     }
   }
-  // Self pairs: partners of any group are read from the staged block in batches of PB so that
-  // their reads are in flight together.  Each pair is visited from both of its spheres: each visit
-  // adds its own sphere's gradient and the lower index adds the cost, so no cross-lane or atomic
-  // accumulation is needed.
+  // Self pairs: partners of any group are read from the LDS image four at a time (one scalar load
+  // of four table entries).  A visit whose squared centre distance exceeds the pair's bound is
+  // inactive and ends there; the others take the exact path.  Each pair is visited from both of its
+  // spheres: each visit adds its own sphere's gradient and the lower index adds the cost, so no
+  // cross-lane or atomic accumulation is needed.
   float self_acc = 0.f;
   constexpr int PB = 4;
 #pragma unroll
@@ -636,36 +645,37 @@ __global__ __launch_bounds__(512) void k_sphere_cost_blk(RobotArgs R, WorldArgs 
     if (i >= active) continue;
     const int s = g * SPH_GROUP + i;
     const float rs = sphere_of(R.sph, s).w;
-    const int j0 = as_const(R.csr_off)[s], j1 = as_const(R.csr_off)[s + 1];
+    const int j0 = as_const(R.pair_off)[s], j1 = as_const(R.pair_off)[s + 1];
     for (int j = j0; j < j1; j += PB) {
-      float tx[PB], ty[PB], tz[PB], rt[PB];
-      int tt[PB];
+      const cptr<float> e = as_const(reinterpret_cast<const float*>(R.pair_tab)) + 4 * j;
+      float tx[PB], ty[PB], tz[PB];
 #pragma unroll
       for (int u = 0; u < PB; ++u) {
-        const int jj = j + u < j1 ? j + u : j;  // a repeated partner is read but not used
-        const int t = as_const(R.csr_nbr)[jj];
-        tt[u] = t;
-        const int tg = t / SPH_GROUP, tp = t % SPH_GROUP;
-        tx[u] = load_elem_at<FS, SPH_GROUP>(sb, tg * 3 + 0, tp, S.scale);
-        ty[u] = load_elem_at<FS, SPH_GROUP>(sb, tg * 3 + 1, tp, S.scale);
-        tz[u] = load_elem_at<FS, SPH_GROUP>(sb, tg * 3 + 2, tp, S.scale);
-        rt[u] = sphere_of(R.sph, t).w;
+        const float* pp = pos + (unsigned)__float_as_int(e[4 * u]) * 3u * 64u + lane;
+        tx[u] = pp[0];
+        ty[u] = pp[64];
+        tz[u] = pp[128];
       }
 #pragma unroll
       for (int u = 0; u < PB; ++u) {
-        if (j + u >= j1) continue;
         const float dx = px[i] - tx[u], dy = py[i] - ty[u], dz = pz[i] - tz[u];
-        const float dist = sqrtf(fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
-        const float e = dist - rs - rt[u];
-        const float act = fmaxf(cp.eta - e, 0.f);
+        const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+        if (!(d2 <= e[4 * u + 2])) continue;
+        // hardware reciprocal square root (about 1 ulp): distance and unit direction in one step;
+        // coincident centres give distance 0 and no gradient
+        const float inv = __builtin_amdgcn_rsqf(d2);
+        const bool apart = d2 > 0.f;
+        const float dist = apart ? d2 * inv : 0.f;
+        const float ev = dist - rs - e[4 * u + 1];
+        const float act = fmaxf(cp.eta - ev, 0.f);
         if (act > 0.f) {
-          if (dist > 0.f) {
-            const float coef = -2.f * cp.w_s * act / dist;
+          const float coef = (-2.f * cp.w_s) * act * inv;
+          if (apart) {
             gx[i] = fmaf(coef, dx, gx[i]);
             gy[i] = fmaf(coef, dy, gy[i]);
             gz[i] = fmaf(coef, dz, gz[i]);
           }
-          if (s < tt[u]) self_acc = fmaf(act, act, self_acc);
+          if (s < __float_as_int(e[4 * u])) self_acc = fmaf(act, act, self_acc);
         }
       }
     }
@@ -1273,12 +1283,12 @@ hipError_t launch_sphere_cost(hipStream_t s, const RobotArgs& R, const WorldArgs
   return hipGetLastError();
 }
 
-size_t sphere_cost_lds_bytes(int P_S, int n_groups) { return (size_t)P_S * 256 + (size_t)n_groups * 256; }
+size_t sphere_cost_lds_bytes(int n_groups) { return (size_t)n_groups * (SPH_GROUP * 3 + 1) * 256; }
 
 hipError_t launch_sphere_cost_blk(hipStream_t s, const RobotArgs& R, const WorldArgs& W, const GridArgs& Gd,
                                   const TV& S, const TV& D, const TV& G, float* selfc, const ShapeArgs& sh,
                                   const CostArgs& cp) {
-  const size_t lds = sphere_cost_lds_bytes(S.P, R.n_groups);
+  const size_t lds = sphere_cost_lds_bytes(R.n_groups);
   const dim3 grid(blocks_for(sh.B, 64)), block(64 * R.n_groups);
   switch (S.fmt) {
 #define VAPR_K2(F) \

@@ -14,6 +14,12 @@ struct RobotArgs {
   const int* csr_off;    // [n_s + 1] self-pair partners of each sphere
   const int* csr_nbr;    // [2 * n_pairs]
   const int* link_groups;  // [N_LINKS][2]: first and one-past-last sphere group holding a sphere of the link
+  // Self-pair visits of sphere s: pair_tab[pair_off[s] .. pair_off[s + 1]), a multiple of 4
+  // entries (partner index as int bits, partner radius, lim2, 0), where lim2 bounds the squared
+  // centre distance beyond which the pair is certainly inactive; lists are padded with entries
+  // (s, 0, -1, 0) that are never active.
+  const int* pair_off;
+  const float4* pair_tab;
   int n_s, n_groups;
   float q_lo[N_JOINTS], q_hi[N_JOINTS];
 };
@@ -71,8 +77,8 @@ hipError_t launch_fk(hipStream_t s, const float* q, const RobotArgs& R, const TV
                      int64_t B, int store_L);
 hipError_t launch_sphere_cost(hipStream_t s, const RobotArgs& R, const WorldArgs& W, const TV& S, const TV& D,
                               const TV& G, float* selfc, const ShapeArgs& sh, const CostArgs& cp);
-// LDS bytes of the block-staged sphere-cost kernel (used for <= 8 sphere groups and <= 64 KiB)
-size_t sphere_cost_lds_bytes(int P_S, int n_groups);
+// LDS bytes of the block-staged sphere-cost kernel (used while they fit in 64 KiB)
+size_t sphere_cost_lds_bytes(int n_groups);
 hipError_t launch_sphere_cost_blk(hipStream_t s, const RobotArgs& R, const WorldArgs& W, const GridArgs& Gd,
                                   const TV& S, const TV& D, const TV& G, float* selfc, const ShapeArgs& sh,
                                   const CostArgs& cp);

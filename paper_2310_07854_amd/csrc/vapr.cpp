@@ -49,6 +49,11 @@ struct vapr_ctx {
   int* d_csr_nbr = nullptr;
   int* d_link_groups = nullptr;
   float q_lo[N_JOINTS], q_hi[N_JOINTS];
+  std::vector<float> h_radius;             // host copies for the self-pair table
+  std::vector<int> h_csr_off, h_csr_nbr;
+  float4* d_pair_tab = nullptr;            // rebuilt lazily when the robot or eta change
+  int* d_pair_off = nullptr;
+  bool pairs_valid = false;
   // worlds
   bool has_worlds = false;
   int n_worlds = 0, n_cuboids = 0;
@@ -139,6 +144,11 @@ void free_robot(vapr_ctx* ctx) {
   (void)hipFree(ctx->d_csr_off);
   (void)hipFree(ctx->d_csr_nbr);
   (void)hipFree(ctx->d_link_groups);
+  (void)hipFree(ctx->d_pair_tab);
+  (void)hipFree(ctx->d_pair_off);
+  ctx->d_pair_tab = nullptr;
+  ctx->d_pair_off = nullptr;
+  ctx->pairs_valid = false;
   ctx->d_fixed = nullptr;
   ctx->d_sph = nullptr;
   ctx->d_link = nullptr;
@@ -182,6 +192,8 @@ RobotArgs robot_args(const vapr_ctx* ctx) {
   R.csr_off = ctx->d_csr_off;
   R.csr_nbr = ctx->d_csr_nbr;
   R.link_groups = ctx->d_link_groups;
+  R.pair_tab = ctx->d_pair_tab;
+  R.pair_off = ctx->d_pair_off;
   R.n_s = ctx->n_s;
   R.n_groups = ctx->n_groups;
   for (int j = 0; j < N_JOINTS; ++j) {
@@ -234,6 +246,46 @@ int timed(vapr_ctx* ctx, int id, F&& launch, const char* what) {
     VAPR_HIP(ctx, hipEventRecord(b, ctx->stream));
     ctx->prof_live.push_back({id, a, b});
   }
+  return VAPR_OK;
+}
+
+// Self-pair visit lists, one per sphere in CSR order, padded to a multiple of 4 entries:
+// (partner, partner radius, lim2, 0).  lim2 >= ((r_s + r_t + eta) * (1 + 2^-8))^2, rounded up: a
+// pair whose FP32 squared centre distance exceeds it has clearance above eta by far more than the
+// rounding of the clearance, so its activation is exactly zero.  Padding entries name the sphere
+// itself with lim2 = -1, which no squared distance reaches.
+int build_pair_table(vapr_ctx* ctx) {
+  if (ctx->d_pair_tab || ctx->d_pair_off) {
+    VAPR_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    (void)hipFree(ctx->d_pair_tab);
+    (void)hipFree(ctx->d_pair_off);
+    ctx->d_pair_tab = nullptr;
+    ctx->d_pair_off = nullptr;
+  }
+  const double eta = ctx->params.eta;
+  auto as_float = [](int v) {
+    float f;
+    std::memcpy(&f, &v, sizeof f);
+    return f;
+  };
+  std::vector<int> off(ctx->n_s + 1, 0);
+  std::vector<float4> tab;
+  for (int s = 0; s < ctx->n_s; ++s) {
+    for (int j = ctx->h_csr_off[s]; j < ctx->h_csr_off[s + 1]; ++j) {
+      const int t = ctx->h_csr_nbr[j];
+      const double lim = ((double)ctx->h_radius[s] + (double)ctx->h_radius[t] + eta) * (1.0 + 1.0 / 256.0);
+      float lim2 = (float)(lim * lim);
+      if ((double)lim2 < lim * lim) lim2 = std::nextafter(lim2, INFINITY);
+      tab.push_back(make_float4(as_float(t), ctx->h_radius[t], lim2, 0.f));
+    }
+    while (tab.size() % 4) tab.push_back(make_float4(as_float(s), 0.f, -1.f, 0.f));
+    off[s + 1] = (int)tab.size();
+  }
+  int st;
+  if ((st = upload(ctx, &ctx->d_pair_tab, tab.empty() ? nullptr : tab.data(), tab.size())) ||
+      (st = upload(ctx, &ctx->d_pair_off, off.data(), off.size())))
+    return st;
+  ctx->pairs_valid = true;
   return VAPR_OK;
 }
 
@@ -335,6 +387,7 @@ int run_fwd(vapr_ctx* ctx, int first, int n_worlds, int tpw, int T, int n_ls, co
       return fail(ctx, VAPR_E_STATE, "workspace does not hold this shape at the current precision");
   }
   const ShapeArgs sh = shape_args(n_worlds, tpw, T, n_ls);
+  if (!ctx->pairs_valid && (st = build_pair_table(ctx))) return st;
   const RobotArgs R = robot_args(ctx);
   const TV tL = tensor_view(ws, L, ctx->prec, T_L), tS = tensor_view(ws, L, ctx->prec, T_S),
            tD = tensor_view(ws, L, ctx->prec, T_D), tG = tensor_view(ws, L, ctx->prec, T_G);
@@ -351,7 +404,7 @@ int run_fwd(vapr_ctx* ctx, int first, int n_worlds, int tpw, int T, int n_ls, co
     const CostArgs cp = ctx->params;
     if (!ctx->grid_valid && (st = build_grid(ctx))) return st;
     const GridArgs Gd = ctx->grid;
-    if (ctx->n_groups <= 8 && sphere_cost_lds_bytes(L.P[T_S], ctx->n_groups) <= 65536) {
+    if (sphere_cost_lds_bytes(ctx->n_groups) <= 65536) {
       st = timed(ctx, K_SPHERE, [&] { return launch_sphere_cost_blk(s, R, W, Gd, tS, tD, tG, selfc, sh, cp); },
                  "k_sphere_cost_blk launch");
     } else {
@@ -570,6 +623,10 @@ int vapr_set_robot(vapr_ctx* ctx, int n_joints, const float* fixed_tf, int n_sph
     ctx->q_lo[j] = q_lo[j];
     ctx->q_hi[j] = q_hi[j];
   }
+  ctx->h_radius.assign(sphere_radius, sphere_radius + n_spheres);
+  ctx->h_csr_off = off;
+  ctx->h_csr_nbr = flat;
+  ctx->pairs_valid = false;
   ctx->has_robot = true;
   ctx->robot_gen++;
   ctx->r_max = 0.f;
@@ -648,6 +705,7 @@ int vapr_set_cost_params(vapr_ctx* ctx, const vapr_cost_params* p) {
     return fail(ctx, VAPR_E_INVALID, "cost parameters out of range");
   ctx->params = CostArgs{p->eta, p->w_coll, p->w_self, p->w_bound, p->w_smooth};
   ctx->grid_valid = false;
+  ctx->pairs_valid = false;
   return VAPR_OK;
 }
 
