@@ -482,19 +482,12 @@ __global__ __launch_bounds__(256) void k_sphere_cost(RobotArgs R, WorldArgs W, T
 // voxel, a bit per cuboid that may lie within eta + r_max (+ margin) of some point of the voxel.  A
 // cuboid without the bit has clearance >= eta for every sphere in the voxel, so it can change
 // neither the activation depth (clamped at zero) nor the closest cuboid of an active sphere: the
-// result is identical to testing every cuboid.  The wavefront tests, per sphere, the union of its
-// lanes' candidate sets, keeping the cuboid on scalar operands.
+// result is identical to testing every cuboid.
 
 #ifndef VAPR_CULL_SPHERES
 #define VAPR_CULL_SPHERES 4
 #endif
 constexpr int CQ = VAPR_CULL_SPHERES;  // spheres sharing one candidate list (divides 16)
-
-__device__ __forceinline__ uint32_t wave_or(uint32_t v) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) v |= (uint32_t)__shfl_xor((int)v, off, 64);
-  return v;
-}
 
 __device__ __forceinline__ int voxel_of(const GridArgs& g, float x, float y, float z) {
   const float fx = (x - g.ox) * g.inv_cell, fy = (y - g.oy) * g.inv_cell, fz = (z - g.oz) * g.inv_cell;
@@ -502,21 +495,6 @@ __device__ __forceinline__ int voxel_of(const GridArgs& g, float x, float y, flo
   // also false for NaN coordinates
   if (!(fx >= 0.f && fx < n && fy >= 0.f && fy < n && fz >= 0.f && fz < n)) return -1;
   return ((int)fz * g.n + (int)fy) * g.n + (int)fx;
-}
-
-// one sphere against one cuboid (scalar operands), running closest-cuboid key
-__device__ __forceinline__ void cuboid_key(cptr<float> bx, float px, float py, float pz, int k, float& best,
-                                           int& bk) {
-  const float u0 = fmaf(bx[0], px, fmaf(bx[1], py, bx[2] * pz)) - bx[9];
-  const float u1 = fmaf(bx[3], px, fmaf(bx[4], py, bx[5] * pz)) - bx[10];
-  const float u2 = fmaf(bx[6], px, fmaf(bx[7], py, bx[8] * pz)) - bx[11];
-  const float a0 = fabsf(u0) - bx[12], a1 = fabsf(u1) - bx[13], a2 = fabsf(u2) - bx[14];
-  const float m0 = fmaxf(a0, 0.f), m1 = fmaxf(a1, 0.f), m2 = fmaxf(a2, 0.f);
-  const float key = fmaf(m0, m0, fmaf(m1, m1, m2 * m2)) + fminf(fmaxf(fmaxf(a0, a1), a2), 0.f);
-  if (key < best) {
-    best = key;
-    bk = k;
-  }
 }
 
 template <int FS>
@@ -571,33 +549,41 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3))) void k
   }
 
   if (Gd.MW > 0) {
-    int vox[SPH_GROUP];
+    // Each lane walks its own candidate list (the union over CQ spheres of its voxels' masks),
+    // reading the cuboid from its world's table: the wavefront iterates as often as its busiest
+    // lane needs, not over the union of all lanes' candidates.
+    if (valid) {
+      const float* wbox = W.box + (int64_t)my_w * K * 16;
+      const uint32_t* wmask = Gd.mask + (int64_t)my_w * ((int64_t)Gd.n * Gd.n * Gd.n) * Gd.MW;
 #pragma unroll
-    for (int i = 0; i < SPH_GROUP; ++i) vox[i] = voxel_of(Gd, px[i], py[i], pz[i]);
-    const int64_t n3 = (int64_t)Gd.n * Gd.n * Gd.n;
-    for (int w = w_lo; w <= w_hi; ++w) {
-      const int wu = uniform(w);
-      const cptr<float> wbox = as_const(W.box) + (int64_t)wu * K * 16;
-      const uint32_t* wmask = Gd.mask + (int64_t)wu * n3 * Gd.MW;
-      for (int mw = 0; mw < Gd.MW; ++mw) {
-        uint32_t mk[SPH_GROUP];
+      for (int i0 = 0; i0 < SPH_GROUP; i0 += CQ) {
+        if (i0 >= active) continue;
+        int vox[CQ];
 #pragma unroll
-        for (int i = 0; i < SPH_GROUP; ++i)
-          mk[i] = (i < active && my_w == wu && vox[i] >= 0) ? wmask[(int64_t)vox[i] * Gd.MW + mw] : 0u;
-        // candidates are shared by CQ consecutive spheres: one scalar load of a cuboid serves them all
+        for (int i = 0; i < CQ; ++i) vox[i] = (i0 + i < active) ? voxel_of(Gd, px[i0 + i], py[i0 + i], pz[i0 + i]) : -1;
+        for (int mw = 0; mw < Gd.MW; ++mw) {
+          uint32_t m = 0;
 #pragma unroll
-        for (int i0 = 0; i0 < SPH_GROUP; i0 += CQ) {
-          if (i0 >= active) continue;
-          uint32_t mq = 0;
-#pragma unroll
-          for (int i = i0; i < i0 + CQ; ++i) mq |= mk[i];
-          uint32_t m = (uint32_t)uniform((int)wave_or(mq));
-          if (my_w != wu) continue;
+          for (int i = 0; i < CQ; ++i)
+            if (vox[i] >= 0) m |= wmask[(int64_t)vox[i] * Gd.MW + mw];
           while (m) {
             const int k = mw * 32 + __builtin_ctz(m);
             m &= m - 1;
+            const float4* c4 = reinterpret_cast<const float4*>(wbox + k * 16);
+            const float4 c0 = c4[0], c1 = c4[1], c2 = c4[2], c3 = c4[3];
 #pragma unroll
-            for (int i = i0; i < i0 + CQ; ++i) cuboid_key(wbox + k * 16, px[i], py[i], pz[i], k, best[i], bk[i]);
+            for (int i = i0; i < i0 + CQ; ++i) {
+              const float u0 = fmaf(c0.x, px[i], fmaf(c0.y, py[i], c0.z * pz[i])) - c2.y;
+              const float u1 = fmaf(c0.w, px[i], fmaf(c1.x, py[i], c1.y * pz[i])) - c2.z;
+              const float u2 = fmaf(c1.z, px[i], fmaf(c1.w, py[i], c2.x * pz[i])) - c2.w;
+              const float a0 = fabsf(u0) - c3.x, a1 = fabsf(u1) - c3.y, a2 = fabsf(u2) - c3.z;
+              const float m0 = fmaxf(a0, 0.f), m1 = fmaxf(a1, 0.f), m2 = fmaxf(a2, 0.f);
+              const float key = fmaf(m0, m0, fmaf(m1, m1, m2 * m2)) + fminf(fmaxf(fmaxf(a0, a1), a2), 0.f);
+              if (key < best[i]) {
+                best[i] = key;
+                bk[i] = k;
+              }
+            }
           }
         }
       }
