@@ -683,10 +683,37 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3))) void k
 
 // ---- K3: aggregation -----------------------------------------------------------------------------
 
+// ---- wavefront reductions: DPP steps inside each 16-lane row, then the four row results added in
+// a fixed order (the same value in every lane; the wavefront must be fully active) ----------------
+
+constexpr int DPP_SWAP1 = 0xB1;         // quad_perm [1,0,3,2]
+constexpr int DPP_SWAP2 = 0x4E;         // quad_perm [2,3,0,1]
+constexpr int DPP_HALF_MIRROR = 0x141;  // lane i <- lane 7 - i of its half-row
+constexpr int DPP_MIRROR = 0x140;       // lane i <- lane 15 - i of its row
+
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const uint64_t u = (uint64_t)__double_as_longlong(v);
+  const uint64_t lo = dpp_u32<CTRL>((uint32_t)u), hi = dpp_u32<CTRL>((uint32_t)(u >> 32));
+  return __longlong_as_double((long long)((hi << 32) | lo));
+}
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+  const uint64_t u = (uint64_t)__double_as_longlong(v);
+  const uint64_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, lane);
+  const uint64_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), lane);
+  return __longlong_as_double((long long)((hi << 32) | lo));
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
+  v += dpp_f64<DPP_SWAP1>(v);
+  v += dpp_f64<DPP_SWAP2>(v);
+  v += dpp_f64<DPP_HALF_MIRROR>(v);
+  v += dpp_f64<DPP_MIRROR>(v);
+  return (readlane_f64(v, 0) + readlane_f64(v, 16)) + (readlane_f64(v, 32) + readlane_f64(v, 48));
 }
 
 __global__ __launch_bounds__(256) void k_reduce(TV D, const float* __restrict__ selfc,
@@ -858,15 +885,23 @@ __global__ __launch_bounds__(256) void k_adjoint(const float* __restrict__ q, Ro
 
 // ---- K5: line search + L-BFGS ----------------------------------------------------------------
 
-constexpr int OPT_NE = (MAX_OPT_T * N_JOINTS + 63) / 64;  // variables per lane
+// variables per lane: NE = ceil(7 T / 64), a template parameter (1..7 for T <= 64)
+constexpr int OPT_NE_MAX = (MAX_OPT_T * N_JOINTS + 63) / 64;
 
 __device__ __forceinline__ float wave_max(float v) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
-  return v;
+  v = fmaxf(v, __uint_as_float(dpp_u32<DPP_SWAP1>(__float_as_uint(v))));
+  v = fmaxf(v, __uint_as_float(dpp_u32<DPP_SWAP2>(__float_as_uint(v))));
+  v = fmaxf(v, __uint_as_float(dpp_u32<DPP_HALF_MIRROR>(__float_as_uint(v))));
+  v = fmaxf(v, __uint_as_float(dpp_u32<DPP_MIRROR>(__float_as_uint(v))));
+  const float r0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0));
+  const float r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 16));
+  const float r2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32));
+  const float r3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 48));
+  return fmaxf(fmaxf(r0, r1), fmaxf(r2, r3));
 }
 
 // -g capped so that its largest component is at most max_step (scale computed in FP64)
+template <int OPT_NE>
 __device__ __forceinline__ void steepest(const float (&g)[OPT_NE], float max_step, float (&d)[OPT_NE]) {
   float gm = 0.f;
 #pragma unroll
@@ -879,6 +914,7 @@ __device__ __forceinline__ void steepest(const float (&g)[OPT_NE], float max_ste
 }
 __constant__ float c_alpha[MAX_LS] = {1.0f, 0.5f, 0.25f, 0.125f};
 
+template <int OPT_NE>
 __global__ __launch_bounds__(256) void k_optimizer(OptArgs o, TV J, const double* __restrict__ cost_in,
                                                    float* __restrict__ q_cand, int mode) {
   const int tr = blockIdx.x * 4 + uniform(threadIdx.x >> 6);
@@ -976,9 +1012,26 @@ __global__ __launch_bounds__(256) void k_optimizer(OptArgs o, TV J, const double
         len = min(len + 1, m);
         flags |= 1;
       }
-      // two-loop recursion, newest pair first; the second pass re-reads the pairs (L2-resident)
-      // rather than holding them in registers, which keeps many wavefronts resident
-      double qv[OPT_NE], a_it[MAX_HIST];
+      // two-loop recursion, newest pair first, on the history loaded into registers up front (every
+      // load in flight together; the recursion itself then waits only on its reductions)
+      float hs[MAX_HIST][OPT_NE], hy[MAX_HIST][OPT_NE];
+      double rho_h[MAX_HIST], a_it[MAX_HIST];
+#pragma unroll
+      for (int it = 0; it < MAX_HIST; ++it) {
+        rho_h[it] = 0.0;
+        if (it < len) {
+          const int slot = (head - 1 - it + 2 * m) % m;
+          const int64_t hb = ((int64_t)tr * m + slot) * n;
+          rho_h[it] = o.rho[(int64_t)tr * m + slot];
+#pragma unroll
+          for (int k = 0; k < OPT_NE; ++k) {
+            const int e = lane + 64 * k;
+            hs[it][k] = e < n ? o.s_hist[hb + e] : 0.f;
+            hy[it][k] = e < n ? o.y_hist[hb + e] : 0.f;
+          }
+        }
+      }
+      double qv[OPT_NE];
 #pragma unroll
       for (int k = 0; k < OPT_NE; ++k) qv[k] = (double)g[k];
       double gamma = 1.0;
@@ -986,29 +1039,19 @@ __global__ __launch_bounds__(256) void k_optimizer(OptArgs o, TV J, const double
       for (int it = 0; it < MAX_HIST; ++it) {
         a_it[it] = 0.0;
         if (it < len) {
-          const int slot = (head - 1 - it + 2 * m) % m;
-          const int64_t hb = ((int64_t)tr * m + slot) * n;
-          const double rho = o.rho[(int64_t)tr * m + slot];
-          float hs[OPT_NE], hy[OPT_NE];
-#pragma unroll
-          for (int k = 0; k < OPT_NE; ++k) {
-            const int e = lane + 64 * k;
-            hs[k] = e < n ? o.s_hist[hb + e] : 0.f;
-            hy[k] = e < n ? o.y_hist[hb + e] : 0.f;
-          }
           double sq = 0.0, sy0 = 0.0, yy0 = 0.0;
 #pragma unroll
           for (int k = 0; k < OPT_NE; ++k) {
-            sq = fma((double)hs[k], qv[k], sq);
+            sq = fma((double)hs[it][k], qv[k], sq);
             if (it == 0) {
-              sy0 = fma((double)hs[k], (double)hy[k], sy0);
-              yy0 = fma((double)hy[k], (double)hy[k], yy0);
+              sy0 = fma((double)hs[it][k], (double)hy[it][k], sy0);
+              yy0 = fma((double)hy[it][k], (double)hy[it][k], yy0);
             }
           }
-          a_it[it] = rho * wave_sum(sq);
+          a_it[it] = rho_h[it] * wave_sum(sq);
           if (it == 0) gamma = wave_sum(sy0) / wave_sum(yy0);
 #pragma unroll
-          for (int k = 0; k < OPT_NE; ++k) qv[k] = fma(-a_it[it], (double)hy[k], qv[k]);
+          for (int k = 0; k < OPT_NE; ++k) qv[k] = fma(-a_it[it], (double)hy[it][k], qv[k]);
         }
       }
 #pragma unroll
@@ -1016,22 +1059,17 @@ __global__ __launch_bounds__(256) void k_optimizer(OptArgs o, TV J, const double
 #pragma unroll
       for (int it = MAX_HIST - 1; it >= 0; --it) {
         if (it < len) {
-          const int slot = (head - 1 - it + 2 * m) % m;
-          const int64_t hb = ((int64_t)tr * m + slot) * n;
-          const double rho = o.rho[(int64_t)tr * m + slot];
-          float hs[OPT_NE], hy[OPT_NE];
-#pragma unroll
-          for (int k = 0; k < OPT_NE; ++k) {
-            const int e = lane + 64 * k;
-            hs[k] = e < n ? o.s_hist[hb + e] : 0.f;
-            hy[k] = e < n ? o.y_hist[hb + e] : 0.f;
-          }
           double yr = 0.0;
 #pragma unroll
-          for (int k = 0; k < OPT_NE; ++k) yr = fma((double)hy[k], qv[k], yr);
-          const double beta = rho * wave_sum(yr);
+          for (int k = 0; k < OPT_NE; ++k) {
+            // converted again here: keeping FP64 copies from the first pass would double the
+            // registers the history needs
+            asm volatile("" : "+v"(hs[it][k]), "+v"(hy[it][k]));
+            yr = fma((double)hy[it][k], qv[k], yr);
+          }
+          const double beta = rho_h[it] * wave_sum(yr);
 #pragma unroll
-          for (int k = 0; k < OPT_NE; ++k) qv[k] = fma(a_it[it] - beta, (double)hs[k], qv[k]);
+          for (int k = 0; k < OPT_NE; ++k) qv[k] = fma(a_it[it] - beta, (double)hs[it][k], qv[k]);
         }
       }
       double gdn = 0.0;
@@ -1309,7 +1347,16 @@ hipError_t launch_adjoint(hipStream_t s, const float* q, const RobotArgs& R, con
 
 hipError_t launch_optimizer(hipStream_t s, const OptArgs& o, const TV& J, const double* cost_in, float* q_cand,
                             int mode) {
-  hipLaunchKernelGGL(k_optimizer, dim3(blocks_for(o.n_traj, 4)), dim3(256), 0, s, o, J, cost_in, q_cand, mode);
+  const dim3 grid(blocks_for(o.n_traj, 4)), block(256);
+  switch ((o.T * N_JOINTS + 63) / 64) {
+#define VAPR_OPT_CASE(NE) \
+  case NE: hipLaunchKernelGGL(k_optimizer<NE>, grid, block, 0, s, o, J, cost_in, q_cand, mode); break;
+    VAPR_OPT_CASE(1) VAPR_OPT_CASE(2) VAPR_OPT_CASE(3) VAPR_OPT_CASE(4) VAPR_OPT_CASE(5) VAPR_OPT_CASE(6)
+    VAPR_OPT_CASE(7)
+#undef VAPR_OPT_CASE
+    default: return hipErrorInvalidValue;
+  }
+  static_assert(OPT_NE_MAX == 7, "optimizer instantiations cover T <= 64");
   return hipGetLastError();
 }
 
