@@ -497,6 +497,22 @@ __device__ __forceinline__ int voxel_of(const GridArgs& g, float x, float y, flo
   return ((int)fz * g.n + (int)fy) * g.n + (int)fx;
 }
 
+// one sphere against one cuboid held in registers (A = R^T rows in c0, c1, c2.x; o = c2.yzw;
+// h = c3.xyz), running closest-cuboid key; the first index wins ties
+__device__ __forceinline__ void cuboid_key_v(const float4& c0, const float4& c1, const float4& c2, const float4& c3,
+                                             float px, float py, float pz, int k, float& best, int& bk) {
+  const float u0 = fmaf(c0.x, px, fmaf(c0.y, py, c0.z * pz)) - c2.y;
+  const float u1 = fmaf(c0.w, px, fmaf(c1.x, py, c1.y * pz)) - c2.z;
+  const float u2 = fmaf(c1.z, px, fmaf(c1.w, py, c2.x * pz)) - c2.w;
+  const float a0 = fabsf(u0) - c3.x, a1 = fabsf(u1) - c3.y, a2 = fabsf(u2) - c3.z;
+  const float m0 = fmaxf(a0, 0.f), m1 = fmaxf(a1, 0.f), m2 = fmaxf(a2, 0.f);
+  const float key = fmaf(m0, m0, fmaf(m1, m1, m2 * m2)) + fminf(fmaxf(fmaxf(a0, a1), a2), 0.f);
+  if (key < best) {
+    best = key;
+    bk = k;
+  }
+}
+
 template <int FS>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3))) void k_sphere_cost_blk(RobotArgs R, WorldArgs W, GridArgs Gd, TV S, TV D, TV G,
                                                           float* __restrict__ selfc, ShapeArgs sh, CostArgs cp) {
@@ -555,34 +571,68 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3))) void k
     if (valid) {
       const float* wbox = W.box + (int64_t)my_w * K * 16;
       const uint32_t* wmask = Gd.mask + (int64_t)my_w * ((int64_t)Gd.n * Gd.n * Gd.n) * Gd.MW;
+      if (Gd.MW <= 2) {
+        // up to 64 cuboids: every sphere's mask gathered at once into one 64-bit list per quad,
+        // then each list walked with the next cuboid's load in flight during the current tests
+        uint64_t mq[SPH_GROUP / CQ];
 #pragma unroll
-      for (int i0 = 0; i0 < SPH_GROUP; i0 += CQ) {
-        if (i0 >= active) continue;
-        int vox[CQ];
+        for (int q = 0; q < SPH_GROUP / CQ; ++q) mq[q] = 0;
 #pragma unroll
-        for (int i = 0; i < CQ; ++i) vox[i] = (i0 + i < active) ? voxel_of(Gd, px[i0 + i], py[i0 + i], pz[i0 + i]) : -1;
-        for (int mw = 0; mw < Gd.MW; ++mw) {
-          uint32_t m = 0;
+        for (int i = 0; i < SPH_GROUP; ++i) {
+          const int v = i < active ? voxel_of(Gd, px[i], py[i], pz[i]) : -1;
+          if (v >= 0) {
+            const uint32_t* mp = wmask + (int64_t)v * Gd.MW;
+            mq[i / CQ] |= (uint64_t)mp[0] | (Gd.MW > 1 ? (uint64_t)mp[1] << 32 : 0);
+          }
+        }
 #pragma unroll
-          for (int i = 0; i < CQ; ++i)
-            if (vox[i] >= 0) m |= wmask[(int64_t)vox[i] * Gd.MW + mw];
-          while (m) {
-            const int k = mw * 32 + __builtin_ctz(m);
+        for (int q = 0; q < SPH_GROUP / CQ; ++q) {
+          const int i0 = q * CQ;
+          if (i0 >= active) continue;
+          uint64_t m = mq[q];
+          int k = -1;
+          float4 c0, c1, c2, c3;
+          if (m) {
+            k = __builtin_ctzll(m);
             m &= m - 1;
             const float4* c4 = reinterpret_cast<const float4*>(wbox + k * 16);
-            const float4 c0 = c4[0], c1 = c4[1], c2 = c4[2], c3 = c4[3];
+            c0 = c4[0]; c1 = c4[1]; c2 = c4[2]; c3 = c4[3];
+          }
+          while (k >= 0) {
+            int kn = -1;
+            float4 n0, n1, n2, n3;
+            if (m) {
+              kn = __builtin_ctzll(m);
+              m &= m - 1;
+              const float4* c4 = reinterpret_cast<const float4*>(wbox + kn * 16);
+              n0 = c4[0]; n1 = c4[1]; n2 = c4[2]; n3 = c4[3];
+            }
 #pragma unroll
-            for (int i = i0; i < i0 + CQ; ++i) {
-              const float u0 = fmaf(c0.x, px[i], fmaf(c0.y, py[i], c0.z * pz[i])) - c2.y;
-              const float u1 = fmaf(c0.w, px[i], fmaf(c1.x, py[i], c1.y * pz[i])) - c2.z;
-              const float u2 = fmaf(c1.z, px[i], fmaf(c1.w, py[i], c2.x * pz[i])) - c2.w;
-              const float a0 = fabsf(u0) - c3.x, a1 = fabsf(u1) - c3.y, a2 = fabsf(u2) - c3.z;
-              const float m0 = fmaxf(a0, 0.f), m1 = fmaxf(a1, 0.f), m2 = fmaxf(a2, 0.f);
-              const float key = fmaf(m0, m0, fmaf(m1, m1, m2 * m2)) + fminf(fmaxf(fmaxf(a0, a1), a2), 0.f);
-              if (key < best[i]) {
-                best[i] = key;
-                bk[i] = k;
-              }
+            for (int i = i0; i < i0 + CQ; ++i) cuboid_key_v(c0, c1, c2, c3, px[i], py[i], pz[i], k, best[i], bk[i]);
+            k = kn;
+            c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+          }
+        }
+      } else {
+#pragma unroll
+        for (int i0 = 0; i0 < SPH_GROUP; i0 += CQ) {
+          if (i0 >= active) continue;
+          int vox[CQ];
+#pragma unroll
+          for (int i = 0; i < CQ; ++i)
+            vox[i] = (i0 + i < active) ? voxel_of(Gd, px[i0 + i], py[i0 + i], pz[i0 + i]) : -1;
+          for (int mw = 0; mw < Gd.MW; ++mw) {
+            uint32_t m = 0;
+#pragma unroll
+            for (int i = 0; i < CQ; ++i)
+              if (vox[i] >= 0) m |= wmask[(int64_t)vox[i] * Gd.MW + mw];
+            while (m) {
+              const int k = mw * 32 + __builtin_ctz(m);
+              m &= m - 1;
+              const float4* c4 = reinterpret_cast<const float4*>(wbox + k * 16);
+              const float4 c0 = c4[0], c1 = c4[1], c2 = c4[2], c3 = c4[3];
+#pragma unroll
+              for (int i = i0; i < i0 + CQ; ++i) cuboid_key_v(c0, c1, c2, c3, px[i], py[i], pz[i], k, best[i], bk[i]);
             }
           }
         }

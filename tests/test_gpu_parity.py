@@ -202,7 +202,7 @@ def shuffled_robot(robot, seed):
 
 
 @pytest.mark.parametrize("case", ["ragged", "no_cuboids", "no_pairs", "one_sphere", "worlds_in_wave",
-                                  "many_spheres", "shuffled_links", "shuffled_many_spheres"])
+                                  "many_spheres", "shuffled_links", "shuffled_many_spheres", "many_cuboids"])
 def test_edge_shapes(case):
     need_gpu()
     kw = dict(seed=21, n_worlds=3, tpw=3, T=5, n_ls=2, n_spheres=37, n_cuboids=7, n_pairs=40)
@@ -211,6 +211,8 @@ def test_edge_shapes(case):
         kw.update(n_spheres=150, n_pairs=400)
     if case == "no_cuboids":
         kw["n_cuboids"] = 0
+    if case == "many_cuboids":  # more than 64 cuboids: more than two culling mask words per voxel
+        kw["n_cuboids"] = 100
     if case == "no_pairs":
         kw["n_pairs"] = 0
     if case == "one_sphere":
@@ -323,14 +325,18 @@ def test_error_paths():
 
 
 @pytest.mark.parametrize("wname,pname", [("dense", "f32"), ("dense", "mixed_fp4"), ("batched", "f32"),
-                                         ("large", "paper_like"), ("edge", "f32")])
+                                         ("large", "paper_like"), ("edge", "f32"), ("dense_k32", "f32"),
+                                         ("dense_k100", "paper_like")])
 def test_culling_is_exact(wname, pname):
     """Skipping cuboids that are out of reach changes nothing: stored codes, self costs and
-    trajectory costs are bit-identical with and without culling."""
+    trajectory costs are bit-identical with and without culling (32, 40, 64 and 100 cuboids cover
+    one, two and more mask words per voxel)."""
     need_gpu()
     prec = {} if pname == "f32" else PRECISIONS[pname]
     if wname == "dense":
         wl = dense_workload()
+    elif wname.startswith("dense_k"):
+        wl = dense_workload(n_cuboids=int(wname[len("dense_k"):]))
     elif wname == "edge":
         wl = dense_workload(seed=21, n_worlds=9, tpw=1, T=4, n_ls=1, n_spheres=37, n_cuboids=7, n_pairs=40)
     else:
