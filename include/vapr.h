@@ -140,11 +140,29 @@ int vapr_get_precision(const vapr_ctx* ctx, vapr_precision* p);
 int vapr_set_cost_params(vapr_ctx* ctx, const vapr_cost_params* p);
 
 /* Exact cuboid culling in the sphere-cost stage (default on).  A voxel grid records, per world,
- * which cuboids can come within eta + max sphere radius of each voxel; cuboids out of reach of
- * every sphere of a wavefront are not tested.  Results are identical with and without culling (it
- * skips only cuboids whose clearance is >= eta); enable = 0 tests every cuboid.  The grid is
- * rebuilt on the next forward pass after the robot, the worlds or eta change. */
+ * which cuboids can come within eta + max sphere radius of each voxel; a sphere tests only the
+ * cuboids marked in its voxel (spheres outside the grid test none).  Results are identical with
+ * and without culling (it skips only cuboids whose clearance is >= eta); enable = 0 tests every
+ * cuboid.  The grid is rebuilt on the next forward pass after the robot, the worlds or eta change. */
 int vapr_set_culling(vapr_ctx* ctx, int enable);
+
+/* Layout of the culling grid of every world: n^3 voxels of edge `cell` from `origin`; voxel
+ * (x, y, z) = (floor((p - origin) / cell) per axis, in FP32: (p - origin) * (1 / cell)) has index
+ * (z * n + y) * n + x and holds mask_words 32-bit words, bit k of word k / 32 set when cuboid k may
+ * lie within reach.  n = 0 when culling is off or the worlds hold no cuboid. */
+typedef struct {
+  int n;
+  int mask_words;
+  float origin[3];
+  float inv_cell; /* 1 / cell, as the kernels use it */
+} vapr_grid_info;
+
+/* Inspect the culling grid (built on demand; needs a robot and worlds): fills *info and, when
+ * mask_out is not NULL, copies world `world`'s n^3 * mask_words words to the host buffer mask_out
+ * of capacity_words words (VAPR_E_INVALID if too small or world out of range).  Synchronous; for
+ * tests and measurement, not for the hot path. */
+int vapr_get_culling_grid(vapr_ctx* ctx, int world, vapr_grid_info* info, uint32_t* mask_out,
+                          size_t capacity_words);
 
 /* Bytes of device workspace a forward/backward pass of this batch shape needs at the current
  * precision (holds L, S, D, G, J and two FP32 scalars per configuration).  Requires a robot. */

@@ -40,6 +40,11 @@ class CostParamsC(ctypes.Structure):
                 ("w_bound", ctypes.c_float), ("w_smooth", ctypes.c_float)]
 
 
+class GridInfoC(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int32), ("mask_words", ctypes.c_int32), ("origin", ctypes.c_float * 3),
+                ("inv_cell", ctypes.c_float)]
+
+
 class LbfgsStateC(ctypes.Structure):
     _fields_ = [("n_traj", ctypes.c_int32), ("T", ctypes.c_int32), ("n_ls", ctypes.c_int32), ("m", ctypes.c_int32),
                 ("max_step", ctypes.c_float), ("x", ctypes.c_void_p), ("g", ctypes.c_void_p), ("d", ctypes.c_void_p), ("cost", ctypes.c_void_p),
@@ -65,6 +70,7 @@ SIGNATURES = {
     "vapr_get_precision": (_I, [_P, ctypes.POINTER(PrecisionC)]),
     "vapr_set_cost_params": (_I, [_P, ctypes.POINTER(CostParamsC)]),
     "vapr_set_culling": (_I, [_P, _I]),
+    "vapr_get_culling_grid": (_I, [_P, _I, ctypes.POINTER(GridInfoC), _P, _SZ]),
     "vapr_workspace_size": (_I, [_P, _I, _I, _I, _I, ctypes.POINTER(_SZ)]),
     "vapr_cost_fwd": (_I, [_P, _I, _I, _I, _I, _P, _P, _SZ, _P, _P]),
     "vapr_cost_fwd_from": (_I, [_P, _I, _I, _I, _I, _I, _P, _P, _SZ, _P, _P]),

@@ -143,6 +143,19 @@ class Context:
         """Exact cuboid culling in the sphere-cost stage (on by default; results are identical)."""
         self._call("vapr_set_culling", 1 if enable else 0)
 
+    def culling_grid(self, world: int):
+        """The culling grid of one world: (info dict, uint32 mask array [n^3, mask_words]), or
+        (info, None) when culling is off or there are no cuboids."""
+        info = L.GridInfoC()
+        self._call("vapr_get_culling_grid", world, ctypes.byref(info), None, 0)
+        d = {"n": info.n, "mask_words": info.mask_words, "origin": tuple(info.origin), "inv_cell": info.inv_cell}
+        if info.n == 0:
+            return d, None
+        words = info.n ** 3 * info.mask_words
+        out = np.empty(words, dtype=np.uint32)
+        self._call("vapr_get_culling_grid", world, ctypes.byref(info), _ptr(out), words)
+        return d, out.reshape(info.n ** 3, info.mask_words)
+
     # -- cost path -----------------------------------------------------------------------------
     def workspace_size(self, shape: Shape) -> int:
         n = ctypes.c_size_t()

@@ -716,6 +716,32 @@ int vapr_set_culling(vapr_ctx* ctx, int enable) {
   return VAPR_OK;
 }
 
+int vapr_get_culling_grid(vapr_ctx* ctx, int world, vapr_grid_info* info, uint32_t* mask_out,
+                          size_t capacity_words) {
+  if (!ctx) return fail(nullptr, VAPR_E_INVALID, "null context");
+  if (!info) return fail(ctx, VAPR_E_INVALID, "null info");
+  if (!ctx->has_robot) return fail(ctx, VAPR_E_STATE, "no robot uploaded");
+  if (!ctx->has_worlds) return fail(ctx, VAPR_E_STATE, "no worlds uploaded");
+  if (world < 0 || world >= ctx->n_worlds) return fail(ctx, VAPR_E_INVALID, "world out of range");
+  int st;
+  if (!ctx->grid_valid && (st = build_grid(ctx))) return st;
+  const GridArgs& g = ctx->grid;
+  *info = vapr_grid_info{};
+  if (g.MW == 0) return VAPR_OK;
+  info->n = g.n;
+  info->mask_words = g.MW;
+  info->origin[0] = g.ox;
+  info->origin[1] = g.oy;
+  info->origin[2] = g.oz;
+  info->inv_cell = g.inv_cell;
+  if (!mask_out) return VAPR_OK;
+  const size_t words = (size_t)g.n * g.n * g.n * g.MW;
+  if (capacity_words < words) return fail(ctx, VAPR_E_INVALID, "mask buffer too small");
+  VAPR_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  VAPR_HIP(ctx, hipMemcpy(mask_out, g.mask + (size_t)world * words, words * 4, hipMemcpyDeviceToHost));
+  return VAPR_OK;
+}
+
 int vapr_workspace_size(const vapr_ctx* cctx, int n_worlds, int tpw, int T, int n_ls, size_t* bytes) {
   vapr_ctx* ctx = const_cast<vapr_ctx*>(cctx);
   if (!bytes) return fail(ctx, VAPR_E_INVALID, "null output pointer");

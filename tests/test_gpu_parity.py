@@ -15,6 +15,7 @@ import pytest
 
 from oracle import cost as OC
 from oracle import formats as F
+from oracle.geometry import obb_signed_distance
 from synthetic import Worlds, make_configs, make_robot, make_workload, make_worlds
 from synthetic.generators import Workload
 from tests.gpu_helpers import (ORACLE_KEY, TENSORS, compare_codes, cost_tolerance, dev, export_codes, grad_tolerance,
@@ -356,3 +357,34 @@ def test_culling_is_exact(wname, pname):
     assert np.array_equal(s1, s2)
     for n in t1:
         assert np.array_equal(t1[n], t2[n]), n
+
+
+@pytest.mark.parametrize("wname", ["dense", "large"])
+def test_culling_grid_is_conservative(wname):
+    """The culling grid the kernels read never drops a cuboid that can matter: at random points
+    (float32, assigned to voxels with the kernels' float32 arithmetic), every cuboid whose bit is
+    clear, and every cuboid at points outside the grid, is at least eta + the largest sphere radius
+    away (FP64 signed distance)."""
+    need_gpu()
+    wl = dense_workload() if wname == "dense" else make_workload(wname)
+    ctx = make_context(wl, {})
+    reach = OC.CostParams().eta + float(wl.robot.sphere_radius.max())
+    rng = np.random.default_rng(7)
+    for w in range(min(3, wl.worlds.pose.shape[0])):
+        info, mask = ctx.culling_grid(w)
+        n = info["n"]
+        assert n > 0 and mask is not None and mask.shape == (n ** 3, info["mask_words"])
+        o = np.array(info["origin"], dtype=np.float32)
+        inv = np.float32(info["inv_cell"])
+        span = n / float(inv)
+        p = (o.astype(np.float64) - 0.1 * span + rng.random((20000, 3)) * 1.2 * span).astype(np.float32)
+        f = (p - o) * inv                                            # float32, as in the kernels
+        inside = np.all((f >= 0) & (f < np.float32(n)), axis=1)
+        v = np.floor(f).astype(np.int64)
+        vid = np.where(inside, (v[:, 2] * n + v[:, 1]) * n + v[:, 0], 0)
+        for k in range(wl.worlds.pose.shape[1]):
+            P = wl.worlds.pose[w, k]
+            sd, _, _ = obb_signed_distance(p.astype(np.float64), P[:, :3], P[:, 3], wl.worlds.half_ext[w, k])
+            bit = (mask[vid, k // 32] >> np.uint32(k % 32)) & np.uint32(1)
+            dropped = ~inside | (bit == 0)
+            assert np.all(sd[dropped] >= reach), (w, k, float(sd[dropped].min()))
