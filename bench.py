@@ -163,7 +163,7 @@ def run_variant(torch, ctx, opt_cls, x0, prec, steps, warmup, want_opt=False):
     return (t1 - t0), prof, cost, (opt if want_opt else None)
 
 
-def cpu_baseline(prec, budget_s=15.0):
+def cpu_baseline(prec, budget_s=12.0):
     """The FP64 oracle (quantisation emulated at the same five tensors) timed on the host for one
     optimisation iteration of a sample of whole trajectories, single-threaded."""
     from threadpoolctl import threadpool_limits
@@ -194,8 +194,10 @@ def cpu_baseline(prec, budget_s=15.0):
         return time.perf_counter() - t0
 
     with threadpool_limits(limits=1):
-        t_small = one(8)
-        n = int(max(8, min(N_WORLDS * TPW, 8 * budget_s / max(t_small, 1e-6))))
+        # per-trajectory time from the slope between two small samples (a call has a fixed cost)
+        t8, t32 = one(8), one(32)
+        per = max((t32 - t8) / 24.0, t32 / 64.0, 1e-6)
+        n = int(max(8, min(N_WORLDS * TPW, budget_s / per)))
         dt = one(n)
     return {"value": n * T * N_LS / dt, "unit": "evals/s", "cores": 1, "kind": "oracle",
             "sample": f"{n} trajectories x {T} timesteps = {n * T} configurations, one iteration, "
