@@ -14,6 +14,7 @@ from __future__ import annotations
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -29,17 +30,20 @@ HBM_PEAK_GBS = 8000.0
 # (an FMA is two flops).  The 157.3 TFLOP/s figure needs packed FP32, which this build does not emit.
 VALU_PEAK_TFLOPS = 78.6
 
+# formats per stored tensor; power-of-two scales are calibrated per run (calibrate_scales)
 PRECISIONS = {
     "f32": {},
-    # the paper's per-tensor findings: sphere positions need FP16, the gradient / distance tensors
-    # tolerate FP4-FP8
-    "paper_like": {"link_poses": "f16", "sphere_pos": "f16", "sphere_dist": ("e2m1", -3),
-                   "sphere_grad": ("e2m1", 5), "joint_grad": ("e4m3", 2)},
-    "all_fp8": {"link_poses": ("e4m3", -7), "sphere_pos": ("e4m3", -7), "sphere_dist": ("e4m3", -10),
-                "sphere_grad": ("e5m2", -9), "joint_grad": ("e5m2", -5)},
-    "mixed_fp4": {"link_poses": ("e4m3", -7), "sphere_pos": ("e4m3", -7), "sphere_dist": ("e2m1", -3),
-                  "sphere_grad": ("e2m1", 5), "joint_grad": ("e4m3", 2)},
+    # the paper's per-tensor requirements: sphere positions FP16, distances and sphere gradients FP8;
+    # link poses FP16 like the positions, joint gradients FP8
+    "paper_like": {"link_poses": "f16", "sphere_pos": "f16", "sphere_dist": "e4m3", "sphere_grad": "e4m3",
+                   "joint_grad": "e4m3"},
+    "all_fp8": {"link_poses": "e4m3", "sphere_pos": "e4m3", "sphere_dist": "e4m3", "sphere_grad": "e5m2",
+                "joint_grad": "e5m2"},
+    "mixed_fp4": {"link_poses": "e4m3", "sphere_pos": "e4m3", "sphere_dist": "e2m1", "sphere_grad": "e2m1",
+                  "joint_grad": "e4m3"},
 }
+MAX_FINITE = {"f16": 65504.0, "bf16": 3.3895313892515355e38, "e4m3": 448.0, "e5m2": 57344.0, "e3m2": 28.0,
+              "e2m1": 6.0}
 BITS = {"f32": 32, "f16": 16, "bf16": 16, "e4m3": 8, "e5m2": 8, "e3m2": 6, "e2m1": 4}
 N_WORLDS, TPW, T, N_LS, N_SPHERES, N_CUBOIDS, N_PAIRS = 64, 64, 48, 1, 60, 64, 300
 HIST_M = 8
@@ -82,8 +86,9 @@ def dense_flops_per_cfg():
     return N_SPHERES * N_CUBOIDS * FLOPS_PER_SPHERE_CUBOID + N_PAIRS * FLOPS_PER_PAIR
 
 
-def traffic_from_profile(kernel_src_hash):
-    """HBM bytes per launch measured with rocprofv3 counters, if taken on the current kernels."""
+def traffic_from_profile(kernel_src_hash, formats):
+    """HBM bytes per launch measured with rocprofv3 counters, if taken on the current kernels and
+    the same format assignment."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
@@ -91,7 +96,8 @@ def traffic_from_profile(kernel_src_hash):
         rec = json.load(open(path))
     except Exception:
         return None
-    return rec if rec.get("kernels_sha256") == kernel_src_hash else None
+    same = rec.get("kernels_sha256") == kernel_src_hash and rec.get("formats") == formats
+    return rec if same else None
 
 
 def kernels_hash():
@@ -143,8 +149,84 @@ def culled_work(ctx, opt, prec):
     return {"needed_tests_per_cfg": needed / B, "issued_lane_tests_per_cfg": issued / B}
 
 
-def run_variant(torch, ctx, opt_cls, x0, prec, steps, warmup, want_opt=False):
-    ctx.set_precision(prec)
+def calibrate_scales(torch, ctx, x0):
+    """amax of each stored tensor on the FP32 path over the run's initial trajectories."""
+    from paper_2310_07854_amd import Shape
+
+    ctx.set_precision({})
+    shape = Shape(N_WORLDS, TPW, T, 1)
+    q = x0.reshape(-1, 7).contiguous()
+    _, ws = ctx.cost_fwd(q, shape)
+    ctx.cost_bwd(q, ws, want_grad=False)
+    names = ("link_poses", "sphere_pos", "sphere_dist", "sphere_grad", "joint_grad")
+    return {t: float(ctx.ws_export(t, ws, shape).view(torch.float32).abs().max()) for t in names}
+
+
+def with_scales(formats, amax):
+    """(format, k) per tensor with k = ceil(log2(amax / max finite)) in [-16, 16] (FP32: k = 0)."""
+    out = {}
+    for t, f in formats.items():
+        k = 0
+        if f != "f32" and amax[t] > 0:
+            k = int(min(16, max(-16, math.ceil(math.log2(amax[t] / MAX_FINITE[f])))))
+        out[t] = (f, k)
+    return out
+
+
+def fwd_bwd_timing(torch, ctx, x0, prec, recompute=False, warmup=20, runs=200):
+    """The cost and gradient path alone (k_fk .. k_adjoint, FP32 joint gradients out) on the
+    196,608 trajectory points: HIP events around each run on the stream the kernels use; median,
+    10th and 90th percentile of the run durations."""
+    from paper_2310_07854_amd import Shape
+
+    ctx.set_precision(prec, recompute_poses=recompute)
+    shape = Shape(N_WORLDS, TPW, T, 1)
+    q = x0.reshape(-1, 7).contiguous()
+    ws = ctx.new_workspace(shape)
+    cost = torch.empty(shape.n_tc, dtype=torch.float64, device=q.device)
+    grad = torch.empty_like(q)
+
+    def once():
+        ctx.cost_fwd(q, shape, ws=ws, cost_traj=cost)
+        ctx.cost_bwd(q, ws, grad_q=grad)
+
+    for _ in range(warmup):
+        once()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(runs)]
+    torch.cuda.synchronize()
+    for a, b in ev:
+        a.record()
+        once()
+        b.record()
+    torch.cuda.synchronize()
+    ms = np.array([a.elapsed_time(b) for a, b in ev])
+    med, p10, p90 = np.median(ms), np.percentile(ms, 10), np.percentile(ms, 90)
+    return {"evals_per_s": shape.B / (med * 1e-3), "median_ms": float(med), "p10_ms": float(p10),
+            "p90_ms": float(p90), "runs": runs, "recompute_poses": recompute}
+
+
+def copy_bandwidth(torch, mib=1024, runs=20):
+    """Achievable HBM bandwidth on this machine: a plain 1 GiB device-to-device copy (read + write
+    bytes over the median duration)."""
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(runs)]
+    torch.cuda.synchronize()
+    for e0, e1 in ev:
+        e0.record()
+        b.copy_(a)
+        e1.record()
+    torch.cuda.synchronize()
+    med = float(np.median([e0.elapsed_time(e1) for e0, e1 in ev]))
+    del a, b
+    return 2.0 * mib * (1 << 20) / (med * 1e-3) / 1e9
+
+
+def run_variant(torch, ctx, opt_cls, x0, prec, steps, warmup, want_opt=False, recompute=False):
+    ctx.set_precision(prec, recompute_poses=recompute)
     opt = opt_cls(ctx, N_WORLDS, TPW, T, n_ls=N_LS, m=HIST_M)
     opt.init(x0)
     for _ in range(warmup):
@@ -212,6 +294,8 @@ def main():
     ap.add_argument("--precision", default="paper_like", choices=[k for k in PRECISIONS if k != "f32"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--variants", action="store_true", help="also time every other assignment")
+    ap.add_argument("--only", choices=list(PRECISIONS), default=None,
+                    help="run one assignment's optimisation loop and nothing else (for profiler runs)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB, 5 times (profiler calibration)")
     args = ap.parse_args()
@@ -245,28 +329,48 @@ def main():
     ctx.set_robot(robot)
     ctx.set_worlds(worlds.pose, worlds.half_ext)
 
+    amax = calibrate_scales(torch, ctx, x0)
+    precs = {name: with_scales(f, amax) for name, f in PRECISIONS.items()}
+    if args.only:
+        dt, prof, _, _ = run_variant(torch, ctx, TrajectoryOptimizer, x0, precs[args.only], args.steps, args.warmup)
+        print(json.dumps({"only": args.only, "ms_per_step": dt / args.steps * 1e3,
+                          "config": {"formats": {k: list(v) for k, v in precs[args.only].items()}},
+                          "kernels_us": {k: v[0] / max(v[1], 1) * 1e3 for k, v in prof.items() if v[1]}}))
+        ctx.close()
+        return
     results = {}
     names = ["f32", args.precision] + ([k for k in PRECISIONS if k not in ("f32", args.precision)]
                                        if args.variants else [])
     culled = None
     for name in names:
         main = name == args.precision
-        dt, prof, cost, opt = run_variant(torch, ctx, TrajectoryOptimizer, x0, PRECISIONS[name], args.steps,
+        dt, prof, cost, opt = run_variant(torch, ctx, TrajectoryOptimizer, x0, precs[name], args.steps,
                                           args.warmup, want_opt=main)
         results[name] = {"seconds": dt, "prof": prof, "cost": cost}
         if main:
-            culled = culled_work(ctx, opt, PRECISIONS[name])
+            culled = culled_work(ctx, opt, precs[name])
             del opt
         print(f"# {name}: {dt / args.steps * 1e3:.3f} ms/step, {B * args.steps / dt / 1e6:.1f} M evals/s, "
               f"kernels " + ", ".join(f"{k} {v[0] / max(v[1], 1) * 1e3:.1f}us" for k, v in prof.items() if v[1]),
               file=sys.stderr, flush=True)
+
+    # recompute-in-backward for the main assignment: the step without the link-pose tensor
+    dt_rc, prof_rc, _, _ = run_variant(torch, ctx, TrajectoryOptimizer, x0, precs[args.precision], args.steps,
+                                       args.warmup, recompute=True)
+    print(f"# {args.precision} recompute: {dt_rc / args.steps * 1e3:.3f} ms/step, "
+          f"{B * args.steps / dt_rc / 1e6:.1f} M evals/s, kernels "
+          + ", ".join(f"{k} {v[0] / max(v[1], 1) * 1e3:.1f}us" for k, v in prof_rc.items() if v[1]),
+          file=sys.stderr, flush=True)
+    fwd_bwd = {name: fwd_bwd_timing(torch, ctx, x0, precs[name]) for name in ("f32", args.precision)}
+    fwd_bwd[args.precision + "_recompute"] = fwd_bwd_timing(torch, ctx, x0, precs[args.precision], True)
+    copy_gbs = copy_bandwidth(torch)
 
     main_r = results[args.precision]
     f32_r = results["f32"]
     dt = main_r["seconds"]
     value = B * args.steps / dt
     value_f32 = B * args.steps / f32_r["seconds"]
-    prec = PRECISIONS[args.precision]
+    prec = precs[args.precision]
     kb = kernel_bytes(prec)
     per_kernel = {}
     for k, (ms, n) in main_r["prof"].items():
@@ -279,7 +383,7 @@ def main():
         per_kernel[k] = entry
     dom = max(per_kernel, key=lambda k: per_kernel[k]["avg_us"] * per_kernel[k]["launches"])
     dom_s = per_kernel[dom]["avg_us"] * 1e-6
-    traffic = traffic_from_profile(kernels_hash())
+    traffic = traffic_from_profile(kernels_hash(), {k: list(v) for k, v in prec.items()})
     if dom == "sphere_cost":
         # the tests exact culling leaves, plus every self pair once
         flops = FLOPS_PER_SPHERE_CUBOID * culled["needed_tests_per_cfg"] + FLOPS_PER_PAIR * N_PAIRS
@@ -311,7 +415,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "64 worlds x 64 seeds x 48 timesteps = 196,608 configurations per step; 7-joint "
                                "arm, 60 spheres, 300 self pairs, 64 oriented cuboids per world; 1 step scale",
-                   "precision": args.precision, "formats": {k: v for k, v in prec.items()},
+                   "precision": args.precision, "formats": {k: list(v) for k, v in prec.items()},
                    "recompute_poses": False},
         "fp32_value": value_f32,
         "speedup_vs_fp32_pct": (value / value_f32 - 1.0) * 100.0,
@@ -319,6 +423,11 @@ def main():
         "kernels": per_kernel,
         "fp32_kernels": {k: v[0] / max(v[1], 1) * 1e3 for k, v in f32_r["prof"].items() if v[1]},
         "roofline": roofline,
+        "recompute_value": B * args.steps / dt_rc,
+        "recompute_kernels": {k: v[0] / max(v[1], 1) * 1e3 for k, v in prof_rc.items() if v[1]},
+        "fwd_bwd": fwd_bwd,
+        "copy_GBs": copy_gbs,
+        "copy_frac_of_peak": copy_gbs / HBM_PEAK_GBS,
     }
     for name in results:
         if name not in ("f32", args.precision):
