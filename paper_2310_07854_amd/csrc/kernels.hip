@@ -363,9 +363,10 @@ __device__ __forceinline__ void closest_cuboids(cptr<float> wbox, int K, const f
     const float o0 = bx[9], o1 = bx[10], o2 = bx[11], h0 = bx[12], h1 = bx[13], h2 = bx[14];
 #pragma unroll
     for (int i = 0; i < NA; ++i) {
-      const float u0 = fmaf(A0, px[i], fmaf(A1, py[i], A2 * pz[i])) - o0;
-      const float u1 = fmaf(A3, px[i], fmaf(A4, py[i], A5 * pz[i])) - o1;
-      const float u2 = fmaf(A6, px[i], fmaf(A7, py[i], A8 * pz[i])) - o2;
+      // the same rounding as the per-lane key of the culled path
+      const float u0 = fmaf(A0, px[i], fmaf(A1, py[i], fmaf(A2, pz[i], -o0)));
+      const float u1 = fmaf(A3, px[i], fmaf(A4, py[i], fmaf(A5, pz[i], -o1)));
+      const float u2 = fmaf(A6, px[i], fmaf(A7, py[i], fmaf(A8, pz[i], -o2)));
       const float a0 = fabsf(u0) - h0, a1 = fabsf(u1) - h1, a2 = fabsf(u2) - h2;
       const float m0 = fmaxf(a0, 0.f), m1 = fmaxf(a1, 0.f), m2 = fmaxf(a2, 0.f);
       const float key = fmaf(m0, m0, fmaf(m1, m1, m2 * m2)) + fminf(fmaxf(fmaxf(a0, a1), a2), 0.f);
@@ -501,9 +502,9 @@ __device__ __forceinline__ int voxel_of(const GridArgs& g, float x, float y, flo
 // h = c3.xyz), running closest-cuboid key; the first index wins ties
 __device__ __forceinline__ void cuboid_key_v(const float4& c0, const float4& c1, const float4& c2, const float4& c3,
                                              float px, float py, float pz, int k, float& best, int& bk) {
-  const float u0 = fmaf(c0.x, px, fmaf(c0.y, py, c0.z * pz)) - c2.y;
-  const float u1 = fmaf(c0.w, px, fmaf(c1.x, py, c1.y * pz)) - c2.z;
-  const float u2 = fmaf(c1.z, px, fmaf(c1.w, py, c2.x * pz)) - c2.w;
+  const float u0 = fmaf(c0.x, px, fmaf(c0.y, py, fmaf(c0.z, pz, -c2.y)));
+  const float u1 = fmaf(c0.w, px, fmaf(c1.x, py, fmaf(c1.y, pz, -c2.z)));
+  const float u2 = fmaf(c1.z, px, fmaf(c1.w, py, fmaf(c2.x, pz, -c2.w)));
   const float a0 = fabsf(u0) - c3.x, a1 = fabsf(u1) - c3.y, a2 = fabsf(u2) - c3.z;
   const float m0 = fmaxf(a0, 0.f), m1 = fmaxf(a1, 0.f), m2 = fmaxf(a2, 0.f);
   const float key = fmaf(m0, m0, fmaf(m1, m1, m2 * m2)) + fminf(fmaxf(fmaxf(a0, a1), a2), 0.f);
@@ -511,6 +512,20 @@ __device__ __forceinline__ void cuboid_key_v(const float4& c0, const float4& c1,
     best = key;
     bk = k;
   }
+}
+
+// lowest candidate of a lane's list (removed from it) with its cuboid loaded; -1 when empty
+__device__ __forceinline__ int pop_cuboid(uint64_t& m, const float* wbox, float4& c0, float4& c1, float4& c2,
+                                          float4& c3) {
+  if (!m) return -1;
+  const int k = __builtin_ctzll(m);
+  m &= m - 1;
+  const float4* c4 = reinterpret_cast<const float4*>(wbox + k * 16);
+  c0 = c4[0];
+  c1 = c4[1];
+  c2 = c4[2];
+  c3 = c4[3];
+  return k;
 }
 
 template <int FS>
@@ -590,27 +605,18 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3))) void k
           const int i0 = q * CQ;
           if (i0 >= active) continue;
           uint64_t m = mq[q];
-          int k = -1;
-          float4 c0, c1, c2, c3;
-          if (m) {
-            k = __builtin_ctzll(m);
-            m &= m - 1;
-            const float4* c4 = reinterpret_cast<const float4*>(wbox + k * 16);
-            c0 = c4[0]; c1 = c4[1]; c2 = c4[2]; c3 = c4[3];
-          }
-          while (k >= 0) {
-            int kn = -1;
-            float4 n0, n1, n2, n3;
-            if (m) {
-              kn = __builtin_ctzll(m);
-              m &= m - 1;
-              const float4* c4 = reinterpret_cast<const float4*>(wbox + kn * 16);
-              n0 = c4[0]; n1 = c4[1]; n2 = c4[2]; n3 = c4[3];
-            }
+          // two cuboid buffers used in turn: the next candidate's load is in flight while the
+          // current one is tested
+          float4 a0, a1, a2, a3, b0, b1, b2, b3;
+          int ka = pop_cuboid(m, wbox, a0, a1, a2, a3);
+          while (ka >= 0) {
+            const int kb = pop_cuboid(m, wbox, b0, b1, b2, b3);
 #pragma unroll
-            for (int i = i0; i < i0 + CQ; ++i) cuboid_key_v(c0, c1, c2, c3, px[i], py[i], pz[i], k, best[i], bk[i]);
-            k = kn;
-            c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+            for (int i = i0; i < i0 + CQ; ++i) cuboid_key_v(a0, a1, a2, a3, px[i], py[i], pz[i], ka, best[i], bk[i]);
+            if (kb < 0) break;
+            ka = pop_cuboid(m, wbox, a0, a1, a2, a3);
+#pragma unroll
+            for (int i = i0; i < i0 + CQ; ++i) cuboid_key_v(b0, b1, b2, b3, px[i], py[i], pz[i], kb, best[i], bk[i]);
           }
         }
       } else {
