@@ -1,7 +1,8 @@
 """Seeded synthetic workloads shared by the oracle tests, the GPU parity tests and the benchmark.
 
 Only random inputs are drawn here: serial 7-joint arms with collision-sphere models, worlds of
-oriented cuboids, joint configurations and seed trajectories.  None of the method's arithmetic
+oriented cuboids, joint configurations, seed trajectories, planning problems and the seeding
+network's initial weights.  None of the method's arithmetic
 (kinematics, distances, costs, gradients, number formats) lives in this package.
 """
 from .generators import (  # noqa: F401
@@ -15,4 +16,9 @@ from .generators import (  # noqa: F401
     make_trajectories,
     make_workload,
     WORKLOADS,
+    SEEDNET_LAYERS,
+    SeedProblems,
+    make_seednet_params,
+    make_seed_problems,
+    make_seed_inits,
 )

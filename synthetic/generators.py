@@ -38,7 +38,7 @@ JOINT_LIMIT = 2.9
 Q_RANGE = 2.8
 
 # independent random streams split off the master seed
-_STREAMS = ("robot", "worlds", "configs", "trajectories", "calibration")
+_STREAMS = ("robot", "worlds", "configs", "trajectories", "calibration", "seednet", "seed_problems", "seed_inits")
 
 
 def _rng(seed: int, stream: str) -> np.random.Generator:
@@ -241,3 +241,77 @@ def make_workload(name: str, seed: int = MASTER_SEED, exact: bool = False) -> Wo
         traj = make_trajectories(W, S, T, seed=seed, exact=exact)  # [W, S, T, 7]
         q = np.repeat(traj.reshape(W * S, 1, T, N_JOINTS), n_ls, axis=1).reshape(B, N_JOINTS)
     return Workload(name=name, robot=robot, worlds=worlds, traj_per_world=S, T=T, n_ls=n_ls, q=q)
+
+
+# ---- learned seeder inputs --------------------------------------------------------------------
+
+# layer sizes of the seeding network: features (start 7, goal 7, occupancy 512) -> 3 x 256 -> 8 seeds
+# x 32 timesteps x 7 joints
+SEEDNET_LAYERS = ((526, 256), (256, 256), (256, 256), (256, 1792))
+
+
+def make_seednet_params(seed: int = MASTER_SEED) -> Dict[str, np.ndarray]:
+    """Initial weights W_l [fan_in, fan_out] and biases b_l [fan_out], l = 1..4, each drawn
+    U(-1/sqrt(fan_in), 1/sqrt(fan_in)) and rounded to FP32."""
+    rng = _rng(seed, "seednet")
+    out = {}
+    for l, (fi, fo) in enumerate(SEEDNET_LAYERS, 1):
+        b = 1.0 / np.sqrt(fi)
+        out[f"W{l}"] = _as_inputs(rng.uniform(-b, b, size=(fi, fo)), False)
+        out[f"b{l}"] = _as_inputs(rng.uniform(-b, b, size=fo), False)
+    return out
+
+
+@dataclass
+class SeedProblems:
+    """Planning problems: one world of cuboids, a start and a goal configuration each."""
+
+    worlds: Worlds
+    start: np.ndarray  # [n, 7]
+    goal: np.ndarray   # [n, 7]
+
+
+def _split_rng(seed: int, stream: str, split: int) -> np.random.Generator:
+    child = np.random.SeedSequence(seed).spawn(len(_STREAMS))[_STREAMS.index(stream)]
+    return np.random.default_rng(child.spawn(split + 1)[split])
+
+
+def make_seed_problems(n: int, n_cuboids: int, split: int = 0, seed: int = MASTER_SEED) -> SeedProblems:
+    """n problems drawn like the benchmark worlds (cuboid centres U[-0.75, 0.75]^3 m, sides
+    U[0.05, 0.5] m, uniform rotations) with start and goal U[-2.8, 2.8]^7; `split` picks an
+    independent set (0: training, 1: evaluation, ...)."""
+    rng = _split_rng(seed, "seed_problems", split)
+    m = n * n_cuboids
+    R = _random_rotations(rng, m)
+    c = rng.uniform(-0.75, 0.75, size=(m, 3))
+    h = 0.5 * rng.uniform(0.05, 0.5, size=(m, 3))
+    pose = np.concatenate([R, c[:, :, None]], axis=2).reshape(n, n_cuboids, 3, 4)
+    start = rng.uniform(-Q_RANGE, Q_RANGE, size=(n, N_JOINTS))
+    goal = rng.uniform(-Q_RANGE, Q_RANGE, size=(n, N_JOINTS))
+    return SeedProblems(worlds=Worlds(pose=_as_inputs(pose, False), half_ext=_as_inputs(h.reshape(n, n_cuboids, 3), False)),
+                        start=_as_inputs(start, False), goal=_as_inputs(goal, False))
+
+
+def make_seed_inits(start: np.ndarray, goal: np.ndarray, n_seeds: int, T: int, kind: str, split: int = 0,
+                    seed: int = MASTER_SEED) -> np.ndarray:
+    """Initial trajectories [n, n_seeds, T, 7] from start to goal (rows 0 and T-1 are the endpoints).
+    kind "linear": the straight line for seed 0, the straight line plus sin(pi tau) delta_s with
+    delta_s ~ U[-1, 1]^7 for the others; kind "random": two straight segments through a via point
+    drawn U[-2.8, 2.8]^7 at tau = 1/2."""
+    rng = _split_rng(seed, "seed_inits", split * 2 + (0 if kind == "linear" else 1))
+    n = start.shape[0]
+    tau = np.linspace(0.0, 1.0, T).reshape(1, 1, T, 1)
+    s0, g0 = start[:, None, None, :], goal[:, None, None, :]
+    if kind == "linear":
+        delta = rng.uniform(-1.0, 1.0, size=(n, n_seeds, 1, N_JOINTS))
+        delta[:, 0] = 0.0
+        traj = s0 + (g0 - s0) * tau + np.sin(np.pi * tau) * delta
+    elif kind == "random":
+        via = rng.uniform(-Q_RANGE, Q_RANGE, size=(n, n_seeds, 1, N_JOINTS))
+        first = s0 + (via - s0) * np.minimum(2.0 * tau, 1.0)
+        traj = np.where(tau <= 0.5, first, via + (g0 - via) * (2.0 * tau - 1.0))
+    else:
+        raise ValueError(kind)
+    traj[:, :, 0, :] = start[:, None, :]
+    traj[:, :, -1, :] = goal[:, None, :]
+    return _as_inputs(traj, False)
