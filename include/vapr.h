@@ -232,6 +232,67 @@ int vapr_optimizer_step(vapr_ctx* ctx, const vapr_lbfgs_state* st, const void* w
  * stream: hipStream_t or NULL.  0 <= n <= 2^32. */
 int vapr_quantize(int fmt, int scale_exp, const float* in, void* out, int64_t n, void* hip_stream);
 int vapr_dequantize(int fmt, int scale_exp, const void* in, float* out, int64_t n, void* hip_stream);
+
+/* ---- Learned trajectory seeder ----------------------------------------------------------------
+ * A network proposes initial trajectories for the optimiser in place of the geometric planner
+ * (Sec. II-A: a network trained for an environment can seed trajectory optimisation; Sec. VI-B:
+ * better seeding cuts planning attempts).  The paper defines no network.  The one built here maps
+ * x = [start (7), goal (7), occupancy (512)] through three GELU layers of 256 units to 8 seeds x 32
+ * timesteps x 7 joints (deviations from the straight line, endpoints pinned by the optimiser).
+ * Weights enter the matrix cores as BF16 with FP32 accumulation; master weights and Adam moments
+ * are FP32.  Every pointer below is device memory on the current device, every call queues its
+ * work on `hip_stream` (hipStream_t or NULL) and checks its arguments before any launch. */
+
+/* Occupancy of the cube [-0.75, 0.75]^3 m cut into 8^3 voxels of edge 0.1875 m, per world:
+ * occ[w][v] = 1 when the smallest signed distance from voxel v's centre to world w's cuboids is
+ * <= 0.09375 m, else 0, with v = (z * 8 + y) * 8 + x.  pose [W][K][3][4] (world <- box [R | c]),
+ * half_ext [W][K][3], occ [W][512] FP32.  K = 0 gives an empty grid.  1 <= W <= 2^20, 0 <= K <= 256. */
+int vapr_seed_occupancy(int n_worlds, int n_cuboids, const float* pose, const float* half_ext, float* occ,
+                        void* hip_stream);
+
+/* Network input rows x[r] = BF16([start[r] (7), goal[r] (7), occ[r] (512), 18 zeros]), x [n][544]
+ * (the width padded to a multiple of 32 for the matrix cores).  start, goal [n][7], occ [n][512]. */
+int vapr_seed_features(int n, const float* start, const float* goal, const float* occ, uint16_t* x,
+                       void* hip_stream);
+
+/* Seed trajectories from the network output: out[r][s][t][j] = start[r][j] + (goal[r][j] -
+ * start[r][j]) t / 31 + y[r][(s * 32 + t) * 7 + j] for t = 1..30, and exactly start / goal at
+ * t = 0 / 31.  y [n][1792], start, goal [n][7], out [n][8][32][7]. */
+int vapr_seed_trajectories(int n, const float* y, const float* start, const float* goal, float* out,
+                           void* hip_stream);
+
+enum { VAPR_GEMM_PLAIN = 0, VAPR_GEMM_GELU = 1, VAPR_GEMM_GELU_GRAD = 2 };
+
+/* Z = A B (+ bias[n]) on the matrix cores: A (M x K) and B (K x N) BF16 (uint16 codes), FP32
+ * accumulation, for the seeder's dense layers and their backward products.  A(m, k) is
+ * A[m * a_ms + k * a_ks], B(k, n) is B[k * b_ks + n * b_ns]; one stride of each operand must be 1,
+ * and when it is the k stride the other stride must be a multiple of 8 with the pointer 16-byte
+ * aligned.  K must be a positive multiple of 32; M, N >= 1.  Epilogue:
+ *   VAPR_GEMM_PLAIN      out = Z
+ *   VAPR_GEMM_GELU       aux = Z, out = GELU(Z) = Z Phi(Z)                (aux required)
+ *   VAPR_GEMM_GELU_GRAD  out = Z * GELU'(aux)                             (aux read)
+ * out goes to C (FP32) and/or C_bf16 (round to nearest even), [M][ldc], ldc >= N; at least one. */
+int vapr_gemm_bf16(int M, int N, int K, const uint16_t* A, int64_t a_ms, int64_t a_ks, const uint16_t* B,
+                   int64_t b_ks, int64_t b_ns, const float* bias, int epilogue, float* aux, float* C,
+                   uint16_t* C_bf16, int64_t ldc, void* hip_stream);
+
+/* Min-over-slot matching loss of n problems: y [n][1792] predicted deviations (8 slots x 224),
+ * targets [n][1792] (8 target trajectories), valid [n][8] (0 / nonzero).  e_sj = mean over 224 of
+ * (y_s - t_j)^2; each valid target takes its smallest e (ties to the lowest slot, assign [n][8]);
+ * *loss = sum of those / n_valid (FP64, dev).  dy [n][1792] = dL/dy.  partial [n] doubles is
+ * caller-owned scratch.  n_valid must be the number of nonzero valid entries (>= 1). */
+int vapr_seed_loss(int n, const float* y, const float* targets, const float* valid, int n_valid, double* loss,
+                   int32_t* assign, float* dy, double* partial, void* hip_stream);
+
+/* out[j] = sum_i X[i * ldx + j] for j < N (bias gradients), summed in row order. */
+int vapr_column_sum(int M, int N, const float* X, int64_t ldx, float* out, void* hip_stream);
+
+/* Adam step `step` (>= 1) on n FP32 weights w with gradient g and moments m, v (FP32, updated in
+ * place): m = b1 m + (1 - b1) g, v = b2 v + (1 - b2) g^2,
+ * w -= lr (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps); w_bf16 (may be NULL) receives
+ * BF16(w). */
+int vapr_adam(int64_t n, float* w, uint16_t* w_bf16, const float* g, float* m, float* v, float lr, float b1,
+              float b2, float eps, int step, void* hip_stream);
 size_t vapr_packed_bytes(int fmt, int64_t n);
 
 /* Tensor identifiers for workspace export/import. */

@@ -84,6 +84,14 @@ SIGNATURES = {
     "vapr_ws_import": (_I, [_P, _I, _I, _I, _I, _P, _SZ, _I, _P, _SZ]),
     "vapr_profile_enable": (_I, [_P, _I]),
     "vapr_profile_read": (_I, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_I64), _I]),
+    "vapr_seed_occupancy": (_I, [_I, _I, _P, _P, _P, _P]),
+    "vapr_seed_features": (_I, [_I, _P, _P, _P, _P, _P]),
+    "vapr_seed_trajectories": (_I, [_I, _P, _P, _P, _P, _P]),
+    "vapr_gemm_bf16": (_I, [_I, _I, _I, _P, _I64, _I64, _P, _I64, _I64, _P, _I, _P, _P, _P, _I64, _P]),
+    "vapr_seed_loss": (_I, [_I, _P, _P, _P, _I, _P, _P, _P, _P, _P]),
+    "vapr_column_sum": (_I, [_I, _I, _P, _I64, _P, _P]),
+    "vapr_adam": (_I, [_I64, _P, _P, _P, _P, _P, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, _I,
+                       _P]),
     "vapr_status_string": (ctypes.c_char_p, [_I]),
     "vapr_last_error": (ctypes.c_char_p, [_P]),
 }

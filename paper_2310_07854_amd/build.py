@@ -13,7 +13,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libvapr.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-SOURCES = ["kernels.hip", "vapr.cpp"]
+SOURCES = ["kernels.hip", "seednet.hip", "vapr.cpp"]
 FLAGS = [
     "--offload-arch=gfx950",
     "-O3",

@@ -14,6 +14,7 @@
 
 #include "kernels.hpp"
 #include "layout.hpp"
+#include "seednet.hpp"
 
 using namespace vapr;
 
@@ -823,6 +824,84 @@ int vapr_dequantize(int fmt, int scale_exp, const void* in, float* out, int64_t 
   hipError_t e = launch_dequantize(static_cast<hipStream_t>(hip_stream), fmt, std::ldexp(1.0f, scale_exp),
                                    static_cast<const uint8_t*>(in), out, n);
   return e == hipSuccess ? VAPR_OK : hip_fail(nullptr, e, "k_dequantize launch");
+}
+
+// ---- learned seeder ---------------------------------------------------------------------------
+
+int vapr_seed_occupancy(int n_worlds, int n_cuboids, const float* pose, const float* half_ext, float* occ,
+                        void* hip_stream) {
+  if (n_worlds < 1 || n_worlds > (1 << 20) || n_cuboids < 0 || n_cuboids > MAX_CUBOIDS)
+    return fail(nullptr, VAPR_E_INVALID, "world shape out of range");
+  if (!occ || (n_cuboids > 0 && (!pose || !half_ext))) return fail(nullptr, VAPR_E_INVALID, "null pointer");
+  hipError_t e = launch_occupancy(static_cast<hipStream_t>(hip_stream), n_worlds, n_cuboids, pose, half_ext, occ);
+  return e == hipSuccess ? VAPR_OK : hip_fail(nullptr, e, "k_occupancy launch");
+}
+
+int vapr_seed_features(int n, const float* start, const float* goal, const float* occ, uint16_t* x,
+                       void* hip_stream) {
+  if (n < 0) return fail(nullptr, VAPR_E_INVALID, "n < 0");
+  if (n == 0) return VAPR_OK;
+  if (!start || !goal || !occ || !x) return fail(nullptr, VAPR_E_INVALID, "null pointer");
+  hipError_t e = launch_features(static_cast<hipStream_t>(hip_stream), n, start, goal, occ, x);
+  return e == hipSuccess ? VAPR_OK : hip_fail(nullptr, e, "k_features launch");
+}
+
+int vapr_seed_trajectories(int n, const float* y, const float* start, const float* goal, float* out,
+                           void* hip_stream) {
+  if (n < 0) return fail(nullptr, VAPR_E_INVALID, "n < 0");
+  if (n == 0) return VAPR_OK;
+  if (!y || !start || !goal || !out) return fail(nullptr, VAPR_E_INVALID, "null pointer");
+  hipError_t e = launch_seed_traj(static_cast<hipStream_t>(hip_stream), n, y, start, goal, out);
+  return e == hipSuccess ? VAPR_OK : hip_fail(nullptr, e, "k_seed_traj launch");
+}
+
+int vapr_gemm_bf16(int M, int N, int K, const uint16_t* A, int64_t a_ms, int64_t a_ks, const uint16_t* B,
+                   int64_t b_ks, int64_t b_ns, const float* bias, int epilogue, float* aux, float* C,
+                   uint16_t* C_bf16, int64_t ldc, void* hip_stream) {
+  if (M < 1 || N < 1 || K < 32 || K % 32) return fail(nullptr, VAPR_E_INVALID, "GEMM shape (K a multiple of 32)");
+  if (!A || !B || (!C && !C_bf16)) return fail(nullptr, VAPR_E_INVALID, "null pointer");
+  if (epilogue < VAPR_GEMM_PLAIN || epilogue > VAPR_GEMM_GELU_GRAD) return fail(nullptr, VAPR_E_INVALID, "epilogue");
+  if (epilogue != VAPR_GEMM_PLAIN && !aux) return fail(nullptr, VAPR_E_INVALID, "GELU epilogues need aux");
+  if (ldc < N) return fail(nullptr, VAPR_E_INVALID, "ldc < N");
+  const bool a_k = a_ks == 1, b_n = b_ns == 1;
+  if (!(a_k || a_ms == 1) || !(b_n || b_ks == 1)) return fail(nullptr, VAPR_E_INVALID, "one stride of A and B must be 1");
+  if (a_k && (a_ms % 8 || reinterpret_cast<uintptr_t>(A) % 16))
+    return fail(nullptr, VAPR_E_INVALID, "k-contiguous A needs a row stride multiple of 8 and 16-byte alignment");
+  if (!b_n && (b_ns % 8 || reinterpret_cast<uintptr_t>(B) % 16))
+    return fail(nullptr, VAPR_E_INVALID, "k-contiguous B needs a column stride multiple of 8 and 16-byte alignment");
+  GemmArgs g{M, N, K, A, a_ms, a_ks, B, b_ks, b_ns, bias, epilogue, aux, C, C_bf16, ldc};
+  hipError_t e = launch_gemm_bf16(static_cast<hipStream_t>(hip_stream), g, a_k, b_n);
+  return e == hipSuccess ? VAPR_OK : hip_fail(nullptr, e, "k_gemm_bf16 launch");
+}
+
+int vapr_seed_loss(int n, const float* y, const float* targets, const float* valid, int n_valid, double* loss,
+                   int32_t* assign, float* dy, double* partial, void* hip_stream) {
+  if (n < 1 || n_valid < 1 || n_valid > 8 * n) return fail(nullptr, VAPR_E_INVALID, "n or n_valid out of range");
+  if (!y || !targets || !valid || !loss || !assign || !dy || !partial) return fail(nullptr, VAPR_E_INVALID, "null pointer");
+  const float coef = (float)(2.0 / ((double)SEED_TRAJ * n_valid));
+  hipError_t e = launch_seed_loss(static_cast<hipStream_t>(hip_stream), n, y, targets, valid, coef, partial, assign,
+                                  dy, 1.0 / n_valid, loss);
+  return e == hipSuccess ? VAPR_OK : hip_fail(nullptr, e, "k_seed_loss launch");
+}
+
+int vapr_column_sum(int M, int N, const float* X, int64_t ldx, float* out, void* hip_stream) {
+  if (M < 1 || N < 1 || ldx < N) return fail(nullptr, VAPR_E_INVALID, "shape");
+  if (!X || !out) return fail(nullptr, VAPR_E_INVALID, "null pointer");
+  hipError_t e = launch_column_sum(static_cast<hipStream_t>(hip_stream), M, N, X, ldx, out);
+  return e == hipSuccess ? VAPR_OK : hip_fail(nullptr, e, "k_column_sum launch");
+}
+
+int vapr_adam(int64_t n, float* w, uint16_t* w_bf16, const float* g, float* m, float* v, float lr, float b1,
+              float b2, float eps, int step, void* hip_stream) {
+  if (n < 0 || step < 1) return fail(nullptr, VAPR_E_INVALID, "n < 0 or step < 1");
+  if (!(b1 >= 0.f && b1 < 1.f && b2 >= 0.f && b2 < 1.f && eps >= 0.f && std::isfinite(lr)))
+    return fail(nullptr, VAPR_E_INVALID, "Adam hyper-parameters");
+  if (n == 0) return VAPR_OK;
+  if (!w || !g || !m || !v) return fail(nullptr, VAPR_E_INVALID, "null pointer");
+  AdamArgs a{lr, b1, b2, eps, (float)(1.0 / (1.0 - std::pow((double)b1, step))),
+             (float)(1.0 / (1.0 - std::pow((double)b2, step)))};
+  hipError_t e = launch_adam(static_cast<hipStream_t>(hip_stream), n, w, w_bf16, g, m, v, a);
+  return e == hipSuccess ? VAPR_OK : hip_fail(nullptr, e, "k_adam launch");
 }
 
 static int ws_io(vapr_ctx* ctx, int n_worlds, int tpw, int T, int n_ls, void* ws, size_t ws_bytes, int tensor,
