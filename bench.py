@@ -286,6 +286,132 @@ def cpu_baseline(prec, budget_s=12.0):
                       f"{dt:.1f} s single-threaded"}
 
 
+def seeding_study(args):
+    """The learned seeder end to end on synthetic problems (one GPU): draw problems of 16 cuboids,
+    keep those with collision-free endpoints, solve each from 32 linear initial trajectories, train
+    the network on the 8 lowest-cost collision-free solutions, then compare network, linear and
+    random seeds (8 each) on held-out problems by iterations until the first collision-free
+    trajectory.  The arm is the benchmark's without self pairs (its random sphere model overlaps
+    itself in nearly every configuration)."""
+    import dataclasses
+
+    import torch
+
+    from paper_2310_07854_amd import Context, seed_pipeline as SP, seeding as SG
+    from synthetic import make_robot, make_seed_inits, make_seed_problems, make_seednet_params
+
+    K, T, S_TRAIN, S_EVAL = 16, 32, 32, 8
+    dev = "cuda:0"
+    d = lambda a: torch.tensor(np.asarray(a, dtype=np.float32), device=dev)
+    robot = make_robot(N_SPHERES, N_PAIRS)
+    robot = dataclasses.replace(robot, pairs=robot.pairs[:0])
+    ctx = Context(0)
+    ctx.set_robot(robot)
+    ctx.set_precision({})
+    ctx.set_culling(False)
+    t_start = time.perf_counter()
+
+    def feasible(n_want, split0):
+        keep = {"pose": [], "half": [], "start": [], "goal": []}
+        have, drawn, split = 0, 0, split0
+        while have < n_want:
+            pr = make_seed_problems(16384, K, split=split)
+            ctx.set_worlds(pr.worlds.pose, pr.worlds.half_ext)
+            ok = SP.endpoints_free(ctx, d(pr.start), d(pr.goal)).cpu().numpy()
+            for key, arr in (("pose", pr.worlds.pose), ("half", pr.worlds.half_ext), ("start", pr.start),
+                             ("goal", pr.goal)):
+                keep[key].append(arr[ok])
+            have += int(ok.sum())
+            drawn += 16384
+            split += 1
+        out = {k: np.concatenate(v)[:n_want] for k, v in keep.items()}
+        return out, drawn
+
+    # training data
+    train_p, drawn = feasible(args.seed_problems, 100)
+    print(f"# seeder: {args.seed_problems} feasible training problems from {drawn} drawn", file=sys.stderr, flush=True)
+    chunks = []
+    t0 = time.perf_counter()
+    for c0 in range(0, args.seed_problems, 2048):
+        sl = slice(c0, min(c0 + 2048, args.seed_problems))
+        ctx.set_worlds(train_p["pose"][sl], train_p["half"][sl])
+        st, gl = d(train_p["start"][sl]), d(train_p["goal"][sl])
+        x0 = d(make_seed_inits(train_p["start"][sl], train_p["goal"][sl], S_TRAIN, T, "linear", split=1000 + c0))
+        sol = SP.solve(ctx, x0, iters=args.seed_solve_iters, check_every=args.seed_solve_iters)
+        tgt, valid = SP.select_targets(sol, st, gl)
+        occ = SG.occupancy(d(train_p["pose"][sl]), d(train_p["half"][sl]))
+        chunks.append({"start": st, "goal": gl, "occ": occ, "targets": tgt, "valid": valid})
+    data = {k: torch.cat([c[k] for c in chunks]) for k in chunks[0]}
+    keep = data["valid"].sum(dim=1) > 0
+    data = {k: v[keep] for k, v in data.items()}
+    t_solve = time.perf_counter() - t0
+    n_data = int(keep.sum().item())
+    print(f"# seeder: solved in {t_solve:.1f} s; {n_data} problems with >= 1 target, "
+          f"{float(data['valid'].sum().item()) / max(n_data, 1):.2f} targets each", file=sys.stderr, flush=True)
+
+    # training
+    net = SG.SeedNet(make_seednet_params())
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    losses = SP.train(net, data, steps=args.seed_train_steps, batch=256, lr=1e-3, log_every=1000)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+
+    # inference throughput of the network (features -> seeds) on a large batch
+    nb = 16384
+    idx = torch.arange(nb, device=dev) % n_data
+    xb = SG.features(data["start"][idx].contiguous(), data["goal"][idx].contiguous(), data["occ"][idx].contiguous())
+    for _ in range(3):
+        net.forward(xb)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(20)]
+    torch.cuda.synchronize()
+    for a, b in ev:
+        a.record()
+        net.forward(xb)
+        b.record()
+    torch.cuda.synchronize()
+    fwd_ms = float(np.median([a.elapsed_time(b) for a, b in ev]))
+    flops = 2.0 * nb * (544 * 256 + 256 * 256 * 2 + 256 * 1792)
+
+    # evaluation on held-out problems
+    eval_p, drawn_eval = feasible(args.seed_eval, 1)
+    ctx.set_worlds(eval_p["pose"], eval_p["half"])
+    st, gl = d(eval_p["start"]), d(eval_p["goal"])
+    occ = SG.occupancy(d(eval_p["pose"]), d(eval_p["half"]))
+    inits = {"network": net.seeds(st, gl, occ),
+             "linear": d(make_seed_inits(eval_p["start"], eval_p["goal"], S_EVAL, T, "linear", split=1)),
+             "random": d(make_seed_inits(eval_p["start"], eval_p["goal"], S_EVAL, T, "random", split=1))}
+    curves, firsts = {}, {}
+    for kind, x0 in inits.items():
+        sol = SP.solve(ctx, x0.contiguous(), iters=args.seed_eval_iters, check_every=1)
+        ff = sol["first_free"].cpu().numpy()
+        firsts[kind] = ff
+        curves[kind] = {str(i): float(np.mean((ff >= 0) & (ff <= i))) for i in (0, 1, 2, 3, 5, 10, 20, args.seed_eval_iters)}
+        print(f"# seeds {kind}: collision-free rate by iteration {curves[kind]}", file=sys.stderr, flush=True)
+    # iterations each kind needs to reach the collision-free rate all three reach
+    rate = min(float(np.mean(ff >= 0)) for ff in firsts.values())
+    need = {}
+    for kind, ff in firsts.items():
+        ok = np.sort(np.where(ff >= 0, ff, 10 ** 9))
+        need[kind] = int(ok[int(np.ceil(rate * len(ff))) - 1]) if rate > 0 else None
+    ctx.close()
+    line = {"metric": "learned seeding: collision-free rate by optimiser iteration (network vs linear vs random "
+                      "seeds, 8 each)",
+            "data": "synthetic", "n_gpus": 1,
+            "config": {"workload": f"7-joint arm, 60 spheres, no self pairs; worlds of {K} cuboids; T = {T}; "
+                                   f"{args.seed_problems} training problems solved from {S_TRAIN} linear seeds "
+                                   f"x {args.seed_solve_iters} iterations; {args.seed_eval} held-out problems",
+                       "train_steps": args.seed_train_steps, "batch": 256, "lr": 1e-3},
+            "problems_drawn": drawn, "problems_with_targets": n_data,
+            "targets_per_problem": float(data["valid"].sum().item()) / max(n_data, 1),
+            "solve_s": t_solve, "train_s": t_train, "loss_first": losses[0], "loss_last": losses[-1],
+            "curves": curves, "common_rate": rate, "iterations_to_common_rate": need,
+            "network_forward": {"batch": nb, "ms": fwd_ms, "TFLOPs": flops / (fwd_ms * 1e-3) / 1e12,
+                                "peak_bf16_TFLOPs": 2500.0},
+            "total_s": time.perf_counter() - t_start}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -294,6 +420,12 @@ def main():
     ap.add_argument("--precision", default="paper_like", choices=[k for k in PRECISIONS if k != "f32"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--variants", action="store_true", help="also time every other assignment")
+    ap.add_argument("--seeding", action="store_true", help="run the learned-seeder study instead")
+    ap.add_argument("--seed-problems", type=int, default=20000)
+    ap.add_argument("--seed-solve-iters", type=int, default=60)
+    ap.add_argument("--seed-train-steps", type=int, default=4000)
+    ap.add_argument("--seed-eval", type=int, default=1024)
+    ap.add_argument("--seed-eval-iters", type=int, default=50)
     ap.add_argument("--only", choices=list(PRECISIONS), default=None,
                     help="run one assignment's optimisation loop and nothing else (for profiler runs)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -309,6 +441,9 @@ def main():
             b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_MiB": args.copy_calibration, "launches": 5}))
+        return
+    if args.seeding:
+        seeding_study(args)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (--gpus {args.gpus} requested): the cost path shards by world "

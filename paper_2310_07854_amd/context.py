@@ -87,6 +87,9 @@ class Context:
             L.check(self._lib.vapr_create(ctypes.byref(h), device, _stream_handle()))
         self._h = h
         self.n_spheres = 0
+        # the library's defaults (eta as the FP32 value the kernels compare with)
+        self.cost_params = {"eta": float(np.float32(0.02)), "w_coll": 100.0, "w_self": 100.0, "w_bound": 10.0,
+                            "w_smooth": 1.0}
         self.precision: Dict[str, Tuple[str, int]] = {t: ("f32", 0) for t in TENSORS}
         self.recompute_poses = False
 
@@ -138,6 +141,8 @@ class Context:
     def set_cost_params(self, eta=0.02, w_coll=100.0, w_self=100.0, w_bound=10.0, w_smooth=1.0) -> None:
         p = L.CostParamsC(eta, w_coll, w_self, w_bound, w_smooth)
         self._call("vapr_set_cost_params", ctypes.byref(p))
+        self.cost_params = {"eta": float(p.eta), "w_coll": w_coll, "w_self": w_self, "w_bound": w_bound,
+                            "w_smooth": w_smooth}
 
     def set_culling(self, enable: bool) -> None:
         """Exact cuboid culling in the sphere-cost stage (on by default; results are identical)."""
