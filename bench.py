@@ -287,22 +287,24 @@ def cpu_baseline(prec, budget_s=12.0):
 
 
 def seeding_study(args):
-    """The learned seeder end to end on synthetic problems (one GPU): draw problems of 16 cuboids,
-    keep those with collision-free endpoints, solve each from 32 linear initial trajectories, train
-    the network on the 8 lowest-cost collision-free solutions, then compare network, linear and
-    random seeds (8 each) on held-out problems by iterations until the first collision-free
-    trajectory.  The arm is the benchmark's without self pairs (its random sphere model overlaps
-    itself in nearly every configuration)."""
+    """The learned seeder end to end on synthetic problems (one GPU), per environment: an environment
+    is a base world of 16 cuboids whose problems jitter every cuboid centre by up to 5 cm and draw
+    start and goal uniformly.  Keep problems with collision-free endpoints, solve each from 32 linear
+    initial trajectories, train the network on the 8 lowest-cost collision-free solutions, then
+    compare network, linear and random seeds (8 each) on held-out problems of the same environment
+    by the first optimiser iteration at which a seed is collision-free.  The arm is the benchmark's
+    without self pairs (its random sphere model overlaps itself in nearly every configuration)."""
     import dataclasses
 
     import torch
 
     from paper_2310_07854_amd import Context, seed_pipeline as SP, seeding as SG
-    from synthetic import make_robot, make_seed_inits, make_seed_problems, make_seednet_params
+    from synthetic import make_robot, make_seed_family, make_seed_inits, make_seednet_params
 
     K, T, S_TRAIN, S_EVAL = 16, 32, 32, 8
     dev = "cuda:0"
     d = lambda a: torch.tensor(np.asarray(a, dtype=np.float32), device=dev)
+    log = lambda msg: print(f"# seeder: {msg}", file=sys.stderr, flush=True)
     robot = make_robot(N_SPHERES, N_PAIRS)
     robot = dataclasses.replace(robot, pairs=robot.pairs[:0])
     ctx = Context(0)
@@ -311,11 +313,11 @@ def seeding_study(args):
     ctx.set_culling(False)
     t_start = time.perf_counter()
 
-    def feasible(n_want, split0):
+    def feasible(family, n_want, split0):
         keep = {"pose": [], "half": [], "start": [], "goal": []}
         have, drawn, split = 0, 0, split0
         while have < n_want:
-            pr = make_seed_problems(16384, K, split=split)
+            pr = make_seed_family(16384, K, family, split=split)
             ctx.set_worlds(pr.worlds.pose, pr.worlds.half_ext)
             ok = SP.endpoints_free(ctx, d(pr.start), d(pr.goal)).cpu().numpy()
             for key, arr in (("pose", pr.worlds.pose), ("half", pr.worlds.half_ext), ("start", pr.start),
@@ -324,91 +326,180 @@ def seeding_study(args):
             have += int(ok.sum())
             drawn += 16384
             split += 1
-        out = {k: np.concatenate(v)[:n_want] for k, v in keep.items()}
-        return out, drawn
+            log(f"environment {family}: {have} of {n_want} feasible problems from {drawn} drawn")
+            if drawn >= 64 * n_want:
+                raise RuntimeError(f"environment {family}: too few problems with collision-free endpoints")
+        return {k: np.concatenate(v)[:n_want] for k, v in keep.items()}, drawn
 
-    # training data
-    train_p, drawn = feasible(args.seed_problems, 100)
-    print(f"# seeder: {args.seed_problems} feasible training problems from {drawn} drawn", file=sys.stderr, flush=True)
-    chunks = []
-    t0 = time.perf_counter()
-    for c0 in range(0, args.seed_problems, 2048):
-        sl = slice(c0, min(c0 + 2048, args.seed_problems))
-        ctx.set_worlds(train_p["pose"][sl], train_p["half"][sl])
-        st, gl = d(train_p["start"][sl]), d(train_p["goal"][sl])
-        x0 = d(make_seed_inits(train_p["start"][sl], train_p["goal"][sl], S_TRAIN, T, "linear", split=1000 + c0))
-        sol = SP.solve(ctx, x0, iters=args.seed_solve_iters, check_every=args.seed_solve_iters)
-        tgt, valid = SP.select_targets(sol, st, gl)
-        occ = SG.occupancy(d(train_p["pose"][sl]), d(train_p["half"][sl]))
-        chunks.append({"start": st, "goal": gl, "occ": occ, "targets": tgt, "valid": valid})
-    data = {k: torch.cat([c[k] for c in chunks]) for k in chunks[0]}
-    keep = data["valid"].sum(dim=1) > 0
-    data = {k: v[keep] for k, v in data.items()}
-    t_solve = time.perf_counter() - t0
-    n_data = int(keep.sum().item())
-    print(f"# seeder: solved in {t_solve:.1f} s; {n_data} problems with >= 1 target, "
-          f"{float(data['valid'].sum().item()) / max(n_data, 1):.2f} targets each", file=sys.stderr, flush=True)
+    def dataset(family):
+        p, drawn = feasible(family, args.seed_problems, 100)
+        chunks = []
+        for c0 in range(0, args.seed_problems, 4096):
+            sl = slice(c0, min(c0 + 4096, args.seed_problems))
+            ctx.set_worlds(p["pose"][sl], p["half"][sl])
+            st, gl = d(p["start"][sl]), d(p["goal"][sl])
+            x0 = d(make_seed_inits(p["start"][sl], p["goal"][sl], S_TRAIN, T, "linear", split=1000 + c0))
+            sol = SP.solve(ctx, x0, iters=args.seed_solve_iters, check_every=args.seed_solve_iters)
+            tgt, valid = SP.select_targets(sol, st, gl)
+            occ = SG.occupancy(d(p["pose"][sl]), d(p["half"][sl]))
+            chunks.append({"start": st, "goal": gl, "occ": occ, "targets": tgt, "valid": valid})
+            log(f"environment {family}: solved {sl.stop} of {args.seed_problems}")
+        data = {k: torch.cat([c[k] for c in chunks]) for k in chunks[0]}
+        keep = data["valid"].sum(dim=1) > 0
+        return {k: v[keep] for k, v in data.items()}, drawn
 
-    # training
-    net = SG.SeedNet(make_seednet_params())
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    losses = SP.train(net, data, steps=args.seed_train_steps, batch=256, lr=1e-3, log_every=1000)
-    torch.cuda.synchronize()
-    t_train = time.perf_counter() - t0
+    envs = []
+    for family in range(args.seed_envs):
+        t0 = time.perf_counter()
+        data, drawn = dataset(family)
+        t_data = time.perf_counter() - t0
+        n_data = int(data["start"].shape[0])
+        net = SG.SeedNet(make_seednet_params())
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        losses = SP.train(net, data, steps=args.seed_train_steps, batch=256, lr=1e-3)
+        torch.cuda.synchronize()
+        t_train = time.perf_counter() - t0
+        log(f"environment {family}: trained {args.seed_train_steps} steps in {t_train:.1f} s, "
+            f"loss {np.mean(losses[:20]):.4f} -> {np.mean(losses[-20:]):.4f}")
+        ev, _ = feasible(family, args.seed_eval, 1)
+        ctx.set_worlds(ev["pose"], ev["half"])
+        st, gl = d(ev["start"]), d(ev["goal"])
+        occ = SG.occupancy(d(ev["pose"]), d(ev["half"]))
+        inits = {"network": net.seeds(st, gl, occ),
+                 "linear": d(make_seed_inits(ev["start"], ev["goal"], S_EVAL, T, "linear", split=1)),
+                 "random": d(make_seed_inits(ev["start"], ev["goal"], S_EVAL, T, "random", split=1))}
+        firsts, final_cost = {}, {}
+        for kind, x0 in inits.items():
+            sol = SP.solve(ctx, x0.contiguous(), iters=args.seed_eval_iters, check_every=1)
+            firsts[kind] = sol["first_free"].cpu().numpy()
+            masked = torch.where(sol["free"], sol["cost"], torch.full_like(sol["cost"], float("inf")))
+            best = masked.min(dim=1).values.cpu().numpy()
+            final_cost[kind] = float(np.median(best[np.isfinite(best)])) if np.isfinite(best).any() else None
+            log(f"environment {family}, {kind} seeds: collision-free by iteration 0/1/5/20: "
+                + " ".join(f"{np.mean((firsts[kind] >= 0) & (firsts[kind] <= i)):.3f}" for i in (0, 1, 5, 20)))
+        envs.append({"environment": family, "problems_drawn": drawn, "problems_with_targets": n_data,
+                     "targets_per_problem": float(data["valid"].sum().item()) / max(n_data, 1),
+                     "data_s": t_data, "train_s": t_train, "loss_first": float(np.mean(losses[:20])),
+                     "loss_last": float(np.mean(losses[-20:])), "firsts": firsts,
+                     "median_final_cost": final_cost})
 
-    # inference throughput of the network (features -> seeds) on a large batch
+    # inference throughput of the network (features -> 8 seeds) at a large batch
     nb = 16384
-    idx = torch.arange(nb, device=dev) % n_data
-    xb = SG.features(data["start"][idx].contiguous(), data["goal"][idx].contiguous(), data["occ"][idx].contiguous())
+    xb = SG.features(d(np.zeros((nb, 7))), d(np.ones((nb, 7))), torch.zeros(nb, 512, device=dev))
     for _ in range(3):
         net.forward(xb)
-    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(20)]
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(20)]
     torch.cuda.synchronize()
-    for a, b in ev:
+    for a, b in evs:
         a.record()
         net.forward(xb)
         b.record()
     torch.cuda.synchronize()
-    fwd_ms = float(np.median([a.elapsed_time(b) for a, b in ev]))
+    fwd_ms = float(np.median([a.elapsed_time(b) for a, b in evs]))
     flops = 2.0 * nb * (544 * 256 + 256 * 256 * 2 + 256 * 1792)
-
-    # evaluation on held-out problems
-    eval_p, drawn_eval = feasible(args.seed_eval, 1)
-    ctx.set_worlds(eval_p["pose"], eval_p["half"])
-    st, gl = d(eval_p["start"]), d(eval_p["goal"])
-    occ = SG.occupancy(d(eval_p["pose"]), d(eval_p["half"]))
-    inits = {"network": net.seeds(st, gl, occ),
-             "linear": d(make_seed_inits(eval_p["start"], eval_p["goal"], S_EVAL, T, "linear", split=1)),
-             "random": d(make_seed_inits(eval_p["start"], eval_p["goal"], S_EVAL, T, "random", split=1))}
-    curves, firsts = {}, {}
-    for kind, x0 in inits.items():
-        sol = SP.solve(ctx, x0.contiguous(), iters=args.seed_eval_iters, check_every=1)
-        ff = sol["first_free"].cpu().numpy()
-        firsts[kind] = ff
-        curves[kind] = {str(i): float(np.mean((ff >= 0) & (ff <= i))) for i in (0, 1, 2, 3, 5, 10, 20, args.seed_eval_iters)}
-        print(f"# seeds {kind}: collision-free rate by iteration {curves[kind]}", file=sys.stderr, flush=True)
-    # iterations each kind needs to reach the collision-free rate all three reach
-    rate = min(float(np.mean(ff >= 0)) for ff in firsts.values())
-    need = {}
-    for kind, ff in firsts.items():
-        ok = np.sort(np.where(ff >= 0, ff, 10 ** 9))
-        need[kind] = int(ok[int(np.ceil(rate * len(ff))) - 1]) if rate > 0 else None
     ctx.close()
+
+    # pooled over environments: collision-free rate by iteration, and the iterations each kind of
+    # seed needs to reach the rate that all three reach
+    kinds = ("network", "linear", "random")
+    pooled = {k: np.concatenate([e["firsts"][k] for e in envs]) for k in kinds}
+    marks = sorted({0, 1, 2, 3, 5, 10, 20, args.seed_eval_iters})
+    curves = {k: {str(i): float(np.mean((ff >= 0) & (ff <= i))) for i in marks} for k, ff in pooled.items()}
+    rate = min(float(np.mean(ff >= 0)) for ff in pooled.values())
+    need = {}
+    for k, ff in pooled.items():
+        srt = np.sort(np.where(ff >= 0, ff, 10 ** 9))
+        need[k] = int(srt[int(np.ceil(rate * len(ff))) - 1]) if rate > 0 else None
+    for e in envs:
+        e.pop("firsts")
     line = {"metric": "learned seeding: collision-free rate by optimiser iteration (network vs linear vs random "
                       "seeds, 8 each)",
-            "data": "synthetic", "n_gpus": 1,
-            "config": {"workload": f"7-joint arm, 60 spheres, no self pairs; worlds of {K} cuboids; T = {T}; "
-                                   f"{args.seed_problems} training problems solved from {S_TRAIN} linear seeds "
-                                   f"x {args.seed_solve_iters} iterations; {args.seed_eval} held-out problems",
+            "data": "synthetic", "n_gpus": 1, "dtype": "bf16 GEMM operands, f32 accumulate",
+            "config": {"workload": f"7-joint arm, 60 spheres, no self pairs; {args.seed_envs} environments of {K} "
+                                   f"cuboids (centres jittered 5 cm per problem); T = {T}; "
+                                   f"{args.seed_problems} training problems per environment solved from "
+                                   f"{S_TRAIN} linear seeds x {args.seed_solve_iters} iterations; "
+                                   f"{args.seed_eval} held-out problems per environment",
                        "train_steps": args.seed_train_steps, "batch": 256, "lr": 1e-3},
-            "problems_drawn": drawn, "problems_with_targets": n_data,
-            "targets_per_problem": float(data["valid"].sum().item()) / max(n_data, 1),
-            "solve_s": t_solve, "train_s": t_train, "loss_first": losses[0], "loss_last": losses[-1],
             "curves": curves, "common_rate": rate, "iterations_to_common_rate": need,
+            "environments": envs,
             "network_forward": {"batch": nb, "ms": fwd_ms, "TFLOPs": flops / (fwd_ms * 1e-3) / 1e12,
                                 "peak_bf16_TFLOPs": 2500.0},
             "total_s": time.perf_counter() - t_start}
+    print(json.dumps(line), flush=True)
+
+
+SEED_FLOPS_PER_PROBLEM = 2 * (544 * 256 + 2 * 256 * 256 + 256 * 1792)
+# algorithmic HBM bytes per problem of each inference kernel (weights, read once per launch, excluded)
+SEED_BYTES = {"k_features": 56 + 2048 + 1088, "gemm1": 1088 + 512, "gemm2": 512 + 512, "gemm3": 512 + 512,
+              "head": 512 + 56 + 7168}
+
+
+def seed_inference(args):
+    """Throughput of the seeding network's inference (features -> 3 BF16 MFMA GEMMs with GELU ->
+    output GEMM fused with the trajectory construction -> 8 seed trajectories) on a batch of problems
+    resident in HBM; weights at their initial values (the work does not depend on them)."""
+    import torch
+
+    from paper_2310_07854_amd import seeding as SG
+    from synthetic import make_seed_problems, make_seednet_params
+
+    nb = args.seed_batch
+    dev = "cuda:0"
+    pr = make_seed_problems(nb, 16, split=7)
+    d = lambda a: torch.tensor(np.asarray(a, dtype=np.float32), device=dev)
+    st, gl = d(pr.start), d(pr.goal)
+    occ = SG.occupancy(d(pr.worlds.pose), d(pr.worlds.half_ext))
+    net = SG.SeedNet(make_seednet_params())
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        net.seeds(st, gl, occ)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        net.seeds(st, gl, occ)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    # per-kernel durations with events around each launch on the launching stream
+    x = SG.features(st, gl, occ)
+    ev = {k: [] for k in SEED_BYTES}
+    a = x
+    reps = 10
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True); e0.record(stream)
+        x = SG.features(st, gl, occ)
+        e1 = torch.cuda.Event(enable_timing=True); e1.record(stream)
+        ev["k_features"].append((e0, e1))
+        a, k = x, 544
+        for l in (1, 2, 3):
+            a_next = torch.empty(nb, 256, dtype=torch.bfloat16, device=dev)
+            e0 = torch.cuda.Event(enable_timing=True); e0.record(stream)
+            SG.gemm(a, k, 1, net.view(net.w16, f"W{l}"), 256, 1, nb, 256, k, bias=net.view(net.w, f"b{l}"),
+                    epilogue=SG.GELU, C16=a_next)
+            e1 = torch.cuda.Event(enable_timing=True); e1.record(stream)
+            ev[f"gemm{l}"].append((e0, e1))
+            a, k = a_next, 256
+        e0 = torch.cuda.Event(enable_timing=True); e0.record(stream)
+        net.head(a, st, gl)
+        e1 = torch.cuda.Event(enable_timing=True); e1.record(stream)
+        ev["head"].append((e0, e1))
+    torch.cuda.synchronize()
+    kern = {}
+    for k, lst in ev.items():
+        us = float(np.mean([a.elapsed_time(b) for a, b in lst])) * 1e3
+        kern[k] = {"us": us, "GBs": SEED_BYTES[k] * nb / (us * 1e-6) / 1e9}
+    dom = max(kern, key=lambda k: kern[k]["us"])
+    ach = kern[dom]["GBs"]
+    line = {"metric": "seeding network inference throughput", "value": nb / (ms * 1e-3), "unit": "problems/s",
+            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "bf16 operands, f32 accumulate", "data": "synthetic",
+            "config": {"workload": f"{nb} problems: 7 + 7 + 512 inputs -> 3 x 256 GELU -> 8 seeds x 32 x 7"},
+            "TFLOPs": SEED_FLOPS_PER_PROBLEM * nb / (ms * 1e-3) / 1e12,
+            "kernels": kern,
+            "roofline": {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": ach / HBM_PEAK_GBS, "traffic": None,
+                         "bytes_per_problem": SEED_BYTES[dom]}}
     print(json.dumps(line), flush=True)
 
 
@@ -421,11 +512,14 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--variants", action="store_true", help="also time every other assignment")
     ap.add_argument("--seeding", action="store_true", help="run the learned-seeder study instead")
-    ap.add_argument("--seed-problems", type=int, default=20000)
+    ap.add_argument("--seed-infer", action="store_true", help="time the seeding network's inference instead")
+    ap.add_argument("--seed-batch", type=int, default=65536)
+    ap.add_argument("--seed-envs", type=int, default=2)
+    ap.add_argument("--seed-problems", type=int, default=32768)
     ap.add_argument("--seed-solve-iters", type=int, default=60)
-    ap.add_argument("--seed-train-steps", type=int, default=4000)
+    ap.add_argument("--seed-train-steps", type=int, default=2000)
     ap.add_argument("--seed-eval", type=int, default=1024)
-    ap.add_argument("--seed-eval-iters", type=int, default=50)
+    ap.add_argument("--seed-eval-iters", type=int, default=30)
     ap.add_argument("--only", choices=list(PRECISIONS), default=None,
                     help="run one assignment's optimisation loop and nothing else (for profiler runs)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -444,6 +538,9 @@ def main():
         return
     if args.seeding:
         seeding_study(args)
+        return
+    if args.seed_infer:
+        seed_inference(args)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (--gpus {args.gpus} requested): the cost path shards by world "

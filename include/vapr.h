@@ -269,12 +269,21 @@ enum { VAPR_GEMM_PLAIN = 0, VAPR_GEMM_GELU = 1, VAPR_GEMM_GELU_GRAD = 2 };
  * and when it is the k stride the other stride must be a multiple of 8 with the pointer 16-byte
  * aligned.  K must be a positive multiple of 32; M, N >= 1.  Epilogue:
  *   VAPR_GEMM_PLAIN      out = Z
- *   VAPR_GEMM_GELU       aux = Z, out = GELU(Z) = Z Phi(Z)                (aux required)
+ *   VAPR_GEMM_GELU       aux = Z (when aux is not null: training keeps it for the backward
+ *                        pass, inference passes null), out = GELU(Z) = Z Phi(Z)
  *   VAPR_GEMM_GELU_GRAD  out = Z * GELU'(aux)                             (aux read)
  * out goes to C (FP32) and/or C_bf16 (round to nearest even), [M][ldc], ldc >= N; at least one. */
 int vapr_gemm_bf16(int M, int N, int K, const uint16_t* A, int64_t a_ms, int64_t a_ks, const uint16_t* B,
                    int64_t b_ks, int64_t b_ns, const float* bias, int epilogue, float* aux, float* C,
                    uint16_t* C_bf16, int64_t ldc, void* hip_stream);
+
+/* The network's output layer fused with the trajectory construction (inference): traj = the
+ * trajectories vapr_seed_trajectories builds from y = a3 W4 + b4, bit-identical to that pair of
+ * calls, without y ever reaching memory.  a3 [n][lda] BF16 codes (lda >= 256, a multiple of 8,
+ * 16-byte aligned) = the last hidden layer, W4 [256][1792] BF16 codes, b4 [1792] FP32, start, goal
+ * [n][7] FP32, traj [n][8][32][7] FP32; all device memory owned by the caller. */
+int vapr_seed_head(int n, const uint16_t* a3, int64_t lda, const uint16_t* W4, const float* b4, const float* start,
+                   const float* goal, float* traj, void* hip_stream);
 
 /* Min-over-slot matching loss of n problems: y [n][1792] predicted deviations (8 slots x 224),
  * targets [n][1792] (8 target trajectories), valid [n][8] (0 / nonzero).  e_sj = mean over 224 of
@@ -284,7 +293,9 @@ int vapr_gemm_bf16(int M, int N, int K, const uint16_t* A, int64_t a_ms, int64_t
 int vapr_seed_loss(int n, const float* y, const float* targets, const float* valid, int n_valid, double* loss,
                    int32_t* assign, float* dy, double* partial, void* hip_stream);
 
-/* out[j] = sum_i X[i * ldx + j] for j < N (bias gradients), summed in row order. */
+/* out[j] = sum_i X[i * ldx + j] for j < N (bias gradients), FP32, rows summed in 16 interleaved
+ * groups and then across groups (within M * 2^-24 * sum_i |X[i][j]| of the exact sum).  M, N >= 1,
+ * ldx >= N. */
 int vapr_column_sum(int M, int N, const float* X, int64_t ldx, float* out, void* hip_stream);
 
 /* Adam step `step` (>= 1) on n FP32 weights w with gradient g and moments m, v (FP32, updated in

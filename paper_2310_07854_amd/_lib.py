@@ -88,6 +88,7 @@ SIGNATURES = {
     "vapr_seed_features": (_I, [_I, _P, _P, _P, _P, _P]),
     "vapr_seed_trajectories": (_I, [_I, _P, _P, _P, _P, _P]),
     "vapr_gemm_bf16": (_I, [_I, _I, _I, _P, _I64, _I64, _P, _I64, _I64, _P, _I, _P, _P, _P, _I64, _P]),
+    "vapr_seed_head": (_I, [_I, _P, _I64, _P, _P, _P, _P, _P, _P]),
     "vapr_seed_loss": (_I, [_I, _P, _P, _P, _I, _P, _P, _P, _P, _P]),
     "vapr_column_sum": (_I, [_I, _I, _P, _I64, _P, _P]),
     "vapr_adam": (_I, [_I64, _P, _P, _P, _P, _P, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, _I,

@@ -61,17 +61,27 @@ __global__ __launch_bounds__(256) void k_occupancy(const float* __restrict__ pos
 
 // ---- features ---------------------------------------------------------------------------------------
 
+// one thread per 8 consecutive columns of a row (one 16-byte store); 68 chunks per 544-wide row
 __global__ __launch_bounds__(256) void k_features(int n, const float* __restrict__ start, const float* __restrict__ goal,
                                                   const float* __restrict__ occ, uint16_t* __restrict__ x) {
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (i >= (int64_t)n * SEED_IN_PAD) return;
-  const int64_t r = i / SEED_IN_PAD;
-  const int c = (int)(i - r * SEED_IN_PAD);
-  float v = 0.f;
-  if (c < SEED_J) v = start[r * SEED_J + c];
-  else if (c < 2 * SEED_J) v = goal[r * SEED_J + c - SEED_J];
-  else if (c < SEED_IN) v = occ[r * SEED_VOXELS + c - 2 * SEED_J];
-  x[i] = to_bf16(v);
+  constexpr int CH = SEED_IN_PAD / 8;
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n * CH) return;
+  const int r = i / CH, c0 = (i - r * CH) * 8;
+  uint16_t v[8];
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const int c = c0 + e;
+    float f = 0.f;
+    if (c < SEED_J) f = start[r * SEED_J + c];
+    else if (c < 2 * SEED_J) f = goal[r * SEED_J + c - SEED_J];
+    else if (c < SEED_IN) f = occ[(int64_t)r * SEED_VOXELS + c - 2 * SEED_J];
+    v[e] = to_bf16(f);
+  }
+  uint4 q;
+  q.x = v[0] | ((uint32_t)v[1] << 16); q.y = v[2] | ((uint32_t)v[3] << 16);
+  q.z = v[4] | ((uint32_t)v[5] << 16); q.w = v[6] | ((uint32_t)v[7] << 16);
+  *reinterpret_cast<uint4*>(x + (int64_t)r * SEED_IN_PAD + c0) = q;
 }
 
 // ---- GEMM on MFMA -------------------------------------------------------------------------------------
@@ -84,113 +94,231 @@ __global__ __launch_bounds__(256) void k_features(int n, const float* __restrict
 
 constexpr int GT = 64, GK = 32, GPAD = 40;
 
+// Seed-trajectory epilogue value for output column n of the block's row r: the straight line from
+// start to goal plus the network's deviation v at interior timesteps, start / goal exactly at the
+// ends.  se holds the block's start rows, then its goal rows ([2][GT][7]).
+__device__ __forceinline__ float seed_traj_value(const float* se, int r, int n, float v) {
+  const int k = n % SEED_TRAJ, t = k / SEED_J, j = k - t * SEED_J;
+  const float s0 = se[r * SEED_J + j], g0 = se[(GT + r) * SEED_J + j];
+  const float line = fmaf(g0 - s0, (float)t / (float)(SEED_T - 1), s0);
+  return t == 0 ? s0 : (t == SEED_T - 1 ? g0 : line + v);
+}
+
+constexpr int CPAD = GT + 4;  // staged output tile row stride (floats)
+static_assert((GT / 2) * CPAD * 4 <= 2 * GT * GPAD * 2, "half output tile must fit in one operand stage");
+
+// One operand tile (64 rows x 32 k) is stored in LDS as [row][k] (row stride GPAD halfwords), with
+// the four 8-element k chunks of a row permuted by an XOR with bits 4..5 of the row: the transposing
+// writes below (rows 4 apart in one instruction) then fall in distinct banks, and an MFMA operand
+// read (16 rows of one 16-row group, one chunk per lane group) stays a permutation of the unswizzled
+// one.  Rows past `rows` read as zero; K is a multiple of 32, so k is always in range.
+//   load_kc / store_kc: element (row, k) at p[row * rs + k] (k contiguous): one 16-byte load per
+//            thread, one 16-byte LDS write
+//   load_rc / store_rc: element (row, k) at p[row + k * ks] (rows contiguous): with `vec` (ks a
+//            multiple of 8, p 16-byte aligned) two 8-byte loads per thread, 4 rows at k and k + 1,
+//            written as 4 32-bit (k, k + 1) pairs; otherwise 8 scalar loads per thread
+__device__ __forceinline__ int lds_off(int row, int chunk) { return row * GPAD + ((chunk ^ ((row >> 4) & 3)) << 3); }
+
+__device__ __forceinline__ uint4 pack8(const uint16_t v[8]) {
+  uint4 q;
+  q.x = v[0] | ((uint32_t)v[1] << 16); q.y = v[2] | ((uint32_t)v[3] << 16);
+  q.z = v[4] | ((uint32_t)v[5] << 16); q.w = v[6] | ((uint32_t)v[7] << 16);
+  return q;
+}
+
+struct Frag {
+  uint4 q;
+};
+
+__device__ __forceinline__ Frag load_kc(const uint16_t* __restrict__ p, int64_t rs, int row0, int rows, int k0, int tid) {
+  const int r = tid >> 2, kc = (tid & 3) * 8;
+  Frag f{make_uint4(0u, 0u, 0u, 0u)};
+  if (row0 + r < rows) f.q = *reinterpret_cast<const uint4*>(p + (int64_t)(row0 + r) * rs + k0 + kc);
+  return f;
+}
+
+__device__ __forceinline__ void store_kc(const Frag& f, uint16_t* __restrict__ s, int tid) {
+  *reinterpret_cast<uint4*>(s + lds_off(tid >> 2, tid & 3)) = f.q;
+}
+
+__device__ __forceinline__ Frag load_rc(const uint16_t* __restrict__ p, int64_t ks, int row0, int rows, int k0,
+                                        bool vec, int tid) {
+  uint16_t v[8];
+  if (vec) {
+    // q.x, q.y: rows 4 nc .. + 3 at k = 2 kp; q.z, q.w: the same rows at k + 1
+    const int nc = tid & 15, kp = tid >> 4;
+    const int r = row0 + nc * 4;
+    const uint16_t* q0 = p + (int64_t)r + (int64_t)(k0 + 2 * kp) * ks;
+    const uint16_t* q1 = q0 + ks;
+    if (r + 3 < rows) {
+      const uint2 a = *reinterpret_cast<const uint2*>(q0), b = *reinterpret_cast<const uint2*>(q1);
+      return Frag{make_uint4(a.x, a.y, b.x, b.y)};
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      v[e] = r + e < rows ? q0[e] : (uint16_t)0;
+      v[4 + e] = r + e < rows ? q1[e] : (uint16_t)0;
+    }
+  } else {
+    const int r = tid & 63, kc = (tid >> 6) * 8;
+#pragma unroll
+    for (int e = 0; e < 8; ++e)
+      v[e] = row0 + r < rows ? p[(int64_t)(row0 + r) + (int64_t)(k0 + kc + e) * ks] : (uint16_t)0;
+  }
+  return Frag{pack8(v)};
+}
+
+__device__ __forceinline__ void store_rc(const Frag& f, bool vec, uint16_t* __restrict__ s, int tid) {
+  if (vec) {
+    const int nc = tid & 15, kp = tid >> 4;
+    const uint32_t lo[2] = {f.q.x, f.q.y}, hi[2] = {f.q.z, f.q.w};
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const uint32_t a = (lo[e >> 1] >> (16 * (e & 1))) & 0xffff, b = (hi[e >> 1] >> (16 * (e & 1))) & 0xffff;
+      *reinterpret_cast<uint32_t*>(s + lds_off(nc * 4 + e, kp >> 2) + 2 * (kp & 3)) = a | (b << 16);
+    }
+  } else {
+    *reinterpret_cast<uint4*>(s + lds_off(tid & 63, tid >> 6)) = f.q;
+  }
+}
+
+// Block -> output tile.  Workgroups go to the 8 XCDs round-robin by linear id; give XCD x a
+// contiguous run of tiles in row-major (row tile, column tile) order, so that the column tiles of
+// one row tile, which share its A rows, run on one XCD and meet them in its L2.
+__device__ __forceinline__ int xcd_tile(int L, int T) {
+  const int q = T >> 3, r = T & 7, x = L & 7, j = L >> 3;
+  return x * q + min(x, r) + j;
+}
+
 template <bool A_K, bool B_N>
 __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
-  __shared__ __attribute__((aligned(16))) uint16_t sA[GT * GPAD];
-  __shared__ __attribute__((aligned(16))) uint16_t sB[GT * GPAD];
+  // two stages of operand tiles (the next K step is loaded into registers while the MFMAs run on
+  // the current one); after the K loop the same memory stages half of the output tile at a time
+  __shared__ __attribute__((aligned(16))) uint16_t smem[2][2 * GT * GPAD];
+  __shared__ float se[2 * GT * SEED_J];  // start / goal rows of the block (GEMM_SEED_TRAJ)
+  float* sC = reinterpret_cast<float*>(smem[0]);
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int m0 = blockIdx.x * GT, n0 = blockIdx.y * GT;
+  const int n_tiles_n = (g.N + GT - 1) / GT;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int m0 = (tile / n_tiles_n) * GT, n0 = (tile % n_tiles_n) * GT;
+  if (g.epilogue == GEMM_SEED_TRAJ) {
+    // read before the K loop, whose barriers publish them
+    for (int i = tid; i < 2 * GT * SEED_J; i += 256) {
+      const int h = i / (GT * SEED_J), q = i - h * GT * SEED_J;
+      const int64_t o = (int64_t)m0 * SEED_J + q;
+      se[i] = o < (int64_t)g.M * SEED_J ? (h ? g.goal : g.start)[o] : 0.f;
+    }
+  }
   const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
+  const bool a_vec = (g.sak & 7) == 0 && (reinterpret_cast<uintptr_t>(g.A) & 15) == 0;
+  const bool b_vec = (g.sbk & 7) == 0 && (reinterpret_cast<uintptr_t>(g.B) & 15) == 0;
+  auto load_a = [&](int k0) {
+    if constexpr (A_K) return load_kc(g.A, g.sam, m0, g.M, k0, tid);
+    else return load_rc(g.A, g.sak, m0, g.M, k0, a_vec, tid);
+  };
+  auto load_b = [&](int k0) {
+    if constexpr (B_N) return load_rc(g.B, g.sbk, n0, g.N, k0, b_vec, tid);
+    else return load_kc(g.B, g.sbn, n0, g.N, k0, tid);
+  };
   f32x4 acc[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-  for (int k0 = 0; k0 < g.K; k0 += GK) {
-    // A tile -> sA[r][kc .. kc + 7]
-    {
-      uint16_t v[8];
-      int r, kc;
-      if constexpr (A_K) {
-        r = tid >> 2;
-        kc = (tid & 3) * 8;
-        const int m = m0 + r;
-        if (m < g.M) {
-          const uint4 q = *reinterpret_cast<const uint4*>(g.A + (int64_t)m * g.sam + k0 + kc);
-          v[0] = q.x & 0xffff; v[1] = q.x >> 16; v[2] = q.y & 0xffff; v[3] = q.y >> 16;
-          v[4] = q.z & 0xffff; v[5] = q.z >> 16; v[6] = q.w & 0xffff; v[7] = q.w >> 16;
-        } else {
-#pragma unroll
-          for (int e = 0; e < 8; ++e) v[e] = 0;
-        }
-      } else {
-        r = tid & 63;
-        kc = (tid >> 6) * 8;
-        const int m = m0 + r;
-#pragma unroll
-        for (int e = 0; e < 8; ++e) v[e] = m < g.M ? g.A[(int64_t)m + (int64_t)(k0 + kc + e) * g.sak] : (uint16_t)0;
-      }
-      uint4 q;
-      q.x = v[0] | ((uint32_t)v[1] << 16); q.y = v[2] | ((uint32_t)v[3] << 16);
-      q.z = v[4] | ((uint32_t)v[5] << 16); q.w = v[6] | ((uint32_t)v[7] << 16);
-      *reinterpret_cast<uint4*>(sA + r * GPAD + kc) = q;
-    }
-    // B tile -> sB[c][kc .. kc + 7]
-    {
-      uint16_t v[8];
-      int c, kc;
-      if constexpr (B_N) {
-        c = tid & 63;
-        kc = (tid >> 6) * 8;
-        const int n = n0 + c;
-#pragma unroll
-        for (int e = 0; e < 8; ++e) v[e] = n < g.N ? g.B[(int64_t)(k0 + kc + e) * g.sbk + n] : (uint16_t)0;
-      } else {
-        c = tid >> 2;
-        kc = (tid & 3) * 8;
-        const int n = n0 + c;
-        if (n < g.N) {
-          const uint4 q = *reinterpret_cast<const uint4*>(g.B + (int64_t)n * g.sbn + k0 + kc);
-          v[0] = q.x & 0xffff; v[1] = q.x >> 16; v[2] = q.y & 0xffff; v[3] = q.y >> 16;
-          v[4] = q.z & 0xffff; v[5] = q.z >> 16; v[6] = q.w & 0xffff; v[7] = q.w >> 16;
-        } else {
-#pragma unroll
-          for (int e = 0; e < 8; ++e) v[e] = 0;
-        }
-      }
-      uint4 q;
-      q.x = v[0] | ((uint32_t)v[1] << 16); q.y = v[2] | ((uint32_t)v[3] << 16);
-      q.z = v[4] | ((uint32_t)v[5] << 16); q.w = v[6] | ((uint32_t)v[7] << 16);
-      *reinterpret_cast<uint4*>(sB + c * GPAD + kc) = q;
-    }
+  Frag fa = load_a(0), fb = load_b(0);
+  for (int k0 = 0, st = 0; k0 < g.K; k0 += GK, st ^= 1) {
+    uint16_t* sA = smem[st];
+    uint16_t* sB = smem[st] + GT * GPAD;
+    if constexpr (A_K) store_kc(fa, sA, tid);
+    else store_rc(fa, a_vec, sA, tid);
+    if constexpr (B_N) store_rc(fb, b_vec, sB, tid);
+    else store_kc(fb, sB, tid);
+    // one barrier per step: the stage written here was last read two steps ago, before the
+    // previous barrier
     __syncthreads();
+    if (k0 + GK < g.K) {
+      fa = load_a(k0 + GK);
+      fb = load_b(k0 + GK);
+    }
     bf16x8 a[2], b[2];
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
-      a[i] = *reinterpret_cast<const bf16x8*>(sA + (wm + i * 16 + (lane & 15)) * GPAD + 8 * (lane >> 4));
-      b[i] = *reinterpret_cast<const bf16x8*>(sB + (wn + i * 16 + (lane & 15)) * GPAD + 8 * (lane >> 4));
+      a[i] = *reinterpret_cast<const bf16x8*>(sA + lds_off(wm + i * 16 + (lane & 15), lane >> 4));
+      b[i] = *reinterpret_cast<const bf16x8*>(sB + lds_off(wn + i * 16 + (lane & 15), lane >> 4));
     }
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
       for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
-    __syncthreads();
   }
+  __syncthreads();
 
+  // write back through LDS, 32 rows at a time (the waves with wm = 32 h stage half h): thread t
+  // takes 4 consecutive columns (t % 16) * 4 of rows t / 16 and t / 16 + 16, so a wavefront stores
+  // 4 full 256-byte row segments per instruction
+  const int cc = (tid & 15) * 4;
+  const bool vec = (g.ldc & 3) == 0 && (((uintptr_t)g.C | (uintptr_t)g.aux) & 15) == 0 && ((uintptr_t)g.C16 & 7) == 0;
+  for (int h = 0; h < 2; ++h) {
+    if ((wave & 1) == h) {
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const int n = n0 + wn + j * 16 + (lane & 15);
-      if (n >= g.N) continue;
-      const float bias = g.bias ? g.bias[n] : 0.f;
+        for (int j = 0; j < 2; ++j)
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int m = m0 + wm + i * 16 + 4 * (lane >> 4) + e;
-        if (m >= g.M) continue;
-        const int64_t o = (int64_t)m * g.ldc + n;
-        float v = acc[i][j][e] + bias;
+          for (int e = 0; e < 4; ++e)
+            sC[(i * 16 + 4 * (lane >> 4) + e) * CPAD + wn + j * 16 + (lane & 15)] = acc[i][j][e];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int rr = 0; rr < 2; ++rr) {
+      const int r = (tid >> 4) + 16 * rr, m = m0 + 32 * h + r;
+      const int nb = n0 + cc;
+      if (m >= g.M || nb >= g.N) continue;
+      const int64_t o = (int64_t)m * g.ldc + nb;
+      const float4 t4 = *reinterpret_cast<const float4*>(sC + r * CPAD + cc);
+      float v[4] = {t4.x, t4.y, t4.z, t4.w};
+#pragma unroll
+      for (int e = 0; e < 4; ++e) v[e] += g.bias && nb + e < g.N ? g.bias[nb + e] : 0.f;
+      if (vec && nb + 3 < g.N) {
         if (g.epilogue == GEMM_GELU) {
-          g.aux[o] = v;
-          v = gelu_f(v);
+          if (g.aux) *reinterpret_cast<float4*>(g.aux + o) = make_float4(v[0], v[1], v[2], v[3]);
+#pragma unroll
+          for (int e = 0; e < 4; ++e) v[e] = gelu_f(v[e]);
         } else if (g.epilogue == GEMM_GELU_GRAD) {
-          v *= gelu_grad_f(g.aux[o]);
+          const float4 z = *reinterpret_cast<const float4*>(g.aux + o);
+          v[0] *= gelu_grad_f(z.x); v[1] *= gelu_grad_f(z.y); v[2] *= gelu_grad_f(z.z); v[3] *= gelu_grad_f(z.w);
+        } else if (g.epilogue == GEMM_SEED_TRAJ) {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) v[e] = seed_traj_value(se, 32 * h + r, nb + e, v[e]);
         }
-        if (g.C) g.C[o] = v;
-        if (g.C16) g.C16[o] = to_bf16(v);
+        if (g.C) *reinterpret_cast<float4*>(g.C + o) = make_float4(v[0], v[1], v[2], v[3]);
+        if (g.C16) {
+          uint2 q;
+          q.x = to_bf16(v[0]) | ((uint32_t)to_bf16(v[1]) << 16);
+          q.y = to_bf16(v[2]) | ((uint32_t)to_bf16(v[3]) << 16);
+          *reinterpret_cast<uint2*>(g.C16 + o) = q;
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          if (nb + e >= g.N) break;
+          float w = v[e];
+          if (g.epilogue == GEMM_GELU) {
+            if (g.aux) g.aux[o + e] = w;
+            w = gelu_f(w);
+          } else if (g.epilogue == GEMM_GELU_GRAD) {
+            w *= gelu_grad_f(g.aux[o + e]);
+          } else if (g.epilogue == GEMM_SEED_TRAJ) {
+            w = seed_traj_value(se, 32 * h + r, nb + e, w);
+          }
+          if (g.C) g.C[o + e] = w;
+          if (g.C16) g.C16[o + e] = to_bf16(w);
+        }
       }
     }
+    __syncthreads();
+  }
 }
 
 // ---- seed trajectories ------------------------------------------------------------------------------
@@ -275,13 +403,31 @@ __global__ __launch_bounds__(64) void k_seed_loss_total(const double* __restrict
 
 // ---- bias gradients, Adam ------------------------------------------------------------------------------
 
-__global__ __launch_bounds__(256) void k_column_sum(int M, int N, const float* __restrict__ X, int64_t ldx,
-                                                    float* __restrict__ out) {
-  const int n = blockIdx.x * 256 + threadIdx.x;
-  if (n >= N) return;
-  float s = 0.f;
-  for (int m = 0; m < M; ++m) s += X[(int64_t)m * ldx + n];
-  out[n] = s;
+// one block per 64 columns: each of the 16 wavefronts sums every 16th row over the block's columns
+// (one coalesced 256-byte row segment per load, four independent partial sums in flight), then the
+// 16 partial sums are added in LDS
+__global__ __launch_bounds__(1024) void k_column_sum(int M, int N, const float* __restrict__ X, int64_t ldx,
+                                                     float* __restrict__ out) {
+  __shared__ float part[16][64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int n = blockIdx.x * 64 + lane;
+  float s[4] = {0.f, 0.f, 0.f, 0.f};
+  if (n < N) {
+    int m = wv;
+    for (; m + 48 < M; m += 64) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) s[u] += X[(int64_t)(m + 16 * u) * ldx + n];
+    }
+    for (; m < M; m += 16) s[0] += X[(int64_t)m * ldx + n];
+  }
+  part[wv][lane] = (s[0] + s[1]) + (s[2] + s[3]);
+  __syncthreads();
+  if (wv == 0 && n < N) {
+    float t = 0.f;
+#pragma unroll
+    for (int w = 0; w < 16; ++w) t += part[w][lane];
+    out[n] = t;
+  }
 }
 
 __global__ __launch_bounds__(256) void k_adam(int64_t n, float* __restrict__ w, uint16_t* __restrict__ w16,
@@ -310,13 +456,15 @@ hipError_t launch_occupancy(hipStream_t s, int W, int K, const float* pose, cons
 
 hipError_t launch_features(hipStream_t s, int n, const float* start, const float* goal, const float* occ,
                            uint16_t* x) {
-  hipLaunchKernelGGL(k_features, dim3(nblocks((int64_t)n * SEED_IN_PAD, 256)), dim3(256), 0, s, n, start, goal,
+  hipLaunchKernelGGL(k_features, dim3(nblocks((int64_t)n * (SEED_IN_PAD / 8), 256)), dim3(256), 0, s, n, start, goal,
                      occ, x);
   return hipGetLastError();
 }
 
 hipError_t launch_gemm_bf16(hipStream_t s, const GemmArgs& g, bool a_k, bool b_n) {
-  const dim3 grid(nblocks(g.M, GT), nblocks(g.N, GT)), block(256);
+  const int64_t tiles = (int64_t)nblocks(g.M, GT) * nblocks(g.N, GT);
+  if (tiles > INT32_MAX) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)tiles), block(256);
   if (a_k && b_n) hipLaunchKernelGGL((k_gemm_bf16<true, true>), grid, block, 0, s, g);
   else if (a_k) hipLaunchKernelGGL((k_gemm_bf16<true, false>), grid, block, 0, s, g);
   else if (b_n) hipLaunchKernelGGL((k_gemm_bf16<false, true>), grid, block, 0, s, g);
@@ -337,7 +485,7 @@ hipError_t launch_seed_loss(hipStream_t s, int n, const float* y, const float* t
 }
 
 hipError_t launch_column_sum(hipStream_t s, int M, int N, const float* X, int64_t ldx, float* out) {
-  hipLaunchKernelGGL(k_column_sum, dim3(nblocks(N, 256)), dim3(256), 0, s, M, N, X, ldx, out);
+  hipLaunchKernelGGL(k_column_sum, dim3(nblocks(N, 64)), dim3(1024), 0, s, M, N, X, ldx, out);
   return hipGetLastError();
 }
 

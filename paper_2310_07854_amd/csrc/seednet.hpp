@@ -17,7 +17,7 @@ constexpr int SEED_T = 32;
 constexpr int SEED_TRAJ = SEED_T * SEED_J;                       // 224 values per seed
 constexpr int SEED_OUT = SEED_SLOTS * SEED_TRAJ;                 // 1792
 
-enum GemmEpilogue { GEMM_PLAIN = 0, GEMM_GELU = 1, GEMM_GELU_GRAD = 2 };
+enum GemmEpilogue { GEMM_PLAIN = 0, GEMM_GELU = 1, GEMM_GELU_GRAD = 2, GEMM_SEED_TRAJ = 3 };
 
 struct GemmArgs {
   int M, N, K;
@@ -31,6 +31,8 @@ struct GemmArgs {
   float* C;           // [M][ldc] FP32 result or null
   uint16_t* C16;      // [M][ldc] BF16 result or null
   int64_t ldc;
+  const float* start;  // [M][7] (GEMM_SEED_TRAJ only)
+  const float* goal;   // [M][7] (GEMM_SEED_TRAJ only)
 };
 
 struct AdamArgs {

@@ -841,7 +841,9 @@ int vapr_seed_features(int n, const float* start, const float* goal, const float
                        void* hip_stream) {
   if (n < 0) return fail(nullptr, VAPR_E_INVALID, "n < 0");
   if (n == 0) return VAPR_OK;
+  if (n > INT32_MAX / (SEED_IN_PAD / 8)) return fail(nullptr, VAPR_E_INVALID, "n too large");
   if (!start || !goal || !occ || !x) return fail(nullptr, VAPR_E_INVALID, "null pointer");
+  if (reinterpret_cast<uintptr_t>(x) % 16) return fail(nullptr, VAPR_E_INVALID, "x must be 16-byte aligned");
   hipError_t e = launch_features(static_cast<hipStream_t>(hip_stream), n, start, goal, occ, x);
   return e == hipSuccess ? VAPR_OK : hip_fail(nullptr, e, "k_features launch");
 }
@@ -861,7 +863,7 @@ int vapr_gemm_bf16(int M, int N, int K, const uint16_t* A, int64_t a_ms, int64_t
   if (M < 1 || N < 1 || K < 32 || K % 32) return fail(nullptr, VAPR_E_INVALID, "GEMM shape (K a multiple of 32)");
   if (!A || !B || (!C && !C_bf16)) return fail(nullptr, VAPR_E_INVALID, "null pointer");
   if (epilogue < VAPR_GEMM_PLAIN || epilogue > VAPR_GEMM_GELU_GRAD) return fail(nullptr, VAPR_E_INVALID, "epilogue");
-  if (epilogue != VAPR_GEMM_PLAIN && !aux) return fail(nullptr, VAPR_E_INVALID, "GELU epilogues need aux");
+  if (epilogue == VAPR_GEMM_GELU_GRAD && !aux) return fail(nullptr, VAPR_E_INVALID, "GELU_GRAD needs aux");
   if (ldc < N) return fail(nullptr, VAPR_E_INVALID, "ldc < N");
   const bool a_k = a_ks == 1, b_n = b_ns == 1;
   if (!(a_k || a_ms == 1) || !(b_n || b_ks == 1)) return fail(nullptr, VAPR_E_INVALID, "one stride of A and B must be 1");
@@ -869,9 +871,22 @@ int vapr_gemm_bf16(int M, int N, int K, const uint16_t* A, int64_t a_ms, int64_t
     return fail(nullptr, VAPR_E_INVALID, "k-contiguous A needs a row stride multiple of 8 and 16-byte alignment");
   if (!b_n && (b_ns % 8 || reinterpret_cast<uintptr_t>(B) % 16))
     return fail(nullptr, VAPR_E_INVALID, "k-contiguous B needs a column stride multiple of 8 and 16-byte alignment");
-  GemmArgs g{M, N, K, A, a_ms, a_ks, B, b_ks, b_ns, bias, epilogue, aux, C, C_bf16, ldc};
+  GemmArgs g{M, N, K, A, a_ms, a_ks, B, b_ks, b_ns, bias, epilogue, aux, C, C_bf16, ldc, nullptr, nullptr};
   hipError_t e = launch_gemm_bf16(static_cast<hipStream_t>(hip_stream), g, a_k, b_n);
   return e == hipSuccess ? VAPR_OK : hip_fail(nullptr, e, "k_gemm_bf16 launch");
+}
+
+int vapr_seed_head(int n, const uint16_t* a3, int64_t lda, const uint16_t* W4, const float* b4, const float* start,
+                   const float* goal, float* traj, void* hip_stream) {
+  if (n < 0) return fail(nullptr, VAPR_E_INVALID, "n < 0");
+  if (n == 0) return VAPR_OK;
+  if (!a3 || !W4 || !b4 || !start || !goal || !traj) return fail(nullptr, VAPR_E_INVALID, "null pointer");
+  if (lda < SEED_HID || lda % 8 || reinterpret_cast<uintptr_t>(a3) % 16)
+    return fail(nullptr, VAPR_E_INVALID, "a3 needs a row stride >= 256, a multiple of 8, and 16-byte alignment");
+  GemmArgs g{n, SEED_OUT, SEED_HID, a3, lda, 1, W4, SEED_OUT, 1, b4, GEMM_SEED_TRAJ, nullptr, traj, nullptr,
+             SEED_OUT, start, goal};
+  hipError_t e = launch_gemm_bf16(static_cast<hipStream_t>(hip_stream), g, true, true);
+  return e == hipSuccess ? VAPR_OK : hip_fail(nullptr, e, "k_gemm_bf16 (seed head) launch");
 }
 
 int vapr_seed_loss(int n, const float* y, const float* targets, const float* valid, int n_valid, double* loss,

@@ -73,8 +73,11 @@ def to_bf16(x: torch.Tensor) -> torch.Tensor:
 
 
 def column_sum(X: torch.Tensor, out: torch.Tensor) -> None:
+    """out[n] = sum_m X[m, n] for a float32 device matrix whose rows may be strided (unit column stride)."""
     M, N = X.shape
-    _call("vapr_column_sum", M, N, _dev(X, torch.float32, "X"), N, out.data_ptr(), _stream_handle())
+    if not X.is_cuda or X.dtype != torch.float32 or X.stride(1) != 1:
+        raise ValueError("X must be a float32 device matrix with unit column stride")
+    _call("vapr_column_sum", M, N, X.data_ptr(), X.stride(0), _dev(out, torch.float32, "out"), _stream_handle())
 
 
 def trajectories(y: torch.Tensor, start: torch.Tensor, goal: torch.Tensor) -> torch.Tensor:
@@ -120,16 +123,17 @@ class SeedNet:
         out["W1"] = out["W1"][:N_IN]
         return out
 
-    def forward(self, x: torch.Tensor) -> Tuple[torch.Tensor, dict]:
+    def forward(self, x: torch.Tensor, train: bool = True) -> Tuple[torch.Tensor, dict]:
         """y [n, 1792] float32 for input rows x [n, 544] bfloat16 (n a multiple of 32 for training,
-        any n >= 1 for inference), and the activations backward needs."""
+        any n >= 1 for inference), and the activations backward needs (train=False keeps none and
+        skips writing the pre-activations)."""
         n = x.shape[0]
         dev = x.device
         cache = {"a0": x}
         a = x
         k = N_IN_PAD
         for l in (1, 2, 3):
-            z = torch.empty(n, N_HID, dtype=torch.float32, device=dev)
+            z = torch.empty(n, N_HID, dtype=torch.float32, device=dev) if train else None
             a_next = torch.empty(n, N_HID, dtype=torch.bfloat16, device=dev)
             gemm(a, k, 1, self.view(self.w16, f"W{l}"), N_HID, 1, n, N_HID, k, bias=self.view(self.w, f"b{l}"),
                  epilogue=GELU, aux=z, C16=a_next)
@@ -188,7 +192,27 @@ class SeedNet:
         self.adam(lr)
         return loss
 
+    def hidden(self, x: torch.Tensor) -> torch.Tensor:
+        """The last hidden layer [n, 256] bfloat16 for input rows x [n, 544] (inference)."""
+        n = x.shape[0]
+        a, k = x, N_IN_PAD
+        for l in (1, 2, 3):
+            a_next = torch.empty(n, N_HID, dtype=torch.bfloat16, device=x.device)
+            gemm(a, k, 1, self.view(self.w16, f"W{l}"), N_HID, 1, n, N_HID, k, bias=self.view(self.w, f"b{l}"),
+                 epilogue=GELU, C16=a_next)
+            a, k = a_next, N_HID
+        return a
+
+    def head(self, a3: torch.Tensor, start: torch.Tensor, goal: torch.Tensor) -> torch.Tensor:
+        """Output layer fused with trajectory construction: [n, 8, 32, 7] seeds from a3 [n, 256]."""
+        n = a3.shape[0]
+        assert a3.dtype == torch.bfloat16 and a3.is_cuda and a3.stride(1) == 1
+        out = torch.empty(n, N_SEEDS, T_SEED, N_J, dtype=torch.float32, device=a3.device)
+        _call("vapr_seed_head", n, a3.data_ptr(), a3.stride(0), self.view(self.w16, "W4").data_ptr(),
+              self.view(self.w, "b4").data_ptr(), _dev(start, torch.float32, "start"),
+              _dev(goal, torch.float32, "goal"), out.data_ptr(), _stream_handle())
+        return out
+
     def seeds(self, start: torch.Tensor, goal: torch.Tensor, occ: torch.Tensor) -> torch.Tensor:
         """[n, 8, 32, 7] seed trajectories for problems (start, goal [n, 7], occ [n, 512])."""
-        y, _ = self.forward(features(start, goal, occ))
-        return trajectories(y, start, goal)
+        return self.head(self.hidden(features(start, goal, occ)), start, goal)

@@ -19,6 +19,7 @@ from .generators import (  # noqa: F401
     SEEDNET_LAYERS,
     SeedProblems,
     make_seednet_params,
+    make_seed_family,
     make_seed_problems,
     make_seed_inits,
 )

@@ -38,7 +38,8 @@ JOINT_LIMIT = 2.9
 Q_RANGE = 2.8
 
 # independent random streams split off the master seed
-_STREAMS = ("robot", "worlds", "configs", "trajectories", "calibration", "seednet", "seed_problems", "seed_inits")
+_STREAMS = ("robot", "worlds", "configs", "trajectories", "calibration", "seednet", "seed_problems", "seed_inits",
+            "seed_family")
 
 
 def _rng(seed: int, stream: str) -> np.random.Generator:
@@ -289,6 +290,25 @@ def make_seed_problems(n: int, n_cuboids: int, split: int = 0, seed: int = MASTE
     start = rng.uniform(-Q_RANGE, Q_RANGE, size=(n, N_JOINTS))
     goal = rng.uniform(-Q_RANGE, Q_RANGE, size=(n, N_JOINTS))
     return SeedProblems(worlds=Worlds(pose=_as_inputs(pose, False), half_ext=_as_inputs(h.reshape(n, n_cuboids, 3), False)),
+                        start=_as_inputs(start, False), goal=_as_inputs(goal, False))
+
+
+def make_seed_family(n: int, n_cuboids: int, family: int, split: int = 0, jitter: float = 0.05,
+                     seed: int = MASTER_SEED) -> SeedProblems:
+    """n problems in one environment: a base world of n_cuboids drawn once per `family` like the
+    benchmark worlds, each problem moving every cuboid centre by U[-jitter, jitter]^3 m, with start
+    and goal U[-2.8, 2.8]^7; `split` picks an independent set of problems in that environment."""
+    base = _split_rng(seed, "seed_family", 2 * family)
+    R = _random_rotations(base, n_cuboids)
+    c = base.uniform(-0.75, 0.75, size=(n_cuboids, 3))
+    h = 0.5 * base.uniform(0.05, 0.5, size=(n_cuboids, 3))
+    rng = _split_rng(seed, "seed_family", 2 * family + 1 + 2 * 1000 * (split + 1))
+    cj = c[None] + rng.uniform(-jitter, jitter, size=(n, n_cuboids, 3))
+    pose = np.concatenate([np.broadcast_to(R, (n, n_cuboids, 3, 3)), cj[..., None]], axis=3)
+    half = np.broadcast_to(h, (n, n_cuboids, 3))
+    start = rng.uniform(-Q_RANGE, Q_RANGE, size=(n, N_JOINTS))
+    goal = rng.uniform(-Q_RANGE, Q_RANGE, size=(n, N_JOINTS))
+    return SeedProblems(worlds=Worlds(pose=_as_inputs(pose, False), half_ext=_as_inputs(np.array(half), False)),
                         start=_as_inputs(start, False), goal=_as_inputs(goal, False))
 
 

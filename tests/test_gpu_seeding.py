@@ -55,7 +55,7 @@ def assert_bf16_in_band(codes: np.ndarray, ref: np.ndarray, band: np.ndarray):
 
 
 @pytest.mark.parametrize("a_k,b_n", [(True, True), (True, False), (False, True), (False, False)])
-@pytest.mark.parametrize("M,N,K", [(100, 80, 96), (64, 64, 32), (37, 200, 544), (256, 1792, 64)])
+@pytest.mark.parametrize("M,N,K", [(100, 80, 96), (64, 64, 32), (37, 200, 544), (256, 1792, 64), (45, 37, 64)])
 def test_gemm_layouts_and_tails(a_k, b_n, M, N, K):
     need_gpu()
     rng = np.random.default_rng(M * 7 + N + K)
@@ -107,6 +107,21 @@ def test_gemm_gelu_epilogues():
     assert np.all(np.abs(out2.cpu().numpy() - want) <= bandg)
 
 
+@pytest.mark.parametrize("M,N,ldx", [(1, 1, 1), (15, 63, 70), (100, 65, 65), (257, 256, 256), (256, 1792, 1800)])
+def test_column_sum_ragged(M, N, ldx):
+    """Bias gradients: FP32 column sums of a row-major [M][ldx] matrix, within M * 2^-24 * sum |x|
+    of the exact sum; the padding columns are never read into the result."""
+    need_gpu()
+    rng = np.random.default_rng(M * 7 + N)
+    X = F.fp32(rng.normal(size=(M, ldx))).astype(np.float64)
+    out = torch.full((N,), float("nan"), dtype=torch.float32, device="cuda:0")
+    S().column_sum(torch.tensor(X, dtype=torch.float32, device="cuda:0")[:, :N], out)
+    got = out.cpu().numpy().astype(np.float64)
+    ref = X[:, :N].sum(axis=0)
+    band = M * U32 * np.abs(X[:, :N]).sum(axis=0) + 1e-30
+    assert np.all(np.abs(got - ref) <= band)
+
+
 def test_occupancy_matches_oracle():
     need_gpu()
     pr = make_seed_problems(24, 20, split=5)
@@ -131,10 +146,50 @@ def test_occupancy_matches_oracle():
     assert not empty.any()
 
 
-def test_features_and_trajectories():
+@pytest.mark.parametrize("ldc_pad", [3, 4])
+def test_gemm_row_stride_keeps_padding(ldc_pad):
+    """Outputs with ldc > N (padded rows, odd and 16-byte multiple strides): every element equals the
+    ldc = N result bit for bit, including the GELU epilogue's pre-activation, and the padding columns
+    keep their contents."""
     need_gpu()
-    rng = np.random.default_rng(12)
-    n = 40
+    rng = np.random.default_rng(31 + ldc_pad)
+    M, N, K = 70, 72, 64
+    A = dev_bf16(rng.normal(size=(M, K)))
+    B = dev_bf16(rng.normal(size=(K, N)))
+    bias = torch.tensor(F.fp32(rng.normal(size=N)), dtype=torch.float32, device="cuda:0")
+    ldc = N + ldc_pad
+    ref_z = torch.empty(M, N, dtype=torch.float32, device="cuda:0")
+    ref_c = torch.empty(M, N, dtype=torch.float32, device="cuda:0")
+    S().gemm(A, K, 1, B, N, 1, M, N, K, bias=bias, epilogue=S().GELU, aux=ref_z, C=ref_c)
+    z = torch.full((M, ldc), 7.0, dtype=torch.float32, device="cuda:0")
+    c = torch.full((M, ldc), 7.0, dtype=torch.float32, device="cuda:0")
+    S().gemm(A, K, 1, B, N, 1, M, N, K, bias=bias, epilogue=S().GELU, aux=z, C=c, ldc=ldc)
+    np.testing.assert_array_equal(z[:, :N].cpu().numpy(), ref_z.cpu().numpy())
+    np.testing.assert_array_equal(c[:, :N].cpu().numpy(), ref_c.cpu().numpy())
+    assert bool((z[:, N:] == 7.0).all()) and bool((c[:, N:] == 7.0).all())
+
+
+@pytest.mark.parametrize("n,lda", [(1, 256), (100, 256), (257, 264)])
+def test_seed_head_equals_gemm_then_trajectories(n, lda):
+    """The fused output layer equals the plain GEMM followed by the trajectory kernel bit for bit
+    (ragged problem counts, a padded hidden-layer row stride)."""
+    need_gpu()
+    rng = np.random.default_rng(n)
+    net = S().SeedNet(make_seednet_params())
+    a3 = dev_bf16(rng.normal(size=(n, lda)))
+    start = torch.tensor(F.fp32(rng.uniform(-2.8, 2.8, size=(n, 7))), dtype=torch.float32, device="cuda:0")
+    goal = torch.tensor(F.fp32(rng.uniform(-2.8, 2.8, size=(n, 7))), dtype=torch.float32, device="cuda:0")
+    y = torch.empty(n, 1792, dtype=torch.float32, device="cuda:0")
+    S().gemm(a3, lda, 1, net.view(net.w16, "W4"), 1792, 1, n, 1792, 256, bias=net.view(net.w, "b4"), C=y)
+    ref = S().trajectories(y, start, goal).cpu().numpy()
+    got = net.head(a3[:, :256], start, goal).cpu().numpy()
+    np.testing.assert_array_equal(got.view(np.uint32), ref.view(np.uint32))
+
+
+@pytest.mark.parametrize("n", [1, 40, 1000])
+def test_features_and_trajectories(n):
+    need_gpu()
+    rng = np.random.default_rng(12 + n)
     start, goal = F.fp32(rng.uniform(-2.8, 2.8, size=(n, 7))), F.fp32(rng.uniform(-2.8, 2.8, size=(n, 7)))
     occ = (rng.random((n, 512)) < 0.3).astype(np.float32)
     d = lambda a: torch.tensor(np.asarray(a, dtype=np.float32), device="cuda:0")
