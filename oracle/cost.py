@@ -27,6 +27,18 @@ the point where the GPU path writes them; all other arithmetic stays FP64.  S is
 unquantised poses; the backward pass uses the quantised poses in stored mode and recomputes them
 from q in recompute mode.
 
+Swept collision (the fifth large tensor of trajectory optimisation, closest_pt_swept, Sec. III-C;
+the paper does not define the sweep).  Reading used here: between consecutive timesteps t and t+1
+of one trajectory-candidate each sphere centre moves on the straight segment between its two stored
+positions, sampled at k interior points u_i = i / (k + 1), i = 1..k:
+
+  p_i = (1 - u_i) p_s(t) + u_i p_s(t+1),     d_i = activation depth of p_i (as above)
+  swept cost of configuration t   (w_sw / k) sum_s sum_i d_i^2       (0 for the last timestep)
+  swept gradient X_s(t)           d/dp_s(t) of the sum over all segments: the segment (t, t+1)
+                                  with weights (1 - u_i), the segment (t-1, t) with weights u_i
+
+and it is stored as its own tensor X (format of its own), added to G in the backward pass.
+
 Parity pins (tests/test_oracle_cost.py): adjoint == explicit Jacobian to 1e-12; joint gradient ==
 central differences of the trajectory cost; sphere gradient == central differences of the
 configuration cost; self pair closed form; hand-computed single-sphere cases; at f32 with emulation
@@ -45,6 +57,7 @@ from .kinematics import (N_JOINTS, forward_kinematics, joint_axes, link_pose_val
                          sphere_positions)
 
 TENSORS = ("link_poses", "sphere_pos", "sphere_dist", "sphere_grad", "joint_grad")
+SWEPT = "swept_grad"
 
 
 @dataclass
@@ -54,6 +67,8 @@ class CostParams:
     w_self: float = 100.0
     w_bound: float = 10.0
     w_smooth: float = 1.0
+    swept_steps: int = 0       # k interior samples per segment; 0 turns the swept term off
+    w_swept: float = 100.0
 
 
 @dataclass
@@ -66,6 +81,7 @@ class Precision:
     sphere_grad: Tuple[str, int] = ("f32", 0)
     joint_grad: Tuple[str, int] = ("f32", 0)
     recompute_poses: bool = False
+    swept_grad: Tuple[str, int] = ("f32", 0)
 
     def get(self, tensor: str) -> Tuple[str, int]:
         return getattr(self, tensor)
@@ -122,6 +138,35 @@ def self_term(S: np.ndarray, radius: np.ndarray, pairs: np.ndarray, eta: float):
         grad[:, a[p]] += ga[:, p]
         grad[:, b[p]] -= ga[:, p]
     return cost, grad, np.min(dist, axis=1) if pairs.shape[0] else np.full(B, np.inf)
+
+
+def swept_term(S: np.ndarray, radius: np.ndarray, pose: np.ndarray, half_ext: np.ndarray,
+               world_of_cfg: np.ndarray, eta: float, T: int, k: int):
+    """Unweighted swept term for configurations laid out with timestep fastest in runs of T.
+    Returns the per-configuration cost (1/k) sum_s sum_i d_i^2 of the segment (t, t+1) [B], its
+    gradient summed over both segments at each configuration [B, n_s, 3] and the smallest kink
+    margin of any sample point of either segment [B]."""
+    B, n_s, _ = S.shape
+    cost = np.zeros(B)
+    X = np.zeros((B, n_s, 3))
+    margin = np.full(B, np.inf)
+    t = np.arange(B) % T
+    seg = np.nonzero(t < T - 1)[0]                    # segment starts
+    if k <= 0 or seg.size == 0:
+        return cost, X, margin
+    P0, P1 = S[seg], S[seg + 1]
+    for i in range(1, k + 1):
+        u = i / (k + 1)
+        Pi = (1.0 - u) * P0 + u * P1
+        d, gdir, _, mg = world_term(Pi, radius, pose, half_ext, world_of_cfg[seg], eta)
+        cost[seg] += np.sum(d * d, axis=1) / k
+        g = np.where(d[..., None] > 0, (-2.0 / k) * d[..., None] * gdir, 0.0)
+        X[seg] += (1.0 - u) * g
+        X[seg + 1] += u * g
+        m = np.min(mg, axis=1)
+        margin[seg] = np.minimum(margin[seg], m)
+        margin[seg + 1] = np.minimum(margin[seg + 1], m)
+    return cost, X, margin
 
 
 def bound_term(q: np.ndarray, q_lo: np.ndarray, q_hi: np.ndarray):
@@ -216,9 +261,21 @@ def fwd_bwd(robot, worlds, q: np.ndarray, traj_per_world: int, T: int, n_ls: int
         bcost_st = fmts.fp32(bcost).astype(np.float64)
     else:
         scost_st, bcost_st = params.w_self * scost, bcost
+    swept = params.swept_steps > 0
+    if swept:
+        wcost, Xs, wmargin = swept_term(S_hat, robot.sphere_radius, worlds.pose, worlds.half_ext, wid, eta, T,
+                                        params.swept_steps)
+        X = params.w_swept * Xs
+        out["X_codes"], X_hat = _store(X, prec, SWEPT)
+        wcost_st = params.w_swept * wcost
+        if prec is not None and emulate_scalars:
+            wcost_st = fmts.fp32(wcost_st).astype(np.float64)
+        out.update(X=X, X_hat=X_hat, swept_cost=wcost_st, swept_margin=wmargin)
+    else:
+        X_hat, wcost_st = 0.0, 0.0
 
     # (4) aggregation
-    cfg = params.w_coll * np.sum(D_hat * D_hat, axis=1) + scost_st + params.w_bound * bcost_st
+    cfg = params.w_coll * np.sum(D_hat * D_hat, axis=1) + scost_st + params.w_bound * bcost_st + wcost_st
     smooth, sgr = smoothness_grad(q, T, n_ls)
     cost_traj = cfg.reshape(n_tc, T).sum(axis=1) + params.w_smooth * smooth
 
@@ -228,7 +285,7 @@ def fwd_bwd(robot, worlds, q: np.ndarray, traj_per_world: int, T: int, n_ls: int
         Pb = sphere_positions(Tb, robot.sphere_center, robot.sphere_link)
     else:
         Tb, Pb = Tk, S
-    Jsph = joint_grad_adjoint(Tb, Pb, G_hat, robot.sphere_link)
+    Jsph = joint_grad_adjoint(Tb, Pb, G_hat + X_hat, robot.sphere_link)
     up = np.ones(n_tc) if upstream is None else np.asarray(upstream, dtype=np.float64)
     J = up.repeat(T)[:, None] * (Jsph + params.w_bound * bgrad + params.w_smooth * sgr)
     out["J_codes"], J_hat = _store(J, prec, "joint_grad")
