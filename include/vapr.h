@@ -35,7 +35,7 @@
 extern "C" {
 #endif
 
-#define VAPR_ABI_VERSION 1
+#define VAPR_ABI_VERSION 2
 
 typedef enum {
   VAPR_OK = 0,
@@ -80,20 +80,33 @@ typedef struct {
   vapr_tensor_format sphere_grad;  /* G: d(config cost)/d(sphere centre), n_s x 3               */
   vapr_tensor_format joint_grad;   /* J: d(loss)/dq, 7 per config                               */
   int32_t recompute_poses;
+  vapr_tensor_format swept_grad;   /* X: swept-term gradient w.r.t. the sphere centres, n_s x 3
+                                      (stored only while swept_steps > 0)                       */
 } vapr_precision;
 
 /* Cost weights (Sec. III-B step (3); the paper gives no values).
  * configuration cost c = w_coll * sum_s d_s^2 + w_self * sum_pairs max(0, eta - e)^2
  *                        + w_bound * sum_j (max(0, q_j - hi_j)^2 + max(0, lo_j - q_j)^2)
+ *                        + swept cost of the segment (t, t+1)
  * trajectory cost      = sum_t c_t + w_smooth * sum_t |q_{t+1} - q_t|^2
  * with d_s = max(0, eta - min_k(sd_k(p_s) - r_s)) and e = |p_a - p_b| - r_a - r_b.
- * Defaults: eta 0.02 m, w_coll 100, w_self 100, w_bound 10, w_smooth 1. */
+ * Swept term (the swept collision of trajectory optimisation, whose output is the paper's fifth
+ * large tensor, Sec. III-C; the paper does not define the sweep): with k = swept_steps > 0, each
+ * sphere centre is sampled at p_j = (1 - u_j) p_s(t) + u_j p_s(t+1), u_j = j / (k + 1), j = 1..k,
+ * between the stored positions of consecutive timesteps of one trajectory-candidate, and the
+ * segment adds (w_swept / k) sum_s sum_j d(p_j)^2 to configuration t (nothing for the last
+ * timestep).  Its gradient w.r.t. the sphere centres, summed over the two segments at each
+ * timestep, is the stored tensor X; the backward pass adds it to G.
+ * Defaults: eta 0.02 m, w_coll 100, w_self 100, w_bound 10, w_smooth 1, swept_steps 0 (off),
+ * w_swept 100.  0 <= swept_steps <= 16.  Changing swept_steps changes the workspace size. */
 typedef struct {
   float eta;
   float w_coll;
   float w_self;
   float w_bound;
   float w_smooth;
+  int32_t swept_steps;
+  float w_swept;
 } vapr_cost_params;
 
 typedef struct vapr_ctx vapr_ctx;
@@ -165,7 +178,8 @@ int vapr_get_culling_grid(vapr_ctx* ctx, int world, vapr_grid_info* info, uint32
                           size_t capacity_words);
 
 /* Bytes of device workspace a forward/backward pass of this batch shape needs at the current
- * precision (holds L, S, D, G, J and two FP32 scalars per configuration).  Requires a robot. */
+ * precision and swept setting (holds L, S, D, G, J and two FP32 scalars per configuration, plus X
+ * and a third scalar while swept_steps > 0).  Requires a robot. */
 int vapr_workspace_size(const vapr_ctx* ctx, int n_worlds, int traj_per_world, int T, int n_ls,
                         size_t* bytes);
 
@@ -314,7 +328,9 @@ typedef enum {
   VAPR_T_SPHERE_GRAD = 3,  /* codes, [B][n_s][3]                                           */
   VAPR_T_JOINT_GRAD = 4,   /* codes, [B][7]                                                */
   VAPR_T_SELF_COST = 5,    /* FP32 [B]: w_self * sum over pairs of max(0, eta - e)^2       */
-  VAPR_T_BOUND_COST = 6    /* FP32 [B]: unweighted joint-limit cost                        */
+  VAPR_T_BOUND_COST = 6,   /* FP32 [B]: unweighted joint-limit cost                        */
+  VAPR_T_SWEPT_GRAD = 7,   /* codes, [B][n_s][3]            (swept_steps > 0 only)          */
+  VAPR_T_SWEPT_COST = 8    /* FP32 [B]: swept cost of the segment (t, t+1)  (idem)         */
 } vapr_tensor;
 
 /* Copy one stored tensor between a workspace and a dense buffer in canonical element order, in the
@@ -333,7 +349,8 @@ int vapr_cost_fwd_from(vapr_ctx* ctx, int first, int n_worlds, int traj_per_worl
 
 /* Per-kernel timing with HIP events recorded around each launch on the context's stream.
  * enable != 0 starts recording (and clears totals); vapr_profile_read synchronises the stream and
- * returns, per kernel id (0 fk, 1 sphere_cost, 2 reduce, 3 adjoint, 4 optimizer, 5 codec, 6 repack),
+ * returns, per kernel id (0 fk, 1 sphere_cost, 2 reduce, 3 adjoint, 4 optimizer, 5 codec, 6 repack,
+ * 7 swept),
  * the summed milliseconds and launch counts for up to n_ids ids. */
 int vapr_profile_enable(vapr_ctx* ctx, int enable);
 int vapr_profile_read(vapr_ctx* ctx, double* total_ms, int64_t* launches, int n_ids);

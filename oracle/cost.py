@@ -117,7 +117,9 @@ def world_term(S: np.ndarray, radius: np.ndarray, pose: np.ndarray, half_ext: np
         d[idx] = np.maximum(0.0, eta - best)
         grad[idx] = bgrad
         kstar[idx] = bk
-        margin[idx] = np.minimum(second - best, bgap)
+        # no runner-up (fewer than two cuboids): no switch to guard against
+        gap2 = np.where(np.isfinite(second), second - best, np.inf)
+        margin[idx] = np.minimum(gap2, bgap)
     return d, grad, kstar, margin
 
 
@@ -145,7 +147,8 @@ def swept_term(S: np.ndarray, radius: np.ndarray, pose: np.ndarray, half_ext: np
     """Unweighted swept term for configurations laid out with timestep fastest in runs of T.
     Returns the per-configuration cost (1/k) sum_s sum_i d_i^2 of the segment (t, t+1) [B], its
     gradient summed over both segments at each configuration [B, n_s, 3] and the smallest kink
-    margin of any sample point of either segment [B]."""
+    margin of any active sample point (d > 0) of either segment [B]; inactive samples contribute
+    nothing to the gradient, so their kinks do not matter."""
     B, n_s, _ = S.shape
     cost = np.zeros(B)
     X = np.zeros((B, n_s, 3))
@@ -163,7 +166,7 @@ def swept_term(S: np.ndarray, radius: np.ndarray, pose: np.ndarray, half_ext: np
         g = np.where(d[..., None] > 0, (-2.0 / k) * d[..., None] * gdir, 0.0)
         X[seg] += (1.0 - u) * g
         X[seg + 1] += u * g
-        m = np.min(mg, axis=1)
+        m = np.min(np.where(d > 0, mg, np.inf), axis=1)
         margin[seg] = np.minimum(margin[seg], m)
         margin[seg + 1] = np.minimum(margin[seg + 1], m)
     return cost, X, margin

@@ -15,9 +15,10 @@ F32, F16, BF16, E4M3, E5M2, E3M2, E2M1 = range(7)
 FORMAT_IDS = {"f32": F32, "f16": F16, "bf16": BF16, "e4m3": E4M3, "e5m2": E5M2, "e3m2": E3M2, "e2m1": E2M1}
 FORMAT_BITS = {F32: 32, F16: 16, BF16: 16, E4M3: 8, E5M2: 8, E3M2: 6, E2M1: 4}
 T_LINK_POSES, T_SPHERE_POS, T_SPHERE_DIST, T_SPHERE_GRAD, T_JOINT_GRAD, T_SELF_COST, T_BOUND_COST = range(7)
+ABI_VERSION = 2  # the structs below match include/vapr.h at this version
 TENSOR_IDS = {"link_poses": 0, "sphere_pos": 1, "sphere_dist": 2, "sphere_grad": 3, "joint_grad": 4,
-              "self_cost": 5, "bound_cost": 6}
-KERNEL_NAMES = ("fk", "sphere_cost", "reduce", "adjoint", "optimizer", "codec", "repack")
+              "self_cost": 5, "bound_cost": 6, "swept_grad": 7, "swept_cost": 8}
+KERNEL_NAMES = ("fk", "sphere_cost", "reduce", "adjoint", "optimizer", "codec", "repack", "swept")
 
 
 class VaprError(RuntimeError):
@@ -32,12 +33,14 @@ class TensorFormat(ctypes.Structure):
 
 class PrecisionC(ctypes.Structure):
     _fields_ = [("link_poses", TensorFormat), ("sphere_pos", TensorFormat), ("sphere_dist", TensorFormat),
-                ("sphere_grad", TensorFormat), ("joint_grad", TensorFormat), ("recompute_poses", ctypes.c_int32)]
+                ("sphere_grad", TensorFormat), ("joint_grad", TensorFormat), ("recompute_poses", ctypes.c_int32),
+                ("swept_grad", TensorFormat)]
 
 
 class CostParamsC(ctypes.Structure):
     _fields_ = [("eta", ctypes.c_float), ("w_coll", ctypes.c_float), ("w_self", ctypes.c_float),
-                ("w_bound", ctypes.c_float), ("w_smooth", ctypes.c_float)]
+                ("w_bound", ctypes.c_float), ("w_smooth", ctypes.c_float), ("swept_steps", ctypes.c_int32),
+                ("w_swept", ctypes.c_float)]
 
 
 class GridInfoC(ctypes.Structure):
@@ -116,6 +119,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         fn = getattr(lib, name)
         fn.restype = res
         fn.argtypes = args
+    if lib.vapr_abi_version() != ABI_VERSION:
+        raise ImportError(f"{path} implements ABI {lib.vapr_abi_version()}, these bindings ABI {ABI_VERSION}; "
+                          "rebuild it")
     _lib = lib
     return lib
 

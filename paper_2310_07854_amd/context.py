@@ -66,9 +66,13 @@ class Shape:
         return (self.n_worlds, self.traj_per_world, self.T, self.n_ls)
 
 
+STORED = TENSORS + ("swept_grad",)
+SCALARS = ("self_cost", "bound_cost", "swept_cost")
+
+
 def precision_struct(spec: Mapping[str, FormatSpec], recompute_poses: bool = False) -> L.PrecisionC:
     p = L.PrecisionC()
-    for name in TENSORS:
+    for name in STORED:
         v = spec.get(name, "f32")
         fmt, k = (v, 0) if isinstance(v, str) else v
         setattr(p, name, L.TensorFormat(L.FORMAT_IDS[fmt], int(k)))
@@ -89,8 +93,8 @@ class Context:
         self.n_spheres = 0
         # the library's defaults (eta as the FP32 value the kernels compare with)
         self.cost_params = {"eta": float(np.float32(0.02)), "w_coll": 100.0, "w_self": 100.0, "w_bound": 10.0,
-                            "w_smooth": 1.0}
-        self.precision: Dict[str, Tuple[str, int]] = {t: ("f32", 0) for t in TENSORS}
+                            "w_smooth": 1.0, "swept_steps": 0, "w_swept": 100.0}
+        self.precision: Dict[str, Tuple[str, int]] = {t: ("f32", 0) for t in STORED}
         self.recompute_poses = False
 
     # -- lifetime ----------------------------------------------------------------------------
@@ -135,14 +139,17 @@ class Context:
         p = precision_struct(spec, recompute_poses)
         self._call("vapr_set_precision", ctypes.byref(p))
         self.precision = {t: ((spec.get(t, "f32"), 0) if isinstance(spec.get(t, "f32"), str) else tuple(spec[t]))
-                          for t in TENSORS}
+                          for t in STORED}
         self.recompute_poses = recompute_poses
 
-    def set_cost_params(self, eta=0.02, w_coll=100.0, w_self=100.0, w_bound=10.0, w_smooth=1.0) -> None:
-        p = L.CostParamsC(eta, w_coll, w_self, w_bound, w_smooth)
+    def set_cost_params(self, eta=0.02, w_coll=100.0, w_self=100.0, w_bound=10.0, w_smooth=1.0,
+                        swept_steps: int = 0, w_swept: float = 100.0) -> None:
+        """Cost weights; swept_steps > 0 turns on the swept term with that many samples per
+        segment (the workspace then also holds the swept gradient and cost)."""
+        p = L.CostParamsC(eta, w_coll, w_self, w_bound, w_smooth, int(swept_steps), w_swept)
         self._call("vapr_set_cost_params", ctypes.byref(p))
         self.cost_params = {"eta": float(p.eta), "w_coll": w_coll, "w_self": w_self, "w_bound": w_bound,
-                            "w_smooth": w_smooth}
+                            "w_smooth": w_smooth, "swept_steps": int(swept_steps), "w_swept": w_swept}
 
     def set_culling(self, enable: bool) -> None:
         """Exact cuboid culling in the sphere-cost stage (on by default; results are identical)."""
@@ -198,11 +205,12 @@ class Context:
     # -- stored tensors --------------------------------------------------------------------------
     def tensor_count(self, name: str) -> int:
         return {"link_poses": 96, "sphere_pos": 3 * self.n_spheres, "sphere_dist": self.n_spheres,
-                "sphere_grad": 3 * self.n_spheres, "joint_grad": 7, "self_cost": 1, "bound_cost": 1}[name]
+                "sphere_grad": 3 * self.n_spheres, "joint_grad": 7, "self_cost": 1, "bound_cost": 1,
+                "swept_grad": 3 * self.n_spheres, "swept_cost": 1}[name]
 
     def tensor_nbytes(self, name: str, shape: Shape) -> int:
         n = shape.B * self.tensor_count(name)
-        if name in ("self_cost", "bound_cost"):
+        if name in SCALARS:
             return 4 * n
         fmt = L.FORMAT_IDS[self.precision[name][0]]
         return int(self._lib.vapr_packed_bytes(fmt, n))
@@ -214,7 +222,7 @@ class Context:
         self._call("vapr_ws_export", *shape.args(), _dev(ws, torch.uint8, "ws"), ws.numel(), L.TENSOR_IDS[name],
                    out.data_ptr(), out.numel())
         out = out[:nb]
-        return out.view(torch.float32) if name in ("self_cost", "bound_cost") else out
+        return out.view(torch.float32) if name in SCALARS else out
 
     def ws_import(self, name: str, ws: torch.Tensor, shape: Shape, data: torch.Tensor) -> None:
         data = data.contiguous()

@@ -1,6 +1,8 @@
 // HIP kernels for gfx950 of one trajectory-optimisation iteration (Sec. III-B):
 //   k_fk          step (2) forward kinematics -> link poses L, sphere centres S, bound cost
 //   k_sphere_cost step (3) world (oriented cuboids) and self-pair costs -> distances D, gradients G
+//   k_swept       step (3), trajectory optimisation: swept world term between consecutive
+//                 timesteps -> swept gradients X, swept cost
 //   k_reduce      step (4) aggregation into FP64 trajectory-candidate costs
 //   k_adjoint     step (5) reverse accumulation down the chain -> joint gradients J
 //   k_optimizer   steps (6), (7), (1): line-search selection, L-BFGS update, next candidates
@@ -737,6 +739,128 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3))) void k
   }
 }
 
+// ---- swept sphere collision (the swept world term of trajectory optimisation) --------------------
+//
+// Between consecutive timesteps of one trajectory-candidate each sphere centre moves on the straight
+// segment between its two stored positions, sampled at u_j = j / (k + 1), j = 1..k.  The segment
+// (t, t+1) adds (w_sw / k) sum_s sum_j d_j^2 to configuration t, and its gradient goes to both ends
+// with weights (1 - u_j) and u_j.
+//
+// A wavefront owns 63 consecutive configurations c = 63 W + lane (lanes 0..62); each of those lanes
+// evaluates the segment (c, c + 1), and lane 63 evaluates (63 W - 1, 63 W), the segment that ends at
+// lane 0.  Every segment is thus evaluated once (64 lanes for 63 configurations), and the gradient
+// at the far end moves one lane up with a cross-lane permute: configuration c receives its own
+// segment's near-end gradient plus the far-end gradient of the segment (c - 1, c), with no atomics
+// and in a fixed order.  Spheres go eight at a time against the world's cuboids (closest cuboid by
+// the same comparison key as the discrete term, exact distance and gradient for the winner).
+template <int FS>
+__global__ __launch_bounds__(256) void k_swept(RobotArgs R, WorldArgs W, TV S, TV X, float* __restrict__ sweptc,
+                                               ShapeArgs sh, CostArgs cp) {
+  const int lane = threadIdx.x & 63;
+  const int64_t wv = (int64_t)blockIdx.x * 4 + uniform(threadIdx.x >> 6);
+  const int64_t first = wv * 63;
+  if (first >= sh.B) return;  // whole wavefront: its own configurations and lane 63's segment lie past B
+  const int64_t c = first + lane;                       // own configuration (lanes 0..62)
+  const int64_t a = lane < 63 ? c : first - 1;          // segment start
+  const bool seg = a >= 0 && a + 1 < sh.B && (a % sh.T) != sh.T - 1;
+  const bool own = lane < 63 && c < sh.B;
+  const int64_t a_lo = first > 0 ? first - 1 : 0;
+  const int64_t a_hi = (first + 62 < sh.B ? first + 62 : sh.B - 1);
+  const int w_lo = uniform((int)(a_lo / sh.cfg_per_world));
+  const int w_hi = uniform((int)(a_hi / sh.cfg_per_world));
+  const int my_w = (int)((a >= 0 ? a : 0) / sh.cfg_per_world);
+  const int K = uniform(W.K);
+  const int ng = uniform(R.n_groups);
+  const int n_s = uniform(R.n_s);
+  const int k_sw = uniform(cp.k_sw);
+  const float coef_base = -2.f * cp.w_sw / (float)k_sw;
+  const int src = ((lane + 63) & 63) << 2;              // ds_bpermute address of lane - 1
+  const uint32_t* b0 = lane_base(S, seg ? a : 0);
+  const uint32_t* b1 = lane_base(S, seg ? a + 1 : 0);
+  float cost = 0.f;
+
+  for (int g = 0; g < ng; ++g) {
+    float xg[SPH_GROUP], yg[SPH_GROUP], zg[SPH_GROUP];
+    const int active = uniform(min(SPH_GROUP, n_s - g * SPH_GROUP));
+    for (int h = 0; h < SPH_GROUP; h += 8) {
+      float p0[3][8], dp[3][8], lo[3][8], hi[3][8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+#pragma unroll
+        for (int q = 0; q < 3; ++q) {
+          float v0 = 0.f, v1 = 0.f;
+          if (seg && h + i < active) {
+            v0 = load_elem_at<FS, SPH_GROUP>(b0, g * 3 + q, h + i, S.scale);
+            v1 = load_elem_at<FS, SPH_GROUP>(b1, g * 3 + q, h + i, S.scale);
+          }
+          p0[q][i] = v0;
+          dp[q][i] = v1 - v0;
+          lo[q][i] = hi[q][i] = 0.f;
+        }
+      }
+      if (h < active) {
+        for (int j = 1; j <= k_sw; ++j) {
+          const float u = (float)j / (float)(k_sw + 1);
+          float px[SPH_GROUP], py[SPH_GROUP], pz[SPH_GROUP], best[SPH_GROUP];
+          int bk[SPH_GROUP];
+#pragma unroll
+          for (int i = 0; i < SPH_GROUP; ++i) {
+            const int ii = i < 8 ? i : 0;
+            px[i] = fmaf(u, dp[0][ii], p0[0][ii]);
+            py[i] = fmaf(u, dp[1][ii], p0[1][ii]);
+            pz[i] = fmaf(u, dp[2][ii], p0[2][ii]);
+            best[i] = INFINITY;
+            bk[i] = 0;
+          }
+          for (int w = w_lo; w <= w_hi; ++w) {
+            if (my_w != w || !seg) continue;
+            const cptr<float> wbox = as_const(W.box) + (int64_t)uniform(w) * K * 16;
+            closest_cuboids<8>(wbox, K, px, py, pz, best, bk);
+          }
+          if (seg && K > 0) {
+            const float* mybox = W.box + (int64_t)my_w * K * 16;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+              if (h + i >= active) continue;
+              float sd, nx, ny, nz;
+              cuboid_sd_grad(mybox + bk[i] * 16, px[i], py[i], pz[i], sd, nx, ny, nz);
+              const float r = sphere_of(R.sph, g * SPH_GROUP + h + i).w;
+              const float d = fmaxf(cp.eta - (sd - r), 0.f);
+              if (d > 0.f) {
+                cost = fmaf(d, d, cost);
+                const float cf = coef_base * d;
+                const float gx = cf * nx, gy = cf * ny, gz = cf * nz;
+                lo[0][i] = fmaf(1.f - u, gx, lo[0][i]);
+                lo[1][i] = fmaf(1.f - u, gy, lo[1][i]);
+                lo[2][i] = fmaf(1.f - u, gz, lo[2][i]);
+                hi[0][i] = fmaf(u, gx, hi[0][i]);
+                hi[1][i] = fmaf(u, gy, hi[1][i]);
+                hi[2][i] = fmaf(u, gz, hi[2][i]);
+              }
+            }
+          }
+        }
+      }
+      // far-end gradient of the segment (c - 1, c) from lane - 1 (lane 63 for lane 0)
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const float fx = __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(hi[0][i])));
+        const float fy = __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(hi[1][i])));
+        const float fz = __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(hi[2][i])));
+        xg[h + i] = lo[0][i] + fx;
+        yg[h + i] = lo[1][i] + fy;
+        zg[h + i] = lo[2][i] + fz;
+      }
+    }
+    if (own) {
+      store_group<SPH_GROUP>(X, c, g * 3 + 0, xg);
+      store_group<SPH_GROUP>(X, c, g * 3 + 1, yg);
+      store_group<SPH_GROUP>(X, c, g * 3 + 2, zg);
+    }
+  }
+  if (own) sweptc[c] = (cp.w_sw / (float)k_sw) * cost;
+}
+
 // ---- K3: aggregation -----------------------------------------------------------------------------
 
 // ---- wavefront reductions: DPP steps inside each 16-lane row, then the four row results added in
@@ -773,7 +897,8 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 __global__ __launch_bounds__(256) void k_reduce(TV D, const float* __restrict__ selfc,
-                                                const float* __restrict__ boundc, const float* __restrict__ q,
+                                                const float* __restrict__ boundc, const float* __restrict__ sweptc,
+                                                const float* __restrict__ q,
                                                 double* __restrict__ cost_traj, float* __restrict__ cost_cfg,
                                                 ShapeArgs sh, CostArgs cp, int n_s) {
   const int64_t tc = (int64_t)blockIdx.x * 4 + uniform(threadIdx.x >> 6);
@@ -795,7 +920,8 @@ __global__ __launch_bounds__(256) void k_reduce(TV D, const float* __restrict__ 
         for (int i = 0; i < SPH_GROUP; ++i)
           if (i < active) sq = fma((double)dv[i], (double)dv[i], sq);
       }
-      const double c = (double)cp.w_c * sq + (double)selfc[b] + (double)cp.w_b * (double)boundc[b];
+      double c = (double)cp.w_c * sq + (double)selfc[b] + (double)cp.w_b * (double)boundc[b];
+      if (sweptc) c += (double)sweptc[b];
       if (cost_cfg) cost_cfg[b] = (float)c;
       double sm = 0.0;
       if (t + 1 < T) {
@@ -816,9 +942,10 @@ __global__ __launch_bounds__(256) void k_reduce(TV D, const float* __restrict__ 
 
 // Force and moment (about the world origin) of the sphere gradients on link l: spheres of the link
 // are visited in increasing index over the groups that hold them, with G decoded a group at a time.
-template <int FG>
-__device__ __forceinline__ void link_wrench(const RobotArgs& R, const uint32_t* gbase, float gscale, int l,
-                                            const float (&T)[LINK_VALUES], float (&f)[3], float (&m)[3]) {
+template <int FG, bool HAS_X>
+__device__ __forceinline__ void link_wrench(const RobotArgs& R, const uint32_t* gbase, float gscale, const TV& X,
+                                            const uint32_t* xbase, int l, const float (&T)[LINK_VALUES],
+                                            float (&f)[3], float (&m)[3]) {
   const cptr<int> lg = as_const(R.link_groups) + 2 * l;
   const int g_lo = lg[0], g_hi = lg[1];
   for (int g = g_lo; g < g_hi; ++g) {
@@ -826,6 +953,19 @@ __device__ __forceinline__ void link_wrench(const RobotArgs& R, const uint32_t* 
     load_group_at<FG, SPH_GROUP>(gbase, g * 3 + 0, gscale, gx);
     load_group_at<FG, SPH_GROUP>(gbase, g * 3 + 1, gscale, gy);
     load_group_at<FG, SPH_GROUP>(gbase, g * 3 + 2, gscale, gz);
+    if constexpr (HAS_X) {
+      // the swept gradient, stored in a tensor of its own, adds to the sphere gradient
+      float vx[SPH_GROUP], vy[SPH_GROUP], vz[SPH_GROUP];
+      load_group_fmt<SPH_GROUP>(X.fmt, xbase, g * 3 + 0, X.scale, vx);
+      load_group_fmt<SPH_GROUP>(X.fmt, xbase, g * 3 + 1, X.scale, vy);
+      load_group_fmt<SPH_GROUP>(X.fmt, xbase, g * 3 + 2, X.scale, vz);
+#pragma unroll
+      for (int i = 0; i < SPH_GROUP; ++i) {
+        gx[i] += vx[i];
+        gy[i] += vy[i];
+        gz[i] += vz[i];
+      }
+    }
 #pragma unroll
     for (int i = 0; i < SPH_GROUP; ++i) {
       const int s = g * SPH_GROUP + i;
@@ -847,8 +987,8 @@ __device__ __forceinline__ void link_wrench(const RobotArgs& R, const uint32_t* 
 // (decoded from L by wavefronts 0-1, or recomputed by wavefront 0); phase 2 gives each wavefront
 // links w+1 and w+5 and leaves their force and moment in LDS; phase 3 (wavefront 0) sums them from
 // the tip to the base into the joint gradients.
-template <int FG>
-__global__ __launch_bounds__(256) void k_adjoint(const float* __restrict__ q, RobotArgs R, TV L, TV G, TV J,
+template <int FG, bool HAS_X>
+__global__ __launch_bounds__(256) void k_adjoint(const float* __restrict__ q, RobotArgs R, TV L, TV G, TV X, TV J,
                                                  const double* __restrict__ up, float* __restrict__ grad_q,
                                                  ShapeArgs sh, CostArgs cp, int recompute) {
   __shared__ float tile[TILE_POSE_WORDS];
@@ -877,11 +1017,12 @@ __global__ __launch_bounds__(256) void k_adjoint(const float* __restrict__ q, Ro
   __syncthreads();
 
   const uint32_t* gbase = lane_base(G, b);
+  const uint32_t* xbase = HAS_X ? lane_base(X, b) : nullptr;
   for (int l = wave + 1; l <= N_FIXED; l += 4) {
     float T[LINK_VALUES];
     pose_from_tile(tile, l, lane, T);
     float f[3] = {0.f, 0.f, 0.f}, m[3] = {0.f, 0.f, 0.f};
-    if (live) link_wrench<FG>(R, gbase, G.scale, l, T, f, m);
+    if (live) link_wrench<FG, HAS_X>(R, gbase, G.scale, X, xbase, l, T, f, m);
     float* w = wrench + (l - 1) * 6 * 64 + lane;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
@@ -1380,19 +1521,39 @@ hipError_t launch_sphere_cost_blk(hipStream_t s, const RobotArgs& R, const World
   return hipGetLastError();
 }
 
-hipError_t launch_reduce(hipStream_t s, const TV& D, const float* selfc, const float* boundc, const float* q,
-                         double* cost_traj, float* cost_cfg, const ShapeArgs& sh, const CostArgs& cp, int n_s) {
-  hipLaunchKernelGGL(k_reduce, dim3(blocks_for(sh.n_tc, 4)), dim3(256), 0, s, D, selfc, boundc, q, cost_traj,
-                     cost_cfg, sh, cp, n_s);
+hipError_t launch_reduce(hipStream_t s, const TV& D, const float* selfc, const float* boundc, const float* sweptc,
+                         const float* q, double* cost_traj, float* cost_cfg, const ShapeArgs& sh, const CostArgs& cp,
+                         int n_s) {
+  hipLaunchKernelGGL(k_reduce, dim3(blocks_for(sh.n_tc, 4)), dim3(256), 0, s, D, selfc, boundc, sweptc, q,
+                     cost_traj, cost_cfg, sh, cp, n_s);
   return hipGetLastError();
 }
 
-hipError_t launch_adjoint(hipStream_t s, const float* q, const RobotArgs& R, const TV& L, const TV& G, const TV& J,
-                          const double* up, float* grad_q, const ShapeArgs& sh, const CostArgs& cp, int recompute) {
+hipError_t launch_swept(hipStream_t s, const RobotArgs& R, const WorldArgs& W, const TV& S, const TV& X,
+                        float* sweptc, const ShapeArgs& sh, const CostArgs& cp) {
+  const int64_t waves = (sh.B + 62) / 63;
+  const dim3 grid(blocks_for(waves, 4)), block(256);
+  switch (S.fmt) {
+#define VAPR_SWEPT_CASE(F) \
+  case F: hipLaunchKernelGGL(k_swept<F>, grid, block, 0, s, R, W, S, X, sweptc, sh, cp); break;
+    VAPR_SWEPT_CASE(F32) VAPR_SWEPT_CASE(F16) VAPR_SWEPT_CASE(BF16) VAPR_SWEPT_CASE(E4M3) VAPR_SWEPT_CASE(E5M2)
+    VAPR_SWEPT_CASE(E3M2) VAPR_SWEPT_CASE(E2M1)
+#undef VAPR_SWEPT_CASE
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint(hipStream_t s, const float* q, const RobotArgs& R, const TV& L, const TV& G, const TV& X,
+                          const TV& J, const double* up, float* grad_q, const ShapeArgs& sh, const CostArgs& cp,
+                          int recompute) {
   const dim3 grid(blocks_for(sh.B, 64)), block(256);
   switch (G.fmt) {
 #define VAPR_ADJ_CASE(F) \
-  case F: hipLaunchKernelGGL(k_adjoint<F>, grid, block, 0, s, q, R, L, G, J, up, grad_q, sh, cp, recompute); break;
+  case F:                                                                                                     \
+    if (X.P) hipLaunchKernelGGL((k_adjoint<F, true>), grid, block, 0, s, q, R, L, G, X, J, up, grad_q, sh, cp, recompute); \
+    else hipLaunchKernelGGL((k_adjoint<F, false>), grid, block, 0, s, q, R, L, G, X, J, up, grad_q, sh, cp, recompute); \
+    break;
     VAPR_ADJ_CASE(F32) VAPR_ADJ_CASE(F16) VAPR_ADJ_CASE(BF16) VAPR_ADJ_CASE(E4M3) VAPR_ADJ_CASE(E5M2)
     VAPR_ADJ_CASE(E3M2) VAPR_ADJ_CASE(E2M1)
 #undef VAPR_ADJ_CASE

@@ -52,6 +52,8 @@ struct ShapeArgs {
 
 struct CostArgs {
   float eta, w_c, w_s, w_b, w_v;
+  int k_sw;    // swept samples per segment (0: off)
+  float w_sw;
 };
 
 struct OptArgs {
@@ -70,7 +72,10 @@ struct OptArgs {
   int* flags;
 };
 
-enum KernelId { K_FK = 0, K_SPHERE = 1, K_REDUCE = 2, K_ADJOINT = 3, K_OPT = 4, K_CODEC = 5, K_REPACK = 6, N_KERNEL_IDS = 7 };
+enum KernelId {
+  K_FK = 0, K_SPHERE = 1, K_REDUCE = 2, K_ADJOINT = 3, K_OPT = 4, K_CODEC = 5, K_REPACK = 6, K_SWEPT = 7,
+  N_KERNEL_IDS = 8
+};
 
 // launch wrappers (return hipError_t of the launch)
 hipError_t launch_fk(hipStream_t s, const float* q, const RobotArgs& R, const TV& L, const TV& S, float* bound,
@@ -82,10 +87,17 @@ size_t sphere_cost_lds_bytes(int n_groups);
 hipError_t launch_sphere_cost_blk(hipStream_t s, const RobotArgs& R, const WorldArgs& W, const GridArgs& Gd,
                                   const TV& S, const TV& D, const TV& G, float* selfc, const ShapeArgs& sh,
                                   const CostArgs& cp);
-hipError_t launch_reduce(hipStream_t s, const TV& D, const float* selfc, const float* boundc, const float* q,
-                         double* cost_traj, float* cost_cfg, const ShapeArgs& sh, const CostArgs& cp, int n_s);
-hipError_t launch_adjoint(hipStream_t s, const float* q, const RobotArgs& R, const TV& L, const TV& G, const TV& J,
-                          const double* up, float* grad_q, const ShapeArgs& sh, const CostArgs& cp, int recompute);
+// swept term (cp.k_sw > 0): X and the swept cost per configuration from S
+hipError_t launch_swept(hipStream_t s, const RobotArgs& R, const WorldArgs& W, const TV& S, const TV& X,
+                        float* sweptc, const ShapeArgs& sh, const CostArgs& cp);
+// sweptc: per-configuration swept cost added to the configuration cost, or null
+hipError_t launch_reduce(hipStream_t s, const TV& D, const float* selfc, const float* boundc, const float* sweptc,
+                         const float* q, double* cost_traj, float* cost_cfg, const ShapeArgs& sh, const CostArgs& cp,
+                         int n_s);
+// X.P == 0: no swept gradient
+hipError_t launch_adjoint(hipStream_t s, const float* q, const RobotArgs& R, const TV& L, const TV& G, const TV& X,
+                          const TV& J, const double* up, float* grad_q, const ShapeArgs& sh, const CostArgs& cp,
+                          int recompute);
 hipError_t launch_optimizer(hipStream_t s, const OptArgs& o, const TV& J, const double* cost_in, float* q_cand,
                             int mode);
 hipError_t launch_quantize(hipStream_t s, int fmt, float inv, const float* in, uint8_t* out, int64_t n);

@@ -1,4 +1,4 @@
-// Workspace layout of the five stored tensors (Sec. III-C) in HBM.
+// Workspace layout of the stored tensors (Sec. III-C) in HBM.
 //
 // Every tensor is a set of dword "planes" per configuration, tiled by blocks of 64 configurations
 // (one wavefront, one configuration per lane): dword (b, p) of a tensor with P planes lives at
@@ -12,7 +12,9 @@
 //   D  ceil(n_s/16) groups of 16 spheres,                plane = g*dw(16) + w
 //   G  like S
 //   J  one group of 8 values (7 joints + a zero)          dw(8) planes
-// followed by two FP32 arrays [Bp] (self cost, bound cost).  Regions are 256-byte aligned.
+//   X  swept sphere gradient, like S (only with the swept term on)
+// followed by FP32 arrays [Bp]: self cost, bound cost (then X) and, with the swept term, the swept
+// cost.  Regions are 256-byte aligned.
 #pragma once
 #include <stddef.h>
 #include <stdint.h>
@@ -36,6 +38,7 @@ constexpr int MAX_T = 4096;
 constexpr int MAX_LS = 4;
 constexpr int MAX_OPT_T = 64;
 constexpr int MAX_HIST = 8;
+constexpr int MAX_SWEEP = 16;       // swept samples per segment
 
 struct TensorFormat {
   int fmt;
@@ -43,17 +46,20 @@ struct TensorFormat {
 };
 
 struct PrecisionCfg {
-  TensorFormat t[5];  // L, S, D, G, J
+  TensorFormat t[6];  // L, S, D, G, J, X
   int recompute;
+  int sweep;          // swept samples per segment (0: no X tensor and no swept cost)
 };
 
-enum { T_L = 0, T_S = 1, T_D = 2, T_G = 3, T_J = 4 };
+enum { T_L = 0, T_S = 1, T_D = 2, T_G = 3, T_J = 4, T_X = 5 };
+// byte-offset slots of the FP32 arrays and of X
+enum { OFF_SELF = 5, OFF_BOUND = 6, OFF_X = 7, OFF_SWEPT = 8 };
 
 struct Layout {
   int64_t B, Bp, nblk;
   int n_s, n_groups;
-  int P[5];             // planes per tensor
-  size_t off[7];        // byte offsets: L S D G J self bound
+  int P[6];             // planes per tensor (X: 0 without the swept term)
+  size_t off[9];        // byte offsets: L S D G J self bound X swept
   size_t bytes;
 };
 
@@ -71,15 +77,20 @@ inline Layout make_layout(int64_t B, int n_s, const PrecisionCfg& pc) {
   L.P[T_D] = L.n_groups * group_dwords(pc.t[T_D].fmt, SPH_GROUP);
   L.P[T_G] = L.n_groups * 3 * group_dwords(pc.t[T_G].fmt, SPH_GROUP);
   L.P[T_J] = group_dwords(pc.t[T_J].fmt, J_GROUP);
+  L.P[T_X] = pc.sweep ? L.n_groups * 3 * group_dwords(pc.t[T_X].fmt, SPH_GROUP) : 0;
   size_t o = 0;
   for (int i = 0; i < 5; ++i) {
     L.off[i] = o;
     o += align256((size_t)L.P[i] * (size_t)L.Bp * 4);
   }
-  L.off[5] = o;
+  L.off[OFF_SELF] = o;
   o += align256((size_t)L.Bp * 4);
-  L.off[6] = o;
+  L.off[OFF_BOUND] = o;
   o += align256((size_t)L.Bp * 4);
+  L.off[OFF_X] = o;
+  o += align256((size_t)L.P[T_X] * (size_t)L.Bp * 4);
+  L.off[OFF_SWEPT] = o;
+  if (pc.sweep) o += align256((size_t)L.Bp * 4);
   L.bytes = o;
   return L;
 }

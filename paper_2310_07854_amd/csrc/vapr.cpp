@@ -68,7 +68,7 @@ struct vapr_ctx {
   float r_max = 0.f;
   // settings
   PrecisionCfg prec{};
-  CostArgs params{0.02f, 100.f, 100.f, 10.f, 1.f};
+  CostArgs params{0.02f, 100.f, 100.f, 10.f, 1.f, 0, 100.f};
   std::unordered_map<const void*, WsRecord> ws;
   std::string err;
   // profiling
@@ -165,19 +165,21 @@ PrecisionCfg to_cfg(const vapr_precision& p) {
   c.t[T_D] = {p.sphere_dist.fmt, p.sphere_dist.scale_exp};
   c.t[T_G] = {p.sphere_grad.fmt, p.sphere_grad.scale_exp};
   c.t[T_J] = {p.joint_grad.fmt, p.joint_grad.scale_exp};
+  c.t[T_X] = {p.swept_grad.fmt, p.swept_grad.scale_exp};
   c.recompute = p.recompute_poses ? 1 : 0;
   return c;
 }
 
+// same formats, pose mode and swept sampling (which decides whether X and the swept cost exist)
 bool same_prec(const PrecisionCfg& a, const PrecisionCfg& b) {
-  for (int i = 0; i < 5; ++i)
+  for (int i = 0; i < 6; ++i)
     if (a.t[i].fmt != b.t[i].fmt || a.t[i].scale_exp != b.t[i].scale_exp) return false;
-  return a.recompute == b.recompute;
+  return a.recompute == b.recompute && a.sweep == b.sweep;
 }
 
 TV tensor_view(void* ws, const Layout& L, const PrecisionCfg& pc, int t) {
   TV v;
-  v.p = reinterpret_cast<uint32_t*>(static_cast<char*>(ws) + L.off[t]);
+  v.p = reinterpret_cast<uint32_t*>(static_cast<char*>(ws) + L.off[t == T_X ? OFF_X : t]);
   v.fmt = pc.t[t].fmt;
   v.P = L.P[t];
   v.scale = std::ldexp(1.0f, pc.t[t].scale_exp);
@@ -392,8 +394,9 @@ int run_fwd(vapr_ctx* ctx, int first, int n_worlds, int tpw, int T, int n_ls, co
   const RobotArgs R = robot_args(ctx);
   const TV tL = tensor_view(ws, L, ctx->prec, T_L), tS = tensor_view(ws, L, ctx->prec, T_S),
            tD = tensor_view(ws, L, ctx->prec, T_D), tG = tensor_view(ws, L, ctx->prec, T_G);
-  float* selfc = reinterpret_cast<float*>(static_cast<char*>(ws) + L.off[5]);
-  float* boundc = reinterpret_cast<float*>(static_cast<char*>(ws) + L.off[6]);
+  float* selfc = reinterpret_cast<float*>(static_cast<char*>(ws) + L.off[OFF_SELF]);
+  float* boundc = reinterpret_cast<float*>(static_cast<char*>(ws) + L.off[OFF_BOUND]);
+  float* sweptc = ctx->prec.sweep ? reinterpret_cast<float*>(static_cast<char*>(ws) + L.off[OFF_SWEPT]) : nullptr;
   hipStream_t s = ctx->stream;
   if (first <= 1) {
     st = timed(ctx, K_FK, [&] { return launch_fk(s, q, R, tL, tS, boundc, B, ctx->prec.recompute ? 0 : 1); },
@@ -413,10 +416,16 @@ int run_fwd(vapr_ctx* ctx, int first, int n_worlds, int tpw, int T, int n_ls, co
                  "k_sphere_cost launch");
     }
     if (st) return st;
+    if (ctx->prec.sweep) {
+      const TV tX = tensor_view(ws, L, ctx->prec, T_X);
+      st = timed(ctx, K_SWEPT, [&] { return launch_swept(s, R, W, tS, tX, sweptc, sh, cp); }, "k_swept launch");
+      if (st) return st;
+    }
   }
   const CostArgs cp = ctx->params;
   const int n_s = ctx->n_s;
-  st = timed(ctx, K_REDUCE, [&] { return launch_reduce(s, tD, selfc, boundc, q, cost_traj, cost_cfg, sh, cp, n_s); },
+  st = timed(ctx, K_REDUCE,
+             [&] { return launch_reduce(s, tD, selfc, boundc, sweptc, q, cost_traj, cost_cfg, sh, cp, n_s); },
              "k_reduce launch");
   if (st) return st;
   ctx->ws[ws] = WsRecord{n_worlds, tpw, T, n_ls, B, ctx->prec, ctx->robot_gen};
@@ -427,7 +436,8 @@ int tensor_count(const vapr_ctx* ctx, int tensor) {
   switch (tensor) {
     case VAPR_T_LINK_POSES: return N_FIXED * LINK_VALUES;
     case VAPR_T_SPHERE_POS:
-    case VAPR_T_SPHERE_GRAD: return ctx->n_s * 3;
+    case VAPR_T_SPHERE_GRAD:
+    case VAPR_T_SWEPT_GRAD: return ctx->n_s * 3;
     case VAPR_T_SPHERE_DIST: return ctx->n_s;
     case VAPR_T_JOINT_GRAD: return N_JOINTS;
     default: return 1;
@@ -682,17 +692,21 @@ int vapr_set_worlds(vapr_ctx* ctx, int n_worlds, int n_cuboids, const float* pos
 int vapr_set_precision(vapr_ctx* ctx, const vapr_precision* p) {
   if (!ctx) return fail(nullptr, VAPR_E_INVALID, "null context");
   if (!p) return fail(ctx, VAPR_E_INVALID, "null precision");
-  const vapr_tensor_format* f[5] = {&p->link_poses, &p->sphere_pos, &p->sphere_dist, &p->sphere_grad, &p->joint_grad};
-  for (int i = 0; i < 5; ++i)
+  const vapr_tensor_format* f[6] = {&p->link_poses, &p->sphere_pos, &p->sphere_dist,
+                                    &p->sphere_grad, &p->joint_grad, &p->swept_grad};
+  for (int i = 0; i < 6; ++i)
     if (!valid_format(*f[i])) return fail(ctx, VAPR_E_INVALID, "unknown format or scale out of range");
+  const int sweep = ctx->prec.sweep;
   ctx->prec = to_cfg(*p);
+  ctx->prec.sweep = sweep;
   return VAPR_OK;
 }
 
 int vapr_get_precision(const vapr_ctx* ctx, vapr_precision* p) {
   if (!ctx || !p) return fail(nullptr, VAPR_E_INVALID, "null pointer");
-  vapr_tensor_format* f[5] = {&p->link_poses, &p->sphere_pos, &p->sphere_dist, &p->sphere_grad, &p->joint_grad};
-  for (int i = 0; i < 5; ++i) *f[i] = {ctx->prec.t[i].fmt, ctx->prec.t[i].scale_exp};
+  vapr_tensor_format* f[6] = {&p->link_poses, &p->sphere_pos, &p->sphere_dist,
+                              &p->sphere_grad, &p->joint_grad, &p->swept_grad};
+  for (int i = 0; i < 6; ++i) *f[i] = {ctx->prec.t[i].fmt, ctx->prec.t[i].scale_exp};
   p->recompute_poses = ctx->prec.recompute;
   return VAPR_OK;
 }
@@ -700,11 +714,12 @@ int vapr_get_precision(const vapr_ctx* ctx, vapr_precision* p) {
 int vapr_set_cost_params(vapr_ctx* ctx, const vapr_cost_params* p) {
   if (!ctx) return fail(nullptr, VAPR_E_INVALID, "null context");
   if (!p) return fail(ctx, VAPR_E_INVALID, "null params");
-  const float v[5] = {p->eta, p->w_coll, p->w_self, p->w_bound, p->w_smooth};
-  if (!finite_all(v, 5) || !(p->eta > 0.f) || p->w_coll < 0.f || p->w_self < 0.f || p->w_bound < 0.f ||
-      p->w_smooth < 0.f)
+  const float v[6] = {p->eta, p->w_coll, p->w_self, p->w_bound, p->w_smooth, p->w_swept};
+  if (!finite_all(v, 6) || !(p->eta > 0.f) || p->w_coll < 0.f || p->w_self < 0.f || p->w_bound < 0.f ||
+      p->w_smooth < 0.f || p->w_swept < 0.f || p->swept_steps < 0 || p->swept_steps > MAX_SWEEP)
     return fail(ctx, VAPR_E_INVALID, "cost parameters out of range");
-  ctx->params = CostArgs{p->eta, p->w_coll, p->w_self, p->w_bound, p->w_smooth};
+  ctx->params = CostArgs{p->eta, p->w_coll, p->w_self, p->w_bound, p->w_smooth, p->swept_steps, p->w_swept};
+  ctx->prec.sweep = p->swept_steps;
   ctx->grid_valid = false;
   ctx->pairs_valid = false;
   return VAPR_OK;
@@ -777,11 +792,11 @@ int vapr_cost_bwd(vapr_ctx* ctx, const float* q, void* ws, size_t ws_bytes, cons
   const ShapeArgs sh = shape_args(r.n_worlds, r.tpw, r.T, r.n_ls);
   const RobotArgs R = robot_args(ctx);
   const TV tL = tensor_view(ws, L, ctx->prec, T_L), tG = tensor_view(ws, L, ctx->prec, T_G),
-           tJ = tensor_view(ws, L, ctx->prec, T_J);
+           tJ = tensor_view(ws, L, ctx->prec, T_J), tX = tensor_view(ws, L, ctx->prec, T_X);
   const CostArgs cp = ctx->params;
   const int rec = ctx->prec.recompute;
   return timed(ctx, K_ADJOINT,
-               [&] { return launch_adjoint(ctx->stream, q, R, tL, tG, tJ, grad_cost_traj, grad_q, sh, cp, rec); },
+               [&] { return launch_adjoint(ctx->stream, q, R, tL, tG, tX, tJ, grad_cost_traj, grad_q, sh, cp, rec); },
                "k_adjoint launch");
 }
 
@@ -925,7 +940,9 @@ static int ws_io(vapr_ctx* ctx, int n_worlds, int tpw, int T, int n_ls, void* ws
   int st = check_shape(ctx, n_worlds, tpw, T, n_ls, &B);
   if (st) return st;
   if (!ws || !buf) return fail(ctx, VAPR_E_INVALID, "null pointer");
-  if (tensor < VAPR_T_LINK_POSES || tensor > VAPR_T_BOUND_COST) return fail(ctx, VAPR_E_INVALID, "unknown tensor");
+  if (tensor < VAPR_T_LINK_POSES || tensor > VAPR_T_SWEPT_COST) return fail(ctx, VAPR_E_INVALID, "unknown tensor");
+  if ((tensor == VAPR_T_SWEPT_GRAD || tensor == VAPR_T_SWEPT_COST) && !ctx->prec.sweep)
+    return fail(ctx, VAPR_E_INVALID, "no swept tensors: the swept term is off (swept_steps = 0)");
   const Layout L = make_layout(B, ctx->n_s, ctx->prec);
   if (ws_bytes < L.bytes) return fail(ctx, VAPR_E_INVALID, "workspace too small");
   if (direction == 0) {
@@ -933,9 +950,10 @@ static int ws_io(vapr_ctx* ctx, int n_worlds, int tpw, int T, int n_ls, void* ws
     if (it == ctx->ws.end() || it->second.B != B || !same_prec(it->second.prec, ctx->prec))
       return fail(ctx, VAPR_E_STATE, "workspace does not hold this shape at the current precision");
   }
-  if (tensor >= VAPR_T_SELF_COST) {
+  if (tensor == VAPR_T_SELF_COST || tensor == VAPR_T_BOUND_COST || tensor == VAPR_T_SWEPT_COST) {
     if (buf_bytes < (size_t)B * 4) return fail(ctx, VAPR_E_INVALID, "buffer too small");
-    char* arr = static_cast<char*>(ws) + L.off[tensor == VAPR_T_SELF_COST ? 5 : 6];
+    char* arr = static_cast<char*>(ws) +
+                L.off[tensor == VAPR_T_SELF_COST ? OFF_SELF : (tensor == VAPR_T_BOUND_COST ? OFF_BOUND : OFF_SWEPT)];
     st = timed(ctx, K_REPACK,
                [&] {
                  return direction == 0 ? hipMemcpyAsync(buf, arr, (size_t)B * 4, hipMemcpyDeviceToDevice, ctx->stream)
@@ -946,12 +964,16 @@ static int ws_io(vapr_ctx* ctx, int n_worlds, int tpw, int T, int n_ls, void* ws
     if (tensor == VAPR_T_LINK_POSES && ctx->prec.recompute)
       return fail(ctx, VAPR_E_INVALID, "no link-pose tensor in recompute mode");
     const int ecfg = tensor_count(ctx, tensor);
-    const int fmt = ctx->prec.t[tensor].fmt;
+    const int t = tensor == VAPR_T_SWEPT_GRAD ? T_X : tensor;  // X is laid out like G
+    const int fmt = ctx->prec.t[t].fmt;
     if (buf_bytes < vapr_packed_bytes(fmt, B * ecfg)) return fail(ctx, VAPR_E_INVALID, "buffer too small");
-    const TV tv = tensor_view(ws, L, ctx->prec, tensor);
+    const TV tv = tensor_view(ws, L, ctx->prec, t);
     const int n_s = ctx->n_s;
+    const int shape_of = t == T_X ? T_G : t;
     st = timed(ctx, K_REPACK,
-               [&] { return launch_repack(ctx->stream, tensor, tv, B, ecfg, n_s, static_cast<uint8_t*>(buf), direction); },
+               [&] {
+                 return launch_repack(ctx->stream, shape_of, tv, B, ecfg, n_s, static_cast<uint8_t*>(buf), direction);
+               },
                "repack launch");
   }
   if (st) return st;

@@ -24,6 +24,7 @@ RISK = {
     "sphere_dist": (1e-5, 8e-6),
     "sphere_grad": (1e-4, 5e-3),
     "joint_grad": (2e-4, 2e-3),
+    "swept_grad": (1e-4, 5e-3),
 }
 
 
