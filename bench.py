@@ -149,6 +149,61 @@ def culled_work(ctx, opt, prec):
     return {"needed_tests_per_cfg": needed / B, "issued_lane_tests_per_cfg": issued / B}
 
 
+def swept_culled_work(ctx, opt, prec, k):
+    """Sample-cuboid tests of one swept launch of the timed loop (its last one), counted like
+    culled_work: `needed` sums, over segments, spheres and the k sample points, the cuboids marked in
+    the point's voxel; `issued` counts the lane slots the kernel spends (per sample, each lane tests
+    the union of four spheres' lists, a wavefront of 64 segment lanes as often as its busiest lane).
+    Sample points are recomputed from the stored positions in FP32."""
+    from paper_2310_07854_amd.context import dequantize
+
+    shape = opt.shape
+    B = shape.B
+    fmt = prec.get("sphere_pos", "f32")
+    fmt, kx = (fmt, 0) if isinstance(fmt, str) else fmt
+    codes = ctx.ws_export("sphere_pos", opt.ws, shape)
+    pos = dequantize(codes, fmt, B * N_SPHERES * 3, kx).view(B, N_SPHERES, 3).cpu().numpy()
+    n_pad = (N_SPHERES + 15) // 16 * 16
+    seg = (np.arange(B) % T) != T - 1
+    seg[-1] = False
+    p0 = pos
+    dp = np.zeros_like(pos)
+    dp[:-1] = pos[1:] - pos[:-1]
+    cand = np.zeros((B, n_pad), dtype=np.uint64)
+    needed = 0
+    issued = 0
+    n_waves = (B + 62) // 63
+    lane_a = (63 * np.arange(n_waves)[:, None] - 1 + np.arange(64)[None, :])          # segment start per lane
+    lane_ok = (lane_a >= 0) & (lane_a < B)
+    lane_a = np.clip(lane_a, 0, B - 1)
+    cfg_per_world = B // N_WORLDS
+    grids = [ctx.culling_grid(w) for w in range(N_WORLDS)]
+    for j in range(1, k + 1):
+        u = np.float32(j) / np.float32(k + 1)
+        pts = (p0 + u * dp).astype(np.float32)
+        cand[:] = 0
+        for w in range(N_WORLDS):
+            info, mask = grids[w]
+            sl = slice(w * cfg_per_world, (w + 1) * cfg_per_world)
+            if mask is None:
+                cand[sl, :N_SPHERES] = np.uint64((1 << N_CUBOIDS) - 1) if N_CUBOIDS < 64 else np.uint64(2 ** 64 - 1)
+                continue
+            m64 = mask[:, 0].astype(np.uint64)
+            if mask.shape[1] > 1:
+                m64 |= mask[:, 1].astype(np.uint64) << np.uint64(32)
+            n = info["n"]
+            f = (pts[sl] - np.array(info["origin"], dtype=np.float32)) * np.float32(info["inv_cell"])
+            inside = np.all((f >= 0) & (f < np.float32(n)), axis=-1)
+            v = np.floor(np.where(inside[..., None], f, 0)).astype(np.int64)
+            cand[sl, :N_SPHERES] = np.where(inside, m64[(v[..., 2] * n + v[..., 1]) * n + v[..., 0]], np.uint64(0))
+        cand[~seg] = 0
+        needed += int(np.bitwise_count(cand).sum())
+        quad = np.bitwise_or.reduce(cand.reshape(B, n_pad // 4, 4), axis=2)           # [B, quads]
+        per_lane = np.bitwise_count(quad).astype(np.int64)[lane_a] * lane_ok[..., None]  # [wave, lane, quad]
+        issued += int(per_lane.max(axis=1).sum()) * 4 * 64
+    return {"needed_tests_per_cfg": needed / B, "issued_lane_tests_per_cfg": issued / B}
+
+
 def calibrate_scales(torch, ctx, x0):
     """amax of each stored tensor on the FP32 path over the run's initial trajectories."""
     from paper_2310_07854_amd import Shape
@@ -159,6 +214,8 @@ def calibrate_scales(torch, ctx, x0):
     _, ws = ctx.cost_fwd(q, shape)
     ctx.cost_bwd(q, ws, want_grad=False)
     names = ("link_poses", "sphere_pos", "sphere_dist", "sphere_grad", "joint_grad")
+    if ctx.cost_params.get("swept_steps", 0) > 0:
+        names += ("swept_grad",)
     return {t: float(ctx.ws_export(t, ws, shape).view(torch.float32).abs().max()) for t in names}
 
 
@@ -503,6 +560,65 @@ def seed_inference(args):
     print(json.dumps(line), flush=True)
 
 
+def swept_bench(args):
+    """One optimiser iteration per step on the 196,608-configuration workload with the swept term
+    on (k samples per segment between consecutive timesteps), FP32 and the paper-like assignment
+    (the swept gradient X stored like G).  The swept kernel tests every sample against the cuboids
+    its world's culling grid marks in the sample's voxel; its algorithmic work is those tests x 35
+    FP32 operations (counted from the last launch's positions)."""
+    import torch
+
+    from paper_2310_07854_amd import Context, TrajectoryOptimizer
+    from synthetic import make_robot, make_trajectories, make_worlds
+
+    k = args.swept
+    B = N_WORLDS * TPW * T * N_LS
+    ctx = Context(0)
+    ctx.set_robot(make_robot(N_SPHERES, N_PAIRS))
+    worlds = make_worlds(N_WORLDS, N_CUBOIDS)
+    ctx.set_worlds(worlds.pose, worlds.half_ext)
+    ctx.set_cost_params(swept_steps=k, w_swept=100.0)
+    x0 = torch.tensor(make_trajectories(N_WORLDS, TPW, T).reshape(N_WORLDS * TPW, T, 7), dtype=torch.float32,
+                      device="cuda:0")
+    amax = calibrate_scales(torch, ctx, x0)
+    out = {}
+    for name in ("f32", "paper_like"):
+        f = dict(PRECISIONS[name])
+        f["swept_grad"] = f.get("sphere_grad", "f32")
+        prec = with_scales(f, amax)
+        dt, prof, _, opt = run_variant(torch, ctx, TrajectoryOptimizer, x0, prec, args.steps, args.warmup,
+                                       want_opt=name == "paper_like")
+        if opt is not None:
+            work = swept_culled_work(ctx, opt, prec, k)
+            del opt
+        kern = {kk: v[0] / max(v[1], 1) * 1e3 for kk, v in prof.items() if v[1]}
+        out[name] = {"value": B * args.steps / dt, "ms_per_step": dt / args.steps * 1e3, "kernels_us": kern,
+                     "formats": {kk: list(v) for kk, v in prec.items()}}
+        print(f"# swept k={k} {name}: {dt / args.steps * 1e3:.3f} ms/step, {B * args.steps / dt / 1e6:.1f} M evals/s, "
+              + ", ".join(f"{kk} {v:.1f}us" for kk, v in kern.items()), file=sys.stderr, flush=True)
+    ctx.close()
+    dense_cfg = (T - 1) / T * N_SPHERES * k * N_CUBOIDS * FLOPS_PER_SPHERE_CUBOID
+    flops_cfg = work["needed_tests_per_cfg"] * FLOPS_PER_SPHERE_CUBOID
+    sw_us = out["paper_like"]["kernels_us"]["swept"]
+    achieved = flops_cfg * B / (sw_us * 1e-6) / 1e12
+    line = {"metric": "cost fwd+bwd evals/s with the swept collision term (one optimiser iteration per step)",
+            "value": out["paper_like"]["value"], "unit": "evals/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": out["paper_like"]["ms_per_step"], "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": f"64 worlds x 64 seeds x 48 timesteps = 196,608 configurations per step; "
+                                   f"7-joint arm, 60 spheres, 300 self pairs, 64 oriented cuboids per world; swept "
+                                   f"term with {k} samples per segment",
+                       "precision": "paper_like", "formats": out["paper_like"]["formats"]},
+            "fp32_value": out["f32"]["value"], "variants": out,
+            "roofline": {"kernel": "k_swept", "bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TFLOPS,
+                         "unit": "TFLOP/s", "frac": achieved / VALU_PEAK_TFLOPS, "flops_per_cfg": flops_cfg,
+                         "culled_tests_per_cfg": work["needed_tests_per_cfg"],
+                         "issued_lane_tests_per_cfg": work["issued_lane_tests_per_cfg"],
+                         "dense_equivalent_TFLOPs": dense_cfg * B / (sw_us * 1e-6) / 1e12, "traffic": None},
+            "cpu_baseline": None}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -513,6 +629,7 @@ def main():
     ap.add_argument("--variants", action="store_true", help="also time every other assignment")
     ap.add_argument("--seeding", action="store_true", help="run the learned-seeder study instead")
     ap.add_argument("--seed-infer", action="store_true", help="time the seeding network's inference instead")
+    ap.add_argument("--swept", type=int, default=0, help="time the step with the swept term (k samples) instead")
     ap.add_argument("--seed-batch", type=int, default=65536)
     ap.add_argument("--seed-envs", type=int, default=2)
     ap.add_argument("--seed-problems", type=int, default=32768)
@@ -541,6 +658,9 @@ def main():
         return
     if args.seed_infer:
         seed_inference(args)
+        return
+    if args.swept:
+        swept_bench(args)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (--gpus {args.gpus} requested): the cost path shards by world "

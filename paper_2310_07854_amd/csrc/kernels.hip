@@ -752,10 +752,13 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3))) void k
 // at the far end moves one lane up with a cross-lane permute: configuration c receives its own
 // segment's near-end gradient plus the far-end gradient of the segment (c - 1, c), with no atomics
 // and in a fixed order.  Spheres go eight at a time against the world's cuboids (closest cuboid by
-// the same comparison key as the discrete term, exact distance and gradient for the winner).
+// the same comparison key as the discrete term, exact distance and gradient for the winner).  With
+// the culling grid (at most 64 cuboids), a sample point only meets the cuboids marked in its voxel,
+// taken in increasing index over the union of four spheres' lists: the grid is conservative for any
+// point a robot sphere can occupy, so the result is the one every cuboid would give.
 template <int FS>
-__global__ __launch_bounds__(256) void k_swept(RobotArgs R, WorldArgs W, TV S, TV X, float* __restrict__ sweptc,
-                                               ShapeArgs sh, CostArgs cp) {
+__global__ __launch_bounds__(256) void k_swept(RobotArgs R, WorldArgs W, GridArgs Gd, TV S, TV X,
+                                               float* __restrict__ sweptc, ShapeArgs sh, CostArgs cp) {
   const int lane = threadIdx.x & 63;
   const int64_t wv = (int64_t)blockIdx.x * 4 + uniform(threadIdx.x >> 6);
   const int64_t first = wv * 63;
@@ -775,6 +778,8 @@ __global__ __launch_bounds__(256) void k_swept(RobotArgs R, WorldArgs W, TV S, T
   const int k_sw = uniform(cp.k_sw);
   const float coef_base = -2.f * cp.w_sw / (float)k_sw;
   const int src = ((lane + 63) & 63) << 2;              // ds_bpermute address of lane - 1
+  const bool culled = Gd.MW > 0 && Gd.MW <= 2;
+  const int64_t n3 = (int64_t)Gd.n * Gd.n * Gd.n;
   const uint32_t* b0 = lane_base(S, seg ? a : 0);
   const uint32_t* b1 = lane_base(S, seg ? a + 1 : 0);
   float cost = 0.f;
@@ -812,16 +817,42 @@ __global__ __launch_bounds__(256) void k_swept(RobotArgs R, WorldArgs W, TV S, T
             best[i] = INFINITY;
             bk[i] = 0;
           }
-          for (int w = w_lo; w <= w_hi; ++w) {
-            if (my_w != w || !seg) continue;
-            const cptr<float> wbox = as_const(W.box) + (int64_t)uniform(w) * K * 16;
-            closest_cuboids<8>(wbox, K, px, py, pz, best, bk);
+          if (culled) {
+            if (seg) {
+              const float* wbox = W.box + (int64_t)my_w * K * 16;
+              const uint32_t* gm = Gd.mask + (int64_t)my_w * n3 * Gd.MW;
+#pragma unroll
+              for (int q4 = 0; q4 < 8; q4 += 4) {
+                uint64_t m = 0;
+#pragma unroll
+                for (int i = q4; i < q4 + 4; ++i) {
+                  if (h + i >= active) continue;
+                  const int vox = voxel_of(Gd, px[i], py[i], pz[i]);
+                  if (vox < 0) continue;
+                  const uint32_t* mv = gm + (int64_t)vox * Gd.MW;
+                  m |= (uint64_t)mv[0] | (Gd.MW > 1 ? (uint64_t)mv[1] << 32 : 0ull);
+                }
+                float4 c0, c1, c2, c3;
+                int kk;
+                while ((kk = pop_cuboid(m, wbox, c0, c1, c2, c3)) >= 0) {
+#pragma unroll
+                  for (int i = q4; i < q4 + 4; ++i) cuboid_key_v(c0, c1, c2, c3, px[i], py[i], pz[i], kk, best[i], bk[i]);
+                }
+              }
+            }
+          } else {
+            for (int w = w_lo; w <= w_hi; ++w) {
+              if (my_w != w || !seg) continue;
+              const cptr<float> wbox = as_const(W.box) + (int64_t)uniform(w) * K * 16;
+              closest_cuboids<8>(wbox, K, px, py, pz, best, bk);
+            }
           }
           if (seg && K > 0) {
             const float* mybox = W.box + (int64_t)my_w * K * 16;
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
-              if (h + i >= active) continue;
+              // no candidate: no cuboid within reach of the point, so the depth is zero
+              if (h + i >= active || best[i] == INFINITY) continue;
               float sd, nx, ny, nz;
               cuboid_sd_grad(mybox + bk[i] * 16, px[i], py[i], pz[i], sd, nx, ny, nz);
               const float r = sphere_of(R.sph, g * SPH_GROUP + h + i).w;
@@ -1529,13 +1560,13 @@ hipError_t launch_reduce(hipStream_t s, const TV& D, const float* selfc, const f
   return hipGetLastError();
 }
 
-hipError_t launch_swept(hipStream_t s, const RobotArgs& R, const WorldArgs& W, const TV& S, const TV& X,
-                        float* sweptc, const ShapeArgs& sh, const CostArgs& cp) {
+hipError_t launch_swept(hipStream_t s, const RobotArgs& R, const WorldArgs& W, const GridArgs& Gd, const TV& S,
+                        const TV& X, float* sweptc, const ShapeArgs& sh, const CostArgs& cp) {
   const int64_t waves = (sh.B + 62) / 63;
   const dim3 grid(blocks_for(waves, 4)), block(256);
   switch (S.fmt) {
 #define VAPR_SWEPT_CASE(F) \
-  case F: hipLaunchKernelGGL(k_swept<F>, grid, block, 0, s, R, W, S, X, sweptc, sh, cp); break;
+  case F: hipLaunchKernelGGL(k_swept<F>, grid, block, 0, s, R, W, Gd, S, X, sweptc, sh, cp); break;
     VAPR_SWEPT_CASE(F32) VAPR_SWEPT_CASE(F16) VAPR_SWEPT_CASE(BF16) VAPR_SWEPT_CASE(E4M3) VAPR_SWEPT_CASE(E5M2)
     VAPR_SWEPT_CASE(E3M2) VAPR_SWEPT_CASE(E2M1)
 #undef VAPR_SWEPT_CASE

@@ -88,8 +88,8 @@ hipError_t launch_sphere_cost_blk(hipStream_t s, const RobotArgs& R, const World
                                   const TV& S, const TV& D, const TV& G, float* selfc, const ShapeArgs& sh,
                                   const CostArgs& cp);
 // swept term (cp.k_sw > 0): X and the swept cost per configuration from S
-hipError_t launch_swept(hipStream_t s, const RobotArgs& R, const WorldArgs& W, const TV& S, const TV& X,
-                        float* sweptc, const ShapeArgs& sh, const CostArgs& cp);
+hipError_t launch_swept(hipStream_t s, const RobotArgs& R, const WorldArgs& W, const GridArgs& Gd, const TV& S,
+                        const TV& X, float* sweptc, const ShapeArgs& sh, const CostArgs& cp);
 // sweptc: per-configuration swept cost added to the configuration cost, or null
 hipError_t launch_reduce(hipStream_t s, const TV& D, const float* selfc, const float* boundc, const float* sweptc,
                          const float* q, double* cost_traj, float* cost_cfg, const ShapeArgs& sh, const CostArgs& cp,

@@ -418,7 +418,7 @@ int run_fwd(vapr_ctx* ctx, int first, int n_worlds, int tpw, int T, int n_ls, co
     if (st) return st;
     if (ctx->prec.sweep) {
       const TV tX = tensor_view(ws, L, ctx->prec, T_X);
-      st = timed(ctx, K_SWEPT, [&] { return launch_swept(s, R, W, tS, tX, sweptc, sh, cp); }, "k_swept launch");
+      st = timed(ctx, K_SWEPT, [&] { return launch_swept(s, R, W, Gd, tS, tX, sweptc, sh, cp); }, "k_swept launch");
       if (st) return st;
     }
   }

@@ -160,3 +160,23 @@ def test_swept_off_and_state_errors():
         ctx.cost_bwd(q, ws)
     with pytest.raises(VaprError):
         ctx.set_cost_params(swept_steps=17)
+
+
+@pytest.mark.parametrize("n_cuboids", [10, 40, 64, 70])
+def test_swept_culling_is_exact(n_cuboids):
+    """The grid-culled sample tests (up to 64 cuboids; more fall back to testing every cuboid) give
+    bit-identical swept costs and gradients to testing every cuboid."""
+    need_gpu()
+    wl = swept_workload(seed=27, T=9, tpw=7, n_cuboids=n_cuboids)
+    shape = shape_of(wl)
+    q = dev(wl.q, torch.float32)
+    out = []
+    for cull in (True, False):
+        ctx = make_context(wl, {}, params={"swept_steps": 3, "w_swept": 80.0})
+        ctx.set_culling(cull)
+        _, ws = ctx.cost_fwd(q, shape)
+        torch.cuda.synchronize()
+        out.append((ctx.ws_export("swept_cost", ws, shape).cpu().numpy(), export_codes(ctx, "swept_grad", ws, shape)))
+    assert (out[0][0] > 0).any()
+    np.testing.assert_array_equal(out[0][0].view(np.uint32), out[1][0].view(np.uint32))
+    np.testing.assert_array_equal(out[0][1], out[1][1])
