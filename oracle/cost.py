@@ -39,6 +39,17 @@ positions, sampled at k interior points u_i = i / (k + 1), i = 1..k:
 
 and it is stored as its own tensor X (format of its own), added to G in the backward pass.
 
+Pose (goal) cost of inverse-kinematics optimisation (the IK stage turns the goal pose of the end
+effector into joint configurations, Sec. II-A, III-B; the paper gives no formula).  Reading used
+here: the end-effector frame is link 8, T_8 = [R | p]; with the goal pose [R_g | p_g] of the
+configuration's problem (one per world),
+
+  pose cost   w_gp |p - p_g|^2 + w_gr ||R - R_g||_F^2      (= w_gr (6 - 2 tr(R_g^T R)))
+
+Its joint gradient, from dp/dq_j = z_j x (p - o_j) and dR/dq_j = [z_j]_x R, is a force
+F = 2 w_gp (p - p_g) at p plus a couple tau = -2 w_gr m(R R_g^T) on link 8, with
+m(M) = (M_23 - M_32, M_31 - M_13, M_12 - M_21):  dC/dq_j = z_j . ((p - o_j) x F + tau).
+
 Parity pins (tests/test_oracle_cost.py): adjoint == explicit Jacobian to 1e-12; joint gradient ==
 central differences of the trajectory cost; sphere gradient == central differences of the
 configuration cost; self pair closed form; hand-computed single-sphere cases; at f32 with emulation
@@ -69,6 +80,8 @@ class CostParams:
     w_smooth: float = 1.0
     swept_steps: int = 0       # k interior samples per segment; 0 turns the swept term off
     w_swept: float = 100.0
+    w_goal_pos: float = 100.0  # pose cost weights (used when goals are given)
+    w_goal_rot: float = 10.0
 
 
 @dataclass
@@ -172,6 +185,47 @@ def swept_term(S: np.ndarray, radius: np.ndarray, pose: np.ndarray, half_ext: np
     return cost, X, margin
 
 
+def pose_term(T: np.ndarray, goal: np.ndarray, w_pos: float, w_rot: float):
+    """Pose cost [B] of link 8 against per-configuration goals [B, 3, 4], and the end-effector
+    wrench: force F [B, 3] at p and couple tau [B, 3] (see the module notes)."""
+    R, p = T[:, 8, :3, :3], T[:, 8, :3, 3]
+    Rg, pg = goal[:, :, :3], goal[:, :, 3]
+    dp = p - pg
+    dR = R - Rg
+    cost = w_pos * np.sum(dp * dp, axis=1) + w_rot * np.sum(dR * dR, axis=(1, 2))
+    M = R @ np.swapaxes(Rg, 1, 2)
+    m = np.stack([M[:, 1, 2] - M[:, 2, 1], M[:, 2, 0] - M[:, 0, 2], M[:, 0, 1] - M[:, 1, 0]], axis=1)
+    return cost, 2.0 * w_pos * dp, -2.0 * w_rot * m
+
+
+def pose_grad_adjoint(T: np.ndarray, F: np.ndarray, tau: np.ndarray) -> np.ndarray:
+    """Joint gradient of the pose cost from the end-effector wrench: z_j . ((p - o_j) x F + tau)."""
+    z, o = joint_axes(T)
+    p = T[:, 8, :3, 3]
+    arm = p[:, None, :] - o
+    return np.sum(z * (np.cross(arm, F[:, None, :]) + tau[:, None, :]), axis=2)
+
+
+def pose_grad_explicit(T: np.ndarray, goal: np.ndarray, w_pos: float, w_rot: float) -> np.ndarray:
+    """The same gradient by the chain rule on the matrices themselves: 2 w_gp (p - p_g).(z_j x
+    (p - o_j)) - 2 w_gr tr(R_g^T [z_j]_x R)."""
+    z, o = joint_axes(T)
+    R, p = T[:, 8, :3, :3], T[:, 8, :3, 3]
+    Rg, pg = goal[:, :, :3], goal[:, :, 3]
+    B = T.shape[0]
+    out = np.zeros((B, N_JOINTS))
+    for j in range(N_JOINTS):
+        zj = z[:, j]
+        dp = np.cross(zj, p - o[:, j])
+        Z = np.zeros((B, 3, 3))
+        Z[:, 0, 1], Z[:, 0, 2], Z[:, 1, 2] = -zj[:, 2], zj[:, 1], -zj[:, 0]
+        Z[:, 1, 0], Z[:, 2, 0], Z[:, 2, 1] = zj[:, 2], -zj[:, 1], zj[:, 0]
+        dR = Z @ R
+        out[:, j] = (2.0 * w_pos * np.sum((p - pg) * dp, axis=1)
+                     - 2.0 * w_rot * np.einsum("bij,bij->b", Rg, dR))
+    return out
+
+
 def bound_term(q: np.ndarray, q_lo: np.ndarray, q_hi: np.ndarray):
     over = np.maximum(0.0, q - q_hi)
     under = np.maximum(0.0, q_lo - q)
@@ -230,11 +284,14 @@ def _store(x: np.ndarray, prec: Optional[Precision], tensor: str):
 
 def fwd_bwd(robot, worlds, q: np.ndarray, traj_per_world: int, T: int, n_ls: int,
             prec: Optional[Precision] = None, params: CostParams = CostParams(),
-            upstream: Optional[np.ndarray] = None, emulate_scalars: bool = True) -> Dict[str, np.ndarray]:
+            upstream: Optional[np.ndarray] = None, emulate_scalars: bool = True,
+            goals: Optional[np.ndarray] = None) -> Dict[str, np.ndarray]:
     """Whole forward + backward pass for configurations q [B, 7] laid out as
     b = ((traj * n_ls + candidate) * T + t).  With `prec` None this is the unquantised FP64 truth;
     otherwise each stored tensor goes through the reference codec (f32 = FP32 rounding) where the
-    GPU path writes it.  `upstream` is d(loss)/d(cost_traj) per trajectory-candidate (default 1)."""
+    GPU path writes it.  `upstream` is d(loss)/d(cost_traj) per trajectory-candidate (default 1).
+    `goals` [n_worlds, 3, 4] adds the pose cost of each world's goal (inverse kinematics): its value
+    from the unquantised poses, its gradient from the poses the backward pass reads."""
     q = np.asarray(q, dtype=np.float64)
     B = q.shape[0]
     n_tc = B // T
@@ -276,9 +333,16 @@ def fwd_bwd(robot, worlds, q: np.ndarray, traj_per_world: int, T: int, n_ls: int
         out.update(X=X, X_hat=X_hat, swept_cost=wcost_st, swept_margin=wmargin)
     else:
         X_hat, wcost_st = 0.0, 0.0
+    if goals is not None:
+        gcfg = np.asarray(goals, dtype=np.float64)[wid]
+        pcost, _, _ = pose_term(Tk, gcfg, params.w_goal_pos, params.w_goal_rot)
+        pcost_st = fmts.fp32(pcost).astype(np.float64) if (prec is not None and emulate_scalars) else pcost
+        out["pose_cost"] = pcost_st
+    else:
+        pcost_st = 0.0
 
     # (4) aggregation
-    cfg = params.w_coll * np.sum(D_hat * D_hat, axis=1) + scost_st + params.w_bound * bcost_st + wcost_st
+    cfg = params.w_coll * np.sum(D_hat * D_hat, axis=1) + scost_st + params.w_bound * bcost_st + wcost_st + pcost_st
     smooth, sgr = smoothness_grad(q, T, n_ls)
     cost_traj = cfg.reshape(n_tc, T).sum(axis=1) + params.w_smooth * smooth
 
@@ -289,6 +353,9 @@ def fwd_bwd(robot, worlds, q: np.ndarray, traj_per_world: int, T: int, n_ls: int
     else:
         Tb, Pb = Tk, S
     Jsph = joint_grad_adjoint(Tb, Pb, G_hat + X_hat, robot.sphere_link)
+    if goals is not None:
+        _, Fp, taup = pose_term(Tb, gcfg, params.w_goal_pos, params.w_goal_rot)
+        Jsph = Jsph + pose_grad_adjoint(Tb, Fp, taup)
     up = np.ones(n_tc) if upstream is None else np.asarray(upstream, dtype=np.float64)
     J = up.repeat(T)[:, None] * (Jsph + params.w_bound * bgrad + params.w_smooth * sgr)
     out["J_codes"], J_hat = _store(J, prec, "joint_grad")

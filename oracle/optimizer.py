@@ -16,7 +16,8 @@ rule below is a reading (per trajectory, n = T * 7 variables, the start and goal
               pair, vectors and dots in FP64, d = fp32(-r); with no history, or if g.d >= 0 (the
               history is then cleared), the steepest-descent direction capped so that no joint
               moves more than max_step at alpha = 1: d = fp32(-g * min(1, max_step / |g|_inf))
-Gradients are zero on the pinned rows t = 0 and t = T - 1.
+Gradients are zero on the pinned rows t = 0 and t = T - 1 of trajectory optimisation; inverse
+kinematics (one configuration per "trajectory", T = 1) pins nothing.
 
 Parity pins (tests/test_oracle_optimizer.py): the two-loop direction equals the dense inverse-Hessian
 product of the BFGS updates built from the same pairs; secant condition H y = s for the newest
@@ -40,9 +41,11 @@ def fp32(x):
     return np.asarray(x, dtype=np.float64).astype(np.float32).astype(np.float64)
 
 
-def pin_rows(g: np.ndarray, T: int) -> np.ndarray:
-    """Zero the start and goal rows of a [T*7] (or [..., T*7]) gradient."""
+def pin_rows(g: np.ndarray, T: int, pin: bool = True) -> np.ndarray:
+    """Zero the start and goal rows of a [T*7] (or [..., T*7]) gradient (pin=False: a copy)."""
     g = np.array(g, dtype=np.float64, copy=True)
+    if not pin:
+        return g
     v = g.reshape(g.shape[:-1] + (T, N_JOINTS))
     v[..., 0, :] = 0.0
     v[..., T - 1, :] = 0.0
@@ -118,8 +121,9 @@ def candidates(x: np.ndarray, d: np.ndarray, n_ls: int) -> np.ndarray:
     return fp32(x[None] + a * d[None]).swapaxes(0, -2) if x.ndim > 1 else fp32(x[None] + a * d[None])
 
 
-def init_state(x0: np.ndarray, cost0: float, g0: np.ndarray, T: int, max_step: float = MAX_STEP) -> TrajState:
-    g = pin_rows(fp32(g0), T)
+def init_state(x0: np.ndarray, cost0: float, g0: np.ndarray, T: int, max_step: float = MAX_STEP,
+               pin: bool = True) -> TrajState:
+    g = pin_rows(fp32(g0), T, pin)
     return TrajState(x=fp32(x0), g=g, d=steepest(g, max_step), cost=float(cost0))
 
 
@@ -133,7 +137,7 @@ def select(cost: float, gd: float, cand_cost: np.ndarray) -> int:
 
 
 def step(st: TrajState, cand_cost: np.ndarray, cand_grad: np.ndarray, T: int, m: int = 8,
-         max_step: float = MAX_STEP) -> dict:
+         max_step: float = MAX_STEP, pin: bool = True) -> dict:
     """One iteration for one trajectory.  cand_grad [n_ls, n] are the joint gradients of the
     candidates (pinned rows are zeroed here).  Mutates st; returns what was decided."""
     n_ls = cand_cost.shape[0]
@@ -146,7 +150,7 @@ def step(st: TrajState, cand_cost: np.ndarray, cand_grad: np.ndarray, T: int, m:
         info["reset"] = True
         return info
     x_new = fp32(st.x + ALPHAS[i] * st.d)
-    g_new = pin_rows(fp32(cand_grad[i]), T)
+    g_new = pin_rows(fp32(cand_grad[i]), T, pin)
     s = fp32(x_new - st.x)
     y = fp32(g_new - st.g)
     sy = float(s @ y)
