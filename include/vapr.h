@@ -97,8 +97,12 @@ typedef struct {
  * segment adds (w_swept / k) sum_s sum_j d(p_j)^2 to configuration t (nothing for the last
  * timestep).  Its gradient w.r.t. the sphere centres, summed over the two segments at each
  * timestep, is the stored tensor X; the backward pass adds it to G.
+ * Pose cost (inverse kinematics, Sec. II-A, III-B; no formula in the paper): with goal poses set,
+ * each configuration also pays w_goal_pos |p - p_g|^2 + w_goal_rot ||R - R_g||_F^2 for its link-8
+ * pose [R | p] against the goal [R_g | p_g] of its world.
  * Defaults: eta 0.02 m, w_coll 100, w_self 100, w_bound 10, w_smooth 1, swept_steps 0 (off),
- * w_swept 100.  0 <= swept_steps <= 16.  Changing swept_steps changes the workspace size. */
+ * w_swept 100, w_goal_pos 100, w_goal_rot 10.  0 <= swept_steps <= 16.  Changing swept_steps
+ * changes the workspace size, as does setting or clearing goal poses. */
 typedef struct {
   float eta;
   float w_coll;
@@ -107,6 +111,8 @@ typedef struct {
   float w_smooth;
   int32_t swept_steps;
   float w_swept;
+  float w_goal_pos;  /* pose cost weights (used while goal poses are set, vapr_set_goals) */
+  float w_goal_rot;
 } vapr_cost_params;
 
 typedef struct vapr_ctx vapr_ctx;
@@ -146,6 +152,12 @@ int vapr_set_worlds(vapr_ctx* ctx, int n_worlds, int n_cuboids, const float* pos
 
 /* Select the storage format of each large tensor (Sec. IV-B, IV-C).  Unknown format or scale out
  * of range -> VAPR_E_INVALID.  Workspaces filled under another precision become invalid. */
+/* Goal poses of inverse kinematics, one per world: goal host [n][3][4], row-major [R_g | p_g] of
+ * link 8 (R_g a rotation to 1e-5).  n = 0 clears them (no pose cost).  Copied; a forward pass with
+ * goals needs n >= its n_worlds.  Inverse kinematics runs as trajectories of one timestep
+ * (T = 1), whose rows the optimiser leaves free (vapr_lbfgs_state.free_ends = 1). */
+int vapr_set_goals(vapr_ctx* ctx, int n, const float* goal);
+
 int vapr_set_precision(vapr_ctx* ctx, const vapr_precision* p);
 int vapr_get_precision(const vapr_ctx* ctx, vapr_precision* p);
 
@@ -204,7 +216,8 @@ int vapr_cost_bwd(vapr_ctx* ctx, const float* q, void* ws, size_t ws_bytes, cons
                   float* grad_q);
 
 /* Optimiser state for n_traj trajectories of T timesteps (n = T*7 variables each), all dev,
- * caller-owned (checkpointing is a copy of these buffers).  Rows t = 0 and t = T-1 are pinned. */
+ * caller-owned (checkpointing is a copy of these buffers).  Unless free_ends, rows t = 0 and
+ * t = T-1 keep their values (start and goal of a trajectory). */
 typedef struct {
   int32_t n_traj, T, n_ls, m;  /* 1 <= T <= 64, 1 <= n_ls <= 4, 1 <= m <= 8                      */
   float max_step;              /* > 0: cap on a joint's move at alpha = 1 along steepest descent  */
@@ -219,6 +232,8 @@ typedef struct {
   int32_t* hist_head;          /* [n_traj]    ring slot the next pair goes to                     */
   int32_t* accepted;           /* [n_traj]    last accepted candidate index, -1 = none            */
   int32_t* flags;              /* [n_traj]    bit 0 pair stored, bit 1 direction reset            */
+  int32_t free_ends;           /* 0: rows t = 0 and t = T-1 stay fixed (trajectory optimisation); */
+                               /* 1: every row moves (inverse kinematics, T = 1)                 */
 } vapr_lbfgs_state;
 
 /* Start the optimiser (Sec. III-B step (1)).  x must hold the start point; ws holds a forward +
@@ -330,7 +345,8 @@ typedef enum {
   VAPR_T_SELF_COST = 5,    /* FP32 [B]: w_self * sum over pairs of max(0, eta - e)^2       */
   VAPR_T_BOUND_COST = 6,   /* FP32 [B]: unweighted joint-limit cost                        */
   VAPR_T_SWEPT_GRAD = 7,   /* codes, [B][n_s][3]            (swept_steps > 0 only)          */
-  VAPR_T_SWEPT_COST = 8    /* FP32 [B]: swept cost of the segment (t, t+1)  (idem)         */
+  VAPR_T_SWEPT_COST = 8,   /* FP32 [B]: swept cost of the segment (t, t+1)  (idem)         */
+  VAPR_T_POSE_COST = 9     /* FP32 [B]: weighted pose cost      (goal poses set only)      */
 } vapr_tensor;
 
 /* Copy one stored tensor between a workspace and a dense buffer in canonical element order, in the

@@ -17,7 +17,8 @@ FORMAT_BITS = {F32: 32, F16: 16, BF16: 16, E4M3: 8, E5M2: 8, E3M2: 6, E2M1: 4}
 T_LINK_POSES, T_SPHERE_POS, T_SPHERE_DIST, T_SPHERE_GRAD, T_JOINT_GRAD, T_SELF_COST, T_BOUND_COST = range(7)
 ABI_VERSION = 2  # the structs below match include/vapr.h at this version
 TENSOR_IDS = {"link_poses": 0, "sphere_pos": 1, "sphere_dist": 2, "sphere_grad": 3, "joint_grad": 4,
-              "self_cost": 5, "bound_cost": 6, "swept_grad": 7, "swept_cost": 8}
+              "self_cost": 5, "bound_cost": 6, "swept_grad": 7, "swept_cost": 8,
+              "pose_cost": 9}
 KERNEL_NAMES = ("fk", "sphere_cost", "reduce", "adjoint", "optimizer", "codec", "repack", "swept")
 
 
@@ -40,7 +41,7 @@ class PrecisionC(ctypes.Structure):
 class CostParamsC(ctypes.Structure):
     _fields_ = [("eta", ctypes.c_float), ("w_coll", ctypes.c_float), ("w_self", ctypes.c_float),
                 ("w_bound", ctypes.c_float), ("w_smooth", ctypes.c_float), ("swept_steps", ctypes.c_int32),
-                ("w_swept", ctypes.c_float)]
+                ("w_swept", ctypes.c_float), ("w_goal_pos", ctypes.c_float), ("w_goal_rot", ctypes.c_float)]
 
 
 class GridInfoC(ctypes.Structure):
@@ -53,7 +54,7 @@ class LbfgsStateC(ctypes.Structure):
                 ("max_step", ctypes.c_float), ("x", ctypes.c_void_p), ("g", ctypes.c_void_p), ("d", ctypes.c_void_p), ("cost", ctypes.c_void_p),
                 ("s_hist", ctypes.c_void_p), ("y_hist", ctypes.c_void_p), ("rho", ctypes.c_void_p),
                 ("hist_len", ctypes.c_void_p), ("hist_head", ctypes.c_void_p), ("accepted", ctypes.c_void_p),
-                ("flags", ctypes.c_void_p)]
+                ("flags", ctypes.c_void_p), ("free_ends", ctypes.c_int32)]
 
 
 _P = ctypes.c_void_p
@@ -69,6 +70,7 @@ SIGNATURES = {
     "vapr_set_stream": (_I, [_P, _P]),
     "vapr_set_robot": (_I, [_P, _I, _P, _I, _P, _P, _P, _I, _P, _P, _P]),
     "vapr_set_worlds": (_I, [_P, _I, _I, _P, _P]),
+    "vapr_set_goals": (_I, [_P, _I, _P]),
     "vapr_set_precision": (_I, [_P, ctypes.POINTER(PrecisionC)]),
     "vapr_get_precision": (_I, [_P, ctypes.POINTER(PrecisionC)]),
     "vapr_set_cost_params": (_I, [_P, ctypes.POINTER(CostParamsC)]),

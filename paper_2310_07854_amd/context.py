@@ -67,7 +67,7 @@ class Shape:
 
 
 STORED = TENSORS + ("swept_grad",)
-SCALARS = ("self_cost", "bound_cost", "swept_cost")
+SCALARS = ("self_cost", "bound_cost", "swept_cost", "pose_cost")
 
 
 def precision_struct(spec: Mapping[str, FormatSpec], recompute_poses: bool = False) -> L.PrecisionC:
@@ -93,7 +93,8 @@ class Context:
         self.n_spheres = 0
         # the library's defaults (eta as the FP32 value the kernels compare with)
         self.cost_params = {"eta": float(np.float32(0.02)), "w_coll": 100.0, "w_self": 100.0, "w_bound": 10.0,
-                            "w_smooth": 1.0, "swept_steps": 0, "w_swept": 100.0}
+                            "w_smooth": 1.0, "swept_steps": 0, "w_swept": 100.0, "w_goal_pos": 100.0,
+                            "w_goal_rot": 10.0}
         self.precision: Dict[str, Tuple[str, int]] = {t: ("f32", 0) for t in STORED}
         self.recompute_poses = False
 
@@ -143,13 +144,25 @@ class Context:
         self.recompute_poses = recompute_poses
 
     def set_cost_params(self, eta=0.02, w_coll=100.0, w_self=100.0, w_bound=10.0, w_smooth=1.0,
-                        swept_steps: int = 0, w_swept: float = 100.0) -> None:
+                        swept_steps: int = 0, w_swept: float = 100.0, w_goal_pos: float = 100.0,
+                        w_goal_rot: float = 10.0) -> None:
         """Cost weights; swept_steps > 0 turns on the swept term with that many samples per
-        segment (the workspace then also holds the swept gradient and cost)."""
-        p = L.CostParamsC(eta, w_coll, w_self, w_bound, w_smooth, int(swept_steps), w_swept)
+        segment (the workspace then also holds the swept gradient and cost); the goal weights
+        apply while goal poses are set."""
+        p = L.CostParamsC(eta, w_coll, w_self, w_bound, w_smooth, int(swept_steps), w_swept, w_goal_pos, w_goal_rot)
         self._call("vapr_set_cost_params", ctypes.byref(p))
         self.cost_params = {"eta": float(p.eta), "w_coll": w_coll, "w_self": w_self, "w_bound": w_bound,
-                            "w_smooth": w_smooth, "swept_steps": int(swept_steps), "w_swept": w_swept}
+                            "w_smooth": w_smooth, "swept_steps": int(swept_steps), "w_swept": w_swept,
+                            "w_goal_pos": w_goal_pos, "w_goal_rot": w_goal_rot}
+
+    def set_goals(self, goals) -> None:
+        """Goal poses of inverse kinematics, one per world: [n, 3, 4] row-major [R_g | p_g] of the
+        end-effector link (None or n = 0 clears them)."""
+        if goals is None:
+            self._call("vapr_set_goals", 0, None)
+            return
+        g = _host(goals, np.float32).reshape(-1, 3, 4)
+        self._call("vapr_set_goals", int(g.shape[0]), _ptr(g) if g.size else None)
 
     def set_culling(self, enable: bool) -> None:
         """Exact cuboid culling in the sphere-cost stage (on by default; results are identical)."""
@@ -206,7 +219,7 @@ class Context:
     def tensor_count(self, name: str) -> int:
         return {"link_poses": 96, "sphere_pos": 3 * self.n_spheres, "sphere_dist": self.n_spheres,
                 "sphere_grad": 3 * self.n_spheres, "joint_grad": 7, "self_cost": 1, "bound_cost": 1,
-                "swept_grad": 3 * self.n_spheres, "swept_cost": 1}[name]
+                "swept_grad": 3 * self.n_spheres, "swept_cost": 1, "pose_cost": 1}[name]
 
     def tensor_nbytes(self, name: str, shape: Shape) -> int:
         n = shape.B * self.tensor_count(name)

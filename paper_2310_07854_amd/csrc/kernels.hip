@@ -280,7 +280,9 @@ __device__ __forceinline__ void place_group(const RobotArgs& R, const TV& S, int
 // the sphere groups and the two link-pose groups are shared out over the wavefronts.
 template <int FS>
 __global__ __launch_bounds__(256) void k_fk(const float* __restrict__ q, RobotArgs R, TV L, TV S,
-                                            float* __restrict__ bound, int64_t B, int store_L) {
+                                            float* __restrict__ bound, int64_t B, int store_L,
+                                            const float* __restrict__ goal, float* __restrict__ posec,
+                                            int64_t cfg_per_world, CostArgs cp) {
   __shared__ float tile[TILE_POSE_WORDS];
   const int wave = uniform(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int64_t b = (int64_t)blockIdx.x * 64 + lane;
@@ -291,6 +293,19 @@ __global__ __launch_bounds__(256) void k_fk(const float* __restrict__ q, RobotAr
     for (int j = 0; j < N_JOINTS; ++j) qv[j] = live ? q[b * N_JOINTS + j] : 0.f;
     if (live) bound[b] = bound_cost(R, qv);
     chain_to_tile(R.fixed, qv, tile, lane);
+    if (goal && live) {
+      // pose cost of link 8 against the goal of the configuration's world (read back from this
+      // lane's own tile entries)
+      const float* g = goal + (b / cfg_per_world) * LINK_VALUES;
+      float sp = 0.f, sr = 0.f;
+#pragma unroll
+      for (int k = 0; k < LINK_VALUES; ++k) {
+        const float e = tile[(N_FIXED * LINK_VALUES + k) * 64 + lane] - g[k];
+        if ((k & 3) == 3) sp = fmaf(e, e, sp);
+        else sr = fmaf(e, e, sr);
+      }
+      posec[b] = fmaf(cp.w_gp, sp, cp.w_gr * sr);
+    }
   }
   __syncthreads();
   if (!live) return;
@@ -929,7 +944,7 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 __global__ __launch_bounds__(256) void k_reduce(TV D, const float* __restrict__ selfc,
                                                 const float* __restrict__ boundc, const float* __restrict__ sweptc,
-                                                const float* __restrict__ q,
+                                                const float* __restrict__ posec, const float* __restrict__ q,
                                                 double* __restrict__ cost_traj, float* __restrict__ cost_cfg,
                                                 ShapeArgs sh, CostArgs cp, int n_s) {
   const int64_t tc = (int64_t)blockIdx.x * 4 + uniform(threadIdx.x >> 6);
@@ -953,6 +968,7 @@ __global__ __launch_bounds__(256) void k_reduce(TV D, const float* __restrict__ 
       }
       double c = (double)cp.w_c * sq + (double)selfc[b] + (double)cp.w_b * (double)boundc[b];
       if (sweptc) c += (double)sweptc[b];
+      if (posec) c += (double)posec[b];
       if (cost_cfg) cost_cfg[b] = (float)c;
       double sm = 0.0;
       if (t + 1 < T) {
@@ -1021,7 +1037,8 @@ __device__ __forceinline__ void link_wrench(const RobotArgs& R, const uint32_t* 
 template <int FG, bool HAS_X>
 __global__ __launch_bounds__(256) void k_adjoint(const float* __restrict__ q, RobotArgs R, TV L, TV G, TV X, TV J,
                                                  const double* __restrict__ up, float* __restrict__ grad_q,
-                                                 ShapeArgs sh, CostArgs cp, int recompute) {
+                                                 ShapeArgs sh, CostArgs cp, int recompute,
+                                                 const float* __restrict__ goal) {
   __shared__ float tile[TILE_POSE_WORDS];
   __shared__ float wrench[N_FIXED * 6 * 64];  // link l: force (3), moment (3) at ((l-1)*6 + k)*64 + lane
   const int wave = uniform(threadIdx.x >> 6), lane = threadIdx.x & 63;
@@ -1067,6 +1084,33 @@ __global__ __launch_bounds__(256) void k_adjoint(const float* __restrict__ q, Ro
   // tip to base: F_j, M_j over links >= j; J_j = z_j . (M_j - o_j x F_j)
   float Jv[J_GROUP];
   float F[3] = {0.f, 0.f, 0.f}, M[3] = {0.f, 0.f, 0.f};
+  if (goal) {
+    // pose cost: force 2 w_gp (p - p_g) at the end-effector origin p and couple -2 w_gr m(R R_g^T)
+    const float* T8 = tile + N_FIXED * LINK_VALUES * 64 + lane;
+    const float* g = goal + (b / sh.cfg_per_world) * LINK_VALUES;
+    float Rm[9], p[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) Rm[r * 3 + c] = T8[(r * 4 + c) * 64];
+      p[r] = T8[(r * 4 + 3) * 64];
+    }
+    float Fp[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) Fp[r] = 2.f * cp.w_gp * (p[r] - g[r * 4 + 3]);
+    // (R R_g^T)_{ik} = sum_c R_ic Rg_kc
+    auto RRg = [&](int i, int k) {
+      return fmaf(Rm[i * 3 + 0], g[k * 4 + 0], fmaf(Rm[i * 3 + 1], g[k * 4 + 1], Rm[i * 3 + 2] * g[k * 4 + 2]));
+    };
+    const float mx = RRg(1, 2) - RRg(2, 1), my = RRg(2, 0) - RRg(0, 2), mz = RRg(0, 1) - RRg(1, 0);
+    const float c2 = -2.f * cp.w_gr;
+    F[0] = Fp[0];
+    F[1] = Fp[1];
+    F[2] = Fp[2];
+    M[0] = fmaf(p[1], Fp[2], fmaf(-p[2], Fp[1], c2 * mx));
+    M[1] = fmaf(p[2], Fp[0], fmaf(-p[0], Fp[2], c2 * my));
+    M[2] = fmaf(p[0], Fp[1], fmaf(-p[1], Fp[0], c2 * mz));
+  }
 #pragma unroll
   for (int l = N_FIXED; l >= 1; --l) {
     const float* w = wrench + (l - 1) * 6 * 64 + lane;
@@ -1160,7 +1204,7 @@ __global__ __launch_bounds__(256) void k_optimizer(OptArgs o, TV J, const double
   }
   auto cand_grad = [&](int cand, int e) -> float {
     const int t = e / N_JOINTS, j = e - t * N_JOINTS;
-    if (t == 0 || t == T - 1) return 0.f;  // start and goal are pinned
+    if (o.pin && (t == 0 || t == T - 1)) return 0.f;  // start and goal are pinned
     const int64_t b = ((int64_t)tr * (mode == 0 ? 1 : n_ls) + cand) * T + t;
     return load_elem<J_GROUP>(J, b, 0, j);
   };
@@ -1516,11 +1560,13 @@ __global__ __launch_bounds__(256) void k_import(TV t, int tensor, int64_t B, int
 static inline unsigned blocks_for(int64_t n, int per_block) { return (unsigned)((n + per_block - 1) / per_block); }
 
 hipError_t launch_fk(hipStream_t s, const float* q, const RobotArgs& R, const TV& L, const TV& S, float* bound,
-                     int64_t B, int store_L) {
+                     int64_t B, int store_L, const float* goal, float* posec, int64_t cfg_per_world,
+                     const CostArgs& cp) {
   const dim3 grid(blocks_for(B, 64)), block(256);
   switch (S.fmt) {
 #define VAPR_FK_CASE(F) \
-  case F: hipLaunchKernelGGL(k_fk<F>, grid, block, 0, s, q, R, L, S, bound, B, store_L); break;
+  case F: hipLaunchKernelGGL(k_fk<F>, grid, block, 0, s, q, R, L, S, bound, B, store_L, goal, posec, cfg_per_world, cp); \
+    break;
     VAPR_FK_CASE(F32) VAPR_FK_CASE(F16) VAPR_FK_CASE(BF16) VAPR_FK_CASE(E4M3) VAPR_FK_CASE(E5M2)
     VAPR_FK_CASE(E3M2) VAPR_FK_CASE(E2M1)
 #undef VAPR_FK_CASE
@@ -1553,9 +1599,9 @@ hipError_t launch_sphere_cost_blk(hipStream_t s, const RobotArgs& R, const World
 }
 
 hipError_t launch_reduce(hipStream_t s, const TV& D, const float* selfc, const float* boundc, const float* sweptc,
-                         const float* q, double* cost_traj, float* cost_cfg, const ShapeArgs& sh, const CostArgs& cp,
-                         int n_s) {
-  hipLaunchKernelGGL(k_reduce, dim3(blocks_for(sh.n_tc, 4)), dim3(256), 0, s, D, selfc, boundc, sweptc, q,
+                         const float* posec, const float* q, double* cost_traj, float* cost_cfg, const ShapeArgs& sh,
+                         const CostArgs& cp, int n_s) {
+  hipLaunchKernelGGL(k_reduce, dim3(blocks_for(sh.n_tc, 4)), dim3(256), 0, s, D, selfc, boundc, sweptc, posec, q,
                      cost_traj, cost_cfg, sh, cp, n_s);
   return hipGetLastError();
 }
@@ -1577,13 +1623,13 @@ hipError_t launch_swept(hipStream_t s, const RobotArgs& R, const WorldArgs& W, c
 
 hipError_t launch_adjoint(hipStream_t s, const float* q, const RobotArgs& R, const TV& L, const TV& G, const TV& X,
                           const TV& J, const double* up, float* grad_q, const ShapeArgs& sh, const CostArgs& cp,
-                          int recompute) {
+                          int recompute, const float* goal) {
   const dim3 grid(blocks_for(sh.B, 64)), block(256);
   switch (G.fmt) {
 #define VAPR_ADJ_CASE(F) \
   case F:                                                                                                     \
-    if (X.P) hipLaunchKernelGGL((k_adjoint<F, true>), grid, block, 0, s, q, R, L, G, X, J, up, grad_q, sh, cp, recompute); \
-    else hipLaunchKernelGGL((k_adjoint<F, false>), grid, block, 0, s, q, R, L, G, X, J, up, grad_q, sh, cp, recompute); \
+    if (X.P) hipLaunchKernelGGL((k_adjoint<F, true>), grid, block, 0, s, q, R, L, G, X, J, up, grad_q, sh, cp, recompute, goal); \
+    else hipLaunchKernelGGL((k_adjoint<F, false>), grid, block, 0, s, q, R, L, G, X, J, up, grad_q, sh, cp, recompute, goal); \
     break;
     VAPR_ADJ_CASE(F32) VAPR_ADJ_CASE(F16) VAPR_ADJ_CASE(BF16) VAPR_ADJ_CASE(E4M3) VAPR_ADJ_CASE(E5M2)
     VAPR_ADJ_CASE(E3M2) VAPR_ADJ_CASE(E2M1)

@@ -54,10 +54,12 @@ struct CostArgs {
   float eta, w_c, w_s, w_b, w_v;
   int k_sw;    // swept samples per segment (0: off)
   float w_sw;
+  float w_gp, w_gr;  // pose cost weights (position, rotation)
 };
 
 struct OptArgs {
   int n_traj, T, n_ls, m;
+  int pin;  // 1: rows t = 0 and T - 1 keep zero gradient (trajectory optimisation)
   float max_step;
   float* x;
   float* g;
@@ -78,8 +80,10 @@ enum KernelId {
 };
 
 // launch wrappers (return hipError_t of the launch)
+// goal [W][12] (row-major [R | p] of link 8 per world) or null; posec [B] receives the pose cost
 hipError_t launch_fk(hipStream_t s, const float* q, const RobotArgs& R, const TV& L, const TV& S, float* bound,
-                     int64_t B, int store_L);
+                     int64_t B, int store_L, const float* goal, float* posec, int64_t cfg_per_world,
+                     const CostArgs& cp);
 hipError_t launch_sphere_cost(hipStream_t s, const RobotArgs& R, const WorldArgs& W, const TV& S, const TV& D,
                               const TV& G, float* selfc, const ShapeArgs& sh, const CostArgs& cp);
 // LDS bytes of the block-staged sphere-cost kernel (used while they fit in 64 KiB)
@@ -90,14 +94,14 @@ hipError_t launch_sphere_cost_blk(hipStream_t s, const RobotArgs& R, const World
 // swept term (cp.k_sw > 0): X and the swept cost per configuration from S
 hipError_t launch_swept(hipStream_t s, const RobotArgs& R, const WorldArgs& W, const GridArgs& Gd, const TV& S,
                         const TV& X, float* sweptc, const ShapeArgs& sh, const CostArgs& cp);
-// sweptc: per-configuration swept cost added to the configuration cost, or null
+// sweptc, posec: per-configuration swept and pose costs added to the configuration cost, or null
 hipError_t launch_reduce(hipStream_t s, const TV& D, const float* selfc, const float* boundc, const float* sweptc,
-                         const float* q, double* cost_traj, float* cost_cfg, const ShapeArgs& sh, const CostArgs& cp,
-                         int n_s);
-// X.P == 0: no swept gradient
+                         const float* posec, const float* q, double* cost_traj, float* cost_cfg, const ShapeArgs& sh,
+                         const CostArgs& cp, int n_s);
+// X.P == 0: no swept gradient; goal null: no pose cost
 hipError_t launch_adjoint(hipStream_t s, const float* q, const RobotArgs& R, const TV& L, const TV& G, const TV& X,
                           const TV& J, const double* up, float* grad_q, const ShapeArgs& sh, const CostArgs& cp,
-                          int recompute);
+                          int recompute, const float* goal);
 hipError_t launch_optimizer(hipStream_t s, const OptArgs& o, const TV& J, const double* cost_in, float* q_cand,
                             int mode);
 hipError_t launch_quantize(hipStream_t s, int fmt, float inv, const float* in, uint8_t* out, int64_t n);

@@ -13,8 +13,8 @@
 //   G  like S
 //   J  one group of 8 values (7 joints + a zero)          dw(8) planes
 //   X  swept sphere gradient, like S (only with the swept term on)
-// followed by FP32 arrays [Bp]: self cost, bound cost (then X) and, with the swept term, the swept
-// cost.  Regions are 256-byte aligned.
+// followed by FP32 arrays [Bp]: self cost, bound cost (then X), with the swept term the swept cost,
+// and with goal poses the pose cost.  Regions are 256-byte aligned.
 #pragma once
 #include <stddef.h>
 #include <stdint.h>
@@ -49,17 +49,18 @@ struct PrecisionCfg {
   TensorFormat t[6];  // L, S, D, G, J, X
   int recompute;
   int sweep;          // swept samples per segment (0: no X tensor and no swept cost)
+  int pose;           // 1: goal poses are set, the workspace holds the pose cost
 };
 
 enum { T_L = 0, T_S = 1, T_D = 2, T_G = 3, T_J = 4, T_X = 5 };
 // byte-offset slots of the FP32 arrays and of X
-enum { OFF_SELF = 5, OFF_BOUND = 6, OFF_X = 7, OFF_SWEPT = 8 };
+enum { OFF_SELF = 5, OFF_BOUND = 6, OFF_X = 7, OFF_SWEPT = 8, OFF_POSE = 9 };
 
 struct Layout {
   int64_t B, Bp, nblk;
   int n_s, n_groups;
   int P[6];             // planes per tensor (X: 0 without the swept term)
-  size_t off[9];        // byte offsets: L S D G J self bound X swept
+  size_t off[10];       // byte offsets: L S D G J self bound X swept pose
   size_t bytes;
 };
 
@@ -91,6 +92,8 @@ inline Layout make_layout(int64_t B, int n_s, const PrecisionCfg& pc) {
   o += align256((size_t)L.P[T_X] * (size_t)L.Bp * 4);
   L.off[OFF_SWEPT] = o;
   if (pc.sweep) o += align256((size_t)L.Bp * 4);
+  L.off[OFF_POSE] = o;
+  if (pc.pose) o += align256((size_t)L.Bp * 4);
   L.bytes = o;
   return L;
 }

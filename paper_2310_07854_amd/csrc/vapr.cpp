@@ -59,6 +59,9 @@ struct vapr_ctx {
   bool has_worlds = false;
   int n_worlds = 0, n_cuboids = 0;
   float* d_box = nullptr;
+  // goal poses of inverse kinematics (one per world), or none
+  int n_goals = 0;
+  float* d_goal = nullptr;
   std::vector<float> h_pose, h_half;  // host copies for the culling grid
   // culling grid (built lazily when robot, worlds or eta change)
   bool cull = true;
@@ -68,7 +71,7 @@ struct vapr_ctx {
   float r_max = 0.f;
   // settings
   PrecisionCfg prec{};
-  CostArgs params{0.02f, 100.f, 100.f, 10.f, 1.f, 0, 100.f};
+  CostArgs params{0.02f, 100.f, 100.f, 10.f, 1.f, 0, 100.f, 100.f, 10.f};
   std::unordered_map<const void*, WsRecord> ws;
   std::string err;
   // profiling
@@ -174,7 +177,7 @@ PrecisionCfg to_cfg(const vapr_precision& p) {
 bool same_prec(const PrecisionCfg& a, const PrecisionCfg& b) {
   for (int i = 0; i < 6; ++i)
     if (a.t[i].fmt != b.t[i].fmt || a.t[i].scale_exp != b.t[i].scale_exp) return false;
-  return a.recompute == b.recompute && a.sweep == b.sweep;
+  return a.recompute == b.recompute && a.sweep == b.sweep && a.pose == b.pose;
 }
 
 TV tensor_view(void* ws, const Layout& L, const PrecisionCfg& pc, int t) {
@@ -397,9 +400,18 @@ int run_fwd(vapr_ctx* ctx, int first, int n_worlds, int tpw, int T, int n_ls, co
   float* selfc = reinterpret_cast<float*>(static_cast<char*>(ws) + L.off[OFF_SELF]);
   float* boundc = reinterpret_cast<float*>(static_cast<char*>(ws) + L.off[OFF_BOUND]);
   float* sweptc = ctx->prec.sweep ? reinterpret_cast<float*>(static_cast<char*>(ws) + L.off[OFF_SWEPT]) : nullptr;
+  float* posec = ctx->prec.pose ? reinterpret_cast<float*>(static_cast<char*>(ws) + L.off[OFF_POSE]) : nullptr;
+  if (ctx->prec.pose && n_worlds > ctx->n_goals)
+    return fail(ctx, VAPR_E_INVALID, "n_worlds exceeds the uploaded goal poses");
   hipStream_t s = ctx->stream;
   if (first <= 1) {
-    st = timed(ctx, K_FK, [&] { return launch_fk(s, q, R, tL, tS, boundc, B, ctx->prec.recompute ? 0 : 1); },
+    const CostArgs cpk = ctx->params;
+    const float* goal = ctx->prec.pose ? ctx->d_goal : nullptr;
+    st = timed(ctx, K_FK,
+               [&] {
+                 return launch_fk(s, q, R, tL, tS, boundc, B, ctx->prec.recompute ? 0 : 1, goal, posec,
+                                  sh.cfg_per_world, cpk);
+               },
                "k_fk launch");
     if (st) return st;
   }
@@ -425,7 +437,7 @@ int run_fwd(vapr_ctx* ctx, int first, int n_worlds, int tpw, int T, int n_ls, co
   const CostArgs cp = ctx->params;
   const int n_s = ctx->n_s;
   st = timed(ctx, K_REDUCE,
-             [&] { return launch_reduce(s, tD, selfc, boundc, sweptc, q, cost_traj, cost_cfg, sh, cp, n_s); },
+             [&] { return launch_reduce(s, tD, selfc, boundc, sweptc, posec, q, cost_traj, cost_cfg, sh, cp, n_s); },
              "k_reduce launch");
   if (st) return st;
   ctx->ws[ws] = WsRecord{n_worlds, tpw, T, n_ls, B, ctx->prec, ctx->robot_gen};
@@ -482,6 +494,7 @@ OptArgs opt_args(const vapr_lbfgs_state* st) {
   o.hist_head = st->hist_head;
   o.accepted = st->accepted;
   o.flags = st->flags;
+  o.pin = st->free_ends ? 0 : 1;
   return o;
 }
 
@@ -543,6 +556,7 @@ int vapr_destroy(vapr_ctx* ctx) {
   (void)hipStreamSynchronize(ctx->stream);
   free_robot(ctx);
   (void)hipFree(ctx->d_box);
+  (void)hipFree(ctx->d_goal);
   (void)hipFree(ctx->d_grid);
   for (auto& pe : ctx->prof_live) {
     (void)hipEventDestroy(pe.start);
@@ -689,6 +703,29 @@ int vapr_set_worlds(vapr_ctx* ctx, int n_worlds, int n_cuboids, const float* pos
   return VAPR_OK;
 }
 
+int vapr_set_goals(vapr_ctx* ctx, int n, const float* goal) {
+  if (!ctx) return fail(nullptr, VAPR_E_INVALID, "null context");
+  if (n < 0 || n > 65536) return fail(ctx, VAPR_E_INVALID, "goal count out of range");
+  if (n > 0 && !goal) return fail(ctx, VAPR_E_INVALID, "null pointer");
+  if (n > 0 && !finite_all(goal, (size_t)n * 12)) return fail(ctx, VAPR_E_INVALID, "non-finite goal pose");
+  if (n > 0)
+    for (int i = 0; i < n; ++i)
+      if (!rotation_ok(goal + (size_t)i * 12)) return fail(ctx, VAPR_E_INVALID, "goal pose is not a rotation");
+  if (ctx->d_goal) {
+    VAPR_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    (void)hipFree(ctx->d_goal);
+    ctx->d_goal = nullptr;
+  }
+  ctx->n_goals = 0;
+  ctx->prec.pose = 0;
+  if (n == 0) return VAPR_OK;
+  int st = upload(ctx, &ctx->d_goal, goal, (size_t)n * 12);
+  if (st) return st;
+  ctx->n_goals = n;
+  ctx->prec.pose = 1;
+  return VAPR_OK;
+}
+
 int vapr_set_precision(vapr_ctx* ctx, const vapr_precision* p) {
   if (!ctx) return fail(nullptr, VAPR_E_INVALID, "null context");
   if (!p) return fail(ctx, VAPR_E_INVALID, "null precision");
@@ -696,9 +733,10 @@ int vapr_set_precision(vapr_ctx* ctx, const vapr_precision* p) {
                                     &p->sphere_grad, &p->joint_grad, &p->swept_grad};
   for (int i = 0; i < 6; ++i)
     if (!valid_format(*f[i])) return fail(ctx, VAPR_E_INVALID, "unknown format or scale out of range");
-  const int sweep = ctx->prec.sweep;
+  const int sweep = ctx->prec.sweep, pose = ctx->prec.pose;
   ctx->prec = to_cfg(*p);
   ctx->prec.sweep = sweep;
+  ctx->prec.pose = pose;
   return VAPR_OK;
 }
 
@@ -714,11 +752,13 @@ int vapr_get_precision(const vapr_ctx* ctx, vapr_precision* p) {
 int vapr_set_cost_params(vapr_ctx* ctx, const vapr_cost_params* p) {
   if (!ctx) return fail(nullptr, VAPR_E_INVALID, "null context");
   if (!p) return fail(ctx, VAPR_E_INVALID, "null params");
-  const float v[6] = {p->eta, p->w_coll, p->w_self, p->w_bound, p->w_smooth, p->w_swept};
-  if (!finite_all(v, 6) || !(p->eta > 0.f) || p->w_coll < 0.f || p->w_self < 0.f || p->w_bound < 0.f ||
-      p->w_smooth < 0.f || p->w_swept < 0.f || p->swept_steps < 0 || p->swept_steps > MAX_SWEEP)
+  const float v[8] = {p->eta, p->w_coll, p->w_self, p->w_bound, p->w_smooth, p->w_swept, p->w_goal_pos, p->w_goal_rot};
+  if (!finite_all(v, 8) || !(p->eta > 0.f) || p->w_coll < 0.f || p->w_self < 0.f || p->w_bound < 0.f ||
+      p->w_smooth < 0.f || p->w_swept < 0.f || p->swept_steps < 0 || p->swept_steps > MAX_SWEEP ||
+      p->w_goal_pos < 0.f || p->w_goal_rot < 0.f)
     return fail(ctx, VAPR_E_INVALID, "cost parameters out of range");
-  ctx->params = CostArgs{p->eta, p->w_coll, p->w_self, p->w_bound, p->w_smooth, p->swept_steps, p->w_swept};
+  ctx->params = CostArgs{p->eta,       p->w_coll,   p->w_self,     p->w_bound,    p->w_smooth,
+                         p->swept_steps, p->w_swept, p->w_goal_pos, p->w_goal_rot};
   ctx->prec.sweep = p->swept_steps;
   ctx->grid_valid = false;
   ctx->pairs_valid = false;
@@ -795,8 +835,12 @@ int vapr_cost_bwd(vapr_ctx* ctx, const float* q, void* ws, size_t ws_bytes, cons
            tJ = tensor_view(ws, L, ctx->prec, T_J), tX = tensor_view(ws, L, ctx->prec, T_X);
   const CostArgs cp = ctx->params;
   const int rec = ctx->prec.recompute;
+  const float* goal = ctx->prec.pose ? ctx->d_goal : nullptr;
+  if (goal && r.n_worlds > ctx->n_goals) return fail(ctx, VAPR_E_STATE, "goal poses changed since the forward pass");
   return timed(ctx, K_ADJOINT,
-               [&] { return launch_adjoint(ctx->stream, q, R, tL, tG, tX, tJ, grad_cost_traj, grad_q, sh, cp, rec); },
+               [&] {
+                 return launch_adjoint(ctx->stream, q, R, tL, tG, tX, tJ, grad_cost_traj, grad_q, sh, cp, rec, goal);
+               },
                "k_adjoint launch");
 }
 
@@ -940,7 +984,9 @@ static int ws_io(vapr_ctx* ctx, int n_worlds, int tpw, int T, int n_ls, void* ws
   int st = check_shape(ctx, n_worlds, tpw, T, n_ls, &B);
   if (st) return st;
   if (!ws || !buf) return fail(ctx, VAPR_E_INVALID, "null pointer");
-  if (tensor < VAPR_T_LINK_POSES || tensor > VAPR_T_SWEPT_COST) return fail(ctx, VAPR_E_INVALID, "unknown tensor");
+  if (tensor < VAPR_T_LINK_POSES || tensor > VAPR_T_POSE_COST) return fail(ctx, VAPR_E_INVALID, "unknown tensor");
+  if (tensor == VAPR_T_POSE_COST && !ctx->prec.pose)
+    return fail(ctx, VAPR_E_INVALID, "no pose cost: no goal poses are set");
   if ((tensor == VAPR_T_SWEPT_GRAD || tensor == VAPR_T_SWEPT_COST) && !ctx->prec.sweep)
     return fail(ctx, VAPR_E_INVALID, "no swept tensors: the swept term is off (swept_steps = 0)");
   const Layout L = make_layout(B, ctx->n_s, ctx->prec);
@@ -950,10 +996,14 @@ static int ws_io(vapr_ctx* ctx, int n_worlds, int tpw, int T, int n_ls, void* ws
     if (it == ctx->ws.end() || it->second.B != B || !same_prec(it->second.prec, ctx->prec))
       return fail(ctx, VAPR_E_STATE, "workspace does not hold this shape at the current precision");
   }
-  if (tensor == VAPR_T_SELF_COST || tensor == VAPR_T_BOUND_COST || tensor == VAPR_T_SWEPT_COST) {
+  if (tensor == VAPR_T_SELF_COST || tensor == VAPR_T_BOUND_COST || tensor == VAPR_T_SWEPT_COST ||
+      tensor == VAPR_T_POSE_COST) {
     if (buf_bytes < (size_t)B * 4) return fail(ctx, VAPR_E_INVALID, "buffer too small");
-    char* arr = static_cast<char*>(ws) +
-                L.off[tensor == VAPR_T_SELF_COST ? OFF_SELF : (tensor == VAPR_T_BOUND_COST ? OFF_BOUND : OFF_SWEPT)];
+    const int slot = tensor == VAPR_T_SELF_COST    ? OFF_SELF
+                     : tensor == VAPR_T_BOUND_COST ? OFF_BOUND
+                     : tensor == VAPR_T_SWEPT_COST ? OFF_SWEPT
+                                                   : OFF_POSE;
+    char* arr = static_cast<char*>(ws) + L.off[slot];
     st = timed(ctx, K_REPACK,
                [&] {
                  return direction == 0 ? hipMemcpyAsync(buf, arr, (size_t)B * 4, hipMemcpyDeviceToDevice, ctx->stream)

@@ -13,7 +13,10 @@ from .context import Context, Shape, _dev
 
 class TrajectoryOptimizer:
     def __init__(self, vctx: Context, n_worlds: int, traj_per_world: int, T: int, n_ls: int = 4, m: int = 8,
-                 max_step: float = 0.2):
+                 max_step: float = 0.2, pin_ends: bool = True):
+        """pin_ends: the first and last timestep stay fixed (trajectory optimisation); False lets
+        every row move (inverse kinematics: T = 1, one seed per trajectory, goals set on the
+        context)."""
         self.vctx = vctx
         self.shape1 = Shape(n_worlds, traj_per_world, T, 1)
         self.shape = Shape(n_worlds, traj_per_world, T, n_ls)
@@ -39,10 +42,10 @@ class TrajectoryOptimizer:
         self.ws1 = vctx.new_workspace(self.shape1)
         self._st = L.LbfgsStateC(n_traj, T, n_ls, m, max_step, *[t.data_ptr() for t in (
             self.x, self.g, self.d, self.cost, self.s_hist, self.y_hist, self.rho, self.hist_len, self.hist_head,
-            self.accepted, self.flags)])
+            self.accepted, self.flags)], 0 if pin_ends else 1)
 
     def init(self, x0: torch.Tensor) -> None:
-        """Start from x0 [n_traj, T, 7] (rows t=0 and t=T-1 are the pinned start and goal)."""
+        """Start from x0 [n_traj, T, 7] (with pin_ends, rows t=0 and t=T-1 are the fixed start and goal)."""
         self.x.copy_(x0.reshape(self.x.shape))
         q0 = self.x.reshape(-1, 7)
         c0, _ = self.vctx.cost_fwd(q0, self.shape1, ws=self.ws1)
