@@ -124,28 +124,26 @@ def culled_work(ctx, opt, prec):
     codes = ctx.ws_export("sphere_pos", opt.ws, shape)
     pos = dequantize(codes, fmt, B * N_SPHERES * 3, k).view(B, N_SPHERES, 3).cpu().numpy()
     cfg_per_world = B // N_WORLDS
-    needed = 0
-    issued = 0
     n_q = (N_SPHERES + 15) // 16 * 4
+    Bp = (B + 63) // 64 * 64
+    cand = np.zeros((Bp, n_q * 4), dtype=np.uint64)   # candidate masks [cfg, sphere], padded
     for w in range(N_WORLDS):
         info, mask = ctx.culling_grid(w)
-        p = pos[w * cfg_per_world:(w + 1) * cfg_per_world]
+        sl = slice(w * cfg_per_world, (w + 1) * cfg_per_world)
         if mask is None:
-            needed += p.shape[0] * N_SPHERES * N_CUBOIDS
+            cand[sl, :N_SPHERES] = np.uint64(2 ** 64 - 1) if N_CUBOIDS >= 64 else np.uint64((1 << N_CUBOIDS) - 1)
             continue
         m64 = mask[:, 0].astype(np.uint64)
         if mask.shape[1] > 1:
             m64 |= mask[:, 1].astype(np.uint64) << np.uint64(32)
         n = info["n"]
-        f = (p - np.array(info["origin"], dtype=np.float32)) * np.float32(info["inv_cell"])
+        f = (pos[sl] - np.array(info["origin"], dtype=np.float32)) * np.float32(info["inv_cell"])
         inside = np.all((f >= 0) & (f < np.float32(n)), axis=-1)
         v = np.floor(np.where(inside[..., None], f, 0)).astype(np.int64)
-        cand = np.where(inside, m64[(v[..., 2] * n + v[..., 1]) * n + v[..., 0]], np.uint64(0))  # [cfg, s]
-        needed += int(np.bitwise_count(cand).sum())
-        padded = np.zeros((cand.shape[0], n_q * 4), dtype=np.uint64)
-        padded[:, :N_SPHERES] = cand
-        quad = np.bitwise_or.reduce(padded.reshape(-1, 64, n_q, 4), axis=3)  # [wave, lane, quad]
-        issued += int(np.bitwise_count(quad).max(axis=1).sum()) * 4 * 64
+        cand[sl, :N_SPHERES] = np.where(inside, m64[(v[..., 2] * n + v[..., 1]) * n + v[..., 0]], np.uint64(0))
+    needed = int(np.bitwise_count(cand).sum())
+    quad = np.bitwise_or.reduce(cand.reshape(-1, 64, n_q, 4), axis=3)  # [wave, lane, quad]
+    issued = int(np.bitwise_count(quad).max(axis=1).sum()) * 4 * 64
     return {"needed_tests_per_cfg": needed / B, "issued_lane_tests_per_cfg": issued / B}
 
 
@@ -619,6 +617,96 @@ def swept_bench(args):
     print(json.dumps(line), flush=True)
 
 
+IK_SEEDS = 2000
+
+
+def ik_bench(args):
+    """Inverse kinematics: 64 problems (worlds of 64 cuboids) x 2,000 seeds, one configuration per
+    trajectory (128,000 configurations per step), pose cost against each problem's goal (the link-8
+    pose of a random configuration, so every goal is reachable) plus the collision, self and bound
+    costs; one optimiser iteration per step with free rows.  FP32 and the paper-like assignment."""
+    import torch
+
+    from paper_2310_07854_amd import Context, TrajectoryOptimizer
+    from synthetic import make_configs, make_robot, make_worlds
+
+    robot = make_robot(N_SPHERES, N_PAIRS)
+    worlds = make_worlds(N_WORLDS, N_CUBOIDS)
+    B = N_WORLDS * IK_SEEDS
+    ctx = Context(0)
+    ctx.set_robot(robot)
+    ctx.set_worlds(worlds.pose, worlds.half_ext)
+    # goals: link-8 poses of random configurations, computed by the library's own kinematics
+    qg = torch.tensor(make_configs(N_WORLDS, seed=77), dtype=torch.float32, device="cuda:0")
+    from paper_2310_07854_amd import Shape
+
+    ctx.set_precision({})
+    sh_g = Shape(N_WORLDS, 1, 1, 1)
+    _, wsg = ctx.cost_fwd(qg, sh_g)
+    L = ctx.ws_export("link_poses", wsg, sh_g).view(torch.float32).view(N_WORLDS, 8, 12)
+    goals = L[:, 7].reshape(N_WORLDS, 3, 4).cpu().numpy()
+    ctx.set_goals(goals)
+    x0 = torch.tensor(make_configs(B, seed=78), dtype=torch.float32, device="cuda:0").reshape(N_WORLDS * IK_SEEDS, 1, 7)
+    ctx.set_precision({})
+    shape = Shape(N_WORLDS, IK_SEEDS, 1, 1)
+    q = x0.reshape(-1, 7).contiguous()
+    _, ws = ctx.cost_fwd(q, shape)
+    ctx.cost_bwd(q, ws, want_grad=False)
+    names = ("link_poses", "sphere_pos", "sphere_dist", "sphere_grad", "joint_grad")
+    amax = {t: float(ctx.ws_export(t, ws, shape).view(torch.float32).abs().max()) for t in names}
+    out = {}
+    for name in ("f32", "paper_like"):
+        prec = with_scales(PRECISIONS[name], amax)
+        ctx.set_precision(prec)
+        opt = TrajectoryOptimizer(ctx, N_WORLDS, IK_SEEDS, 1, n_ls=N_LS, m=HIST_M, pin_ends=False)
+        opt.init(x0)
+        c0 = float(opt.cost.sum())
+        for _ in range(args.warmup):
+            opt.step()
+        torch.cuda.synchronize()
+        ctx.profile_enable(True)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            opt.step()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        prof = ctx.profile_read()
+        ctx.profile_enable(False)
+        kern = {kk: v[0] / max(v[1], 1) * 1e3 for kk, v in prof.items() if v[1]}
+        work = culled_work(ctx, opt, prec) if name == "paper_like" else None
+        out[name] = {"value": B * args.steps / dt, "ms_per_step": dt / args.steps * 1e3, "kernels_us": kern,
+                     "cost_first": c0, "cost_last": float(opt.cost.sum()),
+                     "formats": {kk: list(v) for kk, v in prec.items()}}
+        if work:
+            out[name]["culled"] = work
+        print(f"# ik {name}: {dt / args.steps * 1e3:.3f} ms/step, {B * args.steps / dt / 1e6:.1f} M evals/s, "
+              + ", ".join(f"{kk} {v:.1f}us" for kk, v in kern.items()), file=sys.stderr, flush=True)
+        del opt
+    ctx.close()
+    pl = out["paper_like"]
+    kern = pl["kernels_us"]
+    dom = max(kern, key=lambda k: kern[k])
+    if dom == "sphere_cost":
+        flops = FLOPS_PER_SPHERE_CUBOID * pl["culled"]["needed_tests_per_cfg"] + FLOPS_PER_PAIR * N_PAIRS
+        achieved = flops * B / (kern[dom] * 1e-6) / 1e12
+        roofline = {"kernel": "k_sphere_cost", "bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TFLOPS,
+                    "unit": "TFLOP/s", "frac": achieved / VALU_PEAK_TFLOPS, "flops_per_cfg": flops, "traffic": None}
+    else:
+        kb = kernel_bytes({kk: tuple(v) for kk, v in pl["formats"].items()})
+        achieved = kb.get(dom, 0.0) * B / (kern[dom] * 1e-6) / 1e9
+        roofline = {"kernel": "k_" + dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": achieved / HBM_PEAK_GBS, "traffic": None}
+    line = {"metric": "inverse-kinematics cost fwd+bwd evals/s (one optimiser iteration per step)",
+            "value": pl["value"], "unit": "evals/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": pl["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+            "dtype": "f32", "data": "synthetic",
+            "config": {"workload": f"{N_WORLDS} problems x {IK_SEEDS} seeds = {B:,} configurations per step; 7-joint "
+                                   f"arm, 60 spheres, 300 self pairs, 64 cuboids per world; pose cost + collision",
+                       "precision": "paper_like", "formats": pl["formats"]},
+            "fp32_value": out["f32"]["value"], "variants": out, "roofline": roofline, "cpu_baseline": None}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -630,6 +718,7 @@ def main():
     ap.add_argument("--seeding", action="store_true", help="run the learned-seeder study instead")
     ap.add_argument("--seed-infer", action="store_true", help="time the seeding network's inference instead")
     ap.add_argument("--swept", type=int, default=0, help="time the step with the swept term (k samples) instead")
+    ap.add_argument("--ik", action="store_true", help="time the inverse-kinematics workload instead")
     ap.add_argument("--seed-batch", type=int, default=65536)
     ap.add_argument("--seed-envs", type=int, default=2)
     ap.add_argument("--seed-problems", type=int, default=32768)
@@ -661,6 +750,9 @@ def main():
         return
     if args.swept:
         swept_bench(args)
+        return
+    if args.ik:
+        ik_bench(args)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (--gpus {args.gpus} requested): the cost path shards by world "

@@ -942,6 +942,39 @@ __device__ __forceinline__ double wave_sum(double v) {
   return (readlane_f64(v, 0) + readlane_f64(v, 16)) + (readlane_f64(v, 32) + readlane_f64(v, 48));
 }
 
+// configuration cost of b: w_c sum_s d_s^2 (FP64) + self + w_b bound (+ swept, + pose)
+__device__ __forceinline__ double cfg_cost(const TV& D, const float* __restrict__ selfc,
+                                          const float* __restrict__ boundc, const float* __restrict__ sweptc,
+                                          const float* __restrict__ posec, int64_t b, const CostArgs& cp, int n_s) {
+  const int ng = (n_s + SPH_GROUP - 1) / SPH_GROUP;
+  double sq = 0.0;
+  for (int g = 0; g < ng; ++g) {
+    float dv[SPH_GROUP];
+    load_group<SPH_GROUP>(D, b, g, dv);
+    const int active = min(SPH_GROUP, n_s - g * SPH_GROUP);
+#pragma unroll
+    for (int i = 0; i < SPH_GROUP; ++i)
+      if (i < active) sq = fma((double)dv[i], (double)dv[i], sq);
+  }
+  double c = (double)cp.w_c * sq + (double)selfc[b] + (double)cp.w_b * (double)boundc[b];
+  if (sweptc) c += (double)sweptc[b];
+  if (posec) c += (double)posec[b];
+  return c;
+}
+
+// one-timestep trajectories (inverse kinematics): one configuration per lane; the trajectory cost is
+// the configuration cost, as the general kernel's sum over one timestep gives
+__global__ __launch_bounds__(256) void k_reduce_t1(TV D, const float* __restrict__ selfc,
+                                                   const float* __restrict__ boundc, const float* __restrict__ sweptc,
+                                                   const float* __restrict__ posec, double* __restrict__ cost_traj,
+                                                   float* __restrict__ cost_cfg, ShapeArgs sh, CostArgs cp, int n_s) {
+  const int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (b >= sh.B) return;
+  const double c = cfg_cost(D, selfc, boundc, sweptc, posec, b, cp, n_s);
+  if (cost_cfg) cost_cfg[b] = (float)c;
+  cost_traj[b] = c;
+}
+
 __global__ __launch_bounds__(256) void k_reduce(TV D, const float* __restrict__ selfc,
                                                 const float* __restrict__ boundc, const float* __restrict__ sweptc,
                                                 const float* __restrict__ posec, const float* __restrict__ q,
@@ -951,24 +984,12 @@ __global__ __launch_bounds__(256) void k_reduce(TV D, const float* __restrict__ 
   if (tc >= sh.n_tc) return;
   const int lane = threadIdx.x & 63;
   const int T = sh.T;
-  const int ng = (n_s + SPH_GROUP - 1) / SPH_GROUP;
   double acc = 0.0;
   for (int t0 = 0; t0 < T; t0 += 64) {
     const int t = t0 + lane;
     if (t < T) {
       const int64_t b = tc * T + t;
-      double sq = 0.0;
-      for (int g = 0; g < ng; ++g) {
-        float dv[SPH_GROUP];
-        load_group<SPH_GROUP>(D, b, g, dv);
-        const int active = min(SPH_GROUP, n_s - g * SPH_GROUP);
-#pragma unroll
-        for (int i = 0; i < SPH_GROUP; ++i)
-          if (i < active) sq = fma((double)dv[i], (double)dv[i], sq);
-      }
-      double c = (double)cp.w_c * sq + (double)selfc[b] + (double)cp.w_b * (double)boundc[b];
-      if (sweptc) c += (double)sweptc[b];
-      if (posec) c += (double)posec[b];
+      const double c = cfg_cost(D, selfc, boundc, sweptc, posec, b, cp, n_s);
       if (cost_cfg) cost_cfg[b] = (float)c;
       double sm = 0.0;
       if (t + 1 < T) {
@@ -1173,12 +1194,41 @@ __device__ __forceinline__ float wave_max(float v) {
 }
 
 // -g capped so that its largest component is at most max_step (scale computed in FP64)
-template <int OPT_NE>
+// Reductions over the GL lanes that hold one trajectory: the whole wavefront (GL = 64), or one of
+// its eight 8-lane groups (GL = 8: the DPP steps inside each half-row, every lane of the group ends
+// with the group's value; the other groups are never read).
+template <int GL>
+__device__ __forceinline__ double group_sum(double v) {
+  if constexpr (GL == 64) {
+    return wave_sum(v);
+  } else {
+    static_assert(GL == 8, "8-lane or whole-wavefront groups");
+    v += dpp_f64<DPP_SWAP1>(v);
+    v += dpp_f64<DPP_SWAP2>(v);
+    v += dpp_f64<DPP_HALF_MIRROR>(v);
+    return v;
+  }
+}
+
+template <int GL>
+__device__ __forceinline__ float group_max(float v) {
+  if constexpr (GL == 64) {
+    return wave_max(v);
+  } else {
+    static_assert(GL == 8, "8-lane or whole-wavefront groups");
+    v = fmaxf(v, __uint_as_float(dpp_u32<DPP_SWAP1>(__float_as_uint(v))));
+    v = fmaxf(v, __uint_as_float(dpp_u32<DPP_SWAP2>(__float_as_uint(v))));
+    v = fmaxf(v, __uint_as_float(dpp_u32<DPP_HALF_MIRROR>(__float_as_uint(v))));
+    return v;
+  }
+}
+
+template <int OPT_NE, int GL>
 __device__ __forceinline__ void steepest(const float (&g)[OPT_NE], float max_step, float (&d)[OPT_NE]) {
   float gm = 0.f;
 #pragma unroll
   for (int k = 0; k < OPT_NE; ++k) gm = fmaxf(gm, fabsf(g[k]));
-  gm = wave_max(gm);
+  gm = group_max<GL>(gm);
   double scale = 1.0;
   if (gm > 0.f) scale = fmin(1.0, (double)max_step / (double)gm);
 #pragma unroll
@@ -1186,18 +1236,20 @@ __device__ __forceinline__ void steepest(const float (&g)[OPT_NE], float max_ste
 }
 __constant__ float c_alpha[MAX_LS] = {1.0f, 0.5f, 0.25f, 0.125f};
 
-template <int OPT_NE>
+// GL lanes per trajectory: 64 (one trajectory per wavefront, n <= 64 OPT_NE variables), or 8 for
+// one-configuration trajectories (n = 7: eight trajectories per wavefront, one variable per lane).
+template <int OPT_NE, int GL>
 __global__ __launch_bounds__(256) void k_optimizer(OptArgs o, TV J, const double* __restrict__ cost_in,
                                                    float* __restrict__ q_cand, int mode) {
-  const int tr = blockIdx.x * 4 + uniform(threadIdx.x >> 6);
-  if (tr >= o.n_traj) return;
-  const int lane = threadIdx.x & 63;
+  const int lane = GL == 64 ? (threadIdx.x & 63) : (threadIdx.x & (GL - 1));
+  const int tr = GL == 64 ? blockIdx.x * 4 + uniform(threadIdx.x >> 6) : (blockIdx.x * 256 + threadIdx.x) / GL;
+  if (tr >= o.n_traj) return;  // a whole group
   const int T = o.T, n = T * N_JOINTS, m = o.m, n_ls = o.n_ls;
   const int64_t vb = (int64_t)tr * n;
   float x[OPT_NE], g[OPT_NE], d[OPT_NE];
 #pragma unroll
   for (int k = 0; k < OPT_NE; ++k) {
-    const int e = lane + 64 * k;
+    const int e = lane + GL * k;
     x[k] = e < n ? o.x[vb + e] : 0.f;
     g[k] = e < n ? o.g[vb + e] : 0.f;
     d[k] = e < n ? o.d[vb + e] : 0.f;
@@ -1213,10 +1265,10 @@ __global__ __launch_bounds__(256) void k_optimizer(OptArgs o, TV J, const double
   if (mode == 0) {
 #pragma unroll
     for (int k = 0; k < OPT_NE; ++k) {
-      const int e = lane + 64 * k;
+      const int e = lane + GL * k;
       g[k] = e < n ? cand_grad(0, e) : 0.f;
     }
-    steepest(g, o.max_step, d);
+    steepest<OPT_NE, GL>(g, o.max_step, d);
     len = 0;
     head = 0;
     if (lane == 0) o.cost[tr] = cost_in[tr];
@@ -1224,7 +1276,7 @@ __global__ __launch_bounds__(256) void k_optimizer(OptArgs o, TV J, const double
     double gd = 0.0;
 #pragma unroll
     for (int k = 0; k < OPT_NE; ++k) gd = fma((double)g[k], (double)d[k], gd);
-    gd = wave_sum(gd);
+    gd = group_sum<GL>(gd);
     const double c0 = o.cost[tr];
     int sel = -1;
     for (int i = 0; i < n_ls; ++i) {
@@ -1254,7 +1306,7 @@ __global__ __launch_bounds__(256) void k_optimizer(OptArgs o, TV J, const double
       double sy = 0.0, ss = 0.0, yy = 0.0;
 #pragma unroll
       for (int k = 0; k < OPT_NE; ++k) {
-        const int e = lane + 64 * k;
+        const int e = lane + GL * k;
         const float xn = fmaf(alpha, d[k], x[k]);
         const float gn = e < n ? cand_grad(sel, e) : 0.f;
         s[k] = e < n ? xn - x[k] : 0.f;
@@ -1265,15 +1317,15 @@ __global__ __launch_bounds__(256) void k_optimizer(OptArgs o, TV J, const double
         ss = fma((double)s[k], (double)s[k], ss);
         yy = fma((double)y[k], (double)y[k], yy);
       }
-      sy = wave_sum(sy);
-      ss = wave_sum(ss);
-      yy = wave_sum(yy);
+      sy = group_sum<GL>(sy);
+      ss = group_sum<GL>(ss);
+      yy = group_sum<GL>(yy);
       if (lane == 0) o.cost[tr] = cost_in[(int64_t)tr * n_ls + sel];
       if (sy > 1e-10 * sqrt(ss) * sqrt(yy)) {
         const int64_t hb = ((int64_t)tr * m + head) * n;
 #pragma unroll
         for (int k = 0; k < OPT_NE; ++k) {
-          const int e = lane + 64 * k;
+          const int e = lane + GL * k;
           if (e < n) {
             o.s_hist[hb + e] = s[k];
             o.y_hist[hb + e] = y[k];
@@ -1297,7 +1349,7 @@ __global__ __launch_bounds__(256) void k_optimizer(OptArgs o, TV J, const double
           rho_h[it] = o.rho[(int64_t)tr * m + slot];
 #pragma unroll
           for (int k = 0; k < OPT_NE; ++k) {
-            const int e = lane + 64 * k;
+            const int e = lane + GL * k;
             hs[it][k] = e < n ? o.s_hist[hb + e] : 0.f;
             hy[it][k] = e < n ? o.y_hist[hb + e] : 0.f;
           }
@@ -1320,8 +1372,8 @@ __global__ __launch_bounds__(256) void k_optimizer(OptArgs o, TV J, const double
               yy0 = fma((double)hy[it][k], (double)hy[it][k], yy0);
             }
           }
-          a_it[it] = rho_h[it] * wave_sum(sq);
-          if (it == 0) gamma = wave_sum(sy0) / wave_sum(yy0);
+          a_it[it] = rho_h[it] * group_sum<GL>(sq);
+          if (it == 0) gamma = group_sum<GL>(sy0) / group_sum<GL>(yy0);
 #pragma unroll
           for (int k = 0; k < OPT_NE; ++k) qv[k] = fma(-a_it[it], (double)hy[it][k], qv[k]);
         }
@@ -1339,7 +1391,7 @@ __global__ __launch_bounds__(256) void k_optimizer(OptArgs o, TV J, const double
             asm volatile("" : "+v"(hs[it][k]), "+v"(hy[it][k]));
             yr = fma((double)hy[it][k], qv[k], yr);
           }
-          const double beta = rho_h[it] * wave_sum(yr);
+          const double beta = rho_h[it] * group_sum<GL>(yr);
 #pragma unroll
           for (int k = 0; k < OPT_NE; ++k) qv[k] = fma(a_it[it] - beta, (double)hs[it][k], qv[k]);
         }
@@ -1350,20 +1402,20 @@ __global__ __launch_bounds__(256) void k_optimizer(OptArgs o, TV J, const double
         d[k] = (float)(-qv[k]);
         gdn = fma((double)g[k], (double)d[k], gdn);
       }
-      gdn = wave_sum(gdn);
+      gdn = group_sum<GL>(gdn);
       if (len == 0) {
-        steepest(g, o.max_step, d);
+        steepest<OPT_NE, GL>(g, o.max_step, d);
       } else if (gdn >= 0.0) {
         len = 0;
         head = 0;
         flags |= 2;
-        steepest(g, o.max_step, d);
+        steepest<OPT_NE, GL>(g, o.max_step, d);
       }
     }
   }
 #pragma unroll
   for (int k = 0; k < OPT_NE; ++k) {
-    const int e = lane + 64 * k;
+    const int e = lane + GL * k;
     if (e < n) {
       o.x[vb + e] = x[k];
       o.g[vb + e] = g[k];
@@ -1601,8 +1653,12 @@ hipError_t launch_sphere_cost_blk(hipStream_t s, const RobotArgs& R, const World
 hipError_t launch_reduce(hipStream_t s, const TV& D, const float* selfc, const float* boundc, const float* sweptc,
                          const float* posec, const float* q, double* cost_traj, float* cost_cfg, const ShapeArgs& sh,
                          const CostArgs& cp, int n_s) {
-  hipLaunchKernelGGL(k_reduce, dim3(blocks_for(sh.n_tc, 4)), dim3(256), 0, s, D, selfc, boundc, sweptc, posec, q,
-                     cost_traj, cost_cfg, sh, cp, n_s);
+  if (sh.T == 1)
+    hipLaunchKernelGGL(k_reduce_t1, dim3(blocks_for(sh.B, 256)), dim3(256), 0, s, D, selfc, boundc, sweptc, posec,
+                       cost_traj, cost_cfg, sh, cp, n_s);
+  else
+    hipLaunchKernelGGL(k_reduce, dim3(blocks_for(sh.n_tc, 4)), dim3(256), 0, s, D, selfc, boundc, sweptc, posec, q,
+                       cost_traj, cost_cfg, sh, cp, n_s);
   return hipGetLastError();
 }
 
@@ -1641,10 +1697,15 @@ hipError_t launch_adjoint(hipStream_t s, const float* q, const RobotArgs& R, con
 
 hipError_t launch_optimizer(hipStream_t s, const OptArgs& o, const TV& J, const double* cost_in, float* q_cand,
                             int mode) {
+  if (o.T == 1) {
+    hipLaunchKernelGGL((k_optimizer<1, 8>), dim3(blocks_for(o.n_traj, 32)), dim3(256), 0, s, o, J, cost_in, q_cand,
+                       mode);
+    return hipGetLastError();
+  }
   const dim3 grid(blocks_for(o.n_traj, 4)), block(256);
   switch ((o.T * N_JOINTS + 63) / 64) {
 #define VAPR_OPT_CASE(NE) \
-  case NE: hipLaunchKernelGGL(k_optimizer<NE>, grid, block, 0, s, o, J, cost_in, q_cand, mode); break;
+  case NE: hipLaunchKernelGGL((k_optimizer<NE, 64>), grid, block, 0, s, o, J, cost_in, q_cand, mode); break;
     VAPR_OPT_CASE(1) VAPR_OPT_CASE(2) VAPR_OPT_CASE(3) VAPR_OPT_CASE(4) VAPR_OPT_CASE(5) VAPR_OPT_CASE(6)
     VAPR_OPT_CASE(7)
 #undef VAPR_OPT_CASE
