@@ -62,6 +62,7 @@ from typing import Dict, Optional, Tuple
 
 import numpy as np
 
+from . import exmy
 from . import formats as fmts
 from .geometry import obb_signed_distance
 from .kinematics import (N_JOINTS, forward_kinematics, joint_axes, link_pose_values, poses_from_values,
@@ -275,11 +276,16 @@ def world_index(B: int, traj_per_world: int, T: int, n_ls: int) -> np.ndarray:
 
 
 def _store(x: np.ndarray, prec: Optional[Precision], tensor: str):
-    """(codes, stored float64 values) at a storage point; unquantised pass-through when prec is None."""
+    """(codes, stored float64 values) at a storage point; unquantised pass-through when prec is None.
+    A storage format (f32, f16, bf16, e4m3, e5m2, e3m2, e2m1) goes through its codec; any other
+    'eXmY' is emulated: the FP32 value rounded to that type (codes: its FP32 bit patterns)."""
     if prec is None:
         return None, np.asarray(x, dtype=np.float64)
     fmt, k = prec.get(tensor)
-    return fmts.roundtrip(x, fmt, k)
+    if fmt in fmts.FORMATS:
+        return fmts.roundtrip(x, fmt, k)
+    E, M = exmy.parse(fmt)
+    return exmy.roundtrip(x, E, M, k)
 
 
 def fwd_bwd(robot, worlds, q: np.ndarray, traj_per_world: int, T: int, n_ls: int,

@@ -1,0 +1,120 @@
+"""Generic ExMy rounding: the paper's full format space, emulated.  TEST INFRASTRUCTURE.
+
+The paper searches 21 floating-point types from FP4 to FP32, each one sign bit, E exponent bits and
+M mantissa bits (Sec. IV-A), and evaluates them by quantising every stored tensor to the type and
+back to FP32 at each kernel invocation (Sec. IV-B).  It names 13 of the 21 in its results
+(Table III): E2M1, E2M2, E3M1, E2M3, E3M2, E4M3, E5M2, E6M6, E5M9, E6M8, E5M10, E8M7, and E8M23
+(FP32); it states that exactly three of them (E5M10, E8M7, E8M23) are 16 bits or wider, and lists
+FP4, FP5, FP6, FP8, FP10, FP16 and FP32 as the widths of interest.  Readings used here:
+
+  ladder     the 13 named types plus E1M2 (FP4), E1M3 and E4M0 (FP5), E4M1 (FP6), E3M4 (FP8),
+             E5M4 and E4M5 (FP10) and E5M7 (FP13), 21 in all, ordered by width
+  bias       2^(E-1) - 1; subnormals kept (exponent field 0)
+  specials   E5M10, E8M7 and E8M23 follow IEEE (top exponent field reserved for Inf/NaN; a value
+             that rounds past the largest finite one becomes Inf); every other type has no Inf or
+             NaN: all exponent fields hold finite values and overflow saturates to the largest
+             finite value, Inf inputs too (the convention of the FP6/FP4 storage formats)
+  rounding   to the nearest representable value, ties to even mantissa
+  NaN        passes through as NaN (emulation only; no codes are formed)
+  scale      as for the storage formats: y = fp32(fp32(x) 2^-k), value = fp32(round(y) 2^k)
+
+The rounding of a finite y != 0 with |y| = m 2^e (1 <= m < 2): the grid spacing is
+2^(max(e, e_min) - M) with e_min = 1 - bias; |y| is divided by it (exact), rounded half-to-even to an
+integer and multiplied back (exact).
+
+Parity pins (tests/test_oracle_exmy.py): E3M2 and E2M1 equal the storage codecs' round trips, E5M10
+equals IEEE binary16, E8M7 the bfloat16 round trip and E8M23 the identity, on dense and random
+inputs; the largest finite values by formula; brute-force nearest-value search over every
+representable value of small types; exact midpoints to even; monotonicity.
+"""
+from __future__ import annotations
+
+import re
+from typing import List, Tuple
+
+import numpy as np
+
+IEEE = {(5, 10), (8, 7), (8, 23)}
+
+LADDER: List[Tuple[int, int]] = [
+    (1, 2), (2, 1),                       # FP4
+    (1, 3), (2, 2), (3, 1), (4, 0),       # FP5
+    (2, 3), (3, 2), (4, 1),               # FP6
+    (3, 4), (4, 3), (5, 2),               # FP8
+    (4, 5), (5, 4),                       # FP10
+    (5, 7), (6, 6),                       # FP13
+    (5, 9), (6, 8),                       # FP15
+    (5, 10), (8, 7),                      # FP16
+    (8, 23),                              # FP32
+]
+
+
+def name(E: int, M: int) -> str:
+    return f"e{E}m{M}"
+
+
+def parse(fmt: str) -> Tuple[int, int]:
+    """'eXmY' -> (X, Y); 'f32', 'f16', 'bf16' -> their (E, M)."""
+    alias = {"f32": (8, 23), "f16": (5, 10), "bf16": (8, 7)}
+    if fmt in alias:
+        return alias[fmt]
+    m = re.fullmatch(r"e(\d+)m(\d+)", fmt)
+    if not m:
+        raise ValueError(f"not an ExMy format: {fmt}")
+    E, M = int(m.group(1)), int(m.group(2))
+    check(E, M)
+    return E, M
+
+
+def check(E: int, M: int) -> None:
+    if not (1 <= E <= 8 and 0 <= M <= 23):
+        raise ValueError("ExMy needs 1 <= E <= 8 and 0 <= M <= 23")
+
+
+def bits(E: int, M: int) -> int:
+    return 1 + E + M
+
+
+def limits(E: int, M: int) -> Tuple[int, int, float]:
+    """(e_min, e_max, largest finite value)."""
+    check(E, M)
+    bias = (1 << (E - 1)) - 1
+    e_min = 1 - bias
+    e_max = ((1 << E) - 2 if (E, M) in IEEE else (1 << E) - 1) - bias
+    return e_min, e_max, (2.0 - 2.0 ** -M) * 2.0 ** e_max
+
+
+def round_value(y, E: int, M: int) -> np.ndarray:
+    """Nearest ExMy value of float64 inputs y (float32 values in practice), as float64."""
+    y = np.asarray(y, dtype=np.float64)
+    e_min, _, vmax = limits(E, M)
+    a = np.abs(y)
+    fin = np.isfinite(a) & (a > 0)
+    _, ex = np.frexp(np.where(fin, a, 1.0))          # a = m 2^ex, 0.5 <= m < 1
+    q = np.maximum(ex - 1, e_min) - M                # grid spacing exponent
+    r = np.ldexp(np.rint(np.ldexp(np.where(fin, a, 0.0), -q)), q)
+    over = r > vmax
+    r = np.where(over, np.inf if (E, M) in IEEE else vmax, r)
+    r = np.where(np.isinf(a), np.inf if (E, M) in IEEE else vmax, r)
+    r = np.where(a == 0, 0.0, r)
+    out = np.copysign(r, y)
+    return np.where(np.isnan(y), np.nan, out)
+
+
+def roundtrip(x, E: int, M: int, k: int = 0) -> Tuple[np.ndarray, np.ndarray]:
+    """(float32 bit patterns of the stored values, the values as float64) of the emulated write and
+    read of x with scale exponent k."""
+    x32 = np.asarray(x, dtype=np.float64).astype(np.float32).astype(np.float64)
+    with np.errstate(over="ignore", invalid="ignore"):
+        y = (x32 * 2.0 ** -k).astype(np.float32).astype(np.float64)
+        v = (round_value(y, E, M) * 2.0 ** k).astype(np.float32)
+    return v.view(np.uint32), v.astype(np.float64)
+
+
+def representable(E: int, M: int) -> np.ndarray:
+    """Every finite non-negative value of the type, ascending (small types only)."""
+    e_min, e_max, _ = limits(E, M)
+    vals = [m * 2.0 ** (e_min - M) for m in range(1 << M)]   # zero and subnormals
+    for e in range(e_min, e_max + 1):
+        vals += [(1.0 + m / (1 << M)) * 2.0 ** e for m in range(1 << M)]
+    return np.array(sorted(set(vals)))
