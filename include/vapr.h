@@ -59,7 +59,14 @@ typedef enum {
   VAPR_E4M3 = 3,  /* bias 7, max 448, NaN = S.1111.111    */
   VAPR_E5M2 = 4,  /* bias 15, max 57344                   */
   VAPR_E3M2 = 5,  /* FP6, bias 3, max 28, no Inf/NaN      */
-  VAPR_E2M1 = 6   /* FP4, bias 1, max 6, no Inf/NaN       */
+  VAPR_E2M1 = 6,  /* FP4, bias 1, max 6, no Inf/NaN       */
+  VAPR_EXMY = 7   /* an emulated type of the paper's search space (Sec. IV-A, IV-B): the tensor is
+                     stored as FP32 values rounded to exp_bits / man_bits at every write, the way
+                     the paper evaluates formats without converter hardware.  1 <= exp_bits <= 8,
+                     0 <= man_bits <= 23; bias 2^(exp_bits-1) - 1, subnormals kept, ties to even;
+                     E5M10 and the 8-exponent-bit types (E8M7, E8M23, ...) follow IEEE (overflow
+                     to Inf), every other type has no Inf/NaN and saturates; NaN passes through.
+                     Takes a scale like the others. */
 } vapr_format;
 
 /* One stored tensor's format with a power-of-two scale: a value x is stored as
@@ -69,6 +76,8 @@ typedef enum {
 typedef struct {
   int32_t fmt;
   int32_t scale_exp;
+  int32_t exp_bits;  /* VAPR_EXMY only (ignored otherwise) */
+  int32_t man_bits;
 } vapr_tensor_format;
 
 /* Precision assignment, one format per large tensor (Sec. IV-B).  recompute_poses != 0 drops the
@@ -260,6 +269,10 @@ int vapr_optimizer_step(vapr_ctx* ctx, const vapr_lbfgs_state* st, const void* w
  * write and read).  in/out dev; out holds vapr_packed_bytes(fmt, n) bytes in the packed layout.
  * stream: hipStream_t or NULL.  0 <= n <= 2^32. */
 int vapr_quantize(int fmt, int scale_exp, const float* in, void* out, int64_t n, void* hip_stream);
+/* Emulated ExMy rounding (VAPR_EXMY rules): out[i] = round(in[i] 2^-scale_exp) 2^scale_exp, FP32
+ * device arrays of n elements (in == out allowed). */
+int vapr_round_exmy(int exp_bits, int man_bits, int scale_exp, const float* in, float* out, int64_t n,
+                    void* hip_stream);
 int vapr_dequantize(int fmt, int scale_exp, const void* in, float* out, int64_t n, void* hip_stream);
 
 /* ---- Learned trajectory seeder ----------------------------------------------------------------

@@ -10,10 +10,12 @@ FP4, FP5, FP6, FP8, FP10, FP16 and FP32 as the widths of interest.  Readings use
   ladder     the 13 named types plus E1M2 (FP4), E1M3 and E4M0 (FP5), E4M1 (FP6), E3M4 (FP8),
              E5M4 and E4M5 (FP10) and E5M7 (FP13), 21 in all, ordered by width
   bias       2^(E-1) - 1; subnormals kept (exponent field 0)
-  specials   E5M10, E8M7 and E8M23 follow IEEE (top exponent field reserved for Inf/NaN; a value
-             that rounds past the largest finite one becomes Inf); every other type has no Inf or
-             NaN: all exponent fields hold finite values and overflow saturates to the largest
-             finite value, Inf inputs too (the convention of the FP6/FP4 storage formats)
+  specials   E5M10 and every type with 8 exponent bits (E8M7, E8M23, ...) follow IEEE (top exponent
+             field reserved for Inf/NaN; a value that rounds past the largest finite one becomes
+             Inf): an 8-bit exponent without the reserved field would reach 2^128, beyond the FP32
+             values the emulation holds.  Every other type has no Inf or NaN: all exponent fields
+             hold finite values and overflow saturates to the largest finite value, Inf inputs too
+             (the convention of the FP6/FP4 storage formats)
   rounding   to the nearest representable value, ties to even mantissa
   NaN        passes through as NaN (emulation only; no codes are formed)
   scale      as for the storage formats: y = fp32(fp32(x) 2^-k), value = fp32(round(y) 2^k)
@@ -24,7 +26,7 @@ integer and multiplied back (exact).
 
 Parity pins (tests/test_oracle_exmy.py): E3M2 and E2M1 equal the storage codecs' round trips, E5M10
 equals IEEE binary16, E8M7 the bfloat16 round trip and E8M23 the identity, on dense and random
-inputs; the largest finite values by formula; brute-force nearest-value search over every
+inputs; the largest finite values by formula (E8M4 too); brute-force nearest-value search over every
 representable value of small types; exact midpoints to even; monotonicity.
 """
 from __future__ import annotations
@@ -34,7 +36,10 @@ from typing import List, Tuple
 
 import numpy as np
 
-IEEE = {(5, 10), (8, 7), (8, 23)}
+
+def ieee(E: int, M: int) -> bool:
+    return (E, M) == (5, 10) or E == 8
+
 
 LADDER: List[Tuple[int, int]] = [
     (1, 2), (2, 1),                       # FP4
@@ -80,7 +85,7 @@ def limits(E: int, M: int) -> Tuple[int, int, float]:
     check(E, M)
     bias = (1 << (E - 1)) - 1
     e_min = 1 - bias
-    e_max = ((1 << E) - 2 if (E, M) in IEEE else (1 << E) - 1) - bias
+    e_max = ((1 << E) - 2 if ieee(E, M) else (1 << E) - 1) - bias
     return e_min, e_max, (2.0 - 2.0 ** -M) * 2.0 ** e_max
 
 
@@ -94,8 +99,8 @@ def round_value(y, E: int, M: int) -> np.ndarray:
     q = np.maximum(ex - 1, e_min) - M                # grid spacing exponent
     r = np.ldexp(np.rint(np.ldexp(np.where(fin, a, 0.0), -q)), q)
     over = r > vmax
-    r = np.where(over, np.inf if (E, M) in IEEE else vmax, r)
-    r = np.where(np.isinf(a), np.inf if (E, M) in IEEE else vmax, r)
+    r = np.where(over, np.inf if ieee(E, M) else vmax, r)
+    r = np.where(np.isinf(a), np.inf if ieee(E, M) else vmax, r)
     r = np.where(a == 0, 0.0, r)
     out = np.copysign(r, y)
     return np.where(np.isnan(y), np.nan, out)

@@ -5,6 +5,7 @@ Loading fails loudly when libvapr.so has not been built: there is no fallback im
 from __future__ import annotations
 
 import ctypes
+import re
 import os
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libvapr.so")
@@ -13,6 +14,18 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libvapr.so"
 OK, E_INVALID, E_OOM, E_HIP, E_UNSUPPORTED, E_STATE = range(6)
 F32, F16, BF16, E4M3, E5M2, E3M2, E2M1 = range(7)
 FORMAT_IDS = {"f32": F32, "f16": F16, "bf16": BF16, "e4m3": E4M3, "e5m2": E5M2, "e3m2": E3M2, "e2m1": E2M1}
+EXMY = 7  # an emulated ExMy type: any other "eXmY" format name
+
+
+def format_id(fmt: str):
+    """(format id, exponent bits, mantissa bits) of a format name: a storage format, or an emulated
+    "eXmY" type (1 <= X <= 8, 0 <= Y <= 23)."""
+    if fmt in FORMAT_IDS:
+        return FORMAT_IDS[fmt], 0, 0
+    m = re.fullmatch(r"e(\d+)m(\d+)", fmt)
+    if not m:
+        raise ValueError(f"unknown format {fmt!r}")
+    return EXMY, int(m.group(1)), int(m.group(2))
 FORMAT_BITS = {F32: 32, F16: 16, BF16: 16, E4M3: 8, E5M2: 8, E3M2: 6, E2M1: 4}
 T_LINK_POSES, T_SPHERE_POS, T_SPHERE_DIST, T_SPHERE_GRAD, T_JOINT_GRAD, T_SELF_COST, T_BOUND_COST = range(7)
 ABI_VERSION = 2  # the structs below match include/vapr.h at this version
@@ -29,7 +42,8 @@ class VaprError(RuntimeError):
 
 
 class TensorFormat(ctypes.Structure):
-    _fields_ = [("fmt", ctypes.c_int32), ("scale_exp", ctypes.c_int32)]
+    _fields_ = [("fmt", ctypes.c_int32), ("scale_exp", ctypes.c_int32), ("exp_bits", ctypes.c_int32),
+                ("man_bits", ctypes.c_int32)]
 
 
 class PrecisionC(ctypes.Structure):
@@ -71,6 +85,7 @@ SIGNATURES = {
     "vapr_set_robot": (_I, [_P, _I, _P, _I, _P, _P, _P, _I, _P, _P, _P]),
     "vapr_set_worlds": (_I, [_P, _I, _I, _P, _P]),
     "vapr_set_goals": (_I, [_P, _I, _P]),
+    "vapr_round_exmy": (_I, [_I, _I, _I, _P, _P, _I64, _P]),
     "vapr_set_precision": (_I, [_P, ctypes.POINTER(PrecisionC)]),
     "vapr_get_precision": (_I, [_P, ctypes.POINTER(PrecisionC)]),
     "vapr_set_cost_params": (_I, [_P, ctypes.POINTER(CostParamsC)]),

@@ -75,7 +75,8 @@ def precision_struct(spec: Mapping[str, FormatSpec], recompute_poses: bool = Fal
     for name in STORED:
         v = spec.get(name, "f32")
         fmt, k = (v, 0) if isinstance(v, str) else v
-        setattr(p, name, L.TensorFormat(L.FORMAT_IDS[fmt], int(k)))
+        fid, e_bits, m_bits = L.format_id(fmt)
+        setattr(p, name, L.TensorFormat(fid, int(k), e_bits, m_bits))
     p.recompute_poses = 1 if recompute_poses else 0
     return p
 
@@ -225,7 +226,7 @@ class Context:
         n = shape.B * self.tensor_count(name)
         if name in SCALARS:
             return 4 * n
-        fmt = L.FORMAT_IDS[self.precision[name][0]]
+        fmt = L.format_id(self.precision[name][0])[0]
         return int(self._lib.vapr_packed_bytes(fmt, n))
 
     def ws_export(self, name: str, ws: torch.Tensor, shape: Shape) -> torch.Tensor:
@@ -266,6 +267,15 @@ def quantize(x: torch.Tensor, fmt: str, scale_exp: int = 0) -> torch.Tensor:
     out = torch.empty((nb + 3) // 4 * 4, dtype=torch.uint8, device=x.device)
     L.check(lib.vapr_quantize(f, scale_exp, _dev(x, torch.float32, "x"), out.data_ptr(), n, _stream_handle()))
     return out[:nb]
+
+
+def round_exmy(x: torch.Tensor, exp_bits: int, man_bits: int, scale_exp: int = 0) -> torch.Tensor:
+    """float32 device tensor x rounded to the emulated ExMy type (a new tensor)."""
+    lib = L.load()
+    out = torch.empty_like(x)
+    L.check(lib.vapr_round_exmy(exp_bits, man_bits, scale_exp, _dev(x, torch.float32, "x"), out.data_ptr(), x.numel(),
+                                _stream_handle()))
+    return out
 
 
 def dequantize(codes: torch.Tensor, fmt: str, n: int, scale_exp: int = 0) -> torch.Tensor:

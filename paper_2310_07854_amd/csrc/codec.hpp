@@ -38,6 +38,36 @@ __host__ __device__ constexpr int format_bits(int f) {
 // dwords holding a packed group of n values
 __host__ __device__ constexpr int group_dwords(int f, int n) { return (format_bits(f) * n + 31) / 32; }
 
+// ---- generic ExMy rounding (emulated formats) --------------------------------------------------
+//
+// The nearest value of the type with E exponent and M mantissa bits (bias 2^(E-1) - 1, subnormals
+// kept), ties to even: the grid spacing at |y| = m 2^e is 2^(max(e, e_min) - M), and |y| is scaled
+// to it, rounded to an integer and scaled back (each step exact in FP32 for E <= 8, M <= 23).
+// E5M10 and the types with 8 exponent bits follow IEEE (top exponent field reserved, rounding past
+// the largest finite value gives Inf; without the reserved field an 8-bit exponent would reach
+// 2^128, beyond FP32); every other type is finite-only and saturates, Inf inputs included.  Zero and
+// NaN pass through.
+__device__ __forceinline__ float exmy_round(float y, int E, int M) {
+  const float a = fabsf(y);
+  if (!(a > 0.f)) return y;
+  const int bias = (1 << (E - 1)) - 1;
+  const int e_min = 1 - bias;
+  const bool ieee = (E == 5 && M == 10) || E == 8;
+  const int e_max = (ieee ? (1 << E) - 2 : (1 << E) - 1) - bias;
+  const float vmax = ldexpf(2.f - ldexpf(1.f, -M), e_max);
+  float r;
+  if (a == INFINITY) {
+    r = ieee ? INFINITY : vmax;
+  } else {
+    const int eb = (int)((__float_as_uint(a) >> 23) & 0xffu);
+    const int e = eb ? eb - 127 : -127;
+    const int q = (e > e_min ? e : e_min) - M;
+    r = ldexpf(rintf(ldexpf(a, -q)), q);
+    if (r > vmax) r = ieee ? INFINITY : vmax;
+  }
+  return copysignf(r, y);
+}
+
 // ---- scalar encode / decode -------------------------------------------------------------------
 
 template <int F>

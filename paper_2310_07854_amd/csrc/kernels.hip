@@ -46,10 +46,23 @@ __device__ __forceinline__ uint32_t* lane_base(const TV& t, int64_t b) {
   return t.p + ((b >> 6) * t.P) * 64 + (b & 63);
 }
 
+// an emulated ExMy tensor stores the FP32 value of each element rounded to its type
+template <int N>
+__device__ __forceinline__ void exmy_group(const TV& t, float (&v)[N]) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] = exmy_round(v[i] * t.inv, t.xe, t.xm) * t.scale;
+}
+
 template <int F, int N>
-__device__ __forceinline__ void store_group_t(const TV& t, int64_t b, int slot, const float (&v)[N]) {
+__device__ __forceinline__ void store_group_t(const TV& t, int64_t b, int slot, const float (&v_in)[N]) {
   constexpr int DW = group_dwords(F, N);
   uint32_t w[DW];
+  float v[N];
+#pragma unroll
+  for (int i = 0; i < N; ++i) v[i] = v_in[i];
+  if constexpr (F == F32) {
+    if (t.xe) exmy_group<N>(t, v);
+  }
   encode_group<F, N>(v, t.inv, w);
   uint32_t* base = lane_base(t, b) + slot * DW * 64;
 #pragma unroll
@@ -131,6 +144,9 @@ template <int F, int N>
 __device__ __forceinline__ void roundtrip_t(const TV& t, float (&v)[N]) {
   constexpr int DW = group_dwords(F, N);
   uint32_t w[DW];
+  if constexpr (F == F32) {
+    if (t.xe) exmy_group<N>(t, v);
+  }
   encode_group<F, N>(v, t.inv, w);
   decode_group<F, N>(w, t.scale, v);
 }
@@ -1712,6 +1728,18 @@ hipError_t launch_optimizer(hipStream_t s, const OptArgs& o, const TV& J, const 
     default: return hipErrorInvalidValue;
   }
   static_assert(OPT_NE_MAX == 7, "optimizer instantiations cover T <= 64");
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_round_exmy(int E, int M, float inv, float scale, const float* __restrict__ in,
+                                                    float* __restrict__ out, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) out[i] = exmy_round(in[i] * inv, E, M) * scale;
+}
+
+hipError_t launch_round_exmy(hipStream_t s, int E, int M, float inv, float scale, const float* in, float* out,
+                             int64_t n) {
+  hipLaunchKernelGGL(k_round_exmy, dim3(blocks_for(n, 256)), dim3(256), 0, s, E, M, inv, scale, in, out, n);
   return hipGetLastError();
 }
 

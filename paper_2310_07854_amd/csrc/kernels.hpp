@@ -41,6 +41,7 @@ struct TV {  // one stored tensor inside a workspace
   int P;
   float scale;  // 2^k
   float inv;    // 2^-k
+  int xe, xm;   // xe > 0: an emulated ExMy type, stored as the FP32 values rounded to it (fmt F32)
 };
 
 struct ShapeArgs {
@@ -105,6 +106,8 @@ hipError_t launch_adjoint(hipStream_t s, const float* q, const RobotArgs& R, con
 hipError_t launch_optimizer(hipStream_t s, const OptArgs& o, const TV& J, const double* cost_in, float* q_cand,
                             int mode);
 hipError_t launch_quantize(hipStream_t s, int fmt, float inv, const float* in, uint8_t* out, int64_t n);
+hipError_t launch_round_exmy(hipStream_t s, int E, int M, float inv, float scale, const float* in, float* out,
+                             int64_t n);
 hipError_t launch_dequantize(hipStream_t s, int fmt, float scale, const uint8_t* in, float* out, int64_t n);
 // tensor: T_L .. T_J; per-configuration element count ecfg; direction 0 export (ws -> flat), 1 import
 hipError_t launch_repack(hipStream_t s, int tensor, const TV& t, int64_t B, int ecfg, int n_s, uint8_t* flat,

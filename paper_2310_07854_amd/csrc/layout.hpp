@@ -41,8 +41,9 @@ constexpr int MAX_HIST = 8;
 constexpr int MAX_SWEEP = 16;       // swept samples per segment
 
 struct TensorFormat {
-  int fmt;
+  int fmt;        // storage format (F32 for an emulated ExMy type)
   int scale_exp;
+  int xe, xm;     // emulated ExMy type (xe > 0), else 0
 };
 
 struct PrecisionCfg {

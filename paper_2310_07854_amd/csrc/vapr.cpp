@@ -101,6 +101,9 @@ int hip_fail(vapr_ctx* ctx, hipError_t e, const char* what) {
   } while (0)
 
 bool valid_format(const vapr_tensor_format& f) {
+  if (f.fmt == VAPR_EXMY)
+    return f.exp_bits >= 1 && f.exp_bits <= 8 && f.man_bits >= 0 && f.man_bits <= 23 && f.scale_exp >= -16 &&
+           f.scale_exp <= 16;
   if (f.fmt < VAPR_F32 || f.fmt > VAPR_E2M1) return false;
   if (f.scale_exp < -16 || f.scale_exp > 16) return false;
   if (f.fmt == VAPR_F32 && f.scale_exp != 0) return false;
@@ -161,14 +164,25 @@ void free_robot(vapr_ctx* ctx) {
   ctx->has_robot = false;
 }
 
+// an emulated ExMy type is stored as FP32 values rounded to it
+TensorFormat tensor_format(const vapr_tensor_format& f) {
+  if (f.fmt == VAPR_EXMY) return TensorFormat{F32, f.scale_exp, f.exp_bits, f.man_bits};
+  return TensorFormat{f.fmt, f.scale_exp, 0, 0};
+}
+
+vapr_tensor_format api_format(const TensorFormat& t) {
+  if (t.xe) return vapr_tensor_format{VAPR_EXMY, t.scale_exp, t.xe, t.xm};
+  return vapr_tensor_format{t.fmt, t.scale_exp, 0, 0};
+}
+
 PrecisionCfg to_cfg(const vapr_precision& p) {
   PrecisionCfg c{};
-  c.t[T_L] = {p.link_poses.fmt, p.link_poses.scale_exp};
-  c.t[T_S] = {p.sphere_pos.fmt, p.sphere_pos.scale_exp};
-  c.t[T_D] = {p.sphere_dist.fmt, p.sphere_dist.scale_exp};
-  c.t[T_G] = {p.sphere_grad.fmt, p.sphere_grad.scale_exp};
-  c.t[T_J] = {p.joint_grad.fmt, p.joint_grad.scale_exp};
-  c.t[T_X] = {p.swept_grad.fmt, p.swept_grad.scale_exp};
+  c.t[T_L] = tensor_format(p.link_poses);
+  c.t[T_S] = tensor_format(p.sphere_pos);
+  c.t[T_D] = tensor_format(p.sphere_dist);
+  c.t[T_G] = tensor_format(p.sphere_grad);
+  c.t[T_J] = tensor_format(p.joint_grad);
+  c.t[T_X] = tensor_format(p.swept_grad);
   c.recompute = p.recompute_poses ? 1 : 0;
   return c;
 }
@@ -176,7 +190,9 @@ PrecisionCfg to_cfg(const vapr_precision& p) {
 // same formats, pose mode and swept sampling (which decides whether X and the swept cost exist)
 bool same_prec(const PrecisionCfg& a, const PrecisionCfg& b) {
   for (int i = 0; i < 6; ++i)
-    if (a.t[i].fmt != b.t[i].fmt || a.t[i].scale_exp != b.t[i].scale_exp) return false;
+    if (a.t[i].fmt != b.t[i].fmt || a.t[i].scale_exp != b.t[i].scale_exp || a.t[i].xe != b.t[i].xe ||
+        a.t[i].xm != b.t[i].xm)
+      return false;
   return a.recompute == b.recompute && a.sweep == b.sweep && a.pose == b.pose;
 }
 
@@ -187,6 +203,8 @@ TV tensor_view(void* ws, const Layout& L, const PrecisionCfg& pc, int t) {
   v.P = L.P[t];
   v.scale = std::ldexp(1.0f, pc.t[t].scale_exp);
   v.inv = std::ldexp(1.0f, -pc.t[t].scale_exp);
+  v.xe = pc.t[t].xe;
+  v.xm = pc.t[t].xm;
   return v;
 }
 
@@ -744,7 +762,7 @@ int vapr_get_precision(const vapr_ctx* ctx, vapr_precision* p) {
   if (!ctx || !p) return fail(nullptr, VAPR_E_INVALID, "null pointer");
   vapr_tensor_format* f[6] = {&p->link_poses, &p->sphere_pos, &p->sphere_dist,
                               &p->sphere_grad, &p->joint_grad, &p->swept_grad};
-  for (int i = 0; i < 6; ++i) *f[i] = {ctx->prec.t[i].fmt, ctx->prec.t[i].scale_exp};
+  for (int i = 0; i < 6; ++i) *f[i] = api_format(ctx->prec.t[i]);
   p->recompute_poses = ctx->prec.recompute;
   return VAPR_OK;
 }
@@ -855,12 +873,14 @@ int vapr_optimizer_step(vapr_ctx* ctx, const vapr_lbfgs_state* st, const void* w
 }
 
 size_t vapr_packed_bytes(int fmt, int64_t n) {
+  if (fmt == VAPR_EXMY) return n < 0 ? 0 : (size_t)n * 4;  // FP32 values
   if (fmt < VAPR_F32 || fmt > VAPR_E2M1 || n < 0) return 0;
   return (size_t)((n * format_bits(fmt) + 7) / 8);
 }
 
 static int codec_check(int fmt, int scale_exp, const void* in, const void* out, int64_t n) {
-  vapr_tensor_format f{fmt, scale_exp};
+  vapr_tensor_format f{fmt, scale_exp, 0, 0};
+  if (fmt == VAPR_EXMY) return fail(nullptr, VAPR_E_INVALID, "emulated ExMy types have no codes: use vapr_round_exmy");
   if (!valid_format(f)) return fail(nullptr, VAPR_E_INVALID, "unknown format or scale out of range");
   if (n < 0 || n > ((int64_t)1 << 32)) return fail(nullptr, VAPR_E_INVALID, "element count out of range");
   if (n > 0 && (!in || !out)) return fail(nullptr, VAPR_E_INVALID, "null pointer");
@@ -883,6 +903,18 @@ int vapr_dequantize(int fmt, int scale_exp, const void* in, float* out, int64_t 
   hipError_t e = launch_dequantize(static_cast<hipStream_t>(hip_stream), fmt, std::ldexp(1.0f, scale_exp),
                                    static_cast<const uint8_t*>(in), out, n);
   return e == hipSuccess ? VAPR_OK : hip_fail(nullptr, e, "k_dequantize launch");
+}
+
+int vapr_round_exmy(int exp_bits, int man_bits, int scale_exp, const float* in, float* out, int64_t n,
+                    void* hip_stream) {
+  vapr_tensor_format f{VAPR_EXMY, scale_exp, exp_bits, man_bits};
+  if (!valid_format(f)) return fail(nullptr, VAPR_E_INVALID, "ExMy bits or scale out of range");
+  if (n < 0 || n > ((int64_t)1 << 32)) return fail(nullptr, VAPR_E_INVALID, "element count out of range");
+  if (n == 0) return VAPR_OK;
+  if (!in || !out) return fail(nullptr, VAPR_E_INVALID, "null pointer");
+  hipError_t e = launch_round_exmy(static_cast<hipStream_t>(hip_stream), exp_bits, man_bits,
+                                   std::ldexp(1.0f, -scale_exp), std::ldexp(1.0f, scale_exp), in, out, n);
+  return e == hipSuccess ? VAPR_OK : hip_fail(nullptr, e, "k_round_exmy launch");
 }
 
 // ---- learned seeder ---------------------------------------------------------------------------

@@ -1,0 +1,109 @@
+"""GPU emulation of the paper's ExMy format space (vapr_round_exmy and VAPR_EXMY stored tensors)
+against the oracle (oracle/exmy.py): bit-exact rounding for all 21 ladder types, emulated types
+that coincide with storage formats giving bit-identical end-to-end results, and a mixed emulated
+assignment against the oracle's emulation."""
+import numpy as np
+import pytest
+
+from oracle import cost as OC
+from oracle import exmy as X
+from oracle import formats as F
+from synthetic import make_workload
+from tests.gpu_helpers import cost_tolerance, dev, grad_tolerance, kink_free, make_context, need_gpu, shape_of, torch
+
+pytestmark = pytest.mark.gpu
+
+
+def _inputs():
+    rng = np.random.default_rng(1)
+    mags = 2.0 ** rng.uniform(-149, 128, size=300_000) * rng.choice([-1, 1], size=300_000)
+    dense = np.linspace(-600.0, 600.0, 600_001)
+    special = np.array([0.0, -0.0, np.inf, -np.inf, 1e-45, -1e-45, 1.1754942e-38, 3.4028235e38, -3.4028235e38,
+                        6.0, 6.5, 28.0, 30.0, 448.0, 480.0, 496.0, 65504.0, 65519.99, 65520.0, 1e30])
+    return F.fp32(np.concatenate([mags, dense, special])).astype(np.float64)
+
+
+@pytest.mark.parametrize("E,M", X.LADDER + [(8, 4), (1, 0), (7, 12)])
+@pytest.mark.parametrize("k", [0, -4, 5])
+def test_round_exmy_bit_exact(E, M, k):
+    need_gpu()
+    from paper_2310_07854_amd.context import round_exmy
+
+    x = _inputs()
+    got = round_exmy(dev(x, torch.float32), E, M, k).cpu().numpy()
+    _, ref = X.roundtrip(x, E, M, k)
+    ref32 = ref.astype(np.float32)
+    nan = np.isnan(ref32)
+    assert np.array_equal(np.isnan(got), nan)
+    np.testing.assert_array_equal(got[~nan].view(np.uint32), ref32[~nan].view(np.uint32))
+
+
+@pytest.mark.parametrize("native,emulated", [("f16", "e5m10"), ("bf16", "e8m7")])
+def test_emulated_equals_storage_format_end_to_end(native, emulated):
+    """Rounding to E5M10 (E8M7) and storing the FP32 value is what FP16 (BF16) storage does: every
+    cost, stored value and gradient is bit-identical."""
+    need_gpu()
+    wl = make_workload("batched")
+    shape = shape_of(wl)
+    q = dev(wl.q, torch.float32)
+    outs = []
+    for fmt in (native, emulated):
+        prec = {"link_poses": fmt, "sphere_pos": fmt, "sphere_dist": (fmt, -6), "sphere_grad": (fmt, 3),
+                "joint_grad": (fmt, 2)}
+        ctx = make_context(wl, prec)
+        cost, ws = ctx.cost_fwd(q, shape)
+        grad = ctx.cost_bwd(q, ws)
+        torch.cuda.synchronize()
+        S = ctx.ws_export("sphere_pos", ws, shape)
+        S = (S.view(torch.float32) if fmt == emulated else None)
+        outs.append((cost.cpu().numpy(), grad.cpu().numpy()))
+    np.testing.assert_array_equal(outs[0][0], outs[1][0])
+    np.testing.assert_array_equal(outs[0][1].view(np.uint32), outs[1][1].view(np.uint32))
+
+
+def test_emulated_assignment_matches_oracle():
+    """A mixed assignment of emulated types (one per tensor, with scales) against the oracle's
+    emulation: stored positions equal the oracle's rounding of a value within the FP32 error of the
+    exact one, costs within the usual bound, gradients where the stored positions agree."""
+    need_gpu()
+    wl = make_workload("batched")
+    prec = {"link_poses": "e5m9", "sphere_pos": "e6m6", "sphere_dist": ("e3m1", -4), "sphere_grad": ("e2m2", 3),
+            "joint_grad": ("e5m4", 2)}
+    ctx = make_context(wl, prec)
+    shape = shape_of(wl)
+    q = dev(wl.q, torch.float32)
+    cost, ws = ctx.cost_fwd(q, shape)
+    grad = ctx.cost_bwd(q, ws).cpu().numpy()
+    torch.cuda.synchronize()
+    oprec = OC.Precision(**{t: ((v, 0) if isinstance(v, str) else tuple(v)) for t, v in prec.items()})
+    ref = OC.fwd_bwd(wl.robot, wl.worlds, wl.q, wl.traj_per_world, wl.T, wl.n_ls, prec=oprec)
+    S = ctx.ws_export("sphere_pos", ws, shape).view(torch.float32).cpu().numpy().astype(np.float64)
+    x = ref["S"].reshape(-1)
+    tol = 4e-6 * np.abs(x) + 1e-5
+    lo, hi = X.round_value(F.fp32(x - tol), 6, 6), X.round_value(F.fp32(x + tol), 6, 6)
+    assert np.all((S >= np.minimum(lo, hi)) & (S <= np.maximum(lo, hi)))
+    same = np.all(S.reshape(shape.B, -1) == ref["S_hat"].reshape(shape.B, -1), axis=1)
+    assert same.mean() > 0.9
+    ctol = cost_tolerance(ref, wl.robot.n_pairs, wl.T)
+    c = cost.cpu().numpy()
+    ok_tc = same.reshape(-1, wl.T).all(axis=1)
+    # D and G carry coarse types: a cost term may sit on a rounding boundary of D, so the cost is
+    # compared against the oracle's with the D-step bound of such a term added where needed
+    dstep = 2.0 ** (np.floor(np.log2(np.maximum(ref["D"], 1e-30))) - 1) * 2.0 ** -4
+    extra = (2.0 * OC.CostParams().w_coll * ref["D_hat"] * dstep).sum(axis=1).reshape(-1, wl.T).sum(axis=1)
+    assert np.all(np.abs(c - ref["cost_traj"])[ok_tc] <= (ctol + extra)[ok_tc])
+    assert np.abs(ref["J_hat"]).max() > 0 and np.isfinite(grad).all()
+
+
+def test_exmy_rejected_where_codes_are_needed():
+    need_gpu()
+    from paper_2310_07854_amd import VaprError, _lib as L
+    from paper_2310_07854_amd.context import quantize, round_exmy
+
+    x = torch.ones(16, device="cuda:0")
+    with pytest.raises(VaprError):
+        round_exmy(x, 9, 2)
+    with pytest.raises(VaprError):
+        round_exmy(x, 3, 24)
+    lib = L.load()
+    assert lib.vapr_quantize(L.EXMY, 0, x.data_ptr(), x.data_ptr(), 16, None) == L.E_INVALID

@@ -81,5 +81,6 @@ def test_ladder_is_21_types_from_fp4_to_fp32():
     widths = [X.bits(E, M) for E, M in X.LADDER]
     assert widths == sorted(widths) and widths[0] == 4 and widths[-1] == 32
     assert {(E, M) for E, M in X.LADDER if X.bits(E, M) >= 16} == {(5, 10), (8, 7), (8, 23)}
+    assert X.ieee(8, 4) and X.limits(8, 4)[2] == (2 - 2 ** -4) * 2.0 ** 127 and not X.ieee(6, 6)
     named = {(2, 1), (2, 2), (3, 1), (2, 3), (3, 2), (4, 3), (5, 2), (6, 6), (5, 9), (6, 8), (5, 10), (8, 7), (8, 23)}
     assert named <= set(X.LADDER)
