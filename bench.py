@@ -617,6 +617,66 @@ def swept_bench(args):
     print(json.dumps(line), flush=True)
 
 
+def search_study(args):
+    """The variable-precision search on synthetic planning problems: problems drawn like the
+    benchmark worlds (16 cuboids each, start and goal collision-free), 8 linear seeds of 32
+    timesteps each, `search_iters` optimiser iterations per evaluation; an assignment succeeds on a
+    problem when one of its final trajectories is collision-free, and must keep the FP32 success
+    rate.  The arm is the benchmark's without self pairs (its random sphere model overlaps itself)."""
+    import dataclasses
+    from types import SimpleNamespace
+
+    import torch
+
+    from paper_2310_07854_amd import Context, search as SR, seed_pipeline as SP
+    from synthetic import make_robot, make_seed_inits, make_seed_problems
+
+    K, T_S, S_S = 16, 32, 8
+    robot = make_robot(N_SPHERES, N_PAIRS)
+    robot = dataclasses.replace(robot, pairs=robot.pairs[:0])
+    ctx = Context(0)
+    ctx.set_robot(robot)
+    d = lambda a: torch.tensor(np.asarray(a, dtype=np.float32), device="cuda:0")
+    keep = {"pose": [], "half": [], "start": [], "goal": []}
+    have, split = 0, 200
+    while have < args.search_problems:
+        pr = make_seed_problems(4096, K, split=split)
+        ctx.set_worlds(pr.worlds.pose, pr.worlds.half_ext)
+        ok = SP.endpoints_free(ctx, d(pr.start), d(pr.goal)).cpu().numpy()
+        for key, arr in (("pose", pr.worlds.pose), ("half", pr.worlds.half_ext), ("start", pr.start),
+                         ("goal", pr.goal)):
+            keep[key].append(arr[ok])
+        have += int(ok.sum())
+        split += 1
+    n = args.search_problems
+    p = {k: np.concatenate(v)[:n] for k, v in keep.items()}
+    worlds = SimpleNamespace(pose=p["pose"], half_ext=p["half"])
+    x0 = make_seed_inits(p["start"], p["goal"], S_S, T_S, "linear", split=5)
+    task = SR.OptimizerTask(ctx, worlds, p["start"], p["goal"], x0, iters=args.search_iters, n_ls=4)
+    evals = []
+
+    def timed_eval(a):
+        t0 = time.perf_counter()
+        r = task(a)
+        evals.append(time.perf_counter() - t0)
+        print(f"# search: {r:.4f} " + " ".join(f"{t}={f}" for t, f in a.items()), file=sys.stderr, flush=True)
+        return r
+
+    res = SR.Search(timed_eval, tolerance=0.0).run(budget=args.search_budget, seed=0)
+    ctx.close()
+    line = {"metric": "variable-precision search: fewest stored-tensor bits at the FP32 collision-free rate",
+            "data": "synthetic", "n_gpus": 1,
+            "config": {"workload": f"{n} problems (worlds of {K} cuboids), {S_S} linear seeds x {T_S} timesteps, "
+                                   f"{args.search_iters} optimiser iterations per evaluation; 21-type ladder",
+                       "budget": args.search_budget},
+            "fp32_rate": res.fp32_rate, "target": res.target, "per_tensor": res.per_tensor, "best": res.best,
+            "best_rate": res.best_rate, "best_bits": res.best_bits, "fp32_bits": 32 * len(res.best),
+            "evaluations": res.evaluations, "seconds": res.seconds,
+            "seconds_per_evaluation": float(np.median(evals)) if evals else None,
+            "history": [[a, r] for a, r in res.history]}
+    print(json.dumps(line), flush=True)
+
+
 IK_SEEDS = 2000
 
 
@@ -719,6 +779,10 @@ def main():
     ap.add_argument("--seed-infer", action="store_true", help="time the seeding network's inference instead")
     ap.add_argument("--swept", type=int, default=0, help="time the step with the swept term (k samples) instead")
     ap.add_argument("--ik", action="store_true", help="time the inverse-kinematics workload instead")
+    ap.add_argument("--search", action="store_true", help="run the variable-precision search instead")
+    ap.add_argument("--search-problems", type=int, default=1024)
+    ap.add_argument("--search-iters", type=int, default=60)
+    ap.add_argument("--search-budget", type=int, default=60)
     ap.add_argument("--seed-batch", type=int, default=65536)
     ap.add_argument("--seed-envs", type=int, default=2)
     ap.add_argument("--seed-problems", type=int, default=32768)
@@ -753,6 +817,9 @@ def main():
         return
     if args.ik:
         ik_bench(args)
+        return
+    if args.search:
+        search_study(args)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (--gpus {args.gpus} requested): the cost path shards by world "
