@@ -5,9 +5,9 @@ narrowest floating-point types that keep the task success rate of FP32.
             rate (every other tensor FP32) reaches the target; types narrower than it are dropped
   phase 2   across tensors, minimise the total bit width over the reduced space subject to the
             same success constraint.  The paper drives this phase with NSGA-II in a black-box
-            optimiser; here a seeded (mu + lambda) evolutionary search stands in: assignments are
-            mutated one tensor one ladder step at a time, infeasible ones are discarded, and the
-            search keeps the feasible ones with the fewest bits
+            optimiser; here a budgeted local search stands in: repair the phase-1 assignment step
+            by step until feasible, descend greedily to narrower types, then a seeded (mu + lambda)
+            evolution with the remaining budget
 
 The ladder holds the 21 types of the format space, narrowest first; a type with a storage codec
 (e2m1, e3m2, e4m3, e5m2, f16, bf16, f32) is stored in it, every other type is emulated (FP32
@@ -142,45 +142,72 @@ class Search:
 
     def combine(self, floor: Dict[str, str], target: float, budget: int = 60, population: int = 6,
                 seed: int = 0) -> Tuple[Dict[str, str], float]:
-        """Phase 2: fewest total bits over assignments at or above each tensor's phase-1 type with a
-        success rate reaching the target; (mu + lambda) evolution from the phase-1 assignment and
-        its safer neighbours, mutating one tensor by one ladder step."""
+        """Phase 2: fewest total bits over assignments at or above each tensor's phase-1 type whose
+        success rate reaches the target, within `budget` new evaluations:
+          repair   from the phase-1 types (usually infeasible together), raise one tensor one ladder
+                   step at a time, the step with the best success rate (then fewest bits), until
+                   feasible
+          descent  lower any tensor to the next narrower type while that stays feasible
+          evolve   (mu + lambda) with the remaining budget: mutate one tensor one ladder step,
+                   keep the feasible assignments with the fewest bits"""
         rng = np.random.default_rng(seed)
         lo = {t: self.ladder.index(floor[t]) for t in self.tensors}
         top = len(self.ladder) - 1
+        evals0 = len(self.cache)
+
+        def left():
+            return budget - (len(self.cache) - evals0)
 
         def total(a):
             return sum(bits(a[t]) for t in self.tensors)
 
+        def order(a):
+            return (total(a), tuple(self.ladder.index(a[t]) for t in self.tensors))
+
         def feasible(a):
             return self.rate(a) >= target
 
-        start = [dict(floor)]
-        for t in self.tensors:                       # phase-1 assignment with one tensor one step safer
-            a = dict(floor)
-            a[t] = self.ladder[min(top, lo[t] + 1)]
-            start.append(a)
-        start.append(self._fp32())
-        pool = [a for a in start if feasible(a)]
-        evals0 = len(self.cache)
-        # proposals are bounded as well as new evaluations, so the loop ends when every neighbour of
-        # the pool has been seen
-        for _ in range(8 * budget):
-            if len(self.cache) - evals0 >= budget or not pool:
-                break
-            pool.sort(key=lambda a: (total(a), tuple(self.ladder.index(a[t]) for t in self.tensors)))
-            parents = pool[:population]
-            child = dict(parents[int(rng.integers(len(parents)))])
-            t = self.tensors[int(rng.integers(len(self.tensors)))]
-            i = self.ladder.index(child[t])
-            step = -1 if rng.random() < 0.75 else 1        # mostly try narrower types
+        def moved(a, t, step):
+            i = self.ladder.index(a[t])
             j = min(top, max(lo[t], i + step))
             if j == i:
-                continue
-            child[t] = self.ladder[j]
-            if feasible(child) and child not in pool:
+                return None
+            b = dict(a)
+            b[t] = self.ladder[j]
+            return b
+
+        pool = [self._fp32()] if feasible(self._fp32()) else []
+        a = dict(floor)
+        while not feasible(a) and left() > 0:
+            ups = [b for b in (moved(a, t, 1) for t in self.tensors) if b is not None]
+            if not ups:
+                break
+            a = max(ups, key=lambda b: (self.rate(b), -total(b)))
+        if feasible(a):
+            pool.append(a)
+            improved = True
+            while improved and left() > 0:
+                improved = False
+                for t in sorted(self.tensors, key=lambda t: -bits(a[t])):
+                    b = a
+                    while True:  # the next narrower type (equal widths are skipped)
+                        b = moved(b, t, -1)
+                        if b is None or bits(b[t]) < bits(a[t]):
+                            break
+                    if b is not None and left() > 0 and feasible(b):
+                        a = b
+                        pool.append(a)
+                        improved = True
+        for _ in range(8 * budget):
+            if left() <= 0 or not pool:
+                break
+            pool.sort(key=order)
+            parents = pool[:population]
+            child = moved(parents[int(rng.integers(len(parents)))], self.tensors[int(rng.integers(len(self.tensors)))],
+                          -1 if rng.random() < 0.75 else 1)  # mostly try narrower types
+            if child is not None and feasible(child) and child not in pool:
                 pool.append(child)
-        pool.sort(key=lambda a: (total(a), tuple(self.ladder.index(a[t]) for t in self.tensors)))
+        pool.sort(key=order)
         best = pool[0] if pool else self._fp32()
         return best, self.rate(best)
 
