@@ -617,6 +617,63 @@ def swept_bench(args):
     print(json.dumps(line), flush=True)
 
 
+def graph_bench(args):
+    """Eager iterations against replays of one captured HIP graph of the iteration, on the batched
+    FP32 workload (4 worlds x 32 seeds x 32 timesteps, 4 line-search candidates: 16,384
+    configurations per step, 40 cuboids) and on the 196,608-configuration workload (paper-like)."""
+    import torch
+
+    from paper_2310_07854_amd import Context, TrajectoryOptimizer
+    from synthetic import make_robot, make_trajectories, make_worlds
+
+    out = {}
+    cases = {"batched_4096x4_fp32": (4, 32, 32, 4, 40, "f32"),
+             "large_196608_paper_like": (N_WORLDS, TPW, T, N_LS, N_CUBOIDS, "paper_like")}
+    for name, (W, S, Tn, nls, K, prec) in cases.items():
+        ctx = Context(0)
+        ctx.set_robot(make_robot(N_SPHERES, N_PAIRS))
+        worlds = make_worlds(W, K)
+        ctx.set_worlds(worlds.pose, worlds.half_ext)
+        x0 = torch.tensor(make_trajectories(W, S, Tn).reshape(W * S, Tn, 7), dtype=torch.float32, device="cuda:0")
+        if prec == "paper_like":
+            from paper_2310_07854_amd import Shape
+            ctx.set_precision({})
+            sh = Shape(W, S, Tn, 1)
+            q = x0.reshape(-1, 7).contiguous()
+            _, ws = ctx.cost_fwd(q, sh)
+            ctx.cost_bwd(q, ws, want_grad=False)
+            amax = {t: float(ctx.ws_export(t, ws, sh).view(torch.float32).abs().max()) for t in
+                    ("link_poses", "sphere_pos", "sphere_dist", "sphere_grad", "joint_grad")}
+            ctx.set_precision(with_scales(PRECISIONS["paper_like"], amax))
+        else:
+            ctx.set_precision({})
+        res = {}
+        for mode in ("eager", "graph"):
+            opt = TrajectoryOptimizer(ctx, W, S, Tn, n_ls=nls, m=HIST_M)
+            opt.init(x0)
+            if mode == "graph":
+                opt.capture()
+            run = opt.replay if mode == "graph" else opt.step
+            for _ in range(args.warmup):
+                run()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                run()
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t0) / args.steps
+            B = W * S * Tn * nls
+            res[mode] = {"ms_per_step": dt * 1e3, "evals_per_s": B / dt}
+            del opt
+        ctx.close()
+        res["graph_speedup"] = res["eager"]["ms_per_step"] / res["graph"]["ms_per_step"]
+        out[name] = res
+        print(f"# graph {name}: eager {res['eager']['ms_per_step']*1e3:.1f} us/step, graph "
+              f"{res['graph']['ms_per_step']*1e3:.1f} us/step", file=sys.stderr, flush=True)
+    print(json.dumps({"metric": "optimiser iteration: eager launches vs one HIP graph replay", "data": "synthetic",
+                      "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "results": out}), flush=True)
+
+
 def search_study(args):
     """The variable-precision search on synthetic planning problems: problems drawn like the
     benchmark worlds (16 cuboids each, start and goal collision-free), 8 linear seeds of 32
@@ -786,6 +843,7 @@ def main():
     ap.add_argument("--swept", type=int, default=0, help="time the step with the swept term (k samples) instead")
     ap.add_argument("--ik", action="store_true", help="time the inverse-kinematics workload instead")
     ap.add_argument("--search", action="store_true", help="run the variable-precision search instead")
+    ap.add_argument("--graph", action="store_true", help="time eager iterations against HIP graph replays instead")
     ap.add_argument("--search-problems", type=int, default=1024)
     ap.add_argument("--search-iters", type=int, default=60)
     ap.add_argument("--search-budget", type=int, default=60)
@@ -826,6 +884,9 @@ def main():
         return
     if args.search:
         search_study(args)
+        return
+    if args.graph:
+        graph_bench(args)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (--gpus {args.gpus} requested): the cost path shards by world "

@@ -382,6 +382,14 @@ __device__ __forceinline__ void cuboid_sd_grad(const float* __restrict__ bx, flo
   gz = fmaf(A[2], n[0], fmaf(A[5], n[1], A[8] * n[2]));
 }
 
+// A sphere whose closest-cuboid key exceeds (eta + r)^2 by a margin far above the rounding of the
+// key and of the exact distance is out of reach: its activation depth is exactly 0 and its gradient
+// +0, whatever the exact distance computation would give, so that computation is skipped.
+__device__ __forceinline__ bool out_of_reach(float key, float eta, float r) {
+  const float e = eta + r;
+  return key > e * e * 1.0001f;
+}
+
 // Closest cuboid of NA spheres against the K cuboids of one world.  The comparison key is
 // |max(a,0)|^2 outside (> 0) and max_i a_i inside (<= 0), a monotone function of the signed
 // distance, so no square root is taken per pair; the first index wins ties.
@@ -455,10 +463,10 @@ __global__ __launch_bounds__(256) void k_sphere_cost(RobotArgs R, WorldArgs W, T
     for (int i = 0; i < SPH_GROUP; ++i) {
       dv[i] = 0.f;
       gx[i] = gy[i] = gz[i] = 0.f;
-      if (i < active && K > 0) {
+      const float r = sphere_of(R.sph, g * SPH_GROUP + i).w;
+      if (i < active && K > 0 && !out_of_reach(best[i], cp.eta, r)) {
         float sd, nx, ny, nz;
         cuboid_sd_grad(mybox + bk[i] * 16, px[i], py[i], pz[i], sd, nx, ny, nz);
-        const float r = sphere_of(R.sph, g * SPH_GROUP + i).w;
         const float d = fmaxf(cp.eta - (sd - r), 0.f);
         dv[i] = d;
         if (d > 0.f) {
@@ -694,10 +702,10 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3))) void k
   for (int i = 0; i < SPH_GROUP; ++i) {
     dv[i] = 0.f;
     gx[i] = gy[i] = gz[i] = 0.f;
-    if (i < active && K > 0 && valid) {
+    const float r = i < active ? sphere_of(R.sph, g * SPH_GROUP + i).w : 0.f;
+    if (i < active && K > 0 && valid && !out_of_reach(best[i], cp.eta, r)) {
       float sd, nx, ny, nz;
       cuboid_sd_grad(mybox + bk[i] * 16, px[i], py[i], pz[i], sd, nx, ny, nz);
-      const float r = sphere_of(R.sph, g * SPH_GROUP + i).w;
       const float d = fmaxf(cp.eta - (sd - r), 0.f);
       dv[i] = d;
       if (d > 0.f) {
@@ -882,11 +890,12 @@ __global__ __launch_bounds__(256) void k_swept(RobotArgs R, WorldArgs W, GridArg
             const float* mybox = W.box + (int64_t)my_w * K * 16;
 #pragma unroll
             for (int i = 0; i < 8; ++i) {
-              // no candidate: no cuboid within reach of the point, so the depth is zero
-              if (h + i >= active || best[i] == INFINITY) continue;
+              // no candidate (key INFINITY) or none within reach: the depth is zero
+              if (h + i >= active) continue;
+              const float r = sphere_of(R.sph, g * SPH_GROUP + h + i).w;
+              if (out_of_reach(best[i], cp.eta, r)) continue;
               float sd, nx, ny, nz;
               cuboid_sd_grad(mybox + bk[i] * 16, px[i], py[i], pz[i], sd, nx, ny, nz);
-              const float r = sphere_of(R.sph, g * SPH_GROUP + h + i).w;
               const float d = fmaxf(cp.eta - (sd - r), 0.f);
               if (d > 0.f) {
                 cost = fmaf(d, d, cost);

@@ -53,6 +53,22 @@ class TrajectoryOptimizer:
         self.vctx._call("vapr_optimizer_init", ctypes.byref(self._st), _dev(self.ws1, torch.uint8, "ws"),
                         self.ws1.numel(), _dev(c0, torch.float64, "cost0"), _dev(self.q_cand, torch.float32, "q"))
 
+    def capture(self) -> None:
+        """Record one iteration (forward, backward and optimiser kernels on the candidates) as a HIP
+        graph; `replay` then runs it with one launch.  Call after `init` (which builds the
+        library's lazy tables); the graph reads and writes this optimiser's buffers in place, so
+        replays continue the same optimisation.  Changing the context's robot, worlds, precision or
+        cost parameters afterwards needs a new capture."""
+        torch.cuda.synchronize()
+        self._graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self._graph):
+            self.step()
+        torch.cuda.synchronize()
+
+    def replay(self) -> None:
+        """One iteration by replaying the captured graph."""
+        self._graph.replay()
+
     def step(self) -> None:
         """One iteration: evaluate all candidates (fwd + bwd), select, update, next candidates."""
         self.vctx.cost_fwd(self.q_cand, self.shape, ws=self.ws, cost_traj=self.cost_cand)

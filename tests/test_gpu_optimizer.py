@@ -125,3 +125,29 @@ def test_optimizer_descends_on_batched_workload():
     x = opt.x.reshape(wl.n_traj, T, 7)
     assert torch.equal(x[:, 0], x0[:, 0]) and torch.equal(x[:, -1], x0[:, -1])  # pinned start/goal
     assert float(opt.cost.sum()) < 0.7 * float(c0.sum())
+
+
+def test_graph_replays_match_eager_steps():
+    """One captured iteration replayed many times, with eager work and synchronisation in between,
+    equals the same number of eager iterations bit for bit at every step."""
+    need_gpu()
+    from paper_2310_07854_amd import TrajectoryOptimizer
+
+    wl = make_workload("batched")
+    ctx = make_context(wl, {"sphere_pos": "f16", "sphere_dist": ("e4m3", -10), "sphere_grad": ("e4m3", -1)})
+    T = wl.T
+    x0 = dev(wl.q.reshape(wl.n_traj, wl.n_ls, T, 7)[:, 0], torch.float32)
+    eager = TrajectoryOptimizer(ctx, wl.n_worlds, wl.traj_per_world, T, n_ls=wl.n_ls, m=8)
+    graph = TrajectoryOptimizer(ctx, wl.n_worlds, wl.traj_per_world, T, n_ls=wl.n_ls, m=8)
+    eager.init(x0)
+    graph.init(x0)
+    graph.capture()
+    for it in range(6):
+        eager.step()
+        graph.replay()
+        torch.cuda.synchronize()
+        _ = torch.ones(1000, device="cuda:0").sum().item()  # unrelated eager work between replays
+        assert torch.equal(eager.x, graph.x), it
+        assert torch.equal(eager.cost, graph.cost), it
+        assert torch.equal(eager.d, graph.d), it
+        assert torch.equal(eager.hist_len, graph.hist_len), it
