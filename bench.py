@@ -281,19 +281,24 @@ def copy_bandwidth(torch, mib=1024, runs=20):
 
 
 def run_variant(torch, ctx, opt_cls, x0, prec, steps, warmup, want_opt=False, recompute=False):
+    """`warmup` untimed iterations, then `steps` timed ones with nothing but the iteration's own
+    launches in the stream (the step time), then `steps` more with HIP events recorded around every
+    launch on the library's stream (the per-kernel durations: the events add their own cost to the
+    stream, about 15% of a step here, so they stay out of the step time)."""
     ctx.set_precision(prec, recompute_poses=recompute)
     opt = opt_cls(ctx, N_WORLDS, TPW, T, n_ls=N_LS, m=HIST_M)
     opt.init(x0)
     for _ in range(warmup):
         opt.step()
     torch.cuda.synchronize()
-    ctx.profile_enable(True)
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
         opt.step()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    ctx.profile_enable(True)
+    for _ in range(steps):
+        opt.step()
     prof = ctx.profile_read()
     ctx.profile_enable(False)
     cost = float(opt.cost.sum())
@@ -787,12 +792,15 @@ def ik_bench(args):
         for _ in range(args.warmup):
             opt.step()
         torch.cuda.synchronize()
-        ctx.profile_enable(True)
         t0 = time.perf_counter()
         for _ in range(args.steps):
             opt.step()
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
+        # per-kernel durations from a second region with HIP events around every launch
+        ctx.profile_enable(True)
+        for _ in range(args.steps):
+            opt.step()
         prof = ctx.profile_read()
         ctx.profile_enable(False)
         kern = {kk: v[0] / max(v[1], 1) * 1e3 for kk, v in prof.items() if v[1]}
