@@ -147,12 +147,16 @@ def culled_work(ctx, opt, prec):
     return {"needed_tests_per_cfg": needed / B, "issued_lane_tests_per_cfg": issued / B}
 
 
+SWEPT_SPHERES, SWEPT_SAMPLES = 4, 2  # the swept kernel's candidate lists: 4 spheres x 2 samples
+
+
 def swept_culled_work(ctx, opt, prec, k):
     """Sample-cuboid tests of one swept launch of the timed loop (its last one), counted like
     culled_work: `needed` sums, over segments, spheres and the k sample points, the cuboids marked in
-    the point's voxel; `issued` counts the lane slots the kernel spends (per sample, each lane tests
-    the union of four spheres' lists, a wavefront of 64 segment lanes as often as its busiest lane).
-    Sample points are recomputed from the stored positions in FP32."""
+    the point's voxel; `issued` counts the lane slots the kernel spends (each lane walks one list per
+    4 spheres and chunk of 2 samples, the union of those 8 points' marks, testing all 8 points per
+    entry; a wavefront of 64 segment lanes walks as often as its busiest lane).  Sample points are
+    recomputed from the stored positions in FP32."""
     from paper_2310_07854_amd.context import dequantize
 
     shape = opt.shape
@@ -167,7 +171,6 @@ def swept_culled_work(ctx, opt, prec, k):
     p0 = pos
     dp = np.zeros_like(pos)
     dp[:-1] = pos[1:] - pos[:-1]
-    cand = np.zeros((B, n_pad), dtype=np.uint64)
     needed = 0
     issued = 0
     n_waves = (B + 62) // 63
@@ -176,29 +179,33 @@ def swept_culled_work(ctx, opt, prec, k):
     lane_a = np.clip(lane_a, 0, B - 1)
     cfg_per_world = B // N_WORLDS
     grids = [ctx.culling_grid(w) for w in range(N_WORLDS)]
-    for j in range(1, k + 1):
-        u = np.float32(j) / np.float32(k + 1)
-        pts = (p0 + u * dp).astype(np.float32)
-        cand[:] = 0
-        for w in range(N_WORLDS):
-            info, mask = grids[w]
-            sl = slice(w * cfg_per_world, (w + 1) * cfg_per_world)
-            if mask is None:
-                cand[sl, :N_SPHERES] = np.uint64((1 << N_CUBOIDS) - 1) if N_CUBOIDS < 64 else np.uint64(2 ** 64 - 1)
-                continue
-            m64 = mask[:, 0].astype(np.uint64)
-            if mask.shape[1] > 1:
-                m64 |= mask[:, 1].astype(np.uint64) << np.uint64(32)
-            n = info["n"]
-            f = (pts[sl] - np.array(info["origin"], dtype=np.float32)) * np.float32(info["inv_cell"])
-            inside = np.all((f >= 0) & (f < np.float32(n)), axis=-1)
-            v = np.floor(np.where(inside[..., None], f, 0)).astype(np.int64)
-            cand[sl, :N_SPHERES] = np.where(inside, m64[(v[..., 2] * n + v[..., 1]) * n + v[..., 0]], np.uint64(0))
-        cand[~seg] = 0
-        needed += int(np.bitwise_count(cand).sum())
-        quad = np.bitwise_or.reduce(cand.reshape(B, n_pad // 4, 4), axis=2)           # [B, quads]
-        per_lane = np.bitwise_count(quad).astype(np.int64)[lane_a] * lane_ok[..., None]  # [wave, lane, quad]
-        issued += int(per_lane.max(axis=1).sum()) * 4 * 64
+    n_lists = n_pad // SWEPT_SPHERES
+    for j0 in range(1, k + 1, SWEPT_SAMPLES):
+        chunk = range(j0, min(k, j0 + SWEPT_SAMPLES - 1) + 1)
+        union = np.zeros((B, n_lists), dtype=np.uint64)
+        for j in chunk:
+            u = np.float32(j) / np.float32(k + 1)
+            pts = (p0 + u * dp).astype(np.float32)
+            cand = np.zeros((B, n_pad), dtype=np.uint64)
+            for w in range(N_WORLDS):
+                info, mask = grids[w]
+                sl = slice(w * cfg_per_world, (w + 1) * cfg_per_world)
+                if mask is None:
+                    cand[sl, :N_SPHERES] = np.uint64((1 << N_CUBOIDS) - 1) if N_CUBOIDS < 64 else np.uint64(2 ** 64 - 1)
+                    continue
+                m64 = mask[:, 0].astype(np.uint64)
+                if mask.shape[1] > 1:
+                    m64 |= mask[:, 1].astype(np.uint64) << np.uint64(32)
+                n = info["n"]
+                f = (pts[sl] - np.array(info["origin"], dtype=np.float32)) * np.float32(info["inv_cell"])
+                inside = np.all((f >= 0) & (f < np.float32(n)), axis=-1)
+                v = np.floor(np.where(inside[..., None], f, 0)).astype(np.int64)
+                cand[sl, :N_SPHERES] = np.where(inside, m64[(v[..., 2] * n + v[..., 1]) * n + v[..., 0]], np.uint64(0))
+            cand[~seg] = 0
+            needed += int(np.bitwise_count(cand).sum())
+            union |= np.bitwise_or.reduce(cand.reshape(B, n_lists, SWEPT_SPHERES), axis=2)
+        per_lane = np.bitwise_count(union).astype(np.int64)[lane_a] * lane_ok[..., None]  # [wave, lane, list]
+        issued += int(per_lane.max(axis=1).sum()) * SWEPT_SPHERES * len(chunk) * 64
     return {"needed_tests_per_cfg": needed / B, "issued_lane_tests_per_cfg": issued / B}
 
 

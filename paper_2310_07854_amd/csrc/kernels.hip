@@ -790,15 +790,76 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3))) void k
 // lane 0.  Every segment is thus evaluated once (64 lanes for 63 configurations), and the gradient
 // at the far end moves one lane up with a cross-lane permute: configuration c receives its own
 // segment's near-end gradient plus the far-end gradient of the segment (c - 1, c), with no atomics
-// and in a fixed order.  Spheres go eight at a time against the world's cuboids (closest cuboid by
-// the same comparison key as the discrete term, exact distance and gradient for the winner).  With
-// the culling grid (at most 64 cuboids), a sample point only meets the cuboids marked in its voxel,
-// taken in increasing index over the union of four spheres' lists: the grid is conservative for any
-// point a robot sphere can occupy, so the result is the one every cuboid would give.
+// and in a fixed order.
+//
+// Spheres go four at a time, and two samples of each at once: the 8 sample points share one
+// candidate list (the union of their voxels' masks, walked in increasing cuboid index), so each
+// candidate cuboid is gathered once for 8 tests instead of 4.  Sample points of one segment lie close
+// together, so the union is barely longer than each sample's own list.  Closest
+// cuboid by the same comparison key as the discrete term, exact distance and gradient for the
+// winner.  The grid is conservative for any point a robot sphere can occupy, so the result is the one
+// every cuboid would give; without the grid (or beyond 64 cuboids) every cuboid is tested.
+#ifndef VAPR_SWEPT_SAMPLES
+#define VAPR_SWEPT_SAMPLES 2
+#endif
+#ifndef VAPR_SWEPT_SPHERES
+#define VAPR_SWEPT_SPHERES 4
+#endif
+constexpr int SW_Q = VAPR_SWEPT_SPHERES;   // spheres per candidate list (divides 16)
+constexpr int SW_KS = VAPR_SWEPT_SAMPLES;  // samples per sphere sharing the list (SW_Q * SW_KS <= 16)
+static_assert(SW_Q * SW_KS <= SPH_GROUP && SPH_GROUP % SW_Q == 0, "a chunk holds at most 16 sample points");
+
+// the candidate list m against the first NA points, two cuboid buffers used in turn so that the next
+// candidate's load is in flight while the current one is tested
+template <int NA>
+__device__ __forceinline__ void walk_candidates(uint64_t m, const float* wbox, const float (&px)[SPH_GROUP],
+                                                const float (&py)[SPH_GROUP], const float (&pz)[SPH_GROUP],
+                                                float (&best)[SPH_GROUP], int (&bk)[SPH_GROUP]) {
+  float4 a0, a1, a2, a3, b0, b1, b2, b3;
+  int ka = pop_cuboid(m, wbox, a0, a1, a2, a3);
+  while (ka >= 0) {
+    const int kb = pop_cuboid(m, wbox, b0, b1, b2, b3);
+#pragma unroll
+    for (int n = 0; n < NA; ++n) cuboid_key_v(a0, a1, a2, a3, px[n], py[n], pz[n], ka, best[n], bk[n]);
+    if (kb < 0) break;
+    ka = pop_cuboid(m, wbox, a0, a1, a2, a3);
+#pragma unroll
+    for (int n = 0; n < NA; ++n) cuboid_key_v(b0, b1, b2, b3, px[n], py[n], pz[n], kb, best[n], bk[n]);
+  }
+}
+
+// the live points of a chunk of nj samples (1 <= nj <= NJ) against the candidate list, or against
+// every cuboid
+template <int NJ>
+__device__ __forceinline__ void swept_chunk_walk(int nj, uint64_t m, const float* wbox, const float (&px)[SPH_GROUP],
+                                                 const float (&py)[SPH_GROUP], const float (&pz)[SPH_GROUP],
+                                                 float (&best)[SPH_GROUP], int (&bk)[SPH_GROUP]) {
+  if constexpr (NJ > 1) {
+    if (nj < NJ) return swept_chunk_walk<NJ - 1>(nj, m, wbox, px, py, pz, best, bk);
+  }
+  walk_candidates<NJ * SW_Q>(m, wbox, px, py, pz, best, bk);
+}
+template <int NJ>
+__device__ __forceinline__ void swept_chunk_dense(int nj, cptr<float> wbox, int K, const float (&px)[SPH_GROUP],
+                                                  const float (&py)[SPH_GROUP], const float (&pz)[SPH_GROUP],
+                                                  float (&best)[SPH_GROUP], int (&bk)[SPH_GROUP]) {
+  if constexpr (NJ > 1) {
+    if (nj < NJ) return swept_chunk_dense<NJ - 1>(nj, wbox, K, px, py, pz, best, bk);
+  }
+  closest_cuboids<NJ * SW_Q>(wbox, K, px, py, pz, best, bk);
+}
+
+// X of one sphere group of each wavefront, [wave][sphere * 3 + component][lane], until it is stored
+constexpr int SWEPT_LDS_BYTES = 4 * SPH_GROUP * 3 * 64 * (int)sizeof(float);
+
+// 3 wavefronts per SIMD: the register budget (168) that four spheres by two samples fit without
+// spilling, and what the X staging allows (three 48 KB workgroups per CU)
 template <int FS>
-__global__ __launch_bounds__(256) void k_swept(RobotArgs R, WorldArgs W, GridArgs Gd, TV S, TV X,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_swept(RobotArgs R, WorldArgs W, GridArgs Gd, TV S, TV X,
                                                float* __restrict__ sweptc, ShapeArgs sh, CostArgs cp) {
+  extern __shared__ float lds_sw[];
   const int lane = threadIdx.x & 63;
+  float* xs = lds_sw + (threadIdx.x >> 6) * (SPH_GROUP * 3 * 64) + lane;
   const int64_t wv = (int64_t)blockIdx.x * 4 + uniform(threadIdx.x >> 6);
   const int64_t first = wv * 63;
   if (first >= sh.B) return;  // whole wavefront: its own configurations and lane 63's segment lie past B
@@ -821,92 +882,86 @@ __global__ __launch_bounds__(256) void k_swept(RobotArgs R, WorldArgs W, GridArg
   const int64_t n3 = (int64_t)Gd.n * Gd.n * Gd.n;
   const uint32_t* b0 = lane_base(S, seg ? a : 0);
   const uint32_t* b1 = lane_base(S, seg ? a + 1 : 0);
+  const float* wbox = W.box + (int64_t)my_w * K * 16;
   float cost = 0.f;
 
   for (int g = 0; g < ng; ++g) {
-    float xg[SPH_GROUP], yg[SPH_GROUP], zg[SPH_GROUP];
     const int active = uniform(min(SPH_GROUP, n_s - g * SPH_GROUP));
-    for (int h = 0; h < SPH_GROUP; h += 8) {
-      float p0[3][8], dp[3][8], lo[3][8], hi[3][8];
+    for (int q4 = 0; q4 < SPH_GROUP; q4 += SW_Q) {
+      float p0[3][SW_Q], dp[3][SW_Q], lo[3][SW_Q], hi[3][SW_Q];
 #pragma unroll
-      for (int i = 0; i < 8; ++i) {
+      for (int i = 0; i < SW_Q; ++i) {
 #pragma unroll
         for (int q = 0; q < 3; ++q) {
           float v0 = 0.f, v1 = 0.f;
-          if (seg && h + i < active) {
-            v0 = load_elem_at<FS, SPH_GROUP>(b0, g * 3 + q, h + i, S.scale);
-            v1 = load_elem_at<FS, SPH_GROUP>(b1, g * 3 + q, h + i, S.scale);
+          if (seg && q4 + i < active) {
+            v0 = load_elem_at<FS, SPH_GROUP>(b0, g * 3 + q, q4 + i, S.scale);
+            v1 = load_elem_at<FS, SPH_GROUP>(b1, g * 3 + q, q4 + i, S.scale);
           }
           p0[q][i] = v0;
           dp[q][i] = v1 - v0;
           lo[q][i] = hi[q][i] = 0.f;
         }
       }
-      if (h < active) {
-        for (int j = 1; j <= k_sw; ++j) {
-          const float u = (float)j / (float)(k_sw + 1);
-          float px[SPH_GROUP], py[SPH_GROUP], pz[SPH_GROUP], best[SPH_GROUP];
+      if (q4 < active) {
+        for (int j0 = 1; j0 <= k_sw; j0 += SW_KS) {
+          const int nj = uniform(min(SW_KS, k_sw - j0 + 1));  // samples of this chunk
+          // point n = jj * SW_Q + i: sphere q4 + i at sample j0 + jj (the first SW_Q nj are live)
+          float uu[SW_KS], px[SPH_GROUP], py[SPH_GROUP], pz[SPH_GROUP], best[SPH_GROUP];
           int bk[SPH_GROUP];
 #pragma unroll
-          for (int i = 0; i < SPH_GROUP; ++i) {
-            const int ii = i < 8 ? i : 0;
-            px[i] = fmaf(u, dp[0][ii], p0[0][ii]);
-            py[i] = fmaf(u, dp[1][ii], p0[1][ii]);
-            pz[i] = fmaf(u, dp[2][ii], p0[2][ii]);
-            best[i] = INFINITY;
-            bk[i] = 0;
+          for (int jj = 0; jj < SW_KS; ++jj) uu[jj] = (float)(j0 + jj) / (float)(k_sw + 1);
+#pragma unroll
+          for (int n = 0; n < SW_Q * SW_KS; ++n) {
+            const int jj = n / SW_Q, i = n % SW_Q;
+            px[n] = fmaf(uu[jj], dp[0][i], p0[0][i]);
+            py[n] = fmaf(uu[jj], dp[1][i], p0[1][i]);
+            pz[n] = fmaf(uu[jj], dp[2][i], p0[2][i]);
+            best[n] = INFINITY;
+            bk[n] = 0;
           }
           if (culled) {
             if (seg) {
-              const float* wbox = W.box + (int64_t)my_w * K * 16;
               const uint32_t* gm = Gd.mask + (int64_t)my_w * n3 * Gd.MW;
+              uint64_t m = 0;
 #pragma unroll
-              for (int q4 = 0; q4 < 8; q4 += 4) {
-                uint64_t m = 0;
-#pragma unroll
-                for (int i = q4; i < q4 + 4; ++i) {
-                  if (h + i >= active) continue;
-                  const int vox = voxel_of(Gd, px[i], py[i], pz[i]);
-                  if (vox < 0) continue;
-                  const uint32_t* mv = gm + (int64_t)vox * Gd.MW;
-                  m |= (uint64_t)mv[0] | (Gd.MW > 1 ? (uint64_t)mv[1] << 32 : 0ull);
-                }
-                float4 c0, c1, c2, c3;
-                int kk;
-                while ((kk = pop_cuboid(m, wbox, c0, c1, c2, c3)) >= 0) {
-#pragma unroll
-                  for (int i = q4; i < q4 + 4; ++i) cuboid_key_v(c0, c1, c2, c3, px[i], py[i], pz[i], kk, best[i], bk[i]);
-                }
+              for (int n = 0; n < SW_Q * SW_KS; ++n) {
+                if (n / SW_Q >= nj || q4 + n % SW_Q >= active) continue;
+                const int vox = voxel_of(Gd, px[n], py[n], pz[n]);
+                if (vox < 0) continue;
+                const uint32_t* mv = gm + (int64_t)vox * Gd.MW;
+                m |= (uint64_t)mv[0] | (Gd.MW > 1 ? (uint64_t)mv[1] << 32 : 0ull);
               }
+              swept_chunk_walk<SW_KS>(nj, m, wbox, px, py, pz, best, bk);
             }
           } else {
             for (int w = w_lo; w <= w_hi; ++w) {
               if (my_w != w || !seg) continue;
-              const cptr<float> wbox = as_const(W.box) + (int64_t)uniform(w) * K * 16;
-              closest_cuboids<8>(wbox, K, px, py, pz, best, bk);
+              const cptr<float> ubox = as_const(W.box) + (int64_t)uniform(w) * K * 16;
+              swept_chunk_dense<SW_KS>(nj, ubox, K, px, py, pz, best, bk);
             }
           }
           if (seg && K > 0) {
-            const float* mybox = W.box + (int64_t)my_w * K * 16;
 #pragma unroll
-            for (int i = 0; i < 8; ++i) {
+            for (int n = 0; n < SW_Q * SW_KS; ++n) {
+              const int jj = n / SW_Q, i = n % SW_Q;
               // no candidate (key INFINITY) or none within reach: the depth is zero
-              if (h + i >= active) continue;
-              const float r = sphere_of(R.sph, g * SPH_GROUP + h + i).w;
-              if (out_of_reach(best[i], cp.eta, r)) continue;
+              if (jj >= nj || q4 + i >= active) continue;
+              const float r = sphere_of(R.sph, g * SPH_GROUP + q4 + i).w;
+              if (out_of_reach(best[n], cp.eta, r)) continue;
               float sd, nx, ny, nz;
-              cuboid_sd_grad(mybox + bk[i] * 16, px[i], py[i], pz[i], sd, nx, ny, nz);
+              cuboid_sd_grad(wbox + bk[n] * 16, px[n], py[n], pz[n], sd, nx, ny, nz);
               const float d = fmaxf(cp.eta - (sd - r), 0.f);
               if (d > 0.f) {
                 cost = fmaf(d, d, cost);
                 const float cf = coef_base * d;
                 const float gx = cf * nx, gy = cf * ny, gz = cf * nz;
-                lo[0][i] = fmaf(1.f - u, gx, lo[0][i]);
-                lo[1][i] = fmaf(1.f - u, gy, lo[1][i]);
-                lo[2][i] = fmaf(1.f - u, gz, lo[2][i]);
-                hi[0][i] = fmaf(u, gx, hi[0][i]);
-                hi[1][i] = fmaf(u, gy, hi[1][i]);
-                hi[2][i] = fmaf(u, gz, hi[2][i]);
+                lo[0][i] = fmaf(1.f - uu[jj], gx, lo[0][i]);
+                lo[1][i] = fmaf(1.f - uu[jj], gy, lo[1][i]);
+                lo[2][i] = fmaf(1.f - uu[jj], gz, lo[2][i]);
+                hi[0][i] = fmaf(uu[jj], gx, hi[0][i]);
+                hi[1][i] = fmaf(uu[jj], gy, hi[1][i]);
+                hi[2][i] = fmaf(uu[jj], gz, hi[2][i]);
               }
             }
           }
@@ -914,16 +969,23 @@ __global__ __launch_bounds__(256) void k_swept(RobotArgs R, WorldArgs W, GridArg
       }
       // far-end gradient of the segment (c - 1, c) from lane - 1 (lane 63 for lane 0)
 #pragma unroll
-      for (int i = 0; i < 8; ++i) {
+      for (int i = 0; i < SW_Q; ++i) {
         const float fx = __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(hi[0][i])));
         const float fy = __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(hi[1][i])));
         const float fz = __int_as_float(__builtin_amdgcn_ds_bpermute(src, __float_as_int(hi[2][i])));
-        xg[h + i] = lo[0][i] + fx;
-        yg[h + i] = lo[1][i] + fy;
-        zg[h + i] = lo[2][i] + fz;
+        xs[((q4 + i) * 3 + 0) * 64] = lo[0][i] + fx;
+        xs[((q4 + i) * 3 + 1) * 64] = lo[1][i] + fy;
+        xs[((q4 + i) * 3 + 2) * 64] = lo[2][i] + fz;
       }
     }
     if (own) {
+      float xg[SPH_GROUP], yg[SPH_GROUP], zg[SPH_GROUP];
+#pragma unroll
+      for (int i = 0; i < SPH_GROUP; ++i) {
+        xg[i] = xs[(i * 3 + 0) * 64];
+        yg[i] = xs[(i * 3 + 1) * 64];
+        zg[i] = xs[(i * 3 + 2) * 64];
+      }
       store_group<SPH_GROUP>(X, c, g * 3 + 0, xg);
       store_group<SPH_GROUP>(X, c, g * 3 + 1, yg);
       store_group<SPH_GROUP>(X, c, g * 3 + 2, zg);
@@ -1693,7 +1755,7 @@ hipError_t launch_swept(hipStream_t s, const RobotArgs& R, const WorldArgs& W, c
   const dim3 grid(blocks_for(waves, 4)), block(256);
   switch (S.fmt) {
 #define VAPR_SWEPT_CASE(F) \
-  case F: hipLaunchKernelGGL(k_swept<F>, grid, block, 0, s, R, W, Gd, S, X, sweptc, sh, cp); break;
+  case F: hipLaunchKernelGGL(k_swept<F>, grid, block, SWEPT_LDS_BYTES, s, R, W, Gd, S, X, sweptc, sh, cp); break;
     VAPR_SWEPT_CASE(F32) VAPR_SWEPT_CASE(F16) VAPR_SWEPT_CASE(BF16) VAPR_SWEPT_CASE(E4M3) VAPR_SWEPT_CASE(E5M2)
     VAPR_SWEPT_CASE(E3M2) VAPR_SWEPT_CASE(E2M1)
 #undef VAPR_SWEPT_CASE

@@ -102,10 +102,21 @@ def test_swept_fp32_parity(T, tpw, n_ls):
 
 @pytest.mark.parametrize("k", [1, 2, 7, 16])
 def test_swept_sample_counts(k):
+    """Odd k leaves a last chunk of one sample in the kernel's two-sample candidate lists."""
     need_gpu()
     wl = swept_workload(seed=22, T=7, tpw=5)
     ctx, ws, shape, cost, grad, ref = run(wl, k=k, w_sw=37.5)
     check(wl, ctx, ws, shape, cost, grad, ref, k=k, w_sw=37.5)
+
+
+@pytest.mark.parametrize("n_spheres", [50, 17])
+def test_swept_ragged_sphere_counts(n_spheres):
+    """Sphere counts that leave a partly filled four-sphere list (50: two spheres in the last one)
+    and a nearly empty last group (17)."""
+    need_gpu()
+    wl = swept_workload(seed=28, T=6, tpw=5, n_spheres=n_spheres, n_pairs=min(300, n_spheres * 3))
+    ctx, ws, shape, cost, grad, ref = run(wl, k=3)
+    check(wl, ctx, ws, shape, cost, grad, ref, k=3)
 
 
 @pytest.mark.parametrize("pname,prec", [
@@ -162,12 +173,12 @@ def test_swept_off_and_state_errors():
         ctx.set_cost_params(swept_steps=17)
 
 
-@pytest.mark.parametrize("n_cuboids", [10, 40, 64, 70])
-def test_swept_culling_is_exact(n_cuboids):
+@pytest.mark.parametrize("n_cuboids,n_spheres", [(10, 60), (40, 60), (64, 60), (70, 60), (40, 50)])
+def test_swept_culling_is_exact(n_cuboids, n_spheres):
     """The grid-culled sample tests (up to 64 cuboids; more fall back to testing every cuboid) give
     bit-identical swept costs and gradients to testing every cuboid."""
     need_gpu()
-    wl = swept_workload(seed=27, T=9, tpw=7, n_cuboids=n_cuboids)
+    wl = swept_workload(seed=27, T=9, tpw=7, n_cuboids=n_cuboids, n_spheres=n_spheres)
     shape = shape_of(wl)
     q = dev(wl.q, torch.float32)
     out = []
