@@ -190,6 +190,12 @@ __device__ __forceinline__ int xcd_tile(int L, int T) {
   return x * q + min(x, r) + j;
 }
 
+// Workgroup barrier for LDS traffic only: this wave's LDS operations are complete (lgkmcnt 0), then
+// s_barrier.  Unlike __syncthreads() it does not wait for the wave's outstanding global stores, so
+// the output stores of one half of a tile stay in flight while the next half is staged.  The memory
+// clobber keeps the compiler from moving memory accesses across it.
+__device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
 template <bool A_K, bool B_N>
 __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
   // two stages of operand tiles (the next K step is loaded into registers while the MFMAs run on
@@ -225,6 +231,20 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  // the bias of the thread's four output columns (the same for every row it writes), loaded before
+  // the K loop so that its latency is hidden there
+  const int cc = (tid & 15) * 4;
+  float bias4[4] = {0.f, 0.f, 0.f, 0.f};
+  if (g.bias) {
+    const int nb = n0 + cc;
+    if (nb + 3 < g.N && ((reinterpret_cast<uintptr_t>(g.bias + nb)) & 15) == 0) {
+      const float4 b4 = *reinterpret_cast<const float4*>(g.bias + nb);
+      bias4[0] = b4.x; bias4[1] = b4.y; bias4[2] = b4.z; bias4[3] = b4.w;
+    } else {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) bias4[e] = nb + e < g.N ? g.bias[nb + e] : 0.f;
+    }
+  }
 
   Frag fa = load_a(0), fb = load_b(0);
   for (int k0 = 0, st = 0; k0 < g.K; k0 += GK, st ^= 1) {
@@ -257,7 +277,6 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
   // write back through LDS, 32 rows at a time (the waves with wm = 32 h stage half h): thread t
   // takes 4 consecutive columns (t % 16) * 4 of rows t / 16 and t / 16 + 16, so a wavefront stores
   // 4 full 256-byte row segments per instruction
-  const int cc = (tid & 15) * 4;
   const bool vec = (g.ldc & 3) == 0 && (((uintptr_t)g.C | (uintptr_t)g.aux) & 15) == 0 && ((uintptr_t)g.C16 & 7) == 0;
   for (int h = 0; h < 2; ++h) {
     if ((wave & 1) == h) {
@@ -269,7 +288,7 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
           for (int e = 0; e < 4; ++e)
             sC[(i * 16 + 4 * (lane >> 4) + e) * CPAD + wn + j * 16 + (lane & 15)] = acc[i][j][e];
     }
-    __syncthreads();
+    lds_barrier();
 #pragma unroll
     for (int rr = 0; rr < 2; ++rr) {
       const int r = (tid >> 4) + 16 * rr, m = m0 + 32 * h + r;
@@ -279,7 +298,7 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
       const float4 t4 = *reinterpret_cast<const float4*>(sC + r * CPAD + cc);
       float v[4] = {t4.x, t4.y, t4.z, t4.w};
 #pragma unroll
-      for (int e = 0; e < 4; ++e) v[e] += g.bias && nb + e < g.N ? g.bias[nb + e] : 0.f;
+      for (int e = 0; e < 4; ++e) v[e] += bias4[e];
       if (vec && nb + 3 < g.N) {
         if (g.epilogue == GEMM_GELU) {
           if (g.aux) *reinterpret_cast<float4*>(g.aux + o) = make_float4(v[0], v[1], v[2], v[3]);
@@ -317,7 +336,7 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
         }
       }
     }
-    __syncthreads();
+    lds_barrier();  // the staged half has been read before the next one overwrites it
   }
 }
 
