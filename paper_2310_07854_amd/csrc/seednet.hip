@@ -94,14 +94,23 @@ __global__ __launch_bounds__(256) void k_features(int n, const float* __restrict
 
 constexpr int GT = 64, GK = 32, GPAD = 40;
 
-// Seed-trajectory epilogue value for output column n of the block's row r: the straight line from
-// start to goal plus the network's deviation v at interior timesteps, start / goal exactly at the
-// ends.  se holds the block's start rows, then its goal rows ([2][GT][7]).
-__device__ __forceinline__ float seed_traj_value(const float* se, int r, int n, float v) {
+// Seed-trajectory epilogue for output column n: the straight line from start to goal plus the
+// network's deviation v at interior timesteps, start / goal exactly at the ends.  The column's joint,
+// line fraction t / (T - 1) and kind depend on n only, so a thread works them out once for the four
+// columns it writes; se holds the block's start rows, then its goal rows ([2][GT][7]).
+struct TrajCol {
+  int j;       // joint
+  float frac;  // t / (T - 1)
+  int kind;    // 0 start, 1 goal, 2 interior
+};
+__device__ __forceinline__ TrajCol traj_col(int n) {
   const int k = n % SEED_TRAJ, t = k / SEED_J, j = k - t * SEED_J;
-  const float s0 = se[r * SEED_J + j], g0 = se[(GT + r) * SEED_J + j];
-  const float line = fmaf(g0 - s0, (float)t / (float)(SEED_T - 1), s0);
-  return t == 0 ? s0 : (t == SEED_T - 1 ? g0 : line + v);
+  return TrajCol{j, (float)t / (float)(SEED_T - 1), t == 0 ? 0 : (t == SEED_T - 1 ? 1 : 2)};
+}
+__device__ __forceinline__ float seed_traj_value(const float* se, int r, const TrajCol& c, float v) {
+  const float s0 = se[r * SEED_J + c.j], g0 = se[(GT + r) * SEED_J + c.j];
+  const float line = fmaf(g0 - s0, c.frac, s0);
+  return c.kind == 0 ? s0 : (c.kind == 1 ? g0 : line + v);
 }
 
 constexpr int CPAD = GT + 4;  // staged output tile row stride (floats)
@@ -278,6 +287,9 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
   // takes 4 consecutive columns (t % 16) * 4 of rows t / 16 and t / 16 + 16, so a wavefront stores
   // 4 full 256-byte row segments per instruction
   const bool vec = (g.ldc & 3) == 0 && (((uintptr_t)g.C | (uintptr_t)g.aux) & 15) == 0 && ((uintptr_t)g.C16 & 7) == 0;
+  TrajCol tc[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) tc[e] = traj_col(n0 + cc + e);
   for (int h = 0; h < 2; ++h) {
     if ((wave & 1) == h) {
 #pragma unroll
@@ -309,7 +321,7 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
           v[0] *= gelu_grad_f(z.x); v[1] *= gelu_grad_f(z.y); v[2] *= gelu_grad_f(z.z); v[3] *= gelu_grad_f(z.w);
         } else if (g.epilogue == GEMM_SEED_TRAJ) {
 #pragma unroll
-          for (int e = 0; e < 4; ++e) v[e] = seed_traj_value(se, 32 * h + r, nb + e, v[e]);
+          for (int e = 0; e < 4; ++e) v[e] = seed_traj_value(se, 32 * h + r, tc[e], v[e]);
         }
         if (g.C) *reinterpret_cast<float4*>(g.C + o) = make_float4(v[0], v[1], v[2], v[3]);
         if (g.C16) {
@@ -329,7 +341,7 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
           } else if (g.epilogue == GEMM_GELU_GRAD) {
             w *= gelu_grad_f(g.aux[o + e]);
           } else if (g.epilogue == GEMM_SEED_TRAJ) {
-            w = seed_traj_value(se, 32 * h + r, nb + e, w);
+            w = seed_traj_value(se, 32 * h + r, tc[e], w);
           }
           if (g.C) g.C[o + e] = w;
           if (g.C16) g.C16[o + e] = to_bf16(w);
