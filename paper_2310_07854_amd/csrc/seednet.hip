@@ -92,12 +92,13 @@ __global__ __launch_bounds__(256) void k_features(int n, const float* __restrict
 // accumulator of lane l holds rows 4 (l / 16) + e, column l % 16 of its 16x16 tile.
 // A_K: A(m, k) contiguous in k (else in m); B_N: B(k, n) contiguous in n (else in k).
 
-constexpr int GT = 64, GK = 32, GPAD = 40;
+constexpr int GK = 32, GPAD = 40;
+constexpr int64_t GEMM_BIG_TILES_MIN = 1024;  // 128 x 128 tiles from this many on
 
 // Seed-trajectory epilogue for output column n: the straight line from start to goal plus the
 // network's deviation v at interior timesteps, start / goal exactly at the ends.  The column's joint,
 // line fraction t / (T - 1) and kind depend on n only, so a thread works them out once for the four
-// columns it writes; se holds the block's start rows, then its goal rows ([2][GT][7]).
+// columns it writes; se holds the block's TM start rows, then its TM goal rows ([2][TM][7]).
 struct TrajCol {
   int j;       // joint
   float frac;  // t / (T - 1)
@@ -107,14 +108,13 @@ __device__ __forceinline__ TrajCol traj_col(int n) {
   const int k = n % SEED_TRAJ, t = k / SEED_J, j = k - t * SEED_J;
   return TrajCol{j, (float)t / (float)(SEED_T - 1), t == 0 ? 0 : (t == SEED_T - 1 ? 1 : 2)};
 }
+template <int TM>
 __device__ __forceinline__ float seed_traj_value(const float* se, int r, const TrajCol& c, float v) {
-  const float s0 = se[r * SEED_J + c.j], g0 = se[(GT + r) * SEED_J + c.j];
+  const float s0 = se[r * SEED_J + c.j], g0 = se[(TM + r) * SEED_J + c.j];
   const float line = fmaf(g0 - s0, c.frac, s0);
   return c.kind == 0 ? s0 : (c.kind == 1 ? g0 : line + v);
 }
 
-constexpr int CPAD = GT + 4;  // staged output tile row stride (floats)
-static_assert((GT / 2) * CPAD * 4 <= 2 * GT * GPAD * 2, "half output tile must fit in one operand stage");
 
 // One operand tile (64 rows x 32 k) is stored in LDS as [row][k] (row stride GPAD halfwords), with
 // the four 8-element k chunks of a row permuted by an XOR with bits 4..5 of the row: the transposing
@@ -205,44 +205,57 @@ __device__ __forceinline__ int xcd_tile(int L, int T) {
 // clobber keeps the compiler from moving memory accesses across it.
 __device__ __forceinline__ void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
-template <bool A_K, bool B_N>
-__global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
+// One workgroup (4 wavefronts in 2 x 2) per TM x TN output tile; each wavefront computes a
+// (TM / 2) x (TN / 2) block as (TM / 32) x (TN / 32) MFMA tiles of 16 x 16.  Operand tiles are staged
+// 64 rows at a time with the helpers above.  64 x 64 tiles serve small problems (training batches);
+// 128 x 128 tiles, with 16 MFMAs per wavefront and K step, amortise the staging and addressing of
+// each step over four times the matrix work on large ones.
+template <bool A_K, bool B_N, int TM, int TN>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TM * TN > 64 * 64 ? 3 : 1))) void k_gemm_bf16(
+    GemmArgs g) {
+  static_assert(TM % 64 == 0 && TN % 64 == 0, "tiles are staged 64 rows at a time");
+  constexpr int FM = TM / 32, FN = TN / 32;  // MFMA tiles per wavefront along m and n
+  constexpr int CPAD = TN + 4;               // staged output row stride (floats)
+  constexpr int STAGE = (TM + TN) * GPAD;    // halfwords of one operand stage
+  static_assert((TM / 2) * CPAD * 4 <= 2 * STAGE * 2, "half an output tile must fit in the operand stages");
   // two stages of operand tiles (the next K step is loaded into registers while the MFMAs run on
   // the current one); after the K loop the same memory stages half of the output tile at a time
-  __shared__ __attribute__((aligned(16))) uint16_t smem[2][2 * GT * GPAD];
-  __shared__ float se[2 * GT * SEED_J];  // start / goal rows of the block (GEMM_SEED_TRAJ)
-  float* sC = reinterpret_cast<float*>(smem[0]);
+  __shared__ __attribute__((aligned(16))) uint16_t smem[2][STAGE];
+  __shared__ float se[2 * TM * SEED_J];  // start / goal rows of the block (GEMM_SEED_TRAJ)
+  float* sC = reinterpret_cast<float*>(&smem[0][0]);
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int n_tiles_n = (g.N + GT - 1) / GT;
+  const int n_tiles_n = (g.N + TN - 1) / TN;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  const int m0 = (tile / n_tiles_n) * GT, n0 = (tile % n_tiles_n) * GT;
+  const int m0 = (tile / n_tiles_n) * TM, n0 = (tile % n_tiles_n) * TN;
   if (g.epilogue == GEMM_SEED_TRAJ) {
     // read before the K loop, whose barriers publish them
-    for (int i = tid; i < 2 * GT * SEED_J; i += 256) {
-      const int h = i / (GT * SEED_J), q = i - h * GT * SEED_J;
+    for (int i = tid; i < 2 * TM * SEED_J; i += 256) {
+      const int h = i / (TM * SEED_J), q = i - h * TM * SEED_J;
       const int64_t o = (int64_t)m0 * SEED_J + q;
       se[i] = o < (int64_t)g.M * SEED_J ? (h ? g.goal : g.start)[o] : 0.f;
     }
   }
-  const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
+  const int wm = (wave & 1) * (TM / 2), wn = (wave >> 1) * (TN / 2);
   const bool a_vec = (g.sak & 7) == 0 && (reinterpret_cast<uintptr_t>(g.A) & 15) == 0;
   const bool b_vec = (g.sbk & 7) == 0 && (reinterpret_cast<uintptr_t>(g.B) & 15) == 0;
-  auto load_a = [&](int k0) {
-    if constexpr (A_K) return load_kc(g.A, g.sam, m0, g.M, k0, tid);
-    else return load_rc(g.A, g.sak, m0, g.M, k0, a_vec, tid);
+  // operand rows c * 64 .. c * 64 + 63 of the tile at k step k0
+  auto load_a = [&](int c, int k0) {
+    if constexpr (A_K) return load_kc(g.A, g.sam, m0 + 64 * c, g.M, k0, tid);
+    else return load_rc(g.A, g.sak, m0 + 64 * c, g.M, k0, a_vec, tid);
   };
-  auto load_b = [&](int k0) {
-    if constexpr (B_N) return load_rc(g.B, g.sbk, n0, g.N, k0, b_vec, tid);
-    else return load_kc(g.B, g.sbn, n0, g.N, k0, tid);
+  auto load_b = [&](int c, int k0) {
+    if constexpr (B_N) return load_rc(g.B, g.sbk, n0 + 64 * c, g.N, k0, b_vec, tid);
+    else return load_kc(g.B, g.sbn, n0 + 64 * c, g.N, k0, tid);
   };
-  f32x4 acc[2][2];
+  f32x4 acc[FM][FN];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < FM; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-  // the bias of the thread's four output columns (the same for every row it writes), loaded before
-  // the K loop so that its latency is hidden there
-  const int cc = (tid & 15) * 4;
+    for (int j = 0; j < FN; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  // the output columns of this thread in the write-back (the same for every row it writes): their
+  // bias, loaded before the K loop so that its latency is hidden there
+  constexpr int CG = TN / 4;                 // 4-column groups per row
+  const int cc = (tid % CG) * 4;
   float bias4[4] = {0.f, 0.f, 0.f, 0.f};
   if (g.bias) {
     const int nb = n0 + cc;
@@ -255,55 +268,69 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
     }
   }
 
-  Frag fa = load_a(0), fb = load_b(0);
+  Frag fa[TM / 64], fb[TN / 64];
+#pragma unroll
+  for (int c = 0; c < TM / 64; ++c) fa[c] = load_a(c, 0);
+#pragma unroll
+  for (int c = 0; c < TN / 64; ++c) fb[c] = load_b(c, 0);
   for (int k0 = 0, st = 0; k0 < g.K; k0 += GK, st ^= 1) {
     uint16_t* sA = smem[st];
-    uint16_t* sB = smem[st] + GT * GPAD;
-    if constexpr (A_K) store_kc(fa, sA, tid);
-    else store_rc(fa, a_vec, sA, tid);
-    if constexpr (B_N) store_rc(fb, b_vec, sB, tid);
-    else store_kc(fb, sB, tid);
+    uint16_t* sB = smem[st] + TM * GPAD;
+#pragma unroll
+    for (int c = 0; c < TM / 64; ++c) {
+      if constexpr (A_K) store_kc(fa[c], sA + 64 * c * GPAD, tid);
+      else store_rc(fa[c], a_vec, sA + 64 * c * GPAD, tid);
+    }
+#pragma unroll
+    for (int c = 0; c < TN / 64; ++c) {
+      if constexpr (B_N) store_rc(fb[c], b_vec, sB + 64 * c * GPAD, tid);
+      else store_kc(fb[c], sB + 64 * c * GPAD, tid);
+    }
     // one barrier per step: the stage written here was last read two steps ago, before the
     // previous barrier
     __syncthreads();
     if (k0 + GK < g.K) {
-      fa = load_a(k0 + GK);
-      fb = load_b(k0 + GK);
-    }
-    bf16x8 a[2], b[2];
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
+      for (int c = 0; c < TM / 64; ++c) fa[c] = load_a(c, k0 + GK);
+#pragma unroll
+      for (int c = 0; c < TN / 64; ++c) fb[c] = load_b(c, k0 + GK);
+    }
+    bf16x8 a[FM], b[FN];
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
       a[i] = *reinterpret_cast<const bf16x8*>(sA + lds_off(wm + i * 16 + (lane & 15), lane >> 4));
-      b[i] = *reinterpret_cast<const bf16x8*>(sB + lds_off(wn + i * 16 + (lane & 15), lane >> 4));
-    }
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < FN; ++j)
+      b[j] = *reinterpret_cast<const bf16x8*>(sB + lds_off(wn + j * 16 + (lane & 15), lane >> 4));
 #pragma unroll
-      for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
   }
   __syncthreads();
 
-  // write back through LDS, 32 rows at a time (the waves with wm = 32 h stage half h): thread t
-  // takes 4 consecutive columns (t % 16) * 4 of rows t / 16 and t / 16 + 16, so a wavefront stores
-  // 4 full 256-byte row segments per instruction
+  // write back through LDS, TM / 2 rows at a time (the waves with wm = (TM / 2) h stage half h):
+  // thread t takes 4 consecutive columns (t % CG) * 4 of rows t / CG + (256 / CG) rr, so a
+  // wavefront stores full row segments of 4 TN bytes per instruction
   const bool vec = (g.ldc & 3) == 0 && (((uintptr_t)g.C | (uintptr_t)g.aux) & 15) == 0 && ((uintptr_t)g.C16 & 7) == 0;
   TrajCol tc[4];
 #pragma unroll
   for (int e = 0; e < 4; ++e) tc[e] = traj_col(n0 + cc + e);
+  constexpr int RS = 256 / CG;               // rows per sweep of the workgroup
   for (int h = 0; h < 2; ++h) {
     if ((wave & 1) == h) {
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < FM; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < FN; ++j)
 #pragma unroll
           for (int e = 0; e < 4; ++e)
             sC[(i * 16 + 4 * (lane >> 4) + e) * CPAD + wn + j * 16 + (lane & 15)] = acc[i][j][e];
     }
     lds_barrier();
 #pragma unroll
-    for (int rr = 0; rr < 2; ++rr) {
-      const int r = (tid >> 4) + 16 * rr, m = m0 + 32 * h + r;
+    for (int rr = 0; rr < (TM / 2) / RS; ++rr) {
+      const int r = tid / CG + RS * rr, m = m0 + (TM / 2) * h + r;
       const int nb = n0 + cc;
       if (m >= g.M || nb >= g.N) continue;
       const int64_t o = (int64_t)m * g.ldc + nb;
@@ -321,7 +348,7 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
           v[0] *= gelu_grad_f(z.x); v[1] *= gelu_grad_f(z.y); v[2] *= gelu_grad_f(z.z); v[3] *= gelu_grad_f(z.w);
         } else if (g.epilogue == GEMM_SEED_TRAJ) {
 #pragma unroll
-          for (int e = 0; e < 4; ++e) v[e] = seed_traj_value(se, 32 * h + r, tc[e], v[e]);
+          for (int e = 0; e < 4; ++e) v[e] = seed_traj_value<TM>(se, (TM / 2) * h + r, tc[e], v[e]);
         }
         if (g.C) *reinterpret_cast<float4*>(g.C + o) = make_float4(v[0], v[1], v[2], v[3]);
         if (g.C16) {
@@ -341,7 +368,7 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
           } else if (g.epilogue == GEMM_GELU_GRAD) {
             w *= gelu_grad_f(g.aux[o + e]);
           } else if (g.epilogue == GEMM_SEED_TRAJ) {
-            w = seed_traj_value(se, 32 * h + r, tc[e], w);
+            w = seed_traj_value<TM>(se, (TM / 2) * h + r, tc[e], w);
           }
           if (g.C) g.C[o + e] = w;
           if (g.C16) g.C16[o + e] = to_bf16(w);
@@ -492,15 +519,26 @@ hipError_t launch_features(hipStream_t s, int n, const float* start, const float
   return hipGetLastError();
 }
 
-hipError_t launch_gemm_bf16(hipStream_t s, const GemmArgs& g, bool a_k, bool b_n) {
-  const int64_t tiles = (int64_t)nblocks(g.M, GT) * nblocks(g.N, GT);
+template <int TM, int TN>
+static hipError_t launch_gemm_tiles(hipStream_t s, const GemmArgs& g, bool a_k, bool b_n) {
+  const int64_t tiles = (int64_t)nblocks(g.M, TM) * nblocks(g.N, TN);
   if (tiles > INT32_MAX) return hipErrorInvalidValue;
   const dim3 grid((unsigned)tiles), block(256);
-  if (a_k && b_n) hipLaunchKernelGGL((k_gemm_bf16<true, true>), grid, block, 0, s, g);
-  else if (a_k) hipLaunchKernelGGL((k_gemm_bf16<true, false>), grid, block, 0, s, g);
-  else if (b_n) hipLaunchKernelGGL((k_gemm_bf16<false, true>), grid, block, 0, s, g);
-  else hipLaunchKernelGGL((k_gemm_bf16<false, false>), grid, block, 0, s, g);
+  if (a_k && b_n) hipLaunchKernelGGL((k_gemm_bf16<true, true, TM, TN>), grid, block, 0, s, g);
+  else if (a_k) hipLaunchKernelGGL((k_gemm_bf16<true, false, TM, TN>), grid, block, 0, s, g);
+  else if (b_n) hipLaunchKernelGGL((k_gemm_bf16<false, true, TM, TN>), grid, block, 0, s, g);
+  else hipLaunchKernelGGL((k_gemm_bf16<false, false, TM, TN>), grid, block, 0, s, g);
   return hipGetLastError();
+}
+
+hipError_t launch_gemm_bf16(hipStream_t s, const GemmArgs& g, bool a_k, bool b_n) {
+  // 128 x 128 tiles once they still give every CU several workgroups (large batches: inference);
+  // 64 x 64 tiles otherwise (training batches)
+  // (A with k contiguous: the forward layers; the transposed-A instantiation would not fit three
+  // wavefronts per SIMD)
+  const int64_t big_tiles = (int64_t)nblocks(g.M, 128) * nblocks(g.N, 128);
+  if (a_k && big_tiles >= GEMM_BIG_TILES_MIN) return launch_gemm_tiles<128, 128>(s, g, a_k, b_n);
+  return launch_gemm_tiles<64, 64>(s, g, a_k, b_n);
 }
 
 hipError_t launch_seed_traj(hipStream_t s, int n, const float* y, const float* start, const float* goal, float* out) {

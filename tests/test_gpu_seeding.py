@@ -146,6 +146,42 @@ def test_occupancy_matches_oracle():
     assert not empty.any()
 
 
+@pytest.mark.parametrize("b_n", [True, False])
+def test_gemm_large_tiles_match_small_tiles(b_n):
+    """A product large enough for the 128 x 128 tiles, ragged in M and N: every output equals the
+    same product computed in row slices small enough for the 64 x 64 tiles, bit for bit (both sum K
+    in the same 32-wide MFMA steps), and the GELU pre-activation lies in the FP32 error band of the
+    float64 product."""
+    need_gpu()
+    rng = np.random.default_rng(97 + b_n)
+    M, N, K = 4133, 4100, 96
+    A = F.decode(bf16_codes(rng.normal(size=(M, K))), "bf16").astype(np.float64)
+    B = F.decode(bf16_codes(rng.normal(size=(K, N))), "bf16").astype(np.float64)
+    bias_h = F.fp32(rng.normal(size=N)).astype(np.float64)
+    bias = torch.tensor(bias_h, dtype=torch.float32, device="cuda:0")
+    Ad = dev_bf16(A)
+    Bd = dev_bf16(B if b_n else B.T.copy())
+    b_ks, b_ns = (N, 1) if b_n else (1, K)
+
+    def run(r0, r1, z, c, c16):
+        S().gemm(Ad[r0:r1], K, 1, Bd, b_ks, b_ns, r1 - r0, N, K, bias=bias, epilogue=S().GELU, aux=z[r0:r1],
+                 C=c[r0:r1], C16=c16[r0:r1])
+
+    out = [(torch.empty(M, N, dtype=torch.float32, device="cuda:0"), torch.empty(M, N, dtype=torch.float32,
+            device="cuda:0"), torch.empty(M, N, dtype=torch.bfloat16, device="cuda:0")) for _ in range(2)]
+    run(0, M, *out[0])
+    for r0 in range(0, M, 512):
+        run(r0, min(M, r0 + 512), *out[1])
+    torch.cuda.synchronize()
+    for big, small in zip(out[0], out[1]):
+        np.testing.assert_array_equal(big.view(torch.int16 if big.dtype == torch.bfloat16 else torch.int32).cpu().numpy(),
+                                      small.view(torch.int16 if small.dtype == torch.bfloat16 else torch.int32).cpu().numpy())
+    ref = A @ B + bias_h
+    band = K * U32 * (np.abs(A) @ np.abs(B)) + U32 * np.abs(bias_h) + 1e-30
+    got = out[0][0].cpu().numpy().astype(np.float64)
+    assert np.all(np.abs(got - ref) <= band), float(np.max(np.abs(got - ref) / band))
+
+
 @pytest.mark.parametrize("ldc_pad", [3, 4])
 def test_gemm_row_stride_keeps_padding(ldc_pad):
     """Outputs with ldc > N (padded rows, odd and 16-byte multiple strides): every element equals the
@@ -169,10 +205,11 @@ def test_gemm_row_stride_keeps_padding(ldc_pad):
     assert bool((z[:, N:] == 7.0).all()) and bool((c[:, N:] == 7.0).all())
 
 
-@pytest.mark.parametrize("n,lda", [(1, 256), (100, 256), (257, 264)])
+@pytest.mark.parametrize("n,lda", [(1, 256), (100, 256), (257, 264), (9401, 256)])
 def test_seed_head_equals_gemm_then_trajectories(n, lda):
     """The fused output layer equals the plain GEMM followed by the trajectory kernel bit for bit
-    (ragged problem counts, a padded hidden-layer row stride)."""
+    (ragged problem counts, a padded hidden-layer row stride; 9,401 problems take the 128 x 128
+    tiles)."""
     need_gpu()
     rng = np.random.default_rng(n)
     net = S().SeedNet(make_seednet_params())
