@@ -132,7 +132,8 @@ def world_term(S: np.ndarray, radius: np.ndarray, pose: np.ndarray, half_ext: np
         grad[idx] = bgrad
         kstar[idx] = bk
         # no runner-up (fewer than two cuboids): no switch to guard against
-        gap2 = np.where(np.isfinite(second), second - best, np.inf)
+        with np.errstate(invalid="ignore"):  # inf - inf where there is no runner-up; replaced below
+            gap2 = np.where(np.isfinite(second), second - best, np.inf)
         margin[idx] = np.minimum(gap2, bgap)
     return d, grad, kstar, margin
 

@@ -22,7 +22,7 @@ def _state_case(n_traj=7, T=8, n_ls=4, m=3, seed=0):
     g = O.pin_rows(O.fp32(rng.normal(size=(n_traj, n))), T)
     d = O.fp32(-g * rng.uniform(0.5, 1.5, size=(n_traj, n)))
     cost = rng.uniform(10, 20, size=n_traj)
-    hist_len = np.array([2, 2, 2, 1, 2, 3, 0])[:n_traj]
+    hist_len = np.array([2, 2, 2, 1, 2, m, 0])[:n_traj]  # trajectory 5: a full ring
     hist_head = np.array([2, 2, 2, 1, 2, 1, 0])[:n_traj]
     S = O.fp32(O.pin_rows(rng.normal(size=(n_traj, m, n)) * 0.1, T))
     Y = O.fp32(S * rng.uniform(0.5, 2.0, size=(n_traj, m, n)))  # positive curvature
@@ -57,11 +57,15 @@ def _oracle_step(case, t):
     return st, info
 
 
-def test_step_matches_oracle():
+@pytest.mark.parametrize("T,m", [(8, 3), (19, 3), (48, 8), (64, 8)])
+def test_step_matches_oracle(T, m):
+    """Every variables-per-lane instantiation class: 7T = 56 (one per lane), 133 (ragged, three per
+    lane), 336 (six, the benchmark's horizon) and 448 (seven, the longest horizon), with a short and
+    the full eight-pair history."""
     need_gpu()
     from paper_2310_07854_amd import Shape, _lib as L
 
-    case = _state_case()
+    case = _state_case(T=T, m=m, seed=T + m)
     T, n_ls, m = case["T"], case["n_ls"], case["m"]
     n_traj, n = case["x"].shape
     wl = make_workload("tiny")

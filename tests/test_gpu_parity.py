@@ -63,7 +63,9 @@ def run_oracle(wl, prec=None, recompute=False, upstream=None):
                       prec=oracle_precision(prec, recompute), upstream=upstream)
 
 
-def check_fp32(wl, ref, cost, grad):
+def check_fp32(wl, ref, cost, grad, min_checked=0.5):
+    """Costs within the FP32 bound everywhere; gradients within it on every kink-free
+    configuration, which must be at least `min_checked` of them."""
     tol = cost_tolerance(ref, wl.robot.n_pairs, wl.T)
     err = np.abs(cost - ref["cost_traj"])
     assert np.all(err <= tol), f"cost: max err {err.max():.3e}, worst ratio {(err / tol).max():.3f}"
@@ -72,7 +74,7 @@ def check_fp32(wl, ref, cost, grad):
     gtol = grad_tolerance(ref)
     bad = (gerr > gtol).any(axis=1) & ok
     assert not bad.any(), f"grad: {int(bad.sum())} configs out of tolerance, max err {gerr[ok].max():.3e}"
-    assert ok.mean() > 0.5
+    assert ok.mean() > min_checked
 
 
 @pytest.mark.parametrize("name", ["tiny", "batched"])
@@ -203,10 +205,13 @@ def shuffled_robot(robot, seed):
 
 
 @pytest.mark.parametrize("case", ["ragged", "no_cuboids", "no_pairs", "one_sphere", "worlds_in_wave",
-                                  "many_spheres", "shuffled_links", "shuffled_many_spheres", "many_cuboids"])
+                                  "many_spheres", "shuffled_links", "shuffled_many_spheres", "many_cuboids",
+                                  "max_sizes"])
 def test_edge_shapes(case):
     need_gpu()
     kw = dict(seed=21, n_worlds=3, tpw=3, T=5, n_ls=2, n_spheres=37, n_cuboids=7, n_pairs=40)
+    if case == "max_sizes":  # the largest robot and world the boundary accepts
+        kw.update(n_worlds=2, tpw=2, T=4, n_spheres=256, n_pairs=4096, n_cuboids=256)
     if case in ("many_spheres", "shuffled_many_spheres"):
         # more than 8 sphere groups: the kernel that reads positions from HBM
         kw.update(n_spheres=150, n_pairs=400)
@@ -227,7 +232,9 @@ def test_edge_shapes(case):
     ctx = make_context(wl, {})
     cost, grad, _, _, _ = run_gpu(ctx, wl)
     ref = run_oracle(wl, {})
-    check_fp32(wl, ref, cost, grad)
+    # 256 spheres against 256 doubled cuboids and 4,096 pairs put about half of the configurations
+    # within the kink margin of some sphere or pair; the rest are still checked exactly
+    check_fp32(wl, ref, cost, grad, min_checked=0.3 if case == "max_sizes" else 0.5)
 
 
 def _sampled_oracle(wl, tcs, prec):
