@@ -629,6 +629,48 @@ def swept_bench(args):
     print(json.dumps(line), flush=True)
 
 
+def batched_workload(torch, steps, warmup):
+    """Optimiser iterations per second on the batched workload with a line search: 4 worlds x 32 seeds
+    x 32 timesteps x 4 step-scale candidates = 16,384 configurations per iteration, 40 cuboids,
+    FP32 and the paper-like assignment (scales calibrated on the batch's initial trajectories)."""
+    from paper_2310_07854_amd import Context, Shape, TrajectoryOptimizer
+    from synthetic import make_robot, make_trajectories, make_worlds
+
+    W, S, Tn, nls, K = 4, 32, 32, 4, 40
+    B = W * S * Tn * nls
+    ctx = Context(0)
+    ctx.set_robot(make_robot(N_SPHERES, N_PAIRS))
+    worlds = make_worlds(W, K)
+    ctx.set_worlds(worlds.pose, worlds.half_ext)
+    x0 = torch.tensor(make_trajectories(W, S, Tn).reshape(W * S, Tn, 7), dtype=torch.float32, device="cuda:0")
+    ctx.set_precision({})
+    sh = Shape(W, S, Tn, 1)
+    q = x0.reshape(-1, 7).contiguous()
+    _, ws = ctx.cost_fwd(q, sh)
+    ctx.cost_bwd(q, ws, want_grad=False)
+    amax = {t: float(ctx.ws_export(t, ws, sh).view(torch.float32).abs().max()) for t in
+            ("link_poses", "sphere_pos", "sphere_dist", "sphere_grad", "joint_grad")}
+    out = {"workload": "4 worlds x 32 seeds x 32 timesteps x 4 line-search candidates = 16,384 configurations "
+                       "per iteration; 60 spheres, 300 self pairs, 40 cuboids per world"}
+    for name in ("f32", "paper_like"):
+        ctx.set_precision(with_scales(PRECISIONS[name], amax) if name != "f32" else {})
+        opt = TrajectoryOptimizer(ctx, W, S, Tn, n_ls=nls, m=HIST_M)
+        opt.init(x0)
+        for _ in range(warmup):
+            opt.step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            opt.step()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        out[name] = {"iterations_per_s": 1.0 / dt, "ms_per_iteration": dt * 1e3, "evals_per_s": B / dt,
+                     "cost_sum": float(opt.cost.sum())}
+        del opt
+    ctx.close()
+    return out
+
+
 def graph_bench(args):
     """Eager iterations against replays of one captured HIP graph of the iteration, on the batched
     FP32 workload (4 worlds x 32 seeds x 32 timesteps, 4 line-search candidates: 16,384
@@ -1026,6 +1068,7 @@ def main():
         if name not in ("f32", args.precision):
             line.setdefault("variants", {})[name] = B * args.steps / results[name]["seconds"]
     ctx.close()
+    line["batched"] = batched_workload(torch, max(args.steps, 50), args.warmup)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(prec)
     else:
