@@ -14,7 +14,7 @@ k = ceil(log2(amax / max_finite)) clamped to [-16, 16] (F32: 0).  Bits per confi
 stored values only (L 96, S 180, D 60, G 180, J 7).  Writes every row to a CSV and prints the
 Pareto front of bits against each error plus the named assignments.
 
-  python tests/report_precision_sweep.py [--out gpurun_out/precision_sweep.csv] [--limit N]
+  python tests/report_precision_sweep.py [--out precision_sweep.csv] [--limit N]
 """
 from __future__ import annotations
 
@@ -72,7 +72,7 @@ def pareto(rows, key):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--out", default=os.path.join(ROOT, "gpurun_out", "precision_sweep.csv"))
+    ap.add_argument("--out", default="precision_sweep.csv", help="CSV path (default: the working directory)")
     ap.add_argument("--limit", type=int, default=0, help="only the first N assignments (0: all)")
     args = ap.parse_args()
 
