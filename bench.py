@@ -315,8 +315,6 @@ def run_variant(torch, ctx, opt_cls, x0, prec, steps, warmup, want_opt=False, re
 def cpu_baseline(prec, budget_s=12.0):
     """The FP64 oracle (quantisation emulated at the same five tensors) timed on the host for one
     optimisation iteration of a sample of whole trajectories, single-threaded."""
-    from threadpoolctl import threadpool_limits
-
     from oracle import cost as OC
     from oracle import optimizer as OO
     from synthetic import make_robot, make_trajectories, make_worlds
@@ -342,15 +340,109 @@ def cpu_baseline(prec, budget_s=12.0):
             OO.step(st, out["cost_traj"][i:i + 1], out["grad_q"].reshape(n_traj, 1, -1)[i], T, HIST_M)
         return time.perf_counter() - t0
 
-    with threadpool_limits(limits=1):
-        # per-trajectory time from the slope between two small samples (a call has a fixed cost)
-        t8, t32 = one(8), one(32)
-        per = max((t32 - t8) / 24.0, t32 / 64.0, 1e-6)
-        n = int(max(8, min(N_WORLDS * TPW, budget_s / per)))
-        dt = one(n)
+    n, dt = timed_sample(one, N_WORLDS * TPW, budget_s)
     return {"value": n * T * N_LS / dt, "unit": "evals/s", "cores": 1, "kind": "oracle",
             "sample": f"{n} trajectories x {T} timesteps = {n * T} configurations, one iteration, "
                       f"{dt:.1f} s single-threaded"}
+
+
+def timed_sample(one, n_max, budget_s):
+    """(n, seconds) of one(n) single-threaded, with n sized from the slope between two small samples
+    (a call has a fixed cost) so that it takes about budget_s."""
+    from threadpoolctl import threadpool_limits
+
+    with threadpool_limits(limits=1):
+        t8, t32 = one(8), one(32)
+        per = max((t32 - t8) / 24.0, t32 / 64.0, 1e-6)
+        n = int(max(8, min(n_max, budget_s / per)))
+        dt = one(n)
+        if dt < 0.5 * budget_s and n < n_max:  # the small samples overstated the per-item time
+            n = int(min(n_max, n * budget_s / dt))
+            dt = one(n)
+        return n, dt
+
+
+def swept_cpu_baseline(prec, k, budget_s=12.0):
+    """The oracle with the swept term (k samples per segment, quantisation emulated at the six
+    stored tensors) for one optimisation iteration of a sample of whole trajectories."""
+    from oracle import cost as OC
+    from oracle import optimizer as OO
+    from synthetic import Worlds, make_robot, make_trajectories, make_worlds
+
+    robot = make_robot(N_SPHERES, N_PAIRS)
+    worlds = make_worlds(N_WORLDS, N_CUBOIDS)
+    traj = make_trajectories(N_WORLDS, TPW, T)
+    oprec = OC.Precision(**{t: ((v, 0) if isinstance(v, str) else tuple(v)) for t, v in prec.items()})
+    params = OC.CostParams(swept_steps=k, w_swept=100.0)
+
+    def one(n_traj):
+        x = traj.reshape(-1, T, 7)[:n_traj]
+        sub = Worlds(pose=worlds.pose[np.arange(n_traj) // TPW], half_ext=worlds.half_ext[np.arange(n_traj) // TPW])
+        t0 = time.perf_counter()
+        out = OC.fwd_bwd(robot, sub, x.reshape(-1, 7), 1, T, N_LS, prec=oprec, params=params)
+        for i in range(n_traj):
+            st = OO.TrajState(x=x[i].reshape(-1), g=np.zeros(T * 7), d=-np.ones(T * 7) * 1e-3,
+                              cost=float(out["cost_traj"][i]) + 1.0)
+            OO.step(st, out["cost_traj"][i:i + 1], out["grad_q"].reshape(n_traj, 1, -1)[i], T, HIST_M)
+        return time.perf_counter() - t0
+
+    n, dt = timed_sample(one, N_WORLDS * TPW, budget_s)
+    return {"value": n * T / dt, "unit": "evals/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n} trajectories x {T} timesteps = {n * T} configurations with the swept term "
+                      f"(k = {k}), one iteration, {dt:.1f} s single-threaded"}
+
+
+def ik_cpu_baseline(prec, budget_s=12.0):
+    """The oracle on the inverse-kinematics workload (pose, collision, self and bound costs, one
+    configuration per trajectory, free rows) for one iteration of a sample of seeds against problem 0,
+    with the goal computed by the oracle's own kinematics."""
+    from oracle import cost as OC
+    from oracle import optimizer as OO
+    from oracle.kinematics import forward_kinematics
+    from synthetic import Worlds, make_configs, make_robot, make_worlds
+
+    robot = make_robot(N_SPHERES, N_PAIRS)
+    worlds = make_worlds(N_WORLDS, N_CUBOIDS)
+    qg = make_configs(N_WORLDS, seed=77)
+    goals = forward_kinematics(robot.fixed_tf, qg[:1])[:, 8, :3, :]
+    q = make_configs(N_WORLDS * IK_SEEDS, seed=78)  # the benchmark's seeds, all posed against problem 0
+    oprec = OC.Precision(**{t: ((v, 0) if isinstance(v, str) else tuple(v)) for t, v in prec.items()})
+    sub = Worlds(pose=worlds.pose[:1], half_ext=worlds.half_ext[:1])
+
+    def one(n):
+        t0 = time.perf_counter()
+        out = OC.fwd_bwd(robot, sub, q[:n], n, 1, 1, prec=oprec, goals=goals)
+        for i in range(n):
+            st = OO.TrajState(x=q[i].copy(), g=np.zeros(7), d=-np.ones(7) * 1e-3, cost=float(out["cost_traj"][i]) + 1.0)
+            OO.step(st, out["cost_traj"][i:i + 1], out["grad_q"][i:i + 1], 1, HIST_M, pin=False)
+        return time.perf_counter() - t0
+
+    n, dt = timed_sample(one, len(q), budget_s)
+    return {"value": n / dt, "unit": "evals/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n} seeds against one problem (one configuration each), one iteration, {dt:.1f} s "
+                      f"single-threaded"}
+
+
+def seed_cpu_baseline(budget_s=12.0):
+    """The oracle's seeding network inference (occupancy, features, three GELU layers, output layer
+    and trajectory construction, FP64 with BF16 operands emulated) on a sample of problems."""
+    from oracle import seeding as SD
+    from synthetic import make_seed_problems, make_seednet_params
+
+    params = make_seednet_params()
+    pr = make_seed_problems(8192, 16, split=7)
+
+    def one(n):
+        t0 = time.perf_counter()
+        occ = SD.occupancy(pr.worlds.pose[:n], pr.worlds.half_ext[:n])
+        x = SD.features(pr.start[:n], pr.goal[:n], occ)
+        y, _ = SD.forward(params, x, emulate=True)
+        SD.seeds(y, pr.start[:n], pr.goal[:n])
+        return time.perf_counter() - t0
+
+    n, dt = timed_sample(one, 8192, budget_s)
+    return {"value": n / dt, "unit": "problems/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n} problems of 16 cuboids, inference, {dt:.1f} s single-threaded"}
 
 
 def seeding_study(args):
@@ -566,7 +658,8 @@ def seed_inference(args):
             "kernels": kern,
             "roofline": {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": ach / HBM_PEAK_GBS, "traffic": None,
-                         "bytes_per_problem": SEED_BYTES[dom]}}
+                         "bytes_per_problem": SEED_BYTES[dom]},
+            "cpu_baseline": None if args.no_cpu_baseline else seed_cpu_baseline()}
     print(json.dumps(line), flush=True)
 
 
@@ -625,7 +718,8 @@ def swept_bench(args):
                          "culled_tests_per_cfg": work["needed_tests_per_cfg"],
                          "issued_lane_tests_per_cfg": work["issued_lane_tests_per_cfg"],
                          "dense_equivalent_TFLOPs": dense_cfg * B / (sw_us * 1e-6) / 1e12, "traffic": None},
-            "cpu_baseline": None}
+            "cpu_baseline": None if args.no_cpu_baseline else swept_cpu_baseline(
+                {kk: tuple(v) for kk, v in out["paper_like"]["formats"].items()}, k)}
     print(json.dumps(line), flush=True)
 
 
@@ -883,7 +977,9 @@ def ik_bench(args):
             "config": {"workload": f"{N_WORLDS} problems x {IK_SEEDS} seeds = {B:,} configurations per step; 7-joint "
                                    f"arm, 60 spheres, 300 self pairs, 64 cuboids per world; pose cost + collision",
                        "precision": "paper_like", "formats": pl["formats"]},
-            "fp32_value": out["f32"]["value"], "variants": out, "roofline": roofline, "cpu_baseline": None}
+            "fp32_value": out["f32"]["value"], "variants": out, "roofline": roofline,
+            "cpu_baseline": None if args.no_cpu_baseline else ik_cpu_baseline(
+                {kk: tuple(v) for kk, v in pl["formats"].items()})}
     print(json.dumps(line), flush=True)
 
 
