@@ -528,6 +528,13 @@ def seeding_study(args):
         inits = {"network": net.seeds(st, gl, occ),
                  "linear": d(make_seed_inits(ev["start"], ev["goal"], S_EVAL, T, "linear", split=1)),
                  "random": d(make_seed_inits(ev["start"], ev["goal"], S_EVAL, T, "random", split=1))}
+        # the network's first four slots with four of the linear fallback seeds (those with a random
+        # bend; the straight line is what the network's slots sit close to)
+        inits["network+linear"] = torch.cat([inits["network"][:, :S_EVAL // 2], inits["linear"][:, 1:1 + S_EVAL // 2]],
+                                            dim=1)
+        # ... or with four random-via-point seeds, the family that reaches the hard problems soonest
+        inits["network+random"] = torch.cat([inits["network"][:, :S_EVAL // 2], inits["random"][:, :S_EVAL // 2]],
+                                            dim=1)
         firsts, final_cost = {}, {}
         for kind, x0 in inits.items():
             sol = SP.solve(ctx, x0.contiguous(), iters=args.seed_eval_iters, check_every=1)
@@ -561,7 +568,7 @@ def seeding_study(args):
 
     # pooled over environments: collision-free rate by iteration, and the iterations each kind of
     # seed needs to reach the rate that all three reach
-    kinds = ("network", "linear", "random")
+    kinds = ("network", "linear", "random", "network+linear", "network+random")
     pooled = {k: np.concatenate([e["firsts"][k] for e in envs]) for k in kinds}
     marks = sorted({0, 1, 2, 3, 5, 10, 20, args.seed_eval_iters})
     curves = {k: {str(i): float(np.mean((ff >= 0) & (ff <= i))) for i in marks} for k, ff in pooled.items()}
@@ -573,7 +580,7 @@ def seeding_study(args):
     for e in envs:
         e.pop("firsts")
     line = {"metric": "learned seeding: collision-free rate by optimiser iteration (network vs linear vs random "
-                      "seeds, 8 each)",
+                      "seeds, 8 each; 4 network + 4 linear; 4 network + 4 random)",
             "data": "synthetic", "n_gpus": 1, "dtype": "bf16 GEMM operands, f32 accumulate",
             "config": {"workload": f"7-joint arm, 60 spheres, no self pairs; {args.seed_envs} environments of {K} "
                                    f"cuboids (centres jittered 5 cm per problem); T = {T}; "
@@ -1004,7 +1011,7 @@ def main():
     ap.add_argument("--seed-envs", type=int, default=2)
     ap.add_argument("--seed-problems", type=int, default=32768)
     ap.add_argument("--seed-solve-iters", type=int, default=60)
-    ap.add_argument("--seed-train-steps", type=int, default=2000)
+    ap.add_argument("--seed-train-steps", type=int, default=8000)
     ap.add_argument("--seed-eval", type=int, default=1024)
     ap.add_argument("--seed-eval-iters", type=int, default=30)
     ap.add_argument("--only", choices=list(PRECISIONS), default=None,
