@@ -172,13 +172,17 @@ __device__ __forceinline__ void roundtrip(const TV& t, float (&v)[N]) {
 constexpr int TILE_POSE_WORDS = N_LINKS * LINK_VALUES * 64;
 
 // T_0 = I, T_j = T_{j-1} F_j Rz(q_j) (j = 1..7), T_8 = T_7 F_8, each link written to the tile as
-// it is formed
+// it is formed.  WITH_BASE: the tile holds links 0..8 (link l at slot l); otherwise links 1..8 only
+// (link l at slot l - 1), for kernels that never read the identity base.
+template <bool WITH_BASE = true>
 __device__ __forceinline__ void chain_to_tile(const float* __restrict__ fixed, const float (&qv)[N_JOINTS],
                                               float* tile, int lane) {
   float R[9] = {1.f, 0.f, 0.f, 0.f, 1.f, 0.f, 0.f, 0.f, 1.f};
   float t[3] = {0.f, 0.f, 0.f};
+  if constexpr (WITH_BASE) {
 #pragma unroll
-  for (int k = 0; k < LINK_VALUES; ++k) tile[k * 64 + lane] = (k == 0 || k == 5 || k == 10) ? 1.f : 0.f;
+    for (int k = 0; k < LINK_VALUES; ++k) tile[k * 64 + lane] = (k == 0 || k == 5 || k == 10) ? 1.f : 0.f;
+  }
 #pragma unroll
   for (int l = 0; l < N_FIXED; ++l) {
     const cptr<float> F = as_const(fixed) + l * LINK_VALUES;
@@ -204,7 +208,7 @@ __device__ __forceinline__ void chain_to_tile(const float* __restrict__ fixed, c
     for (int i = 0; i < 9; ++i) R[i] = nR[i];
 #pragma unroll
     for (int i = 0; i < 3; ++i) t[i] = nt[i];
-    float* out = tile + (l + 1) * LINK_VALUES * 64 + lane;
+    float* out = tile + (WITH_BASE ? l + 1 : l) * LINK_VALUES * 64 + lane;
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
       out[(i * 4 + 0) * 64] = R[i * 3 + 0];
@@ -1138,26 +1142,40 @@ __device__ __forceinline__ void link_wrench(const RobotArgs& R, const uint32_t* 
   }
 }
 
-// One block of four wavefronts per 64-configuration tile.  Phase 1 puts the link poses in LDS
-// (decoded from L by wavefronts 0-1, or recomputed by wavefront 0); phase 2 gives each wavefront
-// links w+1 and w+5 and leaves their force and moment in LDS; phase 3 (wavefront 0) sums them from
-// the tip to the base into the joint gradients.
+// One block of four wavefronts per 64-configuration tile.  Phase 1 puts the poses of links 1..8 in
+// LDS (decoded from L by wavefronts 0-1, or recomputed by wavefront 0) while wavefronts 2-3 stage
+// the joint rows the last phase reads (the tile's and one on each side); phase 2 gives each
+// wavefront links w+1 and w+5 and leaves their force and moment in LDS; phase 3 (wavefront 0) sums
+// them from the tip to the base into the joint gradients.  Every load of the block is thus issued
+// before the first barrier except the sphere gradients'.
+constexpr int ADJ_TILE_WORDS = N_FIXED * LINK_VALUES * 64;  // link l (1..8) at slot l - 1
+constexpr int ADJ_Q_ROWS = 64 + 2;                          // joint rows b0 - 1 .. b0 + 64
+
 template <int FG, bool HAS_X>
 __global__ __launch_bounds__(256) void k_adjoint(const float* __restrict__ q, RobotArgs R, TV L, TV G, TV X, TV J,
                                                  const double* __restrict__ up, float* __restrict__ grad_q,
                                                  ShapeArgs sh, CostArgs cp, int recompute,
                                                  const float* __restrict__ goal) {
-  __shared__ float tile[TILE_POSE_WORDS];
+  __shared__ float tile[ADJ_TILE_WORDS];
   __shared__ float wrench[N_FIXED * 6 * 64];  // link l: force (3), moment (3) at ((l-1)*6 + k)*64 + lane
+  __shared__ float qs[ADJ_Q_ROWS * N_JOINTS];  // row b0 - 1 + r at r * 7
   const int wave = uniform(threadIdx.x >> 6), lane = threadIdx.x & 63;
-  const int64_t b = (int64_t)blockIdx.x * 64 + lane;
+  const int64_t b0 = (int64_t)blockIdx.x * 64;
+  const int64_t b = b0 + lane;
   const bool live = b < sh.B;
+  if (wave >= 2) {
+    const int64_t base = (b0 - 1) * N_JOINTS, end = sh.B * N_JOINTS;
+    for (int i = (int)threadIdx.x - 128; i < ADJ_Q_ROWS * N_JOINTS; i += 128) {
+      const int64_t o = base + i;
+      qs[i] = (o >= 0 && o < end) ? q[o] : 0.f;
+    }
+  }
   if (recompute) {
     if (wave == 0) {
       float qv[N_JOINTS];
 #pragma unroll
       for (int j = 0; j < N_JOINTS; ++j) qv[j] = live ? q[b * N_JOINTS + j] : 0.f;
-      chain_to_tile(R.fixed, qv, tile, lane);
+      chain_to_tile<false>(R.fixed, qv, tile, lane);
     }
   } else if (wave < L_GROUPS) {
     float v[L_GROUP];
@@ -1168,7 +1186,7 @@ __global__ __launch_bounds__(256) void k_adjoint(const float* __restrict__ q, Ro
       for (int i = 0; i < L_GROUP; ++i) v[i] = 0.f;
     }
 #pragma unroll
-    for (int i = 0; i < L_GROUP; ++i) tile[(LINK_VALUES + wave * L_GROUP + i) * 64 + lane] = v[i];
+    for (int i = 0; i < L_GROUP; ++i) tile[(wave * L_GROUP + i) * 64 + lane] = v[i];
   }
   __syncthreads();
 
@@ -1176,7 +1194,7 @@ __global__ __launch_bounds__(256) void k_adjoint(const float* __restrict__ q, Ro
   const uint32_t* xbase = HAS_X ? lane_base(X, b) : nullptr;
   for (int l = wave + 1; l <= N_FIXED; l += 4) {
     float T[LINK_VALUES];
-    pose_from_tile(tile, l, lane, T);
+    pose_from_tile(tile, l - 1, lane, T);
     float f[3] = {0.f, 0.f, 0.f}, m[3] = {0.f, 0.f, 0.f};
     if (live) link_wrench<FG, HAS_X>(R, gbase, G.scale, X, xbase, l, T, f, m);
     float* w = wrench + (l - 1) * 6 * 64 + lane;
@@ -1194,7 +1212,7 @@ __global__ __launch_bounds__(256) void k_adjoint(const float* __restrict__ q, Ro
   float F[3] = {0.f, 0.f, 0.f}, M[3] = {0.f, 0.f, 0.f};
   if (goal) {
     // pose cost: force 2 w_gp (p - p_g) at the end-effector origin p and couple -2 w_gr m(R R_g^T)
-    const float* T8 = tile + N_FIXED * LINK_VALUES * 64 + lane;
+    const float* T8 = tile + (N_FIXED - 1) * LINK_VALUES * 64 + lane;
     const float* g = goal + (b / sh.cfg_per_world) * LINK_VALUES;
     float Rm[9], p[3];
 #pragma unroll
@@ -1228,7 +1246,7 @@ __global__ __launch_bounds__(256) void k_adjoint(const float* __restrict__ q, Ro
       M[i] += w[(3 + i) * 64];
     }
     if (l <= N_JOINTS) {
-      const float* T = tile + l * LINK_VALUES * 64 + lane;
+      const float* T = tile + (l - 1) * LINK_VALUES * 64 + lane;
       const float zx = T[2 * 64], zy = T[6 * 64], zz = T[10 * 64];
       const float ox = T[3 * 64], oy = T[7 * 64], oz = T[11 * 64];
       const float tx = M[0] - (oy * F[2] - oz * F[1]);
@@ -1237,9 +1255,10 @@ __global__ __launch_bounds__(256) void k_adjoint(const float* __restrict__ q, Ro
       Jv[l - 1] = fmaf(zx, tx, fmaf(zy, ty, zz * tz));
     }
   }
+  const float* qr = qs + (lane + 1) * N_JOINTS;  // row b; rows b - 1 and b + 1 beside it
   float qv[N_JOINTS];
 #pragma unroll
-  for (int j = 0; j < N_JOINTS; ++j) qv[j] = q[b * N_JOINTS + j];
+  for (int j = 0; j < N_JOINTS; ++j) qv[j] = qr[j];
   const int T = sh.T;
   const int64_t tc = b / T;
   const int t = (int)(b - tc * T);
@@ -1249,8 +1268,8 @@ __global__ __launch_bounds__(256) void k_adjoint(const float* __restrict__ q, Ro
     const float over = fmaxf(qv[j] - R.q_hi[j], 0.f), under = fmaxf(R.q_lo[j] - qv[j], 0.f);
     float gj = fmaf(cp.w_b, 2.f * over - 2.f * under, Jv[j]);
     float sm = 0.f;
-    if (t >= 1) sm += 2.f * (qv[j] - q[(b - 1) * N_JOINTS + j]);
-    if (t + 1 < T) sm -= 2.f * (q[(b + 1) * N_JOINTS + j] - qv[j]);
+    if (t >= 1) sm += 2.f * (qv[j] - qr[j - N_JOINTS]);
+    if (t + 1 < T) sm -= 2.f * (qr[j + N_JOINTS] - qv[j]);
     gj = fmaf(cp.w_v, sm, gj);
     Jv[j] = gj * scale;
   }
