@@ -366,7 +366,15 @@ __device__ __forceinline__ void cuboid_sd_grad(const float* __restrict__ bx, flo
   }
   const float n2 = fmaf(m[0], m[0], fmaf(m[1], m[1], m[2] * m[2]));
   float n[3];
-  if (n2 > 0.f) {
+  if (n2 > 1e-24f) {
+    // hardware reciprocal square root (about 1 ulp): distance and unit direction in one step, in
+    // place of a correctly rounded square root and division (about 15 instructions more)
+    const float inv = __builtin_amdgcn_rsqf(n2);
+    sd = n2 * inv;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) n[i] = (u[i] >= 0.f ? m[i] : -m[i]) * inv;
+  } else if (n2 > 0.f) {
+    // within 1e-12 of the surface (n2 may be subnormal, which the hardware rsq flushes)
     sd = sqrtf(n2);
     const float inv = 1.0f / sd;
 #pragma unroll
