@@ -35,7 +35,7 @@
 extern "C" {
 #endif
 
-#define VAPR_ABI_VERSION 3
+#define VAPR_ABI_VERSION 2
 
 typedef enum {
   VAPR_OK = 0,
@@ -207,9 +207,8 @@ int vapr_workspace_size(const vapr_ctx* ctx, int n_worlds, int traj_per_world, i
 /* Forward pass: kinematics -> sphere costs -> aggregation (Sec. III-B steps (2)-(4)).
  *   q         dev [B][7]               configurations in the layout above
  *   ws        dev, ws_bytes >= vapr_workspace_size(...)
- *   cost_traj dev [n_worlds*traj_per_world*n_ls] FP64, trajectory-candidate costs, or NULL to
- *             leave the aggregation (step (4)) to vapr_optimizer_step_fused
- *   cost_cfg  dev [B] FP32 per-configuration cost, or NULL (must be NULL when cost_traj is)
+ *   cost_traj dev [n_worlds*traj_per_world*n_ls] FP64, trajectory-candidate costs
+ *   cost_cfg  dev [B] FP32 per-configuration cost, or NULL
  * 1 <= T <= 4096, 1 <= n_ls <= 4, n_worlds <= the uploaded world count.  Requires robot and
  * worlds (VAPR_E_STATE otherwise).  Records ws as holding a forward pass of this shape. */
 int vapr_cost_fwd(vapr_ctx* ctx, int n_worlds, int traj_per_world, int T, int n_ls, const float* q,
@@ -265,15 +264,6 @@ int vapr_optimizer_init(vapr_ctx* ctx, const vapr_lbfgs_state* st, const void* w
  * read from. */
 int vapr_optimizer_step(vapr_ctx* ctx, const vapr_lbfgs_state* st, const void* ws, size_t ws_bytes,
                         const double* cost_cand, float* q_cand);
-
-/* vapr_optimizer_step with the aggregation (Sec. III-B step (4)) done inside it: the candidates'
- * costs are reduced from ws exactly as vapr_cost_fwd reduces them (the same values, bit for bit),
- * written to cost_cand dev [n_traj*n_ls] FP64, and used for the selection; the forward pass may then
- * skip its own aggregation (cost_traj = NULL).  q_cand must hold the candidates that forward pass
- * evaluated (their smoothness term is read from it) and receives the next candidates.  Uses the
- * current cost parameters. */
-int vapr_optimizer_step_fused(vapr_ctx* ctx, const vapr_lbfgs_state* st, const void* ws, size_t ws_bytes,
-                              double* cost_cand, float* q_cand);
 
 /* Element-wise codec on the context-free current device (Sec. IV-C's conversion of a tensor on
  * write and read).  in/out dev; out holds vapr_packed_bytes(fmt, n) bytes in the packed layout.

@@ -193,22 +193,18 @@ class Context:
 
     def cost_fwd(self, q: torch.Tensor, shape: Shape, ws: Optional[torch.Tensor] = None,
                  cost_traj: Optional[torch.Tensor] = None, cost_cfg: Optional[torch.Tensor] = None,
-                 first: int = 1, reduce: bool = True):
+                 first: int = 1):
         """Trajectory-candidate costs [n_tc] float64 (and the workspace that holds the stored
-        tensors).  first > 1 resumes from a stored stage (2: sphere costs, 3: aggregation).  With
-        reduce=False the aggregation is left to the fused optimiser step and the costs are None."""
+        tensors).  first > 1 resumes from a stored stage (2: sphere costs, 3: aggregation)."""
         if ws is None:
             ws = self.new_workspace(shape)
-        if reduce and cost_traj is None:
+        if cost_traj is None:
             cost_traj = torch.empty(shape.n_tc, dtype=torch.float64, device=q.device)
-        if not reduce and (cost_traj is not None or cost_cfg is not None):
-            raise ValueError("reduce=False writes no costs")
         if q.shape != (shape.B, 7):
             raise ValueError(f"q must be [{shape.B}, 7]")
         cfg_ptr = _dev(cost_cfg, torch.float32, "cost_cfg") if cost_cfg is not None else None
-        ct_ptr = _dev(cost_traj, torch.float64, "cost_traj") if reduce else None
         self._call("vapr_cost_fwd_from", first, *shape.args(), _dev(q, torch.float32, "q"),
-                   _dev(ws, torch.uint8, "ws"), ws.numel(), ct_ptr, cfg_ptr)
+                   _dev(ws, torch.uint8, "ws"), ws.numel(), _dev(cost_traj, torch.float64, "cost_traj"), cfg_ptr)
         return cost_traj, ws
 
     def cost_bwd(self, q: torch.Tensor, ws: torch.Tensor, grad_cost_traj: Optional[torch.Tensor] = None,

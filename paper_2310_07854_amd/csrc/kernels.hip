@@ -1352,11 +1352,9 @@ __constant__ float c_alpha[MAX_LS] = {1.0f, 0.5f, 0.25f, 0.125f};
 
 // GL lanes per trajectory: 64 (one trajectory per wavefront, n <= 64 OPT_NE variables), or 8 for
 // one-configuration trajectories (n = 7: eight trajectories per wavefront, one variable per lane).
-// q_cand holds the evaluated candidates on entry (read for the smoothness term when ra.on) and
-// receives the next ones; a trajectory's rows are read and written by its own lanes only.
 template <int OPT_NE, int GL>
 __global__ __launch_bounds__(256) void k_optimizer(OptArgs o, TV J, const double* __restrict__ cost_in,
-                                                   float* q_cand, int mode, ReduceArgs ra) {
+                                                   float* __restrict__ q_cand, int mode) {
   const int lane = GL == 64 ? (threadIdx.x & 63) : (threadIdx.x & (GL - 1));
   const int tr = GL == 64 ? blockIdx.x * 4 + uniform(threadIdx.x >> 6) : (blockIdx.x * 256 + threadIdx.x) / GL;
   if (tr >= o.n_traj) return;  // a whole group
@@ -1378,52 +1376,6 @@ __global__ __launch_bounds__(256) void k_optimizer(OptArgs o, TV J, const double
   };
   int len = o.hist_len[tr], head = o.hist_head[tr], flags = 0, acc = 0;
 
-  // candidate costs: from cost_in, or reduced here exactly as the aggregation kernel does (lane t
-  // takes timestep t, FP64, the same wavefront sum; one configuration per trajectory when GL = 8).
-  // Held in four scalars (an indexed array would live in scratch memory).
-  double cc0 = 0.0, cc1 = 0.0, cc2 = 0.0, cc3 = 0.0;
-  static_assert(MAX_LS == 4, "one scalar per step scale");
-  if (ra.on) {
-    // local copies: a reference into the by-value argument struct would put it in scratch memory
-    const TV rD = ra.D;
-    const CostArgs rcp = ra.cp;
-#pragma unroll
-    for (int i = 0; i < MAX_LS; ++i) {
-      if (i < n_ls) {
-        const int64_t tc = (int64_t)tr * n_ls + i;
-        double c;
-        if constexpr (GL == 64) {
-          double a = 0.0;
-          if (lane < T) {
-            const int64_t b = tc * T + lane;
-            const double cfg = cfg_cost(rD, ra.selfc, ra.boundc, ra.sweptc, ra.posec, b, rcp, ra.n_s);
-            double sm = 0.0;
-            if (lane + 1 < T) {
-#pragma unroll
-              for (int j = 0; j < N_JOINTS; ++j) {
-                const double dq = (double)q_cand[(b + 1) * N_JOINTS + j] - (double)q_cand[b * N_JOINTS + j];
-                sm = fma(dq, dq, sm);
-              }
-            }
-            a = cfg + (double)rcp.w_v * sm;
-          }
-          c = group_sum<64>(a);
-        } else {
-          c = cfg_cost(rD, ra.selfc, ra.boundc, ra.sweptc, ra.posec, tc, rcp, ra.n_s);  // T = 1
-        }
-        if (i == 0) cc0 = c;
-        if (i == 1) cc1 = c;
-        if (i == 2) cc2 = c;
-        if (i == 3) cc3 = c;
-        if (lane == 0) ra.cost_out[tc] = c;
-      }
-    }
-  }
-  auto cost_of = [&](int i) __attribute__((always_inline)) -> double {
-    if (!ra.on) return cost_in[(int64_t)tr * n_ls + i];
-    return i == 0 ? cc0 : (i == 1 ? cc1 : (i == 2 ? cc2 : cc3));
-  };
-
   if (mode == 0) {
 #pragma unroll
     for (int k = 0; k < OPT_NE; ++k) {
@@ -1433,7 +1385,7 @@ __global__ __launch_bounds__(256) void k_optimizer(OptArgs o, TV J, const double
     steepest<OPT_NE, GL>(g, o.max_step, d);
     len = 0;
     head = 0;
-    if (lane == 0) o.cost[tr] = ra.on ? cc0 : cost_in[tr];  // the start: one cost per trajectory
+    if (lane == 0) o.cost[tr] = cost_in[tr];
   } else {
     double gd = 0.0;
 #pragma unroll
@@ -1442,7 +1394,7 @@ __global__ __launch_bounds__(256) void k_optimizer(OptArgs o, TV J, const double
     const double c0 = o.cost[tr];
     int sel = -1;
     for (int i = 0; i < n_ls; ++i) {
-      if (cost_of(i) <= c0 + 1e-4 * (double)c_alpha[i] * gd) {
+      if (cost_in[(int64_t)tr * n_ls + i] <= c0 + 1e-4 * (double)c_alpha[i] * gd) {
         sel = i;
         break;
       }
@@ -1450,8 +1402,8 @@ __global__ __launch_bounds__(256) void k_optimizer(OptArgs o, TV J, const double
     if (sel < 0) {
       int bi = 0;
       for (int i = 1; i < n_ls; ++i)
-        if (cost_of(i) < cost_of(bi)) bi = i;
-      if (cost_of(bi) < c0) sel = bi;
+        if (cost_in[(int64_t)tr * n_ls + i] < cost_in[(int64_t)tr * n_ls + bi]) bi = i;
+      if (cost_in[(int64_t)tr * n_ls + bi] < c0) sel = bi;
     }
     acc = sel;
     if (sel < 0) {
@@ -1482,7 +1434,7 @@ __global__ __launch_bounds__(256) void k_optimizer(OptArgs o, TV J, const double
       sy = group_sum<GL>(sy);
       ss = group_sum<GL>(ss);
       yy = group_sum<GL>(yy);
-      if (lane == 0) o.cost[tr] = cost_of(sel);
+      if (lane == 0) o.cost[tr] = cost_in[(int64_t)tr * n_ls + sel];
       if (sy > 1e-10 * sqrt(ss) * sqrt(yy)) {
         const int64_t hb = ((int64_t)tr * m + head) * n;
 #pragma unroll
@@ -1858,16 +1810,16 @@ hipError_t launch_adjoint(hipStream_t s, const float* q, const RobotArgs& R, con
 }
 
 hipError_t launch_optimizer(hipStream_t s, const OptArgs& o, const TV& J, const double* cost_in, float* q_cand,
-                            int mode, const ReduceArgs& ra) {
+                            int mode) {
   if (o.T == 1) {
     hipLaunchKernelGGL((k_optimizer<1, 8>), dim3(blocks_for(o.n_traj, 32)), dim3(256), 0, s, o, J, cost_in, q_cand,
-                       mode, ra);
+                       mode);
     return hipGetLastError();
   }
   const dim3 grid(blocks_for(o.n_traj, 4)), block(256);
   switch ((o.T * N_JOINTS + 63) / 64) {
 #define VAPR_OPT_CASE(NE) \
-  case NE: hipLaunchKernelGGL((k_optimizer<NE, 64>), grid, block, 0, s, o, J, cost_in, q_cand, mode, ra); break;
+  case NE: hipLaunchKernelGGL((k_optimizer<NE, 64>), grid, block, 0, s, o, J, cost_in, q_cand, mode); break;
     VAPR_OPT_CASE(1) VAPR_OPT_CASE(2) VAPR_OPT_CASE(3) VAPR_OPT_CASE(4) VAPR_OPT_CASE(5) VAPR_OPT_CASE(6)
     VAPR_OPT_CASE(7)
 #undef VAPR_OPT_CASE

@@ -75,20 +75,6 @@ struct OptArgs {
   int* flags;
 };
 
-// Step 4 done inside the optimiser kernel: the candidates' trajectory costs reduced from the
-// workspace of their forward pass (the aggregation kernel's arithmetic and order), also written out.
-struct ReduceArgs {
-  int on;
-  TV D;
-  const float* selfc;
-  const float* boundc;
-  const float* sweptc;  // or null
-  const float* posec;   // or null
-  double* cost_out;     // [n_traj * n_ls]
-  CostArgs cp;
-  int n_s;
-};
-
 enum KernelId {
   K_FK = 0, K_SPHERE = 1, K_REDUCE = 2, K_ADJOINT = 3, K_OPT = 4, K_CODEC = 5, K_REPACK = 6, K_SWEPT = 7,
   N_KERNEL_IDS = 8
@@ -118,7 +104,7 @@ hipError_t launch_adjoint(hipStream_t s, const float* q, const RobotArgs& R, con
                           const TV& J, const double* up, float* grad_q, const ShapeArgs& sh, const CostArgs& cp,
                           int recompute, const float* goal);
 hipError_t launch_optimizer(hipStream_t s, const OptArgs& o, const TV& J, const double* cost_in, float* q_cand,
-                            int mode, const ReduceArgs& ra);
+                            int mode);
 hipError_t launch_quantize(hipStream_t s, int fmt, float inv, const float* in, uint8_t* out, int64_t n);
 hipError_t launch_round_exmy(hipStream_t s, int E, int M, float inv, float scale, const float* in, float* out,
                              int64_t n);

@@ -401,8 +401,7 @@ int run_fwd(vapr_ctx* ctx, int first, int n_worlds, int tpw, int T, int n_ls, co
   if (first < 1 || first > 3) return fail(ctx, VAPR_E_INVALID, "first stage must be 1, 2 or 3");
   if (!ctx->has_worlds) return fail(ctx, VAPR_E_STATE, "no worlds uploaded");
   if (n_worlds > ctx->n_worlds) return fail(ctx, VAPR_E_INVALID, "n_worlds exceeds the uploaded worlds");
-  if (!q || !ws) return fail(ctx, VAPR_E_INVALID, "null pointer");
-  if (!cost_traj && cost_cfg) return fail(ctx, VAPR_E_INVALID, "configuration costs need trajectory costs");
+  if (!q || !ws || !cost_traj) return fail(ctx, VAPR_E_INVALID, "null pointer");
   const Layout L = make_layout(B, ctx->n_s, ctx->prec);
   if (ws_bytes < L.bytes) return fail(ctx, VAPR_E_INVALID, "workspace too small");
   if (first >= 2) {
@@ -455,12 +454,10 @@ int run_fwd(vapr_ctx* ctx, int first, int n_worlds, int tpw, int T, int n_ls, co
   }
   const CostArgs cp = ctx->params;
   const int n_s = ctx->n_s;
-  if (cost_traj) {  // otherwise the optimiser step reduces the costs itself
-    st = timed(ctx, K_REDUCE,
-               [&] { return launch_reduce(s, tD, selfc, boundc, sweptc, posec, q, cost_traj, cost_cfg, sh, cp, n_s); },
-               "k_reduce launch");
-    if (st) return st;
-  }
+  st = timed(ctx, K_REDUCE,
+             [&] { return launch_reduce(s, tD, selfc, boundc, sweptc, posec, q, cost_traj, cost_cfg, sh, cp, n_s); },
+             "k_reduce launch");
+  if (st) return st;
   ctx->ws[ws] = WsRecord{n_worlds, tpw, T, n_ls, B, ctx->prec, ctx->robot_gen};
   return VAPR_OK;
 }
@@ -519,35 +516,17 @@ OptArgs opt_args(const vapr_lbfgs_state* st) {
   return o;
 }
 
-// fused: the candidates' costs are reduced by the optimiser kernel from the workspace (and written to
-// cost_out) instead of being read from cost
 int run_opt(vapr_ctx* ctx, const vapr_lbfgs_state* st, const void* ws, size_t ws_bytes, const double* cost,
-            float* q_cand, int mode, double* cost_out = nullptr) {
+            float* q_cand, int mode) {
   WsRecord rec;
   int s = check_opt(ctx, st, ws, mode == 0, &rec);
   if (s) return s;
-  const bool fused = cost_out != nullptr;
-  if ((!fused && !cost) || !q_cand) return fail(ctx, VAPR_E_INVALID, "null pointer");
+  if (!cost || !q_cand) return fail(ctx, VAPR_E_INVALID, "null pointer");
   const Layout L = make_layout(rec.B, ctx->n_s, ctx->prec);
   if (ws_bytes < L.bytes) return fail(ctx, VAPR_E_INVALID, "workspace too small");
-  void* w = const_cast<void*>(ws);
-  const TV tJ = tensor_view(w, L, ctx->prec, T_J);
+  const TV tJ = tensor_view(const_cast<void*>(ws), L, ctx->prec, T_J);
   const OptArgs o = opt_args(st);
-  ReduceArgs ra{};
-  if (fused) {
-    ra.on = 1;
-    ra.D = tensor_view(w, L, ctx->prec, T_D);
-    ra.selfc = reinterpret_cast<const float*>(static_cast<const char*>(ws) + L.off[OFF_SELF]);
-    ra.boundc = reinterpret_cast<const float*>(static_cast<const char*>(ws) + L.off[OFF_BOUND]);
-    ra.sweptc = ctx->prec.sweep ? reinterpret_cast<const float*>(static_cast<const char*>(ws) + L.off[OFF_SWEPT])
-                                : nullptr;
-    ra.posec = ctx->prec.pose ? reinterpret_cast<const float*>(static_cast<const char*>(ws) + L.off[OFF_POSE])
-                              : nullptr;
-    ra.cost_out = cost_out;
-    ra.cp = ctx->params;
-    ra.n_s = ctx->n_s;
-  }
-  return timed(ctx, K_OPT, [&] { return launch_optimizer(ctx->stream, o, tJ, cost, q_cand, mode, ra); },
+  return timed(ctx, K_OPT, [&] { return launch_optimizer(ctx->stream, o, tJ, cost, q_cand, mode); },
                "k_optimizer launch");
 }
 
@@ -891,12 +870,6 @@ int vapr_optimizer_init(vapr_ctx* ctx, const vapr_lbfgs_state* st, const void* w
 int vapr_optimizer_step(vapr_ctx* ctx, const vapr_lbfgs_state* st, const void* ws, size_t ws_bytes,
                         const double* cost_cand, float* q_cand) {
   return run_opt(ctx, st, ws, ws_bytes, cost_cand, q_cand, 1);
-}
-
-int vapr_optimizer_step_fused(vapr_ctx* ctx, const vapr_lbfgs_state* st, const void* ws, size_t ws_bytes,
-                              double* cost_cand, float* q_cand) {
-  if (!cost_cand) return fail(ctx, VAPR_E_INVALID, "null pointer");
-  return run_opt(ctx, st, ws, ws_bytes, nullptr, q_cand, 1, cost_cand);
 }
 
 size_t vapr_packed_bytes(int fmt, int64_t n) {

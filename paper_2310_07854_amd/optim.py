@@ -13,13 +13,11 @@ from .context import Context, Shape, _dev
 
 class TrajectoryOptimizer:
     def __init__(self, vctx: Context, n_worlds: int, traj_per_world: int, T: int, n_ls: int = 4, m: int = 8,
-                 max_step: float = 0.2, pin_ends: bool = True, fused: bool = True):
+                 max_step: float = 0.2, pin_ends: bool = True):
         """pin_ends: the first and last timestep stay fixed (trajectory optimisation); False lets
         every row move (inverse kinematics: T = 1, one seed per trajectory, goals set on the
-        context).  fused: each iteration aggregates the candidates' costs inside the optimiser
-        kernel (vapr_optimizer_step_fused) rather than in the forward pass."""
+        context)."""
         self.vctx = vctx
-        self.fused = fused
         self.shape1 = Shape(n_worlds, traj_per_world, T, 1)
         self.shape = Shape(n_worlds, traj_per_world, T, n_ls)
         self.m = m
@@ -72,16 +70,7 @@ class TrajectoryOptimizer:
         self._graph.replay()
 
     def step(self) -> None:
-        """One iteration: evaluate all candidates (fwd + bwd), select, update, next candidates.  With
-        `fused` (the default) the candidates' costs are aggregated inside the optimiser kernel
-        instead of by a kernel of their own; the results are the same bit for bit."""
-        if self.fused:
-            self.vctx.cost_fwd(self.q_cand, self.shape, ws=self.ws, reduce=False)
-            self.vctx.cost_bwd(self.q_cand, self.ws, want_grad=False)
-            self.vctx._call("vapr_optimizer_step_fused", ctypes.byref(self._st), _dev(self.ws, torch.uint8, "ws"),
-                            self.ws.numel(), _dev(self.cost_cand, torch.float64, "cost"),
-                            _dev(self.q_cand, torch.float32, "q"))
-            return
+        """One iteration: evaluate all candidates (fwd + bwd), select, update, next candidates."""
         self.vctx.cost_fwd(self.q_cand, self.shape, ws=self.ws, cost_traj=self.cost_cand)
         self.vctx.cost_bwd(self.q_cand, self.ws, want_grad=False)
         self.vctx._call("vapr_optimizer_step", ctypes.byref(self._st), _dev(self.ws, torch.uint8, "ws"),

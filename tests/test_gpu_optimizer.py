@@ -155,58 +155,3 @@ def test_graph_replays_match_eager_steps():
         assert torch.equal(eager.cost, graph.cost), it
         assert torch.equal(eager.d, graph.d), it
         assert torch.equal(eager.hist_len, graph.hist_len), it
-
-
-def _fused_vs_separate(ctx, n_worlds, tpw, T, n_ls, x0, steps, pin_ends=True):
-    from paper_2310_07854_amd import TrajectoryOptimizer
-
-    fused = TrajectoryOptimizer(ctx, n_worlds, tpw, T, n_ls=n_ls, m=8, pin_ends=pin_ends, fused=True)
-    sep = TrajectoryOptimizer(ctx, n_worlds, tpw, T, n_ls=n_ls, m=8, pin_ends=pin_ends, fused=False)
-    fused.init(x0)
-    sep.init(x0)
-    for it in range(steps):
-        fused.step()
-        sep.step()
-        torch.cuda.synchronize()
-        for name in ("cost_cand", "cost", "x", "g", "d", "q_cand", "s_hist", "y_hist", "rho", "hist_len",
-                     "accepted", "flags"):
-            a, b = getattr(fused, name), getattr(sep, name)
-            assert torch.equal(a, b), (it, name)
-    return fused
-
-
-@pytest.mark.parametrize("case", ["batched_line_search", "swept_paper_like", "inverse_kinematics"])
-def test_fused_aggregation_matches_separate_kernel(case):
-    """The optimiser step that aggregates the candidates' costs itself gives the same candidate
-    costs, accepted points, histories and next candidates, bit for bit, as the forward pass's own
-    aggregation followed by the plain step: with a 4-scale line search, with the swept term and
-    reduced formats, and on the one-configuration inverse-kinematics layout (pose cost, free rows)."""
-    need_gpu()
-    from synthetic import make_configs, make_robot, make_worlds
-
-    if case == "batched_line_search":
-        wl = make_workload("batched")
-        ctx = make_context(wl, {})
-        x0 = dev(wl.q.reshape(wl.n_traj, wl.n_ls, wl.T, 7)[:, 0], torch.float32)
-        opt = _fused_vs_separate(ctx, wl.n_worlds, wl.traj_per_world, wl.T, wl.n_ls, x0, 5)
-        assert bool((opt.accepted >= 0).any())
-    elif case == "swept_paper_like":
-        wl = make_workload("batched")
-        prec = {"link_poses": "f16", "sphere_pos": "f16", "sphere_dist": ("e4m3", -10),
-                "sphere_grad": ("e4m3", -1), "joint_grad": ("e4m3", 2), "swept_grad": ("e4m3", -2)}
-        ctx = make_context(wl, prec, params={"swept_steps": 3, "w_swept": 100.0})
-        x0 = dev(wl.q.reshape(wl.n_traj, wl.n_ls, wl.T, 7)[:, 0], torch.float32)
-        _fused_vs_separate(ctx, wl.n_worlds, wl.traj_per_world, wl.T, 2, x0, 4)
-    else:
-        from paper_2310_07854_amd import Context
-        from oracle.kinematics import forward_kinematics
-
-        robot = make_robot(60, 300, seed=41)
-        worlds = make_worlds(4, 24, seed=41)
-        ctx = Context(0)
-        ctx.set_robot(robot)
-        ctx.set_worlds(worlds.pose, worlds.half_ext)
-        goals = forward_kinematics(robot.fixed_tf, make_configs(4, seed=42))[:, 8, :3, :]
-        ctx.set_goals(goals)
-        x0 = dev(make_configs(4 * 300, seed=43), torch.float32).reshape(4 * 300, 1, 7)
-        _fused_vs_separate(ctx, 4, 300, 1, 1, x0, 5, pin_ends=False)
