@@ -111,8 +111,8 @@ def culled_work(ctx, opt, prec):
     """Sphere-cuboid tests of one sphere-cost launch of the timed loop (its last one), from the
     sphere positions that launch read and the culling grid it used: `needed` counts, per
     configuration and sphere, the cuboids marked in the sphere's voxel (the tests the exact culling
-    leaves); `issued` counts lane slots the kernel spends (each lane tests the union over 4 spheres
-    of its candidates, a wavefront as often as its busiest lane)."""
+    leaves); `issued` counts lane slots the kernel spends (each lane tests the union over
+    CULL_SPHERES spheres of its candidates, a wavefront as often as its busiest lane)."""
     import torch
 
     from paper_2310_07854_amd.context import dequantize
@@ -124,9 +124,10 @@ def culled_work(ctx, opt, prec):
     codes = ctx.ws_export("sphere_pos", opt.ws, shape)
     pos = dequantize(codes, fmt, B * N_SPHERES * 3, k).view(B, N_SPHERES, 3).cpu().numpy()
     cfg_per_world = B // N_WORLDS
-    n_q = (N_SPHERES + 15) // 16 * 4
+    n_pad = (N_SPHERES + 15) // 16 * 16
+    n_q = n_pad // CULL_SPHERES
     Bp = (B + 63) // 64 * 64
-    cand = np.zeros((Bp, n_q * 4), dtype=np.uint64)   # candidate masks [cfg, sphere], padded
+    cand = np.zeros((Bp, n_pad), dtype=np.uint64)   # candidate masks [cfg, sphere], padded
     for w in range(N_WORLDS):
         info, mask = ctx.culling_grid(w)
         sl = slice(w * cfg_per_world, (w + 1) * cfg_per_world)
@@ -142,11 +143,12 @@ def culled_work(ctx, opt, prec):
         v = np.floor(np.where(inside[..., None], f, 0)).astype(np.int64)
         cand[sl, :N_SPHERES] = np.where(inside, m64[(v[..., 2] * n + v[..., 1]) * n + v[..., 0]], np.uint64(0))
     needed = int(np.bitwise_count(cand).sum())
-    quad = np.bitwise_or.reduce(cand.reshape(-1, 64, n_q, 4), axis=3)  # [wave, lane, quad]
-    issued = int(np.bitwise_count(quad).max(axis=1).sum()) * 4 * 64
+    lists = np.bitwise_or.reduce(cand.reshape(-1, 64, n_q, CULL_SPHERES), axis=3)  # [wave, lane, list]
+    issued = int(np.bitwise_count(lists).max(axis=1).sum()) * CULL_SPHERES * 64
     return {"needed_tests_per_cfg": needed / B, "issued_lane_tests_per_cfg": issued / B}
 
 
+CULL_SPHERES = 8  # spheres per candidate list of the sphere-cost kernel
 SWEPT_SPHERES, SWEPT_SAMPLES = 4, 2  # the swept kernel's candidate lists: 4 spheres x 2 samples
 
 

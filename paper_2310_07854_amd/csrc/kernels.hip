@@ -539,9 +539,12 @@ __global__ __launch_bounds__(256) void k_sphere_cost(RobotArgs R, WorldArgs W, T
 // result is identical to testing every cuboid.
 
 #ifndef VAPR_CULL_SPHERES
-#define VAPR_CULL_SPHERES 4
+#define VAPR_CULL_SPHERES 8
 #endif
-constexpr int CQ = VAPR_CULL_SPHERES;  // spheres sharing one candidate list (divides 16)
+// spheres sharing one candidate list (divides 16).  Eight: each gathered cuboid (64 bytes per lane)
+// serves eight tests; the longer unions cost fewer instructions than the extra gathers of lists of
+// four (measured on trajectory and inverse-kinematics batches; sixteen is slower on trajectories)
+constexpr int CQ = VAPR_CULL_SPHERES;
 
 __device__ __forceinline__ int voxel_of(const GridArgs& g, float x, float y, float z) {
   const float fx = (x - g.ox) * g.inv_cell, fy = (y - g.oy) * g.inv_cell, fz = (z - g.oz) * g.inv_cell;
@@ -640,8 +643,9 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3))) void k
       const float* wbox = W.box + (int64_t)my_w * K * 16;
       const uint32_t* wmask = Gd.mask + (int64_t)my_w * ((int64_t)Gd.n * Gd.n * Gd.n) * Gd.MW;
       if (Gd.MW <= 2) {
-        // up to 64 cuboids: every sphere's mask gathered at once into one 64-bit list per quad,
-        // then each list walked with the next cuboid's load in flight during the current tests
+        // up to 64 cuboids: every sphere's mask gathered at once into one 64-bit list per CQ
+        // spheres, then each list walked with the next cuboid's load in flight during the current
+        // tests
         uint64_t mq[SPH_GROUP / CQ];
 #pragma unroll
         for (int q = 0; q < SPH_GROUP / CQ; ++q) mq[q] = 0;
