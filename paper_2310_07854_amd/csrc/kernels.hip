@@ -545,6 +545,11 @@ __global__ __launch_bounds__(256) void k_sphere_cost(RobotArgs R, WorldArgs W, T
 // serves eight tests; the longer unions cost fewer instructions than the extra gathers of lists of
 // four (measured on trajectory and inverse-kinematics batches; sixteen is slower on trajectories)
 constexpr int CQ = VAPR_CULL_SPHERES;
+// floats per cuboid in the block's LDS copy: 80 bytes keeps 16-byte alignment and spreads the
+// cuboids of different lanes over the LDS banks (a 64-byte stride maps every other cuboid to the
+// same banks)
+constexpr int CUB_STRIDE = 20;
+
 
 __device__ __forceinline__ int voxel_of(const GridArgs& g, float x, float y, float z) {
   const float fx = (x - g.ox) * g.inv_cell, fy = (y - g.oy) * g.inv_cell, fz = (z - g.oz) * g.inv_cell;
@@ -571,17 +576,38 @@ __device__ __forceinline__ void cuboid_key_v(const float4& c0, const float4& c1,
 }
 
 // lowest candidate of a lane's list (removed from it) with its cuboid loaded; -1 when empty
+template <int STRIDE = 16>
 __device__ __forceinline__ int pop_cuboid(uint64_t& m, const float* wbox, float4& c0, float4& c1, float4& c2,
                                           float4& c3) {
   if (!m) return -1;
   const int k = __builtin_ctzll(m);
   m &= m - 1;
-  const float4* c4 = reinterpret_cast<const float4*>(wbox + k * 16);
+  const float4* c4 = reinterpret_cast<const float4*>(wbox + k * STRIDE);
   c0 = c4[0];
   c1 = c4[1];
   c2 = c4[2];
   c3 = c4[3];
   return k;
+}
+
+// The candidate list m against spheres i0 .. i0 + CQ - 1, cuboid k at base + k * STRIDE (the world's
+// table in memory, or the block's LDS copy), two cuboid buffers used in turn so that the next
+// candidate's load is in flight while the current one is tested.
+template <int STRIDE>
+__device__ __forceinline__ void walk_list(uint64_t m, const float* base, int i0, const float (&px)[SPH_GROUP],
+                                          const float (&py)[SPH_GROUP], const float (&pz)[SPH_GROUP],
+                                          float (&best)[SPH_GROUP], int (&bk)[SPH_GROUP]) {
+  float4 a0, a1, a2, a3, b0, b1, b2, b3;
+  int ka = pop_cuboid<STRIDE>(m, base, a0, a1, a2, a3);
+  while (ka >= 0) {
+    const int kb = pop_cuboid<STRIDE>(m, base, b0, b1, b2, b3);
+#pragma unroll
+    for (int i = i0; i < i0 + CQ; ++i) cuboid_key_v(a0, a1, a2, a3, px[i], py[i], pz[i], ka, best[i], bk[i]);
+    if (kb < 0) break;
+    ka = pop_cuboid<STRIDE>(m, base, a0, a1, a2, a3);
+#pragma unroll
+    for (int i = i0; i < i0 + CQ; ++i) cuboid_key_v(b0, b1, b2, b3, px[i], py[i], pz[i], kb, best[i], bk[i]);
+  }
 }
 
 template <int FS>
@@ -597,7 +623,19 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3))) void k
   const int64_t b = blk * 64 + lane;
   const bool valid = b < sh.B;
   float* pos = lds_f;                                // sphere s, component c: pos[(s * 3 + c) * 64 + lane]
-  float* part = lds_f + ng * SPH_GROUP * 3 * 64;     // [ng][64] self-cost partials
+  float* part = lds_f + n_s * 3 * 64;                // [ng][64] self-cost partials
+  float* cub = part + ng * 64;                       // the block's world's cuboids (culled path)
+  const int64_t first = blk * 64;
+  const int64_t last = (first + 63 < sh.B ? first + 63 : sh.B - 1);
+  const int w_lo = uniform((int)(first / sh.cfg_per_world));
+  const int w_hi = uniform((int)(last / sh.cfg_per_world));
+  // one world for the whole block and at most 64 cuboids: its cuboids go to LDS, read there by the
+  // candidate walks and the closest cuboid's distance instead of gathered from memory per lane
+  const bool staged = Gd.MW > 0 && Gd.MW <= 2 && w_lo == w_hi;
+  if (staged) {
+    const float* src = W.box + (int64_t)w_lo * K * 16;
+    for (int i = threadIdx.x; i < K * 16; i += blockDim.x) cub[(i >> 4) * CUB_STRIDE + (i & 15)] = src[i];
+  }
 
   float px[SPH_GROUP], py[SPH_GROUP], pz[SPH_GROUP];
   if (valid) {
@@ -609,10 +647,12 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3))) void k
 #pragma unroll
     for (int i = 0; i < SPH_GROUP; ++i) px[i] = py[i] = pz[i] = 0.f;
   }
+  const int active = uniform(min(SPH_GROUP, n_s - g * SPH_GROUP));
   {
     float* mine = pos + g * SPH_GROUP * 3 * 64 + lane;
 #pragma unroll
     for (int i = 0; i < SPH_GROUP; ++i) {
+      if (i >= active) continue;  // the image holds the n_s real spheres only
       mine[(i * 3 + 0) * 64] = px[i];
       mine[(i * 3 + 1) * 64] = py[i];
       mine[(i * 3 + 2) * 64] = pz[i];
@@ -620,12 +660,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3))) void k
   }
   __syncthreads();
 
-  const int64_t first = blk * 64;
-  const int64_t last = (first + 63 < sh.B ? first + 63 : sh.B - 1);
-  const int w_lo = uniform((int)(first / sh.cfg_per_world));
-  const int w_hi = uniform((int)(last / sh.cfg_per_world));
   const int my_w = valid ? (int)(b / sh.cfg_per_world) : -1;
-  const int active = uniform(min(SPH_GROUP, n_s - g * SPH_GROUP));
 
   float best[SPH_GROUP];
   int bk[SPH_GROUP];
@@ -661,20 +696,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3))) void k
         for (int q = 0; q < SPH_GROUP / CQ; ++q) {
           const int i0 = q * CQ;
           if (i0 >= active) continue;
-          uint64_t m = mq[q];
-          // two cuboid buffers used in turn: the next candidate's load is in flight while the
-          // current one is tested
-          float4 a0, a1, a2, a3, b0, b1, b2, b3;
-          int ka = pop_cuboid(m, wbox, a0, a1, a2, a3);
-          while (ka >= 0) {
-            const int kb = pop_cuboid(m, wbox, b0, b1, b2, b3);
-#pragma unroll
-            for (int i = i0; i < i0 + CQ; ++i) cuboid_key_v(a0, a1, a2, a3, px[i], py[i], pz[i], ka, best[i], bk[i]);
-            if (kb < 0) break;
-            ka = pop_cuboid(m, wbox, a0, a1, a2, a3);
-#pragma unroll
-            for (int i = i0; i < i0 + CQ; ++i) cuboid_key_v(b0, b1, b2, b3, px[i], py[i], pz[i], kb, best[i], bk[i]);
-          }
+          if (staged) walk_list<CUB_STRIDE>(mq[q], cub, i0, px, py, pz, best, bk);
+          else walk_list<16>(mq[q], wbox, i0, px, py, pz, best, bk);
         }
       } else {
 #pragma unroll
@@ -721,7 +744,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3))) void k
     const float r = i < active ? sphere_of(R.sph, g * SPH_GROUP + i).w : 0.f;
     if (i < active && K > 0 && valid && !out_of_reach(best[i], cp.eta, r)) {
       float sd, nx, ny, nz;
-      cuboid_sd_grad(mybox + bk[i] * 16, px[i], py[i], pz[i], sd, nx, ny, nz);
+      if (staged) cuboid_sd_grad(cub + bk[i] * CUB_STRIDE, px[i], py[i], pz[i], sd, nx, ny, nz);
+      else cuboid_sd_grad(mybox + bk[i] * 16, px[i], py[i], pz[i], sd, nx, ny, nz);
       const float d = fmaxf(cp.eta - (sd - r), 0.f);
       dv[i] = d;
       if (d > 0.f) {
@@ -1751,12 +1775,14 @@ hipError_t launch_sphere_cost(hipStream_t s, const RobotArgs& R, const WorldArgs
   return hipGetLastError();
 }
 
-size_t sphere_cost_lds_bytes(int n_groups) { return (size_t)n_groups * (SPH_GROUP * 3 + 1) * 256; }
+size_t sphere_cost_lds_bytes(int n_s, int n_groups) {
+  return ((size_t)n_s * 3 * 64 + (size_t)n_groups * 64 + 64 * CUB_STRIDE) * sizeof(float);
+}
 
 hipError_t launch_sphere_cost_blk(hipStream_t s, const RobotArgs& R, const WorldArgs& W, const GridArgs& Gd,
                                   const TV& S, const TV& D, const TV& G, float* selfc, const ShapeArgs& sh,
                                   const CostArgs& cp) {
-  const size_t lds = sphere_cost_lds_bytes(R.n_groups);
+  const size_t lds = sphere_cost_lds_bytes(R.n_s, R.n_groups);
   const dim3 grid(blocks_for(sh.B, 64)), block(64 * R.n_groups);
   switch (S.fmt) {
 #define VAPR_K2(F) \

@@ -88,7 +88,7 @@ hipError_t launch_fk(hipStream_t s, const float* q, const RobotArgs& R, const TV
 hipError_t launch_sphere_cost(hipStream_t s, const RobotArgs& R, const WorldArgs& W, const TV& S, const TV& D,
                               const TV& G, float* selfc, const ShapeArgs& sh, const CostArgs& cp);
 // LDS bytes of the block-staged sphere-cost kernel (used while they fit in 64 KiB)
-size_t sphere_cost_lds_bytes(int n_groups);
+size_t sphere_cost_lds_bytes(int n_s, int n_groups);
 hipError_t launch_sphere_cost_blk(hipStream_t s, const RobotArgs& R, const WorldArgs& W, const GridArgs& Gd,
                                   const TV& S, const TV& D, const TV& G, float* selfc, const ShapeArgs& sh,
                                   const CostArgs& cp);
