@@ -545,10 +545,6 @@ __global__ __launch_bounds__(256) void k_sphere_cost(RobotArgs R, WorldArgs W, T
 // serves eight tests; the longer unions cost fewer instructions than the extra gathers of lists of
 // four (measured on trajectory and inverse-kinematics batches; sixteen is slower on trajectories)
 constexpr int CQ = VAPR_CULL_SPHERES;
-// floats per cuboid in the block's LDS copy: 80 bytes keeps 16-byte alignment and spreads the
-// cuboids of different lanes over the LDS banks (a 64-byte stride maps every other cuboid to the
-// same banks)
-constexpr int CUB_STRIDE = 20;
 
 
 __device__ __forceinline__ int voxel_of(const GridArgs& g, float x, float y, float z) {
@@ -576,13 +572,12 @@ __device__ __forceinline__ void cuboid_key_v(const float4& c0, const float4& c1,
 }
 
 // lowest candidate of a lane's list (removed from it) with its cuboid loaded; -1 when empty
-template <int STRIDE = 16>
 __device__ __forceinline__ int pop_cuboid(uint64_t& m, const float* wbox, float4& c0, float4& c1, float4& c2,
                                           float4& c3) {
   if (!m) return -1;
   const int k = __builtin_ctzll(m);
   m &= m - 1;
-  const float4* c4 = reinterpret_cast<const float4*>(wbox + k * STRIDE);
+  const float4* c4 = reinterpret_cast<const float4*>(wbox + k * 16);
   c0 = c4[0];
   c1 = c4[1];
   c2 = c4[2];
@@ -590,21 +585,20 @@ __device__ __forceinline__ int pop_cuboid(uint64_t& m, const float* wbox, float4
   return k;
 }
 
-// The candidate list m against spheres i0 .. i0 + CQ - 1, cuboid k at base + k * STRIDE (the world's
-// table in memory, or the block's LDS copy), two cuboid buffers used in turn so that the next
-// candidate's load is in flight while the current one is tested.
-template <int STRIDE>
+// The candidate list m against spheres i0 .. i0 + CQ - 1, cuboid k at base + 16 k (the world's table
+// in memory, or the block's LDS copy), two cuboid buffers used in turn so that the next candidate's
+// load is in flight while the current one is tested.
 __device__ __forceinline__ void walk_list(uint64_t m, const float* base, int i0, const float (&px)[SPH_GROUP],
                                           const float (&py)[SPH_GROUP], const float (&pz)[SPH_GROUP],
                                           float (&best)[SPH_GROUP], int (&bk)[SPH_GROUP]) {
   float4 a0, a1, a2, a3, b0, b1, b2, b3;
-  int ka = pop_cuboid<STRIDE>(m, base, a0, a1, a2, a3);
+  int ka = pop_cuboid(m, base, a0, a1, a2, a3);
   while (ka >= 0) {
-    const int kb = pop_cuboid<STRIDE>(m, base, b0, b1, b2, b3);
+    const int kb = pop_cuboid(m, base, b0, b1, b2, b3);
 #pragma unroll
     for (int i = i0; i < i0 + CQ; ++i) cuboid_key_v(a0, a1, a2, a3, px[i], py[i], pz[i], ka, best[i], bk[i]);
     if (kb < 0) break;
-    ka = pop_cuboid<STRIDE>(m, base, a0, a1, a2, a3);
+    ka = pop_cuboid(m, base, a0, a1, a2, a3);
 #pragma unroll
     for (int i = i0; i < i0 + CQ; ++i) cuboid_key_v(b0, b1, b2, b3, px[i], py[i], pz[i], kb, best[i], bk[i]);
   }
@@ -634,7 +628,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3))) void k
   const bool staged = Gd.MW > 0 && Gd.MW <= 2 && w_lo == w_hi;
   if (staged) {
     const float* src = W.box + (int64_t)w_lo * K * 16;
-    for (int i = threadIdx.x; i < K * 16; i += blockDim.x) cub[(i >> 4) * CUB_STRIDE + (i & 15)] = src[i];
+    for (int i = threadIdx.x; i < K * 16; i += blockDim.x) cub[i] = src[i];
   }
 
   float px[SPH_GROUP], py[SPH_GROUP], pz[SPH_GROUP];
@@ -696,8 +690,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3))) void k
         for (int q = 0; q < SPH_GROUP / CQ; ++q) {
           const int i0 = q * CQ;
           if (i0 >= active) continue;
-          if (staged) walk_list<CUB_STRIDE>(mq[q], cub, i0, px, py, pz, best, bk);
-          else walk_list<16>(mq[q], wbox, i0, px, py, pz, best, bk);
+          if (staged) walk_list(mq[q], cub, i0, px, py, pz, best, bk);
+          else walk_list(mq[q], wbox, i0, px, py, pz, best, bk);
         }
       } else {
 #pragma unroll
@@ -744,7 +738,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3))) void k
     const float r = i < active ? sphere_of(R.sph, g * SPH_GROUP + i).w : 0.f;
     if (i < active && K > 0 && valid && !out_of_reach(best[i], cp.eta, r)) {
       float sd, nx, ny, nz;
-      if (staged) cuboid_sd_grad(cub + bk[i] * CUB_STRIDE, px[i], py[i], pz[i], sd, nx, ny, nz);
+      if (staged) cuboid_sd_grad(cub + bk[i] * 16, px[i], py[i], pz[i], sd, nx, ny, nz);
       else cuboid_sd_grad(mybox + bk[i] * 16, px[i], py[i], pz[i], sd, nx, ny, nz);
       const float d = fmaxf(cp.eta - (sd - r), 0.f);
       dv[i] = d;
@@ -868,8 +862,8 @@ __device__ __forceinline__ void walk_candidates(uint64_t m, const float* wbox, c
   }
 }
 
-// the live points of a chunk of nj samples (1 <= nj <= NJ) against the candidate list, or against
-// every cuboid
+// the live points of a chunk of nj samples (1 <= nj <= NJ) against the candidate list (cuboid k at
+// wbox + 16 k), or against every cuboid
 template <int NJ>
 __device__ __forceinline__ void swept_chunk_walk(int nj, uint64_t m, const float* wbox, const float (&px)[SPH_GROUP],
                                                  const float (&py)[SPH_GROUP], const float (&pz)[SPH_GROUP],
@@ -889,11 +883,15 @@ __device__ __forceinline__ void swept_chunk_dense(int nj, cptr<float> wbox, int 
   closest_cuboids<NJ * SW_Q>(wbox, K, px, py, pz, best, bk);
 }
 
-// X of one sphere group of each wavefront, [wave][sphere * 3 + component][lane], until it is stored
-constexpr int SWEPT_LDS_BYTES = 4 * SPH_GROUP * 3 * 64 * (int)sizeof(float);
+// X of one sphere group of each wavefront, [wave][sphere * 3 + component][lane], until it is stored,
+// then one world's cuboids (culled path, at most 64 of 16 floats): 53,248 bytes, three workgroups
+// per CU. (An 80-byte cuboid stride, 54,272 bytes, leaves room for only two, and the kernel measured
+// 12% slower than without the copy.)
+constexpr int SWEPT_XS_FLOATS = 4 * SPH_GROUP * 3 * 64;
+constexpr int SWEPT_LDS_BYTES = (SWEPT_XS_FLOATS + 64 * 16) * (int)sizeof(float);
 
 // 3 wavefronts per SIMD: the register budget (168) that four spheres by two samples fit without
-// spilling, and what the X staging allows (three 48 KB workgroups per CU)
+// spilling, and what the LDS staging allows (three 53 KB workgroups per CU)
 template <int FS>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_swept(RobotArgs R, WorldArgs W, GridArgs Gd, TV S, TV X,
                                                float* __restrict__ sweptc, ShapeArgs sh, CostArgs cp) {
@@ -902,6 +900,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   float* xs = lds_sw + (threadIdx.x >> 6) * (SPH_GROUP * 3 * 64) + lane;
   const int64_t wv = (int64_t)blockIdx.x * 4 + uniform(threadIdx.x >> 6);
   const int64_t first = wv * 63;
+  const bool culled = Gd.MW > 0 && Gd.MW <= 2;
+  // culled path: the world of the workgroup's middle configuration has its cuboids copied to LDS;
+  // wavefronts whose segments all lie in that world read them there, the others from memory
+  float* cub = lds_sw + SWEPT_XS_FLOATS;
+  const int64_t mid = min((int64_t)blockIdx.x * 4 * 63 + 2 * 63, sh.B - 1);
+  const int w_st = uniform((int)(mid / sh.cfg_per_world));
+  if (culled) {
+    const int kf = uniform(W.K) * 16;
+    const float* srcb = W.box + (int64_t)w_st * kf;
+    for (int i = threadIdx.x; i < kf; i += blockDim.x) cub[i] = srcb[i];
+  }
+  __syncthreads();
   if (first >= sh.B) return;  // whole wavefront: its own configurations and lane 63's segment lie past B
   const int64_t c = first + lane;                       // own configuration (lanes 0..62)
   const int64_t a = lane < 63 ? c : first - 1;          // segment start
@@ -918,7 +928,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   const int k_sw = uniform(cp.k_sw);
   const float coef_base = -2.f * cp.w_sw / (float)k_sw;
   const int src = ((lane + 63) & 63) << 2;              // ds_bpermute address of lane - 1
-  const bool culled = Gd.MW > 0 && Gd.MW <= 2;
+  const bool staged = culled && w_lo == w_hi && w_lo == w_st;
   const int64_t n3 = (int64_t)Gd.n * Gd.n * Gd.n;
   const uint32_t* b0 = lane_base(S, seg ? a : 0);
   const uint32_t* b1 = lane_base(S, seg ? a + 1 : 0);
@@ -972,7 +982,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
                 const uint32_t* mv = gm + (int64_t)vox * Gd.MW;
                 m |= (uint64_t)mv[0] | (Gd.MW > 1 ? (uint64_t)mv[1] << 32 : 0ull);
               }
-              swept_chunk_walk<SW_KS>(nj, m, wbox, px, py, pz, best, bk);
+              if (staged) swept_chunk_walk<SW_KS>(nj, m, cub, px, py, pz, best, bk);
+              else swept_chunk_walk<SW_KS>(nj, m, wbox, px, py, pz, best, bk);
             }
           } else {
             for (int w = w_lo; w <= w_hi; ++w) {
@@ -990,7 +1001,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
               const float r = sphere_of(R.sph, g * SPH_GROUP + q4 + i).w;
               if (out_of_reach(best[n], cp.eta, r)) continue;
               float sd, nx, ny, nz;
-              cuboid_sd_grad(wbox + bk[n] * 16, px[n], py[n], pz[n], sd, nx, ny, nz);
+              if (staged) cuboid_sd_grad(cub + bk[n] * 16, px[n], py[n], pz[n], sd, nx, ny, nz);
+              else cuboid_sd_grad(wbox + bk[n] * 16, px[n], py[n], pz[n], sd, nx, ny, nz);
               const float d = fmaxf(cp.eta - (sd - r), 0.f);
               if (d > 0.f) {
                 cost = fmaf(d, d, cost);
@@ -1776,7 +1788,7 @@ hipError_t launch_sphere_cost(hipStream_t s, const RobotArgs& R, const WorldArgs
 }
 
 size_t sphere_cost_lds_bytes(int n_s, int n_groups) {
-  return ((size_t)n_s * 3 * 64 + (size_t)n_groups * 64 + 64 * CUB_STRIDE) * sizeof(float);
+  return ((size_t)n_s * 3 * 64 + (size_t)n_groups * 64 + 64 * 16) * sizeof(float);
 }
 
 hipError_t launch_sphere_cost_blk(hipStream_t s, const RobotArgs& R, const WorldArgs& W, const GridArgs& Gd,
