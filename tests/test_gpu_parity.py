@@ -206,7 +206,7 @@ def shuffled_robot(robot, seed):
 
 @pytest.mark.parametrize("case", ["ragged", "no_cuboids", "no_pairs", "one_sphere", "worlds_in_wave",
                                   "many_spheres", "shuffled_links", "shuffled_many_spheres", "many_cuboids",
-                                  "max_sizes"])
+                                  "max_sizes", "staged_blocks"])
 def test_edge_shapes(case):
     need_gpu()
     kw = dict(seed=21, n_worlds=3, tpw=3, T=5, n_ls=2, n_spheres=37, n_cuboids=7, n_pairs=40)
@@ -225,6 +225,10 @@ def test_edge_shapes(case):
         kw.update(n_spheres=1, n_pairs=0)
     if case == "worlds_in_wave":
         kw.update(n_worlds=9, tpw=1, T=4, n_ls=1)
+    if case == "staged_blocks":
+        # 96 configurations per world: of the six 64-configuration blocks, four lie in one world and
+        # read its cuboids from their LDS copy, two straddle a world boundary and read them from memory
+        kw.update(n_worlds=4, tpw=2, T=24, n_ls=2, n_cuboids=40)
     wl = dense_workload(**kw)
     if case.startswith("shuffled"):
         wl = dataclasses.replace(wl, robot=shuffled_robot(wl.robot, seed=5))

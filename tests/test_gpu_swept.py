@@ -91,7 +91,9 @@ def check(wl, ctx, ws, shape, cost, grad, ref, k=K_SW, w_sw=W_SW):
 @pytest.mark.parametrize("T,tpw,n_ls", [(8, 4, 1), (5, 13, 1), (2, 40, 1), (48, 2, 1), (6, 4, 3)])
 def test_swept_fp32_parity(T, tpw, n_ls):
     """Ragged shapes: segments across the 63-configuration wavefront boundary, many trajectory
-    ends, a long horizon, and line-search candidates that must not be joined."""
+    ends, a long horizon, and line-search candidates that must not be joined. The long horizon
+    (two worlds of 96 configurations) has wavefronts inside the world whose cuboids the workgroup
+    copies to LDS and wavefronts that read them from memory."""
     need_gpu()
     wl = swept_workload(T=T, tpw=tpw, n_ls=n_ls)
     ctx, ws, shape, cost, grad, ref = run(wl)
