@@ -100,6 +100,22 @@ def traffic_from_profile(kernel_src_hash, formats):
     return rec if same else None
 
 
+def workload_traffic(name, formats, kernel):
+    """HBM bytes per launch of `kernel` in another benchmark mode (`swept_k4`, `ik`), measured with
+    rocprofv3 counters on the current kernels and the same format assignment, else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        rec = json.load(open(path))
+    except Exception:
+        return None
+    if rec.get("kernels_sha256") != kernels_hash():
+        return None
+    w = rec.get("workloads", {}).get(name)
+    if not w or w.get("formats") != json.loads(json.dumps(formats)):
+        return None
+    return w.get("bytes_per_launch", {}).get(kernel)
+
+
 def kernels_hash():
     h = hashlib.sha256()
     for f in ("kernels.hip", "codec.hpp", "layout.hpp"):
@@ -726,7 +742,8 @@ def swept_bench(args):
                          "unit": "TFLOP/s", "frac": achieved / VALU_PEAK_TFLOPS, "flops_per_cfg": flops_cfg,
                          "culled_tests_per_cfg": work["needed_tests_per_cfg"],
                          "issued_lane_tests_per_cfg": work["issued_lane_tests_per_cfg"],
-                         "dense_equivalent_TFLOPs": dense_cfg * B / (sw_us * 1e-6) / 1e12, "traffic": None},
+                         "dense_equivalent_TFLOPs": dense_cfg * B / (sw_us * 1e-6) / 1e12,
+                         "traffic": workload_traffic(f"swept_k{k}", out["paper_like"]["formats"], "k_swept")},
             "cpu_baseline": None if args.no_cpu_baseline else swept_cpu_baseline(
                 {kk: tuple(v) for kk, v in out["paper_like"]["formats"].items()}, k)}
     print(json.dumps(line), flush=True)
@@ -973,12 +990,13 @@ def ik_bench(args):
         flops = FLOPS_PER_SPHERE_CUBOID * pl["culled"]["needed_tests_per_cfg"] + FLOPS_PER_PAIR * N_PAIRS
         achieved = flops * B / (kern[dom] * 1e-6) / 1e12
         roofline = {"kernel": "k_sphere_cost", "bound": "alu", "achieved": achieved, "peak": VALU_PEAK_TFLOPS,
-                    "unit": "TFLOP/s", "frac": achieved / VALU_PEAK_TFLOPS, "flops_per_cfg": flops, "traffic": None}
+                    "unit": "TFLOP/s", "frac": achieved / VALU_PEAK_TFLOPS, "flops_per_cfg": flops}
     else:
         kb = kernel_bytes({kk: tuple(v) for kk, v in pl["formats"].items()})
         achieved = kb.get(dom, 0.0) * B / (kern[dom] * 1e-6) / 1e9
         roofline = {"kernel": "k_" + dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": achieved / HBM_PEAK_GBS, "traffic": None}
+                    "frac": achieved / HBM_PEAK_GBS}
+    roofline["traffic"] = workload_traffic("ik", pl["formats"], roofline["kernel"])
     line = {"metric": "inverse-kinematics cost fwd+bwd evals/s (one optimiser iteration per step)",
             "value": pl["value"], "unit": "evals/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
             "ms_per_step": pl["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
