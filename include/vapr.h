@@ -7,7 +7,7 @@
  * "VaPr: Variable-Precision Tensors to Accelerate Robot Motion Planning").  The five large
  * intermediate tensors of that iteration -- link poses L, sphere positions S, per-sphere distances
  * D, sphere-position gradients G and joint gradients J (Sec. III-C) -- are stored in per-tensor
- * formats chosen from FP32, FP16, BF16, FP8 E4M3/E5M2, FP6 E3M2 and FP4 E2M1 (Sec. IV-A, IV-C);
+ * formats chosen from FP32, FP16, BF16, FP8 E4M3/E5M2, FP6 E3M2 and FP4 E2M1 (Sec. IV-A, V-B);
  * all arithmetic is FP32, reductions feeding the line search are FP64.
  *
  * Conventions shared by every call
@@ -35,7 +35,7 @@
 extern "C" {
 #endif
 
-#define VAPR_ABI_VERSION 2
+#define VAPR_ABI_VERSION 3
 
 typedef enum {
   VAPR_OK = 0,
@@ -159,14 +159,14 @@ int vapr_set_robot(vapr_ctx* ctx, int n_joints, const float* fixed_tf, int n_sph
  * Limits: 1 <= n_worlds <= 65536, 0 <= n_cuboids <= 256. */
 int vapr_set_worlds(vapr_ctx* ctx, int n_worlds, int n_cuboids, const float* pose, const float* half_ext);
 
-/* Select the storage format of each large tensor (Sec. IV-B, IV-C).  Unknown format or scale out
- * of range -> VAPR_E_INVALID.  Workspaces filled under another precision become invalid. */
 /* Goal poses of inverse kinematics, one per world: goal host [n][3][4], row-major [R_g | p_g] of
  * link 8 (R_g a rotation to 1e-5).  n = 0 clears them (no pose cost).  Copied; a forward pass with
  * goals needs n >= its n_worlds.  Inverse kinematics runs as trajectories of one timestep
  * (T = 1), whose rows the optimiser leaves free (vapr_lbfgs_state.free_ends = 1). */
 int vapr_set_goals(vapr_ctx* ctx, int n, const float* goal);
 
+/* Select the storage format of each large tensor (Sec. IV-B, V-B).  Unknown format or scale out
+ * of range -> VAPR_E_INVALID.  Workspaces filled under another precision become invalid. */
 int vapr_set_precision(vapr_ctx* ctx, const vapr_precision* p);
 int vapr_get_precision(const vapr_ctx* ctx, vapr_precision* p);
 
@@ -198,9 +198,40 @@ typedef struct {
 int vapr_get_culling_grid(vapr_ctx* ctx, int world, vapr_grid_info* info, uint32_t* mask_out,
                           size_t capacity_words);
 
+/* Workspace state.  A workspace holds the forward pass that last completed into it.  Its first 256
+ * bytes are a header written by that pass's last kernel: magic, context id, the context's pass
+ * number, B, shape, a tag of the precision assignment, robot and cost-parameter generations.  The
+ * host keeps a record per workspace address; vapr_cost_bwd, vapr_optimizer_init/step,
+ * vapr_cost_fwd_from (first > 1) and vapr_ws_export check it synchronously (VAPR_E_STATE when the
+ * workspace holds no forward pass of this context, or one of another shape, or the precision,
+ * robot or cost parameters changed since).  The backward and optimiser kernels then compare the
+ * header's context id and pass number with the record's before reading anything else: a workspace
+ * whose memory was overwritten in the meantime gives NaN gradients (backward) or leaves the
+ * optimiser state untouched, and raises a flag that vapr_sync reports.
+ *
+ * vapr_ws_reset: announce a newly allocated buffer (or one being reused) as a workspace before its
+ * first use.  It forgets every record of an address inside [ws, ws + ws_bytes) -- memory that was
+ * freed and handed out again must not pass for the forward pass it once held -- and clears the
+ * header on the stream.  ws_bytes >= 256. */
+int vapr_ws_reset(vapr_ctx* ctx, void* ws, size_t ws_bytes);
+
+/* Collision check of a forward pass (the success test of planning, Sec. VI-A: a trajectory is
+ * usable when it is collision-free): free_cfg dev [B] int32 receives 1 for a configuration whose
+ * every sphere clears every cuboid (stored activation depth d < eta, i.e. clearance > 0), whose
+ * every self pair is apart (|p_a - p_b| - r_a - r_b > 0, from the stored sphere centres) and whose
+ * joints are within their limits (bound cost 0), else 0.  ws must hold a forward pass of this shape
+ * under the current settings (VAPR_E_STATE otherwise); with reduced formats the test reads the
+ * stored (quantised) S and D. */
+int vapr_collision_free(vapr_ctx* ctx, int n_worlds, int traj_per_world, int T, int n_ls, const void* ws,
+                        size_t ws_bytes, int32_t* free_cfg);
+
+/* Synchronise the context's stream and report what its kernels found: VAPR_E_STATE (once, the flag
+ * is cleared) when a backward or optimiser kernel met a workspace whose header did not match. */
+int vapr_sync(vapr_ctx* ctx);
+
 /* Bytes of device workspace a forward/backward pass of this batch shape needs at the current
- * precision and swept setting (holds L, S, D, G, J and two FP32 scalars per configuration, plus X
- * and a third scalar while swept_steps > 0).  Requires a robot. */
+ * precision and swept setting (the 256-byte header, then L, S, D, G, J and two FP32 scalars per
+ * configuration, plus X and a third scalar while swept_steps > 0).  Requires a robot. */
 int vapr_workspace_size(const vapr_ctx* ctx, int n_worlds, int traj_per_world, int T, int n_ls,
                         size_t* bytes);
 
@@ -265,7 +296,7 @@ int vapr_optimizer_init(vapr_ctx* ctx, const vapr_lbfgs_state* st, const void* w
 int vapr_optimizer_step(vapr_ctx* ctx, const vapr_lbfgs_state* st, const void* ws, size_t ws_bytes,
                         const double* cost_cand, float* q_cand);
 
-/* Element-wise codec on the context-free current device (Sec. IV-C's conversion of a tensor on
+/* Element-wise codec on the context-free current device (Sec. V-B conversion of a tensor on
  * write and read).  in/out dev; out holds vapr_packed_bytes(fmt, n) bytes in the packed layout.
  * stream: hipStream_t or NULL.  0 <= n <= 2^32. */
 int vapr_quantize(int fmt, int scale_exp, const float* in, void* out, int64_t n, void* hip_stream);
@@ -326,6 +357,13 @@ int vapr_gemm_bf16(int M, int N, int K, const uint16_t* A, int64_t a_ms, int64_t
  * [n][7] FP32, traj [n][8][32][7] FP32; all device memory owned by the caller. */
 int vapr_seed_head(int n, const uint16_t* a3, int64_t lda, const uint16_t* W4, const float* b4, const float* start,
                    const float* goal, float* traj, void* hip_stream);
+
+/* Deviations of m trajectories per problem from the straight line (the inverse of
+ * vapr_seed_trajectories, for training targets): dev[r][i][t][j] = traj[r][i][t][j] - line, with
+ * line = start[r][j] + (goal[r][j] - start[r][j]) t / 31 for t = 1..30, start at t = 0 and goal at
+ * t = 31.  traj, dev [n][m][32][7], start, goal [n][7]; dev may alias traj. */
+int vapr_seed_deviations(int n, int m, const float* traj, const float* start, const float* goal, float* dev,
+                         void* hip_stream);
 
 /* Min-over-slot matching loss of n problems: y [n][1792] predicted deviations (8 slots x 224),
  * targets [n][1792] (8 target trajectories), valid [n][8] (0 / nonzero).  e_sj = mean over 224 of

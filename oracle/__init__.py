@@ -5,7 +5,7 @@ test-suite, the entry point's smoke check and the benchmark's CPU-baseline leg m
 product path never does, and it shares no code with the HIP kernels.
 
 Modules
-  formats    reference encoder/decoder of every storage format (Sec. IV-A, Sec. IV-C)
+  formats    reference encoder/decoder of every storage format (Sec. IV-A, Sec. V-B)
   kinematics serial-chain forward kinematics and collision-sphere placement (Sec. II-B, Sec. III-B)
   geometry   oriented-cuboid signed distance and its gradient
   cost       world/self/bound costs, aggregation, the joint-space gradient two ways, and the

@@ -3,7 +3,7 @@
 The paper searches 21 floating-point types from FP4 to FP32, each one sign bit, E exponent bits and
 M mantissa bits (Sec. IV-A), and evaluates them by quantising every stored tensor to the type and
 back to FP32 at each kernel invocation (Sec. IV-B).  It names 13 of the 21 in its results
-(Table III): E2M1, E2M2, E3M1, E2M3, E3M2, E4M3, E5M2, E6M6, E5M9, E6M8, E5M10, E8M7, and E8M23
+(Table II): E2M1, E2M2, E3M1, E2M3, E3M2, E4M3, E5M2, E6M6, E5M9, E6M8, E5M10, E8M7, and E8M23
 (FP32); it states that exactly three of them (E5M10, E8M7, E8M23) are 16 bits or wider, and lists
 FP4, FP5, FP6, FP8, FP10, FP16 and FP32 as the widths of interest.  Readings used here:
 

@@ -2,7 +2,7 @@
 
 The paper stores large FP32 tensors in narrower ExMy floating-point formats (E exponent bits, M
 mantissa bits, one sign bit; Sec. IV-A) and converts FP32 to FP16 with round-to-nearest on write
-and back to FP32 on read (Sec. IV-C).  It fixes neither exponent bias, nor special values, nor the
+and back to FP32 on read (Sec. V-B).  It fixes neither exponent bias, nor special values, nor the
 overflow rule; the readings used here are:
 
   id name  E  M  bias  max finite   specials              overflow / Inf input

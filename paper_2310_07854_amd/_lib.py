@@ -28,7 +28,7 @@ def format_id(fmt: str):
     return EXMY, int(m.group(1)), int(m.group(2))
 FORMAT_BITS = {F32: 32, F16: 16, BF16: 16, E4M3: 8, E5M2: 8, E3M2: 6, E2M1: 4}
 T_LINK_POSES, T_SPHERE_POS, T_SPHERE_DIST, T_SPHERE_GRAD, T_JOINT_GRAD, T_SELF_COST, T_BOUND_COST = range(7)
-ABI_VERSION = 2  # the structs below match include/vapr.h at this version
+ABI_VERSION = 3  # the structs below match include/vapr.h at this version
 TENSOR_IDS = {"link_poses": 0, "sphere_pos": 1, "sphere_dist": 2, "sphere_grad": 3, "joint_grad": 4,
               "self_cost": 5, "bound_cost": 6, "swept_grad": 7, "swept_cost": 8,
               "pose_cost": 9}
@@ -92,6 +92,10 @@ SIGNATURES = {
     "vapr_set_culling": (_I, [_P, _I]),
     "vapr_get_culling_grid": (_I, [_P, _I, ctypes.POINTER(GridInfoC), _P, _SZ]),
     "vapr_workspace_size": (_I, [_P, _I, _I, _I, _I, ctypes.POINTER(_SZ)]),
+    "vapr_ws_reset": (_I, [_P, _P, _SZ]),
+    "vapr_sync": (_I, [_P]),
+    "vapr_collision_free": (_I, [_P, _I, _I, _I, _I, _P, _SZ, _P]),
+    "vapr_seed_deviations": (_I, [_I, _I, _P, _P, _P, _P, _P]),
     "vapr_cost_fwd": (_I, [_P, _I, _I, _I, _I, _P, _P, _SZ, _P, _P]),
     "vapr_cost_fwd_from": (_I, [_P, _I, _I, _I, _I, _I, _P, _P, _SZ, _P, _P]),
     "vapr_cost_bwd": (_I, [_P, _P, _P, _SZ, _P, _P]),

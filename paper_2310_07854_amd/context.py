@@ -189,7 +189,19 @@ class Context:
         return int(n.value)
 
     def new_workspace(self, shape: Shape) -> torch.Tensor:
-        return torch.empty(self.workspace_size(shape), dtype=torch.uint8, device=f"cuda:{self.device}")
+        """A workspace for batches of this shape, announced to the library (vapr_ws_reset): memory
+        torch hands out again never passes for the forward pass it held before."""
+        ws = torch.empty(self.workspace_size(shape), dtype=torch.uint8, device=f"cuda:{self.device}")
+        self.ws_reset(ws)
+        return ws
+
+    def ws_reset(self, ws: torch.Tensor) -> None:
+        self._call("vapr_ws_reset", _dev(ws, torch.uint8, "ws"), ws.numel())
+
+    def sync(self) -> None:
+        """Wait for the context's work; raises VaprError (E_STATE) if a backward or optimiser kernel
+        met a workspace that no longer held its forward pass."""
+        self._call("vapr_sync")
 
     def cost_fwd(self, q: torch.Tensor, shape: Shape, ws: Optional[torch.Tensor] = None,
                  cost_traj: Optional[torch.Tensor] = None, cost_cfg: Optional[torch.Tensor] = None,
@@ -215,6 +227,13 @@ class Context:
         gp = _dev(grad_q, torch.float32, "grad_q") if grad_q is not None else None
         self._call("vapr_cost_bwd", _dev(q, torch.float32, "q"), _dev(ws, torch.uint8, "ws"), ws.numel(), up, gp)
         return grad_q
+
+    def collision_free(self, ws: torch.Tensor, shape: Shape) -> torch.Tensor:
+        """[B] bool from the forward pass in ws: every sphere clears every cuboid, every self pair is
+        apart and the joints are within their limits."""
+        out = torch.empty(shape.B, dtype=torch.int32, device=ws.device)
+        self._call("vapr_collision_free", *shape.args(), _dev(ws, torch.uint8, "ws"), ws.numel(), out.data_ptr())
+        return out.bool()
 
     # -- stored tensors --------------------------------------------------------------------------
     def tensor_count(self, name: str) -> int:

@@ -1,5 +1,5 @@
 // Device codec for the reduced storage formats (Sec. IV-A: ExMy formats packed several to a 32-bit
-// word; Sec. IV-C: FP32 -> narrow on write, narrow -> FP32 on read, arithmetic in FP32).
+// word; Sec. V-B: FP32 -> narrow on write, narrow -> FP32 on read, arithmetic in FP32).
 //
 // Encoding rounds to nearest with ties to even and keeps subnormals.  FP16/BF16 overflow to Inf;
 // E4M3/E5M2/E3M2/E2M1 saturate to their largest finite magnitude (Inf inputs too).  NaN inputs give

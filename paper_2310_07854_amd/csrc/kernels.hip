@@ -24,6 +24,23 @@ namespace vapr {
 
 __device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// Workspace header: the forward pass's last kernel writes it (first thread of block 0, plain vector
+// stores); the consumers compare context id and pass number before reading the workspace.
+__device__ __forceinline__ void ws_stamp(const WsStamp& st) {
+  if (st.hdr && blockIdx.x == 0 && threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < WH_WORDS; ++i) st.hdr[i] = st.w[i];
+  }
+}
+// true when the workspace holds the forward pass the host expects; otherwise the first thread of
+// block 0 raises the context's stale-workspace flag
+__device__ __forceinline__ bool ws_current(const WsCheck& ck) {
+  if (!ck.hdr) return true;
+  const bool ok = ck.hdr[WH_CTX] == ck.ctx && ck.hdr[WH_GEN] == ck.gen;
+  if (!ok && blockIdx.x == 0 && threadIdx.x == 0) *ck.status = 1u;
+  return ok;
+}
+
 // Read-only tables (robot, cuboids) are read through the constant address space: they are never
 // written while a kernel runs, so wave-uniform reads become scalar (SMEM) loads into SGPRs.
 template <typename T>
@@ -1106,7 +1123,9 @@ __device__ __forceinline__ double cfg_cost(const TV& D, const float* __restrict_
 __global__ __launch_bounds__(256) void k_reduce_t1(TV D, const float* __restrict__ selfc,
                                                    const float* __restrict__ boundc, const float* __restrict__ sweptc,
                                                    const float* __restrict__ posec, double* __restrict__ cost_traj,
-                                                   float* __restrict__ cost_cfg, ShapeArgs sh, CostArgs cp, int n_s) {
+                                                   float* __restrict__ cost_cfg, ShapeArgs sh, CostArgs cp, int n_s,
+                                                   WsStamp st) {
+  ws_stamp(st);
   const int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (b >= sh.B) return;
   const double c = cfg_cost(D, selfc, boundc, sweptc, posec, b, cp, n_s);
@@ -1118,7 +1137,8 @@ __global__ __launch_bounds__(256) void k_reduce(TV D, const float* __restrict__ 
                                                 const float* __restrict__ boundc, const float* __restrict__ sweptc,
                                                 const float* __restrict__ posec, const float* __restrict__ q,
                                                 double* __restrict__ cost_traj, float* __restrict__ cost_cfg,
-                                                ShapeArgs sh, CostArgs cp, int n_s) {
+                                                ShapeArgs sh, CostArgs cp, int n_s, WsStamp st) {
+  ws_stamp(st);
   const int64_t tc = (int64_t)blockIdx.x * 4 + uniform(threadIdx.x >> 6);
   if (tc >= sh.n_tc) return;
   const int lane = threadIdx.x & 63;
@@ -1203,7 +1223,7 @@ template <int FG, bool HAS_X>
 __global__ __launch_bounds__(256) void k_adjoint(const float* __restrict__ q, RobotArgs R, TV L, TV G, TV X, TV J,
                                                  const double* __restrict__ up, float* __restrict__ grad_q,
                                                  ShapeArgs sh, CostArgs cp, int recompute,
-                                                 const float* __restrict__ goal) {
+                                                 const float* __restrict__ goal, WsCheck ck) {
   __shared__ float tile[ADJ_TILE_WORDS];
   __shared__ float wrench[N_FIXED * 6 * 64];  // link l: force (3), moment (3) at ((l-1)*6 + k)*64 + lane
   __shared__ float qs[ADJ_Q_ROWS * N_JOINTS];  // row b0 - 1 + r at r * 7
@@ -1211,6 +1231,14 @@ __global__ __launch_bounds__(256) void k_adjoint(const float* __restrict__ q, Ro
   const int64_t b0 = (int64_t)blockIdx.x * 64;
   const int64_t b = b0 + lane;
   const bool live = b < sh.B;
+  if (!ws_current(ck)) {
+    // not the forward pass this call was issued for: NaN gradients, nothing read from the workspace
+    if (wave == 0 && live && grad_q) {
+#pragma unroll
+      for (int j = 0; j < N_JOINTS; ++j) grad_q[b * N_JOINTS + j] = __builtin_nanf("");
+    }
+    return;
+  }
   if (wave >= 2) {
     const int64_t base = (b0 - 1) * N_JOINTS, end = sh.B * N_JOINTS;
     for (int i = (int)threadIdx.x - 128; i < ADJ_Q_ROWS * N_JOINTS; i += 128) {
@@ -1394,7 +1422,9 @@ __constant__ float c_alpha[MAX_LS] = {1.0f, 0.5f, 0.25f, 0.125f};
 // one-configuration trajectories (n = 7: eight trajectories per wavefront, one variable per lane).
 template <int OPT_NE, int GL>
 __global__ __launch_bounds__(256) void k_optimizer(OptArgs o, TV J, const double* __restrict__ cost_in,
-                                                   float* __restrict__ q_cand, int mode) {
+                                                   float* __restrict__ q_cand, int mode, WsCheck ck) {
+  // a workspace that does not hold the expected forward pass leaves the optimiser state untouched
+  if (!ws_current(ck)) return;
   const int lane = GL == 64 ? (threadIdx.x & 63) : (threadIdx.x & (GL - 1));
   const int tr = GL == 64 ? blockIdx.x * 4 + uniform(threadIdx.x >> 6) : (blockIdx.x * 256 + threadIdx.x) / GL;
   if (tr >= o.n_traj) return;  // a whole group
@@ -1808,13 +1838,13 @@ hipError_t launch_sphere_cost_blk(hipStream_t s, const RobotArgs& R, const World
 
 hipError_t launch_reduce(hipStream_t s, const TV& D, const float* selfc, const float* boundc, const float* sweptc,
                          const float* posec, const float* q, double* cost_traj, float* cost_cfg, const ShapeArgs& sh,
-                         const CostArgs& cp, int n_s) {
+                         const CostArgs& cp, int n_s, const WsStamp& st) {
   if (sh.T == 1)
     hipLaunchKernelGGL(k_reduce_t1, dim3(blocks_for(sh.B, 256)), dim3(256), 0, s, D, selfc, boundc, sweptc, posec,
-                       cost_traj, cost_cfg, sh, cp, n_s);
+                       cost_traj, cost_cfg, sh, cp, n_s, st);
   else
     hipLaunchKernelGGL(k_reduce, dim3(blocks_for(sh.n_tc, 4)), dim3(256), 0, s, D, selfc, boundc, sweptc, posec, q,
-                       cost_traj, cost_cfg, sh, cp, n_s);
+                       cost_traj, cost_cfg, sh, cp, n_s, st);
   return hipGetLastError();
 }
 
@@ -1835,13 +1865,13 @@ hipError_t launch_swept(hipStream_t s, const RobotArgs& R, const WorldArgs& W, c
 
 hipError_t launch_adjoint(hipStream_t s, const float* q, const RobotArgs& R, const TV& L, const TV& G, const TV& X,
                           const TV& J, const double* up, float* grad_q, const ShapeArgs& sh, const CostArgs& cp,
-                          int recompute, const float* goal) {
+                          int recompute, const float* goal, const WsCheck& ck) {
   const dim3 grid(blocks_for(sh.B, 64)), block(256);
   switch (G.fmt) {
 #define VAPR_ADJ_CASE(F) \
   case F:                                                                                                     \
-    if (X.P) hipLaunchKernelGGL((k_adjoint<F, true>), grid, block, 0, s, q, R, L, G, X, J, up, grad_q, sh, cp, recompute, goal); \
-    else hipLaunchKernelGGL((k_adjoint<F, false>), grid, block, 0, s, q, R, L, G, X, J, up, grad_q, sh, cp, recompute, goal); \
+    if (X.P) hipLaunchKernelGGL((k_adjoint<F, true>), grid, block, 0, s, q, R, L, G, X, J, up, grad_q, sh, cp, recompute, goal, ck); \
+    else hipLaunchKernelGGL((k_adjoint<F, false>), grid, block, 0, s, q, R, L, G, X, J, up, grad_q, sh, cp, recompute, goal, ck); \
     break;
     VAPR_ADJ_CASE(F32) VAPR_ADJ_CASE(F16) VAPR_ADJ_CASE(BF16) VAPR_ADJ_CASE(E4M3) VAPR_ADJ_CASE(E5M2)
     VAPR_ADJ_CASE(E3M2) VAPR_ADJ_CASE(E2M1)
@@ -1852,16 +1882,16 @@ hipError_t launch_adjoint(hipStream_t s, const float* q, const RobotArgs& R, con
 }
 
 hipError_t launch_optimizer(hipStream_t s, const OptArgs& o, const TV& J, const double* cost_in, float* q_cand,
-                            int mode) {
+                            int mode, const WsCheck& ck) {
   if (o.T == 1) {
     hipLaunchKernelGGL((k_optimizer<1, 8>), dim3(blocks_for(o.n_traj, 32)), dim3(256), 0, s, o, J, cost_in, q_cand,
-                       mode);
+                       mode, ck);
     return hipGetLastError();
   }
   const dim3 grid(blocks_for(o.n_traj, 4)), block(256);
   switch ((o.T * N_JOINTS + 63) / 64) {
 #define VAPR_OPT_CASE(NE) \
-  case NE: hipLaunchKernelGGL((k_optimizer<NE, 64>), grid, block, 0, s, o, J, cost_in, q_cand, mode); break;
+  case NE: hipLaunchKernelGGL((k_optimizer<NE, 64>), grid, block, 0, s, o, J, cost_in, q_cand, mode, ck); break;
     VAPR_OPT_CASE(1) VAPR_OPT_CASE(2) VAPR_OPT_CASE(3) VAPR_OPT_CASE(4) VAPR_OPT_CASE(5) VAPR_OPT_CASE(6)
     VAPR_OPT_CASE(7)
 #undef VAPR_OPT_CASE
@@ -1929,6 +1959,60 @@ hipError_t launch_repack(hipStream_t s, int tensor, const TV& t, int64_t B, int 
     hipLaunchKernelGGL(k_import, dim3(blocks_for(B * n_slots, 256)), dim3(256), 0, s, t, tensor, B, ecfg, n_slots,
                        n_s, (const uint8_t*)flat);
   }
+  return hipGetLastError();
+}
+
+}  // namespace vapr
+
+namespace vapr {
+
+__global__ void k_ws_stamp(WsStamp st) { ws_stamp(st); }
+
+// Collision-free test of each configuration of a forward pass, from its stored tensors: every
+// sphere's activation depth below eta (clearance > 0), no joint beyond its limits (bound cost 0) and
+// every self pair apart (|p_a - p_b| - r_a - r_b > 0).  One configuration per thread.
+__global__ __launch_bounds__(256) void k_collision_free(RobotArgs R, TV S, TV D, const float* __restrict__ boundc,
+                                                        float eta, int64_t B, int32_t* __restrict__ out) {
+  const int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (b >= B) return;
+  const int n_s = R.n_s;
+  bool ok = boundc[b] == 0.f;
+  for (int g = 0; g < R.n_groups && ok; ++g) {
+    float dv[SPH_GROUP];
+    load_group<SPH_GROUP>(D, b, g, dv);
+#pragma unroll
+    for (int i = 0; i < SPH_GROUP; ++i)
+      if (g * SPH_GROUP + i < n_s && !(dv[i] < eta)) ok = false;
+  }
+  for (int a = 0; a < n_s && ok; ++a) {
+    const int j0 = R.csr_off[a], j1 = R.csr_off[a + 1];
+    if (j0 == j1) continue;
+    const int ga = a / SPH_GROUP, ia = a % SPH_GROUP;
+    const float ax = load_elem<SPH_GROUP>(S, b, ga * 3 + 0, ia), ay = load_elem<SPH_GROUP>(S, b, ga * 3 + 1, ia),
+                az = load_elem<SPH_GROUP>(S, b, ga * 3 + 2, ia);
+    const float ra = R.sph[a].w;
+    for (int j = j0; j < j1 && ok; ++j) {
+      const int t = R.csr_nbr[j];
+      if (t < a) continue;  // each pair once
+      const int gt = t / SPH_GROUP, it = t % SPH_GROUP;
+      const float dx = ax - load_elem<SPH_GROUP>(S, b, gt * 3 + 0, it);
+      const float dy = ay - load_elem<SPH_GROUP>(S, b, gt * 3 + 1, it);
+      const float dz = az - load_elem<SPH_GROUP>(S, b, gt * 3 + 2, it);
+      const float dist = sqrtf(fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
+      if (!(dist - ra - R.sph[t].w > 0.f)) ok = false;
+    }
+  }
+  out[b] = ok ? 1 : 0;
+}
+
+hipError_t launch_collision_free(hipStream_t s, const RobotArgs& R, const TV& S, const TV& D, const float* boundc,
+                                 float eta, int64_t B, int32_t* out) {
+  hipLaunchKernelGGL(k_collision_free, dim3(blocks_for(B, 256)), dim3(256), 0, s, R, S, D, boundc, eta, B, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_ws_stamp(hipStream_t s, const WsStamp& st) {
+  hipLaunchKernelGGL(k_ws_stamp, dim3(1), dim3(64), 0, s, st);
   return hipGetLastError();
 }
 

@@ -98,13 +98,19 @@ hipError_t launch_swept(hipStream_t s, const RobotArgs& R, const WorldArgs& W, c
 // sweptc, posec: per-configuration swept and pose costs added to the configuration cost, or null
 hipError_t launch_reduce(hipStream_t s, const TV& D, const float* selfc, const float* boundc, const float* sweptc,
                          const float* posec, const float* q, double* cost_traj, float* cost_cfg, const ShapeArgs& sh,
-                         const CostArgs& cp, int n_s);
+                         const CostArgs& cp, int n_s, const WsStamp& st);
 // X.P == 0: no swept gradient; goal null: no pose cost
 hipError_t launch_adjoint(hipStream_t s, const float* q, const RobotArgs& R, const TV& L, const TV& G, const TV& X,
                           const TV& J, const double* up, float* grad_q, const ShapeArgs& sh, const CostArgs& cp,
-                          int recompute, const float* goal);
+                          int recompute, const float* goal, const WsCheck& ck);
 hipError_t launch_optimizer(hipStream_t s, const OptArgs& o, const TV& J, const double* cost_in, float* q_cand,
-                            int mode);
+                            int mode, const WsCheck& ck);
+// header write of a workspace outside a forward pass (stage-wise imports, resets)
+hipError_t launch_ws_stamp(hipStream_t s, const WsStamp& st);
+// per configuration 1 if collision-free (every clearance and self-pair clearance > 0, no joint beyond
+// its limits) from a forward pass's stored S, D and bound cost, else 0
+hipError_t launch_collision_free(hipStream_t s, const RobotArgs& R, const TV& S, const TV& D, const float* boundc,
+                                 float eta, int64_t B, int32_t* out);
 hipError_t launch_quantize(hipStream_t s, int fmt, float inv, const float* in, uint8_t* out, int64_t n);
 hipError_t launch_round_exmy(hipStream_t s, int E, int M, float inv, float scale, const float* in, float* out,
                              int64_t n);

@@ -14,7 +14,11 @@
 //   J  one group of 8 values (7 joints + a zero)          dw(8) planes
 //   X  swept sphere gradient, like S (only with the swept term on)
 // followed by FP32 arrays [Bp]: self cost, bound cost (then X), with the swept term the swept cost,
-// and with goal poses the pose cost.  Regions are 256-byte aligned.
+// and with goal poses the pose cost.  Regions are 256-byte aligned and follow a 256-byte header
+// (WsHeader) that the last kernel of every forward pass writes: which context and which of its
+// forward passes filled the workspace, under what shape, precision, robot and cost parameters.  The
+// consumers of a forward pass (adjoint, optimiser) compare the context id and pass number with the
+// ones the host expects before they read anything else.
 #pragma once
 #include <stddef.h>
 #include <stdint.h>
@@ -57,6 +61,32 @@ enum { T_L = 0, T_S = 1, T_D = 2, T_G = 3, T_J = 4, T_X = 5 };
 // byte-offset slots of the FP32 arrays and of X
 enum { OFF_SELF = 5, OFF_BOUND = 6, OFF_X = 7, OFF_SWEPT = 8, OFF_POSE = 9 };
 
+// Header words (uint64 each) at the start of a workspace.
+enum {
+  WH_MAGIC = 0,     // WS_MAGIC
+  WH_CTX = 1,       // id of the context that ran the forward pass (never 0)
+  WH_GEN = 2,       // that context's forward-pass number (never 0)
+  WH_B = 3,         // configurations
+  WH_SHAPE = 4,     // T | n_ls << 16 | n_s << 24
+  WH_PREC = 5,      // hash of the precision assignment (formats, scales, pose mode, swept samples)
+  WH_ROBOT = 6,     // robot generation of the context
+  WH_PARAMS = 7,    // cost-parameter generation of the context
+  WH_WORDS = 8
+};
+constexpr uint64_t WS_MAGIC = 0x3130535752504156ull;  // "VAPRWS01" little-endian
+constexpr size_t WS_HEADER_BYTES = 256;
+
+struct WsStamp {  // written by the forward pass: hdr[i] = w[i]
+  uint64_t* hdr;
+  uint64_t w[WH_WORDS];
+};
+
+struct WsCheck {  // read by the consumers of a forward pass
+  const uint64_t* hdr;
+  uint64_t ctx, gen;    // expected WH_CTX / WH_GEN
+  uint32_t* status;     // bit 0 set when the header does not match (stale workspace)
+};
+
 struct Layout {
   int64_t B, Bp, nblk;
   int n_s, n_groups;
@@ -80,7 +110,7 @@ inline Layout make_layout(int64_t B, int n_s, const PrecisionCfg& pc) {
   L.P[T_G] = L.n_groups * 3 * group_dwords(pc.t[T_G].fmt, SPH_GROUP);
   L.P[T_J] = group_dwords(pc.t[T_J].fmt, J_GROUP);
   L.P[T_X] = pc.sweep ? L.n_groups * 3 * group_dwords(pc.t[T_X].fmt, SPH_GROUP) : 0;
-  size_t o = 0;
+  size_t o = WS_HEADER_BYTES;
   for (int i = 0; i < 5; ++i) {
     L.off[i] = o;
     o += align256((size_t)L.P[i] * (size_t)L.Bp * 4);

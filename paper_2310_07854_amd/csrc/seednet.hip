@@ -394,6 +394,21 @@ __global__ __launch_bounds__(256) void k_seed_traj(int n, const float* __restric
   out[i] = (t == 0 || t == SEED_T - 1) ? (t == 0 ? s0 : g0) : line + y[i];
 }
 
+// inverse of k_seed_traj over m trajectories per problem: dev = traj - line, with the same line
+// (start and goal exactly at the ends)
+__global__ __launch_bounds__(256) void k_seed_dev(int64_t total, int m, const float* __restrict__ traj,
+                                                  const float* __restrict__ start, const float* __restrict__ goal,
+                                                  float* __restrict__ dev) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= total) return;
+  const int64_t r = i / ((int64_t)m * SEED_TRAJ);
+  const int k = (int)(i % SEED_TRAJ);
+  const int j = k % SEED_J, t = k / SEED_J;
+  const float s0 = start[r * SEED_J + j], g0 = goal[r * SEED_J + j];
+  const float line = fmaf(g0 - s0, (float)t / (float)(SEED_T - 1), s0);
+  dev[i] = traj[i] - (t == 0 ? s0 : (t == SEED_T - 1 ? g0 : line));
+}
+
 // ---- loss -------------------------------------------------------------------------------------------
 
 // one wavefront per problem; lane = slot * 8 + target
@@ -543,6 +558,13 @@ hipError_t launch_gemm_bf16(hipStream_t s, const GemmArgs& g, bool a_k, bool b_n
 
 hipError_t launch_seed_traj(hipStream_t s, int n, const float* y, const float* start, const float* goal, float* out) {
   hipLaunchKernelGGL(k_seed_traj, dim3(nblocks((int64_t)n * SEED_OUT, 256)), dim3(256), 0, s, n, y, start, goal, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_seed_dev(hipStream_t s, int n, int m, const float* traj, const float* start, const float* goal,
+                           float* dev) {
+  const int64_t total = (int64_t)n * m * SEED_TRAJ;
+  hipLaunchKernelGGL(k_seed_dev, dim3(nblocks(total, 256)), dim3(256), 0, s, total, m, traj, start, goal, dev);
   return hipGetLastError();
 }
 

@@ -45,6 +45,8 @@ hipError_t launch_features(hipStream_t s, int n, const float* start, const float
                            uint16_t* x);
 hipError_t launch_gemm_bf16(hipStream_t s, const GemmArgs& g, bool a_k, bool b_n);
 hipError_t launch_seed_traj(hipStream_t s, int n, const float* y, const float* start, const float* goal, float* out);
+hipError_t launch_seed_dev(hipStream_t s, int n, int m, const float* traj, const float* start, const float* goal,
+                           float* dev);
 hipError_t launch_seed_loss(hipStream_t s, int n, const float* y, const float* tgt, const float* valid, float coef,
                             double* per_problem, int32_t* assign, float* dy, double inv_valid, double* loss);
 hipError_t launch_column_sum(hipStream_t s, int M, int N, const float* X, int64_t ldx, float* out);

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -22,12 +23,17 @@ namespace {
 
 thread_local std::string g_thread_err;
 
+// What the host knows of a workspace: the forward pass that last completed into it.  The same
+// context id and pass number are in the workspace's header, written by that pass's last kernel;
+// the backward and optimiser kernels compare the two before reading anything else.
 struct WsRecord {
   int n_worlds, tpw, T, n_ls;
   int64_t B;
   PrecisionCfg prec;
-  uint64_t robot_gen;
+  uint64_t robot_gen, params_gen, gen;
 };
+
+std::atomic<uint64_t> g_next_ctx_uid{1};
 
 struct ProfEvent {
   int id;
@@ -39,6 +45,10 @@ struct ProfEvent {
 struct vapr_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
+  uint64_t uid = 0;        // process-unique context id (workspace headers)
+  uint64_t fwd_gen = 0;    // forward passes issued (workspace headers)
+  uint64_t params_gen = 0; // cost-parameter changes
+  uint32_t* d_status = nullptr;  // device flag: a consumer kernel met a workspace it was not issued for
   // robot
   bool has_robot = false;
   uint64_t robot_gen = 0;
@@ -194,6 +204,66 @@ bool same_prec(const PrecisionCfg& a, const PrecisionCfg& b) {
         a.t[i].xm != b.t[i].xm)
       return false;
   return a.recompute == b.recompute && a.sweep == b.sweep && a.pose == b.pose;
+}
+
+// 64-bit FNV-1a over the fields same_prec compares (the workspace header's precision tag)
+uint64_t prec_tag(const PrecisionCfg& p) {
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&h](int64_t v) {
+    for (int i = 0; i < 8; ++i) {
+      h ^= (uint64_t)((v >> (8 * i)) & 0xff);
+      h *= 1099511628211ull;
+    }
+  };
+  for (int i = 0; i < 6; ++i) {
+    mix(p.t[i].fmt);
+    mix(p.t[i].scale_exp);
+    mix(p.t[i].xe);
+    mix(p.t[i].xm);
+  }
+  mix(p.recompute);
+  mix(p.sweep);
+  mix(p.pose);
+  return h;
+}
+
+// The record of a forward pass about to be written into ws, and the header words that go with it.
+WsRecord new_record(vapr_ctx* ctx, int n_worlds, int tpw, int T, int n_ls, int64_t B) {
+  return WsRecord{n_worlds, tpw, T, n_ls, B, ctx->prec, ctx->robot_gen, ctx->params_gen, ++ctx->fwd_gen};
+}
+
+WsStamp stamp_of(const vapr_ctx* ctx, void* ws, const WsRecord& r) {
+  WsStamp st{};
+  st.hdr = static_cast<uint64_t*>(ws);
+  st.w[WH_MAGIC] = WS_MAGIC;
+  st.w[WH_CTX] = ctx->uid;
+  st.w[WH_GEN] = r.gen;
+  st.w[WH_B] = (uint64_t)r.B;
+  st.w[WH_SHAPE] = (uint64_t)r.T | (uint64_t)r.n_ls << 16 | (uint64_t)ctx->n_s << 24;
+  st.w[WH_PREC] = prec_tag(r.prec);
+  st.w[WH_ROBOT] = r.robot_gen;
+  st.w[WH_PARAMS] = r.params_gen;
+  return st;
+}
+
+WsCheck check_of(const vapr_ctx* ctx, const void* ws, const WsRecord& r) {
+  return WsCheck{static_cast<const uint64_t*>(ws), ctx->uid, r.gen, ctx->d_status};
+}
+
+// the record of ws if it holds a forward pass under the context's current robot, precision and cost
+// parameters; otherwise a failure message
+const WsRecord* current_record(const vapr_ctx* ctx, const void* ws, const char** why) {
+  auto it = ctx->ws.find(ws);
+  if (it == ctx->ws.end()) {
+    *why = "workspace holds no forward pass of this context";
+    return nullptr;
+  }
+  const WsRecord& r = it->second;
+  if (!same_prec(r.prec, ctx->prec)) *why = "precision changed since the forward pass";
+  else if (r.robot_gen != ctx->robot_gen) *why = "robot changed since the forward pass";
+  else if (r.params_gen != ctx->params_gen) *why = "cost parameters changed since the forward pass";
+  else return &r;
+  return nullptr;
 }
 
 TV tensor_view(void* ws, const Layout& L, const PrecisionCfg& pc, int t) {
@@ -405,10 +475,11 @@ int run_fwd(vapr_ctx* ctx, int first, int n_worlds, int tpw, int T, int n_ls, co
   const Layout L = make_layout(B, ctx->n_s, ctx->prec);
   if (ws_bytes < L.bytes) return fail(ctx, VAPR_E_INVALID, "workspace too small");
   if (first >= 2) {
-    auto it = ctx->ws.find(ws);
-    if (it == ctx->ws.end() || it->second.B != B || !same_prec(it->second.prec, ctx->prec) ||
-        it->second.robot_gen != ctx->robot_gen)
-      return fail(ctx, VAPR_E_STATE, "workspace does not hold this shape at the current precision");
+    const char* why = nullptr;
+    const WsRecord* r = current_record(ctx, ws, &why);
+    if (!r) return fail(ctx, VAPR_E_STATE, why);
+    if (r->B != B || r->T != T || r->n_ls != n_ls)
+      return fail(ctx, VAPR_E_STATE, "workspace holds a forward pass of another shape");
   }
   const ShapeArgs sh = shape_args(n_worlds, tpw, T, n_ls);
   if (!ctx->pairs_valid && (st = build_pair_table(ctx))) return st;
@@ -422,6 +493,11 @@ int run_fwd(vapr_ctx* ctx, int first, int n_worlds, int tpw, int T, int n_ls, co
   if (ctx->prec.pose && n_worlds > ctx->n_goals)
     return fail(ctx, VAPR_E_INVALID, "n_worlds exceeds the uploaded goal poses");
   hipStream_t s = ctx->stream;
+  // from here on the workspace's old contents are being replaced: it holds no usable forward pass
+  // until this one has been queued completely
+  ctx->ws.erase(ws);
+  const WsRecord rec = new_record(ctx, n_worlds, tpw, T, n_ls, B);
+  const WsStamp stamp = stamp_of(ctx, ws, rec);
   if (first <= 1) {
     const CostArgs cpk = ctx->params;
     const float* goal = ctx->prec.pose ? ctx->d_goal : nullptr;
@@ -455,10 +531,12 @@ int run_fwd(vapr_ctx* ctx, int first, int n_worlds, int tpw, int T, int n_ls, co
   const CostArgs cp = ctx->params;
   const int n_s = ctx->n_s;
   st = timed(ctx, K_REDUCE,
-             [&] { return launch_reduce(s, tD, selfc, boundc, sweptc, posec, q, cost_traj, cost_cfg, sh, cp, n_s); },
+             [&] {
+               return launch_reduce(s, tD, selfc, boundc, sweptc, posec, q, cost_traj, cost_cfg, sh, cp, n_s, stamp);
+             },
              "k_reduce launch");
   if (st) return st;
-  ctx->ws[ws] = WsRecord{n_worlds, tpw, T, n_ls, B, ctx->prec, ctx->robot_gen};
+  ctx->ws[ws] = rec;
   return VAPR_OK;
 }
 
@@ -483,11 +561,10 @@ int check_opt(vapr_ctx* ctx, const vapr_lbfgs_state* st, const void* ws, int ini
   if (st->T < 1 || st->T > MAX_OPT_T || st->n_ls < 1 || st->n_ls > MAX_LS || st->m < 1 || st->m > MAX_HIST ||
       st->n_traj < 1 || !(st->max_step > 0.f) || !std::isfinite(st->max_step))
     return fail(ctx, VAPR_E_INVALID, "optimiser shape out of range");
-  auto it = ctx->ws.find(ws);
-  if (it == ctx->ws.end()) return fail(ctx, VAPR_E_STATE, "workspace holds no forward pass");
-  const WsRecord& r = it->second;
-  if (!same_prec(r.prec, ctx->prec) || r.robot_gen != ctx->robot_gen)
-    return fail(ctx, VAPR_E_STATE, "workspace was filled under another precision or robot");
+  const char* why = nullptr;
+  const WsRecord* rp = current_record(ctx, ws, &why);
+  if (!rp) return fail(ctx, VAPR_E_STATE, why);
+  const WsRecord& r = *rp;
   if ((int64_t)r.n_worlds * r.tpw != st->n_traj || r.T != st->T || r.n_ls != (init ? 1 : st->n_ls))
     return fail(ctx, VAPR_E_STATE, "workspace shape does not match the optimiser state");
   *rec = r;
@@ -526,7 +603,8 @@ int run_opt(vapr_ctx* ctx, const vapr_lbfgs_state* st, const void* ws, size_t ws
   if (ws_bytes < L.bytes) return fail(ctx, VAPR_E_INVALID, "workspace too small");
   const TV tJ = tensor_view(const_cast<void*>(ws), L, ctx->prec, T_J);
   const OptArgs o = opt_args(st);
-  return timed(ctx, K_OPT, [&] { return launch_optimizer(ctx->stream, o, tJ, cost, q_cand, mode); },
+  const WsCheck ck = check_of(ctx, ws, rec);
+  return timed(ctx, K_OPT, [&] { return launch_optimizer(ctx->stream, o, tJ, cost, q_cand, mode, ck); },
                "k_optimizer launch");
 }
 
@@ -558,9 +636,19 @@ int vapr_create(vapr_ctx** out, int device, void* hip_stream) {
   if (device < 0 || device >= n) return fail(nullptr, VAPR_E_INVALID, "device index out of range");
   e = hipSetDevice(device);
   if (e != hipSuccess) return hip_fail(nullptr, e, "hipSetDevice");
+  uint32_t* status = nullptr;
+  e = hipMalloc((void**)&status, sizeof(uint32_t));
+  if (e != hipSuccess) return fail(nullptr, VAPR_E_OOM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  e = hipMemset(status, 0, sizeof(uint32_t));
+  if (e != hipSuccess) {
+    (void)hipFree(status);
+    return hip_fail(nullptr, e, "hipMemset");
+  }
   vapr_ctx* c = new vapr_ctx();
   c->device = device;
   c->stream = static_cast<hipStream_t>(hip_stream);
+  c->uid = g_next_ctx_uid.fetch_add(1);
+  c->d_status = status;
   vapr_precision p{};
   p.link_poses = p.sphere_pos = p.sphere_dist = p.sphere_grad = p.joint_grad = {VAPR_F32, 0};
   c->prec = to_cfg(p);
@@ -576,6 +664,7 @@ int vapr_destroy(vapr_ctx* ctx) {
   (void)hipFree(ctx->d_box);
   (void)hipFree(ctx->d_goal);
   (void)hipFree(ctx->d_grid);
+  (void)hipFree(ctx->d_status);
   for (auto& pe : ctx->prof_live) {
     (void)hipEventDestroy(pe.start);
     (void)hipEventDestroy(pe.stop);
@@ -778,6 +867,7 @@ int vapr_set_cost_params(vapr_ctx* ctx, const vapr_cost_params* p) {
   ctx->params = CostArgs{p->eta,       p->w_coll,   p->w_self,     p->w_bound,    p->w_smooth,
                          p->swept_steps, p->w_swept, p->w_goal_pos, p->w_goal_rot};
   ctx->prec.sweep = p->swept_steps;
+  ctx->params_gen++;
   ctx->grid_valid = false;
   ctx->pairs_valid = false;
   return VAPR_OK;
@@ -840,11 +930,10 @@ int vapr_cost_bwd(vapr_ctx* ctx, const float* q, void* ws, size_t ws_bytes, cons
                   float* grad_q) {
   if (!ctx) return fail(nullptr, VAPR_E_INVALID, "null context");
   if (!q || !ws) return fail(ctx, VAPR_E_INVALID, "null pointer");
-  auto it = ctx->ws.find(ws);
-  if (it == ctx->ws.end()) return fail(ctx, VAPR_E_STATE, "workspace holds no forward pass");
-  const WsRecord r = it->second;
-  if (!same_prec(r.prec, ctx->prec)) return fail(ctx, VAPR_E_STATE, "precision changed since the forward pass");
-  if (r.robot_gen != ctx->robot_gen) return fail(ctx, VAPR_E_STATE, "robot changed since the forward pass");
+  const char* why = nullptr;
+  const WsRecord* rp = current_record(ctx, ws, &why);
+  if (!rp) return fail(ctx, VAPR_E_STATE, why);
+  const WsRecord r = *rp;
   const Layout L = make_layout(r.B, ctx->n_s, ctx->prec);
   if (ws_bytes < L.bytes) return fail(ctx, VAPR_E_INVALID, "workspace too small");
   const ShapeArgs sh = shape_args(r.n_worlds, r.tpw, r.T, r.n_ls);
@@ -855,9 +944,11 @@ int vapr_cost_bwd(vapr_ctx* ctx, const float* q, void* ws, size_t ws_bytes, cons
   const int rec = ctx->prec.recompute;
   const float* goal = ctx->prec.pose ? ctx->d_goal : nullptr;
   if (goal && r.n_worlds > ctx->n_goals) return fail(ctx, VAPR_E_STATE, "goal poses changed since the forward pass");
+  const WsCheck ck = check_of(ctx, ws, r);
   return timed(ctx, K_ADJOINT,
                [&] {
-                 return launch_adjoint(ctx->stream, q, R, tL, tG, tX, tJ, grad_cost_traj, grad_q, sh, cp, rec, goal);
+                 return launch_adjoint(ctx->stream, q, R, tL, tG, tX, tJ, grad_cost_traj, grad_q, sh, cp, rec, goal,
+                                       ck);
                },
                "k_adjoint launch");
 }
@@ -990,6 +1081,15 @@ int vapr_seed_loss(int n, const float* y, const float* targets, const float* val
   return e == hipSuccess ? VAPR_OK : hip_fail(nullptr, e, "k_seed_loss launch");
 }
 
+int vapr_seed_deviations(int n, int m, const float* traj, const float* start, const float* goal, float* dev,
+                         void* hip_stream) {
+  if (n < 0 || m < 1) return fail(nullptr, VAPR_E_INVALID, "n < 0 or m < 1");
+  if (n == 0) return VAPR_OK;
+  if (!traj || !start || !goal || !dev) return fail(nullptr, VAPR_E_INVALID, "null pointer");
+  hipError_t e = launch_seed_dev(static_cast<hipStream_t>(hip_stream), n, m, traj, start, goal, dev);
+  return e == hipSuccess ? VAPR_OK : hip_fail(nullptr, e, "k_seed_dev launch");
+}
+
 int vapr_column_sum(int M, int N, const float* X, int64_t ldx, float* out, void* hip_stream) {
   if (M < 1 || N < 1 || ldx < N) return fail(nullptr, VAPR_E_INVALID, "shape");
   if (!X || !out) return fail(nullptr, VAPR_E_INVALID, "null pointer");
@@ -1024,9 +1124,11 @@ static int ws_io(vapr_ctx* ctx, int n_worlds, int tpw, int T, int n_ls, void* ws
   const Layout L = make_layout(B, ctx->n_s, ctx->prec);
   if (ws_bytes < L.bytes) return fail(ctx, VAPR_E_INVALID, "workspace too small");
   if (direction == 0) {
-    auto it = ctx->ws.find(ws);
-    if (it == ctx->ws.end() || it->second.B != B || !same_prec(it->second.prec, ctx->prec))
-      return fail(ctx, VAPR_E_STATE, "workspace does not hold this shape at the current precision");
+    const char* why = nullptr;
+    const WsRecord* r = current_record(ctx, ws, &why);
+    if (!r) return fail(ctx, VAPR_E_STATE, why);
+    if (r->B != B || r->T != T || r->n_ls != n_ls)
+      return fail(ctx, VAPR_E_STATE, "workspace holds a forward pass of another shape");
   }
   if (tensor == VAPR_T_SELF_COST || tensor == VAPR_T_BOUND_COST || tensor == VAPR_T_SWEPT_COST ||
       tensor == VAPR_T_POSE_COST) {
@@ -1059,7 +1161,14 @@ static int ws_io(vapr_ctx* ctx, int n_worlds, int tpw, int T, int n_ls, void* ws
                "repack launch");
   }
   if (st) return st;
-  if (direction == 1) ctx->ws[ws] = WsRecord{n_worlds, tpw, T, n_ls, B, ctx->prec, ctx->robot_gen};
+  if (direction == 1) {
+    // an imported tensor stands for a forward pass: a new pass number in the header and the record
+    ctx->ws.erase(ws);
+    const WsRecord rec = new_record(ctx, n_worlds, tpw, T, n_ls, B);
+    const hipError_t e = launch_ws_stamp(ctx->stream, stamp_of(ctx, ws, rec));
+    if (e != hipSuccess) return hip_fail(ctx, e, "k_ws_stamp launch");
+    ctx->ws[ws] = rec;
+  }
   return VAPR_OK;
 }
 
@@ -1071,6 +1180,60 @@ int vapr_ws_export(vapr_ctx* ctx, int n_worlds, int tpw, int T, int n_ls, const 
 int vapr_ws_import(vapr_ctx* ctx, int n_worlds, int tpw, int T, int n_ls, void* ws, size_t ws_bytes, int tensor,
                    const void* in, size_t in_bytes) {
   return ws_io(ctx, n_worlds, tpw, T, n_ls, ws, ws_bytes, tensor, const_cast<void*>(in), in_bytes, 1);
+}
+
+int vapr_ws_reset(vapr_ctx* ctx, void* ws, size_t ws_bytes) {
+  if (!ctx) return fail(nullptr, VAPR_E_INVALID, "null context");
+  if (!ws) return fail(ctx, VAPR_E_INVALID, "null pointer");
+  if (ws_bytes < WS_HEADER_BYTES) return fail(ctx, VAPR_E_INVALID, "workspace smaller than its header");
+  // forget every record inside the buffer: their memory has been handed out again
+  const char* lo = static_cast<const char*>(ws);
+  const char* hi = lo + ws_bytes;
+  for (auto it = ctx->ws.begin(); it != ctx->ws.end();) {
+    const char* p = static_cast<const char*>(it->first);
+    if (p >= lo && p < hi) it = ctx->ws.erase(it);
+    else ++it;
+  }
+  WsStamp st{};
+  st.hdr = static_cast<uint64_t*>(ws);
+  const hipError_t e = launch_ws_stamp(ctx->stream, st);
+  return e == hipSuccess ? VAPR_OK : hip_fail(ctx, e, "k_ws_stamp launch");
+}
+
+int vapr_collision_free(vapr_ctx* ctx, int n_worlds, int tpw, int T, int n_ls, const void* ws, size_t ws_bytes,
+                        int32_t* free_cfg) {
+  int64_t B;
+  int st = check_shape(ctx, n_worlds, tpw, T, n_ls, &B);
+  if (st) return st;
+  if (!ws || !free_cfg) return fail(ctx, VAPR_E_INVALID, "null pointer");
+  const Layout L = make_layout(B, ctx->n_s, ctx->prec);
+  if (ws_bytes < L.bytes) return fail(ctx, VAPR_E_INVALID, "workspace too small");
+  const char* why = nullptr;
+  const WsRecord* r = current_record(ctx, ws, &why);
+  if (!r) return fail(ctx, VAPR_E_STATE, why);
+  if (r->B != B || r->T != T || r->n_ls != n_ls)
+    return fail(ctx, VAPR_E_STATE, "workspace holds a forward pass of another shape");
+  void* w = const_cast<void*>(ws);
+  const TV tS = tensor_view(w, L, ctx->prec, T_S), tD = tensor_view(w, L, ctx->prec, T_D);
+  const float* boundc = reinterpret_cast<const float*>(static_cast<const char*>(ws) + L.off[OFF_BOUND]);
+  const RobotArgs R = robot_args(ctx);
+  const float eta = ctx->params.eta;
+  const hipError_t e = launch_collision_free(ctx->stream, R, tS, tD, boundc, eta, B, free_cfg);
+  return e == hipSuccess ? VAPR_OK : hip_fail(ctx, e, "k_collision_free launch");
+}
+
+int vapr_sync(vapr_ctx* ctx) {
+  if (!ctx) return fail(nullptr, VAPR_E_INVALID, "null context");
+  VAPR_HIP(ctx, hipSetDevice(ctx->device));
+  VAPR_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  uint32_t flag = 0;
+  VAPR_HIP(ctx, hipMemcpy(&flag, ctx->d_status, sizeof flag, hipMemcpyDeviceToHost));
+  if (!flag) return VAPR_OK;
+  const uint32_t zero = 0;
+  VAPR_HIP(ctx, hipMemcpy(ctx->d_status, &zero, sizeof zero, hipMemcpyHostToDevice));
+  return fail(ctx, VAPR_E_STATE,
+              "a backward or optimiser call met a workspace that no longer held the forward pass it was issued "
+              "for (its gradients were written as NaN, optimiser state was left unchanged)");
 }
 
 int vapr_profile_enable(vapr_ctx* ctx, int enable) {

@@ -225,8 +225,8 @@ class Search:
 class OptimizerTask:
     """Success rate of an assignment on synthetic planning problems: every problem's seeds go
     through `iters` optimiser iterations with the assignment's stored-tensor types, and a problem
-    succeeds when one of its final trajectories is collision-free (no sphere penetrates a cuboid,
-    joint limits hold, at every timestep, checked in FP32)."""
+    succeeds when one of its final trajectories is collision-free (no sphere penetrates a cuboid, no
+    self pair overlaps, joint limits hold, at every timestep, checked in FP32)."""
 
     def __init__(self, ctx, worlds, start, goal, x0, iters: int = 40, n_ls: int = 4):
         import torch

@@ -3,7 +3,7 @@
 Problems come as arrays: worlds (already uploaded to the context, one per problem), start and goal
 [W, 7], and initial trajectories [W, S, T, 7].
   endpoints_free      start and goal are collision-free: no sphere penetrates a cuboid (clearance
-                      > 0, i.e. activation depth below eta) and the joint limits hold
+                      > 0), no self pair overlaps and the joint limits hold
   trajectories_free   every timestep of a trajectory is collision-free
   solve               run the optimiser from the initial trajectories; final trajectories and costs,
                       collision-free flags and, per problem, the first iteration at which any of its
@@ -22,18 +22,15 @@ import torch
 
 from .context import Context, Shape
 from .optim import TrajectoryOptimizer
-from .seeding import N_SEEDS, SeedNet, features
+from .seeding import N_SEEDS, SeedNet, deviations, features
 
 
 def configs_free(ctx: Context, q: torch.Tensor, shape: Shape) -> torch.Tensor:
-    """[B] bool: no sphere penetrates a cuboid (every activation depth d = eta - clearance stays
-    below eta, i.e. clearance > 0) and the joint limits hold (bound cost 0).  The context must store
-    D and the bound cost in FP32."""
+    """[B] bool: every sphere clears every cuboid, every self pair is apart and the joint limits
+    hold (the library's collision check of the forward pass)."""
     ws = ctx.new_workspace(shape)
     ctx.cost_fwd(q.reshape(-1, 7).contiguous(), shape, ws=ws)
-    d = ctx.ws_export("sphere_dist", ws, shape).view(torch.float32).view(shape.B, -1)
-    bound = ctx.ws_export("bound_cost", ws, shape).view(shape.B)
-    return (d.amax(dim=1) < ctx.cost_params["eta"]) & (bound == 0)
+    return ctx.collision_free(ws, shape)
 
 
 def endpoints_free(ctx: Context, start: torch.Tensor, goal: torch.Tensor) -> torch.Tensor:
@@ -79,12 +76,11 @@ def select_targets(sol: Dict[str, torch.Tensor], start: torch.Tensor, goal: torc
     W, S, T, _ = x.shape
     masked = torch.where(free, cost, torch.full_like(cost, float("inf")))
     order = torch.argsort(masked, dim=1, stable=True)[:, :N_SEEDS]
-    valid = torch.isfinite(torch.gather(masked, 1, order)).float()
-    tau = torch.linspace(0.0, 1.0, T, device=x.device).view(1, 1, T, 1)
-    line = start.view(W, 1, 1, 7) + (goal - start).view(W, 1, 1, 7) * tau
-    dev = x - line
+    ok = torch.isfinite(torch.gather(masked, 1, order))
+    dev = deviations(x.contiguous(), start.contiguous(), goal.contiguous())
     idx = order.view(W, N_SEEDS, 1, 1).expand(W, N_SEEDS, T, 7)
-    return torch.gather(dev, 1, idx) * valid.view(W, N_SEEDS, 1, 1), valid
+    picked = torch.gather(dev, 1, idx)
+    return torch.where(ok.view(W, N_SEEDS, 1, 1), picked, torch.zeros_like(picked)), ok.float()
 
 
 def train(net: SeedNet, data: Dict[str, torch.Tensor], steps: int, batch: int = 256, lr: float = 1e-3,

@@ -80,6 +80,18 @@ def column_sum(X: torch.Tensor, out: torch.Tensor) -> None:
     _call("vapr_column_sum", M, N, X.data_ptr(), X.stride(0), _dev(out, torch.float32, "out"), _stream_handle())
 
 
+def deviations(traj: torch.Tensor, start: torch.Tensor, goal: torch.Tensor) -> torch.Tensor:
+    """Deviations [n, m, 32, 7] of trajectories traj [n, m, 32, 7] from the straight line between
+    start and goal [n, 7] (the inverse of `trajectories`)."""
+    n, m = traj.shape[0], traj.shape[1]
+    if traj.shape[2:] != (T_SEED, N_J):
+        raise ValueError(f"trajectories must be [n, m, {T_SEED}, {N_J}]")
+    out = torch.empty_like(traj)
+    _call("vapr_seed_deviations", n, m, _dev(traj, torch.float32, "traj"), _dev(start, torch.float32, "start"),
+          _dev(goal, torch.float32, "goal"), out.data_ptr(), _stream_handle())
+    return out
+
+
 def trajectories(y: torch.Tensor, start: torch.Tensor, goal: torch.Tensor) -> torch.Tensor:
     """[n, 8, 32, 7] seeds: straight line plus the predicted deviation, endpoints exact."""
     n = y.shape[0]

@@ -44,7 +44,7 @@ def test_every_declared_symbol_is_exported():
 
 def test_host_side_validation():
     L, so = lib()
-    assert so.vapr_abi_version() == 2
+    assert so.vapr_abi_version() == 3
     assert so.vapr_status_string(L.E_STATE) == b"invalid state"
     assert so.vapr_packed_bytes(L.E3M2, 5) == 4
     assert so.vapr_packed_bytes(L.E2M1, 3) == 2
@@ -61,4 +61,6 @@ def test_host_side_validation():
     # context-taking calls reject a null context
     assert so.vapr_set_precision(None, None) == L.E_INVALID
     assert so.vapr_cost_bwd(None, None, None, 0, None, None) == L.E_INVALID
+    assert so.vapr_ws_reset(None, None, 0) == L.E_INVALID
+    assert so.vapr_sync(None) == L.E_INVALID
     assert so.vapr_destroy(None) == L.OK

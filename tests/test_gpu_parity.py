@@ -336,6 +336,61 @@ def test_error_paths():
     assert e.value.status == L.E_STATE
 
 
+def test_workspace_state():
+    """The workspace's forward-pass record: a freed workspace whose address torch hands out again is
+    not mistaken for the forward pass it held; changed cost parameters invalidate it; a header
+    overwritten behind the library's back
+    makes the backward kernel write NaN and vapr_sync report it; a call rejected for its arguments leaves
+    the record as it was."""
+    need_gpu()
+    from paper_2310_07854_amd import VaprError, _lib as L
+
+    wl = make_workload("tiny")
+    ctx = make_context(wl, {})
+    shape = shape_of(wl)
+    q = dev(wl.q, torch.float32)
+    ws = ctx.new_workspace(shape)
+    ctx.cost_fwd(q, shape, ws=ws)
+    good = ctx.cost_bwd(q, ws)
+    torch.cuda.synchronize()
+    assert torch.isfinite(good).all()
+    # recycled address: same size, same place under the caching allocator
+    ptr = ws.data_ptr()
+    del ws
+    ws2 = ctx.new_workspace(shape)
+    assert ws2.data_ptr() == ptr
+    with pytest.raises(VaprError) as e:
+        ctx.cost_bwd(q, ws2)
+    assert e.value.status == L.E_STATE
+    # cost parameters changed between the passes
+    ctx.cost_fwd(q, shape, ws=ws2)
+    ctx.set_cost_params(w_smooth=2.0)
+    with pytest.raises(VaprError) as e:
+        ctx.cost_bwd(q, ws2)
+    assert e.value.status == L.E_STATE
+    ctx.set_cost_params()
+    # a forward pass into a workspace that already held one, with an argument error: no record left
+    ctx.cost_fwd(q, shape, ws=ws2)
+    with pytest.raises(VaprError) as e:
+        ctx.cost_fwd(q, shape, ws=ws2[:16])  # same address, too small: rejected before any change
+    assert e.value.status == L.E_INVALID
+    ctx.cost_bwd(q, ws2)
+    # header overwritten behind the library's back: NaN gradients, flag reported by sync
+    ctx.cost_fwd(q, shape, ws=ws2)
+    ws2[:64].zero_()
+    grad = ctx.cost_bwd(q, ws2)
+    with pytest.raises(VaprError) as e:
+        ctx.sync()
+    assert e.value.status == L.E_STATE
+    assert torch.isnan(grad).all()
+    ctx.sync()  # reported once
+    ctx.cost_fwd(q, shape, ws=ws2)
+    again = ctx.cost_bwd(q, ws2)
+    ctx.sync()
+    assert torch.equal(again, good)
+    ctx.close()
+
+
 @pytest.mark.parametrize("wname,pname", [("dense", "f32"), ("dense", "mixed_fp4"), ("batched", "f32"),
                                          ("large", "paper_like"), ("edge", "f32"), ("dense_k32", "f32"),
                                          ("dense_k100", "paper_like")])
@@ -399,3 +454,54 @@ def test_culling_grid_is_conservative(wname):
             bit = (mask[vid, k // 32] >> np.uint32(k % 32)) & np.uint32(1)
             dropped = ~inside | (bit == 0)
             assert np.all(sd[dropped] >= reach), (w, k, float(sd[dropped].min()))
+
+
+@pytest.mark.parametrize("wname", ["tiny", "dense", "tiny_no_pairs"])
+def test_collision_free(wname):
+    """vapr_collision_free against the oracle's clearances: a configuration is free when every
+    sphere clears every cuboid, every self pair is apart and the joints are within their limits.
+    Configurations whose smallest clearance is within FP32 rounding of zero may go either way."""
+    need_gpu()
+    if wname == "dense":
+        wl = dense_workload()
+    else:
+        wl = make_workload("tiny")
+        if wname == "tiny_no_pairs":
+            wl = dataclasses.replace(wl, robot=dataclasses.replace(wl.robot, pairs=wl.robot.pairs[:0]))
+    ctx = make_context(wl, {})
+    shape = shape_of(wl)
+    q = dev(wl.q, torch.float32)
+    _, ws = ctx.cost_fwd(q, shape)
+    got = ctx.collision_free(ws, shape).cpu().numpy()
+    ref = run_oracle(wl)
+    r = wl.robot.sphere_radius.astype(np.float64)
+    S = ref["S"]
+    a, b = wl.robot.pairs[:, 0], wl.robot.pairs[:, 1]
+    pair_clear = np.linalg.norm(S[:, a] - S[:, b], axis=-1) - r[a] - r[b]
+    world_clear = OC.CostParams().eta - ref["D"].max(axis=1)  # the smallest clearance when it is < eta
+    min_clear = np.minimum(world_clear, pair_clear.min(axis=1)) if pair_clear.shape[1] else world_clear
+    want = (min_clear > 0) & (ref["bound_cost"] == 0)
+    sure = np.abs(min_clear) > 1e-5
+    assert np.array_equal(got[sure].astype(bool), want[sure])
+    print(f"[collision_free] {wname}: {int(want.sum())} of {want.size} free, {int((~sure).sum())} undecided")
+    ctx.close()
+
+
+def test_seed_deviations_invert_trajectories():
+    need_gpu()
+    from paper_2310_07854_amd import seeding
+
+    rng = np.random.default_rng(3)
+    n = 5
+    start = dev(rng.uniform(-2, 2, (n, 7)), torch.float32)
+    goal = dev(rng.uniform(-2, 2, (n, 7)), torch.float32)
+    y = dev(rng.normal(0, 0.3, (n, 8 * 32 * 7)), torch.float32)
+    traj = seeding.trajectories(y, start, goal)
+    got = seeding.deviations(traj, start, goal).cpu().numpy().reshape(n, 8, 32, 7)
+    want = y.cpu().numpy().reshape(n, 8, 32, 7).astype(np.float64)
+    want[:, :, 0] = 0.0
+    want[:, :, 31] = 0.0
+    # line + y rounded to FP32 and the line subtracted again: within one ulp of |line + y|
+    tr = traj.cpu().numpy().reshape(n, 8, 32, 7).astype(np.float64)
+    assert np.all(np.abs(got - want) <= np.spacing(np.abs(tr).astype(np.float32)).astype(np.float64) * 1.01)
+    assert np.all(got[:, :, 0] == 0) and np.all(got[:, :, 31] == 0)
