@@ -255,6 +255,21 @@ int vapr_cost_fwd(vapr_ctx* ctx, int n_worlds, int traj_per_world, int T, int n_
 int vapr_cost_bwd(vapr_ctx* ctx, const float* q, void* ws, size_t ws_bytes, const double* grad_cost_traj,
                   float* grad_q);
 
+/* Forward and backward pass without a caller workspace and without allocating, for callers that
+ * cannot allocate device memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments and results as vapr_cost_fwd followed by vapr_cost_bwd (q,
+ * grad_cost_traj, cost_traj, cost_cfg and grad_q as there; grad_cost_traj and cost_cfg may be NULL,
+ * grad_q must not be), with the stored tensors kept in a static workspace of 64 MiB on each device
+ * the library runs on, held until the process ends.  A batch whose workspace (vapr_workspace_size)
+ * exceeds 64 MiB fails with VAPR_E_INVALID before any launch.  The lookup tables must already be
+ * built: after changing the robot, worlds, culling or cost parameters run one vapr_cost_fwd first
+ * (VAPR_E_STATE otherwise).  Every call on a device shares that device's static workspace, which
+ * keeps the last call's contents: calls that overlap on one device (other streams, other contexts,
+ * other host threads) race and must be serialised by the caller.  Per-kernel event timing does not
+ * cover these launches. */
+int vapr_cost_fwd_bwd_noalloc(vapr_ctx* ctx, int n_worlds, int traj_per_world, int T, int n_ls, const float* q,
+                              const double* grad_cost_traj, double* cost_traj, float* cost_cfg, float* grad_q);
+
 /* Optimiser state for n_traj trajectories of T timesteps (n = T*7 variables each), all dev,
  * caller-owned (checkpointing is a copy of these buffers).  Unless free_ends, rows t = 0 and
  * t = T-1 keep their values (start and goal of a trajectory). */

@@ -99,6 +99,7 @@ SIGNATURES = {
     "vapr_cost_fwd": (_I, [_P, _I, _I, _I, _I, _P, _P, _SZ, _P, _P]),
     "vapr_cost_fwd_from": (_I, [_P, _I, _I, _I, _I, _I, _P, _P, _SZ, _P, _P]),
     "vapr_cost_bwd": (_I, [_P, _P, _P, _SZ, _P, _P]),
+    "vapr_cost_fwd_bwd_noalloc": (_I, [_P, _I, _I, _I, _I, _P, _P, _P, _P, _P]),
     "vapr_optimizer_init": (_I, [_P, ctypes.POINTER(LbfgsStateC), _P, _SZ, _P, _P]),
     "vapr_optimizer_step": (_I, [_P, ctypes.POINTER(LbfgsStateC), _P, _SZ, _P, _P]),
     "vapr_quantize": (_I, [_I, _I, _P, _P, _I64, _P]),

@@ -235,6 +235,18 @@ class Context:
         self._call("vapr_collision_free", *shape.args(), _dev(ws, torch.uint8, "ws"), ws.numel(), out.data_ptr())
         return out.bool()
 
+    def cost_fwd_bwd_noalloc(self, q: torch.Tensor, shape: Shape, cost_traj: torch.Tensor, grad_q: torch.Tensor,
+                             grad_cost_traj: Optional[torch.Tensor] = None,
+                             cost_cfg: Optional[torch.Tensor] = None) -> None:
+        """Forward + backward pass into caller-provided outputs, with the stored tensors in the
+        library's static per-device workspace (no allocation; batches up to 64 MiB of workspace)."""
+        if q.shape != (shape.B, 7) or grad_q.shape != (shape.B, 7):
+            raise ValueError(f"q and grad_q must be [{shape.B}, 7]")
+        up = _dev(grad_cost_traj, torch.float64, "grad_cost_traj") if grad_cost_traj is not None else None
+        cfg = _dev(cost_cfg, torch.float32, "cost_cfg") if cost_cfg is not None else None
+        self._call("vapr_cost_fwd_bwd_noalloc", *shape.args(), _dev(q, torch.float32, "q"), up,
+                   _dev(cost_traj, torch.float64, "cost_traj"), cfg, _dev(grad_q, torch.float32, "grad_q"))
+
     # -- stored tensors --------------------------------------------------------------------------
     def tensor_count(self, name: str) -> int:
         return {"link_poses": 96, "sphere_pos": 3 * self.n_spheres, "sphere_dist": self.n_spheres,

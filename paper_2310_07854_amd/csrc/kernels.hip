@@ -2005,6 +2005,18 @@ __global__ __launch_bounds__(256) void k_collision_free(RobotArgs R, TV S, TV D,
   out[b] = ok ? 1 : 0;
 }
 
+// Workspace of the allocation-free entry point: one array per device, held until the process
+// ends.  In host code `scratch` names a host-side stand-in, never the device memory: the device
+// address comes from hipGetSymbolAddress below, once per device with that device current, and only
+// that address is passed to kernels.
+constexpr size_t SCRATCH_BYTES = (size_t)64 << 20;
+static __device__ __align__(256) uint8_t scratch[SCRATCH_BYTES];
+
+hipError_t scratch_address(void** ptr, size_t* bytes) {
+  *bytes = SCRATCH_BYTES;
+  return hipGetSymbolAddress(ptr, HIP_SYMBOL(scratch));
+}
+
 hipError_t launch_collision_free(hipStream_t s, const RobotArgs& R, const TV& S, const TV& D, const float* boundc,
                                  float eta, int64_t B, int32_t* out) {
   hipLaunchKernelGGL(k_collision_free, dim3(blocks_for(B, 256)), dim3(256), 0, s, R, S, D, boundc, eta, B, out);

@@ -107,6 +107,9 @@ hipError_t launch_optimizer(hipStream_t s, const OptArgs& o, const TV& J, const 
                             int mode, const WsCheck& ck);
 // header write of a workspace outside a forward pass (stage-wise imports, resets)
 hipError_t launch_ws_stamp(hipStream_t s, const WsStamp& st);
+// device address of the current device's static scratch (the allocation-free entry point's
+// workspace) and its size; call once per device with that device current
+hipError_t scratch_address(void** ptr, size_t* bytes);
 // per configuration 1 if collision-free (every clearance and self-pair clearance > 0, no joint beyond
 // its limits) from a forward pass's stored S, D and bound cost, else 0
 hipError_t launch_collision_free(hipStream_t s, const RobotArgs& R, const TV& S, const TV& D, const float* boundc,

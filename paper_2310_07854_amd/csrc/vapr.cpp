@@ -9,6 +9,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <unordered_map>
 #include <vector>
@@ -35,6 +36,29 @@ struct WsRecord {
 
 std::atomic<uint64_t> g_next_ctx_uid{1};
 
+// Device address of each device's static scratch, looked up once per device (by the first
+// vapr_create on it, with the device current).
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+size_t g_scratch_bytes = 0;
+
+hipError_t device_scratch(int device, void** ptr, size_t* bytes) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* p = nullptr;
+    size_t n = 0;
+    const hipError_t e = scratch_address(&p, &n);
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_ptr[device] = p;
+    g_scratch_bytes = n;
+  }
+  *ptr = g_scratch_ptr[device];
+  *bytes = g_scratch_bytes;
+  return hipSuccess;
+}
+
 struct ProfEvent {
   int id;
   hipEvent_t start, stop;
@@ -49,6 +73,8 @@ struct vapr_ctx {
   uint64_t fwd_gen = 0;    // forward passes issued (workspace headers)
   uint64_t params_gen = 0; // cost-parameter changes
   uint32_t* d_status = nullptr;  // device flag: a consumer kernel met a workspace it was not issued for
+  void* scratch = nullptr;       // this device's static workspace (allocation-free entry point)
+  size_t scratch_bytes = 0;
   // robot
   bool has_robot = false;
   uint64_t robot_gen = 0;
@@ -463,8 +489,11 @@ int build_grid(vapr_ctx* ctx) {
   return VAPR_OK;
 }
 
+// Forward pass into ws.  static_ws: ws is the library's static scratch (the allocation-free entry
+// point): the lookup tables must already be built (building them allocates), no host record is
+// kept and the forward pass's record goes to *out_rec instead.
 int run_fwd(vapr_ctx* ctx, int first, int n_worlds, int tpw, int T, int n_ls, const float* q, void* ws,
-            size_t ws_bytes, double* cost_traj, float* cost_cfg) {
+            size_t ws_bytes, double* cost_traj, float* cost_cfg, bool static_ws = false, WsRecord* out_rec = nullptr) {
   int64_t B;
   int st = check_shape(ctx, n_worlds, tpw, T, n_ls, &B);
   if (st) return st;
@@ -473,7 +502,17 @@ int run_fwd(vapr_ctx* ctx, int first, int n_worlds, int tpw, int T, int n_ls, co
   if (n_worlds > ctx->n_worlds) return fail(ctx, VAPR_E_INVALID, "n_worlds exceeds the uploaded worlds");
   if (!q || !ws || !cost_traj) return fail(ctx, VAPR_E_INVALID, "null pointer");
   const Layout L = make_layout(B, ctx->n_s, ctx->prec);
-  if (ws_bytes < L.bytes) return fail(ctx, VAPR_E_INVALID, "workspace too small");
+  if (ws_bytes < L.bytes) {
+    if (static_ws)
+      return fail(ctx, VAPR_E_INVALID,
+                  "batch needs a " + std::to_string(L.bytes) + "-byte workspace; the static workspace holds " +
+                      std::to_string(ws_bytes) + " bytes");
+    return fail(ctx, VAPR_E_INVALID, "workspace too small");
+  }
+  if (static_ws && (!ctx->pairs_valid || !ctx->grid_valid))
+    return fail(ctx, VAPR_E_STATE,
+                "lookup tables not built: run one vapr_cost_fwd after changing the robot, worlds, culling or cost "
+                "parameters (building them allocates device memory)");
   if (first >= 2) {
     const char* why = nullptr;
     const WsRecord* r = current_record(ctx, ws, &why);
@@ -495,7 +534,7 @@ int run_fwd(vapr_ctx* ctx, int first, int n_worlds, int tpw, int T, int n_ls, co
   hipStream_t s = ctx->stream;
   // from here on the workspace's old contents are being replaced: it holds no usable forward pass
   // until this one has been queued completely
-  ctx->ws.erase(ws);
+  if (!static_ws) ctx->ws.erase(ws);
   const WsRecord rec = new_record(ctx, n_worlds, tpw, T, n_ls, B);
   const WsStamp stamp = stamp_of(ctx, ws, rec);
   if (first <= 1) {
@@ -536,7 +575,8 @@ int run_fwd(vapr_ctx* ctx, int first, int n_worlds, int tpw, int T, int n_ls, co
              },
              "k_reduce launch");
   if (st) return st;
-  ctx->ws[ws] = rec;
+  if (static_ws) *out_rec = rec;
+  else ctx->ws[ws] = rec;
   return VAPR_OK;
 }
 
@@ -608,6 +648,28 @@ int run_opt(vapr_ctx* ctx, const vapr_lbfgs_state* st, const void* ws, size_t ws
                "k_optimizer launch");
 }
 
+// Backward pass over the forward pass `r` held in ws (checked by the caller).
+int run_bwd(vapr_ctx* ctx, const float* q, void* ws, size_t ws_bytes, const WsRecord& r, const double* grad_cost_traj,
+            float* grad_q) {
+  const Layout L = make_layout(r.B, ctx->n_s, ctx->prec);
+  if (ws_bytes < L.bytes) return fail(ctx, VAPR_E_INVALID, "workspace too small");
+  const ShapeArgs sh = shape_args(r.n_worlds, r.tpw, r.T, r.n_ls);
+  const RobotArgs R = robot_args(ctx);
+  const TV tL = tensor_view(ws, L, ctx->prec, T_L), tG = tensor_view(ws, L, ctx->prec, T_G),
+           tJ = tensor_view(ws, L, ctx->prec, T_J), tX = tensor_view(ws, L, ctx->prec, T_X);
+  const CostArgs cp = ctx->params;
+  const int rec = ctx->prec.recompute;
+  const float* goal = ctx->prec.pose ? ctx->d_goal : nullptr;
+  if (goal && r.n_worlds > ctx->n_goals) return fail(ctx, VAPR_E_STATE, "goal poses changed since the forward pass");
+  const WsCheck ck = check_of(ctx, ws, r);
+  return timed(ctx, K_ADJOINT,
+               [&] {
+                 return launch_adjoint(ctx->stream, q, R, tL, tG, tX, tJ, grad_cost_traj, grad_q, sh, cp, rec, goal,
+                                       ck);
+               },
+               "k_adjoint launch");
+}
+
 }  // namespace
 
 extern "C" {
@@ -633,9 +695,14 @@ int vapr_create(vapr_ctx** out, int device, void* hip_stream) {
   int n = 0;
   hipError_t e = hipGetDeviceCount(&n);
   if (e != hipSuccess) return hip_fail(nullptr, e, "hipGetDeviceCount");
-  if (device < 0 || device >= n) return fail(nullptr, VAPR_E_INVALID, "device index out of range");
+  if (device < 0 || device >= n || device >= MAX_DEVICES)
+    return fail(nullptr, VAPR_E_INVALID, "device index out of range");
   e = hipSetDevice(device);
   if (e != hipSuccess) return hip_fail(nullptr, e, "hipSetDevice");
+  void* scratch = nullptr;
+  size_t scratch_bytes = 0;
+  e = device_scratch(device, &scratch, &scratch_bytes);
+  if (e != hipSuccess) return hip_fail(nullptr, e, "hipGetSymbolAddress(scratch)");
   uint32_t* status = nullptr;
   e = hipMalloc((void**)&status, sizeof(uint32_t));
   if (e != hipSuccess) return fail(nullptr, VAPR_E_OOM, std::string("hipMalloc: ") + hipGetErrorString(e));
@@ -649,6 +716,8 @@ int vapr_create(vapr_ctx** out, int device, void* hip_stream) {
   c->stream = static_cast<hipStream_t>(hip_stream);
   c->uid = g_next_ctx_uid.fetch_add(1);
   c->d_status = status;
+  c->scratch = scratch;
+  c->scratch_bytes = scratch_bytes;
   vapr_precision p{};
   p.link_poses = p.sphere_pos = p.sphere_dist = p.sphere_grad = p.joint_grad = {VAPR_F32, 0};
   c->prec = to_cfg(p);
@@ -933,24 +1002,23 @@ int vapr_cost_bwd(vapr_ctx* ctx, const float* q, void* ws, size_t ws_bytes, cons
   const char* why = nullptr;
   const WsRecord* rp = current_record(ctx, ws, &why);
   if (!rp) return fail(ctx, VAPR_E_STATE, why);
-  const WsRecord r = *rp;
-  const Layout L = make_layout(r.B, ctx->n_s, ctx->prec);
-  if (ws_bytes < L.bytes) return fail(ctx, VAPR_E_INVALID, "workspace too small");
-  const ShapeArgs sh = shape_args(r.n_worlds, r.tpw, r.T, r.n_ls);
-  const RobotArgs R = robot_args(ctx);
-  const TV tL = tensor_view(ws, L, ctx->prec, T_L), tG = tensor_view(ws, L, ctx->prec, T_G),
-           tJ = tensor_view(ws, L, ctx->prec, T_J), tX = tensor_view(ws, L, ctx->prec, T_X);
-  const CostArgs cp = ctx->params;
-  const int rec = ctx->prec.recompute;
-  const float* goal = ctx->prec.pose ? ctx->d_goal : nullptr;
-  if (goal && r.n_worlds > ctx->n_goals) return fail(ctx, VAPR_E_STATE, "goal poses changed since the forward pass");
-  const WsCheck ck = check_of(ctx, ws, r);
-  return timed(ctx, K_ADJOINT,
-               [&] {
-                 return launch_adjoint(ctx->stream, q, R, tL, tG, tX, tJ, grad_cost_traj, grad_q, sh, cp, rec, goal,
-                                       ck);
-               },
-               "k_adjoint launch");
+  return run_bwd(ctx, q, ws, ws_bytes, *rp, grad_cost_traj, grad_q);
+}
+
+int vapr_cost_fwd_bwd_noalloc(vapr_ctx* ctx, int n_worlds, int tpw, int T, int n_ls, const float* q,
+                              const double* grad_cost_traj, double* cost_traj, float* cost_cfg, float* grad_q) {
+  if (!ctx) return fail(nullptr, VAPR_E_INVALID, "null context");
+  if (!grad_q) return fail(ctx, VAPR_E_INVALID, "null grad_q");
+  if (!ctx->scratch) return fail(ctx, VAPR_E_STATE, "no static workspace on this device");
+  // per-kernel event timing is left out: creating events allocates
+  const bool prof = ctx->prof;
+  ctx->prof = false;
+  WsRecord rec{};
+  int st = run_fwd(ctx, 1, n_worlds, tpw, T, n_ls, q, ctx->scratch, ctx->scratch_bytes, cost_traj, cost_cfg, true,
+                   &rec);
+  if (!st) st = run_bwd(ctx, q, ctx->scratch, ctx->scratch_bytes, rec, grad_cost_traj, grad_q);
+  ctx->prof = prof;
+  return st;
 }
 
 int vapr_optimizer_init(vapr_ctx* ctx, const vapr_lbfgs_state* st, const void* ws, size_t ws_bytes,
