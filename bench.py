@@ -42,8 +42,7 @@ PRECISIONS = {
     "mixed_fp4": {"link_poses": "e4m3", "sphere_pos": "e4m3", "sphere_dist": "e2m1", "sphere_grad": "e2m1",
                   "joint_grad": "e4m3"},
 }
-MAX_FINITE = {"f16": 65504.0, "bf16": 3.3895313892515355e38, "e4m3": 448.0, "e5m2": 57344.0, "e3m2": 28.0,
-              "e2m1": 6.0}
+TENSOR_NAMES = ("link_poses", "sphere_pos", "sphere_dist", "sphere_grad", "joint_grad", "swept_grad")
 BITS = {"f32": 32, "f16": 16, "bf16": 16, "e4m3": 8, "e5m2": 8, "e3m2": 6, "e2m1": 4}
 N_WORLDS, TPW, T, N_LS, N_SPHERES, N_CUBOIDS, N_PAIRS = 64, 64, 48, 1, 60, 64, 300
 HIST_M = 8
@@ -258,15 +257,13 @@ def calibrate_scales(torch, ctx, x0):
     return {t: float(ctx.ws_export(t, ws, shape).view(torch.float32).abs().max()) for t in names}
 
 
-def with_scales(formats, amax):
-    """(format, k) per tensor with k = ceil(log2(amax / max finite)) in [-16, 16] (FP32: k = 0)."""
-    out = {}
-    for t, f in formats.items():
-        k = 0
-        if f != "f32" and amax[t] > 0:
-            k = int(min(16, max(-16, math.ceil(math.log2(amax[t] / MAX_FINITE[f])))))
-        out[t] = (f, k)
-    return out
+def with_scales(formats, amax, reach):
+    """(format, k) per tensor: link poses and sphere positions from the robot's reach, the others
+    from their FP32 magnitude on the calibration pass (one binade of headroom for FP16/BF16, which
+    overflow to Inf); |k| <= 16, FP32 k = 0."""
+    from paper_2310_07854_amd.search import spec
+
+    return spec({t: fmt_of(formats, t) for t in TENSOR_NAMES if t in amax or t in formats}, amax, reach)
 
 
 def fwd_bwd_timing(torch, ctx, x0, prec, recompute=False, warmup=20, runs=200):
@@ -729,7 +726,7 @@ def swept_bench(args):
     for name in ("f32", "paper_like"):
         f = dict(PRECISIONS[name])
         f["swept_grad"] = f.get("sphere_grad", "f32")
-        prec = with_scales(f, amax)
+        prec = with_scales(f, amax, ctx.reach())
         dt, prof, _, opt = run_variant(torch, ctx, TrajectoryOptimizer, x0, prec, args.steps, args.warmup,
                                        want_opt=name == "paper_like")
         if opt is not None:
@@ -789,7 +786,7 @@ def batched_workload(torch, steps, warmup):
     out = {"workload": "4 worlds x 32 seeds x 32 timesteps x 4 line-search candidates = 16,384 configurations "
                        "per iteration; 60 spheres, 300 self pairs, 40 cuboids per world"}
     for name in ("f32", "paper_like"):
-        ctx.set_precision(with_scales(PRECISIONS[name], amax) if name != "f32" else {})
+        ctx.set_precision(with_scales(PRECISIONS[name], amax, ctx.reach()) if name != "f32" else {})
         opt = TrajectoryOptimizer(ctx, W, S, Tn, n_ls=nls, m=HIST_M)
         opt.init(x0)
         for _ in range(warmup):
@@ -834,7 +831,7 @@ def graph_bench(args):
             ctx.cost_bwd(q, ws, want_grad=False)
             amax = {t: float(ctx.ws_export(t, ws, sh).view(torch.float32).abs().max()) for t in
                     ("link_poses", "sphere_pos", "sphere_dist", "sphere_grad", "joint_grad")}
-            ctx.set_precision(with_scales(PRECISIONS["paper_like"], amax))
+            ctx.set_precision(with_scales(PRECISIONS["paper_like"], amax, ctx.reach()))
         else:
             ctx.set_precision({})
         res = {}
@@ -969,7 +966,7 @@ def ik_bench(args):
     amax = {t: float(ctx.ws_export(t, ws, shape).view(torch.float32).abs().max()) for t in names}
     out = {}
     for name in ("f32", "paper_like"):
-        prec = with_scales(PRECISIONS[name], amax)
+        prec = with_scales(PRECISIONS[name], amax, ctx.reach())
         ctx.set_precision(prec)
         opt = TrajectoryOptimizer(ctx, N_WORLDS, IK_SEEDS, 1, n_ls=N_LS, m=HIST_M, pin_ends=False)
         opt.init(x0)
@@ -1104,7 +1101,7 @@ def main():
     ctx.set_worlds(worlds.pose, worlds.half_ext)
 
     amax = calibrate_scales(torch, ctx, x0)
-    precs = {name: with_scales(f, amax) for name, f in PRECISIONS.items()}
+    precs = {name: with_scales(f, amax, ctx.reach()) for name, f in PRECISIONS.items()}
     if args.only:
         dt, prof, _, _ = run_variant(torch, ctx, TrajectoryOptimizer, x0, precs[args.only], args.steps, args.warmup)
         print(json.dumps({"only": args.only, "ms_per_step": dt / args.steps * 1e3,

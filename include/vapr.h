@@ -153,6 +153,11 @@ int vapr_set_robot(vapr_ctx* ctx, int n_joints, const float* fixed_tf, int n_sph
                    const float* sphere_center, const float* sphere_radius, const int32_t* sphere_link,
                    int n_pairs, const int32_t* pairs, const float* q_lo, const float* q_hi);
 
+/* The robot's reach: bounds on |value| of every stored link-pose entry (at least 1, the rotation
+ * entries) and every sphere-centre coordinate over all configurations (metres), the quantities
+ * the overflow guard of vapr_set_precision compares with the formats' ranges.  For choosing scales. */
+int vapr_robot_reach(const vapr_ctx* ctx, double* link_poses, double* sphere_pos);
+
 /* Upload the worlds (Sec. II-B: robot-environment distance queries).  Host arrays, copied:
  *   pose     [n_worlds][n_cuboids][3][4]  world <- box transform [R | c]; |R^T R - I| < 1e-5
  *   half_ext [n_worlds][n_cuboids][3]     > 0
@@ -166,7 +171,12 @@ int vapr_set_worlds(vapr_ctx* ctx, int n_worlds, int n_cuboids, const float* pos
 int vapr_set_goals(vapr_ctx* ctx, int n, const float* goal);
 
 /* Select the storage format of each large tensor (Sec. IV-B, V-B).  Unknown format or scale out
- * of range -> VAPR_E_INVALID.  Workspaces filled under another precision become invalid. */
+ * of range -> VAPR_E_INVALID.  Workspaces filled under another precision become invalid.
+ * Overflow guard: FP16, BF16 and the IEEE-like emulated types (E5M10, E8My) overflow to Inf.  A
+ * forward pass fails with VAPR_E_INVALID, before any launch, when the robot's reach -- the sum of
+ * its fixed translation lengths up to a link, plus the sphere offset, at most 1 for rotation
+ * entries -- exceeds the largest value of the link-pose or sphere-position format at its scale, so
+ * no configuration can store Inf there.  The saturating formats clamp instead. */
 int vapr_set_precision(vapr_ctx* ctx, const vapr_precision* p);
 int vapr_get_precision(const vapr_ctx* ctx, vapr_precision* p);
 

@@ -292,13 +292,17 @@ def _store(x: np.ndarray, prec: Optional[Precision], tensor: str):
 def fwd_bwd(robot, worlds, q: np.ndarray, traj_per_world: int, T: int, n_ls: int,
             prec: Optional[Precision] = None, params: CostParams = CostParams(),
             upstream: Optional[np.ndarray] = None, emulate_scalars: bool = True,
-            goals: Optional[np.ndarray] = None) -> Dict[str, np.ndarray]:
+            goals: Optional[np.ndarray] = None,
+            perturb: Optional[Dict[str, np.ndarray]] = None) -> Dict[str, np.ndarray]:
     """Whole forward + backward pass for configurations q [B, 7] laid out as
     b = ((traj * n_ls + candidate) * T + t).  With `prec` None this is the unquantised FP64 truth;
     otherwise each stored tensor goes through the reference codec (f32 = FP32 rounding) where the
     GPU path writes it.  `upstream` is d(loss)/d(cost_traj) per trajectory-candidate (default 1).
     `goals` [n_worlds, 3, 4] adds the pose cost of each world's goal (inverse kinematics): its value
-    from the unquantised poses, its gradient from the poses the backward pass reads."""
+    from the unquantised poses, its gradient from the poses the backward pass reads.
+    `perturb` maps some of "L", "S", "D", "G", "J" to arrays added to that stored tensor right after
+    its store (the brute-force check of the error budget's sensitivities); a perturbed L is read by
+    the backward pass even without a precision assignment."""
     q = np.asarray(q, dtype=np.float64)
     B = q.shape[0]
     n_tc = B // T
@@ -310,10 +314,13 @@ def fwd_bwd(robot, worlds, q: np.ndarray, traj_per_world: int, T: int, n_ls: int
     # (2) kinematics: link poses and sphere centres
     Tk = forward_kinematics(robot.fixed_tf, q)
     Lval = link_pose_values(Tk)
+    perturb = perturb or {}
     out["L_codes"], L_hat = _store(Lval, None if (prec is not None and prec.recompute_poses) else prec,
                                    "link_poses")
+    L_hat = L_hat + perturb.get("L", 0.0)
     S = sphere_positions(Tk, robot.sphere_center, robot.sphere_link)
     out["S_codes"], S_hat = _store(S, prec, "sphere_pos")
+    S_hat = S_hat + perturb.get("S", 0.0)
     bcost, bgrad = bound_term(q, robot.q_lo, robot.q_hi)
 
     # (3) costs from the stored sphere positions
@@ -323,6 +330,8 @@ def fwd_bwd(robot, worlds, q: np.ndarray, traj_per_world: int, T: int, n_ls: int
     G = np.where(d[..., None] > 0, -2.0 * params.w_coll * d[..., None] * gdir, 0.0) + params.w_self * sgrad
     out["D_codes"], D_hat = _store(d, prec, "sphere_dist")
     out["G_codes"], G_hat = _store(G, prec, "sphere_grad")
+    D_hat = D_hat + perturb.get("D", 0.0)
+    G_hat = G_hat + perturb.get("G", 0.0)
     if prec is not None and emulate_scalars:
         scost_st = fmts.fp32(params.w_self * scost).astype(np.float64)
         bcost_st = fmts.fp32(bcost).astype(np.float64)
@@ -354,7 +363,7 @@ def fwd_bwd(robot, worlds, q: np.ndarray, traj_per_world: int, T: int, n_ls: int
     cost_traj = cfg.reshape(n_tc, T).sum(axis=1) + params.w_smooth * smooth
 
     # (5) backward to joint space
-    if prec is not None and not prec.recompute_poses:
+    if (prec is not None and not prec.recompute_poses) or "L" in perturb:
         Tb = poses_from_values(L_hat)
         Pb = sphere_positions(Tb, robot.sphere_center, robot.sphere_link)
     else:
@@ -366,6 +375,7 @@ def fwd_bwd(robot, worlds, q: np.ndarray, traj_per_world: int, T: int, n_ls: int
     up = np.ones(n_tc) if upstream is None else np.asarray(upstream, dtype=np.float64)
     J = up.repeat(T)[:, None] * (Jsph + params.w_bound * bgrad + params.w_smooth * sgr)
     out["J_codes"], J_hat = _store(J, prec, "joint_grad")
+    J_hat = J_hat + perturb.get("J", 0.0)
 
     out.update(L=Lval, L_hat=L_hat, S=S, S_hat=S_hat, D=d, D_hat=D_hat, G=G, G_hat=G_hat, J=J, J_hat=J_hat,
                self_cost=scost_st, bound_cost=bcost_st, cfg_cost=cfg, cost_traj=cost_traj, grad_q=J_hat,

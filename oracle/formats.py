@@ -284,8 +284,10 @@ def packed_nbytes(fmt, n: int) -> int:
 
 
 def ulp_at(x, fmt, k: int = 0) -> np.ndarray:
-    """Spacing of the format's representable values around |x| (unscaled units): the larger of the
-    two gaps adjacent to the value x rounds to.  Used for first-order error budgets."""
+    """Width of the interval between the two representable values that enclose |x| (unscaled
+    units; at a representable value, the gap below it; for f32, numpy's spacing above fp32(|x|),
+    which is never smaller).  Rounding to nearest moves an in-range x by at most half of it: the
+    per-element term of the first-order error budget (oracle/budget.py)."""
     f = get(fmt)
     x = np.asarray(x, dtype=np.float64)
     if f.name == "f32":

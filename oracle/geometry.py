@@ -45,3 +45,24 @@ def obb_signed_distance(p: np.ndarray, R: np.ndarray, c: np.ndarray, h: np.ndarr
     a_sorted = np.sort(a, axis=-1)
     axis_gap = np.where(norm_o > 0.0, np.inf, a_sorted[..., 2] - a_sorted[..., 1])
     return sd, grad, axis_gap
+
+
+def obb_hessian(p: np.ndarray, R: np.ndarray, c: np.ndarray, h: np.ndarray) -> np.ndarray:
+    """Hessian of sd w.r.t. p [..., 3] for one cuboid: [..., 3, 3].  Outside, sd = ||o|| with
+    o = max(|u| - h, 0) over the axes where |u_i| > h_i, whose Hessian in the box frame is
+    (P - n n^T) / ||o|| (P: those axes, n: the unit outward direction sign(u) o / ||o||), turned into
+    the world frame as R (.) R^T.  Inside sd is max_i a_i, piecewise linear: zero Hessian.  Undefined
+    where an axis is exactly on its face plane or the inside axis is not unique (the kinks)."""
+    p = np.asarray(p, dtype=np.float64)
+    R = np.asarray(R, dtype=np.float64)
+    u = (p - c) @ R
+    a = np.abs(u) - h
+    o = np.maximum(a, 0.0)
+    norm_o = np.sqrt(np.sum(o * o, axis=-1))
+    out = norm_o > 0.0
+    safe = np.where(out, norm_o, 1.0)[..., None]
+    n = np.where(u >= 0.0, 1.0, -1.0) * o / safe
+    P = (a > 0.0).astype(np.float64)
+    Hu = (P[..., :, None] * np.eye(3) - n[..., :, None] * n[..., None, :]) / safe[..., None]
+    Hu = np.where(out[..., None, None], Hu, 0.0)
+    return R @ Hu @ R.T

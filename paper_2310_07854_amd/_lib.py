@@ -84,6 +84,7 @@ SIGNATURES = {
     "vapr_set_stream": (_I, [_P, _P]),
     "vapr_set_robot": (_I, [_P, _I, _P, _I, _P, _P, _P, _I, _P, _P, _P]),
     "vapr_set_worlds": (_I, [_P, _I, _I, _P, _P]),
+    "vapr_robot_reach": (_I, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
     "vapr_set_goals": (_I, [_P, _I, _P]),
     "vapr_round_exmy": (_I, [_I, _I, _I, _P, _P, _I64, _P]),
     "vapr_set_precision": (_I, [_P, ctypes.POINTER(PrecisionC)]),

@@ -130,6 +130,13 @@ class Context:
                    int(pairs.shape[0]), _ptr(pairs) if pairs.size else None, _ptr(lo), _ptr(hi))
         self.n_spheres = int(radius.shape[0])
 
+    def reach(self) -> Tuple[float, float]:
+        """(link-pose bound, sphere-centre bound): the largest |value| any configuration stores in
+        L and S, from the robot's translation lengths and sphere offsets."""
+        lp, sp = ctypes.c_double(), ctypes.c_double()
+        self._call("vapr_robot_reach", ctypes.byref(lp), ctypes.byref(sp))
+        return lp.value, sp.value
+
     def set_worlds(self, pose, half_ext) -> None:
         pose = _host(pose, np.float32)
         half = _host(half_ext, np.float32)

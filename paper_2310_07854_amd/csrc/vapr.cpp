@@ -105,6 +105,9 @@ struct vapr_ctx {
   uint32_t* d_grid = nullptr;
   GridArgs grid{};
   float r_max = 0.f;
+  // largest |value| any configuration can give the stored poses and sphere centres (the chain's
+  // translation lengths add up along it, rotations keep lengths): overflow guard of the scales
+  double reach_L = 0.0, reach_S = 0.0;
   // settings
   PrecisionCfg prec{};
   CostArgs params{0.02f, 100.f, 100.f, 10.f, 1.f, 0, 100.f, 100.f, 10.f};
@@ -230,6 +233,45 @@ bool same_prec(const PrecisionCfg& a, const PrecisionCfg& b) {
         a.t[i].xm != b.t[i].xm)
       return false;
   return a.recompute == b.recompute && a.sweep == b.sweep && a.pose == b.pose;
+}
+
+// Largest finite value of a stored format at its scale when it overflows to Inf (FP16, BF16 and the
+// IEEE-like emulated types E5M10 and E8My); +inf for the saturating formats, whose overflow stays
+// finite.
+double overflow_limit(const TensorFormat& f) {
+  double mf;
+  if (f.xe) {
+    if (!((f.xe == 5 && f.xm == 10) || f.xe == 8)) return INFINITY;
+    const int bias = (1 << (f.xe - 1)) - 1;
+    mf = (2.0 - std::ldexp(1.0, -f.xm)) * std::ldexp(1.0, (1 << f.xe) - 2 - bias);
+  } else if (f.fmt == F16) {
+    mf = 65504.0;
+  } else if (f.fmt == BF16) {
+    mf = (2.0 - std::ldexp(1.0, -7)) * std::ldexp(1.0, 127);
+  } else {
+    return INFINITY;
+  }
+  return mf * std::ldexp(1.0, f.scale_exp);
+}
+
+// VAPR_OK, or the reason why some configuration's poses or sphere centres would overflow to Inf
+int check_reach(vapr_ctx* ctx) {
+  char msg[256];
+  const double lim_s = overflow_limit(ctx->prec.t[T_S]);
+  if (ctx->reach_S > lim_s) {
+    std::snprintf(msg, sizeof msg,
+                  "sphere centres reach %.4g m, beyond the largest value %.4g of the sphere_pos format at its scale "
+                  "(they would overflow to Inf): raise its scale_exp", ctx->reach_S, lim_s);
+    return fail(ctx, VAPR_E_INVALID, msg);
+  }
+  const double lim_l = overflow_limit(ctx->prec.t[T_L]);
+  if (!ctx->prec.recompute && ctx->reach_L > lim_l) {
+    std::snprintf(msg, sizeof msg,
+                  "link poses reach %.4g, beyond the largest value %.4g of the link_poses format at its scale "
+                  "(they would overflow to Inf): raise its scale_exp", ctx->reach_L, lim_l);
+    return fail(ctx, VAPR_E_INVALID, msg);
+  }
+  return VAPR_OK;
 }
 
 // 64-bit FNV-1a over the fields same_prec compares (the workspace header's precision tag)
@@ -499,6 +541,7 @@ int run_fwd(vapr_ctx* ctx, int first, int n_worlds, int tpw, int T, int n_ls, co
   if (st) return st;
   if (first < 1 || first > 3) return fail(ctx, VAPR_E_INVALID, "first stage must be 1, 2 or 3");
   if (!ctx->has_worlds) return fail(ctx, VAPR_E_STATE, "no worlds uploaded");
+  if ((st = check_reach(ctx))) return st;
   if (n_worlds > ctx->n_worlds) return fail(ctx, VAPR_E_INVALID, "n_worlds exceeds the uploaded worlds");
   if (!q || !ws || !cost_traj) return fail(ctx, VAPR_E_INVALID, "null pointer");
   const Layout L = make_layout(B, ctx->n_s, ctx->prec);
@@ -832,7 +875,31 @@ int vapr_set_robot(vapr_ctx* ctx, int n_joints, const float* fixed_tf, int n_sph
   ctx->robot_gen++;
   ctx->r_max = 0.f;
   for (int i = 0; i < n_spheres; ++i) ctx->r_max = std::max(ctx->r_max, sphere_radius[i]);
+  // |t_l| <= sum of the translation lengths of F_1..F_l; |p_s| <= |t_l(s)| + |c_s|; rotation
+  // entries are at most 1
+  double reach_link[N_LINKS] = {0.0};
+  for (int l = 1; l < N_LINKS; ++l) {
+    const float* F = fixed_tf + (l - 1) * 12;
+    reach_link[l] = reach_link[l - 1] + std::sqrt((double)F[3] * F[3] + (double)F[7] * F[7] + (double)F[11] * F[11]);
+  }
+  ctx->reach_L = std::max(1.0, reach_link[N_LINKS - 1]);
+  ctx->reach_S = 0.0;
+  for (int i = 0; i < n_spheres; ++i) {
+    const float* c = sphere_center + 3 * i;
+    ctx->reach_S = std::max(ctx->reach_S, reach_link[sphere_link[i]] +
+                                              std::sqrt((double)c[0] * c[0] + (double)c[1] * c[1] + (double)c[2] * c[2]));
+  }
   ctx->grid_valid = false;
+  return VAPR_OK;
+}
+
+int vapr_robot_reach(const vapr_ctx* cctx, double* link_poses, double* sphere_pos) {
+  vapr_ctx* ctx = const_cast<vapr_ctx*>(cctx);
+  if (!ctx) return fail(nullptr, VAPR_E_INVALID, "null context");
+  if (!link_poses || !sphere_pos) return fail(ctx, VAPR_E_INVALID, "null pointer");
+  if (!ctx->has_robot) return fail(ctx, VAPR_E_STATE, "no robot uploaded");
+  *link_poses = ctx->reach_L;
+  *sphere_pos = ctx->reach_S;
   return VAPR_OK;
 }
 

@@ -11,8 +11,9 @@ narrowest floating-point types that keep the task success rate of FP32.
 
 The ladder holds the 21 types of the format space, narrowest first; a type with a storage codec
 (e2m1, e3m2, e4m3, e5m2, f16, bf16, f32) is stored in it, every other type is emulated (FP32
-values rounded to it at each write).  Each type gets a power-of-two scale from the tensor's FP32
-magnitude so that its largest finite value covers it.
+values rounded to it at each write).  Each type gets a power-of-two scale so that its largest finite
+value covers the tensor: the robot's reach for link poses and sphere positions, the FP32 magnitude
+on a calibration batch (with a binade of headroom where overflow gives Inf) for the others.
 
 The search only needs an `evaluate(assignment) -> success rate` callable; `OptimizerTask` builds
 one from synthetic planning problems run through the library's optimiser.
@@ -74,16 +75,35 @@ def max_finite(fmt: str) -> float:
     return (2.0 - 2.0 ** -M) * 2.0 ** e_max
 
 
-def scale_for(fmt: str, amax: float) -> int:
-    """Power-of-two scale exponent k (|k| <= 16) with amax 2^-k within the type's range; 0 for f32."""
+def saturates(fmt: str) -> bool:
+    """True for the types whose overflow clamps to the largest finite value; FP16, BF16, FP32 and
+    the IEEE-like emulated types (E5M10, E8My) overflow to Inf instead."""
+    E, M = exp_man(fmt)
+    return not (fmt in ("f16", "bf16", "f32") or (E, M) == (5, 10) or E == 8)
+
+
+def scale_for(fmt: str, amax: float, headroom: int = 0) -> int:
+    """Power-of-two scale exponent k (|k| <= 16) with amax 2^(headroom - k) within the type's range;
+    0 for f32."""
     if fmt == "f32" or amax <= 0:
         return 0
-    return int(min(16, max(-16, math.ceil(math.log2(amax / max_finite(fmt))))))
+    return int(min(16, max(-16, math.ceil(math.log2(amax * 2.0 ** headroom / max_finite(fmt))))))
 
 
-def spec(assignment: Dict[str, str], amax: Dict[str, float]) -> Dict[str, Tuple[str, int]]:
-    """Context.set_precision argument for an assignment of ladder types."""
-    return {t: (f, scale_for(f, amax.get(t, 0.0))) for t, f in assignment.items()}
+def spec(assignment: Dict[str, str], amax: Dict[str, float],
+         reach: Optional[Tuple[float, float]] = None) -> Dict[str, Tuple[str, int]]:
+    """Context.set_precision argument for an assignment of ladder types.  With the robot's reach
+    (Context.reach(): bounds of every link-pose entry and sphere coordinate over all
+    configurations), link poses and sphere positions take their scale from it, so that no
+    configuration leaves the range; the other tensors from their FP32 magnitude `amax` on a
+    calibration batch, with one binade of headroom for the types that overflow to Inf."""
+    out = {}
+    for t, f in assignment.items():
+        if reach is not None and t in ("link_poses", "sphere_pos"):
+            out[t] = (f, scale_for(f, reach[0] if t == "link_poses" else reach[1]))
+        else:
+            out[t] = (f, scale_for(f, amax.get(t, 0.0), 0 if saturates(f) else 1))
+    return out
 
 
 @dataclass
@@ -246,12 +266,13 @@ class OptimizerTask:
         _, ws = ctx.cost_fwd(q, shape)
         ctx.cost_bwd(q, ws, want_grad=False)
         self.amax = {t: float(ctx.ws_export(t, ws, shape).view(torch.float32).abs().max()) for t in TENSORS}
+        self.reach = ctx.reach()
 
     def __call__(self, assignment: Dict[str, str]) -> float:
         from . import seed_pipeline as SP
         from .optim import TrajectoryOptimizer
 
-        self.ctx.set_precision(spec(assignment, self.amax))
+        self.ctx.set_precision(spec(assignment, self.amax, self.reach))
         opt = TrajectoryOptimizer(self.ctx, self.W, self.S, self.T, n_ls=self.n_ls)
         opt.init(self.x0)
         for _ in range(self.iters):

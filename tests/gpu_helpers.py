@@ -116,25 +116,29 @@ def compare_codes(name, fmt, k, gpu_codes, oracle_codes, oracle_values, exempt=N
     return int(flagged.sum()), int(diff.sum())
 
 
+def cfg_cost_tolerance(ref, n_pairs, params=OC.CostParams(), eps_pos=4e-6):
+    """Per-configuration part of cost_tolerance (see there)."""
+    world = 2.0 * params.w_coll * ref["D"].sum(axis=1) * eps_pos
+    sum_act = np.sqrt(n_pairs * np.maximum(ref["self_cost"], 0.0) / params.w_self)
+    self_ = 2.0 * params.w_self * sum_act * 2.0 * eps_pos
+    return world + self_ + 2e-6 * np.abs(ref["cfg_cost"])
+
+
 def cost_tolerance(ref, n_pairs, T, params=OC.CostParams(), eps_pos=4e-6):
     """Per trajectory-candidate bound on |cost_gpu - cost_oracle|.  A term w (max(0, eta - e))^2
     moves by at most 2 w act |de| when its clearance moves by de; sphere clearances carry the
     position error eps_pos, pair clearances two of them, and sum_p act_p <= sqrt(P sum_p act_p^2)
     bounds the pair activations from the stored self cost.  A relative 2e-6 covers FP32 rounding
     of the per-configuration sums."""
-    world = 2.0 * params.w_coll * ref["D"].sum(axis=1) * eps_pos
-    sum_act = np.sqrt(n_pairs * np.maximum(ref["self_cost"], 0.0) / params.w_self)
-    self_ = 2.0 * params.w_self * sum_act * 2.0 * eps_pos
-    per_cfg = world + self_ + 2e-6 * np.abs(ref["cfg_cost"])
+    per_cfg = cfg_cost_tolerance(ref, n_pairs, params, eps_pos)
     return per_cfg.reshape(-1, T).sum(axis=1) + 1e-6 * np.abs(ref["cost_traj"]) + 1e-9
 
 
 def grad_tolerance(ref):
-    """Per-configuration bound on |grad_gpu - grad_oracle|: 2e-4 of the configuration's largest
-    component plus 2e-3 absolute (float32 direction errors of the closest-cuboid gradient scale with
-    2 w d and the lever arms of up to ~2 m)."""
+    """Per-configuration bound on |grad_gpu - grad_oracle| of the FP32 path: 1e-4 (|J|_inf + 1e-3)
+    of the configuration's joint gradient (the acceptance band of the FP32 path against FP64)."""
     J = ref["J"]
-    return 2e-4 * np.abs(J).max(axis=1, keepdims=True) + 2e-3
+    return 1e-4 * (np.abs(J).max(axis=1, keepdims=True) + 1e-3)
 
 
 def kink_free(ref, margin=1e-4):

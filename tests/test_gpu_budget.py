@@ -1,0 +1,80 @@
+"""Error of the GPU path against the unquantised FP64 oracle, per named precision assignment, within
+the oracle's first-order error budget (oracle/budget.py): the measured cost error of every sampled
+trajectory candidate and the measured joint-gradient error of every kink-free configuration must be
+at most twice the budget, plus the FP32 computation bound of the same quantity.
+
+Scales come from the same calibration as the benchmark: link poses and sphere positions from the
+robot's reach, the other tensors from their magnitude on an FP32 pass (Context.reach, search.spec).
+"""
+import numpy as np
+import pytest
+
+from oracle import budget as BG
+from oracle import cost as OC
+from synthetic import Worlds, make_workload
+from tests.gpu_helpers import cost_tolerance, dev, grad_tolerance, make_context, need_gpu, shape_of, torch
+
+pytestmark = pytest.mark.gpu
+
+ASSIGNMENTS = {
+    "paper_like": {"link_poses": "f16", "sphere_pos": "f16", "sphere_dist": "e4m3", "sphere_grad": "e4m3",
+                   "joint_grad": "e4m3"},
+    "f16": {t: "f16" for t in OC.TENSORS},
+    "bf16": {t: "bf16" for t in OC.TENSORS},
+    "all_fp8": {"link_poses": "e4m3", "sphere_pos": "e4m3", "sphere_dist": "e4m3", "sphere_grad": "e5m2",
+                "joint_grad": "e5m2"},
+    "mixed_fp4": {"link_poses": "e4m3", "sphere_pos": "e4m3", "sphere_dist": "e2m1", "sphere_grad": "e2m1",
+                  "joint_grad": "e4m3"},
+}
+
+
+def calibrated(ctx, wl, assignment):
+    from paper_2310_07854_amd.search import spec
+
+    shape = shape_of(wl)
+    q = dev(wl.q, torch.float32)
+    ctx.set_precision({})
+    _, ws = ctx.cost_fwd(q, shape)
+    ctx.cost_bwd(q, ws, want_grad=False)
+    amax = {t: float(ctx.ws_export(t, ws, shape).view(torch.float32).abs().max()) for t in OC.TENSORS}
+    return spec(assignment, amax, ctx.reach())
+
+
+@pytest.mark.parametrize("name", list(ASSIGNMENTS))
+def test_error_within_twice_the_budget(name):
+    need_gpu()
+    wl = make_workload("batched")
+    ctx = make_context(wl)
+    prec = calibrated(ctx, wl, ASSIGNMENTS[name])
+    ctx.set_precision(prec)
+    shape = shape_of(wl)
+    q = dev(wl.q, torch.float32)
+    cost, ws = ctx.cost_fwd(q, shape)
+    grad = ctx.cost_bwd(q, ws)
+    torch.cuda.synchronize()
+    cost, grad = cost.cpu().numpy(), grad.cpu().numpy()
+    # 16 sampled trajectory candidates, each with its own world
+    T = wl.T
+    rng = np.random.default_rng(7)
+    tcs = np.sort(rng.choice(shape.n_tc, 16, replace=False))
+    rows = np.concatenate([np.arange(tc * T, (tc + 1) * T) for tc in tcs])
+    worlds = [(tc // wl.n_ls) // wl.traj_per_world for tc in tcs]
+    sub = Worlds(pose=wl.worlds.pose[worlds], half_ext=wl.worlds.half_ext[worlds])
+    oprec = OC.Precision(**{t: tuple(v) for t, v in prec.items()})
+    bud = BG.error_budget(wl.robot, sub, wl.q[rows], 1, T, 1, oprec)
+    ref = bud["ref"]
+    dc = np.abs(cost[tcs] - ref["cost_traj"])
+    cbound = 2.0 * bud["cost"] + cost_tolerance(ref, wl.robot.n_pairs, T)
+    assert np.all(dc <= cbound), (dc / cbound).max()
+    # gradients of configurations away from the kinks (closest cuboid, inside axis, OBB region)
+    active = ref["D"] > 0
+    ok = (np.where(active, ref["margin"], np.inf).min(axis=1) > 1e-3)
+    ok &= BG.hessian_margin(ref, sub.pose, sub.half_ext) > 1e-3
+    dg = np.abs(grad[rows] - ref["J"])
+    gbound = 2.0 * bud["grad"] + grad_tolerance(ref)
+    assert ok.sum() >= 64, int(ok.sum())
+    assert np.all((dg <= gbound)[ok]), (dg / gbound)[ok].max()
+    print(f"[budget] {name} {prec}: cost error / budget max {(dc / bud['cost']).max():.3f}; gradient error / "
+          f"budget max {(dg / bud['grad'])[ok].max():.3f} over {int(ok.sum())} kink-free configurations, "
+          f"relative L2 {np.linalg.norm(dg) / np.linalg.norm(ref['J']):.2e}")
+    ctx.close()

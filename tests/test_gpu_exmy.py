@@ -64,7 +64,9 @@ def test_emulated_equals_storage_format_end_to_end(native, emulated):
 def test_emulated_assignment_matches_oracle():
     """A mixed assignment of emulated types (one per tensor, with scales) against the oracle's
     emulation: stored positions equal the oracle's rounding of a value within the FP32 error of the
-    exact one, costs within the usual bound, gradients where the stored positions agree."""
+    exact one, costs within the usual bound; on kink-free configurations whose stored positions,
+    poses and sphere gradients equal the oracle's, the stored joint gradient is the rounding of a
+    value within the FP32 gradient band of the oracle's."""
     need_gpu()
     wl = make_workload("batched")
     prec = {"link_poses": "e5m9", "sphere_pos": "e6m6", "sphere_dist": ("e3m1", -4), "sphere_grad": ("e2m2", 3),
@@ -93,6 +95,22 @@ def test_emulated_assignment_matches_oracle():
     extra = (2.0 * OC.CostParams().w_coll * ref["D_hat"] * dstep).sum(axis=1).reshape(-1, wl.T).sum(axis=1)
     assert np.all(np.abs(c - ref["cost_traj"])[ok_tc] <= (ctol + extra)[ok_tc])
     assert np.abs(ref["J_hat"]).max() > 0 and np.isfinite(grad).all()
+    # gradients: identical stored inputs to the adjoint leave only FP32 arithmetic before J's rounding
+    def stored(name, key):
+        v = ctx.ws_export(name, ws, shape).view(torch.float32).cpu().numpy().astype(np.float64)
+        return np.all(v.reshape(shape.B, -1) == ref[key].reshape(shape.B, -1), axis=1)
+    rows = same & stored("link_poses", "L_hat") & stored("sphere_grad", "G_hat") & kink_free(ref)
+    assert rows.mean() > 0.3, rows.mean()
+    tol = grad_tolerance(ref)
+    E, M = X.parse(prec["joint_grad"][0])
+    kj = prec["joint_grad"][1]
+    lo = X.roundtrip(ref["J"] - tol, E, M, kj)[1]
+    hi = X.roundtrip(ref["J"] + tol, E, M, kj)[1]
+    g = grad.astype(np.float64)
+    ok = (g >= np.minimum(lo, hi)) & (g <= np.maximum(lo, hi))
+    assert ok[rows].all(), int((~ok[rows]).sum())
+    print(f"[exmy] gradients of {int(rows.sum())}/{shape.B} configurations compared, "
+          f"{int((g != ref['J_hat'])[rows].sum())} stored values one step from the oracle's")
 
 
 def test_exmy_rejected_where_codes_are_needed():

@@ -18,7 +18,7 @@ from oracle import formats as F
 from oracle.geometry import obb_signed_distance
 from synthetic import Worlds, make_configs, make_robot, make_workload, make_worlds
 from synthetic.generators import Workload
-from tests.gpu_helpers import (ORACLE_KEY, TENSORS, compare_codes, cost_tolerance, dev, export_codes, grad_tolerance,
+from tests.gpu_helpers import (ORACLE_KEY, TENSORS, cfg_cost_tolerance, compare_codes, cost_tolerance, dev, export_codes, grad_tolerance,
                                import_codes, kink_free, make_context, need_gpu, oracle_precision, shape_of, torch)
 
 pytestmark = pytest.mark.gpu
@@ -32,8 +32,13 @@ PRECISIONS = {
             "sphere_grad": ("e3m2", 2), "joint_grad": ("e3m2", 6)},
     "mixed_fp4": {"link_poses": ("e4m3", -7), "sphere_pos": ("e4m3", -7), "sphere_dist": ("e2m1", -3),
                   "sphere_grad": ("e2m1", 5), "joint_grad": ("e4m3", 2)},
-    "paper_like": {"link_poses": "f16", "sphere_pos": "f16", "sphere_dist": ("e2m1", -3),
-                   "sphere_grad": ("e2m1", 5), "joint_grad": ("e4m3", 2)},
+    # FP16 poses and positions with FP4 distances and sphere gradients
+    "f16_fp4": {"link_poses": "f16", "sphere_pos": "f16", "sphere_dist": ("e2m1", -3),
+                "sphere_grad": ("e2m1", 5), "joint_grad": ("e4m3", 2)},
+    # the benchmark's headline assignment with the scales it calibrates on the 196,608-configuration
+    # batch: poses and positions from the arm's reach, the rest from their FP32 magnitude
+    "paper_like": {"link_poses": ("f16", -15), "sphere_pos": ("f16", -15), "sphere_dist": ("e4m3", -10),
+                   "sphere_grad": ("e4m3", -1), "joint_grad": ("e4m3", 0)},
 }
 
 
@@ -75,6 +80,10 @@ def check_fp32(wl, ref, cost, grad, min_checked=0.5):
     bad = (gerr > gtol).any(axis=1) & ok
     assert not bad.any(), f"grad: {int(bad.sum())} configs out of tolerance, max err {gerr[ok].max():.3e}"
     assert ok.mean() > min_checked
+    # the acceptance band 1e-4 (|g|_inf + 1e-3) per configuration, reported beside the test's band
+    acc = 1e-4 * (np.abs(ref["grad_q"]).max(axis=1, keepdims=True) + 1e-3)
+    print(f"[fp32] cost err/bound {(err / tol).max():.3f}; grad err/band {(gerr / gtol)[ok].max():.3f}, "
+          f"err/acceptance {(gerr / acc)[ok].max():.3f} over {int(ok.sum())} configurations")
 
 
 @pytest.mark.parametrize("name", ["tiny", "batched"])
@@ -251,8 +260,13 @@ def _sampled_oracle(wl, tcs, prec):
     return ref, rows
 
 
-@pytest.mark.parametrize("pname", ["f32", "fp8"])
+@pytest.mark.parametrize("pname", ["f32", "paper_like"])
 def test_large_batch_sampled(pname):
+    """The full 196,608-configuration batch in the benchmark's launch configuration, compared on 12
+    sampled trajectories (the last one included) with the oracle.  FP32: costs and gradients within
+    the FP32 bounds.  Headline assignment: every stored code of all five tensors, stage by stage --
+    S everywhere, D and G on configurations whose S codes equal the oracle's, J where L, S and G
+    do -- then costs where S and D agree and gradients (the dequantised J) as codes."""
     need_gpu()
     prec = {} if pname == "f32" else PRECISIONS[pname]
     wl = make_workload("large")
@@ -265,11 +279,42 @@ def test_large_batch_sampled(pname):
     if pname == "f32":
         sub = dataclasses.replace(wl, q=wl.q[rows])
         check_fp32(sub, ref, cost[tcs], grad[rows])
-    else:
-        S = export_codes(ctx, "sphere_pos", ws, shape).reshape(shape.B, -1)[rows]
-        fmt, k = ctx.precision["sphere_pos"]
-        compare_codes("sphere_pos", fmt, k, S, ref["S_codes"], ref["S"])
-        assert np.all(np.isfinite(cost)) and np.all(np.isfinite(grad))
+        ctx.close()
+        return
+    B = len(rows)
+    codes = {name: export_codes(ctx, name, ws, shape).reshape(shape.B, -1)[rows] for name in TENSORS}
+    same = {}
+    for name in TENSORS:
+        key = ORACLE_KEY[name]
+        fmt, k = ctx.precision[name]
+        want = ref[key + "_codes"].reshape(B, -1)
+        if name in ("link_poses", "sphere_pos"):
+            rows_ok = np.ones(B, dtype=bool)
+        elif name in ("sphere_dist", "sphere_grad"):
+            rows_ok = same["sphere_pos"]
+        else:
+            rows_ok = same["sphere_pos"] & same["sphere_grad"] & same["link_poses"]
+        kink = np.repeat(((ref["D"] > 0) & (ref["margin"] < 1e-4))[..., None], 3, axis=2).reshape(B, -1)
+        ex = (kink if name == "sphere_grad" else np.zeros_like(want, dtype=bool)) | ~rows_ok[:, None]
+        compare_codes(name, fmt, k, codes[name], want, ref[key].reshape(B, -1), ex)
+        same[name] = np.all(codes[name] == want, axis=1) & rows_ok
+        assert rows_ok.mean() > 0.5, (name, rows_ok.mean())
+    # configuration costs where the configuration's S and D codes all equal the oracle's: FP32 bound
+    cfg = torch.empty(shape.B, dtype=torch.float32, device="cuda:0")
+    ctx.cost_fwd(dev(wl.q, torch.float32), shape, ws=ws, cost_cfg=cfg)
+    cfg = cfg.cpu().numpy()[rows].astype(np.float64)
+    c_ok = same["sphere_pos"] & same["sphere_dist"]
+    tol = cfg_cost_tolerance(ref, wl.robot.n_pairs)
+    err = np.abs(cfg - ref["cfg_cost"])
+    assert c_ok.mean() > 0.5 and np.all(err[c_ok] <= tol[c_ok]), (c_ok.mean(), (err / tol)[c_ok].max())
+    print(f"[large/{pname}] configuration cost error / bound max {(err / tol)[c_ok].max():.3f} over "
+          f"{int(c_ok.sum())}/{B}; J rows compared {int(same['joint_grad'].sum())}/{B}")
+    # the gradient handed to torch is the dequantised stored J
+    fmt, k = ctx.precision["joint_grad"]
+    np.testing.assert_array_equal(grad[rows].astype(np.float64).reshape(-1),
+                                  F.dequantize(codes["joint_grad"].reshape(-1), fmt, k))
+    assert np.all(np.isfinite(cost)) and np.all(np.isfinite(grad))
+    ctx.close()
 
 
 def test_deterministic():
@@ -505,3 +550,62 @@ def test_seed_deviations_invert_trajectories():
     tr = traj.cpu().numpy().reshape(n, 8, 32, 7).astype(np.float64)
     assert np.all(np.abs(got - want) <= np.spacing(np.abs(tr).astype(np.float32)).astype(np.float64) * 1.01)
     assert np.all(got[:, :, 0] == 0) and np.all(got[:, :, 31] == 0)
+
+
+def test_scale_overflow_guard_and_far_reach():
+    """FP16 sphere positions at a scale the arm can leave (2^-16, what a sampled calibration picks
+    for the benchmark arm: at most 0.9995 m) are refused before any launch; at the scale of the
+    arm's reach, configurations beyond that range are stored finite, and the cuboids placed on their
+    farthest spheres cost what the oracle's emulation gives."""
+    need_gpu()
+    from oracle.kinematics import forward_kinematics, sphere_positions
+    from paper_2310_07854_amd import Shape, VaprError, _lib as L
+
+    from paper_2310_07854_amd.search import scale_for
+
+    # the benchmark arm with its links stretched by 40 %: some configurations pass 1 m
+    robot = make_workload("batched").robot
+    stretched = robot.fixed_tf.copy()
+    stretched[:, :, 3] *= 1.4
+    robot = dataclasses.replace(robot, fixed_tf=F.fp32(stretched).astype(np.float64))
+    rng = np.random.default_rng(12)
+    q = rng.uniform(-2.9, 2.9, size=(20000, 7))
+    P = sphere_positions(forward_kinematics(robot.fixed_tf, q), robot.sphere_center, robot.sphere_link)
+    far = np.abs(P).max(axis=(1, 2))
+    pick = np.argsort(far)[-8:]
+    assert far[pick].min() > 65504.0 * 2.0 ** -16, far[pick]
+    qs = F.fp32(q[pick]).astype(np.float64)
+    # one world, a cuboid on each configuration's farthest sphere
+    Ps = sphere_positions(forward_kinematics(robot.fixed_tf, qs), robot.sphere_center, robot.sphere_link)
+    idx = np.abs(Ps).max(axis=2).argmax(axis=1)
+    pose = np.zeros((1, 8, 3, 4))
+    pose[0, :, :, :3] = np.eye(3)
+    pose[0, :, :, 3] = Ps[np.arange(8), idx]
+    worlds = Worlds(pose=F.fp32(pose).astype(np.float64), half_ext=np.full((1, 8, 3), 0.05))
+    wl2 = Workload("far", robot, worlds, 1, 8, 1, qs)
+    ctx = make_context(wl2)
+    lp, sp = ctx.reach()
+    assert sp >= far.max()
+    shape = Shape(1, 1, 8, 1)
+    qd = dev(qs, torch.float32)
+    ctx.set_precision({"sphere_pos": ("f16", -16)})
+    with pytest.raises(VaprError) as e:
+        ctx.cost_fwd(qd, shape)
+    assert e.value.status == L.E_INVALID and "reach" in str(e.value)
+    ks = scale_for("f16", sp)
+    prec = {"link_poses": ("f16", scale_for("f16", lp)), "sphere_pos": ("f16", ks), "sphere_dist": ("e4m3", -10),
+            "sphere_grad": ("e4m3", -1), "joint_grad": ("e4m3", 0)}
+    ctx.set_precision(prec)
+    cost, ws = ctx.cost_fwd(qd, shape)
+    grad = ctx.cost_bwd(qd, ws)
+    torch.cuda.synchronize()
+    S = ctx.ws_export("sphere_pos", ws, shape)
+    Sv = F.dequantize(F.unpack(S.cpu().numpy(), "f16", shape.B * robot.sphere_radius.shape[0] * 3), "f16", ks)
+    assert np.all(np.isfinite(Sv)) and np.abs(Sv).max() > 0.9995
+    ref = run_oracle(wl2, prec)
+    Dg = export_codes(ctx, "sphere_dist", ws, shape).reshape(shape.B, -1)
+    assert np.all(F.dequantize(Dg[np.arange(8), idx], "e4m3", -10) > 0)   # the far spheres collide
+    tol = cost_tolerance(ref, robot.n_pairs, 8)
+    c = cost.cpu().numpy()
+    assert np.all(np.abs(c - ref["cost_traj"]) <= tol) and np.all(np.isfinite(grad.cpu().numpy()))
+    ctx.close()

@@ -10,7 +10,7 @@ from tests.gpu_helpers import dev, make_context, need_gpu, torch
 
 pytestmark = pytest.mark.gpu
 
-PAPER_LIKE = {"link_poses": ("f16", -15), "sphere_pos": ("f16", -16), "sphere_dist": ("e4m3", -10),
+PAPER_LIKE = {"link_poses": ("f16", -15), "sphere_pos": ("f16", -15), "sphere_dist": ("e4m3", -10),
               "sphere_grad": ("e4m3", -1), "joint_grad": ("e4m3", 0)}
 
 
