@@ -318,6 +318,48 @@ def copy_bandwidth(torch, mib=1024, runs=20):
     return 2.0 * mib * (1 << 20) / (med * 1e-3) / 1e9
 
 
+def cold_kernels(torch, ctx, opt_cls, x0, prec, recompute=False, reps=10, flush_mib=1024):
+    """Per-kernel durations with the caches emptied before each measured launch: a 1 GiB buffer is
+    written first, so the kernel finds none of its inputs in the 4 MB L2 of each XCD or the 256 MB
+    Infinity Cache and reads them from HBM.  Each kernel is reached through the call that launches it
+    first: the forward pass from stage 1 (k_fk), 2 (k_sphere_cost) and 3 (k_reduce), the backward
+    pass (k_adjoint) and the optimiser update after an evaluated iteration (k_optimizer).  HIP events
+    around each launch; the mean over `reps`, cold and warm (the same call without the flush)."""
+    ctx.set_precision(prec, recompute_poses=recompute)
+    opt = opt_cls(ctx, N_WORLDS, TPW, T, n_ls=N_LS, m=HIST_M)
+    opt.init(x0)
+    for _ in range(3):
+        opt.step()
+    flush = torch.empty(flush_mib << 18, dtype=torch.float32, device="cuda:0")
+    q, shape, ws, cost = opt.q_cand, opt.shape, opt.ws, opt.cost_cand
+    calls = {
+        "fk": (None, lambda: ctx.cost_fwd(q, shape, ws=ws, cost_traj=cost, first=1)),
+        "sphere_cost": (None, lambda: ctx.cost_fwd(q, shape, ws=ws, cost_traj=cost, first=2)),
+        "reduce": (None, lambda: ctx.cost_fwd(q, shape, ws=ws, cost_traj=cost, first=3)),
+        "adjoint": (None, lambda: ctx.cost_bwd(q, ws, want_grad=False)),
+        "optimizer": (opt.evaluate, opt.update),
+    }
+    out = {}
+    for name, (before, call) in calls.items():
+        res = {}
+        for mode in ("cold", "warm"):
+            total = 0.0
+            for i in range(reps):
+                if before is not None:
+                    before()
+                if mode == "cold":
+                    flush.fill_(float(i))
+                ctx.profile_enable(True)
+                call()
+                ms, n = ctx.profile_read()[name]
+                ctx.profile_enable(False)
+                total += ms / max(n, 1)
+            res[mode + "_us"] = total / reps * 1e3
+        out[name] = res
+    del flush, opt
+    return out
+
+
 def run_variant(torch, ctx, opt_cls, x0, prec, steps, warmup, want_opt=False, recompute=False):
     """`warmup` untimed iterations, then `steps` timed ones with nothing but the iteration's own
     launches in the stream (the step time), then `steps` more with HIP events recorded around every
@@ -343,38 +385,111 @@ def run_variant(torch, ctx, opt_cls, x0, prec, steps, warmup, want_opt=False, re
     return (t1 - t0), prof, cost, (opt if want_opt else None)
 
 
-def cpu_baseline(prec, budget_s=12.0):
-    """The FP64 oracle (quantisation emulated at the same five tensors) timed on the host for one
-    optimisation iteration of a sample of whole trajectories, single-threaded."""
+def _oracle_trajectories(prec_kw, start, count):
+    """One optimisation iteration of the FP64 oracle (quantisation emulated) over trajectories
+    start .. start + count - 1 of the benchmark batch, each in its world; returns the seconds."""
+    from threadpoolctl import threadpool_limits
+
     from oracle import cost as OC
     from oracle import optimizer as OO
-    from synthetic import make_robot, make_trajectories, make_worlds
+    from synthetic import Worlds, make_robot, make_trajectories, make_worlds
 
     robot = make_robot(N_SPHERES, N_PAIRS)
     worlds = make_worlds(N_WORLDS, N_CUBOIDS)
-    traj = make_trajectories(N_WORLDS, TPW, T)  # [W, S, T, 7]
-    kw = {t: ((v, 0) if isinstance(v, str) else tuple(v)) for t, v in prec.items()}
-    oprec = OC.Precision(**kw)
-
-    def one(n_traj):
-        # trajectories 0..n_traj-1 of world 0.. in order; candidates = current points (N_LS = 1)
-        x = traj.reshape(-1, T, 7)[:n_traj]
-        wl_pose = worlds.pose[np.arange(n_traj) // TPW]
-        wl_half = worlds.half_ext[np.arange(n_traj) // TPW]
-        from synthetic import Worlds
-        sub = Worlds(pose=wl_pose, half_ext=wl_half)
+    traj = make_trajectories(N_WORLDS, TPW, T).reshape(-1, T, 7)
+    oprec = OC.Precision(**prec_kw)
+    idx = np.arange(start, start + count)
+    sub = Worlds(pose=worlds.pose[idx // TPW], half_ext=worlds.half_ext[idx // TPW])
+    x = traj[idx]
+    with threadpool_limits(limits=1):
         t0 = time.perf_counter()
         out = OC.fwd_bwd(robot, sub, x.reshape(-1, 7), 1, T, N_LS, prec=oprec)
-        for i in range(n_traj):
+        for i in range(count):
             st = OO.TrajState(x=x[i].reshape(-1), g=np.zeros(T * 7), d=-np.ones(T * 7) * 1e-3,
                               cost=float(out["cost_traj"][i]) + 1.0)
-            OO.step(st, out["cost_traj"][i:i + 1], out["grad_q"].reshape(n_traj, 1, -1)[i], T, HIST_M)
+            OO.step(st, out["cost_traj"][i:i + 1], out["grad_q"].reshape(count, 1, -1)[i], T, HIST_M)
         return time.perf_counter() - t0
 
-    n, dt = timed_sample(one, N_WORLDS * TPW, budget_s)
-    return {"value": n * T * N_LS / dt, "unit": "evals/s", "cores": 1, "kind": "oracle",
+
+def _host_cpu():
+    """(usable cores, CPU model) of this host."""
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return cores, model
+
+
+def cpu_baseline(prec, budget_s=12.0, all_core_s=10.0, max_workers=16):
+    """The FP64 oracle (quantisation emulated at the same five tensors) timed on the host for one
+    optimisation iteration of a sample of whole trajectories: single-threaded, and on all usable
+    cores (up to max_workers processes, one thread each, started fresh: no GPU state is inherited)."""
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+
+    prec_kw = {t: ((v, 0) if isinstance(v, str) else tuple(v)) for t, v in prec.items()}
+    n, dt = timed_sample(lambda k: _oracle_trajectories(prec_kw, 0, k), N_WORLDS * TPW, budget_s)
+    single = n * T * N_LS / dt
+    cores, model = _host_cpu()
+    workers = max(1, min(cores, max_workers))
+    per_traj = dt / n
+    chunk = max(4, int(0.5 / per_traj))  # about half a second per task
+    n_all = int(min(N_WORLDS * TPW, all_core_s * workers / per_traj)) // chunk * chunk
+    n_all = max(n_all, chunk)
+    tasks = [(prec_kw, s0, chunk) for s0 in range(0, n_all, chunk)]
+    # a worker that dies raises BrokenProcessPool here instead of leaving the map waiting
+    with ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as pool:
+        list(pool.map(_oracle_trajectories, *zip(*[(prec_kw, 0, 2)] * workers), timeout=300))  # imports
+        t0 = time.perf_counter()
+        list(pool.map(_oracle_trajectories, *zip(*tasks), timeout=600))
+        wall = time.perf_counter() - t0
+    return {"value": single, "unit": "evals/s", "cores": 1, "kind": "oracle",
             "sample": f"{n} trajectories x {T} timesteps = {n * T} configurations, one iteration, "
-                      f"{dt:.1f} s single-threaded"}
+                      f"{dt:.1f} s single-threaded",
+            "all_cores": {"value": n_all * T * N_LS / wall, "unit": "evals/s", "cores": workers,
+                          "host_cores": cores, "cpu_model": model,
+                          "sample": f"{n_all} trajectories in {len(tasks)} tasks of {chunk}, {wall:.1f} s on "
+                                    f"{workers} processes"}}
+
+
+def error_vs_fp64(prec, gpu):
+    """Error of the GPU's cost and gradient against the unquantised FP64 oracle on sampled
+    trajectories of the benchmark batch (at its initial trajectories), with the oracle's first-order
+    error budget of the assignment: cost error relative to |cost| (max, median) and to the budget;
+    gradient error relative in L2 over the sample and, on configurations away from the kinks (where
+    a rounding of the sphere centres cannot switch a branch of the cost), to the budget (max, 99th
+    percentile)."""
+    from oracle import budget as BG
+    from oracle import cost as OC
+    from synthetic import Worlds, make_robot, make_trajectories, make_worlds
+
+    robot = make_robot(N_SPHERES, N_PAIRS)
+    worlds = make_worlds(N_WORLDS, N_CUBOIDS)
+    traj = make_trajectories(N_WORLDS, TPW, T).reshape(-1, T, 7)
+    tr = gpu["traj"]
+    sub = Worlds(pose=worlds.pose[tr // TPW], half_ext=worlds.half_ext[tr // TPW])
+    oprec = OC.Precision(**{t: ((v, 0) if isinstance(v, str) else tuple(v)) for t, v in prec.items()})
+    t0 = time.perf_counter()
+    bud = BG.error_budget(robot, sub, traj[tr].reshape(-1, 7), 1, T, 1, oprec)
+    ref = bud["ref"]
+    dc = np.abs(gpu["cost"] - ref["cost_traj"])
+    dg = np.abs(gpu["grad"] - ref["J"])
+    ok = BG.smooth_configurations(robot, ref, sub.pose, sub.half_ext, BG.position_gap(oprec, ref))
+    gr = (dg / bud["grad"])[ok]
+    return {"trajectories": int(len(tr)), "configurations": int(len(tr) * T),
+            "cost_max_rel": float(np.max(dc / np.abs(ref["cost_traj"]))),
+            "cost_med_rel": float(np.median(dc / np.abs(ref["cost_traj"]))),
+            "grad_rel_l2": float(np.linalg.norm(dg) / np.linalg.norm(ref["J"])),
+            "budget_ratio": {"cost_max": float(np.max(dc / bud["cost"])),
+                             "grad_max": float(gr.max()) if gr.size else None,
+                             "grad_p99": float(np.percentile(gr, 99)) if gr.size else None,
+                             "grad_configurations": int(ok.sum())},
+            "oracle_seconds": time.perf_counter() - t0}
 
 
 def timed_sample(one, n_max, budget_s):
@@ -1030,7 +1145,6 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--precision", default="paper_like", choices=[k for k in PRECISIONS if k != "f32"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--variants", action="store_true", help="also time every other assignment")
     ap.add_argument("--seeding", action="store_true", help="run the learned-seeder study instead")
     ap.add_argument("--seed-infer", action="store_true", help="time the seeding network's inference instead")
     ap.add_argument("--swept", type=int, default=0, help="time the step with the swept term (k samples) instead")
@@ -1109,36 +1223,54 @@ def main():
                           "kernels_us": {k: v[0] / max(v[1], 1) * 1e3 for k, v in prof.items() if v[1]}}))
         ctx.close()
         return
+    # every named assignment, stored poses and recomputed in the backward pass; FP32 only stored
     results = {}
-    names = ["f32", args.precision] + ([k for k in PRECISIONS if k not in ("f32", args.precision)]
-                                       if args.variants else [])
+    names = ["f32", args.precision] + [k for k in PRECISIONS if k not in ("f32", args.precision)]
     culled = None
     for name in names:
-        main = name == args.precision
-        dt, prof, cost, opt = run_variant(torch, ctx, TrajectoryOptimizer, x0, precs[name], args.steps,
-                                          args.warmup, want_opt=main)
-        results[name] = {"seconds": dt, "prof": prof, "cost": cost}
-        if main:
-            culled = culled_work(ctx, opt, precs[name])
-            del opt
-        print(f"# {name}: {dt / args.steps * 1e3:.3f} ms/step, {B * args.steps / dt / 1e6:.1f} M evals/s, "
-              f"kernels " + ", ".join(f"{k} {v[0] / max(v[1], 1) * 1e3:.1f}us" for k, v in prof.items() if v[1]),
-              file=sys.stderr, flush=True)
+        for recompute in ((False,) if name == "f32" else (False, True)):
+            main = name == args.precision and not recompute
+            dt, prof, cost, opt = run_variant(torch, ctx, TrajectoryOptimizer, x0, precs[name], args.steps,
+                                              args.warmup, want_opt=main, recompute=recompute)
+            results[(name, recompute)] = {"seconds": dt, "prof": prof, "cost": cost}
+            if main:
+                culled = culled_work(ctx, opt, precs[name])
+                del opt
+            print(f"# {name}{' recompute' if recompute else ''}: {dt / args.steps * 1e3:.3f} ms/step, "
+                  f"{B * args.steps / dt / 1e6:.1f} M evals/s, kernels "
+                  + ", ".join(f"{k} {v[0] / max(v[1], 1) * 1e3:.1f}us" for k, v in prof.items() if v[1]),
+                  file=sys.stderr, flush=True)
+            if not math.isfinite(cost):
+                raise RuntimeError(f"{name}: non-finite total cost after the timed steps")
 
-    # recompute-in-backward for the main assignment: the step without the link-pose tensor
-    dt_rc, prof_rc, _, _ = run_variant(torch, ctx, TrajectoryOptimizer, x0, precs[args.precision], args.steps,
-                                       args.warmup, recompute=True)
-    print(f"# {args.precision} recompute: {dt_rc / args.steps * 1e3:.3f} ms/step, "
-          f"{B * args.steps / dt_rc / 1e6:.1f} M evals/s, kernels "
-          + ", ".join(f"{k} {v[0] / max(v[1], 1) * 1e3:.1f}us" for k, v in prof_rc.items() if v[1]),
-          file=sys.stderr, flush=True)
     fwd_bwd = {name: fwd_bwd_timing(torch, ctx, x0, precs[name]) for name in ("f32", args.precision)}
     fwd_bwd[args.precision + "_recompute"] = fwd_bwd_timing(torch, ctx, x0, precs[args.precision], True)
     copy_gbs = copy_bandwidth(torch)
+    cold = {name: cold_kernels(torch, ctx, TrajectoryOptimizer, x0, precs[name]) for name in ("f32", args.precision)}
+    print("# cold/warm us: " + "; ".join(f"{n} " + ", ".join(f"{k} {v['cold_us']:.1f}/{v['warm_us']:.1f}"
+                                                          for k, v in c.items()) for n, c in cold.items()),
+          file=sys.stderr, flush=True)
 
-    main_r = results[args.precision]
-    f32_r = results["f32"]
+    # the headline assignment's cost and gradient at the initial trajectories, for the error of
+    # sampled trajectories against the FP64 oracle (cpu_baseline leg)
+    from paper_2310_07854_amd import Shape
+
+    ctx.set_precision(precs[args.precision])
+    shape1 = Shape(N_WORLDS, TPW, T, 1)
+    q0 = x0.reshape(-1, 7).contiguous()
+    c0, ws0 = ctx.cost_fwd(q0, shape1)
+    g0 = ctx.cost_bwd(q0, ws0)
+    err_tr = np.sort(np.random.default_rng(2310).choice(N_WORLDS * TPW, 16, replace=False))
+    err_rows = (err_tr[:, None] * T + np.arange(T)[None, :]).reshape(-1)
+    gpu_sample = {"traj": err_tr, "cost": c0.cpu().numpy()[err_tr], "grad": g0.cpu().numpy()[err_rows]}
+    del ws0
+
+    main_r = results[(args.precision, False)]
+    f32_r = results[("f32", False)]
+    rc_r = results[(args.precision, True)]
     dt = main_r["seconds"]
+    dt_rc = rc_r["seconds"]
+    prof_rc = rc_r["prof"]
     value = B * args.steps / dt
     value_f32 = B * args.steps / f32_r["seconds"]
     prec = precs[args.precision]
@@ -1151,6 +1283,13 @@ def main():
         entry = {"avg_us": avg_s * 1e6, "launches": n}
         if k in kb:
             entry["algorithmic_GBs"] = kb[k] * B / avg_s / 1e9
+        if k in cold[args.precision]:
+            cu = cold[args.precision][k]["cold_us"]
+            entry["cold_us"] = cu
+            if k in kb:
+                entry["cold_algorithmic_GBs"] = kb[k] * B / (cu * 1e-6) / 1e9
+                entry["cold_frac_of_peak"] = entry["cold_algorithmic_GBs"] / HBM_PEAK_GBS
+                entry["cold_frac_of_copy"] = entry["cold_algorithmic_GBs"] / copy_gbs
         per_kernel[k] = entry
     dom = max(per_kernel, key=lambda k: per_kernel[k]["avg_us"] * per_kernel[k]["launches"])
     dom_s = per_kernel[dom]["avg_us"] * 1e-6
@@ -1170,6 +1309,16 @@ def main():
                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS}
     roofline["traffic"] = (traffic or {}).get("bytes_per_launch", {}).get(roofline["kernel"]) if traffic else None
 
+    def kernels_us(prof):
+        return {k: v[0] / max(v[1], 1) * 1e3 for k, v in prof.items() if v[1]}
+
+    variants = {}
+    for (name, recompute), r in results.items():
+        v = B * args.steps / r["seconds"]
+        variants[name + ("_recompute" if recompute else "")] = {
+            "value": v, "ms_per_step": r["seconds"] / args.steps * 1e3,
+            "speedup_vs_fp32_pct": (v / value_f32 - 1.0) * 100.0,
+            "formats": {k: list(f) for k, f in precs[name].items()}, "kernels_us": kernels_us(r["prof"])}
     step_bytes = sum(kb[k] for k in kb) * B
     line = {
         "metric": "cost fwd+bwd evals/s (one optimiser iteration per step), variable precision vs FP32",
@@ -1189,26 +1338,28 @@ def main():
                    "precision": args.precision, "formats": {k: list(v) for k, v in prec.items()},
                    "recompute_poses": False},
         "fp32_value": value_f32,
+        # the paper's definition: (t_FP32 / t_X - 1) * 100 %
         "speedup_vs_fp32_pct": (value / value_f32 - 1.0) * 100.0,
         "hbm_algorithmic_GBs": step_bytes / (dt / args.steps) / 1e9,
         "kernels": per_kernel,
-        "fp32_kernels": {k: v[0] / max(v[1], 1) * 1e3 for k, v in f32_r["prof"].items() if v[1]},
+        "fp32_kernels": kernels_us(f32_r["prof"]),
         "roofline": roofline,
         "recompute_value": B * args.steps / dt_rc,
-        "recompute_kernels": {k: v[0] / max(v[1], 1) * 1e3 for k, v in prof_rc.items() if v[1]},
+        "recompute_kernels": kernels_us(prof_rc),
+        "variants": variants,
+        "cold_kernels": cold,
         "fwd_bwd": fwd_bwd,
         "copy_GBs": copy_gbs,
         "copy_frac_of_peak": copy_gbs / HBM_PEAK_GBS,
     }
-    for name in results:
-        if name not in ("f32", args.precision):
-            line.setdefault("variants", {})[name] = B * args.steps / results[name]["seconds"]
     ctx.close()
     line["batched"] = batched_workload(torch, max(args.steps, 50), args.warmup)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(prec)
+        line["error_vs_fp64"] = error_vs_fp64(prec, gpu_sample)
     else:
         line["cpu_baseline"] = None
+        line["error_vs_fp64"] = None
     print(json.dumps(line), flush=True)
 
 

@@ -224,5 +224,34 @@ def hessian_margin(ref: Dict[str, np.ndarray], pose: np.ndarray, half_ext: np.nd
     return m
 
 
+def smooth_configurations(robot, ref: Dict[str, np.ndarray], pose: np.ndarray, half_ext: np.ndarray,
+                          gap: float, eta: float = CostParams().eta) -> np.ndarray:
+    """[B] bool: configurations whose cost and gradient are smooth within `gap` of the unquantised
+    sphere centres -- every active sphere's closest cuboid, inside axis and OBB region unambiguous by
+    more than gap, every active depth and every self-pair activation more than gap from zero.  The
+    first-order budget describes the rounding error only there; elsewhere a rounding within gap may
+    switch a branch of the cost."""
+    d = ref["D"]
+    active = d > 0
+    ok = np.where(active, ref["margin"], np.inf).min(axis=1) > gap
+    ok &= hessian_margin(ref, pose, half_ext) > gap
+    ok &= ~np.any(active & (d < gap), axis=1)
+    pairs = np.asarray(robot.pairs).reshape(-1, 2)
+    if pairs.shape[0]:
+        r = np.asarray(robot.sphere_radius, dtype=np.float64)
+        S = ref["S"]
+        dist = np.linalg.norm(S[:, pairs[:, 0]] - S[:, pairs[:, 1]], axis=-1)
+        act = eta - (dist - r[pairs[:, 0]] - r[pairs[:, 1]])
+        ok &= ~np.any(np.abs(act) < gap, axis=1)
+    return ok
+
+
+def position_gap(prec: Precision, ref: Dict[str, np.ndarray]) -> float:
+    """Four times the largest rounding of a sphere centre under `prec` (at least 1 mm): the `gap` of
+    smooth_configurations for this assignment."""
+    f, k = prec.get("sphere_pos")
+    return max(1e-3, 4.0 * float(np.max(half_ulp(ref["S"], f, k))))
+
+
 __all__ = ["half_ulp", "world_hessian", "pair_hessian", "jacobian_columns", "sensitivities", "error_budget",
-           "hessian_margin", "world_index"]
+           "hessian_margin", "smooth_configurations", "position_gap", "world_index"]

@@ -71,8 +71,16 @@ class TrajectoryOptimizer:
 
     def step(self) -> None:
         """One iteration: evaluate all candidates (fwd + bwd), select, update, next candidates."""
+        self.evaluate()
+        self.update()
+
+    def evaluate(self) -> None:
+        """The iteration's forward and backward pass over every candidate."""
         self.vctx.cost_fwd(self.q_cand, self.shape, ws=self.ws, cost_traj=self.cost_cand)
         self.vctx.cost_bwd(self.q_cand, self.ws, want_grad=False)
+
+    def update(self) -> None:
+        """The iteration's line-search selection, L-BFGS update and next candidates."""
         self.vctx._call("vapr_optimizer_step", ctypes.byref(self._st), _dev(self.ws, torch.uint8, "ws"),
                         self.ws.numel(), _dev(self.cost_cand, torch.float64, "cost"),
                         _dev(self.q_cand, torch.float32, "q"))

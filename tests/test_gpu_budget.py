@@ -66,13 +66,13 @@ def test_error_within_twice_the_budget(name):
     dc = np.abs(cost[tcs] - ref["cost_traj"])
     cbound = 2.0 * bud["cost"] + cost_tolerance(ref, wl.robot.n_pairs, T)
     assert np.all(dc <= cbound), (dc / cbound).max()
-    # gradients of configurations away from the kinks (closest cuboid, inside axis, OBB region)
-    active = ref["D"] > 0
-    ok = (np.where(active, ref["margin"], np.inf).min(axis=1) > 1e-3)
-    ok &= BG.hessian_margin(ref, sub.pose, sub.half_ext) > 1e-3
+    # gradients of configurations more than 1 mm away from the kinks (closest cuboid, inside axis,
+    # OBB region, activation hinges); BF16 and FP8 centres round by up to 4 and 60 mm, so there the
+    # first order is stretched, and twice the budget is the criterion
+    ok = BG.smooth_configurations(wl.robot, ref, sub.pose, sub.half_ext, 1e-3)
     dg = np.abs(grad[rows] - ref["J"])
     gbound = 2.0 * bud["grad"] + grad_tolerance(ref)
-    assert ok.sum() >= 64, int(ok.sum())
+    assert ok.sum() >= 32, int(ok.sum())
     assert np.all((dg <= gbound)[ok]), (dg / gbound)[ok].max()
     print(f"[budget] {name} {prec}: cost error / budget max {(dc / bud['cost']).max():.3f}; gradient error / "
           f"budget max {(dg / bud['grad'])[ok].max():.3f} over {int(ok.sum())} kink-free configurations, "

@@ -24,20 +24,7 @@ def small_workload(seed=5, W=2, tpw=2, T=4, n_s=20, K=10, P=40):
 
 
 def away_from_kinks(robot, worlds, ref, gap=1e-3):
-    """Configurations whose outputs are smooth within `gap` of every stored value: closest cuboid,
-    inside axis and OBB region unambiguous, every active depth and pair activation clear of zero."""
-    d = ref["D"]
-    active = d > 0
-    ok = np.where(active, ref["margin"], np.inf).min(axis=1) > gap
-    ok &= BG.hessian_margin(ref, worlds.pose, worlds.half_ext) > gap
-    ok &= ~np.any(active & (d < gap), axis=1)
-    pairs = robot.pairs
-    r = robot.sphere_radius.astype(np.float64)
-    S = ref["S"]
-    dist = np.linalg.norm(S[:, pairs[:, 0]] - S[:, pairs[:, 1]], axis=-1)
-    act = OC.CostParams().eta - (dist - r[pairs[:, 0]] - r[pairs[:, 1]])
-    ok &= ~np.any(np.abs(act) < gap, axis=1)
-    return ok
+    return BG.smooth_configurations(robot, ref, worlds.pose, worlds.half_ext, gap)
 
 
 def run(robot, worlds, q, tpw, T, perturb=None, prec=None):
