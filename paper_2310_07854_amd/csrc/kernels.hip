@@ -14,6 +14,8 @@
 // scalar loads: the inner cuboid loop runs on SGPR operands with no LDS traffic.
 #include <hip/hip_runtime.h>
 #include <math.h>
+
+#include <algorithm>
 #include <stdint.h>
 
 #include "codec.hpp"
@@ -422,10 +424,9 @@ __device__ __forceinline__ bool out_of_reach(float key, float eta, float r) {
 // Closest cuboid of NA spheres against the K cuboids of one world.  The comparison key is
 // |max(a,0)|^2 outside (> 0) and max_i a_i inside (<= 0), a monotone function of the signed
 // distance, so no square root is taken per pair; the first index wins ties.
-template <int NA>
-__device__ __forceinline__ void closest_cuboids(cptr<float> wbox, int K, const float (&px)[SPH_GROUP],
-                                                const float (&py)[SPH_GROUP], const float (&pz)[SPH_GROUP],
-                                                float (&best)[SPH_GROUP], int (&bk)[SPH_GROUP]) {
+template <int NA, int N = SPH_GROUP>
+__device__ __forceinline__ void closest_cuboids(cptr<float> wbox, int K, const float (&px)[N], const float (&py)[N],
+                                                const float (&pz)[N], float (&best)[N], int (&bk)[N]) {
   for (int k = 0; k < K; ++k) {
     const cptr<float> bx = wbox + k * 16;
     const float A0 = bx[0], A1 = bx[1], A2 = bx[2], A3 = bx[3], A4 = bx[4], A5 = bx[5], A6 = bx[6], A7 = bx[7],
@@ -605,19 +606,20 @@ __device__ __forceinline__ int pop_cuboid(uint64_t& m, const float* wbox, float4
 // The candidate list m against spheres i0 .. i0 + CQ - 1, cuboid k at base + 16 k (the world's table
 // in memory, or the block's LDS copy), two cuboid buffers used in turn so that the next candidate's
 // load is in flight while the current one is tested.
-__device__ __forceinline__ void walk_list(uint64_t m, const float* base, int i0, const float (&px)[SPH_GROUP],
-                                          const float (&py)[SPH_GROUP], const float (&pz)[SPH_GROUP],
-                                          float (&best)[SPH_GROUP], int (&bk)[SPH_GROUP]) {
+template <int N = SPH_GROUP, int Q = CQ>
+__device__ __forceinline__ void walk_list(uint64_t m, const float* base, int i0, const float (&px)[N],
+                                          const float (&py)[N], const float (&pz)[N], float (&best)[N],
+                                          int (&bk)[N]) {
   float4 a0, a1, a2, a3, b0, b1, b2, b3;
   int ka = pop_cuboid(m, base, a0, a1, a2, a3);
   while (ka >= 0) {
     const int kb = pop_cuboid(m, base, b0, b1, b2, b3);
 #pragma unroll
-    for (int i = i0; i < i0 + CQ; ++i) cuboid_key_v(a0, a1, a2, a3, px[i], py[i], pz[i], ka, best[i], bk[i]);
+    for (int i = i0; i < i0 + Q; ++i) cuboid_key_v(a0, a1, a2, a3, px[i], py[i], pz[i], ka, best[i], bk[i]);
     if (kb < 0) break;
     ka = pop_cuboid(m, base, a0, a1, a2, a3);
 #pragma unroll
-    for (int i = i0; i < i0 + CQ; ++i) cuboid_key_v(b0, b1, b2, b3, px[i], py[i], pz[i], kb, best[i], bk[i]);
+    for (int i = i0; i < i0 + Q; ++i) cuboid_key_v(b0, b1, b2, b3, px[i], py[i], pz[i], kb, best[i], bk[i]);
   }
 }
 
@@ -825,6 +827,277 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3))) void k
   if (g == 0 && valid) {
     float sum = 0.f;
     for (int gg = 0; gg < ng; ++gg) sum += part[gg * 64 + lane];
+    selfc[b] = cp.w_s * sum;
+  }
+}
+
+// ---- K2 with two wavefronts per sphere group ---------------------------------------------------
+//
+// The work of k_sphere_cost_blk, split finer: wavefront w of the block owns half h = w & 1 (8
+// spheres) of sphere group g = w >> 1.  A wavefront then needs half the registers, and the CU holds
+// twice the wavefronts for the same LDS per block, which is what covers the latency of the
+// candidate walks and of the partner reads.  Per sphere the arithmetic is unchanged: the same
+// candidate lists of 8 spheres, the same closest-cuboid keys, the same pair visits in the same order.
+// At the end the second half of each group leaves its 8 results in LDS (over the position image,
+// no longer needed) and the first half encodes and stores the group's 16 values.
+
+#ifndef VAPR_K2H_WAVES
+#define VAPR_K2H_WAVES 4
+#endif
+#ifndef VAPR_K2H_SINGLE
+#define VAPR_K2H_SINGLE 0
+#endif
+constexpr int HS = SPH_GROUP / 2;
+
+size_t sphere_cost_half_lds_bytes(int n_s, int n_groups) {
+  const size_t img = std::max((size_t)n_s * 3 * 64, (size_t)n_groups * 4 * HS * 64);
+  return (img + (size_t)2 * n_groups * 64 + 64 * 16) * sizeof(float);
+}
+
+// The candidate list m against the half's spheres, one cuboid at a time (the other wavefronts of the
+// CU cover the load's latency).
+template <int N>
+__device__ __forceinline__ void walk_list_single(uint64_t m, const float* base, const float (&px)[N],
+                                                 const float (&py)[N], const float (&pz)[N], float (&best)[N],
+                                                 int (&bk)[N]) {
+  float4 c0, c1, c2, c3;
+  for (int k = pop_cuboid(m, base, c0, c1, c2, c3); k >= 0; k = pop_cuboid(m, base, c0, c1, c2, c3)) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) cuboid_key_v(c0, c1, c2, c3, px[i], py[i], pz[i], k, best[i], bk[i]);
+  }
+}
+
+// Values h * 8 .. h * 8 + 7 of a stored group of 16.  Every format but FP6 packs 8 values into half
+// the group's dwords, which are read alone; FP6 groups (3 dwords) are decoded whole.
+template <int FS>
+__device__ __forceinline__ void load_half_at(const uint32_t* base, int slot, int h, float scale, float (&v)[HS]) {
+  if constexpr (FS == E3M2) {
+    float f[SPH_GROUP];
+    load_group_at<FS, SPH_GROUP>(base, slot, scale, f);
+#pragma unroll
+    for (int i = 0; i < HS; ++i) v[i] = h ? f[HS + i] : f[i];
+  } else {
+    constexpr int DW = group_dwords(FS, SPH_GROUP), DWH = DW / 2;
+    static_assert(group_dwords(FS, HS) == DWH, "8 values fill half a group's dwords");
+    uint32_t w[DWH];
+#pragma unroll
+    for (int k = 0; k < DWH; ++k) w[k] = base[(slot * DW + h * DWH + k) * 64];
+    decode_group<FS, HS>(w, scale, v);
+  }
+}
+
+template <int FS>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(VAPR_K2H_WAVES))) void k_sphere_cost_half(
+    RobotArgs R, WorldArgs W, GridArgs Gd, TV S, TV D, TV G, float* __restrict__ selfc, ShapeArgs sh, CostArgs cp) {
+  extern __shared__ float lds_f[];
+  const int lane = threadIdx.x & 63;
+  const int wv = uniform(threadIdx.x >> 6);
+  const int g = wv >> 1, h = wv & 1;
+  const int ng = uniform(R.n_groups);
+  const int n_s = uniform(R.n_s);
+  const int K = uniform(W.K);
+  const int64_t blk = blockIdx.x;
+  const int64_t b = blk * 64 + lane;
+  const bool valid = b < sh.B;
+  const int img_words = max(n_s * 3 * 64, ng * 4 * HS * 64);
+  float* pos = lds_f;                      // sphere s, component c: pos[(s * 3 + c) * 64 + lane]
+  float* part = lds_f + img_words;         // [2 ng][64] self-cost partials
+  float* cub = part + 2 * ng * 64;         // the block's world's cuboids (culled path)
+  const int64_t first = blk * 64;
+  const int64_t last = (first + 63 < sh.B ? first + 63 : sh.B - 1);
+  const int w_lo = uniform((int)(first / sh.cfg_per_world));
+  const int w_hi = uniform((int)(last / sh.cfg_per_world));
+  const bool staged = Gd.MW > 0 && Gd.MW <= 2 && w_lo == w_hi;
+  if (staged) {
+    const float* src = W.box + (int64_t)w_lo * K * 16;
+    for (int i = threadIdx.x; i < K * 16; i += blockDim.x) cub[i] = src[i];
+  }
+
+  const int s0 = g * SPH_GROUP + h * HS;                 // first sphere of this half
+  const int active = uniform(max(0, min(HS, n_s - s0)));
+  float px[HS], py[HS], pz[HS];
+  if (valid) {
+    const uint32_t* sb = lane_base(S, b);
+    load_half_at<FS>(sb, g * 3 + 0, h, S.scale, px);
+    load_half_at<FS>(sb, g * 3 + 1, h, S.scale, py);
+    load_half_at<FS>(sb, g * 3 + 2, h, S.scale, pz);
+  } else {
+#pragma unroll
+    for (int i = 0; i < HS; ++i) px[i] = py[i] = pz[i] = 0.f;
+  }
+  {
+    float* mine = pos + s0 * 3 * 64 + lane;
+#pragma unroll
+    for (int i = 0; i < HS; ++i) {
+      if (i >= active) continue;  // the image holds the n_s real spheres only
+      mine[(i * 3 + 0) * 64] = px[i];
+      mine[(i * 3 + 1) * 64] = py[i];
+      mine[(i * 3 + 2) * 64] = pz[i];
+    }
+  }
+  __syncthreads();
+
+  const int my_w = valid ? (int)(b / sh.cfg_per_world) : -1;
+  float best[HS];
+  int bk[HS];
+#pragma unroll
+  for (int i = 0; i < HS; ++i) {
+    best[i] = INFINITY;
+    bk[i] = 0;
+  }
+  if (active > 0) {
+    if (Gd.MW > 0) {
+      if (valid) {
+        const float* wbox = W.box + (int64_t)my_w * K * 16;
+        const uint32_t* wmask = Gd.mask + (int64_t)my_w * ((int64_t)Gd.n * Gd.n * Gd.n) * Gd.MW;
+        if (Gd.MW <= 2) {
+          // one candidate list for the half's 8 spheres: the union of their voxels' masks
+          uint64_t mq = 0;
+#pragma unroll
+          for (int i = 0; i < HS; ++i) {
+            const int v = i < active ? voxel_of(Gd, px[i], py[i], pz[i]) : -1;
+            if (v >= 0) {
+              const uint32_t* mp = wmask + (int64_t)v * Gd.MW;
+              mq |= (uint64_t)mp[0] | (Gd.MW > 1 ? (uint64_t)mp[1] << 32 : 0);
+            }
+          }
+#if VAPR_K2H_SINGLE
+          if (staged) walk_list_single<HS>(mq, cub, px, py, pz, best, bk);
+          else walk_list_single<HS>(mq, wbox, px, py, pz, best, bk);
+#else
+          if (staged) walk_list<HS, HS>(mq, cub, 0, px, py, pz, best, bk);
+          else walk_list<HS, HS>(mq, wbox, 0, px, py, pz, best, bk);
+#endif
+        } else {
+          int vox[HS];
+#pragma unroll
+          for (int i = 0; i < HS; ++i) vox[i] = i < active ? voxel_of(Gd, px[i], py[i], pz[i]) : -1;
+          for (int mw = 0; mw < Gd.MW; ++mw) {
+            uint32_t m = 0;
+#pragma unroll
+            for (int i = 0; i < HS; ++i)
+              if (vox[i] >= 0) m |= wmask[(int64_t)vox[i] * Gd.MW + mw];
+            while (m) {
+              const int k = mw * 32 + __builtin_ctz(m);
+              m &= m - 1;
+              const float4* c4 = reinterpret_cast<const float4*>(wbox + k * 16);
+              const float4 c0 = c4[0], c1 = c4[1], c2 = c4[2], c3 = c4[3];
+#pragma unroll
+              for (int i = 0; i < HS; ++i) cuboid_key_v(c0, c1, c2, c3, px[i], py[i], pz[i], k, best[i], bk[i]);
+            }
+          }
+        }
+      }
+    } else {
+      for (int w = w_lo; w <= w_hi; ++w) {
+        if (my_w != w) continue;
+        const cptr<float> wbox = as_const(W.box) + (int64_t)uniform(w) * K * 16;
+        if (active > 4) closest_cuboids<HS, HS>(wbox, K, px, py, pz, best, bk);
+        else closest_cuboids<4, HS>(wbox, K, px, py, pz, best, bk);
+      }
+    }
+  }
+
+  // From here on a sphere's own centre is read back from the image when needed rather than kept in
+  // registers through the rest of the kernel (that keeps the wavefront within 80 registers).
+  const float* own = pos + s0 * 3 * 64 + lane;
+  float dv[HS], gx[HS], gy[HS], gz[HS];
+  const float* mybox = W.box + (int64_t)(valid ? my_w : 0) * K * 16;
+#pragma unroll
+  for (int i = 0; i < HS; ++i) {
+    dv[i] = 0.f;
+    gx[i] = gy[i] = gz[i] = 0.f;
+    const float r = i < active ? sphere_of(R.sph, s0 + i).w : 0.f;
+    if (i < active && K > 0 && valid && !out_of_reach(best[i], cp.eta, r)) {
+      float sd, nx, ny, nz;
+      const float qx = own[(i * 3 + 0) * 64], qy = own[(i * 3 + 1) * 64], qz = own[(i * 3 + 2) * 64];
+      if (staged) cuboid_sd_grad(cub + bk[i] * 16, qx, qy, qz, sd, nx, ny, nz);
+      else cuboid_sd_grad(mybox + bk[i] * 16, qx, qy, qz, sd, nx, ny, nz);
+      const float d = fmaxf(cp.eta - (sd - r), 0.f);
+      dv[i] = d;
+      if (d > 0.f) {
+        const float coef = -2.f * cp.w_c * d;
+        gx[i] = coef * nx;
+        gy[i] = coef * ny;
+        gz[i] = coef * nz;
+      }
+    }
+    // one sphere's cuboid at a time: the compiler would otherwise hoist the LDS reads of later
+    // spheres' cuboids (they cannot fault) and hold them in registers
+    asm volatile("" ::: "memory");
+  }
+  // Self pairs, as in k_sphere_cost_blk: partners from the LDS image four at a time, every pair
+  // visited from both spheres, the lower index adding the cost.
+  float self_acc = 0.f;
+  constexpr int PB = 4;
+#pragma unroll
+  for (int i = 0; i < HS; ++i) {
+    if (i >= active) continue;
+    const int s = s0 + i;
+    const float rs = sphere_of(R.sph, s).w;
+    const float qx = own[(i * 3 + 0) * 64], qy = own[(i * 3 + 1) * 64], qz = own[(i * 3 + 2) * 64];
+    const int j0 = as_const(R.pair_off)[s], j1 = as_const(R.pair_off)[s + 1];
+    for (int j = j0; j < j1; j += PB) {
+      const cptr<float> e = as_const(reinterpret_cast<const float*>(R.pair_tab)) + 4 * j;
+      float tx[PB], ty[PB], tz[PB];
+#pragma unroll
+      for (int u = 0; u < PB; ++u) {
+        const float* pp = pos + (unsigned)__float_as_int(e[4 * u]) * 3u * 64u + lane;
+        tx[u] = pp[0];
+        ty[u] = pp[64];
+        tz[u] = pp[128];
+      }
+#pragma unroll
+      for (int u = 0; u < PB; ++u) {
+        const float dx = qx - tx[u], dy = qy - ty[u], dz = qz - tz[u];
+        const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+        if (!(d2 <= e[4 * u + 2])) continue;
+        const float inv = __builtin_amdgcn_rsqf(d2);
+        const bool apart = d2 > 0.f;
+        const float dist = apart ? d2 * inv : 0.f;
+        const float ev = dist - rs - e[4 * u + 1];
+        const float act = fmaxf(cp.eta - ev, 0.f);
+        if (act > 0.f) {
+          const float coef = (-2.f * cp.w_s) * act * inv;
+          if (apart) {
+            gx[i] = fmaf(coef, dx, gx[i]);
+            gy[i] = fmaf(coef, dy, gy[i]);
+            gz[i] = fmaf(coef, dz, gz[i]);
+          }
+          if (s < __float_as_int(e[4 * u])) self_acc = fmaf(act, act, self_acc);
+        }
+      }
+    }
+  }
+  __syncthreads();  // the position image is read for the last time above
+  float* xg = pos + g * (4 * HS * 64) + lane;
+  if (h == 1) {
+#pragma unroll
+    for (int i = 0; i < HS; ++i) {
+      xg[(0 * HS + i) * 64] = dv[i];
+      xg[(1 * HS + i) * 64] = gx[i];
+      xg[(2 * HS + i) * 64] = gy[i];
+      xg[(3 * HS + i) * 64] = gz[i];
+    }
+  }
+  part[wv * 64 + lane] = self_acc;
+  __syncthreads();
+  if (h == 0 && valid) {
+    float v[SPH_GROUP];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+#pragma unroll
+      for (int i = 0; i < HS; ++i) {
+        v[i] = c == 0 ? dv[i] : (c == 1 ? gx[i] : (c == 2 ? gy[i] : gz[i]));
+        v[HS + i] = xg[(c * HS + i) * 64];
+      }
+      if (c == 0) store_group<SPH_GROUP>(D, b, g, v);
+      else store_group<SPH_GROUP>(G, b, g * 3 + (c - 1), v);
+    }
+  }
+  if (wv == 0 && valid) {
+    float sum = 0.f;
+    for (int k = 0; k < 2 * ng; ++k) sum += part[k * 64 + lane];
     selfc[b] = cp.w_s * sum;
   }
 }
@@ -1821,6 +2094,20 @@ size_t sphere_cost_lds_bytes(int n_s, int n_groups) {
   return ((size_t)n_s * 3 * 64 + (size_t)n_groups * 64 + 64 * 16) * sizeof(float);
 }
 
+hipError_t launch_sphere_cost_half(hipStream_t s, const RobotArgs& R, const WorldArgs& W, const GridArgs& Gd,
+                                   const TV& S, const TV& D, const TV& G, float* selfc, const ShapeArgs& sh,
+                                   const CostArgs& cp) {
+  const size_t lds = sphere_cost_half_lds_bytes(R.n_s, R.n_groups);
+  const dim3 grid(blocks_for(sh.B, 64)), block(128 * R.n_groups);
+  switch (S.fmt) {
+#define VAPR_K2H(F) \
+  case F: hipLaunchKernelGGL(k_sphere_cost_half<F>, grid, block, lds, s, R, W, Gd, S, D, G, selfc, sh, cp); break;
+    VAPR_K2H(F32) VAPR_K2H(F16) VAPR_K2H(BF16) VAPR_K2H(E4M3) VAPR_K2H(E5M2) VAPR_K2H(E3M2) VAPR_K2H(E2M1)
+#undef VAPR_K2H
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
 hipError_t launch_sphere_cost_blk(hipStream_t s, const RobotArgs& R, const WorldArgs& W, const GridArgs& Gd,
                                   const TV& S, const TV& D, const TV& G, float* selfc, const ShapeArgs& sh,
                                   const CostArgs& cp) {

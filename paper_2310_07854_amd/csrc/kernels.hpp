@@ -89,6 +89,11 @@ hipError_t launch_sphere_cost(hipStream_t s, const RobotArgs& R, const WorldArgs
                               const TV& G, float* selfc, const ShapeArgs& sh, const CostArgs& cp);
 // LDS bytes of the block-staged sphere-cost kernel (used while they fit in 64 KiB)
 size_t sphere_cost_lds_bytes(int n_s, int n_groups);
+// two wavefronts per sphere group (up to 8 groups, LDS sphere_cost_half_lds_bytes <= 64 KiB)
+size_t sphere_cost_half_lds_bytes(int n_s, int n_groups);
+hipError_t launch_sphere_cost_half(hipStream_t s, const RobotArgs& R, const WorldArgs& W, const GridArgs& Gd,
+                                   const TV& S, const TV& D, const TV& G, float* selfc, const ShapeArgs& sh,
+                                   const CostArgs& cp);
 hipError_t launch_sphere_cost_blk(hipStream_t s, const RobotArgs& R, const WorldArgs& W, const GridArgs& Gd,
                                   const TV& S, const TV& D, const TV& G, float* selfc, const ShapeArgs& sh,
                                   const CostArgs& cp);

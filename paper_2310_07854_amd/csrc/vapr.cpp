@@ -596,7 +596,10 @@ int run_fwd(vapr_ctx* ctx, int first, int n_worlds, int tpw, int T, int n_ls, co
     const CostArgs cp = ctx->params;
     if (!ctx->grid_valid && (st = build_grid(ctx))) return st;
     const GridArgs Gd = ctx->grid;
-    if (sphere_cost_lds_bytes(ctx->n_s, ctx->n_groups) <= 65536) {
+    if (ctx->n_groups <= 8 && sphere_cost_half_lds_bytes(ctx->n_s, ctx->n_groups) <= 65536) {
+      st = timed(ctx, K_SPHERE, [&] { return launch_sphere_cost_half(s, R, W, Gd, tS, tD, tG, selfc, sh, cp); },
+                 "k_sphere_cost_half launch");
+    } else if (sphere_cost_lds_bytes(ctx->n_s, ctx->n_groups) <= 65536) {
       st = timed(ctx, K_SPHERE, [&] { return launch_sphere_cost_blk(s, R, W, Gd, tS, tD, tG, selfc, sh, cp); },
                  "k_sphere_cost_blk launch");
     } else {
