@@ -17,8 +17,15 @@ FP4, FP5, FP6, FP8, FP10, FP16 and FP32 as the widths of interest.  Readings use
              hold finite values and overflow saturates to the largest finite value, Inf inputs too
              (the convention of the FP6/FP4 storage formats)
   rounding   to the nearest representable value, ties to even mantissa
-  NaN        passes through as NaN (emulation only; no codes are formed)
+  NaN        passes through as NaN in the rounding; as a code: the quiet NaN (top exponent field,
+             mantissa MSB) for the IEEE-like types, outside the contract for the others (they
+             store the largest magnitude)
   scale      as for the storage formats: y = fp32(fp32(x) 2^-k), value = fp32(round(y) 2^k)
+  codes      sign bit, E exponent bits (the biased exponent, 0 for zero and subnormals) and M
+             mantissa bits, sign at bit E + M; b = 1 + E + M bits
+  packing    a 32-bit word holds floor(32 / b) codes (one FP32, two FP16, three FP10, four FP8, five
+             FP6, six FP5, eight FP4 -- the register packing of Sec. IV-A): code i of a tensor goes
+             to word i // q at bits (i % q) b, the top 32 - q b bits of each word stay zero
 
 The rounding of a finite y != 0 with |y| = m 2^e (1 <= m < 2): the grid spacing is
 2^(max(e, e_min) - M) with e_min = 1 - bias; |y| is divided by it (exact), rounded half-to-even to an
@@ -27,7 +34,10 @@ integer and multiplied back (exact).
 Parity pins (tests/test_oracle_exmy.py): E3M2 and E2M1 equal the storage codecs' round trips, E5M10
 equals IEEE binary16, E8M7 the bfloat16 round trip and E8M23 the identity, on dense and random
 inputs; the largest finite values by formula (E8M4 too); brute-force nearest-value search over every
-representable value of small types; exact midpoints to even; monotonicity.
+representable value of small types; exact midpoints to even; monotonicity.  Codes: E5M10, E8M7 and
+E8M23 codes equal numpy float16 bits, bfloat16 bits (the top half of FP32) and FP32 bits; E3M2 and
+E2M1 codes equal the storage codecs'; every code of small types decodes to the value its fields
+give and back to itself; packing places hand-checked words.
 """
 from __future__ import annotations
 
@@ -123,3 +133,76 @@ def representable(E: int, M: int) -> np.ndarray:
     for e in range(e_min, e_max + 1):
         vals += [(1.0 + m / (1 << M)) * 2.0 ** e for m in range(1 << M)]
     return np.array(sorted(set(vals)))
+
+
+def encode(x, E: int, M: int, k: int = 0) -> np.ndarray:
+    """Codes (uint32, sign at bit E + M) of the write path: the code of round_value(fp32(fp32(x)
+    2^-k)).  Zero keeps its sign; NaN gives the quiet NaN of the IEEE-like types and the largest
+    magnitude of the others (outside the contract)."""
+    check(E, M)
+    x32 = np.asarray(x, dtype=np.float64).astype(np.float32).astype(np.float64)
+    with np.errstate(over="ignore", invalid="ignore"):
+        y = (x32 * 2.0 ** -k).astype(np.float32).astype(np.float64)
+    r = round_value(y, E, M)
+    bias = (1 << (E - 1)) - 1
+    e_min = 1 - bias
+    sign = np.signbit(r).astype(np.uint64) << np.uint64(E + M)
+    a = np.abs(r)
+    top = (1 << E) - 1
+    nan_code = (top << M) | ((1 << (M - 1)) if M > 0 else 0) if ieee(E, M) else (top << M) | ((1 << M) - 1)
+    fin = np.isfinite(a) & (a > 0)
+    af = np.where(fin, a, 1.0)
+    m, ex = np.frexp(af)                              # af = m 2^ex, 1/2 <= m < 1
+    e = ex - 1                                        # af = (2m) 2^e
+    normal = e >= e_min
+    with np.errstate(invalid="ignore", over="ignore"):   # each branch is exact where it is selected
+        mant_n = np.rint((af / np.ldexp(1.0, e) - 1.0) * (1 << M)).astype(np.int64)
+        mant_s = np.rint(np.minimum(af / np.ldexp(1.0, e_min - M), 2.0 ** 62)).astype(np.int64)
+    mag = np.where(normal, ((e + bias).astype(np.int64) << M) | mant_n, mant_s)
+    mag = np.where(a == 0, 0, mag)
+    mag = np.where(np.isinf(a), top << M, mag)
+    mag = np.where(np.isnan(a), nan_code, mag)
+    return (mag.astype(np.uint64) | sign).astype(np.uint32)
+
+
+def decode(codes, E: int, M: int, k: int = 0) -> np.ndarray:
+    """Values (float64) of codes, times 2^k, rounded to FP32 as the read path returns them."""
+    check(E, M)
+    c = np.asarray(codes).astype(np.int64)
+    bias = (1 << (E - 1)) - 1
+    mag = c & ((1 << (E + M)) - 1)
+    ef = mag >> M
+    mant = mag & ((1 << M) - 1)
+    v = np.where(ef == 0, mant * np.ldexp(1.0, 1 - bias - M),
+                 ((1 << M) + mant) * np.ldexp(1.0, (ef - bias - M).astype(np.int64)))
+    if ieee(E, M):
+        top = (1 << E) - 1
+        v = np.where(ef == top, np.where(mant != 0, np.nan, np.inf), v)
+    v = np.where((c >> (E + M)) & 1, -v, v)
+    with np.errstate(over="ignore"):
+        return (v * 2.0 ** k).astype(np.float32).astype(np.float64)
+
+
+def per_word(E: int, M: int) -> int:
+    """Codes per 32-bit word: floor(32 / b)."""
+    return 32 // bits(E, M)
+
+
+def pack(codes, E: int, M: int) -> np.ndarray:
+    """Words (uint32) holding the codes, per_word(E, M) to a word from the low bits up."""
+    b, q = bits(E, M), per_word(E, M)
+    c = np.asarray(codes, dtype=np.uint64).ravel()
+    n_words = (c.shape[0] + q - 1) // q
+    padded = np.zeros(n_words * q, dtype=np.uint64)
+    padded[: c.shape[0]] = c
+    shifts = (np.arange(q, dtype=np.uint64) * np.uint64(b))[None, :]
+    return np.bitwise_or.reduce(padded.reshape(n_words, q) << shifts, axis=1).astype(np.uint32)
+
+
+def unpack(words, E: int, M: int, n: int) -> np.ndarray:
+    """Inverse of `pack` for n codes."""
+    b, q = bits(E, M), per_word(E, M)
+    w = np.asarray(words, dtype=np.uint64).ravel()
+    shifts = (np.arange(q, dtype=np.uint64) * np.uint64(b))[None, :]
+    mask = np.uint64((1 << b) - 1)
+    return ((w[:, None] >> shifts) & mask).ravel()[:n].astype(np.uint32)

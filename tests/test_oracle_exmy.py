@@ -84,3 +84,62 @@ def test_ladder_is_21_types_from_fp4_to_fp32():
     assert X.ieee(8, 4) and X.limits(8, 4)[2] == (2 - 2 ** -4) * 2.0 ** 127 and not X.ieee(6, 6)
     named = {(2, 1), (2, 2), (3, 1), (2, 3), (3, 2), (4, 3), (5, 2), (6, 6), (5, 9), (6, 8), (5, 10), (8, 7), (8, 23)}
     assert named <= set(X.LADDER)
+
+
+# ---- codes and word packing ---------------------------------------------------------------------
+
+def test_codes_of_ieee_types_are_the_library_bit_patterns():
+    torch = pytest.importorskip("torch")
+    x = _inputs(seed=3)
+    x = x[np.isfinite(x)]
+    h = np.abs(x) < 65000.0
+    assert np.array_equal(X.encode(x[h], 5, 10), x[h].astype(np.float32).astype(np.float16).view(np.uint16))
+    assert np.array_equal(X.encode(x, 8, 23), x.astype(np.float32).view(np.uint32))
+    bf = torch.tensor(x.astype(np.float32)).to(torch.bfloat16).view(torch.int16).numpy().view(np.uint16)
+    assert np.array_equal(X.encode(x, 8, 7), bf)
+    # Inf and the largest finite values
+    assert X.encode(np.array([np.inf, -np.inf, 65504.0]), 5, 10).tolist() == [0x7C00, 0xFC00, 0x7BFF]
+
+
+@pytest.mark.parametrize("E,M,fmt", [(3, 2, "e3m2"), (2, 1, "e2m1")])
+def test_codes_equal_the_storage_codecs(E, M, fmt):
+    for k in (0, -3, 4):
+        x = _inputs(seed=4 + k)
+        x = x[~np.isnan(x)]
+        assert np.array_equal(X.encode(x, E, M, k), F.quantize(x, fmt, k))
+
+
+@pytest.mark.parametrize("E,M", [(1, 2), (2, 2), (3, 1), (1, 3), (4, 0), (2, 3), (4, 1), (3, 4), (4, 5)])
+def test_every_code_decodes_to_its_fields_and_back(E, M):
+    bias = (1 << (E - 1)) - 1
+    for c in range(1 << (1 + E + M)):
+        ef, mant, s = (c >> M) & ((1 << E) - 1), c & ((1 << M) - 1), c >> (E + M)
+        v = (mant / 2 ** M) * 2.0 ** (1 - bias) if ef == 0 else (1 + mant / 2 ** M) * 2.0 ** (ef - bias)
+        v = -v if s else v
+        got = X.decode(np.array([c]), E, M)[0]
+        assert got == v and np.signbit(got) == bool(s), (E, M, c, got, v)
+        assert X.encode(np.array([v]), E, M)[0] == c
+
+
+@pytest.mark.parametrize("E,M", X.LADDER)
+def test_decode_of_encode_is_the_rounding(E, M):
+    for k in (0, -5, 3):
+        x = _inputs(seed=11 + k)
+        fin = ~np.isnan(x)
+        _, want = X.roundtrip(x[fin], E, M, k)
+        got = X.decode(X.encode(x[fin], E, M, k), E, M, k)
+        assert np.array_equal(got, want) and np.array_equal(np.signbit(got), np.signbit(want))
+
+
+def test_word_packing():
+    # E3M1: b = 5, six codes a word; E4M5: b = 10, three codes a word; E2M1: eight codes a word
+    codes = np.array([1, 2, 3, 4, 5, 6, 7], dtype=np.uint32)
+    w = X.pack(codes, 3, 1)
+    assert w.tolist() == [1 | 2 << 5 | 3 << 10 | 4 << 15 | 5 << 20 | 6 << 25, 7]
+    assert X.pack(np.array([0x3FF, 1, 0x200, 5]), 4, 5).tolist() == [0x3FF | 1 << 10 | 0x200 << 20, 5]
+    assert X.pack(np.arange(8), 2, 1).tolist() == [sum(i << (4 * i) for i in range(8))]
+    assert X.per_word(5, 10) == 2 and X.per_word(2, 3) == 5 and X.per_word(8, 23) == 1
+    rng = np.random.default_rng(2)
+    for E, M in X.LADDER:
+        c = rng.integers(0, 1 << X.bits(E, M), size=101).astype(np.uint32)
+        assert np.array_equal(X.unpack(X.pack(c, E, M), E, M, 101), c)
