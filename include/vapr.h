@@ -35,7 +35,7 @@
 extern "C" {
 #endif
 
-#define VAPR_ABI_VERSION 3
+#define VAPR_ABI_VERSION 4
 
 typedef enum {
   VAPR_OK = 0,
@@ -60,13 +60,17 @@ typedef enum {
   VAPR_E5M2 = 4,  /* bias 15, max 57344                   */
   VAPR_E3M2 = 5,  /* FP6, bias 3, max 28, no Inf/NaN      */
   VAPR_E2M1 = 6,  /* FP4, bias 1, max 6, no Inf/NaN       */
-  VAPR_EXMY = 7   /* an emulated type of the paper's search space (Sec. IV-A, IV-B): the tensor is
-                     stored as FP32 values rounded to exp_bits / man_bits at every write, the way
-                     the paper evaluates formats without converter hardware.  1 <= exp_bits <= 8,
-                     0 <= man_bits <= 23; bias 2^(exp_bits-1) - 1, subnormals kept, ties to even;
-                     E5M10 and the 8-exponent-bit types (E8M7, E8M23, ...) follow IEEE (overflow
-                     to Inf), every other type has no Inf/NaN and saturates; NaN passes through.
-                     Takes a scale like the others. */
+  VAPR_EXMY = 7   /* any type of the paper's search space (Sec. IV-A, IV-B), 1 <= exp_bits <= 8,
+                     0 <= man_bits <= 23, b = 1 + exp_bits + man_bits bits, encoded in software:
+                     bias 2^(exp_bits-1) - 1, subnormals kept, ties to even; E5M10 and the
+                     8-exponent-bit types (E8M7, E8M23, ...) follow IEEE (overflow to Inf, Inf and
+                     NaN codes in the top exponent field), every other type has no Inf/NaN and
+                     saturates (a NaN input stores the largest magnitude: outside the contract).
+                     Code: sign at bit b-1, biased exponent, mantissa.  Stored packed
+                     floor(32 / b) codes to a 32-bit word from the low bits up (the paper's
+                     register packing: 3 FP10, 5 FP6, 6 FP5 ...), the unused top bits zero; so
+                     the tensor moves b-bit codes, not FP32 values.  Takes a scale like the
+                     others. */
 } vapr_format;
 
 /* One stored tensor's format with a power-of-two scale: a value x is stored as
@@ -322,7 +326,8 @@ int vapr_optimizer_step(vapr_ctx* ctx, const vapr_lbfgs_state* st, const void* w
                         const double* cost_cand, float* q_cand);
 
 /* Element-wise codec on the context-free current device (Sec. V-B conversion of a tensor on
- * write and read).  in/out dev; out holds vapr_packed_bytes(fmt, n) bytes in the packed layout.
+ * write and read), storage formats (VAPR_F32 .. VAPR_E2M1).  in/out dev; out holds
+ * vapr_packed_bytes(fmt, n) bytes in the packed layout.
  * stream: hipStream_t or NULL.  0 <= n <= 2^32. */
 int vapr_quantize(int fmt, int scale_exp, const float* in, void* out, int64_t n, void* hip_stream);
 /* Emulated ExMy rounding (VAPR_EXMY rules): out[i] = round(in[i] 2^-scale_exp) 2^scale_exp, FP32
@@ -330,6 +335,15 @@ int vapr_quantize(int fmt, int scale_exp, const float* in, void* out, int64_t n,
 int vapr_round_exmy(int exp_bits, int man_bits, int scale_exp, const float* in, float* out, int64_t n,
                     void* hip_stream);
 int vapr_dequantize(int fmt, int scale_exp, const void* in, float* out, int64_t n, void* hip_stream);
+/* The same for an emulated ExMy type (VAPR_EXMY): out holds vapr_exmy_packed_bytes(exp_bits,
+ * man_bits, n) bytes, code i at bits (i % q) b of 32-bit word i / q, q = floor(32 / b). */
+int vapr_quantize_exmy(int exp_bits, int man_bits, int scale_exp, const float* in, void* out, int64_t n,
+                       void* hip_stream);
+int vapr_dequantize_exmy(int exp_bits, int man_bits, int scale_exp, const void* in, float* out, int64_t n,
+                         void* hip_stream);
+/* Bytes of n packed codes: vapr_packed_bytes for the storage formats (0 for VAPR_EXMY), and
+ * 4 ceil(n / floor(32 / b)) for an ExMy type (0 when its bits are out of range). */
+size_t vapr_exmy_packed_bytes(int exp_bits, int man_bits, int64_t n);
 
 /* ---- Learned trajectory seeder ----------------------------------------------------------------
  * A network proposes initial trajectories for the optimiser in place of the geometric planner
@@ -426,9 +440,10 @@ typedef enum {
 } vapr_tensor;
 
 /* Copy one stored tensor between a workspace and a dense buffer in canonical element order, in the
- * packed layout of the tensor's current format (vapr_packed_bytes(fmt, count) bytes).  Used to
- * inspect and to seed individual stages.  Import records ws as holding a forward pass of this shape
- * (so a backward pass may follow).  out/in dev; sizes checked against the shape. */
+ * packed layout of the tensor's current format (vapr_packed_bytes(fmt, count) bytes; for an ExMy
+ * type vapr_exmy_packed_bytes(exp_bits, man_bits, count) bytes, 4-byte aligned).  Used to inspect
+ * and to seed individual stages.  Import records ws as holding a forward pass of this shape (so a
+ * backward pass may follow).  out/in dev; sizes checked against the shape. */
 int vapr_ws_export(vapr_ctx* ctx, int n_worlds, int traj_per_world, int T, int n_ls, const void* ws,
                    size_t ws_bytes, int tensor, void* out, size_t out_bytes);
 int vapr_ws_import(vapr_ctx* ctx, int n_worlds, int traj_per_world, int T, int n_ls, void* ws,

@@ -28,7 +28,7 @@ def format_id(fmt: str):
     return EXMY, int(m.group(1)), int(m.group(2))
 FORMAT_BITS = {F32: 32, F16: 16, BF16: 16, E4M3: 8, E5M2: 8, E3M2: 6, E2M1: 4}
 T_LINK_POSES, T_SPHERE_POS, T_SPHERE_DIST, T_SPHERE_GRAD, T_JOINT_GRAD, T_SELF_COST, T_BOUND_COST = range(7)
-ABI_VERSION = 3  # the structs below match include/vapr.h at this version
+ABI_VERSION = 4  # the structs below match include/vapr.h at this version
 TENSOR_IDS = {"link_poses": 0, "sphere_pos": 1, "sphere_dist": 2, "sphere_grad": 3, "joint_grad": 4,
               "self_cost": 5, "bound_cost": 6, "swept_grad": 7, "swept_cost": 8,
               "pose_cost": 9}
@@ -106,6 +106,9 @@ SIGNATURES = {
     "vapr_quantize": (_I, [_I, _I, _P, _P, _I64, _P]),
     "vapr_dequantize": (_I, [_I, _I, _P, _P, _I64, _P]),
     "vapr_packed_bytes": (_SZ, [_I, _I64]),
+    "vapr_exmy_packed_bytes": (_SZ, [_I, _I, _I64]),
+    "vapr_quantize_exmy": (_I, [_I, _I, _I, _P, _P, _I64, _P]),
+    "vapr_dequantize_exmy": (_I, [_I, _I, _I, _P, _P, _I64, _P]),
     "vapr_ws_export": (_I, [_P, _I, _I, _I, _I, _P, _SZ, _I, _P, _SZ]),
     "vapr_ws_import": (_I, [_P, _I, _I, _I, _I, _P, _SZ, _I, _P, _SZ]),
     "vapr_profile_enable": (_I, [_P, _I]),

@@ -264,8 +264,7 @@ class Context:
         n = shape.B * self.tensor_count(name)
         if name in SCALARS:
             return 4 * n
-        fmt = L.format_id(self.precision[name][0])[0]
-        return int(self._lib.vapr_packed_bytes(fmt, n))
+        return packed_bytes(self.precision[name][0], n)
 
     def ws_export(self, name: str, ws: torch.Tensor, shape: Shape) -> torch.Tensor:
         """Packed codes (uint8) of a stored tensor in canonical order, or float32 for the scalars."""
@@ -296,12 +295,50 @@ class Context:
         return {name: (ms[i], cnt[i]) for i, name in enumerate(L.KERNEL_NAMES)}
 
 
-def quantize(x: torch.Tensor, fmt: str, scale_exp: int = 0) -> torch.Tensor:
-    """Packed codes (uint8 tensor) of float32 device tensor x."""
+def packed_bytes(fmt: str, n: int) -> int:
+    """Bytes of n packed codes of a storage format or an emulated "eXmY" type."""
     lib = L.load()
-    f = L.FORMAT_IDS[fmt]
+    f, e_bits, m_bits = L.format_id(fmt)
+    if f == L.EXMY:
+        return int(lib.vapr_exmy_packed_bytes(e_bits, m_bits, n))
+    return int(lib.vapr_packed_bytes(f, n))
+
+
+def quantize_exmy(x: torch.Tensor, exp_bits: int, man_bits: int, scale_exp: int = 0) -> torch.Tensor:
+    """Packed codes (uint8 tensor, floor(32 / b) codes to a 32-bit word) of float32 device tensor x
+    in the emulated type E<exp_bits>M<man_bits>."""
+    lib = L.load()
     n = x.numel()
-    nb = int(lib.vapr_packed_bytes(f, n))
+    nb = int(lib.vapr_exmy_packed_bytes(exp_bits, man_bits, n))
+    out = torch.empty(nb, dtype=torch.uint8, device=x.device)
+    L.check(lib.vapr_quantize_exmy(exp_bits, man_bits, scale_exp, _dev(x, torch.float32, "x"), out.data_ptr(), n,
+                                   _stream_handle()))
+    return out
+
+
+def dequantize_exmy(words: torch.Tensor, exp_bits: int, man_bits: int, n: int, scale_exp: int = 0) -> torch.Tensor:
+    """float32 values of n packed codes of an emulated type (uint8 device tensor)."""
+    lib = L.load()
+    nb = int(lib.vapr_exmy_packed_bytes(exp_bits, man_bits, n))
+    buf = words
+    if words.numel() % 4 or words.data_ptr() % 4:
+        buf = torch.zeros((nb + 3) // 4 * 4, dtype=torch.uint8, device=words.device)
+        buf[:nb] = words[:nb]
+    out = torch.empty(n, dtype=torch.float32, device=words.device)
+    L.check(lib.vapr_dequantize_exmy(exp_bits, man_bits, scale_exp, _dev(buf, torch.uint8, "words"), out.data_ptr(),
+                                     n, _stream_handle()))
+    return out
+
+
+def quantize(x: torch.Tensor, fmt: str, scale_exp: int = 0) -> torch.Tensor:
+    """Packed codes (uint8 tensor) of float32 device tensor x in a storage format, or in an emulated
+    "eXmY" type named by one that is not a storage format's name."""
+    lib = L.load()
+    f, e_bits, m_bits = L.format_id(fmt)
+    if f == L.EXMY:
+        return quantize_exmy(x, e_bits, m_bits, scale_exp)
+    n = x.numel()
+    nb = packed_bytes(fmt, n)
     out = torch.empty((nb + 3) // 4 * 4, dtype=torch.uint8, device=x.device)
     L.check(lib.vapr_quantize(f, scale_exp, _dev(x, torch.float32, "x"), out.data_ptr(), n, _stream_handle()))
     return out[:nb]
@@ -319,8 +356,10 @@ def round_exmy(x: torch.Tensor, exp_bits: int, man_bits: int, scale_exp: int = 0
 def dequantize(codes: torch.Tensor, fmt: str, n: int, scale_exp: int = 0) -> torch.Tensor:
     """float32 values of n packed codes (uint8 device tensor)."""
     lib = L.load()
-    f = L.FORMAT_IDS[fmt]
-    nb = int(lib.vapr_packed_bytes(f, n))
+    f, e_bits, m_bits = L.format_id(fmt)
+    if f == L.EXMY:
+        return dequantize_exmy(codes, e_bits, m_bits, n, scale_exp)
+    nb = packed_bytes(fmt, n)
     buf = codes
     if codes.numel() % 4 or codes.data_ptr() % 4:
         buf = torch.zeros((nb + 3) // 4 * 4, dtype=torch.uint8, device=codes.device)

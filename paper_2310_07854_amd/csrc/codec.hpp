@@ -20,7 +20,8 @@
 
 namespace vapr {
 
-enum : int { F32 = 0, F16 = 1, BF16 = 2, E4M3 = 3, E5M2 = 4, E3M2 = 5, E2M1 = 6, N_FORMATS = 7 };
+// PXM: an emulated ExMy type stored as its own packed codes (E and M travel beside the format id)
+enum : int { F32 = 0, F16 = 1, BF16 = 2, E4M3 = 3, E5M2 = 4, E3M2 = 5, E2M1 = 6, PXM = 7, N_FORMATS = 8 };
 
 template <int F> struct Fmt;
 //                 E   M  bias sat   bits  max magnitude  inf       nan
@@ -66,6 +67,96 @@ __device__ __forceinline__ float exmy_round(float y, int E, int M) {
     if (r > vmax) r = ieee ? INFINITY : vmax;
   }
   return copysignf(r, y);
+}
+
+// ---- packed ExMy codes (emulated types stored in their own bits) --------------------------------
+//
+// Code of a value of the type: sign at bit E + M, the biased exponent field (0 for zero and
+// subnormals), M mantissa bits.  A 32-bit word holds q = floor(32 / b) codes, b = 1 + E + M, from the
+// low bits up (one FP32, two FP16, three FP10, four FP8, five FP6, six FP5 or eight FP4 a register,
+// Sec. IV-A); the top 32 - q b bits stay zero.  A group of n values takes ceil(n / q) words.
+
+__host__ __device__ constexpr int pxm_per_word(int E, int M) { return 32 / (1 + E + M); }
+__host__ __device__ constexpr int pxm_group_dwords(int E, int M, int n) {
+  return (n + pxm_per_word(E, M) - 1) / pxm_per_word(E, M);
+}
+
+// The code of exmy_round(y): the rounded value is representable, so its fields are read off its FP32
+// bits -- exponent rebiased and mantissa truncated to M bits for normal values, the significand
+// shifted to the subnormal grid 2^(e_min - M) otherwise.  Inf gives the Inf code and NaN the quiet
+// NaN of the IEEE-like types; a NaN of the saturating types (outside the contract) stores the
+// largest magnitude.
+__device__ __forceinline__ uint32_t exmy_encode(float y, int E, int M) {
+  const uint32_t u = __float_as_uint(exmy_round(y, E, M));
+  const uint32_t sign = (u >> 31) << (E + M);
+  const uint32_t a = u & 0x7fffffffu;
+  const uint32_t top = (1u << E) - 1u;
+  if (a >= 0x7f800000u) {
+    const bool ieee = (E == 5 && M == 10) || E == 8;
+    if (ieee) return sign | (top << M) | (a > 0x7f800000u && M > 0 ? 1u << (M - 1) : 0u);
+    return sign | (top << M) | ((1u << M) - 1u);
+  }
+  if (a == 0u) return sign;
+  const int bias = (1 << (E - 1)) - 1;
+  const int e_min = 1 - bias;
+  const int fe = (int)(a >> 23);
+  if (fe != 0 && fe - 127 >= e_min) return sign | ((uint32_t)(fe - 127 + bias) << M) | ((a & 0x7fffffu) >> (23 - M));
+  const uint32_t sig = (a & 0x7fffffu) | (fe ? 0x800000u : 0u);  // value = sig 2^(max(fe, 1) - 150)
+  const int sh = (e_min - M) - ((fe ? fe : 1) - 150);
+  return sign | (sh >= 32 ? 0u : sig >> sh);
+}
+
+__device__ __forceinline__ float exmy_decode(uint32_t c, int E, int M) {
+  const uint32_t mag = c & ((1u << (E + M)) - 1u);
+  const uint32_t ef = mag >> M, mant = mag & ((1u << M) - 1u);
+  const int bias = (1 << (E - 1)) - 1;
+  const bool ieee = (E == 5 && M == 10) || E == 8;
+  float v;
+  if (ieee && ef == (1u << E) - 1u) v = mant ? __uint_as_float(0x7fc00000u) : __uint_as_float(0x7f800000u);
+  else if (ef == 0u) v = ldexpf((float)mant, 1 - bias - M);
+  else v = ldexpf((float)((1u << M) | mant), (int)ef - bias - M);
+  return ((c >> (E + M)) & 1u) ? -v : v;
+}
+
+// a group of N values as ceil(N / Q) words (Q = codes per word)
+// Group of N values to packed codes: q = floor(32 / b) codes per word, code i at bits (i % q) b of
+// word i / q, written to base[k * stride] for word k.  q is a runtime property of the type; the walk
+// keeps one word in flight, so the code does not depend on q.
+template <int N>
+__device__ __forceinline__ void pxm_store_words(const float (&v)[N], int E, int M, int q, float inv, uint32_t* base,
+                                                int stride) {
+  const int b = 1 + E + M;
+  uint32_t acc = 0u;
+  int c = 0, k = 0;
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    acc |= exmy_encode(v[i] * inv, E, M) << (c * b);
+    if (++c == q) {
+      base[k * stride] = acc;
+      ++k;
+      acc = 0u;
+      c = 0;
+    }
+  }
+  if (c) base[k * stride] = acc;
+}
+
+template <int N>
+__device__ __forceinline__ void pxm_load_words(const uint32_t* base, int stride, int E, int M, int q, float scale,
+                                               float (&v)[N]) {
+  const int b = 1 + E + M;
+  const uint32_t mask = b >= 32 ? 0xffffffffu : (1u << b) - 1u;
+  uint32_t w = base[0];
+  int c = 0, k = 0;
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+    if (c == q) {
+      w = base[++k * stride];
+      c = 0;
+    }
+    v[i] = exmy_decode((w >> (c * b)) & mask, E, M) * scale;
+    ++c;
+  }
 }
 
 // ---- scalar encode / decode -------------------------------------------------------------------

@@ -65,27 +65,50 @@ __device__ __forceinline__ uint32_t* lane_base(const TV& t, int64_t b) {
   return t.p + ((b >> 6) * t.P) * 64 + (b & 63);
 }
 
-// an emulated ExMy tensor stores the FP32 value of each element rounded to its type
+// values of a group after a round trip through an emulated ExMy type (codes then values)
 template <int N>
 __device__ __forceinline__ void exmy_group(const TV& t, float (&v)[N]) {
 #pragma unroll
   for (int i = 0; i < N; ++i) v[i] = exmy_round(v[i] * t.inv, t.xe, t.xm) * t.scale;
 }
 
+// ---- packed ExMy groups: group `slot` of N values occupies ceil(N / q) words, q = floor(32 / b) ------
+
+template <int N>
+__device__ __forceinline__ void pxm_store(const TV& t, uint32_t* lane, int slot, const float (&v)[N]) {
+  const int dw = (N + t.pq - 1) / t.pq;
+  pxm_store_words<N>(v, t.xe, t.xm, t.pq, t.inv, lane + slot * dw * 64, 64);
+}
+
+template <int N>
+__device__ __forceinline__ void pxm_load(const TV& t, const uint32_t* lane, int slot, float (&v)[N]) {
+  const int dw = (N + t.pq - 1) / t.pq;
+  pxm_load_words<N>(lane + slot * dw * 64, 64, t.xe, t.xm, t.pq, t.scale, v);
+}
+
+template <int N>
+__device__ __forceinline__ float pxm_load_elem(const TV& t, const uint32_t* lane, int slot, int pos) {
+  const int q = t.pq, b = 1 + t.xe + t.xm;
+  const int dw = (N + q - 1) / q;
+  const uint32_t w = lane[(slot * dw + pos / q) * 64];
+  const uint32_t mask = b >= 32 ? 0xffffffffu : (1u << b) - 1u;
+  return exmy_decode((w >> ((pos % q) * b)) & mask, t.xe, t.xm) * t.scale;
+}
+
+// ---- format-dispatched group access ---------------------------------------------------------------
+
 template <int F, int N>
 __device__ __forceinline__ void store_group_t(const TV& t, int64_t b, int slot, const float (&v_in)[N]) {
-  constexpr int DW = group_dwords(F, N);
-  uint32_t w[DW];
-  float v[N];
+  if constexpr (F == PXM) {
+    pxm_store<N>(t, lane_base(t, b), slot, v_in);
+  } else {
+    constexpr int DW = group_dwords(F, N);
+    uint32_t w[DW];
+    encode_group<F, N>(v_in, t.inv, w);
+    uint32_t* base = lane_base(t, b) + slot * DW * 64;
 #pragma unroll
-  for (int i = 0; i < N; ++i) v[i] = v_in[i];
-  if constexpr (F == F32) {
-    if (t.xe) exmy_group<N>(t, v);
+    for (int k = 0; k < DW; ++k) base[k * 64] = w[k];
   }
-  encode_group<F, N>(v, t.inv, w);
-  uint32_t* base = lane_base(t, b) + slot * DW * 64;
-#pragma unroll
-  for (int k = 0; k < DW; ++k) base[k * 64] = w[k];
 }
 
 template <int N>
@@ -97,77 +120,90 @@ __device__ __forceinline__ void store_group(const TV& t, int64_t b, int slot, co
     case E4M3: store_group_t<E4M3, N>(t, b, slot, v); break;
     case E5M2: store_group_t<E5M2, N>(t, b, slot, v); break;
     case E3M2: store_group_t<E3M2, N>(t, b, slot, v); break;
-    default: store_group_t<E2M1, N>(t, b, slot, v); break;
+    case E2M1: store_group_t<E2M1, N>(t, b, slot, v); break;
+    default: store_group_t<PXM, N>(t, b, slot, v); break;
   }
 }
 
+// group `slot` of N values of tensor t, from a lane base (HBM or an LDS image of the same layout)
 template <int F, int N>
-__device__ __forceinline__ void load_group_at(const uint32_t* base, int slot, float scale, float (&v)[N]) {
-  constexpr int DW = group_dwords(F, N);
-  uint32_t w[DW];
+__device__ __forceinline__ void load_group_at(const TV& t, const uint32_t* base, int slot, float (&v)[N]) {
+  if constexpr (F == PXM) {
+    pxm_load<N>(t, base, slot, v);
+  } else {
+    constexpr int DW = group_dwords(F, N);
+    uint32_t w[DW];
 #pragma unroll
-  for (int k = 0; k < DW; ++k) w[k] = base[(slot * DW + k) * 64];
-  decode_group<F, N>(w, scale, v);
+    for (int k = 0; k < DW; ++k) w[k] = base[(slot * DW + k) * 64];
+    decode_group<F, N>(w, t.scale, v);
+  }
 }
 
 template <int N>
-__device__ __forceinline__ void load_group_fmt(int fmt, const uint32_t* base, int slot, float scale, float (&v)[N]) {
-  switch (fmt) {
-    case F32: load_group_at<F32, N>(base, slot, scale, v); break;
-    case F16: load_group_at<F16, N>(base, slot, scale, v); break;
-    case BF16: load_group_at<BF16, N>(base, slot, scale, v); break;
-    case E4M3: load_group_at<E4M3, N>(base, slot, scale, v); break;
-    case E5M2: load_group_at<E5M2, N>(base, slot, scale, v); break;
-    case E3M2: load_group_at<E3M2, N>(base, slot, scale, v); break;
-    default: load_group_at<E2M1, N>(base, slot, scale, v); break;
+__device__ __forceinline__ void load_group_fmt(const TV& t, const uint32_t* base, int slot, float (&v)[N]) {
+  switch (t.fmt) {
+    case F32: load_group_at<F32, N>(t, base, slot, v); break;
+    case F16: load_group_at<F16, N>(t, base, slot, v); break;
+    case BF16: load_group_at<BF16, N>(t, base, slot, v); break;
+    case E4M3: load_group_at<E4M3, N>(t, base, slot, v); break;
+    case E5M2: load_group_at<E5M2, N>(t, base, slot, v); break;
+    case E3M2: load_group_at<E3M2, N>(t, base, slot, v); break;
+    case E2M1: load_group_at<E2M1, N>(t, base, slot, v); break;
+    default: load_group_at<PXM, N>(t, base, slot, v); break;
   }
 }
 
 template <int N>
 __device__ __forceinline__ void load_group(const TV& t, int64_t b, int slot, float (&v)[N]) {
-  load_group_fmt<N>(t.fmt, lane_base(t, b), slot, t.scale, v);
+  load_group_fmt<N>(t, lane_base(t, b), slot, v);
 }
 
 // stored value of element `pos` of the group of N values in slot `slot`
 template <int F, int N>
-__device__ __forceinline__ float load_elem_at(const uint32_t* base, int slot, int pos, float scale) {
-  constexpr int DW = group_dwords(F, N);
-  constexpr int BITS = Fmt<F>::BITS;
-  const int bit = pos * BITS, wi = bit >> 5, sh = bit & 31;
-  uint64_t v = base[(slot * DW + wi) * 64];
-  if (sh + BITS > 32) v |= (uint64_t)base[(slot * DW + wi + 1) * 64] << 32;
-  const uint32_t code = (uint32_t)(v >> sh) & (BITS == 32 ? 0xffffffffu : ((1u << BITS) - 1u));
-  return decode_one<F>(code, scale);
+__device__ __forceinline__ float load_elem_at(const TV& t, const uint32_t* base, int slot, int pos) {
+  if constexpr (F == PXM) {
+    return pxm_load_elem<N>(t, base, slot, pos);
+  } else {
+    constexpr int DW = group_dwords(F, N);
+    constexpr int BITS = Fmt<F>::BITS;
+    const int bit = pos * BITS, wi = bit >> 5, sh = bit & 31;
+    uint64_t v = base[(slot * DW + wi) * 64];
+    if (sh + BITS > 32) v |= (uint64_t)base[(slot * DW + wi + 1) * 64] << 32;
+    const uint32_t code = (uint32_t)(v >> sh) & (BITS == 32 ? 0xffffffffu : ((1u << BITS) - 1u));
+    return decode_one<F>(code, t.scale);
+  }
 }
 
 template <int N>
-__device__ __forceinline__ float load_elem_fmt(int fmt, const uint32_t* base, int slot, int pos, float scale) {
-  switch (fmt) {
-    case F32: return load_elem_at<F32, N>(base, slot, pos, scale);
-    case F16: return load_elem_at<F16, N>(base, slot, pos, scale);
-    case BF16: return load_elem_at<BF16, N>(base, slot, pos, scale);
-    case E4M3: return load_elem_at<E4M3, N>(base, slot, pos, scale);
-    case E5M2: return load_elem_at<E5M2, N>(base, slot, pos, scale);
-    case E3M2: return load_elem_at<E3M2, N>(base, slot, pos, scale);
-    default: return load_elem_at<E2M1, N>(base, slot, pos, scale);
+__device__ __forceinline__ float load_elem_fmt(const TV& t, const uint32_t* base, int slot, int pos) {
+  switch (t.fmt) {
+    case F32: return load_elem_at<F32, N>(t, base, slot, pos);
+    case F16: return load_elem_at<F16, N>(t, base, slot, pos);
+    case BF16: return load_elem_at<BF16, N>(t, base, slot, pos);
+    case E4M3: return load_elem_at<E4M3, N>(t, base, slot, pos);
+    case E5M2: return load_elem_at<E5M2, N>(t, base, slot, pos);
+    case E3M2: return load_elem_at<E3M2, N>(t, base, slot, pos);
+    case E2M1: return load_elem_at<E2M1, N>(t, base, slot, pos);
+    default: return load_elem_at<PXM, N>(t, base, slot, pos);
   }
 }
 
 template <int N>
 __device__ __forceinline__ float load_elem(const TV& t, int64_t b, int slot, int pos) {
-  return load_elem_fmt<N>(t.fmt, lane_base(t, b), slot, pos, t.scale);
+  return load_elem_fmt<N>(t, lane_base(t, b), slot, pos);
 }
 
 // stored values of a group after a round trip through the format (what a reader will see)
 template <int F, int N>
 __device__ __forceinline__ void roundtrip_t(const TV& t, float (&v)[N]) {
-  constexpr int DW = group_dwords(F, N);
-  uint32_t w[DW];
-  if constexpr (F == F32) {
-    if (t.xe) exmy_group<N>(t, v);
+  if constexpr (F == PXM) {
+    exmy_group<N>(t, v);
+  } else {
+    constexpr int DW = group_dwords(F, N);
+    uint32_t w[DW];
+    encode_group<F, N>(v, t.inv, w);
+    decode_group<F, N>(w, t.scale, v);
   }
-  encode_group<F, N>(v, t.inv, w);
-  decode_group<F, N>(w, t.scale, v);
 }
 
 template <int N>
@@ -179,7 +215,8 @@ __device__ __forceinline__ void roundtrip(const TV& t, float (&v)[N]) {
     case E4M3: roundtrip_t<E4M3, N>(t, v); break;
     case E5M2: roundtrip_t<E5M2, N>(t, v); break;
     case E3M2: roundtrip_t<E3M2, N>(t, v); break;
-    default: roundtrip_t<E2M1, N>(t, v); break;
+    case E2M1: roundtrip_t<E2M1, N>(t, v); break;
+    default: roundtrip_t<PXM, N>(t, v); break;
   }
 }
 
@@ -653,9 +690,9 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3))) void k
   float px[SPH_GROUP], py[SPH_GROUP], pz[SPH_GROUP];
   if (valid) {
     const uint32_t* sb = lane_base(S, b);
-    load_group_at<FS, SPH_GROUP>(sb, g * 3 + 0, S.scale, px);
-    load_group_at<FS, SPH_GROUP>(sb, g * 3 + 1, S.scale, py);
-    load_group_at<FS, SPH_GROUP>(sb, g * 3 + 2, S.scale, pz);
+    load_group_at<FS, SPH_GROUP>(S, sb, g * 3 + 0, px);
+    load_group_at<FS, SPH_GROUP>(S, sb, g * 3 + 1, py);
+    load_group_at<FS, SPH_GROUP>(S, sb, g * 3 + 2, pz);
   } else {
 #pragma unroll
     for (int i = 0; i < SPH_GROUP; ++i) px[i] = py[i] = pz[i] = 0.f;
@@ -867,13 +904,14 @@ __device__ __forceinline__ void walk_list_single(uint64_t m, const float* base, 
   }
 }
 
-// Values h * 8 .. h * 8 + 7 of a stored group of 16.  Every format but FP6 packs 8 values into half
-// the group's dwords, which are read alone; FP6 groups (3 dwords) are decoded whole.
+// Values h * 8 .. h * 8 + 7 of a stored group of 16.  Every storage format but FP6 packs 8 values into
+// half the group's dwords, which are read alone; FP6 groups (3 dwords) and packed ExMy groups are
+// decoded whole.
 template <int FS>
-__device__ __forceinline__ void load_half_at(const uint32_t* base, int slot, int h, float scale, float (&v)[HS]) {
-  if constexpr (FS == E3M2) {
+__device__ __forceinline__ void load_half_at(const TV& t, const uint32_t* base, int slot, int h, float (&v)[HS]) {
+  if constexpr (FS == E3M2 || FS == PXM) {
     float f[SPH_GROUP];
-    load_group_at<FS, SPH_GROUP>(base, slot, scale, f);
+    load_group_at<FS, SPH_GROUP>(t, base, slot, f);
 #pragma unroll
     for (int i = 0; i < HS; ++i) v[i] = h ? f[HS + i] : f[i];
   } else {
@@ -882,7 +920,7 @@ __device__ __forceinline__ void load_half_at(const uint32_t* base, int slot, int
     uint32_t w[DWH];
 #pragma unroll
     for (int k = 0; k < DWH; ++k) w[k] = base[(slot * DW + h * DWH + k) * 64];
-    decode_group<FS, HS>(w, scale, v);
+    decode_group<FS, HS>(w, t.scale, v);
   }
 }
 
@@ -918,9 +956,9 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(VAPR_K2H_WA
   float px[HS], py[HS], pz[HS];
   if (valid) {
     const uint32_t* sb = lane_base(S, b);
-    load_half_at<FS>(sb, g * 3 + 0, h, S.scale, px);
-    load_half_at<FS>(sb, g * 3 + 1, h, S.scale, py);
-    load_half_at<FS>(sb, g * 3 + 2, h, S.scale, pz);
+    load_half_at<FS>(S, sb, g * 3 + 0, h, px);
+    load_half_at<FS>(S, sb, g * 3 + 1, h, py);
+    load_half_at<FS>(S, sb, g * 3 + 2, h, pz);
   } else {
 #pragma unroll
     for (int i = 0; i < HS; ++i) px[i] = py[i] = pz[i] = 0.f;
@@ -1235,8 +1273,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
         for (int q = 0; q < 3; ++q) {
           float v0 = 0.f, v1 = 0.f;
           if (seg && q4 + i < active) {
-            v0 = load_elem_at<FS, SPH_GROUP>(b0, g * 3 + q, q4 + i, S.scale);
-            v1 = load_elem_at<FS, SPH_GROUP>(b1, g * 3 + q, q4 + i, S.scale);
+            v0 = load_elem_at<FS, SPH_GROUP>(S, b0, g * 3 + q, q4 + i);
+            v1 = load_elem_at<FS, SPH_GROUP>(S, b1, g * 3 + q, q4 + i);
           }
           p0[q][i] = v0;
           dp[q][i] = v1 - v0;
@@ -1443,22 +1481,22 @@ __global__ __launch_bounds__(256) void k_reduce(TV D, const float* __restrict__ 
 // Force and moment (about the world origin) of the sphere gradients on link l: spheres of the link
 // are visited in increasing index over the groups that hold them, with G decoded a group at a time.
 template <int FG, bool HAS_X>
-__device__ __forceinline__ void link_wrench(const RobotArgs& R, const uint32_t* gbase, float gscale, const TV& X,
+__device__ __forceinline__ void link_wrench(const RobotArgs& R, const uint32_t* gbase, const TV& G, const TV& X,
                                             const uint32_t* xbase, int l, const float (&T)[LINK_VALUES],
                                             float (&f)[3], float (&m)[3]) {
   const cptr<int> lg = as_const(R.link_groups) + 2 * l;
   const int g_lo = lg[0], g_hi = lg[1];
   for (int g = g_lo; g < g_hi; ++g) {
     float gx[SPH_GROUP], gy[SPH_GROUP], gz[SPH_GROUP];
-    load_group_at<FG, SPH_GROUP>(gbase, g * 3 + 0, gscale, gx);
-    load_group_at<FG, SPH_GROUP>(gbase, g * 3 + 1, gscale, gy);
-    load_group_at<FG, SPH_GROUP>(gbase, g * 3 + 2, gscale, gz);
+    load_group_at<FG, SPH_GROUP>(G, gbase, g * 3 + 0, gx);
+    load_group_at<FG, SPH_GROUP>(G, gbase, g * 3 + 1, gy);
+    load_group_at<FG, SPH_GROUP>(G, gbase, g * 3 + 2, gz);
     if constexpr (HAS_X) {
       // the swept gradient, stored in a tensor of its own, adds to the sphere gradient
       float vx[SPH_GROUP], vy[SPH_GROUP], vz[SPH_GROUP];
-      load_group_fmt<SPH_GROUP>(X.fmt, xbase, g * 3 + 0, X.scale, vx);
-      load_group_fmt<SPH_GROUP>(X.fmt, xbase, g * 3 + 1, X.scale, vy);
-      load_group_fmt<SPH_GROUP>(X.fmt, xbase, g * 3 + 2, X.scale, vz);
+      load_group_fmt<SPH_GROUP>(X, xbase, g * 3 + 0, vx);
+      load_group_fmt<SPH_GROUP>(X, xbase, g * 3 + 1, vy);
+      load_group_fmt<SPH_GROUP>(X, xbase, g * 3 + 2, vz);
 #pragma unroll
       for (int i = 0; i < SPH_GROUP; ++i) {
         gx[i] += vx[i];
@@ -1545,7 +1583,7 @@ __global__ __launch_bounds__(256) void k_adjoint(const float* __restrict__ q, Ro
     float T[LINK_VALUES];
     pose_from_tile(tile, l - 1, lane, T);
     float f[3] = {0.f, 0.f, 0.f}, m[3] = {0.f, 0.f, 0.f};
-    if (live) link_wrench<FG, HAS_X>(R, gbase, G.scale, X, xbase, l, T, f, m);
+    if (live) link_wrench<FG, HAS_X>(R, gbase, G, X, xbase, l, T, f, m);
     float* w = wrench + (l - 1) * 6 * 64 + lane;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
@@ -2064,6 +2102,92 @@ __global__ __launch_bounds__(256) void k_import(TV t, int tensor, int64_t B, int
   for (int k = 0; k < DW; ++k) t.p[plane_index(b, t.P, slot * DW + k)] = w[k];
 }
 
+// Packed ExMy tensors: the flat buffer holds the codes in canonical element order, floor(32 / b) to a
+// word (the same packing as the workspace groups).  Export: one thread per flat word; import: one
+// thread per (configuration, slot) group.
+__device__ __forceinline__ uint32_t pxm_code_at(const TV& t, int tensor, int64_t b, int slot, int pos) {
+  const int q = t.pq, bits = 1 + t.xe + t.xm;
+  const int DW = pxm_group_dwords(t.xe, t.xm, group_size(tensor));
+  const uint32_t w = t.p[plane_index(b, t.P, slot * DW + pos / q)];
+  return (w >> ((pos % q) * bits)) & (bits >= 32 ? 0xffffffffu : (1u << bits) - 1u);
+}
+
+__global__ __launch_bounds__(256) void k_export_pxm(TV t, int tensor, int64_t B, int ecfg, uint32_t* __restrict__ flat) {
+  const int64_t wi = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int q = t.pq, bits = 1 + t.xe + t.xm;
+  const int64_t total_e = B * ecfg;
+  if (wi * q >= total_e) return;
+  uint32_t w = 0;
+  for (int j = 0; j < q; ++j) {
+    const int64_t e = wi * q + j;
+    if (e >= total_e) break;
+    const int64_t b = e / ecfg;
+    int slot, pos;
+    elem_slot(tensor, (int)(e - b * ecfg), slot, pos);
+    w |= pxm_code_at(t, tensor, b, slot, pos) << (j * bits);
+  }
+  flat[wi] = w;
+}
+
+__global__ __launch_bounds__(256) void k_import_pxm(TV t, int tensor, int64_t B, int ecfg, int n_slots, int n_s,
+                                                    const uint32_t* __restrict__ flat) {
+  const int64_t gi = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (gi >= B * n_slots) return;
+  const int64_t b = gi / n_slots;
+  const int slot = (int)(gi - b * n_slots);
+  const int gs = group_size(tensor);
+  const int q = t.pq, bits = 1 + t.xe + t.xm;
+  const uint32_t mask = bits >= 32 ? 0xffffffffu : (1u << bits) - 1u;
+  const int DW = pxm_group_dwords(t.xe, t.xm, gs);
+  uint32_t w[L_GROUP];  // at most 48 words (one code a word)
+  for (int k = 0; k < DW; ++k) w[k] = 0;
+  for (int pos = 0; pos < gs; ++pos) {
+    int loc = -1;
+    switch (tensor) {
+      case T_L: loc = (slot * 4 + pos / LINK_VALUES) * LINK_VALUES + pos % LINK_VALUES; break;
+      case T_S:
+      case T_G: {
+        const int s = (slot / 3) * SPH_GROUP + pos;
+        loc = s < n_s ? s * 3 + slot % 3 : -1;
+      } break;
+      case T_D: {
+        const int s = slot * SPH_GROUP + pos;
+        loc = s < n_s ? s : -1;
+      } break;
+      default: loc = pos < N_JOINTS ? pos : -1; break;
+    }
+    if (loc < 0 || loc >= ecfg) continue;
+    const int64_t e = b * ecfg + loc;
+    const uint32_t c = (flat[e / q] >> ((e % q) * bits)) & mask;
+    w[pos / q] |= c << ((pos % q) * bits);
+  }
+  for (int k = 0; k < DW; ++k) t.p[plane_index(b, t.P, slot * DW + k)] = w[k];
+}
+
+// packed ExMy element-wise codec: one thread per output word (q = floor(32 / b) values)
+__global__ __launch_bounds__(256) void k_quantize_pxm(int E, int M, float inv, const float* __restrict__ in,
+                                                      uint32_t* __restrict__ out, int64_t n) {
+  const int q = pxm_per_word(E, M), b = 1 + E + M;
+  const int64_t wi = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (wi * q >= n) return;
+  uint32_t w = 0;
+  for (int j = 0; j < q; ++j) {
+    const int64_t i = wi * q + j;
+    if (i >= n) break;
+    w |= exmy_encode(in[i] * inv, E, M) << (j * b);
+  }
+  out[wi] = w;
+}
+
+__global__ __launch_bounds__(256) void k_dequantize_pxm(int E, int M, float scale, const uint32_t* __restrict__ in,
+                                                        float* __restrict__ out, int64_t n) {
+  const int q = pxm_per_word(E, M), b = 1 + E + M;
+  const uint32_t mask = b >= 32 ? 0xffffffffu : (1u << b) - 1u;
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  out[i] = exmy_decode((in[i / q] >> ((i % q) * b)) & mask, E, M) * scale;
+}
+
 // ---- launch wrappers ----------------------------------------------------------------------------
 
 static inline unsigned blocks_for(int64_t n, int per_block) { return (unsigned)((n + per_block - 1) / per_block); }
@@ -2077,7 +2201,7 @@ hipError_t launch_fk(hipStream_t s, const float* q, const RobotArgs& R, const TV
   case F: hipLaunchKernelGGL(k_fk<F>, grid, block, 0, s, q, R, L, S, bound, B, store_L, goal, posec, cfg_per_world, cp); \
     break;
     VAPR_FK_CASE(F32) VAPR_FK_CASE(F16) VAPR_FK_CASE(BF16) VAPR_FK_CASE(E4M3) VAPR_FK_CASE(E5M2)
-    VAPR_FK_CASE(E3M2) VAPR_FK_CASE(E2M1)
+    VAPR_FK_CASE(E3M2) VAPR_FK_CASE(E2M1) VAPR_FK_CASE(PXM)
 #undef VAPR_FK_CASE
     default: return hipErrorInvalidValue;
   }
@@ -2102,7 +2226,7 @@ hipError_t launch_sphere_cost_half(hipStream_t s, const RobotArgs& R, const Worl
   switch (S.fmt) {
 #define VAPR_K2H(F) \
   case F: hipLaunchKernelGGL(k_sphere_cost_half<F>, grid, block, lds, s, R, W, Gd, S, D, G, selfc, sh, cp); break;
-    VAPR_K2H(F32) VAPR_K2H(F16) VAPR_K2H(BF16) VAPR_K2H(E4M3) VAPR_K2H(E5M2) VAPR_K2H(E3M2) VAPR_K2H(E2M1)
+    VAPR_K2H(F32) VAPR_K2H(F16) VAPR_K2H(BF16) VAPR_K2H(E4M3) VAPR_K2H(E5M2) VAPR_K2H(E3M2) VAPR_K2H(E2M1) VAPR_K2H(PXM)
 #undef VAPR_K2H
     default: return hipErrorInvalidValue;
   }
@@ -2116,7 +2240,7 @@ hipError_t launch_sphere_cost_blk(hipStream_t s, const RobotArgs& R, const World
   switch (S.fmt) {
 #define VAPR_K2(F) \
   case F: hipLaunchKernelGGL(k_sphere_cost_blk<F>, grid, block, lds, s, R, W, Gd, S, D, G, selfc, sh, cp); break;
-    VAPR_K2(F32) VAPR_K2(F16) VAPR_K2(BF16) VAPR_K2(E4M3) VAPR_K2(E5M2) VAPR_K2(E3M2) VAPR_K2(E2M1)
+    VAPR_K2(F32) VAPR_K2(F16) VAPR_K2(BF16) VAPR_K2(E4M3) VAPR_K2(E5M2) VAPR_K2(E3M2) VAPR_K2(E2M1) VAPR_K2(PXM)
 #undef VAPR_K2
     default: return hipErrorInvalidValue;
   }
@@ -2143,7 +2267,7 @@ hipError_t launch_swept(hipStream_t s, const RobotArgs& R, const WorldArgs& W, c
 #define VAPR_SWEPT_CASE(F) \
   case F: hipLaunchKernelGGL(k_swept<F>, grid, block, SWEPT_LDS_BYTES, s, R, W, Gd, S, X, sweptc, sh, cp); break;
     VAPR_SWEPT_CASE(F32) VAPR_SWEPT_CASE(F16) VAPR_SWEPT_CASE(BF16) VAPR_SWEPT_CASE(E4M3) VAPR_SWEPT_CASE(E5M2)
-    VAPR_SWEPT_CASE(E3M2) VAPR_SWEPT_CASE(E2M1)
+    VAPR_SWEPT_CASE(E3M2) VAPR_SWEPT_CASE(E2M1) VAPR_SWEPT_CASE(PXM)
 #undef VAPR_SWEPT_CASE
     default: return hipErrorInvalidValue;
   }
@@ -2161,7 +2285,7 @@ hipError_t launch_adjoint(hipStream_t s, const float* q, const RobotArgs& R, con
     else hipLaunchKernelGGL((k_adjoint<F, false>), grid, block, 0, s, q, R, L, G, X, J, up, grad_q, sh, cp, recompute, goal, ck); \
     break;
     VAPR_ADJ_CASE(F32) VAPR_ADJ_CASE(F16) VAPR_ADJ_CASE(BF16) VAPR_ADJ_CASE(E4M3) VAPR_ADJ_CASE(E5M2)
-    VAPR_ADJ_CASE(E3M2) VAPR_ADJ_CASE(E2M1)
+    VAPR_ADJ_CASE(E3M2) VAPR_ADJ_CASE(E2M1) VAPR_ADJ_CASE(PXM)
 #undef VAPR_ADJ_CASE
     default: return hipErrorInvalidValue;
   }
@@ -2200,6 +2324,18 @@ hipError_t launch_round_exmy(hipStream_t s, int E, int M, float inv, float scale
   return hipGetLastError();
 }
 
+hipError_t launch_quantize_exmy(hipStream_t s, int E, int M, float inv, const float* in, uint32_t* out, int64_t n) {
+  const int64_t words = (n + pxm_per_word(E, M) - 1) / pxm_per_word(E, M);
+  hipLaunchKernelGGL(k_quantize_pxm, dim3(blocks_for(words, 256)), dim3(256), 0, s, E, M, inv, in, out, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_dequantize_exmy(hipStream_t s, int E, int M, float scale, const uint32_t* in, float* out,
+                                  int64_t n) {
+  hipLaunchKernelGGL(k_dequantize_pxm, dim3(blocks_for(n, 256)), dim3(256), 0, s, E, M, scale, in, out, n);
+  return hipGetLastError();
+}
+
 hipError_t launch_quantize(hipStream_t s, int fmt, float inv, const float* in, uint8_t* out, int64_t n) {
   const dim3 grid(blocks_for((n + 15) / 16, 256)), block(256);
   switch (fmt) {
@@ -2230,7 +2366,11 @@ hipError_t launch_dequantize(hipStream_t s, int fmt, float scale, const uint8_t*
 
 hipError_t launch_repack(hipStream_t s, int tensor, const TV& t, int64_t B, int ecfg, int n_s, uint8_t* flat,
                          int direction) {
-  if (direction == 0) {
+  if (direction == 0 && t.fmt == PXM) {
+    const int64_t words = (B * ecfg + t.pq - 1) / t.pq;
+    hipLaunchKernelGGL(k_export_pxm, dim3(blocks_for(words, 256)), dim3(256), 0, s, t, tensor, B, ecfg,
+                       reinterpret_cast<uint32_t*>(flat));
+  } else if (direction == 0) {
     hipLaunchKernelGGL(k_export, dim3(blocks_for((B * ecfg + 15) / 16, 256)), dim3(256), 0, s, t, tensor, B, ecfg,
                        flat);
   } else {
@@ -2243,8 +2383,12 @@ hipError_t launch_repack(hipStream_t s, int tensor, const TV& t, int64_t B, int 
       case T_D: n_slots = ng; break;
       default: n_slots = 1; break;
     }
-    hipLaunchKernelGGL(k_import, dim3(blocks_for(B * n_slots, 256)), dim3(256), 0, s, t, tensor, B, ecfg, n_slots,
-                       n_s, (const uint8_t*)flat);
+    if (t.fmt == PXM)
+      hipLaunchKernelGGL(k_import_pxm, dim3(blocks_for(B * n_slots, 256)), dim3(256), 0, s, t, tensor, B, ecfg,
+                         n_slots, n_s, reinterpret_cast<const uint32_t*>(flat));
+    else
+      hipLaunchKernelGGL(k_import, dim3(blocks_for(B * n_slots, 256)), dim3(256), 0, s, t, tensor, B, ecfg, n_slots,
+                         n_s, (const uint8_t*)flat);
   }
   return hipGetLastError();
 }

@@ -41,7 +41,8 @@ struct TV {  // one stored tensor inside a workspace
   int P;
   float scale;  // 2^k
   float inv;    // 2^-k
-  int xe, xm;   // xe > 0: an emulated ExMy type, stored as the FP32 values rounded to it (fmt F32)
+  int xe, xm;   // fmt PXM: an emulated ExMy type (exponent, mantissa bits) stored as packed codes,
+  int pq;       // pq = floor(32 / (1 + xe + xm)) codes per word
 };
 
 struct ShapeArgs {
@@ -123,6 +124,10 @@ hipError_t launch_quantize(hipStream_t s, int fmt, float inv, const float* in, u
 hipError_t launch_round_exmy(hipStream_t s, int E, int M, float inv, float scale, const float* in, float* out,
                              int64_t n);
 hipError_t launch_dequantize(hipStream_t s, int fmt, float scale, const uint8_t* in, float* out, int64_t n);
+// packed codes of an emulated ExMy type, floor(32 / b) per word
+hipError_t launch_quantize_exmy(hipStream_t s, int E, int M, float inv, const float* in, uint32_t* out, int64_t n);
+hipError_t launch_dequantize_exmy(hipStream_t s, int E, int M, float scale, const uint32_t* in, float* out,
+                                  int64_t n);
 // tensor: T_L .. T_J; per-configuration element count ecfg; direction 0 export (ws -> flat), 1 import
 hipError_t launch_repack(hipStream_t s, int tensor, const TV& t, int64_t B, int ecfg, int n_s, uint8_t* flat,
                          int direction);

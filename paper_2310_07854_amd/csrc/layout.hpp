@@ -6,7 +6,8 @@
 // A wavefront therefore reads or writes 256 contiguous bytes per instruction and a block's whole
 // tensor is one contiguous run of P * 256 bytes.
 //
-// Plane contents (values packed as in codec.hpp, dw(n) = dwords of a packed group of n values):
+// Plane contents (values packed as in codec.hpp, dw(n) = dwords of a packed group of n values; a
+// packed ExMy type holds floor(32 / b) codes a dword, so dw(n) = ceil(n / floor(32 / b))):
 //   L  links 1..8, [R | t] row-major: 2 groups of 48 values (links 1-4, 5-8)   2 * dw(48) planes
 //   S  ceil(n_s/16) groups of 16 spheres x 3 components, plane = (g*3 + c)*dw(16) + w
 //   D  ceil(n_s/16) groups of 16 spheres,                plane = g*dw(16) + w
@@ -45,10 +46,15 @@ constexpr int MAX_HIST = 8;
 constexpr int MAX_SWEEP = 16;       // swept samples per segment
 
 struct TensorFormat {
-  int fmt;        // storage format (F32 for an emulated ExMy type)
+  int fmt;        // storage format (PXM for an emulated ExMy type)
   int scale_exp;
   int xe, xm;     // emulated ExMy type (xe > 0), else 0
 };
+
+// dwords of a packed group of n values
+__host__ __device__ inline int tf_group_dwords(const TensorFormat& f, int n) {
+  return f.fmt == PXM ? pxm_group_dwords(f.xe, f.xm, n) : group_dwords(f.fmt, n);
+}
 
 struct PrecisionCfg {
   TensorFormat t[6];  // L, S, D, G, J, X
@@ -104,12 +110,12 @@ inline Layout make_layout(int64_t B, int n_s, const PrecisionCfg& pc) {
   L.nblk = L.Bp / 64;
   L.n_s = n_s;
   L.n_groups = (n_s + SPH_GROUP - 1) / SPH_GROUP;
-  L.P[T_L] = pc.recompute ? 0 : L_GROUPS * group_dwords(pc.t[T_L].fmt, L_GROUP);
-  L.P[T_S] = L.n_groups * 3 * group_dwords(pc.t[T_S].fmt, SPH_GROUP);
-  L.P[T_D] = L.n_groups * group_dwords(pc.t[T_D].fmt, SPH_GROUP);
-  L.P[T_G] = L.n_groups * 3 * group_dwords(pc.t[T_G].fmt, SPH_GROUP);
-  L.P[T_J] = group_dwords(pc.t[T_J].fmt, J_GROUP);
-  L.P[T_X] = pc.sweep ? L.n_groups * 3 * group_dwords(pc.t[T_X].fmt, SPH_GROUP) : 0;
+  L.P[T_L] = pc.recompute ? 0 : L_GROUPS * tf_group_dwords(pc.t[T_L], L_GROUP);
+  L.P[T_S] = L.n_groups * 3 * tf_group_dwords(pc.t[T_S], SPH_GROUP);
+  L.P[T_D] = L.n_groups * tf_group_dwords(pc.t[T_D], SPH_GROUP);
+  L.P[T_G] = L.n_groups * 3 * tf_group_dwords(pc.t[T_G], SPH_GROUP);
+  L.P[T_J] = tf_group_dwords(pc.t[T_J], J_GROUP);
+  L.P[T_X] = pc.sweep ? L.n_groups * 3 * tf_group_dwords(pc.t[T_X], SPH_GROUP) : 0;
   size_t o = WS_HEADER_BYTES;
   for (int i = 0; i < 5; ++i) {
     L.off[i] = o;

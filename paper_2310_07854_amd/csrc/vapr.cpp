@@ -203,9 +203,9 @@ void free_robot(vapr_ctx* ctx) {
   ctx->has_robot = false;
 }
 
-// an emulated ExMy type is stored as FP32 values rounded to it
+// an emulated ExMy type is stored as its own packed codes
 TensorFormat tensor_format(const vapr_tensor_format& f) {
-  if (f.fmt == VAPR_EXMY) return TensorFormat{F32, f.scale_exp, f.exp_bits, f.man_bits};
+  if (f.fmt == VAPR_EXMY) return TensorFormat{PXM, f.scale_exp, f.exp_bits, f.man_bits};
   return TensorFormat{f.fmt, f.scale_exp, 0, 0};
 }
 
@@ -343,6 +343,7 @@ TV tensor_view(void* ws, const Layout& L, const PrecisionCfg& pc, int t) {
   v.inv = std::ldexp(1.0f, -pc.t[t].scale_exp);
   v.xe = pc.t[t].xe;
   v.xm = pc.t[t].xm;
+  v.pq = pc.t[t].fmt == PXM ? pxm_per_word(v.xe, v.xm) : 0;
   return v;
 }
 
@@ -1102,14 +1103,20 @@ int vapr_optimizer_step(vapr_ctx* ctx, const vapr_lbfgs_state* st, const void* w
 }
 
 size_t vapr_packed_bytes(int fmt, int64_t n) {
-  if (fmt == VAPR_EXMY) return n < 0 ? 0 : (size_t)n * 4;  // FP32 values
-  if (fmt < VAPR_F32 || fmt > VAPR_E2M1 || n < 0) return 0;
+  if (fmt < VAPR_F32 || fmt > VAPR_E2M1 || n < 0) return 0;  // VAPR_EXMY: vapr_exmy_packed_bytes
   return (size_t)((n * format_bits(fmt) + 7) / 8);
+}
+
+size_t vapr_exmy_packed_bytes(int exp_bits, int man_bits, int64_t n) {
+  if (exp_bits < 1 || exp_bits > 8 || man_bits < 0 || man_bits > 23 || n < 0) return 0;
+  const int64_t q = pxm_per_word(exp_bits, man_bits);
+  return (size_t)((n + q - 1) / q) * 4;
 }
 
 static int codec_check(int fmt, int scale_exp, const void* in, const void* out, int64_t n) {
   vapr_tensor_format f{fmt, scale_exp, 0, 0};
-  if (fmt == VAPR_EXMY) return fail(nullptr, VAPR_E_INVALID, "emulated ExMy types have no codes: use vapr_round_exmy");
+  if (fmt == VAPR_EXMY)
+    return fail(nullptr, VAPR_E_INVALID, "emulated ExMy types: use vapr_quantize_exmy / vapr_dequantize_exmy");
   if (!valid_format(f)) return fail(nullptr, VAPR_E_INVALID, "unknown format or scale out of range");
   if (n < 0 || n > ((int64_t)1 << 32)) return fail(nullptr, VAPR_E_INVALID, "element count out of range");
   if (n > 0 && (!in || !out)) return fail(nullptr, VAPR_E_INVALID, "null pointer");
@@ -1132,6 +1139,34 @@ int vapr_dequantize(int fmt, int scale_exp, const void* in, float* out, int64_t 
   hipError_t e = launch_dequantize(static_cast<hipStream_t>(hip_stream), fmt, std::ldexp(1.0f, scale_exp),
                                    static_cast<const uint8_t*>(in), out, n);
   return e == hipSuccess ? VAPR_OK : hip_fail(nullptr, e, "k_dequantize launch");
+}
+
+static int exmy_codec_check(int exp_bits, int man_bits, int scale_exp, const void* in, const void* out, int64_t n) {
+  const vapr_tensor_format f{VAPR_EXMY, scale_exp, exp_bits, man_bits};
+  if (!valid_format(f)) return fail(nullptr, VAPR_E_INVALID, "ExMy bits or scale out of range");
+  if (n < 0 || n > ((int64_t)1 << 32)) return fail(nullptr, VAPR_E_INVALID, "element count out of range");
+  if (n > 0 && (!in || !out)) return fail(nullptr, VAPR_E_INVALID, "null pointer");
+  if ((reinterpret_cast<uintptr_t>(in) | reinterpret_cast<uintptr_t>(out)) & 3)
+    return fail(nullptr, VAPR_E_INVALID, "buffers must be 4-byte aligned");
+  return VAPR_OK;
+}
+
+int vapr_quantize_exmy(int exp_bits, int man_bits, int scale_exp, const float* in, void* out, int64_t n,
+                       void* hip_stream) {
+  int st = exmy_codec_check(exp_bits, man_bits, scale_exp, in, out, n);
+  if (st || n == 0) return st;
+  hipError_t e = launch_quantize_exmy(static_cast<hipStream_t>(hip_stream), exp_bits, man_bits,
+                                      std::ldexp(1.0f, -scale_exp), in, static_cast<uint32_t*>(out), n);
+  return e == hipSuccess ? VAPR_OK : hip_fail(nullptr, e, "k_quantize_pxm launch");
+}
+
+int vapr_dequantize_exmy(int exp_bits, int man_bits, int scale_exp, const void* in, float* out, int64_t n,
+                         void* hip_stream) {
+  int st = exmy_codec_check(exp_bits, man_bits, scale_exp, in, out, n);
+  if (st || n == 0) return st;
+  hipError_t e = launch_dequantize_exmy(static_cast<hipStream_t>(hip_stream), exp_bits, man_bits,
+                                        std::ldexp(1.0f, scale_exp), static_cast<const uint32_t*>(in), out, n);
+  return e == hipSuccess ? VAPR_OK : hip_fail(nullptr, e, "k_dequantize_pxm launch");
 }
 
 int vapr_round_exmy(int exp_bits, int man_bits, int scale_exp, const float* in, float* out, int64_t n,
@@ -1287,8 +1322,11 @@ static int ws_io(vapr_ctx* ctx, int n_worlds, int tpw, int T, int n_ls, void* ws
       return fail(ctx, VAPR_E_INVALID, "no link-pose tensor in recompute mode");
     const int ecfg = tensor_count(ctx, tensor);
     const int t = tensor == VAPR_T_SWEPT_GRAD ? T_X : tensor;  // X is laid out like G
-    const int fmt = ctx->prec.t[t].fmt;
-    if (buf_bytes < vapr_packed_bytes(fmt, B * ecfg)) return fail(ctx, VAPR_E_INVALID, "buffer too small");
+    const TensorFormat& tf = ctx->prec.t[t];
+    const size_t need = tf.fmt == PXM ? vapr_exmy_packed_bytes(tf.xe, tf.xm, B * ecfg) : vapr_packed_bytes(tf.fmt, B * ecfg);
+    if (buf_bytes < need) return fail(ctx, VAPR_E_INVALID, "buffer too small");
+    if (tf.fmt == PXM && (reinterpret_cast<uintptr_t>(buf) & 3))
+      return fail(ctx, VAPR_E_INVALID, "packed ExMy buffers must be 4-byte aligned");
     const TV tv = tensor_view(ws, L, ctx->prec, t);
     const int n_s = ctx->n_s;
     const int shape_of = t == T_X ? T_G : t;

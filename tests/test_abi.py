@@ -44,7 +44,7 @@ def test_every_declared_symbol_is_exported():
 
 def test_host_side_validation():
     L, so = lib()
-    assert so.vapr_abi_version() == 3
+    assert so.vapr_abi_version() == 4
     assert so.vapr_status_string(L.E_STATE) == b"invalid state"
     assert so.vapr_packed_bytes(L.E3M2, 5) == 4
     assert so.vapr_packed_bytes(L.E2M1, 3) == 2
