@@ -934,7 +934,11 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(VAPR_K2H_WA
   const int ng = uniform(R.n_groups);
   const int n_s = uniform(R.n_s);
   const int K = uniform(W.K);
-  const int64_t blk = blockIdx.x;
+  // Workgroups go to the eight XCDs in turn (workgroup i to XCD i mod 8); the first 8 floor(nb / 8)
+  // are remapped so that each XCD takes one contiguous run of tiles, i.e. of worlds, and its L2 holds
+  // the voxel masks and cuboids of the few worlds it is working on.
+  const int64_t nb = gridDim.x, full = nb / 8 * 8, bid = blockIdx.x;
+  const int64_t blk = bid < full ? (bid % 8) * (nb / 8) + bid / 8 : bid;
   const int64_t b = blk * 64 + lane;
   const bool valid = b < sh.B;
   const int img_words = max(n_s * 3 * 64, ng * 4 * HS * 64);
@@ -1526,7 +1530,8 @@ __device__ __forceinline__ void link_wrench(const RobotArgs& R, const uint32_t* 
 // the joint rows the last phase reads (the tile's and one on each side); phase 2 gives each
 // wavefront links w+1 and w+5 and leaves their force and moment in LDS; phase 3 (wavefront 0) sums
 // them from the tip to the base into the joint gradients.  Every load of the block is thus issued
-// before the first barrier except the sphere gradients'.
+// before the first barrier except the sphere gradients'.  (Copying a narrow G run into LDS in phase 1
+// as well costs a fourth of the blocks per CU and was slower.)
 constexpr int ADJ_TILE_WORDS = N_FIXED * LINK_VALUES * 64;  // link l (1..8) at slot l - 1
 constexpr int ADJ_Q_ROWS = 64 + 2;                          // joint rows b0 - 1 .. b0 + 64
 

@@ -115,6 +115,38 @@ def test_fp32_dense_with_upstream_and_recompute():
         check_fp32(wl, ref, cost, grad)
 
 
+def _eligible_pairs(robot):
+    link = robot.sphere_link
+    n = link.shape[0]
+    return np.array([(a, b) for a in range(n) for b in range(a + 1, n) if abs(int(link[a]) - int(link[b])) >= 2],
+                    dtype=np.int32)
+
+
+@pytest.mark.parametrize("kind", ["hubs", "all_eligible"])
+def test_self_pair_tables(kind):
+    """Robots whose self-pair lists are far from the benchmark's: three hub spheres paired with every
+    eligible partner (about 50 each) plus 200 random pairs, and every eligible pair (about 1,250).
+    Against the FP32 oracle."""
+    need_gpu()
+    wl = dense_workload(seed=13, n_worlds=1, tpw=4, T=8, n_ls=2)
+    el = _eligible_pairs(wl.robot)
+    if kind == "hubs":
+        rng = np.random.default_rng(2)
+        hub = el[(el[:, 0] == 0) | (el[:, 1] == 59) | (el[:, 0] == 30) | (el[:, 1] == 30)]
+        rest = el[rng.choice(len(el), 200, replace=False)]
+        pairs = np.unique(np.concatenate([hub, rest]), axis=0)
+    else:
+        pairs = el
+    wl = dataclasses.replace(wl, robot=dataclasses.replace(wl.robot, pairs=pairs.astype(np.int32)))
+    ctx = make_context(wl)
+    cost, grad, _, _, _ = run_gpu(ctx, wl)
+    ref = run_oracle(wl, {})
+    assert ref["self_cost"].max() > 0
+    check_fp32(wl, ref, cost, grad)
+    print(f"[self pairs] {kind}: {len(pairs)} pairs")
+    ctx.close()
+
+
 @pytest.mark.parametrize("pname", list(PRECISIONS))
 def test_stage_fk_codes(pname):
     need_gpu()
