@@ -3,11 +3,14 @@ sphere costs, aggregation, adjoint, line-search selection and L-BFGS update) ove
 64 worlds x 64 seeds x 48 timesteps = 196,608 configurations of a synthetic 7-joint arm with 60
 spheres and 300 self pairs among 64 random cuboids per world.  Reports configuration evaluations
 (cost + joint gradient) per second for a variable-precision assignment of the five stored tensors
-and for FP32 on the same GPU, with per-kernel times from HIP events recorded around each launch on
-the stream the kernels run on, the dominant kernel's roofline, and the FP64 oracle's rate on the
-host cores for a bounded sample.
+and for FP32 on the same GPU.  The timed steps run the batch split by worlds over --parts contexts,
+each on a stream of its own (identical results; one partition's kernels fill the GPU while
+another's drain); the same steps are also timed on one stream, and that run gives the per-kernel
+times (HIP events recorded around each launch on the stream the kernels run on) and the dominant
+kernel's roofline.  The FP64 oracle's rate on the host cores for a bounded sample is reported
+beside it.
 
-  python bench.py [--steps K] [--warmup W] [--precision NAME] [--no-cpu-baseline]
+  python bench.py [--steps K] [--warmup W] [--precision NAME] [--parts P] [--no-cpu-baseline]
 """
 from __future__ import annotations
 
@@ -46,6 +49,7 @@ TENSOR_NAMES = ("link_poses", "sphere_pos", "sphere_dist", "sphere_grad", "joint
 BITS = {"f32": 32, "f16": 16, "bf16": 16, "e4m3": 8, "e5m2": 8, "e3m2": 6, "e2m1": 4}
 N_WORLDS, TPW, T, N_LS, N_SPHERES, N_CUBOIDS, N_PAIRS = 64, 64, 48, 1, 60, 64, 300
 HIST_M = 8
+PARTS = 2  # world partitions (contexts on streams of their own) for the timed steps
 # algorithmic FP32 operations of one sphere-cuboid test (FMA = 2): R^T p - R^T c (18),
 # |u| - h (3), max(a, 0) (3), |max(a,0)|^2 (5), min(max_i a_i, 0) (3), key (1), running arg-min (2)
 FLOPS_PER_SPHERE_CUBOID = 35
@@ -383,6 +387,28 @@ def run_variant(torch, ctx, opt_cls, x0, prec, steps, warmup, want_opt=False, re
     ctx.profile_enable(False)
     cost = float(opt.cost.sum())
     return (t1 - t0), prof, cost, (opt if want_opt else None)
+
+
+def run_partitioned(torch, ctx, x0, prec, steps, warmup, parts, recompute=False):
+    """The same iterations with the batch split by worlds over `parts` contexts and streams
+    (PartitionedOptimizer: identical results, the kernels of one partition filling the GPU while
+    another's drain).  Returns (seconds for `steps` timed iterations, total final cost)."""
+    from paper_2310_07854_amd import PartitionedOptimizer
+
+    ctx.set_precision(prec, recompute_poses=recompute)
+    opt = PartitionedOptimizer(ctx, N_WORLDS, TPW, T, n_ls=N_LS, m=HIST_M, parts=parts)
+    opt.init(x0)
+    for _ in range(warmup):
+        opt.step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        opt.step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    cost = float(opt.cost.sum())
+    opt.close()
+    return t1 - t0, cost
 
 
 def _oracle_trajectories(prec_kw, start, count):
@@ -1144,6 +1170,8 @@ def main():
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--precision", default="paper_like", choices=[k for k in PRECISIONS if k != "f32"])
+    ap.add_argument("--parts", type=int, default=PARTS,
+                    help="world partitions, one context and stream each, for the timed steps (1: one stream)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--seeding", action="store_true", help="run the learned-seeder study instead")
     ap.add_argument("--seed-infer", action="store_true", help="time the seeding network's inference instead")
@@ -1236,8 +1264,17 @@ def main():
             if main:
                 culled = culled_work(ctx, opt, precs[name])
                 del opt
+            if args.parts > 1:
+                dtp, costp = run_partitioned(torch, ctx, x0, precs[name], args.steps, args.warmup, args.parts,
+                                             recompute)
+                if not math.isfinite(costp):
+                    raise RuntimeError(f"{name}: non-finite total cost after the partitioned steps")
+            else:
+                dtp = dt
+            results[(name, recompute)]["seconds_parts"] = dtp
             print(f"# {name}{' recompute' if recompute else ''}: {dt / args.steps * 1e3:.3f} ms/step, "
-                  f"{B * args.steps / dt / 1e6:.1f} M evals/s, kernels "
+                  f"{B * args.steps / dt / 1e6:.1f} M evals/s on one stream, "
+                  f"{B * args.steps / dtp / 1e6:.1f} M evals/s on {args.parts}, kernels "
                   + ", ".join(f"{k} {v[0] / max(v[1], 1) * 1e3:.1f}us" for k, v in prof.items() if v[1]),
                   file=sys.stderr, flush=True)
             if not math.isfinite(cost):
@@ -1268,11 +1305,13 @@ def main():
     main_r = results[(args.precision, False)]
     f32_r = results[("f32", False)]
     rc_r = results[(args.precision, True)]
-    dt = main_r["seconds"]
-    dt_rc = rc_r["seconds"]
+    dt = main_r["seconds_parts"]
+    dt_rc = rc_r["seconds_parts"]
     prof_rc = rc_r["prof"]
     value = B * args.steps / dt
-    value_f32 = B * args.steps / f32_r["seconds"]
+    value_f32 = B * args.steps / f32_r["seconds_parts"]
+    value_1 = B * args.steps / main_r["seconds"]
+    value_f32_1 = B * args.steps / f32_r["seconds"]
     prec = precs[args.precision]
     kb = kernel_bytes(prec)
     per_kernel = {}
@@ -1314,10 +1353,12 @@ def main():
 
     variants = {}
     for (name, recompute), r in results.items():
-        v = B * args.steps / r["seconds"]
+        v = B * args.steps / r["seconds_parts"]
+        v1 = B * args.steps / r["seconds"]
         variants[name + ("_recompute" if recompute else "")] = {
-            "value": v, "ms_per_step": r["seconds"] / args.steps * 1e3,
+            "value": v, "ms_per_step": r["seconds_parts"] / args.steps * 1e3,
             "speedup_vs_fp32_pct": (v / value_f32 - 1.0) * 100.0,
+            "single_stream_value": v1, "single_stream_speedup_vs_fp32_pct": (v1 / value_f32_1 - 1.0) * 100.0,
             "formats": {k: list(f) for k, f in precs[name].items()}, "kernels_us": kernels_us(r["prof"])}
     step_bytes = sum(kb[k] for k in kb) * B
     line = {
@@ -1336,7 +1377,11 @@ def main():
         "config": {"workload": "64 worlds x 64 seeds x 48 timesteps = 196,608 configurations per step; 7-joint "
                                "arm, 60 spheres, 300 self pairs, 64 oriented cuboids per world; 1 step scale",
                    "precision": args.precision, "formats": {k: list(v) for k, v in prec.items()},
-                   "recompute_poses": False},
+                   "recompute_poses": False, "partitions": args.parts},
+        # the same steps on one stream; per-kernel times and the roofline come from that run, where
+        # each launch has the GPU to itself
+        "single_stream": {"value": value_1, "ms_per_step": main_r["seconds"] / args.steps * 1e3,
+                          "fp32_value": value_f32_1, "speedup_vs_fp32_pct": (value_1 / value_f32_1 - 1.0) * 100.0},
         "fp32_value": value_f32,
         # the paper's definition: (t_FP32 / t_X - 1) * 100 %
         "speedup_vs_fp32_pct": (value / value_f32 - 1.0) * 100.0,

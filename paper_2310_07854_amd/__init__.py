@@ -17,7 +17,7 @@ def __getattr__(name):
     if name in ("VaprCost", "trajectory_cost"):
         from . import cost
         return getattr(cost, name)
-    if name == "TrajectoryOptimizer":
+    if name in ("TrajectoryOptimizer", "PartitionedOptimizer"):
         from . import optim
-        return optim.TrajectoryOptimizer
+        return getattr(optim, name)
     raise AttributeError(name)

@@ -98,6 +98,11 @@ class Context:
                             "w_goal_rot": 10.0}
         self.precision: Dict[str, Tuple[str, int]] = {t: ("f32", 0) for t in STORED}
         self.recompute_poses = False
+        # what was uploaded, for subset()
+        self._robot = None
+        self._worlds = None
+        self._goals = None
+        self._culling = True
 
     # -- lifetime ----------------------------------------------------------------------------
     def close(self) -> None:
@@ -129,6 +134,7 @@ class Context:
         self._call("vapr_set_robot", 7, _ptr(fixed), int(radius.shape[0]), _ptr(centers), _ptr(radius), _ptr(link),
                    int(pairs.shape[0]), _ptr(pairs) if pairs.size else None, _ptr(lo), _ptr(hi))
         self.n_spheres = int(radius.shape[0])
+        self._robot = robot
 
     def reach(self) -> Tuple[float, float]:
         """(link-pose bound, sphere-centre bound): the largest |value| any configuration stores in
@@ -142,6 +148,7 @@ class Context:
         half = _host(half_ext, np.float32)
         W, K = pose.shape[0], pose.shape[1]
         self._call("vapr_set_worlds", W, K, _ptr(pose) if pose.size else None, _ptr(half) if half.size else None)
+        self._worlds = (pose, half)
 
     def set_precision(self, spec: Optional[Mapping[str, FormatSpec]] = None, recompute_poses: bool = False) -> None:
         spec = spec or {}
@@ -168,13 +175,35 @@ class Context:
         end-effector link (None or n = 0 clears them)."""
         if goals is None:
             self._call("vapr_set_goals", 0, None)
+            self._goals = None
             return
         g = _host(goals, np.float32).reshape(-1, 3, 4)
         self._call("vapr_set_goals", int(g.shape[0]), _ptr(g) if g.size else None)
+        self._goals = g if g.size else None
 
     def set_culling(self, enable: bool) -> None:
         """Exact cuboid culling in the sphere-cost stage (on by default; results are identical)."""
         self._call("vapr_set_culling", 1 if enable else 0)
+        self._culling = bool(enable)
+
+    def subset(self, w0: int, w1: int) -> "Context":
+        """A new context on the same device for worlds w0 .. w1 - 1 of this one: the same robot, cost
+        parameters, precision, culling and (if set) those worlds' goal poses."""
+        if self._robot is None or self._worlds is None:
+            raise ValueError("subset needs the robot and worlds to be set")
+        pose, half = self._worlds
+        if not 0 <= w0 < w1 <= pose.shape[0]:
+            raise ValueError(f"world range {w0}..{w1} outside 0..{pose.shape[0]}")
+        c = Context(self.device)
+        c.set_robot(self._robot)
+        c.set_worlds(pose[w0:w1], half[w0:w1])
+        c.set_cost_params(**self.cost_params)
+        if self._goals is not None:
+            c.set_goals(self._goals[w0:w1])
+        if not self._culling:
+            c.set_culling(False)
+        c.set_precision({t: v for t, v in self.precision.items()}, self.recompute_poses)
+        return c
 
     def culling_grid(self, world: int):
         """The culling grid of one world: (info dict, uint32 mask array [n^3, mask_words]), or

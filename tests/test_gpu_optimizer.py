@@ -155,3 +155,34 @@ def test_graph_replays_match_eager_steps():
         assert torch.equal(eager.cost, graph.cost), it
         assert torch.equal(eager.d, graph.d), it
         assert torch.equal(eager.hist_len, graph.hist_len), it
+
+
+@pytest.mark.parametrize("parts", [2, 3, 4])
+def test_partitioned_optimizer_matches_one_optimizer(parts):
+    """The batch split by worlds over contexts and streams (uneven splits included: 4 worlds in 3
+    parts) gives the single optimiser's iterates, costs and flags bit for bit, with a stored-mode
+    reduced-precision assignment and the swept term off."""
+    need_gpu()
+    from paper_2310_07854_amd import PartitionedOptimizer, TrajectoryOptimizer
+
+    wl = make_workload("batched")
+    prec = {"link_poses": ("f16", -15), "sphere_pos": ("f16", -15), "sphere_dist": ("e4m3", -10),
+            "sphere_grad": ("e4m3", -1), "joint_grad": ("e4m3", 0)}
+    ctx = make_context(wl, prec)
+    T = wl.T
+    x0 = dev(wl.q.reshape(wl.n_traj, wl.n_ls, T, 7)[:, 0], torch.float32)
+    one = TrajectoryOptimizer(ctx, wl.n_worlds, wl.traj_per_world, T, n_ls=wl.n_ls, m=8)
+    split = PartitionedOptimizer(ctx, wl.n_worlds, wl.traj_per_world, T, n_ls=wl.n_ls, m=8, parts=parts)
+    assert len(split.parts) == min(parts, wl.n_worlds)
+    one.init(x0)
+    split.init(x0)
+    for it in range(6):
+        one.step()
+        split.step()
+        if it % 2 == 1:
+            assert torch.equal(split.x, one.x), it
+            assert torch.equal(split.cost, one.cost), it
+            assert torch.equal(split.flags, one.flags), it
+    prof_parts = split.parts
+    assert all(c.precision == ctx.precision for c, _, _ in prof_parts)
+    split.close()
