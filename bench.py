@@ -49,7 +49,7 @@ TENSOR_NAMES = ("link_poses", "sphere_pos", "sphere_dist", "sphere_grad", "joint
 BITS = {"f32": 32, "f16": 16, "bf16": 16, "e4m3": 8, "e5m2": 8, "e3m2": 6, "e2m1": 4}
 N_WORLDS, TPW, T, N_LS, N_SPHERES, N_CUBOIDS, N_PAIRS = 64, 64, 48, 1, 60, 64, 300
 HIST_M = 8
-PARTS = 2  # world partitions (contexts on streams of their own) for the timed steps
+PARTS = 4  # world partitions (contexts on streams of their own) for the timed steps
 # algorithmic FP32 operations of one sphere-cuboid test (FMA = 2): R^T p - R^T c (18),
 # |u| - h (3), max(a, 0) (3), |max(a,0)|^2 (5), min(max_i a_i, 0) (3), key (1), running arg-min (2)
 FLOPS_PER_SPHERE_CUBOID = 35
@@ -409,6 +409,26 @@ def run_partitioned(torch, ctx, x0, prec, steps, warmup, parts, recompute=False)
     cost = float(opt.cost.sum())
     opt.close()
     return t1 - t0, cost
+
+
+def stored_tensor_report(torch, ctx, opt, prec):
+    """After the timed steps of one assignment: per stored tensor the census of its codes (at the
+    format's largest finite magnitude -- saturated --, and Inf/NaN), and the fraction of spheres
+    with a nonzero distance and a nonzero gradient (how dense D and G are on this workload)."""
+    from paper_2310_07854_amd.context import dequantize
+
+    shape = opt.shape
+    census = {}
+    for t in ("link_poses", "sphere_pos", "sphere_dist", "sphere_grad", "joint_grad"):
+        a, b = ctx.census(t, opt.ws, shape)
+        census[t] = {"largest_magnitude": a, "inf_nan": b, "of": shape.B * ctx.tensor_count(t)}
+    act = {}
+    for t in ("sphere_dist", "sphere_grad"):
+        fmt, k = prec.get(t, ("f32", 0)) if not isinstance(prec.get(t, "f32"), str) else (prec[t], 0)
+        n = shape.B * ctx.tensor_count(t)
+        v = dequantize(ctx.ws_export(t, opt.ws, shape), fmt, n, k).view(shape.B, N_SPHERES, -1)
+        act[t] = float((v != 0).any(dim=2).float().mean())
+    return census, act
 
 
 def _oracle_trajectories(prec_kw, start, count):
@@ -1255,23 +1275,24 @@ def main():
     results = {}
     names = ["f32", args.precision] + [k for k in PRECISIONS if k not in ("f32", args.precision)]
     culled = None
+    census = activity = None
     for name in names:
         for recompute in ((False,) if name == "f32" else (False, True)):
             main = name == args.precision and not recompute
-            dt, prof, cost, opt = run_variant(torch, ctx, TrajectoryOptimizer, x0, precs[name], args.steps,
-                                              args.warmup, want_opt=main, recompute=recompute)
-            results[(name, recompute)] = {"seconds": dt, "prof": prof, "cost": cost}
-            if main:
-                culled = culled_work(ctx, opt, precs[name])
-                del opt
             if args.parts > 1:
                 dtp, costp = run_partitioned(torch, ctx, x0, precs[name], args.steps, args.warmup, args.parts,
                                              recompute)
                 if not math.isfinite(costp):
                     raise RuntimeError(f"{name}: non-finite total cost after the partitioned steps")
-            else:
+            dt, prof, cost, opt = run_variant(torch, ctx, TrajectoryOptimizer, x0, precs[name], args.steps,
+                                              args.warmup, want_opt=main, recompute=recompute)
+            if args.parts <= 1:
                 dtp = dt
-            results[(name, recompute)]["seconds_parts"] = dtp
+            results[(name, recompute)] = {"seconds": dt, "prof": prof, "cost": cost, "seconds_parts": dtp}
+            if main:
+                culled = culled_work(ctx, opt, precs[name])
+                census, activity = stored_tensor_report(torch, ctx, opt, precs[name])
+                del opt
             print(f"# {name}{' recompute' if recompute else ''}: {dt / args.steps * 1e3:.3f} ms/step, "
                   f"{B * args.steps / dt / 1e6:.1f} M evals/s on one stream, "
                   f"{B * args.steps / dtp / 1e6:.1f} M evals/s on {args.parts}, kernels "
@@ -1389,6 +1410,10 @@ def main():
         "kernels": per_kernel,
         "fp32_kernels": kernels_us(f32_r["prof"]),
         "roofline": roofline,
+        # codes of the headline's stored tensors after the timed steps: saturated or Inf/NaN counts
+        # (static scales outgrown), and how dense D and G are (the share of spheres with a nonzero value)
+        "census": census,
+        "active_fraction": activity,
         "recompute_value": B * args.steps / dt_rc,
         "recompute_kernels": kernels_us(prof_rc),
         "variants": variants,

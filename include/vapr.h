@@ -229,6 +229,24 @@ int vapr_get_culling_grid(vapr_ctx* ctx, int world, vapr_grid_info* info, uint32
  * header on the stream.  ws_bytes >= 256. */
 int vapr_ws_reset(vapr_ctx* ctx, void* ws, size_t ws_bytes);
 
+/* Debugging aid: vapr_ws_reset, then every byte after the header set to 0xFF on the stream (NaN in
+ * FP32, FP16, BF16, FP8; the largest negative magnitude in FP6/FP4 and the saturating ExMy types).
+ * A forward and backward pass from a poisoned workspace must give results bit-identical to a clean
+ * one: every location a stage reads was written by an earlier stage of the same pass.  ws dev,
+ * 256-byte aligned, ws_bytes a multiple of 4. */
+int vapr_ws_poison(vapr_ctx* ctx, void* ws, size_t ws_bytes);
+
+/* Census of one stored code tensor (VAPR_T_LINK_POSES, _SPHERE_POS, _SPHERE_DIST, _SPHERE_GRAD,
+ * _JOINT_GRAD, _SWEPT_GRAD) of the forward pass ws holds, over its B configurations in canonical
+ * order (padding spheres excluded): counts[0] = codes at the format's largest finite magnitude,
+ * where a saturating format (FP8, FP6, FP4, the non-IEEE ExMy types) puts every value beyond its
+ * range; counts[1] = Inf or NaN codes, where FP32/FP16/BF16 and the IEEE-like ExMy types put them.
+ * It watches the static power-of-two scales of Sec. IV-B: counts that appear or grow during an
+ * optimisation show values outgrowing the scale.  counts host int64[2]; synchronises the stream
+ * (not for graph capture).  VAPR_E_STATE as for vapr_ws_export. */
+int vapr_ws_census(vapr_ctx* ctx, int n_worlds, int traj_per_world, int T, int n_ls, const void* ws,
+                   size_t ws_bytes, int tensor, int64_t* counts);
+
 /* Collision check of a forward pass (the success test of planning, Sec. VI-A: a trajectory is
  * usable when it is collision-free): free_cfg dev [B] int32 receives 1 for a configuration whose
  * every sphere clears every cuboid (stored activation depth d < eta, i.e. clearance > 0), whose

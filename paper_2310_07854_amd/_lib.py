@@ -106,6 +106,8 @@ SIGNATURES = {
     "vapr_quantize": (_I, [_I, _I, _P, _P, _I64, _P]),
     "vapr_dequantize": (_I, [_I, _I, _P, _P, _I64, _P]),
     "vapr_packed_bytes": (_SZ, [_I, _I64]),
+    "vapr_ws_poison": (_I, [_P, _P, _SZ]),
+    "vapr_ws_census": (_I, [_P, _I, _I, _I, _I, _P, _SZ, _I, _P]),
     "vapr_exmy_packed_bytes": (_SZ, [_I, _I, _I64]),
     "vapr_quantize_exmy": (_I, [_I, _I, _I, _P, _P, _I64, _P]),
     "vapr_dequantize_exmy": (_I, [_I, _I, _I, _P, _P, _I64, _P]),
@@ -129,11 +131,14 @@ SIGNATURES = {
 _lib = None
 
 
-def load(path: str = LIB_PATH) -> ctypes.CDLL:
-    """The loaded library; raises if it has not been built."""
+def load(path: str = None) -> ctypes.CDLL:
+    """The loaded library (VAPR_LIB names another build of it, e.g. libvapr_ubsan.so); raises if it
+    has not been built."""
     global _lib
     if _lib is not None:
         return _lib
+    if path is None:
+        path = os.environ.get("VAPR_LIB") or LIB_PATH
     # torch brings its own HIP runtime; loading it first makes this library bind to the same one
     # (two runtimes in one process do not share devices or streams)
     import torch  # noqa: F401

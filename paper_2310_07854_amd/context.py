@@ -234,6 +234,16 @@ class Context:
     def ws_reset(self, ws: torch.Tensor) -> None:
         self._call("vapr_ws_reset", _dev(ws, torch.uint8, "ws"), ws.numel())
 
+    def ws_poison(self, ws: torch.Tensor) -> None:
+        """Fill the workspace (after its header) with 0xFF bytes and forget its forward pass."""
+        self._call("vapr_ws_poison", _dev(ws, torch.uint8, "ws"), ws.numel())
+
+    def census(self, name: str, ws: torch.Tensor, shape: Shape) -> Tuple[int, int]:
+        """(codes at the largest finite magnitude, Inf/NaN codes) of a stored tensor."""
+        out = (ctypes.c_int64 * 2)()
+        self._call("vapr_ws_census", *shape.args(), _dev(ws, torch.uint8, "ws"), ws.numel(), L.TENSOR_IDS[name], out)
+        return int(out[0]), int(out[1])
+
     def sync(self) -> None:
         """Wait for the context's work; raises VaprError (E_STATE) if a backward or optimiser kernel
         met a workspace that no longer held its forward pass."""

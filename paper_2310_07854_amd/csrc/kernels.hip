@@ -2459,6 +2459,71 @@ hipError_t launch_collision_free(hipStream_t s, const RobotArgs& R, const TV& S,
   return hipGetLastError();
 }
 
+// ---- diagnostics: workspace poisoning and code census --------------------------------------------
+
+__global__ __launch_bounds__(256) void k_fill_u32(uint32_t* __restrict__ p, int64_t n, uint32_t v) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// 0: an ordinary value, 1: the format's largest finite magnitude, 2: Inf or NaN
+__device__ __forceinline__ int code_class(const TV& t, uint32_t c) {
+  int bits;
+  uint32_t maxmag;
+  if (t.fmt == PXM) {
+    const int E = t.xe, M = t.xm;
+    bits = 1 + E + M;
+    const bool ieee = E == 8 || (E == 5 && M == 10);
+    const uint32_t mall = M ? (1u << M) - 1u : 0u;
+    maxmag = ieee ? ((((1u << E) - 2u) << M) | mall) : ((1u << (E + M)) - 1u);
+  } else {
+    switch (t.fmt) {
+      case F32: bits = 32, maxmag = Fmt<F32>::MAXMAG; break;
+      case F16: bits = 16, maxmag = Fmt<F16>::MAXMAG; break;
+      case BF16: bits = 16, maxmag = Fmt<BF16>::MAXMAG; break;
+      case E4M3: bits = 8, maxmag = Fmt<E4M3>::MAXMAG; break;
+      case E5M2: bits = 8, maxmag = Fmt<E5M2>::MAXMAG; break;
+      case E3M2: bits = 6, maxmag = Fmt<E3M2>::MAXMAG; break;
+      default: bits = 4, maxmag = Fmt<E2M1>::MAXMAG; break;
+    }
+  }
+  const uint32_t mag = c & (bits >= 32 ? 0x7fffffffu : ((1u << (bits - 1)) - 1u));
+  return mag > maxmag ? 2 : (mag == maxmag ? 1 : 0);
+}
+
+// One thread per element of the B configurations (canonical order, padding spheres excluded); a
+// wavefront adds its counts with one atomic per class.
+__global__ __launch_bounds__(256) void k_code_census(TV t, int tensor, int64_t B, int ecfg,
+                                                     unsigned long long* __restrict__ counts) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  int cls = 0;
+  if (e < B * ecfg) {
+    const int64_t b = e / ecfg;
+    int slot, pos;
+    elem_slot(tensor, (int)(e - b * ecfg), slot, pos);
+    const uint32_t c = t.fmt == PXM ? pxm_code_at(t, tensor, b, slot, pos) : get_code(t, tensor, b, slot, pos);
+    cls = code_class(t, c);
+  }
+  const unsigned long long n1 = __popcll(__ballot(cls == 1)), n2 = __popcll(__ballot(cls == 2));
+  if ((threadIdx.x & 63) == 0) {
+    if (n1) atomicAdd(counts, n1);
+    if (n2) atomicAdd(counts + 1, n2);
+  }
+}
+
+hipError_t launch_fill_u32(hipStream_t s, uint32_t* p, int64_t n, uint32_t v) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_u32, dim3(blocks_for(n, 256)), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_code_census(hipStream_t s, int tensor, const TV& t, int64_t B, int ecfg,
+                              unsigned long long* counts) {
+  if (B * ecfg <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_code_census, dim3(blocks_for(B * ecfg, 256)), dim3(256), 0, s, t, tensor, B, ecfg, counts);
+  return hipGetLastError();
+}
+
 hipError_t launch_ws_stamp(hipStream_t s, const WsStamp& st) {
   hipLaunchKernelGGL(k_ws_stamp, dim3(1), dim3(64), 0, s, st);
   return hipGetLastError();

@@ -113,6 +113,9 @@ hipError_t launch_optimizer(hipStream_t s, const OptArgs& o, const TV& J, const 
                             int mode, const WsCheck& ck);
 // header write of a workspace outside a forward pass (stage-wise imports, resets)
 hipError_t launch_ws_stamp(hipStream_t s, const WsStamp& st);
+hipError_t launch_fill_u32(hipStream_t s, uint32_t* p, int64_t n, uint32_t v);
+hipError_t launch_code_census(hipStream_t s, int tensor, const TV& t, int64_t B, int ecfg,
+                              unsigned long long* counts);
 // device address of the current device's static scratch (the allocation-free entry point's
 // workspace) and its size; call once per device with that device current
 hipError_t scratch_address(void** ptr, size_t* bytes);

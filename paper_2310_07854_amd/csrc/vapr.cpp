@@ -113,6 +113,7 @@ struct vapr_ctx {
   CostArgs params{0.02f, 100.f, 100.f, 10.f, 1.f, 0, 100.f, 100.f, 10.f};
   std::unordered_map<const void*, WsRecord> ws;
   std::string err;
+  unsigned long long* d_census = nullptr;  // two counters of vapr_ws_census (allocated at first use)
   // profiling
   bool prof = false;
   std::vector<ProfEvent> prof_live;
@@ -786,6 +787,7 @@ int vapr_destroy(vapr_ctx* ctx) {
   (void)hipFree(ctx->d_goal);
   (void)hipFree(ctx->d_grid);
   (void)hipFree(ctx->d_status);
+  (void)hipFree(ctx->d_census);
   for (auto& pe : ctx->prof_live) {
     (void)hipEventDestroy(pe.start);
     (void)hipEventDestroy(pe.stop);
@@ -1379,6 +1381,55 @@ int vapr_ws_reset(vapr_ctx* ctx, void* ws, size_t ws_bytes) {
   st.hdr = static_cast<uint64_t*>(ws);
   const hipError_t e = launch_ws_stamp(ctx->stream, st);
   return e == hipSuccess ? VAPR_OK : hip_fail(ctx, e, "k_ws_stamp launch");
+}
+
+int vapr_ws_poison(vapr_ctx* ctx, void* ws, size_t ws_bytes) {
+  if (!ctx) return fail(nullptr, VAPR_E_INVALID, "null context");
+  if (!ws) return fail(ctx, VAPR_E_INVALID, "null pointer");
+  if (ws_bytes < WS_HEADER_BYTES || ws_bytes % 4) return fail(ctx, VAPR_E_INVALID, "workspace size");
+  if (reinterpret_cast<uintptr_t>(ws) & 255) return fail(ctx, VAPR_E_INVALID, "workspace not 256-byte aligned");
+  int st = vapr_ws_reset(ctx, ws, ws_bytes);
+  if (st) return st;
+  uint32_t* body = reinterpret_cast<uint32_t*>(static_cast<char*>(ws) + WS_HEADER_BYTES);
+  const hipError_t e = launch_fill_u32(ctx->stream, body, (int64_t)((ws_bytes - WS_HEADER_BYTES) / 4), 0xFFFFFFFFu);
+  return e == hipSuccess ? VAPR_OK : hip_fail(ctx, e, "k_fill_u32 launch");
+}
+
+int vapr_ws_census(vapr_ctx* ctx, int n_worlds, int tpw, int T, int n_ls, const void* ws, size_t ws_bytes,
+                   int tensor, int64_t* counts) {
+  int64_t B;
+  int st = check_shape(ctx, n_worlds, tpw, T, n_ls, &B);
+  if (st) return st;
+  if (!ws || !counts) return fail(ctx, VAPR_E_INVALID, "null pointer");
+  if (tensor < VAPR_T_LINK_POSES || tensor > VAPR_T_SWEPT_GRAD || tensor == VAPR_T_SELF_COST ||
+      tensor == VAPR_T_BOUND_COST)
+    return fail(ctx, VAPR_E_INVALID, "census covers the stored code tensors only");
+  if (tensor == VAPR_T_LINK_POSES && ctx->prec.recompute)
+    return fail(ctx, VAPR_E_INVALID, "no link-pose tensor in recompute mode");
+  if (tensor == VAPR_T_SWEPT_GRAD && !ctx->prec.sweep)
+    return fail(ctx, VAPR_E_INVALID, "no swept tensors: the swept term is off (swept_steps = 0)");
+  const Layout L = make_layout(B, ctx->n_s, ctx->prec);
+  if (ws_bytes < L.bytes) return fail(ctx, VAPR_E_INVALID, "workspace too small");
+  const char* why = nullptr;
+  const WsRecord* r = current_record(ctx, ws, &why);
+  if (!r) return fail(ctx, VAPR_E_STATE, why);
+  if (r->B != B || r->T != T || r->n_ls != n_ls)
+    return fail(ctx, VAPR_E_STATE, "workspace holds a forward pass of another shape");
+  if (!ctx->d_census && (st = upload(ctx, &ctx->d_census, static_cast<const unsigned long long*>(nullptr), 2)))
+    return st;
+  const unsigned long long zero[2] = {0ull, 0ull};
+  VAPR_HIP(ctx, hipMemcpyAsync(ctx->d_census, zero, sizeof zero, hipMemcpyHostToDevice, ctx->stream));
+  const int t = tensor == VAPR_T_SWEPT_GRAD ? T_X : tensor;
+  const TV tv = tensor_view(const_cast<void*>(ws), L, ctx->prec, t);
+  const hipError_t e = launch_code_census(ctx->stream, t == T_X ? T_G : t, tv, B, tensor_count(ctx, tensor),
+                                          ctx->d_census);
+  if (e != hipSuccess) return hip_fail(ctx, e, "k_code_census launch");
+  unsigned long long got[2];
+  VAPR_HIP(ctx, hipMemcpyAsync(got, ctx->d_census, sizeof got, hipMemcpyDeviceToHost, ctx->stream));
+  VAPR_HIP(ctx, hipStreamSynchronize(ctx->stream));
+  counts[0] = (int64_t)got[0];
+  counts[1] = (int64_t)got[1];
+  return VAPR_OK;
 }
 
 int vapr_collision_free(vapr_ctx* ctx, int n_worlds, int tpw, int T, int n_ls, const void* ws, size_t ws_bytes,

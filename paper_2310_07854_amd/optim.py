@@ -95,15 +95,51 @@ def split_worlds(n_worlds: int, parts: int):
     return [(p * n_worlds // parts, (p + 1) * n_worlds // parts) for p in range(parts)]
 
 
+def streams_run_concurrently(streams, spin_cycles: int = 20_000_000) -> bool:
+    """True when work queued on each stream runs while every other one is busy.  Streams that the
+    runtime put on one hardware queue execute one after another, and partitions on them would
+    lose what partitioning is for; this is checked by keeping one stream busy with a bounded spin
+    kernel and seeing an event on each other stream complete before it."""
+    for i, busy in enumerate(streams):
+        done = torch.cuda.Event()
+        with torch.cuda.stream(busy):
+            torch.cuda._sleep(spin_cycles)
+            done.record(busy)
+        ok = True
+        for j, s in enumerate(streams):
+            if j == i:
+                continue
+            ev = torch.cuda.Event()
+            ev.record(s)
+            ev.synchronize()
+            if done.query():  # the busy stream finished first: s waited behind it
+                ok = False
+        done.synchronize()
+        if not ok:
+            return False
+    return True
+
+
+def concurrent_streams(n: int, device: int = 0, attempts: int = 16):
+    """n streams that run concurrently (see streams_run_concurrently), taking fresh ones from
+    torch's pool until a set does; the last set drawn if none does within `attempts`."""
+    streams = []
+    for _ in range(attempts):
+        streams = [torch.cuda.Stream(device=device) for _ in range(n)]
+        if n < 2 or streams_run_concurrently(streams):
+            break
+    return streams
+
+
 class PartitionedOptimizer:
     """The optimiser over a batch split by worlds into partitions, each with its own context and
     HIP stream.  Worlds are independent problems (every kernel works per configuration, per
     trajectory or per world), so the results are those of one TrajectoryOptimizer over the whole
     batch, bit for bit.  What changes is scheduling: with one stream, each of an iteration's five
     kernels drains before the next starts and the GPU idles in every drain; with a few streams
-    running free, one partition's kernels fill the CUs that another's are leaving.  Two partitions
-    gave a steady 3-8% on the 196,608-configuration batch; four gave about 6% in most runs but fell
-    14% behind one stream in about a third of them, when the partitions ran in step.
+    running free, one partition's kernels fill the CUs that another's are leaving.  The streams
+    are checked to run concurrently: two streams the runtime puts on one hardware queue run one
+    after the other, which is slower than one stream.
 
     `step` queues each partition's iteration on its own stream and returns; `join` makes the
     caller's current stream wait for all of them (the properties below join first)."""
@@ -114,9 +150,9 @@ class PartitionedOptimizer:
         self.traj_per_world = traj_per_world
         self.shape = Shape(n_worlds, traj_per_world, T, n_ls)
         self.parts = []
-        for w0, w1 in self.ranges:
+        streams = concurrent_streams(len(self.ranges), vctx.device)
+        for (w0, w1), s in zip(self.ranges, streams):
             c = vctx.subset(w0, w1)
-            s = torch.cuda.Stream(device=vctx.device)
             with torch.cuda.stream(s):
                 o = TrajectoryOptimizer(c, w1 - w0, traj_per_world, T, n_ls=n_ls, m=m, max_step=max_step,
                                         pin_ends=pin_ends)

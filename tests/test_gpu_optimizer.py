@@ -186,3 +186,15 @@ def test_partitioned_optimizer_matches_one_optimizer(parts):
     prof_parts = split.parts
     assert all(c.precision == ctx.precision for c, _, _ in prof_parts)
     split.close()
+
+
+def test_stream_concurrency_probe():
+    """The probe behind PartitionedOptimizer's streams: a stream is not concurrent with itself, and
+    the streams concurrent_streams returns are concurrent."""
+    need_gpu()
+    from paper_2310_07854_amd.optim import concurrent_streams, streams_run_concurrently
+
+    s = torch.cuda.Stream()
+    assert not streams_run_concurrently([s, s])
+    got = concurrent_streams(3)
+    assert len(got) == 3 and streams_run_concurrently(got)
