@@ -689,9 +689,15 @@ def seeding_study(args):
             sl = slice(c0, min(c0 + 4096, args.seed_problems))
             ctx.set_worlds(p["pose"][sl], p["half"][sl])
             st, gl = d(p["start"][sl]), d(p["goal"][sl])
-            x0 = d(make_seed_inits(p["start"][sl], p["goal"][sl], S_TRAIN, T, "linear", split=1000 + c0))
+            if args.seed_train_inits == "linear":
+                x0 = d(make_seed_inits(p["start"][sl], p["goal"][sl], S_TRAIN, T, "linear", split=1000 + c0))
+            else:
+                x0 = torch.cat([d(make_seed_inits(p["start"][sl], p["goal"][sl], S_TRAIN // 2, T, "linear",
+                                                  split=1000 + c0)),
+                                d(make_seed_inits(p["start"][sl], p["goal"][sl], S_TRAIN // 2, T, "random",
+                                                  split=1000 + c0))], dim=1).contiguous()
             sol = SP.solve(ctx, x0, iters=args.seed_solve_iters, check_every=args.seed_solve_iters)
-            tgt, valid = SP.select_targets(sol, st, gl)
+            tgt, valid = SP.select_targets(sol, st, gl, diverse=args.seed_targets == "diverse")
             occ = SG.occupancy(d(p["pose"][sl]), d(p["half"][sl]))
             chunks.append({"start": st, "goal": gl, "occ": occ, "targets": tgt, "valid": valid})
             log(f"environment {family}: solved {sl.stop} of {args.seed_problems}")
@@ -777,7 +783,8 @@ def seeding_study(args):
             "config": {"workload": f"7-joint arm, 60 spheres, no self pairs; {args.seed_envs} environments of {K} "
                                    f"cuboids (centres jittered 5 cm per problem); T = {T}; "
                                    f"{args.seed_problems} training problems per environment solved from "
-                                   f"{S_TRAIN} linear seeds x {args.seed_solve_iters} iterations; "
+                                   f"{S_TRAIN} {args.seed_train_inits} seeds x {args.seed_solve_iters} iterations, "
+                                   f"{args.seed_targets} targets; "
                                    f"{args.seed_eval} held-out problems per environment",
                        "train_steps": args.seed_train_steps, "batch": 256, "lr": 1e-3},
             "curves": curves, "common_rate": rate, "iterations_to_common_rate": need,
@@ -1209,6 +1216,10 @@ def main():
     ap.add_argument("--seed-train-steps", type=int, default=8000)
     ap.add_argument("--seed-eval", type=int, default=1024)
     ap.add_argument("--seed-eval-iters", type=int, default=30)
+    ap.add_argument("--seed-targets", choices=["lowest", "diverse"], default="lowest",
+                    help="training targets: the 8 lowest-cost solutions, or 8 spread-out ones")
+    ap.add_argument("--seed-train-inits", choices=["linear", "mixed"], default="linear",
+                    help="initial trajectories of the training solves: linear, or half linear half random")
     ap.add_argument("--only", choices=list(PRECISIONS), default=None,
                     help="run one assignment's optimisation loop and nothing else (for profiler runs)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",

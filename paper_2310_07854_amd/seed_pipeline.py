@@ -69,15 +69,39 @@ def solve(ctx: Context, x0: torch.Tensor, iters: int, n_ls: int = 4, check_every
     return {"x": x, "cost": opt.cost.view(W, S).clone(), "free": trajectories_free(ctx, x), "first_free": first}
 
 
-def select_targets(sol: Dict[str, torch.Tensor], start: torch.Tensor, goal: torch.Tensor
+def select_targets(sol: Dict[str, torch.Tensor], start: torch.Tensor, goal: torch.Tensor, diverse: bool = False
                    ) -> Tuple[torch.Tensor, torch.Tensor]:
-    """targets [W, 8, T, 7] (deviations from the straight line) and valid [W, 8] (float 0/1)."""
+    """targets [W, 8, T, 7] (deviations from the straight line) and valid [W, 8] (float 0/1).
+    diverse=False: the 8 lowest-cost collision-free solutions.  diverse=True: the lowest-cost one,
+    then seven more picked one at a time as the collision-free solution farthest (L2 over the whole
+    deviation) from those already picked, so that the network's slots learn different routes
+    rather than near-copies of the cheapest one."""
     x, cost, free = sol["x"], sol["cost"], sol["free"]
     W, S, T, _ = x.shape
     masked = torch.where(free, cost, torch.full_like(cost, float("inf")))
-    order = torch.argsort(masked, dim=1, stable=True)[:, :N_SEEDS]
-    ok = torch.isfinite(torch.gather(masked, 1, order))
     dev = deviations(x.contiguous(), start.contiguous(), goal.contiguous())
+    if diverse:
+        rows = torch.arange(W, device=x.device)
+        flat = dev.reshape(W, S, T * 7)
+        dist = torch.cdist(flat, flat)                                  # [W, S, S]
+        first = torch.argmin(masked, dim=1)
+        order = [first]
+        ok = [torch.isfinite(masked[rows, first])]
+        avail = free.clone()
+        avail[rows, first] = False
+        near = dist[rows, first]                                        # distance to the picked set
+        for _ in range(1, N_SEEDS):
+            score = torch.where(avail, near, torch.full_like(near, -1.0))
+            nxt = torch.argmax(score, dim=1)
+            ok.append(score[rows, nxt] >= 0)
+            order.append(nxt)
+            avail[rows, nxt] = False
+            near = torch.minimum(near, dist[rows, nxt])
+        order = torch.stack(order, dim=1)
+        ok = torch.stack(ok, dim=1)
+    else:
+        order = torch.argsort(masked, dim=1, stable=True)[:, :N_SEEDS]
+        ok = torch.isfinite(torch.gather(masked, 1, order))
     idx = order.view(W, N_SEEDS, 1, 1).expand(W, N_SEEDS, T, 7)
     picked = torch.gather(dev, 1, idx)
     return torch.where(ok.view(W, N_SEEDS, 1, 1), picked, torch.zeros_like(picked)), ok.float()

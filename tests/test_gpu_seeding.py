@@ -391,3 +391,50 @@ def test_training_reduces_the_loss():
     L, _, _ = SD.loss(y.cpu().numpy().astype(np.float64), tgt, valid)
     loss, _, _ = net.loss(y, tt, vv, nv)
     assert abs(L - float(loss.item())) <= 1e-5 * L
+
+
+@pytest.mark.parametrize("diverse", [False, True])
+def test_select_targets(diverse):
+    """Training targets of the seeder: the lowest-cost collision-free solution first; then either the
+    next-cheapest ones or, one at a time, the collision-free solution farthest from those picked
+    (brute force over the same distances); problems with fewer than 8 collision-free solutions mark
+    the rest invalid."""
+    need_gpu()
+    from paper_2310_07854_amd import seed_pipeline as SP
+    from paper_2310_07854_amd.seeding import N_SEEDS
+
+    rng = np.random.default_rng(3)
+    W, S, T = 3, 12, 32
+    start = rng.uniform(-1, 1, size=(W, 7)).astype(np.float32)
+    goal = rng.uniform(-1, 1, size=(W, 7)).astype(np.float32)
+    tau = np.linspace(0, 1, T)[None, None, :, None]
+    bend = rng.uniform(-1, 1, size=(W, S, 1, 7))
+    x = (start[:, None, None] + (goal - start)[:, None, None] * tau + np.sin(np.pi * tau) * bend).astype(np.float32)
+    cost = rng.uniform(1, 2, size=(W, S))
+    free = rng.random((W, S)) < 0.8
+    free[2, :] = False
+    free[2, :5] = True                    # only 5 collision-free solutions
+    d = lambda a, dt=torch.float32: torch.tensor(a, dtype=dt, device="cuda:0")
+    sol = {"x": d(x), "cost": d(cost, torch.float64), "free": d(free, torch.bool)}
+    tgt, valid = SP.select_targets(sol, d(start), d(goal), diverse=diverse)
+    tgt, valid = tgt.cpu().numpy(), valid.cpu().numpy()
+    dev = x - (start[:, None, None] + (goal - start)[:, None, None] * tau)
+    for w in range(W):
+        ids = np.flatnonzero(free[w])
+        n = min(N_SEEDS, len(ids))
+        assert valid[w].tolist() == [1.0] * n + [0.0] * (N_SEEDS - n)
+        first = ids[np.argmin(cost[w, ids])]
+        picked = [first]
+        if diverse:
+            flat = dev[w].reshape(S, -1).astype(np.float64)
+            near = np.linalg.norm(flat - flat[first], axis=1)
+            for _ in range(1, n):
+                cand = [i for i in ids if i not in picked]
+                nxt = max(cand, key=lambda i: (near[i], -i))
+                picked.append(nxt)
+                near = np.minimum(near, np.linalg.norm(flat - flat[nxt], axis=1))
+        else:
+            picked = list(ids[np.argsort(cost[w, ids], kind="stable")][:n])
+        for k, i in enumerate(picked):
+            np.testing.assert_allclose(tgt[w, k], dev[w, i], atol=2e-6)
+        assert np.all(tgt[w, n:] == 0)
