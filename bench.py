@@ -69,12 +69,50 @@ def tensor_bytes(prec):
     return {k: v * BITS[fmt_of(prec, k)] / 8.0 for k, v in vals.items()}
 
 
-def kernel_bytes(prec, recompute=False):
-    """Algorithmic HBM bytes per configuration of each kernel (stored tensors, q, FP32 scalars)."""
+def optimizer_traj_bytes(jg_bytes, n, stats=None):
+    """Algorithmic HBM bytes of one trajectory's optimiser update (mode 1, n variables, jg_bytes per
+    stored joint-gradient element): x, g, d read and written; the selected candidate's gradient
+    read when a candidate is accepted; the new (s, y) pair and its rho written when it is kept; the
+    history pairs the two-loop recursion uses read (each 2 n FP32 values and an FP64 rho); n_ls
+    candidates written; FP64 costs and the int32 state words.  `stats` holds the per-trajectory means
+    over iterations (`accepted`, `pairs_written`, `pairs_read`); without it every candidate is taken
+    as accepted with a full history of HIST_M pairs."""
+    st = stats or {"accepted": 1.0, "pairs_written": 1.0, "pairs_read": float(HIST_M)}
+    pair = 2 * n * 4 + 8
+    return (3 * n * 4 * 2 + st["accepted"] * (n * jg_bytes + 8) + st["pairs_written"] * pair
+            + st["pairs_read"] * pair + N_LS * n * 4 + N_LS * 8 + 8 + 8 + 16)
+
+
+def optimizer_stats_add(torch, opt, prev_len, sums):
+    """Adds, on the GPU, what one optimiser update touched per trajectory to `sums` (a float64
+    tensor of four running totals: iterations, accepted candidates, kept (s, y) pairs, history pairs
+    read by the two-loop recursion -- the history length after the update, or before the reset when
+    the new direction was not a descent direction); `prev_len` is the history length before it."""
+    a, f, ln = opt.accepted, opt.flags, opt.hist_len
+    ok = a >= 0
+    kept = ok & ((f & 1) != 0)
+    reset = ok & ((f & 2) != 0)
+    r = torch.where(reset, torch.clamp(prev_len + kept.to(prev_len.dtype), max=opt.m), ln)
+    r = torch.where(ok, r, torch.zeros_like(r))
+    n = float(ok.numel())
+    sums += torch.stack([torch.ones((), device=ok.device, dtype=torch.float64), ok.double().sum() / n,
+                         kept.double().sum() / n, r.double().sum() / n])
+    return sums
+
+
+def optimizer_stats(sums):
+    it, acc, kept, reads = (float(v) for v in sums.cpu())
+    k = max(it, 1.0)
+    return {"accepted": acc / k, "pairs_written": kept / k, "pairs_read": reads / k, "iterations": int(it)}
+
+
+def kernel_bytes(prec, recompute=False, opt_stats=None):
+    """Algorithmic HBM bytes per configuration of each kernel (stored tensors, q, FP32 scalars); the
+    optimiser's from the measured update statistics when given."""
     b = tensor_bytes(prec)
     L = 0.0 if recompute else b["link_poses"]
     n = T * 7
-    k5_per_traj = (3 * n * 4) * 2 + 2 * HIST_M * n * 4 + 2 * n * 4 + N_LS * n * 4 + n * b["joint_grad"] / 7 * 1 + 64
+    k5_per_traj = optimizer_traj_bytes(b["joint_grad"] / 7, n, opt_stats)
     return {
         "fk": 28 + L + b["sphere_pos"] + 4,
         "sphere_cost": b["sphere_pos"] + b["sphere_dist"] + b["sphere_grad"] + 4,
@@ -380,13 +418,19 @@ def run_variant(torch, ctx, opt_cls, x0, prec, steps, warmup, want_opt=False, re
         opt.step()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    # the per-kernel window; the optimiser's update statistics are gathered over the same
+    # iterations by small torch kernels between them (outside the events around each launch)
+    sums = torch.zeros(4, dtype=torch.float64, device=x0.device)
     ctx.profile_enable(True)
     for _ in range(steps):
+        prev = opt.hist_len.clone()
         opt.step()
+        optimizer_stats_add(torch, opt, prev, sums)
     prof = ctx.profile_read()
     ctx.profile_enable(False)
     cost = float(opt.cost.sum())
-    return (t1 - t0), prof, cost, (opt if want_opt else None)
+    prof_stats = optimizer_stats(sums)
+    return (t1 - t0), prof, cost, (opt if want_opt else None), prof_stats
 
 
 def run_partitioned(torch, ctx, x0, prec, steps, warmup, parts, recompute=False):
@@ -895,7 +939,7 @@ def swept_bench(args):
         f = dict(PRECISIONS[name])
         f["swept_grad"] = f.get("sphere_grad", "f32")
         prec = with_scales(f, amax, ctx.reach())
-        dt, prof, _, opt = run_variant(torch, ctx, TrajectoryOptimizer, x0, prec, args.steps, args.warmup,
+        dt, prof, _, opt, _ = run_variant(torch, ctx, TrajectoryOptimizer, x0, prec, args.steps, args.warmup,
                                        want_opt=name == "paper_like")
         if opt is not None:
             work = swept_culled_work(ctx, opt, prec, k)
@@ -1276,10 +1320,14 @@ def main():
     amax = calibrate_scales(torch, ctx, x0)
     precs = {name: with_scales(f, amax, ctx.reach()) for name, f in PRECISIONS.items()}
     if args.only:
-        dt, prof, _, _ = run_variant(torch, ctx, TrajectoryOptimizer, x0, precs[args.only], args.steps, args.warmup)
+        dt, prof, _, _, st = run_variant(torch, ctx, TrajectoryOptimizer, x0, precs[args.only], args.steps,
+                                         args.warmup)
         print(json.dumps({"only": args.only, "ms_per_step": dt / args.steps * 1e3,
                           "config": {"formats": {k: list(v) for k, v in precs[args.only].items()}},
-                          "kernels_us": {k: v[0] / max(v[1], 1) * 1e3 for k, v in prof.items() if v[1]}}))
+                          "kernels_us": {k: v[0] / max(v[1], 1) * 1e3 for k, v in prof.items() if v[1]},
+                          "optimizer_stats": st,
+                          "optimizer_bytes_per_launch": kernel_bytes(precs[args.only], opt_stats=st)["optimizer"]
+                          * N_WORLDS * TPW * T * N_LS}))
         ctx.close()
         return
     # every named assignment, stored poses and recomputed in the backward pass; FP32 only stored
@@ -1287,6 +1335,7 @@ def main():
     names = ["f32", args.precision] + [k for k in PRECISIONS if k not in ("f32", args.precision)]
     culled = None
     census = activity = None
+    opt_stats = {}
     for name in names:
         for recompute in ((False,) if name == "f32" else (False, True)):
             main = name == args.precision and not recompute
@@ -1295,8 +1344,9 @@ def main():
                                              recompute)
                 if not math.isfinite(costp):
                     raise RuntimeError(f"{name}: non-finite total cost after the partitioned steps")
-            dt, prof, cost, opt = run_variant(torch, ctx, TrajectoryOptimizer, x0, precs[name], args.steps,
-                                              args.warmup, want_opt=main, recompute=recompute)
+            dt, prof, cost, opt, st = run_variant(torch, ctx, TrajectoryOptimizer, x0, precs[name], args.steps,
+                                                  args.warmup, want_opt=main, recompute=recompute)
+            opt_stats[name + ("_recompute" if recompute else "")] = st
             if args.parts <= 1:
                 dtp = dt
             results[(name, recompute)] = {"seconds": dt, "prof": prof, "cost": cost, "seconds_parts": dtp}
@@ -1307,7 +1357,9 @@ def main():
             print(f"# {name}{' recompute' if recompute else ''}: {dt / args.steps * 1e3:.3f} ms/step, "
                   f"{B * args.steps / dt / 1e6:.1f} M evals/s on one stream, "
                   f"{B * args.steps / dtp / 1e6:.1f} M evals/s on {args.parts}, kernels "
-                  + ", ".join(f"{k} {v[0] / max(v[1], 1) * 1e3:.1f}us" for k, v in prof.items() if v[1]),
+                  + ", ".join(f"{k} {v[0] / max(v[1], 1) * 1e3:.1f}us" for k, v in prof.items() if v[1])
+                  + "; optimiser per trajectory and iteration: "
+                  + ", ".join(f"{k} {v:.3f}" for k, v in st.items() if k != "iterations"),
                   file=sys.stderr, flush=True)
             if not math.isfinite(cost):
                 raise RuntimeError(f"{name}: non-finite total cost after the timed steps")
@@ -1345,7 +1397,7 @@ def main():
     value_1 = B * args.steps / main_r["seconds"]
     value_f32_1 = B * args.steps / f32_r["seconds"]
     prec = precs[args.precision]
-    kb = kernel_bytes(prec)
+    kb = kernel_bytes(prec, opt_stats=opt_stats.get(args.precision))
     per_kernel = {}
     for k, (ms, n) in main_r["prof"].items():
         if n == 0:
@@ -1425,6 +1477,9 @@ def main():
         # (static scales outgrown), and how dense D and G are (the share of spheres with a nonzero value)
         "census": census,
         "active_fraction": activity,
+        # per trajectory and iteration after the timed steps: accepted candidates, kept (s, y) pairs
+        # and history pairs read by the two-loop recursion (the optimiser's algorithmic bytes use them)
+        "optimizer_stats": opt_stats,
         "recompute_value": B * args.steps / dt_rc,
         "recompute_kernels": kernels_us(prof_rc),
         "variants": variants,
