@@ -1482,66 +1482,128 @@ __global__ __launch_bounds__(256) void k_reduce(TV D, const float* __restrict__ 
 
 // ---- K4: reverse accumulation -------------------------------------------------------------------
 
-// Force and moment (about the world origin) of the sphere gradients on link l: spheres of the link
-// are visited in increasing index over the groups that hold them, with G decoded a group at a time.
+// Sphere gradients of group g for this lane (the swept gradient, stored in a tensor of its own,
+// added when present).
 template <int FG, bool HAS_X>
-__device__ __forceinline__ void link_wrench(const RobotArgs& R, const uint32_t* gbase, const TV& G, const TV& X,
-                                            const uint32_t* xbase, int l, const float (&T)[LINK_VALUES],
-                                            float (&f)[3], float (&m)[3]) {
-  const cptr<int> lg = as_const(R.link_groups) + 2 * l;
-  const int g_lo = lg[0], g_hi = lg[1];
-  for (int g = g_lo; g < g_hi; ++g) {
-    float gx[SPH_GROUP], gy[SPH_GROUP], gz[SPH_GROUP];
-    load_group_at<FG, SPH_GROUP>(G, gbase, g * 3 + 0, gx);
-    load_group_at<FG, SPH_GROUP>(G, gbase, g * 3 + 1, gy);
-    load_group_at<FG, SPH_GROUP>(G, gbase, g * 3 + 2, gz);
-    if constexpr (HAS_X) {
-      // the swept gradient, stored in a tensor of its own, adds to the sphere gradient
-      float vx[SPH_GROUP], vy[SPH_GROUP], vz[SPH_GROUP];
-      load_group_fmt<SPH_GROUP>(X, xbase, g * 3 + 0, vx);
-      load_group_fmt<SPH_GROUP>(X, xbase, g * 3 + 1, vy);
-      load_group_fmt<SPH_GROUP>(X, xbase, g * 3 + 2, vz);
-#pragma unroll
-      for (int i = 0; i < SPH_GROUP; ++i) {
-        gx[i] += vx[i];
-        gy[i] += vy[i];
-        gz[i] += vz[i];
-      }
-    }
+__device__ __forceinline__ void load_sphere_grads(const TV& G, const uint32_t* gbase, const TV& X,
+                                                  const uint32_t* xbase, int g, float (&gx)[SPH_GROUP],
+                                                  float (&gy)[SPH_GROUP], float (&gz)[SPH_GROUP]) {
+  load_group_at<FG, SPH_GROUP>(G, gbase, g * 3 + 0, gx);
+  load_group_at<FG, SPH_GROUP>(G, gbase, g * 3 + 1, gy);
+  load_group_at<FG, SPH_GROUP>(G, gbase, g * 3 + 2, gz);
+  if constexpr (HAS_X) {
+    float vx[SPH_GROUP], vy[SPH_GROUP], vz[SPH_GROUP];
+    load_group_fmt<SPH_GROUP>(X, xbase, g * 3 + 0, vx);
+    load_group_fmt<SPH_GROUP>(X, xbase, g * 3 + 1, vy);
+    load_group_fmt<SPH_GROUP>(X, xbase, g * 3 + 2, vz);
 #pragma unroll
     for (int i = 0; i < SPH_GROUP; ++i) {
-      const int s = g * SPH_GROUP + i;
-      if (as_const(R.link)[s] != l) continue;
-      const float4 c = sphere_of(R.sph, s);
-      float x, y, z;
-      xform(T, c.x, c.y, c.z, x, y, z);
-      f[0] += gx[i];
-      f[1] += gy[i];
-      f[2] += gz[i];
-      m[0] = fmaf(y, gz[i], fmaf(-z, gy[i], m[0]));
-      m[1] = fmaf(z, gx[i], fmaf(-x, gz[i], m[1]));
-      m[2] = fmaf(x, gy[i], fmaf(-y, gx[i], m[2]));
+      gx[i] += vx[i];
+      gy[i] += vy[i];
+      gz[i] += vz[i];
     }
   }
 }
 
-// One block of four wavefronts per 64-configuration tile.  Phase 1 puts the poses of links 1..8 in
-// LDS (decoded from L by wavefronts 0-1, or recomputed by wavefront 0) while wavefronts 2-3 stage
-// the joint rows the last phase reads (the tile's and one on each side); phase 2 gives each
-// wavefront links w+1 and w+5 and leaves their force and moment in LDS; phase 3 (wavefront 0) sums
-// them from the tip to the base into the joint gradients.  Every load of the block is thus issued
-// before the first barrier except the sphere gradients'.  (Copying a narrow G run into LDS in phase 1
-// as well costs a fourth of the blocks per CU and was slower.)
+// Adds the spheres of group g that sit on link l to f = sum g_s and C = sum c_s g_s^T (C[3 m + k]
+// = sum c_m g_k, c_s the sphere centre in the link frame), in increasing sphere index.  Neither sum
+// needs the link's pose: with x_s = R c_s + o, the moment about the world origin is
+// sum x_s x g_s = vee(R C) + o x f (link_moment).
+__device__ __forceinline__ void group_link_sums(const RobotArgs& R, int g, int l, const float (&gx)[SPH_GROUP],
+                                                const float (&gy)[SPH_GROUP], const float (&gz)[SPH_GROUP],
+                                                float (&f)[3], float (&C)[9]) {
+#pragma unroll
+  for (int i = 0; i < SPH_GROUP; ++i) {
+    const int s = g * SPH_GROUP + i;
+    if (as_const(R.link)[s] != l) continue;
+    const float4 c = sphere_of(R.sph, s);
+    const float cv[3] = {c.x, c.y, c.z}, gv[3] = {gx[i], gy[i], gz[i]};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) f[k] += gv[k];
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) C[m * 3 + k] = fmaf(cv[m], gv[k], C[m * 3 + k]);
+    }
+  }
+}
+
+// m = vee(R C) + o x f for the pose T = [R | o]: with P = R C, vee(P) = (P_yz - P_zy, P_zx - P_xz,
+// P_xy - P_yx); then both scaled by s (a power of two, so the scaling is exact)
+__device__ __forceinline__ void link_moment(const float (&T)[LINK_VALUES], const float (&C)[9], float s,
+                                            float (&f)[3], float (&m)[3]) {
+  auto P = [&](int j, int k) {
+    return fmaf(T[j * 4 + 0], C[0 * 3 + k], fmaf(T[j * 4 + 1], C[1 * 3 + k], T[j * 4 + 2] * C[2 * 3 + k]));
+  };
+  const float ox = T[3], oy = T[7], oz = T[11];
+  m[0] = (P(1, 2) - P(2, 1)) + fmaf(oy, f[2], -oz * f[1]);
+  m[1] = (P(2, 0) - P(0, 2)) + fmaf(oz, f[0], -ox * f[2]);
+  m[2] = (P(0, 1) - P(1, 0)) + fmaf(ox, f[1], -oy * f[0]);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    f[k] *= s;
+    m[k] *= s;
+  }
+}
+
+// The sphere gradients are decoded without their power-of-two scale when it can be applied to the
+// sums instead (no swept gradient to add first): f, C and the moment are linear in them, so the
+// result is the same to the bit and each group saves a multiply per value.
+template <bool HAS_X>
+__device__ __forceinline__ float fold_scale(TV& G) {
+  if constexpr (HAS_X) {
+    return 1.f;
+  } else {
+    const float s = G.scale;
+    G.scale = 1.f;
+    return s;
+  }
+}
+
 constexpr int ADJ_TILE_WORDS = N_FIXED * LINK_VALUES * 64;  // link l (1..8) at slot l - 1
 constexpr int ADJ_Q_ROWS = 64 + 2;                          // joint rows b0 - 1 .. b0 + 64
+// After the link's owner has read its pose, the first two rotation columns of the link's tile slot
+// hold the link's force (f) and moment (m); the last phase reads only z = the third column and o.
+constexpr int ADJ_F[3] = {0, 4, 8}, ADJ_M[3] = {1, 5, 9}, ADJ_Z[3] = {2, 6, 10}, ADJ_O[3] = {3, 7, 11};
 
+// Pose cost at the end effector (pose T8 = [R | p], goal [R_g | p_g]): force 2 w_gp (p - p_g) at p
+// and couple -2 w_gr m(R R_g^T), added to the force and moment about the world origin.
+__device__ __forceinline__ void pose_cost_wrench(const float (&T8)[LINK_VALUES], const float* __restrict__ g,
+                                                 const CostArgs& cp, float (&f)[3], float (&m)[3]) {
+  float Fp[3];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) Fp[r] = 2.f * cp.w_gp * (T8[r * 4 + 3] - g[r * 4 + 3]);
+  // (R R_g^T)_{ik} = sum_c R_ic Rg_kc
+  auto RRg = [&](int i, int k) {
+    return fmaf(T8[i * 4 + 0], g[k * 4 + 0], fmaf(T8[i * 4 + 1], g[k * 4 + 1], T8[i * 4 + 2] * g[k * 4 + 2]));
+  };
+  const float mx = RRg(1, 2) - RRg(2, 1), my = RRg(2, 0) - RRg(0, 2), mz = RRg(0, 1) - RRg(1, 0);
+  const float c2 = -2.f * cp.w_gr;
+  const float px = T8[3], py = T8[7], pz = T8[11];
+  const float Mp[3] = {fmaf(py, Fp[2], fmaf(-pz, Fp[1], c2 * mx)), fmaf(pz, Fp[0], fmaf(-px, Fp[2], c2 * my)),
+                       fmaf(px, Fp[1], fmaf(-py, Fp[0], c2 * mz))};
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    f[k] = Fp[k] + f[k];
+    m[k] = Mp[k] + m[k];
+  }
+}
+
+// One block of four wavefronts per 64-configuration tile; wavefront w owns links w + 1 and w + 5.
+// Phase 1: each wavefront forms the pose-free sums of its links from the sphere groups that hold
+// their spheres (one group at a time); then the poses of links 1..8 go into the tile (decoded from L
+// by wavefronts 0-1, or recomputed by wavefront 0) and the joint rows the last phase reads (the
+// tile's and one on each side) into qs (wavefronts 2-3).  Phase 2: each owner turns its links' sums
+// into a force and a moment with the link's pose (adding the pose cost at link 8) and leaves them in
+// the link's tile slot.  Phase 3 (wavefront 0): the joint gradients from the tip to the base.  The
+// block's LDS (26 KB) allows six blocks per CU; the wavefronts are held to 128 VGPRs, four per SIMD
+// (not with a swept gradient, whose groups are decoded beside the sphere gradients').
 template <int FG, bool HAS_X>
-__global__ __launch_bounds__(256) void k_adjoint(const float* __restrict__ q, RobotArgs R, TV L, TV G, TV X, TV J,
-                                                 const double* __restrict__ up, float* __restrict__ grad_q,
-                                                 ShapeArgs sh, CostArgs cp, int recompute,
-                                                 const float* __restrict__ goal, WsCheck ck) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(HAS_X ? 1 : 4))) void k_adjoint(
+    const float* __restrict__ q, RobotArgs R, TV L, TV G, TV X, TV J, const double* __restrict__ up,
+    float* __restrict__ grad_q, ShapeArgs sh, CostArgs cp, int recompute, const float* __restrict__ goal,
+    WsCheck ck) {
   __shared__ float tile[ADJ_TILE_WORDS];
-  __shared__ float wrench[N_FIXED * 6 * 64];  // link l: force (3), moment (3) at ((l-1)*6 + k)*64 + lane
   __shared__ float qs[ADJ_Q_ROWS * N_JOINTS];  // row b0 - 1 + r at r * 7
   const int wave = uniform(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int64_t b0 = (int64_t)blockIdx.x * 64;
@@ -1554,6 +1616,30 @@ __global__ __launch_bounds__(256) void k_adjoint(const float* __restrict__ q, Ro
       for (int j = 0; j < N_JOINTS; ++j) grad_q[b * N_JOINTS + j] = __builtin_nanf("");
     }
     return;
+  }
+
+  // the sums need no pose: they come first, so that their loads are in flight before the staging's
+  const uint32_t* gbase = lane_base(G, b);
+  const uint32_t* xbase = HAS_X ? lane_base(X, b) : nullptr;
+  TV Gd = G;
+  const float gs = fold_scale<HAS_X>(Gd);
+  float f[2][3], C[2][9];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) f[h][k] = 0.f;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) C[h][k] = 0.f;
+    const int l = wave + 1 + 4 * h;
+    if (live) {
+      const cptr<int> lg = as_const(R.link_groups) + 2 * l;
+      const int g_lo = lg[0], g_hi = lg[1];
+      for (int g = g_lo; g < g_hi; ++g) {
+        float gx[SPH_GROUP], gy[SPH_GROUP], gz[SPH_GROUP];
+        load_sphere_grads<FG, HAS_X>(Gd, gbase, X, xbase, g, gx, gy, gz);
+        group_link_sums(R, g, l, gx, gy, gz, f[h], C[h]);
+      }
+    }
   }
   if (wave >= 2) {
     const int64_t base = (b0 - 1) * N_JOINTS, end = sh.B * N_JOINTS;
@@ -1582,18 +1668,18 @@ __global__ __launch_bounds__(256) void k_adjoint(const float* __restrict__ q, Ro
   }
   __syncthreads();
 
-  const uint32_t* gbase = lane_base(G, b);
-  const uint32_t* xbase = HAS_X ? lane_base(X, b) : nullptr;
-  for (int l = wave + 1; l <= N_FIXED; l += 4) {
-    float T[LINK_VALUES];
-    pose_from_tile(tile, l - 1, lane, T);
-    float f[3] = {0.f, 0.f, 0.f}, m[3] = {0.f, 0.f, 0.f};
-    if (live) link_wrench<FG, HAS_X>(R, gbase, G, X, xbase, l, T, f, m);
-    float* w = wrench + (l - 1) * 6 * 64 + lane;
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      w[k * 64] = f[k];
-      w[(3 + k) * 64] = m[k];
+  for (int h = 0; h < 2; ++h) {
+    const int l = wave + 1 + 4 * h;
+    float T[LINK_VALUES], m[3];
+    pose_from_tile(tile, l - 1, lane, T);
+    link_moment(T, C[h], gs, f[h], m);
+    if (l == N_FIXED && goal && live) pose_cost_wrench(T, goal + (b / sh.cfg_per_world) * LINK_VALUES, cp, f[h], m);
+    float* w = tile + (l - 1) * LINK_VALUES * 64 + lane;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      w[ADJ_F[c] * 64] = f[h][c];
+      w[ADJ_M[c] * 64] = m[c];
     }
   }
   __syncthreads();
@@ -1602,45 +1688,17 @@ __global__ __launch_bounds__(256) void k_adjoint(const float* __restrict__ q, Ro
   // tip to base: F_j, M_j over links >= j; J_j = z_j . (M_j - o_j x F_j)
   float Jv[J_GROUP];
   float F[3] = {0.f, 0.f, 0.f}, M[3] = {0.f, 0.f, 0.f};
-  if (goal) {
-    // pose cost: force 2 w_gp (p - p_g) at the end-effector origin p and couple -2 w_gr m(R R_g^T)
-    const float* T8 = tile + (N_FIXED - 1) * LINK_VALUES * 64 + lane;
-    const float* g = goal + (b / sh.cfg_per_world) * LINK_VALUES;
-    float Rm[9], p[3];
-#pragma unroll
-    for (int r = 0; r < 3; ++r) {
-#pragma unroll
-      for (int c = 0; c < 3; ++c) Rm[r * 3 + c] = T8[(r * 4 + c) * 64];
-      p[r] = T8[(r * 4 + 3) * 64];
-    }
-    float Fp[3];
-#pragma unroll
-    for (int r = 0; r < 3; ++r) Fp[r] = 2.f * cp.w_gp * (p[r] - g[r * 4 + 3]);
-    // (R R_g^T)_{ik} = sum_c R_ic Rg_kc
-    auto RRg = [&](int i, int k) {
-      return fmaf(Rm[i * 3 + 0], g[k * 4 + 0], fmaf(Rm[i * 3 + 1], g[k * 4 + 1], Rm[i * 3 + 2] * g[k * 4 + 2]));
-    };
-    const float mx = RRg(1, 2) - RRg(2, 1), my = RRg(2, 0) - RRg(0, 2), mz = RRg(0, 1) - RRg(1, 0);
-    const float c2 = -2.f * cp.w_gr;
-    F[0] = Fp[0];
-    F[1] = Fp[1];
-    F[2] = Fp[2];
-    M[0] = fmaf(p[1], Fp[2], fmaf(-p[2], Fp[1], c2 * mx));
-    M[1] = fmaf(p[2], Fp[0], fmaf(-p[0], Fp[2], c2 * my));
-    M[2] = fmaf(p[0], Fp[1], fmaf(-p[1], Fp[0], c2 * mz));
-  }
 #pragma unroll
   for (int l = N_FIXED; l >= 1; --l) {
-    const float* w = wrench + (l - 1) * 6 * 64 + lane;
+    const float* T = tile + (l - 1) * LINK_VALUES * 64 + lane;
 #pragma unroll
-    for (int i = 0; i < 3; ++i) {
-      F[i] += w[i * 64];
-      M[i] += w[(3 + i) * 64];
+    for (int c = 0; c < 3; ++c) {
+      F[c] += T[ADJ_F[c] * 64];
+      M[c] += T[ADJ_M[c] * 64];
     }
     if (l <= N_JOINTS) {
-      const float* T = tile + (l - 1) * LINK_VALUES * 64 + lane;
-      const float zx = T[2 * 64], zy = T[6 * 64], zz = T[10 * 64];
-      const float ox = T[3 * 64], oy = T[7 * 64], oz = T[11 * 64];
+      const float zx = T[ADJ_Z[0] * 64], zy = T[ADJ_Z[1] * 64], zz = T[ADJ_Z[2] * 64];
+      const float ox = T[ADJ_O[0] * 64], oy = T[ADJ_O[1] * 64], oz = T[ADJ_O[2] * 64];
       const float tx = M[0] - (oy * F[2] - oz * F[1]);
       const float ty = M[1] - (oz * F[0] - ox * F[2]);
       const float tz = M[2] - (ox * F[1] - oy * F[0]);
