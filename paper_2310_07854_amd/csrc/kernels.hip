@@ -125,6 +125,60 @@ __device__ __forceinline__ void store_group(const TV& t, int64_t b, int slot, co
   }
 }
 
+// A group of N values produced one at a time by get(i), for groups too large to hold at once: the
+// fixed formats pack every 16 values into whole dwords, so the group is encoded and stored 16 values
+// at a time (the same words as the whole group's); packed ExMy codes go word by word.
+template <int F, int N, typename Get>
+__device__ __forceinline__ void store_group_from_t(const TV& t, int64_t b, int slot, Get get) {
+  static_assert(N % 16 == 0, "16-value chunks");
+  uint32_t* lane = lane_base(t, b);
+  if constexpr (F == PXM) {
+    const int q = t.pq, bits = 1 + t.xe + t.xm;
+    uint32_t* base = lane + slot * ((N + q - 1) / q) * 64;
+    uint32_t acc = 0u;
+    int c = 0, k = 0;
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      acc |= exmy_encode(get(i) * t.inv, t.xe, t.xm) << (c * bits);
+      if (++c == q) {
+        base[k * 64] = acc;
+        ++k;
+        acc = 0u;
+        c = 0;
+      }
+    }
+    if (c) base[k * 64] = acc;
+  } else {
+    constexpr int DW = group_dwords(F, N), DW16 = group_dwords(F, 16);
+    static_assert(DW == DW16 * (N / 16), "whole dwords per 16 values");
+    uint32_t* base = lane + slot * DW * 64;
+#pragma unroll
+    for (int k = 0; k < N / 16; ++k) {
+      float v[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) v[i] = get(16 * k + i);
+      uint32_t w[DW16];
+      encode_group<F, 16>(v, t.inv, w);
+#pragma unroll
+      for (int d = 0; d < DW16; ++d) base[(k * DW16 + d) * 64] = w[d];
+    }
+  }
+}
+
+template <int N, typename Get>
+__device__ __forceinline__ void store_group_from(const TV& t, int64_t b, int slot, Get get) {
+  switch (t.fmt) {
+    case F32: store_group_from_t<F32, N>(t, b, slot, get); break;
+    case F16: store_group_from_t<F16, N>(t, b, slot, get); break;
+    case BF16: store_group_from_t<BF16, N>(t, b, slot, get); break;
+    case E4M3: store_group_from_t<E4M3, N>(t, b, slot, get); break;
+    case E5M2: store_group_from_t<E5M2, N>(t, b, slot, get); break;
+    case E3M2: store_group_from_t<E3M2, N>(t, b, slot, get); break;
+    case E2M1: store_group_from_t<E2M1, N>(t, b, slot, get); break;
+    default: store_group_from_t<PXM, N>(t, b, slot, get); break;
+  }
+}
+
 // group `slot` of N values of tensor t, from a lane base (HBM or an LDS image of the same layout)
 template <int F, int N>
 __device__ __forceinline__ void load_group_at(const TV& t, const uint32_t* base, int slot, float (&v)[N]) {
@@ -222,23 +276,17 @@ __device__ __forceinline__ void roundtrip(const TV& t, float (&v)[N]) {
 
 // ---- serial chain, link poses of a tile in LDS ---------------------------------------------------
 
-// LDS image of the nine link poses of a 64-configuration tile: value k of link l (0..8, [R | t]
-// row-major; link 0 is the identity) for lane j is word (l * 12 + k) * 64 + j, so a wavefront-wide
-// access touches 64 consecutive words, one per bank.
-constexpr int TILE_POSE_WORDS = N_LINKS * LINK_VALUES * 64;
+// LDS image of the poses of links 1..8 of a 64-configuration tile: value k of link l ([R | t]
+// row-major) for lane j is word ((l - 1) * 12 + k) * 64 + j, so a wavefront-wide access touches 64
+// consecutive words, one per bank.  The base, link 0, is the identity and is not stored.
+constexpr int TILE_POSE_WORDS = N_FIXED * LINK_VALUES * 64;
 
 // T_0 = I, T_j = T_{j-1} F_j Rz(q_j) (j = 1..7), T_8 = T_7 F_8, each link written to the tile as
-// it is formed.  WITH_BASE: the tile holds links 0..8 (link l at slot l); otherwise links 1..8 only
-// (link l at slot l - 1), for kernels that never read the identity base.
-template <bool WITH_BASE = true>
+// it is formed.
 __device__ __forceinline__ void chain_to_tile(const float* __restrict__ fixed, const float (&qv)[N_JOINTS],
                                               float* tile, int lane) {
   float R[9] = {1.f, 0.f, 0.f, 0.f, 1.f, 0.f, 0.f, 0.f, 1.f};
   float t[3] = {0.f, 0.f, 0.f};
-  if constexpr (WITH_BASE) {
-#pragma unroll
-    for (int k = 0; k < LINK_VALUES; ++k) tile[k * 64 + lane] = (k == 0 || k == 5 || k == 10) ? 1.f : 0.f;
-  }
 #pragma unroll
   for (int l = 0; l < N_FIXED; ++l) {
     const cptr<float> F = as_const(fixed) + l * LINK_VALUES;
@@ -264,7 +312,7 @@ __device__ __forceinline__ void chain_to_tile(const float* __restrict__ fixed, c
     for (int i = 0; i < 9; ++i) R[i] = nR[i];
 #pragma unroll
     for (int i = 0; i < 3; ++i) t[i] = nt[i];
-    float* out = tile + (WITH_BASE ? l + 1 : l) * LINK_VALUES * 64 + lane;
+    float* out = tile + l * LINK_VALUES * 64 + lane;
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
       out[(i * 4 + 0) * 64] = R[i * 3 + 0];
@@ -275,35 +323,14 @@ __device__ __forceinline__ void chain_to_tile(const float* __restrict__ fixed, c
   }
 }
 
-// pose of link l (0..8) of this lane
+// pose of link l (1..8) of this lane
 __device__ __forceinline__ void pose_from_tile(const float* tile, int l, int lane, float (&T)[LINK_VALUES]) {
-  const float* p = tile + l * LINK_VALUES * 64 + lane;
+  const float* p = tile + (l - 1) * LINK_VALUES * 64 + lane;
 #pragma unroll
   for (int k = 0; k < LINK_VALUES; ++k) T[k] = p[k * 64];
 }
 
-// The same read issued as explicit LDS instructions, so that it stays inside its wave-uniform
-// branch (the compiler would otherwise hoist the guarded reads of every sphere out of their branches
-// and keep all of them live).  Six ds_read2st64_b32 (two words 64 words apart each), then a wait.
 typedef float f32x2 __attribute__((ext_vector_type(2)));
-__device__ __forceinline__ void pose_from_tile_guarded(const float* tile, int l, int lane, float (&T)[LINK_VALUES]) {
-  const uint32_t addr =
-      (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) float*)(tile + l * LINK_VALUES * 64 + lane);
-  f32x2 a, b, c, d, e, f;
-  asm volatile(
-      "ds_read2st64_b32 %0, %6 offset0:0 offset1:1\n"
-      "ds_read2st64_b32 %1, %6 offset0:2 offset1:3\n"
-      "ds_read2st64_b32 %2, %6 offset0:4 offset1:5\n"
-      "ds_read2st64_b32 %3, %6 offset0:6 offset1:7\n"
-      "ds_read2st64_b32 %4, %6 offset0:8 offset1:9\n"
-      "ds_read2st64_b32 %5, %6 offset0:10 offset1:11\n"
-      "s_waitcnt lgkmcnt(0)"
-      : "=&v"(a), "=&v"(b), "=&v"(c), "=&v"(d), "=&v"(e), "=&v"(f)
-      : "v"(addr)
-      : "memory");
-  T[0] = a.x; T[1] = a.y; T[2] = b.x; T[3] = b.y; T[4] = c.x; T[5] = c.y;
-  T[6] = d.x; T[7] = d.y; T[8] = e.x; T[9] = e.y; T[10] = f.x; T[11] = f.y;
-}
 
 __device__ __forceinline__ void xform(const float (&T)[LINK_VALUES], float cx, float cy, float cz, float& x,
                                       float& y, float& z) {
@@ -324,32 +351,58 @@ __device__ __forceinline__ float bound_cost(const RobotArgs& R, const float (&qv
 
 // ---- K1: forward kinematics ---------------------------------------------------------------------
 
-// World centres of sphere group g (p_s = R_l c_s + t_l).  The pose is re-read from the tile only
-// when the link changes from one sphere to the next; robots list their spheres link by link, so a
-// group reads two or three poses.  The zero padding sits on link 0.
+// Row c (R_c0, R_c1, R_c2, t_c) of the pose of link l (1..8), read as explicit LDS instructions so
+// that it stays inside its wave-uniform branch (the compiler would otherwise hoist the guarded reads
+// of every sphere out of their branches and keep all of them live): two ds_read2st64_b32 (two words
+// 64 words apart each), then a wait.  Link 0 is the identity.
+__device__ __forceinline__ void pose_row_guarded(const float* tile, int l, int c, int lane, float (&r)[4]) {
+  if (l == 0) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) r[k] = k == c ? 1.f : 0.f;
+    return;
+  }
+  const uint32_t addr = (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) float*)(
+      tile + ((l - 1) * LINK_VALUES + c * 4) * 64 + lane);
+  f32x2 a, b;
+  asm volatile(
+      "ds_read2st64_b32 %0, %2 offset0:0 offset1:1\n"
+      "ds_read2st64_b32 %1, %2 offset0:2 offset1:3\n"
+      "s_waitcnt lgkmcnt(0)"
+      : "=&v"(a), "=&v"(b)
+      : "v"(addr)
+      : "memory");
+  r[0] = a.x; r[1] = a.y; r[2] = b.x; r[3] = b.y;
+}
+
+// World centres of sphere group g (p_s = R_l c_s + t_l), one coordinate plane at a time: a plane
+// needs only its row of each pose, so its 16 values are the only ones held, and it is stored as
+// soon as it is formed.  The row is re-read from the tile only when the link changes from one
+// sphere to the next; robots list their spheres link by link, so a group reads two or three poses.
+// The zero padding sits on link 0.
 template <int FS>
 __device__ __forceinline__ void place_group(const RobotArgs& R, const TV& S, int64_t b, int g, const float* tile,
                                             int lane) {
-  float px[SPH_GROUP], py[SPH_GROUP], pz[SPH_GROUP];
-  float T[LINK_VALUES];
-  int cur = as_const(R.link)[g * SPH_GROUP];
-  pose_from_tile(tile, cur, lane, T);
 #pragma unroll
-  for (int i = 0; i < SPH_GROUP; ++i) {
-    const int s = g * SPH_GROUP + i;
-    const float4 c = sphere_of(R.sph, s);
-    const int l = as_const(R.link)[s];
-    if (l != cur) {
-      cur = l;
-      pose_from_tile_guarded(tile, l, lane, T);
+  for (int c = 0; c < 3; ++c) {
+    float v[SPH_GROUP];
+    float r[4];
+    int cur = as_const(R.link)[g * SPH_GROUP];
+    pose_row_guarded(tile, cur, c, lane, r);
+#pragma unroll
+    for (int i = 0; i < SPH_GROUP; ++i) {
+      const int s = g * SPH_GROUP + i;
+      const float4 cs = sphere_of(R.sph, s);
+      const int l = as_const(R.link)[s];
+      if (l != cur) {
+        cur = l;
+        pose_row_guarded(tile, l, c, lane, r);
+      }
+      v[i] = fmaf(r[0], cs.x, fmaf(r[1], cs.y, fmaf(r[2], cs.z, r[3])));
+      // computed here, not sunk past the next pose change (which would keep every row version live)
+      asm volatile("" : "+v"(v[i]));
     }
-    xform(T, c.x, c.y, c.z, px[i], py[i], pz[i]);
-    // computed here, not sunk past the next pose change (which would keep every pose version live)
-    asm volatile("" : "+v"(px[i]), "+v"(py[i]), "+v"(pz[i]));
+    store_group_t<FS, SPH_GROUP>(S, b, g * 3 + c, v);
   }
-  store_group_t<FS, SPH_GROUP>(S, b, g * 3 + 0, px);
-  store_group_t<FS, SPH_GROUP>(S, b, g * 3 + 1, py);
-  store_group_t<FS, SPH_GROUP>(S, b, g * 3 + 2, pz);
 }
 
 // One block of four wavefronts per 64-configuration tile: wavefront 0 runs the chain into LDS, then
@@ -376,7 +429,7 @@ __global__ __launch_bounds__(256) void k_fk(const float* __restrict__ q, RobotAr
       float sp = 0.f, sr = 0.f;
 #pragma unroll
       for (int k = 0; k < LINK_VALUES; ++k) {
-        const float e = tile[(N_FIXED * LINK_VALUES + k) * 64 + lane] - g[k];
+        const float e = tile[((N_FIXED - 1) * LINK_VALUES + k) * 64 + lane] - g[k];
         if ((k & 3) == 3) sp = fmaf(e, e, sp);
         else sr = fmaf(e, e, sr);
       }
@@ -393,10 +446,8 @@ __global__ __launch_bounds__(256) void k_fk(const float* __restrict__ q, RobotAr
       place_group<FS>(R, S, b, it, tile, lane);
     } else {
       const int gr = it - ng;
-      float v[L_GROUP];
-#pragma unroll
-      for (int i = 0; i < L_GROUP; ++i) v[i] = tile[(LINK_VALUES + gr * L_GROUP + i) * 64 + lane];
-      store_group<L_GROUP>(L, b, gr, v);
+      const float* src = tile + gr * L_GROUP * 64 + lane;
+      store_group_from<L_GROUP>(L, b, gr, [&](int i) { return src[i * 64]; });
     }
   }
 }
@@ -1560,7 +1611,6 @@ __device__ __forceinline__ float fold_scale(TV& G) {
   }
 }
 
-constexpr int ADJ_TILE_WORDS = N_FIXED * LINK_VALUES * 64;  // link l (1..8) at slot l - 1
 constexpr int ADJ_Q_ROWS = 64 + 2;                          // joint rows b0 - 1 .. b0 + 64
 // After the link's owner has read its pose, the first two rotation columns of the link's tile slot
 // hold the link's force (f) and moment (m); the last phase reads only z = the third column and o.
@@ -1603,7 +1653,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(HAS_X ? 1 :
     const float* __restrict__ q, RobotArgs R, TV L, TV G, TV X, TV J, const double* __restrict__ up,
     float* __restrict__ grad_q, ShapeArgs sh, CostArgs cp, int recompute, const float* __restrict__ goal,
     WsCheck ck) {
-  __shared__ float tile[ADJ_TILE_WORDS];
+  __shared__ float tile[TILE_POSE_WORDS];
   __shared__ float qs[ADJ_Q_ROWS * N_JOINTS];  // row b0 - 1 + r at r * 7
   const int wave = uniform(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int64_t b0 = (int64_t)blockIdx.x * 64;
@@ -1653,7 +1703,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(HAS_X ? 1 :
       float qv[N_JOINTS];
 #pragma unroll
       for (int j = 0; j < N_JOINTS; ++j) qv[j] = live ? q[b * N_JOINTS + j] : 0.f;
-      chain_to_tile<false>(R.fixed, qv, tile, lane);
+      chain_to_tile(R.fixed, qv, tile, lane);
     }
   } else if (wave < L_GROUPS) {
     float v[L_GROUP];
@@ -1672,7 +1722,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(HAS_X ? 1 :
   for (int h = 0; h < 2; ++h) {
     const int l = wave + 1 + 4 * h;
     float T[LINK_VALUES], m[3];
-    pose_from_tile(tile, l - 1, lane, T);
+    pose_from_tile(tile, l, lane, T);
     link_moment(T, C[h], gs, f[h], m);
     if (l == N_FIXED && goal && live) pose_cost_wrench(T, goal + (b / sh.cfg_per_world) * LINK_VALUES, cp, f[h], m);
     float* w = tile + (l - 1) * LINK_VALUES * 64 + lane;
