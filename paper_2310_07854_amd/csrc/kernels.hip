@@ -528,7 +528,7 @@ __device__ __forceinline__ void closest_cuboids(cptr<float> wbox, int K, const f
       const float u2 = fmaf(A6, px[i], fmaf(A7, py[i], fmaf(A8, pz[i], -o2)));
       const float a0 = fabsf(u0) - h0, a1 = fabsf(u1) - h1, a2 = fabsf(u2) - h2;
       const float m0 = fmaxf(a0, 0.f), m1 = fmaxf(a1, 0.f), m2 = fmaxf(a2, 0.f);
-      const float key = fmaf(m0, m0, fmaf(m1, m1, m2 * m2)) + fminf(fmaxf(fmaxf(a0, a1), a2), 0.f);
+      const float key = fmaf(m0, m0, fmaf(m1, m1, fmaf(m2, m2, fminf(fmaxf(fmaxf(a0, a1), a2), 0.f))));
       if (key < best[i]) {
         best[i] = key;
         bk[i] = k;
@@ -670,7 +670,10 @@ __device__ __forceinline__ void cuboid_key_v(const float4& c0, const float4& c1,
   const float u2 = fmaf(c1.z, px, fmaf(c1.w, py, fmaf(c2.x, pz, -c2.w)));
   const float a0 = fabsf(u0) - c3.x, a1 = fabsf(u1) - c3.y, a2 = fabsf(u2) - c3.z;
   const float m0 = fmaxf(a0, 0.f), m1 = fmaxf(a1, 0.f), m2 = fmaxf(a2, 0.f);
-  const float key = fmaf(m0, m0, fmaf(m1, m1, m2 * m2)) + fminf(fmaxf(fmaxf(a0, a1), a2), 0.f);
+  // |m|^2 outside (max a > 0, the min term is 0) and max a inside (m = 0): the min term goes in as
+  // the innermost addend, which gives the same value to the bit as adding it last, one instruction
+  // fewer
+  const float key = fmaf(m0, m0, fmaf(m1, m1, fmaf(m2, m2, fminf(fmaxf(fmaxf(a0, a1), a2), 0.f))));
   if (key < best) {
     best = key;
     bk = k;
