@@ -1467,19 +1467,27 @@ __device__ __forceinline__ double wave_sum(double v) {
   return (readlane_f64(v, 0) + readlane_f64(v, 16)) + (readlane_f64(v, 32) + readlane_f64(v, 48));
 }
 
-// configuration cost of b: w_c sum_s d_s^2 (FP64) + self + w_b bound (+ swept, + pose)
+// configuration cost of b: w_c sum_s d_s^2 (FP64) + self + w_b bound (+ swept, + pose).  D's groups
+// are loaded four at a time, all four in flight together (the index clamped to the last group, so
+// no branch separates the loads), then added in sphere order.
+template <int FD>
 __device__ __forceinline__ double cfg_cost(const TV& D, const float* __restrict__ selfc,
                                           const float* __restrict__ boundc, const float* __restrict__ sweptc,
                                           const float* __restrict__ posec, int64_t b, const CostArgs& cp, int n_s) {
   const int ng = (n_s + SPH_GROUP - 1) / SPH_GROUP;
+  const uint32_t* base = lane_base(D, b);
   double sq = 0.0;
-  for (int g = 0; g < ng; ++g) {
-    float dv[SPH_GROUP];
-    load_group<SPH_GROUP>(D, b, g, dv);
-    const int active = min(SPH_GROUP, n_s - g * SPH_GROUP);
+  for (int g0 = 0; g0 < ng; g0 += 4) {
+    float dv[4][SPH_GROUP];
 #pragma unroll
-    for (int i = 0; i < SPH_GROUP; ++i)
-      if (i < active) sq = fma((double)dv[i], (double)dv[i], sq);
+    for (int j = 0; j < 4; ++j) load_group_at<FD, SPH_GROUP>(D, base, min(g0 + j, ng - 1), dv[j]);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int active = g0 + j < ng ? min(SPH_GROUP, n_s - (g0 + j) * SPH_GROUP) : 0;
+#pragma unroll
+      for (int i = 0; i < SPH_GROUP; ++i)
+        if (i < active) sq = fma((double)dv[j][i], (double)dv[j][i], sq);
+    }
   }
   double c = (double)cp.w_c * sq + (double)selfc[b] + (double)cp.w_b * (double)boundc[b];
   if (sweptc) c += (double)sweptc[b];
@@ -1489,6 +1497,7 @@ __device__ __forceinline__ double cfg_cost(const TV& D, const float* __restrict_
 
 // one-timestep trajectories (inverse kinematics): one configuration per lane; the trajectory cost is
 // the configuration cost, as the general kernel's sum over one timestep gives
+template <int FD>
 __global__ __launch_bounds__(256) void k_reduce_t1(TV D, const float* __restrict__ selfc,
                                                    const float* __restrict__ boundc, const float* __restrict__ sweptc,
                                                    const float* __restrict__ posec, double* __restrict__ cost_traj,
@@ -1497,11 +1506,12 @@ __global__ __launch_bounds__(256) void k_reduce_t1(TV D, const float* __restrict
   ws_stamp(st);
   const int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (b >= sh.B) return;
-  const double c = cfg_cost(D, selfc, boundc, sweptc, posec, b, cp, n_s);
+  const double c = cfg_cost<FD>(D, selfc, boundc, sweptc, posec, b, cp, n_s);
   if (cost_cfg) cost_cfg[b] = (float)c;
   cost_traj[b] = c;
 }
 
+template <int FD>
 __global__ __launch_bounds__(256) void k_reduce(TV D, const float* __restrict__ selfc,
                                                 const float* __restrict__ boundc, const float* __restrict__ sweptc,
                                                 const float* __restrict__ posec, const float* __restrict__ q,
@@ -1517,7 +1527,7 @@ __global__ __launch_bounds__(256) void k_reduce(TV D, const float* __restrict__ 
     const int t = t0 + lane;
     if (t < T) {
       const int64_t b = tc * T + t;
-      const double c = cfg_cost(D, selfc, boundc, sweptc, posec, b, cp, n_s);
+      const double c = cfg_cost<FD>(D, selfc, boundc, sweptc, posec, b, cp, n_s);
       if (cost_cfg) cost_cfg[b] = (float)c;
       double sm = 0.0;
       if (t + 1 < T) {
@@ -2366,12 +2376,21 @@ hipError_t launch_sphere_cost_blk(hipStream_t s, const RobotArgs& R, const World
 hipError_t launch_reduce(hipStream_t s, const TV& D, const float* selfc, const float* boundc, const float* sweptc,
                          const float* posec, const float* q, double* cost_traj, float* cost_cfg, const ShapeArgs& sh,
                          const CostArgs& cp, int n_s, const WsStamp& st) {
-  if (sh.T == 1)
-    hipLaunchKernelGGL(k_reduce_t1, dim3(blocks_for(sh.B, 256)), dim3(256), 0, s, D, selfc, boundc, sweptc, posec,
-                       cost_traj, cost_cfg, sh, cp, n_s, st);
-  else
-    hipLaunchKernelGGL(k_reduce, dim3(blocks_for(sh.n_tc, 4)), dim3(256), 0, s, D, selfc, boundc, sweptc, posec, q,
-                       cost_traj, cost_cfg, sh, cp, n_s, st);
+  switch (D.fmt) {
+#define VAPR_REDUCE_CASE(F)                                                                                   \
+  case F:                                                                                                     \
+    if (sh.T == 1)                                                                                            \
+      hipLaunchKernelGGL(k_reduce_t1<F>, dim3(blocks_for(sh.B, 256)), dim3(256), 0, s, D, selfc, boundc, sweptc, \
+                         posec, cost_traj, cost_cfg, sh, cp, n_s, st);                                        \
+    else                                                                                                      \
+      hipLaunchKernelGGL(k_reduce<F>, dim3(blocks_for(sh.n_tc, 4)), dim3(256), 0, s, D, selfc, boundc, sweptc, \
+                         posec, q, cost_traj, cost_cfg, sh, cp, n_s, st);                                     \
+    break;
+    VAPR_REDUCE_CASE(F32) VAPR_REDUCE_CASE(F16) VAPR_REDUCE_CASE(BF16) VAPR_REDUCE_CASE(E4M3)
+    VAPR_REDUCE_CASE(E5M2) VAPR_REDUCE_CASE(E3M2) VAPR_REDUCE_CASE(E2M1) VAPR_REDUCE_CASE(PXM)
+#undef VAPR_REDUCE_CASE
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
