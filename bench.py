@@ -681,6 +681,10 @@ def seed_cpu_baseline(budget_s=12.0):
             "sample": f"{n} problems of 16 cuboids, inference, {dt:.1f} s single-threaded"}
 
 
+class InfeasibleEnvironment(RuntimeError):
+    pass
+
+
 def seeding_study(args):
     """The learned seeder end to end on synthetic problems (one GPU), per environment: an environment
     is a base world of 16 cuboids whose problems jitter every cuboid centre by up to 5 cm and draw
@@ -723,7 +727,7 @@ def seeding_study(args):
             split += 1
             log(f"environment {family}: {have} of {n_want} feasible problems from {drawn} drawn")
             if drawn >= 64 * n_want:
-                raise RuntimeError(f"environment {family}: too few problems with collision-free endpoints")
+                raise InfeasibleEnvironment(f"environment {family}: too few problems with collision-free endpoints")
         return {k: np.concatenate(v)[:n_want] for k, v in keep.items()}, drawn
 
     def dataset(family):
@@ -749,10 +753,20 @@ def seeding_study(args):
         keep = data["valid"].sum(dim=1) > 0
         return {k: v[keep] for k, v in data.items()}, drawn
 
-    envs = []
-    for family in range(args.seed_envs):
+    # environments are drawn in turn; one whose base world leaves almost no start and goal
+    # collision-free (fewer than 1 in 64 draws) is skipped and recorded
+    envs, skipped, family = [], [], -1
+    while len(envs) < args.seed_envs:
+        family += 1
+        if family >= 4 * args.seed_envs:
+            raise RuntimeError("too many environments without collision-free problems")
         t0 = time.perf_counter()
-        data, drawn = dataset(family)
+        try:
+            data, drawn = dataset(family)
+        except InfeasibleEnvironment as e:
+            log(str(e) + ": skipped")
+            skipped.append(family)
+            continue
         t_data = time.perf_counter() - t0
         n_data = int(data["start"].shape[0])
         net = SG.SeedNet(make_seednet_params())
@@ -777,6 +791,13 @@ def seeding_study(args):
         # ... or with four random-via-point seeds, the family that reaches the hard problems soonest
         inits["network+random"] = torch.cat([inits["network"][:, :S_EVAL // 2], inits["random"][:, :S_EVAL // 2]],
                                             dim=1)
+        # each network slot bent through a random via point: the slot plus the random seed's
+        # deviation from the straight line (zero at the endpoints), so the learned route keeps the
+        # random seeds' spread; alone, and its first four with the network's first four
+        straight = inits["linear"][:, :1]
+        inits["network bent"] = inits["network"] + (inits["random"] - straight)
+        inits["network+bent"] = torch.cat([inits["network"][:, :S_EVAL // 2],
+                                           inits["network bent"][:, :S_EVAL // 2]], dim=1)
         firsts, final_cost = {}, {}
         for kind, x0 in inits.items():
             sol = SP.solve(ctx, x0.contiguous(), iters=args.seed_eval_iters, check_every=1)
@@ -810,7 +831,7 @@ def seeding_study(args):
 
     # pooled over environments: collision-free rate by iteration, and the iterations each kind of
     # seed needs to reach the rate that all three reach
-    kinds = ("network", "linear", "random", "network+linear", "network+random")
+    kinds = ("network", "linear", "random", "network+linear", "network+random", "network bent", "network+bent")
     pooled = {k: np.concatenate([e["firsts"][k] for e in envs]) for k in kinds}
     marks = sorted({0, 1, 2, 3, 5, 10, 20, args.seed_eval_iters})
     curves = {k: {str(i): float(np.mean((ff >= 0) & (ff <= i))) for i in marks} for k, ff in pooled.items()}
@@ -822,7 +843,8 @@ def seeding_study(args):
     for e in envs:
         e.pop("firsts")
     line = {"metric": "learned seeding: collision-free rate by optimiser iteration (network vs linear vs random "
-                      "seeds, 8 each; 4 network + 4 linear; 4 network + 4 random)",
+                      "seeds, 8 each; 4 network + 4 linear; 4 network + 4 random; network slots bent through "
+                      "random via points, 8, and 4 network + 4 of those)",
             "data": "synthetic", "n_gpus": 1, "dtype": "bf16 GEMM operands, f32 accumulate",
             "config": {"workload": f"7-joint arm, 60 spheres, no self pairs; {args.seed_envs} environments of {K} "
                                    f"cuboids (centres jittered 5 cm per problem); T = {T}; "
@@ -832,7 +854,7 @@ def seeding_study(args):
                                    f"{args.seed_eval} held-out problems per environment",
                        "train_steps": args.seed_train_steps, "batch": 256, "lr": 1e-3},
             "curves": curves, "common_rate": rate, "iterations_to_common_rate": need,
-            "environments": envs,
+            "environments": envs, "environments_skipped": skipped,
             "network_forward": {"batch": nb, "ms": fwd_ms, "TFLOPs": flops / (fwd_ms * 1e-3) / 1e12,
                                 "peak_bf16_TFLOPs": 2500.0},
             "total_s": time.perf_counter() - t_start}
