@@ -332,13 +332,6 @@ __device__ __forceinline__ void pose_from_tile(const float* tile, int l, int lan
 
 typedef float f32x2 __attribute__((ext_vector_type(2)));
 
-__device__ __forceinline__ void xform(const float (&T)[LINK_VALUES], float cx, float cy, float cz, float& x,
-                                      float& y, float& z) {
-  x = fmaf(T[0], cx, fmaf(T[1], cy, fmaf(T[2], cz, T[3])));
-  y = fmaf(T[4], cx, fmaf(T[5], cy, fmaf(T[6], cz, T[7])));
-  z = fmaf(T[8], cx, fmaf(T[9], cy, fmaf(T[10], cz, T[11])));
-}
-
 __device__ __forceinline__ float bound_cost(const RobotArgs& R, const float (&qv)[N_JOINTS]) {
   float bc = 0.f;
 #pragma unroll
