@@ -17,14 +17,18 @@ ORACLE_KEY = {"link_poses": "L", "sphere_pos": "S", "sphere_dist": "D", "sphere_
 # Bounds on the error of the float32 computation of each stored quantity before it is encoded
 # (absolute in the tensor's units, plus a relative part).  Positions and poses come out of an
 # 8-transform chain of float32 products (about 24 roundings of unit-size terms); distances add the
-# cuboid transform; gradients scale a distance error by 2*w = 200 and a direction error by 2*w*d.
+# cuboid transform.  A sphere gradient sums up to 1 + 8 terms (its closest cuboid and its active
+# pairs), each a distance carrying about 2.4e-7 m of rounding (two roundings of 2 m coordinates)
+# scaled by 2w = 200: 4.3e-4, doubled.  A joint gradient sums lever arm x sphere gradient over the
+# spheres beyond the joint.  The FP32 assignment of the stage tests prints how much of each band
+# its arithmetic uses (at most about a quarter for G at this band, a twentieth for the others).
 RISK = {
     "link_poses": (1e-5, 4e-6),
     "sphere_pos": (1e-5, 4e-6),
     "sphere_dist": (1e-5, 8e-6),
-    "sphere_grad": (1e-4, 5e-3),
+    "sphere_grad": (1e-4, 1e-3),
     "joint_grad": (2e-4, 2e-3),
-    "swept_grad": (1e-4, 5e-3),
+    "swept_grad": (1e-4, 1e-3),
 }
 
 
@@ -111,8 +115,13 @@ def compare_codes(name, fmt, k, gpu_codes, oracle_codes, oracle_values, exempt=N
     # +0 and -0 are one value (ordinal 0): which sign an exact zero carries is not compared
     diff = keep & (og != ordinal(oracle_codes, fmt))
     assert not (diff & ~flagged).any()
+    ratio = ""
+    if fmt == "f32" and keep.any():
+        # FP32 codes are the computed values themselves: how much of the band the error uses
+        err = np.abs(F.dequantize(gpu_codes, fmt, k).astype(np.float64) - x)
+        ratio = f", worst error / band {float((err / tol)[keep].max()):.3f}"
     print(f"[codes] {name}/{fmt} k={k}: {int(keep.sum())} compared, {int(flagged.sum())} near a boundary, "
-          f"{int(diff.sum())} differ from the oracle")
+          f"{int(diff.sum())} differ from the oracle{ratio}")
     return int(flagged.sum()), int(diff.sum())
 
 

@@ -24,6 +24,9 @@ from tests.gpu_helpers import (ORACLE_KEY, TENSORS, cfg_cost_tolerance, compare_
 pytestmark = pytest.mark.gpu
 
 PRECISIONS = {
+    # FP32 codes are the computed values: the code tests then report how much of each band the FP32
+    # arithmetic uses
+    "f32": {t: "f32" for t in TENSORS},
     "f16": {t: "f16" for t in TENSORS},
     "bf16": {t: "bf16" for t in TENSORS},
     "fp8": {"link_poses": ("e4m3", -7), "sphere_pos": ("e4m3", -7), "sphere_dist": ("e4m3", -10),
