@@ -707,6 +707,63 @@ __device__ __forceinline__ void walk_list(uint64_t m, const float* base, int i0,
   }
 }
 
+// NB self-pair visits of sphere s (centre q, radius rs) from its visit list at e: partner centres
+// from the block's LDS image (all NB loads issued before the first test), the sphere's gradient
+// into g, and the cost of the pairs whose partner has the higher index into acc.  A pair whose
+// squared centre distance exceeds the entry's lim2 has an activation of exactly zero.
+template <int NB>
+__device__ __forceinline__ void pair_visits(cptr<float> e, const float* pos, int lane, int s, float qx, float qy,
+                                            float qz, float rs, const CostArgs& cp, float& gx, float& gy,
+                                            float& gz, float& acc) {
+  float tx[NB], ty[NB], tz[NB];
+#pragma unroll
+  for (int u = 0; u < NB; ++u) {
+    const float* pp = pos + (unsigned)__float_as_int(e[4 * u]) * 3u * 64u + lane;
+    tx[u] = pp[0];
+    ty[u] = pp[64];
+    tz[u] = pp[128];
+  }
+#pragma unroll
+  for (int u = 0; u < NB; ++u) {
+    const float dx = qx - tx[u], dy = qy - ty[u], dz = qz - tz[u];
+    const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+    if (!(d2 <= e[4 * u + 2])) continue;
+    // hardware reciprocal square root (about 1 ulp): distance and unit direction in one step;
+    // coincident centres give distance 0 and no gradient
+    const float inv = __builtin_amdgcn_rsqf(d2);
+    const bool apart = d2 > 0.f;
+    const float dist = apart ? d2 * inv : 0.f;
+    const float ev = dist - rs - e[4 * u + 1];
+    const float act = fmaxf(cp.eta - ev, 0.f);
+    if (act > 0.f) {
+      const float coef = (-2.f * cp.w_s) * act * inv;
+      if (apart) {
+        gx = fmaf(coef, dx, gx);
+        gy = fmaf(coef, dy, gy);
+        gz = fmaf(coef, dz, gz);
+      }
+      if (s < __float_as_int(e[4 * u])) acc = fmaf(act, act, acc);
+    }
+  }
+}
+
+// Sphere s's whole visit list [j0, j1): four visits at a time, then a pair and a single for the
+// remainder (the counts are the same in every lane).
+__device__ __forceinline__ void sphere_pair_visits(const RobotArgs& R, const float* pos, int lane, int s, float qx,
+                                                   float qy, float qz, float rs, const CostArgs& cp, float& gx,
+                                                   float& gy, float& gz, float& acc) {
+  const int j0 = as_const(R.pair_off)[s], j1 = as_const(R.pair_off)[s + 1];
+  const cptr<float> tab = as_const(reinterpret_cast<const float*>(R.pair_tab));
+  const int j4 = j0 + ((j1 - j0) & ~3);
+  for (int j = j0; j < j4; j += 4) pair_visits<4>(tab + 4 * j, pos, lane, s, qx, qy, qz, rs, cp, gx, gy, gz, acc);
+  int j = j4;
+  if ((j1 - j) & 2) {
+    pair_visits<2>(tab + 4 * j, pos, lane, s, qx, qy, qz, rs, cp, gx, gy, gz, acc);
+    j += 2;
+  }
+  if (j < j1) pair_visits<1>(tab + 4 * j, pos, lane, s, qx, qy, qz, rs, cp, gx, gy, gz, acc);
+}
+
 template <int FS>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3))) void k_sphere_cost_blk(RobotArgs R, WorldArgs W, GridArgs Gd, TV S, TV D, TV G,
                                                           float* __restrict__ selfc, ShapeArgs sh, CostArgs cp) {
@@ -854,51 +911,16 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3))) void k
     }
   }
   // Self pairs: partners of any group are read from the LDS image four at a time (one scalar load
-  // of four table entries).  A visit whose squared centre distance exceeds the pair's bound is
+  // of four table entries), then two and one for the rest of the list.  A visit whose squared centre distance exceeds the pair's bound is
   // inactive and ends there; the others take the exact path.  Each pair is visited from both of its
   // spheres: each visit adds its own sphere's gradient and the lower index adds the cost, so no
   // cross-lane or atomic accumulation is needed.
   float self_acc = 0.f;
-  constexpr int PB = 4;
 #pragma unroll
   for (int i = 0; i < SPH_GROUP; ++i) {
     if (i >= active) continue;
     const int s = g * SPH_GROUP + i;
-    const float rs = sphere_of(R.sph, s).w;
-    const int j0 = as_const(R.pair_off)[s], j1 = as_const(R.pair_off)[s + 1];
-    for (int j = j0; j < j1; j += PB) {
-      const cptr<float> e = as_const(reinterpret_cast<const float*>(R.pair_tab)) + 4 * j;
-      float tx[PB], ty[PB], tz[PB];
-#pragma unroll
-      for (int u = 0; u < PB; ++u) {
-        const float* pp = pos + (unsigned)__float_as_int(e[4 * u]) * 3u * 64u + lane;
-        tx[u] = pp[0];
-        ty[u] = pp[64];
-        tz[u] = pp[128];
-      }
-#pragma unroll
-      for (int u = 0; u < PB; ++u) {
-        const float dx = px[i] - tx[u], dy = py[i] - ty[u], dz = pz[i] - tz[u];
-        const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-        if (!(d2 <= e[4 * u + 2])) continue;
-        // hardware reciprocal square root (about 1 ulp): distance and unit direction in one step;
-        // coincident centres give distance 0 and no gradient
-        const float inv = __builtin_amdgcn_rsqf(d2);
-        const bool apart = d2 > 0.f;
-        const float dist = apart ? d2 * inv : 0.f;
-        const float ev = dist - rs - e[4 * u + 1];
-        const float act = fmaxf(cp.eta - ev, 0.f);
-        if (act > 0.f) {
-          const float coef = (-2.f * cp.w_s) * act * inv;
-          if (apart) {
-            gx[i] = fmaf(coef, dx, gx[i]);
-            gy[i] = fmaf(coef, dy, gy[i]);
-            gz[i] = fmaf(coef, dz, gz[i]);
-          }
-          if (s < __float_as_int(e[4 * u])) self_acc = fmaf(act, act, self_acc);
-        }
-      }
-    }
+    sphere_pair_visits(R, pos, lane, s, px[i], py[i], pz[i], sphere_of(R.sph, s).w, cp, gx[i], gy[i], gz[i], self_acc);
   }
   if (valid) {
     store_group<SPH_GROUP>(D, b, g, dv);
@@ -1115,48 +1137,15 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(VAPR_K2H_WA
     // spheres' cuboids (they cannot fault) and hold them in registers
     asm volatile("" ::: "memory");
   }
-  // Self pairs, as in k_sphere_cost_blk: partners from the LDS image four at a time, every pair
-  // visited from both spheres, the lower index adding the cost.
+  // Self pairs, as in k_sphere_cost_blk: partners from the LDS image four at a time (then two and
+  // one), every pair visited from both spheres, the lower index adding the cost.
   float self_acc = 0.f;
-  constexpr int PB = 4;
 #pragma unroll
   for (int i = 0; i < HS; ++i) {
     if (i >= active) continue;
     const int s = s0 + i;
-    const float rs = sphere_of(R.sph, s).w;
     const float qx = own[(i * 3 + 0) * 64], qy = own[(i * 3 + 1) * 64], qz = own[(i * 3 + 2) * 64];
-    const int j0 = as_const(R.pair_off)[s], j1 = as_const(R.pair_off)[s + 1];
-    for (int j = j0; j < j1; j += PB) {
-      const cptr<float> e = as_const(reinterpret_cast<const float*>(R.pair_tab)) + 4 * j;
-      float tx[PB], ty[PB], tz[PB];
-#pragma unroll
-      for (int u = 0; u < PB; ++u) {
-        const float* pp = pos + (unsigned)__float_as_int(e[4 * u]) * 3u * 64u + lane;
-        tx[u] = pp[0];
-        ty[u] = pp[64];
-        tz[u] = pp[128];
-      }
-#pragma unroll
-      for (int u = 0; u < PB; ++u) {
-        const float dx = qx - tx[u], dy = qy - ty[u], dz = qz - tz[u];
-        const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-        if (!(d2 <= e[4 * u + 2])) continue;
-        const float inv = __builtin_amdgcn_rsqf(d2);
-        const bool apart = d2 > 0.f;
-        const float dist = apart ? d2 * inv : 0.f;
-        const float ev = dist - rs - e[4 * u + 1];
-        const float act = fmaxf(cp.eta - ev, 0.f);
-        if (act > 0.f) {
-          const float coef = (-2.f * cp.w_s) * act * inv;
-          if (apart) {
-            gx[i] = fmaf(coef, dx, gx[i]);
-            gy[i] = fmaf(coef, dy, gy[i]);
-            gz[i] = fmaf(coef, dz, gz[i]);
-          }
-          if (s < __float_as_int(e[4 * u])) self_acc = fmaf(act, act, self_acc);
-        }
-      }
-    }
+    sphere_pair_visits(R, pos, lane, s, qx, qy, qz, sphere_of(R.sph, s).w, cp, gx[i], gy[i], gz[i], self_acc);
   }
   __syncthreads();  // the position image is read for the last time above
   float* xg = pos + g * (4 * HS * 64) + lane;

@@ -14,10 +14,9 @@ struct RobotArgs {
   const int* csr_off;    // [n_s + 1] self-pair partners of each sphere
   const int* csr_nbr;    // [2 * n_pairs]
   const int* link_groups;  // [N_LINKS][2]: first and one-past-last sphere group holding a sphere of the link
-  // Self-pair visits of sphere s: pair_tab[pair_off[s] .. pair_off[s + 1]), a multiple of 4
-  // entries (partner index as int bits, partner radius, lim2, 0), where lim2 bounds the squared
-  // centre distance beyond which the pair is certainly inactive; lists are padded with entries
-  // (s, 0, -1, 0) that are never active.
+  // Self-pair visits of sphere s: pair_tab[pair_off[s] .. pair_off[s + 1]), entries (partner index
+  // as int bits, partner radius, lim2, 0), where lim2 bounds the squared centre distance beyond
+  // which the pair is certainly inactive.
   const int* pair_off;
   const float4* pair_tab;
   int n_s, n_groups;

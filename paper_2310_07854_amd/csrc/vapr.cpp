@@ -413,11 +413,10 @@ int timed(vapr_ctx* ctx, int id, F&& launch, const char* what) {
   return VAPR_OK;
 }
 
-// Self-pair visit lists, one per sphere in CSR order, padded to a multiple of 4 entries:
-// (partner, partner radius, lim2, 0).  lim2 >= ((r_s + r_t + eta) * (1 + 2^-8))^2, rounded up: a
-// pair whose FP32 squared centre distance exceeds it has clearance above eta by far more than the
-// rounding of the clearance, so its activation is exactly zero.  Padding entries name the sphere
-// itself with lim2 = -1, which no squared distance reaches.
+// Self-pair visit lists, one per sphere in CSR order: (partner, partner radius, lim2, 0).
+// lim2 >= ((r_s + r_t + eta) * (1 + 2^-8))^2, rounded up: a pair whose FP32 squared centre distance
+// exceeds it has clearance above eta by far more than the rounding of the clearance, so its
+// activation is exactly zero.
 int build_pair_table(vapr_ctx* ctx) {
   if (ctx->d_pair_tab || ctx->d_pair_off) {
     VAPR_HIP(ctx, hipStreamSynchronize(ctx->stream));
@@ -442,7 +441,6 @@ int build_pair_table(vapr_ctx* ctx) {
       if ((double)lim2 < lim * lim) lim2 = std::nextafter(lim2, INFINITY);
       tab.push_back(make_float4(as_float(t), ctx->h_radius[t], lim2, 0.f));
     }
-    while (tab.size() % 4) tab.push_back(make_float4(as_float(s), 0.f, -1.f, 0.f));
     off[s + 1] = (int)tab.size();
   }
   int st;
