@@ -3,11 +3,11 @@ sphere costs, aggregation, adjoint, line-search selection and L-BFGS update) ove
 64 worlds x 64 seeds x 48 timesteps = 196,608 configurations of a synthetic 7-joint arm with 60
 spheres and 300 self pairs among 64 random cuboids per world.  Reports configuration evaluations
 (cost + joint gradient) per second for a variable-precision assignment of the five stored tensors
-and for FP32 on the same GPU.  The timed steps run the batch split by worlds over --parts contexts,
-each on a stream of its own (identical results; one partition's kernels fill the GPU while
-another's drain); the same steps are also timed on one stream, and that run gives the per-kernel
-times (HIP events recorded around each launch on the stream the kernels run on) and the dominant
-kernel's roofline.  The FP64 oracle's rate on the host cores for a bounded sample is reported
+and for FP32 on the same GPU.  The timed steps run on one stream by default; with --parts P > 1 the
+batch is split by worlds over P contexts, each on a stream of its own (identical results; one
+partition's kernels can fill the GPU while another's drain), and the same steps are also timed on
+one stream.  The one-stream run gives the per-kernel times (HIP events recorded around each launch
+on the stream the kernels run on) and the dominant kernel's roofline.  The FP64 oracle's rate on the host cores for a bounded sample is reported
 beside it.
 
   python bench.py [--steps K] [--warmup W] [--precision NAME] [--parts P] [--no-cpu-baseline]
@@ -49,7 +49,9 @@ TENSOR_NAMES = ("link_poses", "sphere_pos", "sphere_dist", "sphere_grad", "joint
 BITS = {"f32": 32, "f16": 16, "bf16": 16, "e4m3": 8, "e5m2": 8, "e3m2": 6, "e2m1": 4}
 N_WORLDS, TPW, T, N_LS, N_SPHERES, N_CUBOIDS, N_PAIRS = 64, 64, 48, 1, 60, 64, 300
 HIST_M = 8
-PARTS = 4  # world partitions (contexts on streams of their own) for the timed steps
+# world partitions (contexts on streams of their own) for the timed steps: with the sphere-cost
+# kernel at three blocks per CU, one stream is the faster for the variable-precision assignments
+PARTS = 1
 # algorithmic FP32 operations of one sphere-cuboid test (FMA = 2): R^T p - R^T c (18),
 # |u| - h (3), max(a, 0) (3), |max(a,0)|^2 (5), min(max_i a_i, 0) (3), key (1), running arg-min (2)
 FLOPS_PER_SPHERE_CUBOID = 35

@@ -946,13 +946,14 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(3))) void k
 // candidate lists of 8 spheres, the same closest-cuboid keys, the same pair visits in the same order.
 // At the end the second half of each group leaves its 8 results in LDS (over the position image,
 // no longer needed) and the first half encodes and stores the group's 16 values.
-
-#ifndef VAPR_K2H_WAVES
-#define VAPR_K2H_WAVES 4
-#endif
-#ifndef VAPR_K2H_SINGLE
-#define VAPR_K2H_SINGLE 0
-#endif
+//
+// Occupancy: the candidate walks hold one cuboid at a time (16 registers fewer than a double
+// buffer), and the kernel is held to 80 VGPRs, six wavefronts per SIMD: three 512-thread blocks per
+// CU, which the 52 KB of LDS per block (60 spheres) allow.  The few values that no longer fit are
+// spilled in the set-up before the walks and around the final stores, not in the walks or the pair
+// visits; the extra block per CU covers the candidate loads and partner reads that one cuboid in
+// flight no longer does (at 94 VGPRs with two cuboids in flight, two blocks per CU, the kernel took
+// 10 % longer).  Packed ExMy positions, whose decode needs more registers, keep two blocks per CU.
 constexpr int HS = SPH_GROUP / 2;
 
 size_t sphere_cost_half_lds_bytes(int n_s, int n_groups) {
@@ -994,7 +995,7 @@ __device__ __forceinline__ void load_half_at(const TV& t, const uint32_t* base, 
 }
 
 template <int FS>
-__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(VAPR_K2H_WAVES))) void k_sphere_cost_half(
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(FS == PXM ? 4 : 6))) void k_sphere_cost_half(
     RobotArgs R, WorldArgs W, GridArgs Gd, TV S, TV D, TV G, float* __restrict__ selfc, ShapeArgs sh, CostArgs cp) {
   extern __shared__ float lds_f[];
   const int lane = threadIdx.x & 63;
@@ -1072,13 +1073,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(VAPR_K2H_WA
               mq |= (uint64_t)mp[0] | (Gd.MW > 1 ? (uint64_t)mp[1] << 32 : 0);
             }
           }
-#if VAPR_K2H_SINGLE
           if (staged) walk_list_single<HS>(mq, cub, px, py, pz, best, bk);
           else walk_list_single<HS>(mq, wbox, px, py, pz, best, bk);
-#else
-          if (staged) walk_list<HS, HS>(mq, cub, 0, px, py, pz, best, bk);
-          else walk_list<HS, HS>(mq, wbox, 0, px, py, pz, best, bk);
-#endif
         } else {
           int vox[HS];
 #pragma unroll
